@@ -1,0 +1,390 @@
+"""Pins of the CPU oracle against facts fixed outside it (paper and mathematics).
+
+Each test names the passage it relies on.  None of these needs a GPU.
+"""
+import itertools
+import json
+import math
+import os
+import random
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+M64 = (1 << 64) - 1
+
+
+# ----------------------------------------------------------------- shape ---
+
+def test_shape_rule_closed_form(built):
+    """R = ceil(log2 V) + 1, B = ceil(log2 n) + 1 with n = C(V, 2), C = 8.
+
+    The small uniform workload states R = 11 and B = 20 for V = 1024 and the dense
+    R-MAT workload states R = 15 for V = 2^14; the rest is the closed form.
+    """
+    assert oracle.shape(1024)[:3] == (11, 8, 20)
+    assert oracle.shape(1 << 14)[0] == 15
+    for V in [2, 3, 4, 5, 63, 64, 65, 1000, 1024, 1025, 2048, 1 << 14, 1 << 15, 1 << 16]:
+        R, C, B, n = oracle.shape(V)
+        assert n == V * (V - 1) // 2
+        assert C == 8
+        # smallest k with 2^k >= V, by exact integer search
+        k = 0
+        while (1 << k) < V:
+            k += 1
+        assert R == k + 1
+        k = 0
+        while (1 << k) < n:
+            k += 1
+        assert B == k + 1
+        assert B <= 32  # row hash has 32 bits
+
+
+def test_shape_rejects_out_of_range(built):
+    for V in [0, 1, 65537]:
+        with pytest.raises(ValueError):
+            oracle.shape(V)
+
+
+# ------------------------------------------------------------ edge index ---
+
+def test_edge_index_is_a_bijection_onto_pairs(built):
+    """Sec. 2.2: characteristic vectors are indexed by the C(V,2) node pairs."""
+    for V in [2, 3, 7, 64, 181]:
+        n = V * (V - 1) // 2
+        seen = np.zeros(n, bool)
+        for v in range(V):
+            for u in range(v):
+                i = oracle.edge_index(u, v)
+                assert oracle.edge_index(v, u) == i
+                assert 0 <= i < n and not seen[i]
+                seen[i] = True
+                assert oracle.edge_decode(i) == (u, v)
+        assert seen.all()
+
+
+def test_edge_decode_extremes(built):
+    V = 1 << 16
+    n = V * (V - 1) // 2
+    rng = random.Random(7)
+    probes = [0, 1, 2, n - 1, n - 2] + [rng.randrange(n) for _ in range(2000)]
+    for i in probes:
+        u, v = oracle.edge_decode(i)
+        # the row is fixed by the triangular numbers: v(v-1)/2 <= i < v(v+1)/2
+        assert v * (v - 1) // 2 <= i < v * (v + 1) // 2
+        assert 0 <= u < v < V
+        assert oracle.edge_index(u, v) == i
+
+
+# ----------------------------------------------------------------- seeds ---
+
+def test_splitmix64_known_answer(built):
+    kat = json.load(open(os.path.join(GOLDEN, "splitmix64_kat.json")))
+    assert oracle.splitmix64(kat["seed"], len(kat["outputs"])) == kat["outputs"]
+
+
+def test_seed_table_is_the_splitmix_stream_in_round_column_hash_order(built):
+    R = 5
+    tab = oracle.seed_table(1234567, R)
+    stream = oracle.splitmix64(1234567, R * 8 * 6)
+    assert tab.reshape(-1).tolist() == stream
+
+
+def test_seed_table_prefix_independent_of_round_count(built):
+    a = oracle.seed_table(99, 7)
+    b = oracle.seed_table(99, 12)
+    assert (a == b[:7]).all()
+
+
+# ------------------------------------------------------------------ hash ---
+
+def test_hash_depth_law(built):
+    """Row membership: h1(e) = 0 mod 2^k with probability 2^-k (Sec. 3.2)."""
+    O = oracle.Oracle(1 << 14, seed=2024)
+    counts = np.zeros(12)
+    rng = np.random.default_rng(1)
+    xs = rng.integers(0, O.n, 20000)
+    total = 0
+    for r, c in [(0, 0), (3, 5), (14, 7)]:
+        for x in xs.tolist():
+            h = O.row_hash(r, c, x)
+            tz = (h & -h).bit_length() - 1 if h else 32
+            for k in range(12):
+                if tz >= k:
+                    counts[k] += 1
+            total += 1
+    for k in range(12):
+        p = counts[k] / total
+        expect = 2.0 ** -k
+        sd = math.sqrt(expect * (1 - expect) / total)
+        assert abs(p - expect) < 6 * sd + 1e-12, (k, p, expect)
+
+
+@pytest.mark.parametrize("x,y", [(0, 1), (2, 6), (4, 12), (1 << 20, (1 << 20) + 2), (123456, 7654321)])
+def test_hash_pairwise_uniform(built, x, y):
+    """2-wise independence (Sec. 3.2): over random seeds, (h(x), h(y)) low bits are uniform."""
+    rng = random.Random(x * 31 + y)
+    cells = np.zeros(16)
+    trials = 16000
+    for _ in range(trials):
+        a, b = rng.getrandbits(64), rng.getrandbits(64)
+        hx, hy = oracle.hash32(a, b, x), oracle.hash32(a, b, y)
+        cells[(hx & 3) * 4 + (hy & 3)] += 1
+    exp = trials / 16
+    chi2 = float(((cells - exp) ** 2 / exp).sum())
+    assert chi2 < 45.0, chi2  # 15 dof; p ~ 1e-4
+
+
+def test_checksum_of_zero_nonzero(built):
+    """Edge index 0 must stay sampleable: its checksum may not vanish."""
+    for seed in range(50):
+        O = oracle.Oracle(64, seed)
+        assert O.seeds_valid()
+
+
+# ---------------------------------------------------------------- sketch ---
+
+def _py_hash(a, b, x):
+    return ((a * x + b) & M64) >> 32
+
+
+def _closed_form(V, seed, edges):
+    """Eq. (1)-(2): bucket (r, c, b) of node w XORs every final incident edge in it."""
+    R, C, B, n = oracle.shape(V)
+    tab = oracle.seed_table(seed, R)
+    al = np.zeros((V, R, C, B), np.uint64)
+    ga = np.zeros((V, R, C, B), np.uint64)
+    for (u, v) in edges:
+        i = v * (v - 1) // 2 + u
+        for r in range(R):
+            for c in range(C):
+                (a1, b1), (ah, bh), (alo, blo) = [tuple(int(t) for t in tab[r, c, k]) for k in range(3)]
+                h1 = _py_hash(a1, b1, i)
+                chk = (_py_hash(ah, bh, i) << 32) | _py_hash(alo, blo, i)
+                for b in range(B):
+                    # e is in row b when h1(e) = 0 mod 2^b; the last row also keeps deeper ones
+                    if h1 % (1 << b) == 0:
+                        for w in (u, v):
+                            al[w, r, c, b] ^= np.uint64(i)
+                            ga[w, r, c, b] ^= np.uint64(chk)
+    return al, ga
+
+
+def _random_toggle_stream(V, n, rng):
+    src, dst = [], []
+    for _ in range(n):
+        u, v = rng.sample(range(V), 2)
+        src.append(u)
+        dst.append(v)
+    return np.array(src, np.uint32), np.array(dst, np.uint32)
+
+
+def test_sketch_equals_closed_form_eq_1_2(built):
+    rng = random.Random(3)
+    for V, n, seed in [(2, 5, 1), (9, 60, 2), (23, 400, 3)]:
+        src, dst = _random_toggle_stream(V, n, rng)
+        O = oracle.Oracle(V, seed)
+        O.ingest(src, dst)
+        s = workloads.Stream(V, src, dst, np.ones(len(src), np.uint8))
+        fu, fv = workloads.final_edges(s)
+        al, ga = _closed_form(V, seed, list(zip(fu.tolist(), fv.tolist())))
+        assert (O.alpha == al).all()
+        assert (O.gamma == ga).all()
+
+
+def test_sketch_independent_of_stream_order(built):
+    rng = random.Random(5)
+    src, dst = _random_toggle_stream(40, 3000, rng)
+    perm = np.random.default_rng(0).permutation(len(src))
+    A = oracle.Oracle(40, 77)
+    A.ingest(src, dst)
+    Bo = oracle.Oracle(40, 77)
+    Bo.ingest(dst[perm], src[perm])  # endpoint order flipped as well
+    assert (A.alpha == Bo.alpha).all() and (A.gamma == Bo.gamma).all()
+
+
+def test_linearity_xor(built):
+    """S(A) xor S(B) = S(A symmetric-difference B) (Sec. 3.2, linearity by XOR)."""
+    rng = random.Random(11)
+    V = 30
+    sa, da = _random_toggle_stream(V, 500, rng)
+    sb, db = _random_toggle_stream(V, 700, rng)
+    A, Bo, AB = oracle.Oracle(V, 5), oracle.Oracle(V, 5), oracle.Oracle(V, 5)
+    A.ingest(sa, da)
+    Bo.ingest(sb, db)
+    AB.ingest(np.concatenate([sa, sb]), np.concatenate([da, db]))
+    assert ((A.alpha ^ Bo.alpha) == AB.alpha).all()
+    assert ((A.gamma ^ Bo.gamma) == AB.gamma).all()
+
+
+def test_support_one_exact_recovery(built):
+    """Lemma goodcheck: a bucket holding one nonzero entry always passes."""
+    V = 1 << 12
+    rng = random.Random(2)
+    for trial in range(20):
+        u, v = rng.sample(range(V), 2)
+        O = oracle.Oracle(V, 1000 + trial)
+        O.update(u, v)
+        i = oracle.edge_index(u, v)
+        for w in (u, v):
+            for r in range(O.R):
+                kind, got = O.query_node(w, r)
+                assert kind == oracle.SAMPLE and got == i
+                for c in range(O.C):
+                    h = O.row_hash(r, c, i)
+                    depth = min(((h & -h).bit_length() - 1) if h else 32, O.B - 1)
+                    chk = O.checksum(r, c, i)
+                    for b in range(O.B):
+                        if b <= depth:
+                            assert O.alpha[w, r, c, b] == i and O.gamma[w, r, c, b] == chk
+                        else:
+                            assert O.alpha[w, r, c, b] == 0 and O.gamma[w, r, c, b] == 0
+        # every other node is untouched: ZERO
+        other = next(x for x in range(V) if x not in (u, v))
+        assert O.query_node(other, 0)[0] == oracle.ZERO
+    # edge index 0 (pair (0, 1)) has alpha = 0 but is still recovered
+    O = oracle.Oracle(V, 3)
+    O.update(0, 1)
+    assert O.query_node(0, 0) == (oracle.SAMPLE, 0)
+
+
+def test_sampled_index_in_support_and_goodset_bound(built):
+    """Lemma goodcheck (sample is in the support) and Lemma goodset (per column > 1/8)."""
+    V = 600
+    rng = random.Random(9)
+    fails = 0
+    col_good = 0
+    col_total = 0
+    for trial in range(60):
+        deg = rng.choice([1, 2, 3, 5, 9, 17, 40, 120, 400])
+        nbrs = rng.sample(range(1, V), deg)
+        O = oracle.Oracle(V, 5000 + trial)
+        O.ingest(np.zeros(deg, np.uint32), np.array(nbrs, np.uint32))
+        support = {oracle.edge_index(0, x) for x in nbrs}
+        for r in range(O.R):
+            kind, got = O.query_node(0, r)
+            if kind == oracle.SAMPLE:
+                assert got in support
+            else:
+                assert kind == oracle.FAIL
+                fails += 1
+            for c in range(O.C):
+                col_total += 1
+                good = False
+                for b in range(O.B):
+                    k = O.bucket_class(r, c, int(O.alpha[0, r, c, b]), int(O.gamma[0, r, c, b]))
+                    if k == oracle.GOOD:
+                        # a GOOD bucket holds exactly one member (collisions have p ~ 2^-64)
+                        members = [i for i in support
+                                   if O.row_hash(r, c, i) % (1 << b) == 0]
+                        assert len(members) == 1 and members[0] == O.alpha[0, r, c, b]
+                        good = True
+                col_good += good
+    assert col_good / col_total > 1 / 8
+    assert fails <= 2
+
+
+# ------------------------------------------------------------- boruvka -----
+
+def _check_forest(V, labels, forest, fu, fv):
+    edges = set(zip(fu.tolist(), fv.tolist()))
+    ncc = len(set(labels.tolist()))
+    assert len(forest) == V - ncc
+    parent = list(range(V))
+
+    def find(x):
+        while parent[x] != x:
+            parent[x] = parent[parent[x]]
+            x = parent[x]
+        return x
+
+    for a, b in forest.tolist():
+        assert a < b and (a, b) in edges
+        ra, rb = find(a), find(b)
+        assert ra != rb, "forest has a cycle"
+        parent[ra] = rb
+        assert labels[a] == labels[b]
+    idx = [b * (b - 1) // 2 + a for a, b in forest.tolist()]
+    assert idx == sorted(idx)
+
+
+def test_components_match_union_find_many_tiny_streams(built):
+    """Paper's own correctness method (Sec. 6): compare against an exact graph algorithm."""
+    rng = random.Random(2022)
+    for trial in range(600):
+        V = rng.randint(2, 48)
+        density = rng.random()
+        n_upd = rng.randint(0, 3 * V)
+        src, dst = [], []
+        for _ in range(n_upd):
+            if rng.random() < density:
+                u, v = rng.sample(range(V), 2)
+                src.append(u)
+                dst.append(v)
+        s = workloads.Stream(V, np.array(src, np.uint32), np.array(dst, np.uint32),
+                             np.ones(len(src), np.uint8))
+        O = oracle.Oracle(V, rng.getrandbits(64))
+        O.ingest(s.src, s.dst)
+        st, labels, forest, used = O.connected_components()
+        fu, fv = workloads.final_edges(s)
+        ref = workloads.union_find_labels(V, fu, fv)
+        assert st == oracle.OK
+        assert (labels == ref).all(), trial
+        _check_forest(V, labels, forest, fu, fv)
+
+
+def test_components_periodic_queries_mid_stream(built):
+    """Queries interleaved with ingestion see the prefix graph and leave sketches intact."""
+    s = workloads.uniform_stream(256, 900, 400, seed=17)
+    O = oracle.Oracle(256, 99)
+    step = 100
+    for k in range(0, s.N, step):
+        O.ingest(s.src[k:k + step], s.dst[k:k + step])
+        before = O.alpha.copy()
+        st, labels, forest, _ = O.connected_components()
+        assert (O.alpha == before).all()
+        pre = workloads.Stream(256, s.src[:k + step], s.dst[:k + step], s.op[:k + step])
+        fu, fv = workloads.final_edges(pre)
+        assert st == oracle.OK
+        assert (labels == workloads.union_find_labels(256, fu, fv)).all()
+        _check_forest(256, labels, forest, fu, fv)
+
+
+def test_small_uniform_workload_components(built):
+    s = workloads.config_uniform_small()
+    O = oracle.Oracle(s.V, 1)
+    O.ingest(s.src, s.dst)
+    st, labels, forest, used = O.connected_components()
+    fu, fv = workloads.final_edges(s)
+    assert st == oracle.OK
+    assert (labels == workloads.scipy_labels(s.V, fu, fv)).all()
+    _check_forest(s.V, labels, forest, fu, fv)
+
+
+def test_forced_sketch_failure_when_rounds_run_out(built):
+    """With a single round a long path cannot finish: status SKETCH_FAIL, labels still a coarsening."""
+    V = 64
+    src = np.arange(V - 1, dtype=np.uint32)
+    dst = np.arange(1, V, dtype=np.uint32)
+    O = oracle.Oracle(V, 3, R=1)
+    O.ingest(src, dst)
+    st, labels, forest, used = O.connected_components()
+    assert st == oracle.SKETCH_FAIL
+    assert used == 1
+    assert len(set(labels.tolist())) > 1
+    # every label class is a set of consecutive path nodes joined by forest edges
+    for a, b in forest.tolist():
+        assert b == a + 1 and labels[a] == labels[b]
+
+
+def test_invalid_updates_rejected_atomically(built):
+    O = oracle.Oracle(10, 1)
+    with pytest.raises(ValueError):
+        O.ingest(np.array([1, 2], np.uint32), np.array([2, 2], np.uint32))
+    assert not O.alpha.any()
+    with pytest.raises(ValueError):
+        O.ingest(np.array([1], np.uint32), np.array([10], np.uint32))

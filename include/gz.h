@@ -1,0 +1,234 @@
+/*
+ * gz.h -- C ABI of the MI355X CubeSketch connectivity library.
+ *
+ * The library keeps, for every node of a graph, one CubeSketch per Boruvka
+ * round (GraphZeppelin, Tench et al. SIGMOD 2022: Sec. 2.2 for the node
+ * sketches, Sec. 3.2 / Fig. "cube_code" for CubeSketch), resident in HBM, and
+ * answers the streaming connected-components problem of Sec. 2.1: given an
+ * insert/delete edge stream, return a spanning forest (and the component of
+ * every node).
+ *
+ * Conventions shared by every call:
+ *   - every call returns a gz_status; GZ_OK (0) on success;
+ *   - a call that fails with GZ_EINVAL changes nothing;
+ *   - gz_last_error() returns a message for the last failure on this thread;
+ *   - a gz_graph handle may not be used from two host threads at once;
+ *   - node ids are uint32 in [0, V); an update (u, v) needs u != v;
+ *   - the sketch of a stream depends only on the set of pairs that occur an
+ *     odd number of times (vectors over Z2, Sec. 3.2), so insertions and
+ *     deletions are the same operation and their order does not matter;
+ *   - stream arguments are hipStream_t values (0 = the null stream);
+ *   - flags: GZ_DEVICE_PTR says that the array arguments point to device
+ *     memory (else host memory); GZ_ASYNC skips the synchronous validation
+ *     check, so an invalid update is reported by the next gz_flush instead
+ *     (the offending call still applies nothing).
+ *
+ * Hash contract (identical for every implementation that must agree bit for
+ * bit; the paper leaves the family open beyond 2-wise independence):
+ *   shape   C = 8 columns, R = bitlen(V-1)+1 rounds, B = bitlen(n-1)+1 rows,
+ *           n = V(V-1)/2, 2 <= V <= 65536;
+ *   index   idx(u, v) = v(v-1)/2 + u for u < v (position in the
+ *           characteristic vector, Sec. 2.2);
+ *   seeds   a SplitMix64 stream (Steele, Lea, Flood 2014) started at the graph
+ *           seed gives, for r = 0..R-1, c = 0..C-1, k in (row hash, checksum
+ *           high, checksum low), a multiplier then an increment (uint64);
+ *   hash    h(x) = ((mult * x + incr) mod 2^64) >> 32 (multiply-add-shift,
+ *           strongly universal on 32-bit keys);
+ *   depth   d = min(ctz(h_row(idx)), B-1), ctz(0) = 32: the update goes into
+ *           rows 0..d of column c (row k+1 takes it while bit k of the row
+ *           hash is zero, Fig. "cube_code");
+ *   bucket  alpha ^= idx, gamma ^= checksum(idx) = h_hi(idx) << 32 | h_lo(idx);
+ *   query   a bucket is EMPTY if alpha = gamma = 0, GOOD if not EMPTY, alpha < n
+ *           and gamma = checksum(alpha), else BAD; a sketch is queried column by
+ *           column, rows ascending, and yields the first GOOD alpha, else ZERO
+ *           when every bucket is EMPTY, else FAIL (Sec. 3.2, result rule after
+ *           Eq. (1)-(2)).
+ */
+#ifndef GZ_H
+#define GZ_H
+
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t gz_status;
+
+enum {
+    GZ_OK = 0,
+    GZ_EINVAL = 1,        /* bad argument or invalid update; nothing applied */
+    GZ_ENOMEM = 2,        /* device or host allocation failed / over budget */
+    GZ_EDEVICE = 3,       /* a HIP runtime call failed */
+    GZ_ESKETCH_FAIL = 4,  /* Boruvka ran out of rounds with a component still active */
+    GZ_EBUSY = 5,         /* server: queue full or session not admitted yet */
+    GZ_ESTATE = 6         /* call not valid in the object's current state */
+};
+
+#define GZ_DEVICE_PTR 0x1u
+#define GZ_ASYNC 0x2u
+
+#define GZ_COLUMNS 8u
+#define GZ_MAX_NODES 65536u
+
+typedef struct gz_graph gz_graph;
+
+/* Optional overrides; zero fields keep the shape rule / library defaults. */
+typedef struct gz_config {
+    uint32_t rounds;      /* R override (tests force failures with a small R); 0 = rule */
+    uint32_t reserved0;
+    uint64_t reserved1;
+} gz_config;
+
+/* Kernel launch parameters of the ingest path; gz_autotune picks them. */
+typedef struct gz_tuning {
+    uint32_t wg_size;     /* threads per sketch-update workgroup (multiple of 64, <= 1024) */
+    uint32_t lds_rows;    /* rows kept in the LDS tile (1..B); deeper rows go to HBM atomics */
+    uint32_t chunk;       /* max updates of one node per work item (gutter split threshold) */
+    uint32_t wgs_per_cu;  /* persistent grid = wgs_per_cu * CUs */
+} gz_tuning;
+
+/* ------------------------------------------------------------------------
+ * gz_sketch_init -- create a graph on V nodes with all-zero sketches.
+ *   Paper: node sketches of O(log V) CubeSketches, one per Boruvka round
+ *   (Sec. 2.2); CubeSketch layout of Sec. 3.2; all-zero start = empty graph.
+ *   out   receives the handle (library-owned until gz_free);
+ *   V     2 .. 65536 (keys idx < 2^31 for the 32-bit hash); else GZ_EINVAL;
+ *   seed  graph seed of the hash contract above;
+ *   cfg   NULL or overrides.
+ *   Allocates 12*B*R*C bytes per node of HBM on the current device
+ *   (GZ_ENOMEM if that fails).  GZ_EINVAL also if the seed yields a zero
+ *   checksum for index 0 (probability 2^-64): edge (0,1) would be unsampleable.
+ * ---------------------------------------------------------------------- */
+gz_status gz_sketch_init(gz_graph** out, uint32_t V, uint64_t seed, const gz_config* cfg);
+
+/* Release the graph and all its device memory.  NULL is accepted. */
+gz_status gz_free(gz_graph* g);
+
+/* Shape of the graph's sketches (any output pointer may be NULL). */
+gz_status gz_shape(const gz_graph* g, uint32_t* V, uint32_t* R, uint32_t* C, uint32_t* B,
+                   uint64_t* n);
+
+/* Zero every sketch (the graph becomes empty again).  Stream-ordered on `stream`. */
+gz_status gz_reset(gz_graph* g, hipStream_t stream);
+
+/* ------------------------------------------------------------------------
+ * gz_update_sketch_batch -- apply one node's batch of updates to that node's
+ *   sketch only, in one kernel launch.  This is the per-node batch application
+ *   of Sec. 5.1 (a Graph Worker applies a gutter of updates bound for one node
+ *   to that node's CubeSketches); the mirror update of every edge must be
+ *   submitted to the other endpoint by the caller.
+ *   node   the node whose sketch changes (< V);
+ *   nbrs   count neighbour ids: edge {node, nbrs[k]} is toggled in node's
+ *          sketch; host or device memory (GZ_DEVICE_PTR), borrowed for the
+ *          call (host memory is copied before the call returns);
+ *   Errors: GZ_EINVAL if any nbrs[k] == node or >= V (nothing applied).
+ *   Stream-ordered on `stream`.
+ * ---------------------------------------------------------------------- */
+gz_status gz_update_sketch_batch(gz_graph* g, uint32_t node, const uint32_t* nbrs, uint64_t count,
+                                 uint32_t flags, hipStream_t stream);
+
+/* ------------------------------------------------------------------------
+ * gz_ingest -- apply a chunk of the edge stream: update k toggles edge
+ *   {src[k], dst[k]} in the sketches of both endpoints (Sec. 2.2: each
+ *   update changes both endpoints' characteristic vectors).  The updates are
+ *   grouped by endpoint on the device and applied in one persistent launch
+ *   (the role of the gutters of Sec. 4-5).
+ *   src, dst  N node ids each, host or device memory (GZ_DEVICE_PTR);
+ *             device inputs must stay valid until the stream reaches the call;
+ *   N         < 2^31 per call.
+ *   Errors: GZ_EINVAL if any src[k] == dst[k] or an id >= V (nothing applied).
+ *   Returns after enqueueing (GZ_ASYNC) or after the validation check.
+ * ---------------------------------------------------------------------- */
+gz_status gz_ingest(gz_graph* g, const uint32_t* src, const uint32_t* dst, uint64_t N,
+                    uint32_t flags, hipStream_t stream);
+
+/* ------------------------------------------------------------------------
+ * gz_ingest_multi -- gz_ingest over G independent graphs in one fused
+ *   launch sequence.  Updates offs[k] .. offs[k+1]-1 of src/dst belong to gs[k]
+ *   (ids local to that graph).  offs is host memory (G+1 entries, offs[0]=0,
+ *   non-decreasing); src/dst as in gz_ingest.  The result equals G separate
+ *   gz_ingest calls.  The graphs must be distinct and on the current device.
+ * ---------------------------------------------------------------------- */
+gz_status gz_ingest_multi(gz_graph* const* gs, uint32_t G, const uint64_t* offs,
+                          const uint32_t* src, const uint32_t* dst, uint32_t flags,
+                          hipStream_t stream);
+
+/* ------------------------------------------------------------------------
+ * gz_flush -- the paper's cleanup() step (Sec. 5.2): wait until every update
+ *   submitted to g has been applied.  Returns GZ_EINVAL if an asynchronous
+ *   call on g carried an invalid update since the last flush.
+ * ---------------------------------------------------------------------- */
+gz_status gz_flush(gz_graph* g);
+
+/* ------------------------------------------------------------------------
+ * gz_connected_components -- flush, then run Boruvka over XOR-merged
+ *   sketches (Sec. 2.2; the three phases of Sec. 4.2: sample one edge per
+ *   component, merge, sum sketches).  Round r uses every node's round-r
+ *   sketch; a component whose sketch is ZERO is complete; a GOOD sample whose
+ *   edge does not leave the component counts as FAIL; the sampled edges form a
+ *   functional graph whose every cycle loses the edge of its smallest
+ *   component.  Works on scratch copies: the sketches are not modified, so
+ *   queries may be interleaved with ingestion.
+ *   labels  host array of V entries: smallest node id of each node's component;
+ *   num_cc  (nullable) number of components.
+ *   Returns GZ_ESKETCH_FAIL (outputs still written) if a component was still
+ *   active after R rounds.
+ * ---------------------------------------------------------------------- */
+gz_status gz_connected_components(gz_graph* g, uint32_t* labels, uint32_t* num_cc);
+
+/* ------------------------------------------------------------------------
+ * gz_list_spanning_forest -- the problem's output (Sec. 2.1): a spanning
+ *   forest of the current graph, from the same Boruvka run as
+ *   gz_connected_components.
+ *   edges      host array of 2*(V-1) entries: pairs (u, v), u < v, sorted by
+ *              idx(u, v);
+ *   num_edges  number of pairs written.
+ *   Status rules as gz_connected_components.
+ * ---------------------------------------------------------------------- */
+gz_status gz_list_spanning_forest(gz_graph* g, uint32_t* edges, uint64_t* num_edges);
+
+/* Labels, component count, forest and status of one Boruvka run in one call
+ * (any output pointer may be NULL; status per gz_connected_components). */
+gz_status gz_query(gz_graph* g, uint32_t* labels, uint32_t* num_cc, uint32_t* edges,
+                   uint64_t* num_edges);
+
+/* ------------------------------------------------------------------------
+ * gz_connected_components_multi -- Boruvka over G graphs at once (the
+ *   many-graph form of gz_connected_components).  labels: host array of
+ *   sum(V_k) entries, graph k's labels at offset sum_{j<k} V_j, local ids;
+ *   num_cc, status: host arrays of G entries (nullable).  Returns GZ_OK if
+ *   every graph finished, GZ_ESKETCH_FAIL if any did not.
+ * ---------------------------------------------------------------------- */
+gz_status gz_connected_components_multi(gz_graph* const* gs, uint32_t G, uint32_t* labels,
+                                        uint32_t* num_cc, int32_t* status);
+
+/* ------------------------------------------------------------------------
+ * gz_export_sketches -- copy the sketches of nodes [node_lo, node_hi) to the
+ *   host in the canonical layout alpha/gamma[node][r][c][b] (uint64, rows in
+ *   the nested form of Eq. (1)-(2): row b holds every index with depth >= b),
+ *   whatever the internal layout.  alpha and gamma hold
+ *   (node_hi - node_lo) * R * C * B entries each.  Flushes first.
+ * ---------------------------------------------------------------------- */
+gz_status gz_export_sketches(gz_graph* g, uint32_t node_lo, uint32_t node_hi, uint64_t* alpha,
+                             uint64_t* gamma);
+
+/* Device address and byte size of the internal sketch array (for tools that
+ * measure traffic); the layout is private. */
+gz_status gz_sketch_storage(const gz_graph* g, void** dev_ptr, uint64_t* bytes);
+
+/* Launch parameters of the ingest path for this graph (get / set). */
+gz_status gz_get_tuning(const gz_graph* g, gz_tuning* t);
+gz_status gz_set_tuning(gz_graph* g, const gz_tuning* t);
+
+/* Human-readable name of a status code, and the last error message of this thread. */
+const char* gz_status_str(gz_status s);
+const char* gz_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GZ_H */

@@ -1,0 +1,310 @@
+"""MI355X-native CubeSketch ingestion and Boruvka connectivity (GraphZeppelin's hot path).
+
+This package is a thin ctypes binding over ``libgz.so`` (HIP, gfx950).  It only
+marshals arguments: every step of ingestion and of the query runs in the
+library's kernels.  PyTorch is used, when present, for device memory and
+streams.  Importing fails loudly if the library has not been built.
+
+The functions keep the C names of ``include/gz.h``; :class:`Graph` wraps a
+handle for convenience.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgz.so")
+
+GZ_OK, GZ_EINVAL, GZ_ENOMEM, GZ_EDEVICE, GZ_ESKETCH_FAIL, GZ_EBUSY, GZ_ESTATE = range(7)
+GZ_DEVICE_PTR = 0x1
+GZ_ASYNC = 0x2
+GZ_COLUMNS = 8
+
+
+class GzError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_status_name(status)}: {msg}")
+        self.status = status
+
+
+class gz_config(ctypes.Structure):
+    _fields_ = [("rounds", ctypes.c_uint32), ("reserved0", ctypes.c_uint32),
+                ("reserved1", ctypes.c_uint64)]
+
+
+class gz_tuning(ctypes.Structure):
+    _fields_ = [("wg_size", ctypes.c_uint32), ("lds_rows", ctypes.c_uint32),
+                ("chunk", ctypes.c_uint32), ("wgs_per_cu", ctypes.c_uint32)]
+
+    def as_dict(self):
+        return {f: int(getattr(self, f)) for f, _ in self._fields_}
+
+
+_lib = None
+
+_SIGS = {
+    "gz_sketch_init": ([ctypes.POINTER(ctypes.c_void_p), ctypes.c_uint32, ctypes.c_uint64,
+                        ctypes.POINTER(gz_config)], ctypes.c_int32),
+    "gz_free": ([ctypes.c_void_p], ctypes.c_int32),
+    "gz_shape": ([ctypes.c_void_p] + [ctypes.POINTER(ctypes.c_uint32)] * 4
+                 + [ctypes.POINTER(ctypes.c_uint64)], ctypes.c_int32),
+    "gz_reset": ([ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int32),
+    "gz_update_sketch_batch": ([ctypes.c_void_p, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_uint64,
+                                ctypes.c_uint32, ctypes.c_void_p], ctypes.c_int32),
+    "gz_ingest": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64,
+                   ctypes.c_uint32, ctypes.c_void_p], ctypes.c_int32),
+    "gz_ingest_multi": ([ctypes.POINTER(ctypes.c_void_p), ctypes.c_uint32,
+                         ctypes.POINTER(ctypes.c_uint64), ctypes.c_void_p, ctypes.c_void_p,
+                         ctypes.c_uint32, ctypes.c_void_p], ctypes.c_int32),
+    "gz_flush": ([ctypes.c_void_p], ctypes.c_int32),
+    "gz_connected_components": ([ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint32),
+                                 ctypes.POINTER(ctypes.c_uint32)], ctypes.c_int32),
+    "gz_list_spanning_forest": ([ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint32),
+                                 ctypes.POINTER(ctypes.c_uint64)], ctypes.c_int32),
+    "gz_query": ([ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_uint32),
+                  ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_uint64)], ctypes.c_int32),
+    "gz_connected_components_multi": ([ctypes.POINTER(ctypes.c_void_p), ctypes.c_uint32,
+                                       ctypes.POINTER(ctypes.c_uint32),
+                                       ctypes.POINTER(ctypes.c_uint32),
+                                       ctypes.POINTER(ctypes.c_int32)], ctypes.c_int32),
+    "gz_export_sketches": ([ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint32,
+                            ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64)],
+                           ctypes.c_int32),
+    "gz_sketch_storage": ([ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p),
+                           ctypes.POINTER(ctypes.c_uint64)], ctypes.c_int32),
+    "gz_get_tuning": ([ctypes.c_void_p, ctypes.POINTER(gz_tuning)], ctypes.c_int32),
+    "gz_set_tuning": ([ctypes.c_void_p, ctypes.POINTER(gz_tuning)], ctypes.c_int32),
+    "gz_status_str": ([ctypes.c_int32], ctypes.c_char_p),
+    "gz_last_error": ([], ctypes.c_char_p),
+}
+
+# exported names declared in include/gz.h and the optional server/autotune headers
+EXPORTED = list(_SIGS)
+
+
+def lib():
+    """Load libgz.so (raises if it is missing: there is no fallback path)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
+                           "(there is no CPU fallback)")
+    L = ctypes.CDLL(LIB_PATH)
+    for name, (args, res) in _SIGS.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = res
+    _extend_server(L)
+    _lib = L
+    return L
+
+
+def _extend_server(L):
+    from . import server as _srv  # noqa: F401  (declares the server entry points)
+    _srv._declare(L)
+
+
+def _status_name(s: int) -> str:
+    try:
+        return lib().gz_status_str(s).decode()
+    except Exception:  # library not loaded yet
+        return str(s)
+
+
+def check(status: int, allow=()):
+    if status != GZ_OK and status not in allow:
+        raise GzError(status, lib().gz_last_error().decode())
+    return status
+
+
+# ------------------------------------------------------------- marshalling
+
+
+def _is_torch(x) -> bool:
+    return type(x).__module__.startswith("torch")
+
+
+def _stream_handle(stream):
+    if stream is not None:
+        return ctypes.c_void_p(int(getattr(stream, "cuda_stream", stream)))
+    try:
+        import torch
+
+        if torch.cuda.is_available():
+            return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    except Exception:
+        pass
+    return ctypes.c_void_p(0)
+
+
+def _u32_arg(x):
+    """-> (pointer, flags, keepalive) for a uint32 array on the host or the device."""
+    if _is_torch(x):
+        import torch
+
+        if x.dtype not in (torch.int32, torch.uint32):
+            raise TypeError("expected an int32/uint32 tensor")
+        if not x.is_contiguous():
+            raise ValueError("tensor must be contiguous")
+        if x.is_cuda:
+            return ctypes.c_void_p(x.data_ptr()), GZ_DEVICE_PTR, x
+        x = x.numpy()
+    a = np.ascontiguousarray(x, dtype=np.uint32)
+    return ctypes.c_void_p(a.ctypes.data), 0, a
+
+
+class Graph:
+    """One graph's device-resident node sketches."""
+
+    def __init__(self, V: int, seed: int, rounds: int = 0):
+        L = lib()
+        h = ctypes.c_void_p()
+        cfg = gz_config(rounds, 0, 0)
+        check(L.gz_sketch_init(ctypes.byref(h), V, seed & 0xFFFFFFFFFFFFFFFF, ctypes.byref(cfg)))
+        self._h = h
+        self.seed = seed
+        dims = [ctypes.c_uint32() for _ in range(4)]
+        n = ctypes.c_uint64()
+        check(L.gz_shape(h, *[ctypes.byref(d) for d in dims], ctypes.byref(n)))
+        self.V, self.R, self.C, self.B = (d.value for d in dims)
+        self.n = n.value
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().gz_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ingestion ---------------------------------------------------------
+    def ingest(self, src, dst, flags: int = 0, stream=None):
+        ps, fs, ks = _u32_arg(src)
+        pd, fd, kd = _u32_arg(dst)
+        if fs != fd:
+            raise ValueError("src and dst must both live on the host or both on the device")
+        n = len(ks)
+        if len(kd) != n:
+            raise ValueError("src and dst lengths differ")
+        return check(lib().gz_ingest(self._h, ps, pd, n, fs | flags, _stream_handle(stream)))
+
+    def update_sketch_batch(self, node: int, nbrs, flags: int = 0, stream=None):
+        p, f, k = _u32_arg(nbrs)
+        return check(lib().gz_update_sketch_batch(self._h, node, p, len(k), f | flags,
+                                                  _stream_handle(stream)))
+
+    def reset(self, stream=None):
+        return check(lib().gz_reset(self._h, _stream_handle(stream)))
+
+    def flush(self):
+        return check(lib().gz_flush(self._h))
+
+    # queries -----------------------------------------------------------
+    def query(self, forest: bool = True):
+        """-> (status, labels uint32[V], num_cc, forest uint32[F, 2] or None)."""
+        labels = np.zeros(self.V, np.uint32)
+        ncc = ctypes.c_uint32()
+        edges = np.zeros(2 * max(self.V - 1, 1), np.uint32) if forest else None
+        ne = ctypes.c_uint64()
+        st = lib().gz_query(
+            self._h, labels.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)), ctypes.byref(ncc),
+            edges.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)) if forest else None,
+            ctypes.byref(ne) if forest else None)
+        check(st, allow=(GZ_ESKETCH_FAIL,))
+        f = edges[: 2 * ne.value].reshape(-1, 2).copy() if forest else None
+        return st, labels, ncc.value, f
+
+    def connected_components(self):
+        labels = np.zeros(self.V, np.uint32)
+        ncc = ctypes.c_uint32()
+        st = lib().gz_connected_components(
+            self._h, labels.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)), ctypes.byref(ncc))
+        check(st, allow=(GZ_ESKETCH_FAIL,))
+        return st, labels, ncc.value
+
+    def list_spanning_forest(self):
+        edges = np.zeros(2 * max(self.V - 1, 1), np.uint32)
+        ne = ctypes.c_uint64()
+        st = lib().gz_list_spanning_forest(
+            self._h, edges.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)), ctypes.byref(ne))
+        check(st, allow=(GZ_ESKETCH_FAIL,))
+        return st, edges[: 2 * ne.value].reshape(-1, 2).copy()
+
+    def export(self, lo: int = 0, hi: int | None = None):
+        """Canonical nested sketches: (alpha, gamma) uint64[hi-lo, R, C, B]."""
+        hi = self.V if hi is None else hi
+        shape = (hi - lo, self.R, self.C, self.B)
+        a = np.zeros(shape, np.uint64)
+        g = np.zeros(shape, np.uint64)
+        check(lib().gz_export_sketches(self._h, lo, hi,
+                                       a.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
+                                       g.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))))
+        return a, g
+
+    def storage(self):
+        p = ctypes.c_void_p()
+        n = ctypes.c_uint64()
+        check(lib().gz_sketch_storage(self._h, ctypes.byref(p), ctypes.byref(n)))
+        return p.value, n.value
+
+    @property
+    def tuning(self) -> dict:
+        t = gz_tuning()
+        check(lib().gz_get_tuning(self._h, ctypes.byref(t)))
+        return t.as_dict()
+
+    def set_tuning(self, **kw):
+        t = gz_tuning()
+        check(lib().gz_get_tuning(self._h, ctypes.byref(t)))
+        for k, v in kw.items():
+            setattr(t, k, int(v))
+        check(lib().gz_set_tuning(self._h, ctypes.byref(t)))
+
+
+def _handles(graphs):
+    arr = (ctypes.c_void_p * len(graphs))(*[g.handle for g in graphs])
+    return arr
+
+
+def ingest_multi(graphs, offs, src, dst, flags: int = 0, stream=None):
+    """Fused ingest over several graphs: updates offs[k]..offs[k+1]-1 go to graphs[k]."""
+    ps, fs, ks = _u32_arg(src)
+    pd, fd, kd = _u32_arg(dst)
+    if fs != fd:
+        raise ValueError("src and dst must both live on the host or both on the device")
+    o = np.ascontiguousarray(offs, np.uint64)
+    if len(o) != len(graphs) + 1:
+        raise ValueError("offs needs len(graphs)+1 entries")
+    return check(lib().gz_ingest_multi(_handles(graphs), len(graphs),
+                                       o.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), ps, pd,
+                                       fs | flags, _stream_handle(stream)))
+
+
+def connected_components_multi(graphs):
+    """-> (labels per graph (list of uint32 arrays), num_cc uint32[G], status int32[G])."""
+    G = len(graphs)
+    total = sum(g.V for g in graphs)
+    labels = np.zeros(total, np.uint32)
+    ncc = np.zeros(G, np.uint32)
+    stt = np.zeros(G, np.int32)
+    st = lib().gz_connected_components_multi(
+        _handles(graphs), G, labels.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)),
+        ncc.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)),
+        stt.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+    check(st, allow=(GZ_ESKETCH_FAIL,))
+    out, o = [], 0
+    for g in graphs:
+        out.append(labels[o:o + g.V])
+        o += g.V
+    return out, ncc, stt

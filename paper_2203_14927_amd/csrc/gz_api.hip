@@ -1,0 +1,386 @@
+// C-ABI entry points: graph lifecycle, seeds, export, status reporting.
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "gz_device.h"
+#include "gz_internal.h"
+
+namespace gz {
+
+namespace {
+thread_local std::string g_last_error;
+
+uint32_t bitlen64(uint64_t x) {
+    uint32_t n = 0;
+    while (x) { ++n; x >>= 1; }
+    return n;
+}
+
+// SplitMix64 (Steele, Lea, Flood, OOPSLA 2014): one output per call
+uint64_t splitmix64(uint64_t& st) {
+    st += 0x9E3779B97F4A7C15ull;
+    uint64_t z = st;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+uint32_t host_hash(uint64_t mult, uint64_t incr, uint64_t x) {
+    return (uint32_t)((mult * x + incr) >> 32);
+}
+}  // namespace
+
+gz_status fail(gz_status s, const std::string& msg) {
+    g_last_error = msg;
+    return s;
+}
+
+gz_status hip_fail(hipError_t e, const char* what) {
+    g_last_error = std::string(what) + ": " + hipGetErrorString(e);
+    return e == hipErrorOutOfMemory ? GZ_ENOMEM : GZ_EDEVICE;
+}
+
+int device_cu_count() {
+    static int cached[64] = {0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 256;
+    if (!cached[dev % 64]) {
+        int n = 0;
+        if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            n <= 0)
+            n = 256;
+        cached[dev % 64] = n;
+    }
+    return cached[dev % 64];
+}
+
+uint32_t default_lds_rows(uint32_t B) { return std::min<uint32_t>(B, 16u); }
+
+// exact-depth rows -> nested rows (row b = XOR of rows d >= b), widened to 64 bits
+__global__ void k_export(const uint32_t* __restrict__ sk, uint32_t lo, uint32_t hi, uint32_t R,
+                         uint32_t B, uint32_t P, uint64_t* __restrict__ alpha,
+                         uint64_t* __restrict__ gamma) {
+    const uint64_t total = (uint64_t)(hi - lo) * P;
+    for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+         t += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t v = lo + (uint32_t)(t / P);
+        const uint32_t p = (uint32_t)(t % P);  // p = r * C + c
+        const uint32_t* base = sk + (uint64_t)v * kPlanes * B * P + p;
+        const uint64_t out0 = (t / P) * (uint64_t)R * kC * B + (uint64_t)p * B;
+        uint32_t a = 0, gl = 0, gh = 0;
+        for (int b = (int)B - 1; b >= 0; --b) {
+            a ^= base[(uint64_t)(0 * B + b) * P];
+            gl ^= base[(uint64_t)(1 * B + b) * P];
+            gh ^= base[(uint64_t)(2 * B + b) * P];
+            alpha[out0 + b] = a;
+            gamma[out0 + b] = ((uint64_t)gh << 32) | gl;
+        }
+    }
+}
+
+gz_status export_nested(gz_graph* g, uint32_t lo, uint32_t hi, uint64_t* alpha, uint64_t* gamma) {
+    const uint64_t n = (uint64_t)(hi - lo) * g->R * kC * g->B;
+    if (n == 0) return GZ_OK;
+    uint64_t *da = nullptr, *dg = nullptr;
+    GZ_HIP(hipMalloc((void**)&da, n * 8));
+    if (hipMalloc((void**)&dg, n * 8) != hipSuccess) {
+        hipFree(da);
+        return fail(GZ_ENOMEM, "export buffer");
+    }
+    hipStream_t s = g->qstream;
+    hipError_t e = hipStreamWaitEvent(s, g->last, 0);
+    if (e == hipSuccess) {
+        const uint64_t total = (uint64_t)(hi - lo) * g->P;
+        const uint32_t blocks = (uint32_t)std::min<uint64_t>((total + 255) / 256, 65535);
+        k_export<<<blocks, 256, 0, s>>>(g->sk, lo, hi, g->R, g->B, g->P, da, dg);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(alpha, da, n * 8, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(gamma, dg, n * 8, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    hipFree(da);
+    hipFree(dg);
+    if (e != hipSuccess) return hip_fail(e, "export");
+    return GZ_OK;
+}
+
+gz_status init_graph(gz_graph** out, uint32_t V, uint64_t seed, const gz_config* cfg) {
+    if (!out) return fail(GZ_EINVAL, "null output handle");
+    *out = nullptr;
+    if (V < 2 || V > GZ_MAX_NODES) return fail(GZ_EINVAL, "V must be in [2, 65536]");
+    gz_graph* g = new gz_graph();
+    GZ_HIP(hipGetDevice(&g->device));
+    g->V = V;
+    g->n = (uint64_t)V * (V - 1) / 2;
+    g->R = bitlen64((uint64_t)V - 1) + 1;
+    g->C = kC;
+    g->B = bitlen64(g->n - 1) + 1;
+    if (cfg && cfg->rounds) g->R = cfg->rounds;
+    if (g->R > 64) {
+        delete g;
+        return fail(GZ_EINVAL, "too many rounds");
+    }
+    g->P = g->R * kC;
+    g->seed = seed;
+    // seeds: SplitMix64 stream in (round, column, hash) order, multiplier then increment
+    g->seeds_host.resize((size_t)g->P * 6);
+    uint64_t st = seed;
+    for (uint32_t p = 0; p < g->P; ++p)
+        for (uint32_t k = 0; k < 6; ++k) g->seeds_host[(size_t)p * 6 + k] = splitmix64(st);
+    for (uint32_t p = 0; p < g->P; ++p) {
+        const uint64_t* s = &g->seeds_host[(size_t)p * 6];
+        uint64_t chk0 = ((uint64_t)host_hash(s[2], s[3], 0) << 32) | host_hash(s[4], s[5], 0);
+        if (chk0 == 0) {
+            delete g;
+            return fail(GZ_EINVAL, "seed gives a zero checksum for index 0; pick another seed");
+        }
+    }
+    std::vector<uint32_t> soa((size_t)kSeedWords * g->P);
+    for (uint32_t p = 0; p < g->P; ++p) {
+        const uint64_t* s = &g->seeds_host[(size_t)p * 6];
+        for (uint32_t k = 0; k < 6; ++k) {
+            soa[(size_t)(2 * k) * g->P + p] = (uint32_t)s[k];
+            soa[(size_t)(2 * k + 1) * g->P + p] = (uint32_t)(s[k] >> 32);
+        }
+    }
+    g->sk_words = (uint64_t)V * kPlanes * g->B * g->P;
+    hipError_t e = hipMalloc((void**)&g->sk, g->sk_words * 4);
+    if (e != hipSuccess) {
+        delete g;
+        return fail(GZ_ENOMEM, "out of device memory for the sketches");
+    }
+    e = hipMalloc((void**)&g->seeds, soa.size() * 4);
+    if (e == hipSuccess) e = hipMemcpy(g->seeds, soa.data(), soa.size() * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemset(g->sk, 0, g->sk_words * 4);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&g->qstream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&g->last, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventRecord(g->last, g->qstream);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+        gz_status s = hip_fail(e, "graph init");
+        hipFree(g->sk);
+        hipFree(g->seeds);
+        delete g;
+        return s;
+    }
+    g->tuning.lds_rows = default_lds_rows(g->B);
+    g->tuning.chunk = 2048;
+    g->tuning.wgs_per_cu = 4;
+    // smallest multiple of 64 with good lane use for P pairs (J = wg / P groups)
+    uint32_t best = 0;
+    double best_use = -1.0;
+    for (uint32_t wg = 64; wg <= 512; wg += 64) {
+        if (wg < g->P) continue;
+        double use = (double)((wg / g->P) * g->P) / wg;
+        if (use > best_use + 0.02) {
+            best_use = use;
+            best = wg;
+        }
+    }
+    g->tuning.wg_size = best ? best : ((g->P + 63) / 64) * 64;
+    *out = g;
+    return GZ_OK;
+}
+
+}  // namespace gz
+
+using namespace gz;
+
+extern "C" {
+
+gz_status gz_sketch_init(gz_graph** out, uint32_t V, uint64_t seed, const gz_config* cfg) {
+    return init_graph(out, V, seed, cfg);
+}
+
+gz_status gz_free(gz_graph* g) {
+    if (!g) return GZ_OK;
+    hipStreamSynchronize(g->qstream);
+    hipEventSynchronize(g->last);
+    free_ingest_scratch(g->ing);
+    free_query_scratch(g->q);
+    hipFree(g->sk);
+    hipFree(g->seeds);
+    hipEventDestroy(g->last);
+    hipStreamDestroy(g->qstream);
+    delete g;
+    return GZ_OK;
+}
+
+gz_status gz_shape(const gz_graph* g, uint32_t* V, uint32_t* R, uint32_t* C, uint32_t* B,
+                   uint64_t* n) {
+    if (!g) return fail(GZ_EINVAL, "null graph");
+    if (V) *V = g->V;
+    if (R) *R = g->R;
+    if (C) *C = g->C;
+    if (B) *B = g->B;
+    if (n) *n = g->n;
+    return GZ_OK;
+}
+
+gz_status gz_reset(gz_graph* g, hipStream_t stream) {
+    if (!g) return fail(GZ_EINVAL, "null graph");
+    GZ_HIP(hipStreamWaitEvent(stream, g->last, 0));
+    GZ_HIP(hipMemsetAsync(g->sk, 0, g->sk_words * 4, stream));
+    GZ_HIP(hipEventRecord(g->last, stream));
+    return GZ_OK;
+}
+
+gz_status gz_update_sketch_batch(gz_graph* g, uint32_t node, const uint32_t* nbrs, uint64_t count,
+                                 uint32_t flags, hipStream_t stream) {
+    if (!g) return fail(GZ_EINVAL, "null graph");
+    return update_node_batch(g, node, nbrs, count, flags, stream);
+}
+
+gz_status gz_ingest(gz_graph* g, const uint32_t* src, const uint32_t* dst, uint64_t N,
+                    uint32_t flags, hipStream_t stream) {
+    if (!g) return fail(GZ_EINVAL, "null graph");
+    if (N == 0) return GZ_OK;
+    gz_graph* gs[1] = {g};
+    return ingest_fused(gs, 1, nullptr, src, dst, N, flags, stream, g->ing);
+}
+
+gz_status gz_ingest_multi(gz_graph* const* gs, uint32_t G, const uint64_t* offs,
+                          const uint32_t* src, const uint32_t* dst, uint32_t flags,
+                          hipStream_t stream) {
+    if (!gs || !offs || G == 0) return fail(GZ_EINVAL, "null argument");
+    for (uint32_t k = 0; k < G; ++k) {
+        if (!gs[k]) return fail(GZ_EINVAL, "null graph handle");
+        for (uint32_t j = 0; j < k; ++j)
+            if (gs[j] == gs[k]) return fail(GZ_EINVAL, "graph listed twice");
+    }
+    const uint64_t N = offs[G];
+    if (N == 0) return GZ_OK;
+    std::unique_lock<std::mutex> lock;
+    IngestScratch& S = shared_ingest_scratch(gs[0]->device, lock);
+    return ingest_fused(gs, G, offs, src, dst, N, flags, stream, S);
+}
+
+gz_status gz_flush(gz_graph* g) {
+    if (!g) return fail(GZ_EINVAL, "null graph");
+    GZ_HIP(hipEventSynchronize(g->last));
+    if (g->pending_error) {
+        g->pending_error = false;
+        uint32_t sticky = 0;
+        uint32_t* ctls[2] = {g->ing.ctl, nullptr};
+        std::unique_lock<std::mutex> lock;
+        IngestScratch& shared = shared_ingest_scratch(g->device, lock);
+        ctls[1] = shared.ctl;
+        for (uint32_t* c : ctls) {
+            if (!c) continue;
+            uint32_t v = 0;
+            GZ_HIP(hipMemcpy(&v, c + 3, 4, hipMemcpyDeviceToHost));
+            if (v) {
+                sticky = 1;
+                GZ_HIP(hipMemset(c + 3, 0, 4));
+            }
+        }
+        if (sticky) return fail(GZ_EINVAL, "an asynchronous update batch was invalid and skipped");
+    }
+    return GZ_OK;
+}
+
+gz_status gz_query(gz_graph* g, uint32_t* labels, uint32_t* num_cc, uint32_t* edges,
+                   uint64_t* num_edges) {
+    if (!g) return fail(GZ_EINVAL, "null graph");
+    gz_status st = gz_flush(g);
+    if (st) return st;
+    QueryResult res;
+    gz_graph* gs[1] = {g};
+    st = boruvka(gs, 1, edges != nullptr || num_edges != nullptr, res);
+    if (st) return st;
+    if (labels) std::memcpy(labels, res.labels.data(), 4ull * g->V);
+    if (num_cc) *num_cc = res.num_cc[0];
+    if (edges) std::memcpy(edges, res.forest.data(), 4ull * res.forest.size());
+    if (num_edges) *num_edges = res.forest.size() / 2;
+    if (res.status[0] != GZ_OK)
+        return fail(GZ_ESKETCH_FAIL, "a component was still active after the last round");
+    return GZ_OK;
+}
+
+gz_status gz_connected_components(gz_graph* g, uint32_t* labels, uint32_t* num_cc) {
+    if (!labels) return fail(GZ_EINVAL, "null labels");
+    return gz_query(g, labels, num_cc, nullptr, nullptr);
+}
+
+gz_status gz_list_spanning_forest(gz_graph* g, uint32_t* edges, uint64_t* num_edges) {
+    if (!edges || !num_edges) return fail(GZ_EINVAL, "null output");
+    return gz_query(g, nullptr, nullptr, edges, num_edges);
+}
+
+gz_status gz_connected_components_multi(gz_graph* const* gs, uint32_t G, uint32_t* labels,
+                                        uint32_t* num_cc, int32_t* status) {
+    if (!gs || !labels || G == 0) return fail(GZ_EINVAL, "null argument");
+    for (uint32_t k = 0; k < G; ++k) {
+        gz_status st = gz_flush(gs[k]);
+        if (st) return st;
+    }
+    QueryResult res;
+    gz_status st = boruvka(gs, G, false, res);
+    if (st) return st;
+    std::memcpy(labels, res.labels.data(), 4ull * res.labels.size());
+    bool any_fail = false;
+    for (uint32_t k = 0; k < G; ++k) {
+        if (num_cc) num_cc[k] = res.num_cc[k];
+        if (status) status[k] = res.status[k];
+        any_fail |= res.status[k] != GZ_OK;
+    }
+    if (any_fail) return fail(GZ_ESKETCH_FAIL, "some graph still had an active component");
+    return GZ_OK;
+}
+
+gz_status gz_export_sketches(gz_graph* g, uint32_t node_lo, uint32_t node_hi, uint64_t* alpha,
+                             uint64_t* gamma) {
+    if (!g || !alpha || !gamma) return fail(GZ_EINVAL, "null argument");
+    if (node_lo > node_hi || node_hi > g->V) return fail(GZ_EINVAL, "bad node range");
+    gz_status st = gz_flush(g);
+    if (st) return st;
+    return export_nested(g, node_lo, node_hi, alpha, gamma);
+}
+
+gz_status gz_sketch_storage(const gz_graph* g, void** dev_ptr, uint64_t* bytes) {
+    if (!g) return fail(GZ_EINVAL, "null graph");
+    if (dev_ptr) *dev_ptr = g->sk;
+    if (bytes) *bytes = g->sk_words * 4;
+    return GZ_OK;
+}
+
+gz_status gz_get_tuning(const gz_graph* g, gz_tuning* t) {
+    if (!g || !t) return fail(GZ_EINVAL, "null argument");
+    *t = g->tuning;
+    return GZ_OK;
+}
+
+gz_status gz_set_tuning(gz_graph* g, const gz_tuning* t) {
+    if (!g || !t) return fail(GZ_EINVAL, "null argument");
+    if (t->wg_size < 64 || t->wg_size > 1024 || t->wg_size % 64 || t->wg_size < g->P)
+        return fail(GZ_EINVAL, "wg_size must be a multiple of 64 in [max(64, R*C), 1024]");
+    if (t->lds_rows < 1) return fail(GZ_EINVAL, "lds_rows must be >= 1");
+    if (t->chunk < 1 || t->chunk > 16384) return fail(GZ_EINVAL, "chunk must be in [1, 16384]");
+    if (t->wgs_per_cu < 1 || t->wgs_per_cu > 64) return fail(GZ_EINVAL, "wgs_per_cu in [1, 64]");
+    size_t smem = (size_t)t->chunk * 4 +
+                  (size_t)kPlanes * std::min(t->lds_rows, g->B) * ((g->P + 63) / 64 * 64) * 4;
+    if (smem > 160 * 1024) return fail(GZ_EINVAL, "LDS tile + chunk exceed 160 KiB");
+    g->tuning = *t;
+    return GZ_OK;
+}
+
+const char* gz_status_str(gz_status s) {
+    switch (s) {
+        case GZ_OK: return "GZ_OK";
+        case GZ_EINVAL: return "GZ_EINVAL";
+        case GZ_ENOMEM: return "GZ_ENOMEM";
+        case GZ_EDEVICE: return "GZ_EDEVICE";
+        case GZ_ESKETCH_FAIL: return "GZ_ESKETCH_FAIL";
+        case GZ_EBUSY: return "GZ_EBUSY";
+        case GZ_ESTATE: return "GZ_ESTATE";
+        default: return "GZ_UNKNOWN";
+    }
+}
+
+const char* gz_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

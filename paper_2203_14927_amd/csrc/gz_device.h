@@ -1,0 +1,78 @@
+// Device-side arithmetic of the hash contract (see include/gz.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "gz_internal.h"
+
+namespace gz {
+
+// multiply-add-shift: ((m * x + i) mod 2^64) >> 32 for a 32-bit key x, with the
+// 64-bit multiplier split into words.  (m*x) mod 2^64 = mlo*x + (mhi*x mod 2^32)*2^32,
+// so the high word is hi32(mlo*x + i) + mhi*x (mod 2^32): two v_mad_u64_u32.
+__device__ __forceinline__ uint32_t mas_hash(uint32_t mlo, uint32_t mhi, uint64_t incr,
+                                             uint32_t x) {
+    uint64_t t = (uint64_t)mlo * x + incr;
+    return (uint32_t)(t >> 32) + mhi * x;
+}
+
+// Seeds of one (round, column) pair held in registers.
+struct PairSeeds {
+    uint32_t row_mlo, row_mhi, chi_mlo, chi_mhi, clo_mlo, clo_mhi;
+    uint64_t row_inc, chi_inc, clo_inc;
+};
+
+__device__ __forceinline__ PairSeeds load_pair_seeds(const uint32_t* __restrict__ seeds,
+                                                     uint32_t P, uint32_t p) {
+    PairSeeds s;
+    s.row_mlo = seeds[S_ROW_MLO * P + p];
+    s.row_mhi = seeds[S_ROW_MHI * P + p];
+    s.row_inc = (uint64_t)seeds[S_ROW_ILO * P + p] | ((uint64_t)seeds[S_ROW_IHI * P + p] << 32);
+    s.chi_mlo = seeds[S_CHI_MLO * P + p];
+    s.chi_mhi = seeds[S_CHI_MHI * P + p];
+    s.chi_inc = (uint64_t)seeds[S_CHI_ILO * P + p] | ((uint64_t)seeds[S_CHI_IHI * P + p] << 32);
+    s.clo_mlo = seeds[S_CLO_MLO * P + p];
+    s.clo_mhi = seeds[S_CLO_MHI * P + p];
+    s.clo_inc = (uint64_t)seeds[S_CLO_ILO * P + p] | ((uint64_t)seeds[S_CLO_IHI * P + p] << 32);
+    return s;
+}
+
+// depth = min(count of trailing zeros of the row hash, B-1); a zero hash counts 32
+__device__ __forceinline__ uint32_t row_depth(const PairSeeds& s, uint32_t x, uint32_t Bm1) {
+    uint32_t h = mas_hash(s.row_mlo, s.row_mhi, s.row_inc, x);
+    uint32_t tz = __builtin_ctzg(h, 32);
+    return tz < Bm1 ? tz : Bm1;
+}
+
+__device__ __forceinline__ uint32_t chk_hi(const PairSeeds& s, uint32_t x) {
+    return mas_hash(s.chi_mlo, s.chi_mhi, s.chi_inc, x);
+}
+
+__device__ __forceinline__ uint32_t chk_lo(const PairSeeds& s, uint32_t x) {
+    return mas_hash(s.clo_mlo, s.clo_mhi, s.clo_inc, x);
+}
+
+// position of pair {u, v} in the characteristic vector; ids < 2^16 keep it in 32 bits
+__device__ __forceinline__ uint32_t edge_index(uint32_t u, uint32_t v) {
+    uint32_t lo = u < v ? u : v;
+    uint32_t hi = u < v ? v : u;
+    return ((hi * (hi - 1u)) >> 1) + lo;
+}
+
+// inverse of edge_index: hi = largest v with v(v-1)/2 <= i
+__device__ __forceinline__ void edge_pair(uint32_t i, uint32_t* u, uint32_t* v) {
+    double di = (double)i;
+    uint32_t hi = (uint32_t)((1.0 + sqrt(1.0 + 8.0 * di)) * 0.5);
+    // correct a possible rounding step in either direction
+    while ((uint64_t)hi * (hi - 1) / 2 > i) --hi;
+    while ((uint64_t)(hi + 1) * hi / 2 <= i) ++hi;
+    *v = hi;
+    *u = i - (uint32_t)((uint64_t)hi * (hi - 1) / 2);
+}
+
+__device__ __forceinline__ uint32_t uniform(uint32_t x) {
+    return __builtin_amdgcn_readfirstlane(x);
+}
+
+}  // namespace gz

@@ -1,0 +1,156 @@
+// Internal types of the CubeSketch library (host and device).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "gz.h"
+
+namespace gz {
+
+constexpr uint32_t kC = GZ_COLUMNS;   // columns per CubeSketch
+constexpr uint32_t kPlanes = 3;       // alpha, gamma low word, gamma high word
+constexpr uint32_t kSeedWords = 12;   // per (round, column): 3 hashes x (mult, incr) x 2 words
+constexpr uint32_t kNone = 0xFFFFFFFFu;
+
+// Seeds are stored structure-of-arrays: word k of pair p at seeds[k * P + p].
+enum SeedWord : uint32_t {
+    S_ROW_MLO = 0, S_ROW_MHI, S_ROW_ILO, S_ROW_IHI,
+    S_CHI_MLO, S_CHI_MHI, S_CHI_ILO, S_CHI_IHI,
+    S_CLO_MLO, S_CLO_MHI, S_CLO_ILO, S_CLO_IHI
+};
+
+// Per-graph data a kernel needs; kept in a device table for fused launches.
+//
+// Sketch words of node v (32-bit, "exact-depth" basis: row d holds the XOR of
+// the indices whose depth is exactly d, so each update touches one row per
+// column):  sk[((v * kPlanes + plane) * B + d) * P + p],  p = r * C + c.
+// Planes: 0 = alpha (indices are < 2^31, the high word is always zero),
+// 1 = gamma low word, 2 = gamma high word.  The nested rows of the paper are
+// the suffix XORs over d >= b of this basis (a linear, invertible change).
+struct GraphDesc {
+    uint32_t* sk;
+    const uint32_t* seeds;
+    uint64_t n;          // V(V-1)/2
+    uint32_t V, R, B, P;
+    uint32_t node_base;  // first global node id in a fused launch
+    uint32_t pad;
+};
+
+// One unit of work of the persistent sketch-update kernel: up to `chunk`
+// endpoint entries of one node, stored contiguously in the grouped array.
+struct WorkItem {
+    uint32_t begin;   // first entry in the grouped index array
+    uint32_t count;
+    uint32_t gnode;   // global node id
+    uint32_t graph;   // index into the descriptor table
+    uint32_t shared;  // 1 if other items of this launch update the same node
+    uint32_t pad;
+};
+
+// Arguments of a fused ingest launch sequence, read by the kernels from device
+// memory so that a captured graph can be replayed on new inputs.
+struct IngestArgs {
+    const uint32_t* src;
+    const uint32_t* dst;
+    const uint64_t* offs;     // G+1 update offsets (device)
+    uint64_t N;
+    uint32_t G;
+    uint32_t T;               // total nodes over all graphs
+    uint32_t chunk;
+    uint32_t lds_rows;
+};
+
+// Device scratch of the ingest path, grown on demand.
+struct IngestScratch {
+    int device = -1;
+    uint64_t cap_updates = 0;   // capacity of the grouped array (entries = 2N)
+    uint32_t cap_nodes = 0;
+    uint32_t cap_graphs = 0;
+    uint64_t cap_items = 0;
+    uint32_t* counts = nullptr;     // T: entries per node (u32)
+    uint64_t* packed = nullptr;     // T+1: scanned (entries | items << 40)
+    uint64_t* block_sums = nullptr; // scan partials
+    uint32_t* cursor = nullptr;     // T
+    uint32_t* grouped = nullptr;    // 2N edge indices grouped by endpoint
+    WorkItem* items = nullptr;
+    uint32_t* ctl = nullptr;        // [0] ticket, [1] n_items, [2] call error, [3] sticky errors
+    IngestArgs* args = nullptr;
+    uint64_t* offs = nullptr;       // G+1
+    GraphDesc* descs = nullptr;     // G
+    uint32_t* staging = nullptr;    // host-pointer inputs copied here
+    uint64_t cap_staging = 0;
+    // pinned host copies of the per-call tables; reused once the previous
+    // call's uploads have completed (copied_ev)
+    IngestArgs* h_args = nullptr;
+    GraphDesc* h_descs = nullptr;
+    uint64_t* h_offs = nullptr;
+    uint32_t cap_h_graphs = 0;
+    hipEvent_t copied_ev = nullptr;
+    uint32_t* h_err = nullptr;
+};
+
+struct QueryScratch;
+
+}  // namespace gz
+
+struct gz_graph {
+    int device = 0;
+    uint32_t V = 0, R = 0, C = 0, B = 0, P = 0;
+    uint64_t n = 0;
+    uint64_t seed = 0;
+    uint32_t* sk = nullptr;            // device sketch words
+    uint64_t sk_words = 0;
+    uint32_t* seeds = nullptr;         // device seeds [12][P]
+    std::vector<uint64_t> seeds_host;  // [R][C][3][2]
+    gz_tuning tuning{};
+    hipStream_t qstream = nullptr;     // query stream
+    hipEvent_t last = nullptr;         // last submitted work on this graph
+    gz::IngestScratch ing;
+    gz::QueryScratch* q = nullptr;
+    bool pending_error = false;
+};
+
+namespace gz {
+
+// error reporting
+gz_status fail(gz_status s, const std::string& msg);
+gz_status hip_fail(hipError_t e, const char* what);
+#define GZ_HIP(call)                                              \
+    do {                                                          \
+        hipError_t e_ = (call);                                   \
+        if (e_ != hipSuccess) return ::gz::hip_fail(e_, #call);   \
+    } while (0)
+
+int device_cu_count();
+uint32_t default_lds_rows(uint32_t B);
+
+// ingest path (gz_ingest.hip)
+gz_status ingest_fused(gz_graph* const* gs, uint32_t G, const uint64_t* offs_host,
+                       const uint32_t* src, const uint32_t* dst, uint64_t N, uint32_t flags,
+                       hipStream_t stream, IngestScratch& S);
+gz_status update_node_batch(gz_graph* g, uint32_t node, const uint32_t* nbrs, uint64_t count,
+                            uint32_t flags, hipStream_t stream);
+void free_ingest_scratch(IngestScratch& S);
+IngestScratch& shared_ingest_scratch(int device, std::unique_lock<std::mutex>& lock);
+
+// query path (gz_query.hip)
+struct QueryResult {
+    std::vector<uint32_t> labels;    // sum V, local ids
+    std::vector<uint32_t> num_cc;    // per graph
+    std::vector<int32_t> status;     // per graph: GZ_OK / GZ_ESKETCH_FAIL
+    std::vector<uint32_t> forest;    // per graph pairs, concatenated
+    std::vector<uint64_t> forest_off;  // G+1 offsets into forest pairs
+    uint32_t rounds = 0;
+};
+gz_status boruvka(gz_graph* const* gs, uint32_t G, bool want_forest, QueryResult& out);
+void free_query_scratch(QueryScratch* q);
+
+// sketch export (gz_api.hip)
+gz_status export_nested(gz_graph* g, uint32_t lo, uint32_t hi, uint64_t* alpha, uint64_t* gamma);
+
+}  // namespace gz

@@ -1,0 +1,537 @@
+// Query path: Boruvka over XOR-merged node sketches, fully on the device.
+//
+// Paper: Boruvka emulated on characteristic vectors (Sec. 2.2), with one
+// fresh CubeSketch per round; each round (Sec. 4.2) (1) recovers an edge from
+// the sketch of every current component, (2) merges components along the
+// recovered edges, (3) sums the merged components' sketches.  Step (3) is done
+// lazily: the next round XOR-reduces the round-r rows of each component's
+// members.  CubeSketch query: Sec. 3.2 and Fig. "cube_code".
+//
+// Merging is deterministic: the recovered edges form a functional graph over
+// components (out-degree <= 1); its cycles are found by pointer doubling
+// (successor and running minimum) and each cycle drops the edge of its
+// smallest component; the kept edges join the forest and every resulting tree
+// takes its smallest component id as label.
+#include <algorithm>
+#include <cstring>
+
+#include "gz_device.h"
+#include "gz_internal.h"
+
+namespace gz {
+
+struct QueryScratch {
+    int device = -1;
+    uint32_t cap_nodes = 0, cap_graphs = 0, cap_wpr = 0;
+    uint32_t *comp = nullptr, *L = nullptr, *L2 = nullptr, *A = nullptr, *slot = nullptr;
+    uint32_t *done = nullptr, *hook = nullptr, *hedge = nullptr, *s = nullptr, *s2 = nullptr;
+    uint32_t *m = nullptr, *m2 = nullptr, *rootOf = nullptr, *newlab = nullptr, *merged = nullptr;
+    uint32_t *gof = nullptr, *acc = nullptr, *ctl = nullptr, *labels = nullptr;
+    uint32_t *gcount = nullptr, *gfail = nullptr, *foff = nullptr, *fcur = nullptr;
+    uint32_t *fcnt = nullptr;
+    uint32_t *fpairs = nullptr;
+    uint64_t *forest = nullptr, *fsorted = nullptr;
+    GraphDesc* descs = nullptr;
+};
+
+// ctl words
+enum : uint32_t { Q_NL = 0, Q_NA = 1, Q_NL2 = 2, Q_NF = 3 };
+
+// ---------------------------------------------------------------- kernels --
+
+__device__ __forceinline__ uint32_t q_graph_of_node(const GraphDesc* __restrict__ gd, uint32_t G,
+                                                    uint32_t node) {
+    uint32_t lo = 0, hi = G - 1;
+    while (lo < hi) {
+        uint32_t mid = (lo + hi + 1) >> 1;
+        if (gd[mid].node_base <= node) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+__global__ void k_q_init(uint32_t T, const GraphDesc* __restrict__ gd, uint32_t G,
+                         uint32_t* __restrict__ comp, uint32_t* __restrict__ L,
+                         uint32_t* __restrict__ done, uint32_t* __restrict__ gof,
+                         uint32_t* __restrict__ ctl) {
+    uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v == 0) {
+        ctl[Q_NL] = T;
+        ctl[Q_NA] = 0;
+        ctl[Q_NL2] = 0;
+        ctl[Q_NF] = 0;
+    }
+    if (v < T) {
+        comp[v] = v;
+        L[v] = v;
+        done[v] = 0;
+        gof[v] = G == 1 ? 0u : q_graph_of_node(gd, G, v);
+    }
+}
+
+__global__ void k_q_select(uint32_t r, const uint32_t* __restrict__ L, uint32_t* __restrict__ ctl,
+                           const uint32_t* __restrict__ done, const uint32_t* __restrict__ gof,
+                           const GraphDesc* __restrict__ gd, uint32_t* __restrict__ slot,
+                           uint32_t* __restrict__ A, uint32_t* __restrict__ hook,
+                           uint32_t* __restrict__ newlab, uint32_t* __restrict__ merged) {
+    const uint32_t nL = ctl[Q_NL];
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nL; i += gridDim.x * blockDim.x) {
+        const uint32_t X = L[i];
+        hook[X] = kNone;
+        newlab[X] = kNone;
+        merged[X] = 0;
+        if (!done[X] && r < gd[gof[X]].R) {
+            const uint32_t a = atomicAdd(&ctl[Q_NA], 1u);
+            A[a] = X;
+            slot[X] = a;
+        } else {
+            slot[X] = kNone;
+        }
+    }
+}
+
+// one wave per node: XOR the node's round-r rows into its component's
+// accumulator [slot][plane][d][c]
+__global__ void k_q_reduce(uint32_t r, uint32_t T, const uint32_t* __restrict__ comp,
+                           const uint32_t* __restrict__ slot, const uint32_t* __restrict__ gof,
+                           const GraphDesc* __restrict__ gd, uint32_t wpr,
+                           uint32_t* __restrict__ acc) {
+    const uint32_t waves = (gridDim.x * blockDim.x) >> 6;
+    const uint32_t lane = threadIdx.x & 63;
+    for (uint32_t v = (blockIdx.x * blockDim.x + threadIdx.x) >> 6; v < T; v += waves) {
+        const uint32_t sl = slot[comp[v]];
+        if (sl == kNone) continue;
+        const GraphDesc g = gd[gof[v]];
+        const uint32_t local = v - g.node_base;
+        const uint32_t words = kPlanes * g.B * kC;
+        const uint32_t* base = g.sk + (uint64_t)local * kPlanes * g.B * g.P + r * kC;
+        uint32_t* out = acc + (uint64_t)sl * wpr;
+        for (uint32_t w = lane; w < words; w += 64) {
+            const uint32_t c = w & (kC - 1);
+            const uint32_t row = w >> 3;  // plane * B + d
+            const uint32_t val = base[(uint64_t)row * g.P + c];
+            if (val) atomicXor(&out[w], val);
+        }
+    }
+}
+
+// 8 lanes per component (one per column): walk rows from deepest to row 0,
+// accumulating the nested bucket (suffix XOR of the exact-depth rows), and
+// keep the shallowest GOOD row; then the first column with a GOOD row wins.
+__global__ void k_q_query(uint32_t r, const uint32_t* __restrict__ A, const uint32_t* __restrict__ ctl,
+                          const uint32_t* __restrict__ acc, uint32_t wpr,
+                          const uint32_t* __restrict__ gof, const GraphDesc* __restrict__ gd,
+                          const uint32_t* __restrict__ comp, uint32_t* __restrict__ hook,
+                          uint32_t* __restrict__ hedge, uint32_t* __restrict__ done) {
+    const uint32_t nA = ctl[Q_NA];
+    const uint32_t gtid = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t a = gtid >> 3;
+    const uint32_t c = gtid & 7;
+    const bool valid = a < nA;
+    uint32_t X = 0, key = kNone, alpha_best = 0, nonempty = 0;
+    if (valid) {
+        X = A[a];
+        const GraphDesc g = gd[gof[X]];
+        const uint32_t p = r * kC + c;
+        const PairSeeds s = load_pair_seeds(g.seeds, g.P, p);
+        const uint32_t* in = acc + (uint64_t)a * wpr;
+        const uint32_t B = g.B;
+        uint32_t al = 0, glo = 0, ghi = 0;
+        for (int b = (int)B - 1; b >= 0; --b) {
+            al ^= in[(0 * B + b) * kC + c];
+            glo ^= in[(1 * B + b) * kC + c];
+            ghi ^= in[(2 * B + b) * kC + c];
+            if (al | glo | ghi) {
+                nonempty = 1;
+                if ((uint64_t)al < g.n && chk_lo(s, al) == glo && chk_hi(s, al) == ghi) {
+                    key = c * B + (uint32_t)b;
+                    alpha_best = al;
+                }
+            }
+        }
+    }
+    // reduce over the 8 lanes of this component: smallest key, any non-empty
+    for (uint32_t off = 1; off < 8; off <<= 1) {
+        const uint32_t k2 = __shfl_xor(key, off, 8);
+        const uint32_t a2 = __shfl_xor(alpha_best, off, 8);
+        const uint32_t n2 = __shfl_xor(nonempty, off, 8);
+        if (k2 < key) { key = k2; alpha_best = a2; }
+        nonempty |= n2;
+    }
+    if (!valid || c != 0) return;
+    if (!nonempty) {  // ZERO: no edge leaves X
+        done[X] = 1;
+        return;
+    }
+    if (key == kNone) return;  // FAIL
+    uint32_t u, v;
+    edge_pair(alpha_best, &u, &v);
+    const GraphDesc g = gd[gof[X]];
+    const uint32_t cu = comp[g.node_base + u], cv = comp[g.node_base + v];
+    const bool iu = cu == X, iv = cv == X;
+    if (iu == iv) return;  // the edge does not leave X: treated as FAIL
+    hook[X] = iu ? cv : cu;
+    hedge[X] = alpha_best;
+}
+
+__global__ void k_q_double_init(const uint32_t* __restrict__ L, const uint32_t* __restrict__ ctl,
+                                const uint32_t* __restrict__ hook, uint32_t* __restrict__ s,
+                                uint32_t* __restrict__ m) {
+    const uint32_t nL = ctl[Q_NL];
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nL; i += gridDim.x * blockDim.x) {
+        const uint32_t X = L[i];
+        const uint32_t h = hook[X];
+        s[X] = h == kNone ? X : h;
+        m[X] = X;
+    }
+}
+
+// one doubling step: s2 = s o s, m2 = min(m, m o s)
+__global__ void k_q_double(const uint32_t* __restrict__ L, const uint32_t* __restrict__ ctl,
+                           const uint32_t* __restrict__ s, const uint32_t* __restrict__ m,
+                           uint32_t* __restrict__ s2, uint32_t* __restrict__ m2) {
+    const uint32_t nL = ctl[Q_NL];
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nL; i += gridDim.x * blockDim.x) {
+        const uint32_t X = L[i];
+        const uint32_t y = s[X];
+        s2[X] = s[y];
+        m2[X] = min(m[X], m[y]);
+    }
+}
+
+// after enough doubling steps s[X] lies on X's terminal cycle and m[s[X]] is
+// that cycle's smallest component: the root of X's tree once its edge is cut
+__global__ void k_q_root(const uint32_t* __restrict__ L, uint32_t* __restrict__ ctl,
+                         const uint32_t* __restrict__ s, const uint32_t* __restrict__ m,
+                         const uint32_t* __restrict__ hook, const uint32_t* __restrict__ hedge,
+                         const uint32_t* __restrict__ gof, uint32_t* __restrict__ rootOf,
+                         uint32_t* __restrict__ newlab, uint32_t* __restrict__ merged,
+                         uint64_t* __restrict__ forest) {
+    const uint32_t nL = ctl[Q_NL];
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nL; i += gridDim.x * blockDim.x) {
+        const uint32_t X = L[i];
+        const uint32_t R = m[s[X]];
+        rootOf[X] = R;
+        atomicMin(&newlab[R], X);
+        if (hook[X] != kNone && X != R) {
+            merged[R] = 1;
+            const uint32_t f = atomicAdd(&ctl[Q_NF], 1u);
+            forest[f] = ((uint64_t)gof[X] << 32) | hedge[X];
+        }
+    }
+}
+
+__global__ void k_q_newcomps(const uint32_t* __restrict__ L, uint32_t* __restrict__ ctl,
+                             const uint32_t* __restrict__ rootOf,
+                             const uint32_t* __restrict__ newlab,
+                             const uint32_t* __restrict__ merged, uint32_t* __restrict__ done,
+                             uint32_t* __restrict__ L2) {
+    const uint32_t nL = ctl[Q_NL];
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nL; i += gridDim.x * blockDim.x) {
+        const uint32_t X = L[i];
+        const uint32_t R = rootOf[X];
+        if (newlab[R] == X) {
+            if (merged[R]) done[X] = 0;
+            L2[atomicAdd(&ctl[Q_NL2], 1u)] = X;
+        }
+    }
+}
+
+__global__ void k_q_relabel(uint32_t T, uint32_t* __restrict__ comp,
+                            const uint32_t* __restrict__ rootOf,
+                            const uint32_t* __restrict__ newlab) {
+    for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < T; v += gridDim.x * blockDim.x)
+        comp[v] = newlab[rootOf[comp[v]]];
+}
+
+__global__ void k_q_next_round(uint32_t* __restrict__ ctl) {
+    ctl[Q_NL] = ctl[Q_NL2];
+    ctl[Q_NL2] = 0;
+    ctl[Q_NA] = 0;
+}
+
+__global__ void k_q_finish(const uint32_t* __restrict__ L, const uint32_t* __restrict__ ctl,
+                           const uint32_t* __restrict__ done, const uint32_t* __restrict__ gof,
+                           uint32_t* __restrict__ gcount, uint32_t* __restrict__ gfail) {
+    const uint32_t nL = ctl[Q_NL];
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nL; i += gridDim.x * blockDim.x) {
+        const uint32_t X = L[i];
+        atomicAdd(&gcount[gof[X]], 1u);
+        if (!done[X]) atomicOr(&gfail[gof[X]], 1u);
+    }
+}
+
+__global__ void k_q_labels(uint32_t T, const uint32_t* __restrict__ comp,
+                           const uint32_t* __restrict__ gof, const GraphDesc* __restrict__ gd,
+                           uint32_t* __restrict__ out) {
+    for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < T; v += gridDim.x * blockDim.x)
+        out[v] = comp[v] - gd[gof[v]].node_base;
+}
+
+// forest: count per graph, scan, scatter into per-graph segments, then rank
+// each key inside its segment (keys are distinct) to sort by edge index
+__global__ void k_q_fcount(const uint64_t* __restrict__ forest, const uint32_t* __restrict__ ctl,
+                           uint32_t* __restrict__ fcnt) {
+    const uint32_t nF = ctl[Q_NF];
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nF; i += gridDim.x * blockDim.x)
+        atomicAdd(&fcnt[(uint32_t)(forest[i] >> 32)], 1u);
+}
+
+__global__ void k_q_fscan(const uint32_t* __restrict__ fcnt, uint32_t G, uint32_t* __restrict__ foff,
+                          uint32_t* __restrict__ fcur) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        uint32_t acc = 0;
+        for (uint32_t g = 0; g < G; ++g) {
+            const uint32_t c = fcnt[g];
+            foff[g] = acc;
+            fcur[g] = acc;
+            acc += c;
+        }
+        foff[G] = acc;
+    }
+}
+
+__global__ void k_q_fscatter(const uint64_t* __restrict__ forest, const uint32_t* __restrict__ ctl,
+                             uint32_t* __restrict__ fcur, uint64_t* __restrict__ out) {
+    const uint32_t nF = ctl[Q_NF];
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nF; i += gridDim.x * blockDim.x) {
+        const uint64_t k = forest[i];
+        out[atomicAdd(&fcur[(uint32_t)(k >> 32)], 1u)] = k;
+    }
+}
+
+constexpr uint32_t kRankThreads = 256;
+
+__global__ __launch_bounds__(kRankThreads) void k_q_frank(const uint64_t* __restrict__ keys,
+                                                           const uint32_t* __restrict__ ctl,
+                                                           const uint32_t* __restrict__ foff,
+                                                           uint32_t* __restrict__ pairs) {
+    __shared__ uint64_t tile[kRankThreads];
+    __shared__ uint32_t s_lo, s_hi;
+    const uint32_t nF = ctl[Q_NF];
+    const uint32_t i0 = blockIdx.x * kRankThreads;
+    if (i0 >= nF) return;
+    const uint32_t i = i0 + threadIdx.x;
+    const bool valid = i < nF;
+    const uint64_t key = valid ? keys[i] : 0;
+    const uint32_t g = (uint32_t)(key >> 32);
+    const uint32_t lo = valid ? foff[g] : 0, hi = valid ? foff[g + 1] : 0;
+    if (threadIdx.x == 0) {
+        s_lo = foff[(uint32_t)(keys[i0] >> 32)];
+        const uint32_t last = min(i0 + kRankThreads, nF) - 1;
+        s_hi = foff[(uint32_t)(keys[last] >> 32) + 1];
+    }
+    __syncthreads();
+    uint32_t rank = 0;
+    for (uint32_t j0 = s_lo; j0 < s_hi; j0 += kRankThreads) {
+        const uint32_t j = j0 + threadIdx.x;
+        tile[threadIdx.x] = j < s_hi ? keys[j] : ~0ull;
+        __syncthreads();
+        const uint32_t n = min(kRankThreads, s_hi - j0);
+        for (uint32_t t = 0; t < n; ++t) {
+            const uint32_t jj = j0 + t;
+            if (jj >= lo && jj < hi && tile[t] < key) ++rank;
+        }
+        __syncthreads();
+    }
+    if (valid) {
+        uint32_t u, v;
+        edge_pair((uint32_t)key, &u, &v);
+        pairs[2 * (lo + rank)] = u;
+        pairs[2 * (lo + rank) + 1] = v;
+    }
+}
+
+// ------------------------------------------------------------------- host --
+
+namespace {
+
+template <typename T>
+gz_status qalloc(T** p, uint64_t n) {
+    if (*p) GZ_HIP(hipFree(*p));
+    *p = nullptr;
+    if (hipMalloc((void**)p, std::max<uint64_t>(n, 1) * sizeof(T)) != hipSuccess) {
+        *p = nullptr;
+        return fail(GZ_ENOMEM, "out of device memory for the query scratch");
+    }
+    return GZ_OK;
+}
+
+gz_status ensure_query(QueryScratch& Q, uint32_t T, uint32_t G, uint32_t wpr) {
+    int dev = 0;
+    GZ_HIP(hipGetDevice(&dev));
+    Q.device = dev;
+    gz_status st;
+    if (T > Q.cap_nodes || !Q.comp) {
+        uint32_t** arrs[] = {&Q.comp, &Q.L, &Q.L2, &Q.A, &Q.slot, &Q.done, &Q.hook, &Q.hedge,
+                             &Q.s, &Q.s2, &Q.m, &Q.m2, &Q.rootOf, &Q.newlab, &Q.merged, &Q.gof,
+                             &Q.labels};
+        for (auto a : arrs)
+            if ((st = qalloc(a, T))) return st;
+        if ((st = qalloc(&Q.fpairs, 2ull * T))) return st;
+        if ((st = qalloc(&Q.forest, T))) return st;
+        if ((st = qalloc(&Q.fsorted, T))) return st;
+        if (!Q.ctl && (st = qalloc(&Q.ctl, 8))) return st;
+        Q.cap_nodes = T;
+        Q.cap_wpr = 0;
+    }
+    if (wpr > Q.cap_wpr || !Q.acc) {
+        if ((st = qalloc(&Q.acc, (uint64_t)T * wpr))) return st;
+        Q.cap_wpr = wpr;
+    }
+    if (G > Q.cap_graphs || !Q.descs) {
+        if ((st = qalloc(&Q.descs, G))) return st;
+        if ((st = qalloc(&Q.gcount, G))) return st;
+        if ((st = qalloc(&Q.gfail, G))) return st;
+        if ((st = qalloc(&Q.foff, (uint64_t)G + 1))) return st;
+        if ((st = qalloc(&Q.fcur, G))) return st;
+        if ((st = qalloc(&Q.fcnt, G))) return st;
+        Q.cap_graphs = G;
+    }
+    return GZ_OK;
+}
+
+uint32_t blocks_for(uint64_t n, uint32_t threads) {
+    uint64_t b = (n + threads - 1) / threads;
+    if (b < 1) b = 1;
+    if (b > 65535) b = 65535;
+    return (uint32_t)b;
+}
+
+uint32_t bitlen32(uint32_t x) {
+    uint32_t n = 0;
+    while (x) { ++n; x >>= 1; }
+    return n;
+}
+
+}  // namespace
+
+void free_query_scratch(QueryScratch* q) {
+    if (!q) return;
+    uint32_t* arrs[] = {q->comp, q->L, q->L2, q->A, q->slot, q->done, q->hook, q->hedge, q->s,
+                        q->s2, q->m, q->m2, q->rootOf, q->newlab, q->merged, q->gof, q->acc,
+                        q->ctl, q->labels, q->gcount, q->gfail, q->foff, q->fcur, q->fpairs,
+                        q->fcnt};
+    for (auto a : arrs) hipFree(a);
+    hipFree(q->forest);
+    hipFree(q->fsorted);
+    hipFree(q->descs);
+    delete q;
+}
+
+gz_status boruvka(gz_graph* const* gs, uint32_t G, bool want_forest, QueryResult& out) {
+    if (G == 0) return fail(GZ_EINVAL, "no graphs");
+    std::vector<GraphDesc> descs(G);
+    uint64_t T64 = 0;
+    uint32_t Rmax = 0, Bmax = 0, Vmax = 0;
+    for (uint32_t k = 0; k < G; ++k) {
+        const gz_graph* g = gs[k];
+        if (!g) return fail(GZ_EINVAL, "null graph handle");
+        descs[k] = GraphDesc{g->sk, g->seeds, g->n, g->V, g->R, g->B, g->P, (uint32_t)T64, 0};
+        T64 += g->V;
+        Rmax = std::max(Rmax, g->R);
+        Bmax = std::max(Bmax, g->B);
+        Vmax = std::max(Vmax, g->V);
+    }
+    if (T64 >= (1ull << 31)) return fail(GZ_EINVAL, "too many nodes in one query");
+    const uint32_t T = (uint32_t)T64;
+    const uint32_t wpr = kPlanes * Bmax * kC;
+
+    // single graphs keep their scratch; fused queries use a temporary one
+    QueryScratch* Q = nullptr;
+    bool owned = false;
+    if (G == 1) {
+        if (!gs[0]->q) gs[0]->q = new QueryScratch();
+        Q = gs[0]->q;
+    } else {
+        Q = new QueryScratch();
+        owned = true;
+    }
+    struct Guard {
+        QueryScratch* q;
+        bool own;
+        ~Guard() { if (own) free_query_scratch(q); }
+    } guard{Q, owned};
+    gz_status st = ensure_query(*Q, T, G, wpr);
+    if (st) return st;
+
+    hipStream_t qs = gs[0]->qstream;
+    for (uint32_t k = 0; k < G; ++k) GZ_HIP(hipStreamWaitEvent(qs, gs[k]->last, 0));
+    GZ_HIP(hipMemcpyAsync(Q->descs, descs.data(), sizeof(GraphDesc) * G, hipMemcpyHostToDevice, qs));
+    const uint32_t tb = blocks_for(T, 256);
+    k_q_init<<<(T + 255) / 256, 256, 0, qs>>>(T, Q->descs, G, Q->comp, Q->L, Q->done, Q->gof,
+                                               Q->ctl);
+    const uint32_t K = std::max(1u, bitlen32(Vmax - 1));  // 2^K >= any tail + cycle length
+    uint32_t* s = Q->s;
+    uint32_t* s2 = Q->s2;
+    uint32_t* m = Q->m;
+    uint32_t* m2 = Q->m2;
+    uint32_t* L = Q->L;
+    uint32_t* L2 = Q->L2;
+    uint32_t rounds = 0;
+    for (uint32_t r = 0; r < Rmax; ++r) {
+        k_q_select<<<tb, 256, 0, qs>>>(r, L, Q->ctl, Q->done, Q->gof, Q->descs, Q->slot, Q->A,
+                                       Q->hook, Q->newlab, Q->merged);
+        uint32_t nA = 0;
+        GZ_HIP(hipMemcpyAsync(&nA, Q->ctl + Q_NA, 4, hipMemcpyDeviceToHost, qs));
+        GZ_HIP(hipStreamSynchronize(qs));
+        if (nA == 0) break;
+        rounds = r + 1;
+        GZ_HIP(hipMemsetAsync(Q->acc, 0, (size_t)nA * wpr * 4, qs));
+        const uint32_t rgrid = (uint32_t)std::min<uint64_t>((T64 * 64 + 255) / 256, 65535);
+        k_q_reduce<<<rgrid, 256, 0, qs>>>(r, T, Q->comp, Q->slot, Q->gof, Q->descs, wpr, Q->acc);
+        k_q_query<<<(nA * 8 + 255) / 256, 256, 0, qs>>>(r, Q->A, Q->ctl, Q->acc, wpr, Q->gof,
+                                                         Q->descs, Q->comp, Q->hook, Q->hedge,
+                                                         Q->done);
+        k_q_double_init<<<tb, 256, 0, qs>>>(L, Q->ctl, Q->hook, s, m);
+        for (uint32_t k = 0; k < K; ++k) {
+            k_q_double<<<tb, 256, 0, qs>>>(L, Q->ctl, s, m, s2, m2);
+            std::swap(s, s2);
+            std::swap(m, m2);
+        }
+        k_q_root<<<tb, 256, 0, qs>>>(L, Q->ctl, s, m, Q->hook, Q->hedge, Q->gof, Q->rootOf,
+                                     Q->newlab, Q->merged, Q->forest);
+        k_q_newcomps<<<tb, 256, 0, qs>>>(L, Q->ctl, Q->rootOf, Q->newlab, Q->merged, Q->done, L2);
+        k_q_relabel<<<tb, 256, 0, qs>>>(T, Q->comp, Q->rootOf, Q->newlab);
+        k_q_next_round<<<1, 1, 0, qs>>>(Q->ctl);
+        std::swap(L, L2);
+    }
+    GZ_HIP(hipMemsetAsync(Q->gcount, 0, 4ull * G, qs));
+    GZ_HIP(hipMemsetAsync(Q->gfail, 0, 4ull * G, qs));
+    k_q_finish<<<tb, 256, 0, qs>>>(L, Q->ctl, Q->done, Q->gof, Q->gcount, Q->gfail);
+    k_q_labels<<<tb, 256, 0, qs>>>(T, Q->comp, Q->gof, Q->descs, Q->labels);
+    out.labels.resize(T);
+    out.num_cc.resize(G);
+    std::vector<uint32_t> gfail(G);
+    GZ_HIP(hipMemcpyAsync(out.labels.data(), Q->labels, 4ull * T, hipMemcpyDeviceToHost, qs));
+    GZ_HIP(hipMemcpyAsync(out.num_cc.data(), Q->gcount, 4ull * G, hipMemcpyDeviceToHost, qs));
+    GZ_HIP(hipMemcpyAsync(gfail.data(), Q->gfail, 4ull * G, hipMemcpyDeviceToHost, qs));
+    uint32_t nF = 0;
+    GZ_HIP(hipMemcpyAsync(&nF, Q->ctl + Q_NF, 4, hipMemcpyDeviceToHost, qs));
+    if (want_forest) {
+        GZ_HIP(hipMemsetAsync(Q->fcnt, 0, 4ull * G, qs));
+        k_q_fcount<<<tb, 256, 0, qs>>>(Q->forest, Q->ctl, Q->fcnt);
+        k_q_fscan<<<1, 1, 0, qs>>>(Q->fcnt, G, Q->foff, Q->fcur);
+        k_q_fscatter<<<tb, 256, 0, qs>>>(Q->forest, Q->ctl, Q->fcur, Q->fsorted);
+        k_q_frank<<<(T + kRankThreads - 1) / kRankThreads, kRankThreads, 0, qs>>>(
+            Q->fsorted, Q->ctl, Q->foff, Q->fpairs);
+    }
+    GZ_HIP(hipGetLastError());
+    GZ_HIP(hipStreamSynchronize(qs));
+    if (want_forest) {
+        std::vector<uint32_t> foff(G + 1);
+        GZ_HIP(hipMemcpy(foff.data(), Q->foff, 4ull * (G + 1), hipMemcpyDeviceToHost));
+        out.forest.resize(2ull * nF);
+        if (nF)
+            GZ_HIP(hipMemcpy(out.forest.data(), Q->fpairs, 8ull * nF, hipMemcpyDeviceToHost));
+        out.forest_off.assign(foff.begin(), foff.end());
+    } else {
+        out.forest.clear();
+        out.forest_off.clear();
+    }
+    out.status.resize(G);
+    for (uint32_t k = 0; k < G; ++k) out.status[k] = gfail[k] ? GZ_ESKETCH_FAIL : GZ_OK;
+    out.rounds = rounds;
+    return GZ_OK;
+}
+
+}  // namespace gz

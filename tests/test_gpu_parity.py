@@ -1,0 +1,221 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle, bit for bit.
+
+All arithmetic is integer; the bar is exact equality of sketch bits, component
+labels, forest edges and status.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from helpers import (assert_query_equal, assert_sketch_equal, check_forest_valid, final_labels,
+                     gz_status_of, oracle_for, to_dev)
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def gz(built):
+    import torch
+
+    assert torch.cuda.is_available()
+    import paper_2203_14927_amd as gz
+
+    gz.lib()
+    return gz
+
+
+def _stream(V, n, seed, p_repeat=0.2):
+    rng = np.random.default_rng(seed)
+    src = rng.integers(0, V, n, dtype=np.int64)
+    dst = rng.integers(0, V, n, dtype=np.int64)
+    keep = src != dst
+    src, dst = src[keep], dst[keep]
+    # repeat some updates so that toggles cancel
+    k = int(len(src) * p_repeat)
+    if k:
+        pick = rng.integers(0, len(src), k)
+        src = np.concatenate([src, dst[pick]])
+        dst = np.concatenate([dst, src[pick]])
+    return workloads.Stream(V, src.astype(np.uint32), dst.astype(np.uint32),
+                            np.ones(len(src), np.uint8))
+
+
+@pytest.mark.parametrize("V,n,seed", [(2, 7, 1), (3, 20, 2), (5, 40, 3), (64, 900, 4),
+                                      (100, 3000, 5), (257, 9000, 6), (1000, 20000, 7)])
+def test_small_streams_sketch_and_query(gz, V, n, seed):
+    s = _stream(V, n, seed)
+    g = gz.Graph(V, seed=seed * 7919 + 1)
+    g.ingest(to_dev(s.src), to_dev(s.dst))
+    O = oracle_for(s, seed * 7919 + 1)
+    assert_sketch_equal(g, O)
+    assert_query_equal(g, O)
+
+
+def test_uniform_small_workload_full_parity(gz):
+    """V=1024, 150k inserts then 50k deletes: every node's sketch, labels and forest."""
+    s = workloads.config_uniform_small()
+    g = gz.Graph(s.V, seed=1)
+    g.ingest(to_dev(s.src), to_dev(s.dst))
+    O = oracle_for(s, 1)
+    assert_sketch_equal(g, O)
+    st, labels, forest = assert_query_equal(g, O)
+    ref, fu, fv = final_labels(s)
+    assert (labels == ref).all()
+    check_forest_valid(s.V, labels, forest, fu, fv)
+
+
+def test_host_pointer_path_equals_device_path(gz):
+    s = _stream(300, 5000, 11)
+    g1 = gz.Graph(300, seed=5)
+    g2 = gz.Graph(300, seed=5)
+    g1.ingest(s.src, s.dst)
+    g2.ingest(to_dev(s.src), to_dev(s.dst))
+    a1, b1 = g1.export()
+    a2, b2 = g2.export()
+    assert (a1 == a2).all() and (b1 == b2).all()
+
+
+def test_chunked_ingest_equals_one_call(gz):
+    s = _stream(500, 20000, 12)
+    g1 = gz.Graph(500, seed=9)
+    g2 = gz.Graph(500, seed=9)
+    g1.ingest(to_dev(s.src), to_dev(s.dst))
+    for k in range(0, s.N, 3001):
+        g2.ingest(to_dev(s.src[k:k + 3001]), to_dev(s.dst[k:k + 3001]))
+    a1, b1 = g1.export()
+    a2, b2 = g2.export()
+    assert (a1 == a2).all() and (b1 == b2).all()
+
+
+@pytest.mark.parametrize("tuning", [dict(chunk=7), dict(chunk=64, lds_rows=1),
+                                    dict(lds_rows=3, wg_size=512), dict(wgs_per_cu=1, chunk=1),
+                                    dict(wg_size=1024, chunk=16384, lds_rows=20)])
+def test_tuning_variants_are_bit_exact(gz, tuning):
+    """Split gutters (HBM atomics), shallow LDS tiles (deep rows in HBM) and odd shapes."""
+    s = _stream(700, 30000, 13)
+    g = gz.Graph(700, seed=77)
+    g.set_tuning(**tuning)
+    g.ingest(to_dev(s.src), to_dev(s.dst))
+    O = oracle_for(s, 77)
+    assert_sketch_equal(g, O)
+    assert_query_equal(g, O)
+
+
+def test_plain_per_node_batches_equal_fused_ingest(gz):
+    """update_sketch_batch per node (both endpoints submitted) == gz_ingest == oracle."""
+    s = _stream(200, 6000, 14)
+    g = gz.Graph(200, seed=3)
+    u = np.concatenate([s.src, s.dst])
+    v = np.concatenate([s.dst, s.src])
+    order = np.argsort(u, kind="stable")
+    u, v = u[order], v[order]
+    bounds = np.searchsorted(u, np.arange(201))
+    for node in range(200):
+        nb = v[bounds[node]:bounds[node + 1]]
+        for k in range(0, len(nb), 37):  # gutters of 37 updates
+            g.update_sketch_batch(node, to_dev(nb[k:k + 37]))
+    # host pointers too, through the same entry point
+    O = oracle_for(s, 3)
+    assert_sketch_equal(g, O)
+    g2 = gz.Graph(200, seed=3)
+    for node in range(200):
+        g2.update_sketch_batch(node, v[bounds[node]:bounds[node + 1]])
+    assert_sketch_equal(g2, O)
+    assert_query_equal(g2, O)
+
+
+def test_invalid_updates_rejected_and_nothing_applied(gz):
+    g = gz.Graph(50, seed=1)
+    good_src = np.array([1, 2, 3], np.uint32)
+    good_dst = np.array([4, 5, 6], np.uint32)
+    g.ingest(to_dev(good_src), to_dev(good_dst))
+    before = g.export()
+    for src, dst in [([1, 7], [1, 8]), ([1, 2], [3, 50]), ([60], [1])]:
+        with pytest.raises(gz.GzError) as e:
+            g.ingest(to_dev(np.array(src, np.uint32)), to_dev(np.array(dst, np.uint32)))
+        assert e.value.status == gz.GZ_EINVAL
+        with pytest.raises(gz.GzError):
+            g.ingest(np.array(src, np.uint32), np.array(dst, np.uint32))
+    with pytest.raises(gz.GzError):
+        g.update_sketch_batch(3, to_dev(np.array([4, 3], np.uint32)))
+    with pytest.raises(gz.GzError):
+        g.update_sketch_batch(3, np.array([4, 99], np.uint32))
+    with pytest.raises(gz.GzError):
+        g.update_sketch_batch(50, np.array([4], np.uint32))
+    after = g.export()
+    assert (before[0] == after[0]).all() and (before[1] == after[1]).all()
+    # asynchronous submission reports at flush, still applying nothing
+    g.ingest(to_dev(np.array([9, 9], np.uint32)), to_dev(np.array([9, 10], np.uint32)),
+             flags=gz.GZ_ASYNC)
+    with pytest.raises(gz.GzError):
+        g.flush()
+    g.flush()
+    after = g.export()
+    assert (before[0] == after[0]).all()
+    with pytest.raises(gz.GzError):
+        gz.Graph(1, seed=1)
+    with pytest.raises(gz.GzError):
+        gz.Graph(65537, seed=1)
+
+
+def test_empty_and_isolated(gz):
+    g = gz.Graph(10, seed=2)
+    g.ingest(np.zeros(0, np.uint32), np.zeros(0, np.uint32))
+    st, labels, ncc, forest = g.query()
+    assert st == gz.GZ_OK and ncc == 10 and (labels == np.arange(10)).all() and len(forest) == 0
+    # an edge inserted and deleted leaves nothing
+    g.ingest(np.array([3, 4], np.uint32), np.array([4, 3], np.uint32))
+    st, labels, ncc, forest = g.query()
+    assert ncc == 10
+    a, b = g.export()
+    assert not a.any() and not b.any()
+
+
+def test_edge_zero_is_recoverable(gz):
+    """Pair (0,1) has index 0: alpha stays 0 but the checksum makes the bucket GOOD."""
+    g = gz.Graph(2, seed=4)
+    g.ingest(np.array([1], np.uint32), np.array([0], np.uint32))
+    st, labels, ncc, forest = g.query()
+    assert ncc == 1 and forest.tolist() == [[0, 1]]
+
+
+def test_forced_sketch_failure_matches_oracle(gz):
+    V = 64
+    s = workloads.Stream(V, np.arange(V - 1, dtype=np.uint32), np.arange(1, V, dtype=np.uint32),
+                         np.ones(V - 1, np.uint8))
+    g = gz.Graph(V, seed=3, rounds=1)
+    g.ingest(to_dev(s.src), to_dev(s.dst))
+    O = oracle_for(s, 3, R=1)
+    assert_sketch_equal(g, O)
+    st, labels, forest = assert_query_equal(g, O)
+    assert st == gz.GZ_ESKETCH_FAIL
+
+
+def test_queries_interleaved_with_ingest(gz):
+    s = workloads.uniform_stream(400, 3000, 1500, seed=21)
+    g = gz.Graph(400, seed=8)
+    O = oracle.Oracle(400, 8)
+    for k in range(0, s.N, 700):
+        g.ingest(to_dev(s.src[k:k + 700]), to_dev(s.dst[k:k + 700]))
+        O.ingest(s.src[k:k + 700], s.dst[k:k + 700])
+        assert_query_equal(g, O)
+    assert_sketch_equal(g, O)
+
+
+def test_many_graphs_fused_equals_separate(gz):
+    streams = workloads.config_many_gnp(seed=4, G=24, vlo=2, vhi=300)
+    seeds = [workloads.many_graph_seed(4, k) for k in range(len(streams))]
+    graphs = [gz.Graph(s.V, seed=sd) for s, sd in zip(streams, seeds)]
+    offs = np.zeros(len(streams) + 1, np.uint64)
+    offs[1:] = np.cumsum([s.N for s in streams])
+    src = np.concatenate([s.src for s in streams])
+    dst = np.concatenate([s.dst for s in streams])
+    gz.ingest_multi(graphs, offs, to_dev(src), to_dev(dst))
+    labels, ncc, stt = gz.connected_components_multi(graphs)
+    for k, (s, g) in enumerate(zip(streams, graphs)):
+        O = oracle_for(s, seeds[k])
+        assert_sketch_equal(g, O)
+        ost, olabels, _, _ = O.connected_components()
+        assert stt[k] == gz_status_of(ost) and (labels[k] == olabels).all()
+        assert_query_equal(g, O)

@@ -69,6 +69,9 @@ enum {
 
 #define GZ_DEVICE_PTR 0x1u
 #define GZ_ASYNC 0x2u
+#define GZ_UNCHECKED 0x4u  /* caller guarantees valid ids: skip the validation launch of
+                              gz_update_sketch_batch (invalid ids then corrupt only that
+                              node's own sketch, never other memory) */
 
 #define GZ_COLUMNS 8u
 #define GZ_MAX_NODES 65536u
@@ -222,6 +225,20 @@ gz_status gz_sketch_storage(const gz_graph* g, void** dev_ptr, uint64_t* bytes);
 /* Launch parameters of the ingest path for this graph (get / set). */
 gz_status gz_get_tuning(const gz_graph* g, gz_tuning* t);
 gz_status gz_set_tuning(gz_graph* g, const gz_tuning* t);
+
+/* Per-phase device timings of the most recent gz_ingest / gz_ingest_multi on a
+ * graph (the first graph of a fused call), taken with HIP events on the stream
+ * the kernels ran on.  Profiling is off by default; gz_profile_last waits for
+ * the profiled call to finish. */
+typedef struct gz_profile {
+    float group_ms;    /* count + scan + scatter (grouping by endpoint) */
+    float update_ms;   /* persistent sketch-update kernel */
+    float ingest_ms;   /* whole ingest launch sequence */
+    uint32_t calls;    /* profiled ingest calls since enabling */
+    uint32_t reserved;
+} gz_profile;
+gz_status gz_profile_enable(gz_graph* g, int on);
+gz_status gz_profile_last(gz_graph* g, gz_profile* out);
 
 /* Human-readable name of a status code, and the last error message of this thread. */
 const char* gz_status_str(gz_status s);

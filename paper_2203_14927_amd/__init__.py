@@ -21,6 +21,7 @@ LIB_PATH = os.path.join(_HERE, "libgz.so")
 GZ_OK, GZ_EINVAL, GZ_ENOMEM, GZ_EDEVICE, GZ_ESKETCH_FAIL, GZ_EBUSY, GZ_ESTATE = range(7)
 GZ_DEVICE_PTR = 0x1
 GZ_ASYNC = 0x2
+GZ_UNCHECKED = 0x4
 GZ_COLUMNS = 8
 
 
@@ -41,6 +42,12 @@ class gz_tuning(ctypes.Structure):
 
     def as_dict(self):
         return {f: int(getattr(self, f)) for f, _ in self._fields_}
+
+
+class gz_profile(ctypes.Structure):
+    _fields_ = [("group_ms", ctypes.c_float), ("update_ms", ctypes.c_float),
+                ("ingest_ms", ctypes.c_float), ("calls", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32)]
 
 
 _lib = None
@@ -77,6 +84,8 @@ _SIGS = {
                            ctypes.POINTER(ctypes.c_uint64)], ctypes.c_int32),
     "gz_get_tuning": ([ctypes.c_void_p, ctypes.POINTER(gz_tuning)], ctypes.c_int32),
     "gz_set_tuning": ([ctypes.c_void_p, ctypes.POINTER(gz_tuning)], ctypes.c_int32),
+    "gz_profile_enable": ([ctypes.c_void_p, ctypes.c_int], ctypes.c_int32),
+    "gz_profile_last": ([ctypes.c_void_p, ctypes.POINTER(gz_profile)], ctypes.c_int32),
     "gz_status_str": ([ctypes.c_int32], ctypes.c_char_p),
     "gz_last_error": ([], ctypes.c_char_p),
 }
@@ -257,6 +266,15 @@ class Graph:
         n = ctypes.c_uint64()
         check(lib().gz_sketch_storage(self._h, ctypes.byref(p), ctypes.byref(n)))
         return p.value, n.value
+
+    def profile(self, on: bool = True):
+        check(lib().gz_profile_enable(self._h, int(on)))
+
+    def last_profile(self) -> dict:
+        p = gz_profile()
+        check(lib().gz_profile_last(self._h, ctypes.byref(p)))
+        return {"group_ms": p.group_ms, "update_ms": p.update_ms, "ingest_ms": p.ingest_ms,
+                "calls": p.calls}
 
     @property
     def tuning(self) -> dict:

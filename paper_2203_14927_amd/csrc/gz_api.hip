@@ -58,7 +58,29 @@ int device_cu_count() {
     return cached[dev % 64];
 }
 
-uint32_t default_lds_rows(uint32_t B) { return std::min<uint32_t>(B, 16u); }
+// Defaults before autotuning: the whole tile in LDS when it takes at most 48 KiB,
+// the workgroup (multiple of 64, 256..512 lanes) with the best lane use for P
+// pairs, and as many resident workgroups per CU as 160 KiB of LDS allows.
+gz_tuning default_tuning(uint32_t P, uint32_t B) {
+    gz_tuning t{};
+    const uint32_t Pst = (P + 63) / 64 * 64;
+    t.chunk = 2048;
+    t.lds_rows = (kPlanes * B * Pst * 4 <= 48 * 1024) ? B : std::min<uint32_t>(B, 16u);
+    uint32_t best = 0;
+    double best_use = -1.0;
+    for (uint32_t wg = 256; wg <= 512; wg += 64) {
+        if (wg < P) continue;
+        const double use = (double)((wg / P) * P) / wg;
+        if (use > best_use + 0.01) {
+            best_use = use;
+            best = wg;
+        }
+    }
+    t.wg_size = best ? best : std::min<uint32_t>(1024, (P + 63) / 64 * 64);
+    const uint32_t smem = t.chunk * 4 + kPlanes * std::min(t.lds_rows, B) * Pst * 4;
+    t.wgs_per_cu = std::max<uint32_t>(1, std::min<uint32_t>(8, (160 * 1024) / smem));
+    return t;
+}
 
 // exact-depth rows -> nested rows (row b = XOR of rows d >= b), widened to 64 bits
 __global__ void k_export(const uint32_t* __restrict__ sk, uint32_t lo, uint32_t hi, uint32_t R,
@@ -167,21 +189,7 @@ gz_status init_graph(gz_graph** out, uint32_t V, uint64_t seed, const gz_config*
         delete g;
         return s;
     }
-    g->tuning.lds_rows = default_lds_rows(g->B);
-    g->tuning.chunk = 2048;
-    g->tuning.wgs_per_cu = 4;
-    // smallest multiple of 64 with good lane use for P pairs (J = wg / P groups)
-    uint32_t best = 0;
-    double best_use = -1.0;
-    for (uint32_t wg = 64; wg <= 512; wg += 64) {
-        if (wg < g->P) continue;
-        double use = (double)((wg / g->P) * g->P) / wg;
-        if (use > best_use + 0.02) {
-            best_use = use;
-            best = wg;
-        }
-    }
-    g->tuning.wg_size = best ? best : ((g->P + 63) / 64) * 64;
+    g->tuning = default_tuning(g->P, g->B);
     *out = g;
     return GZ_OK;
 }
@@ -205,8 +213,35 @@ gz_status gz_free(gz_graph* g) {
     hipFree(g->sk);
     hipFree(g->seeds);
     hipEventDestroy(g->last);
+    for (hipEvent_t e : g->prof_ev)
+        if (e) hipEventDestroy(e);
     hipStreamDestroy(g->qstream);
     delete g;
+    return GZ_OK;
+}
+
+gz_status gz_profile_enable(gz_graph* g, int on) {
+    if (!g) return fail(GZ_EINVAL, "null graph");
+    if (on && !g->prof_ev[0])
+        for (hipEvent_t& e : g->prof_ev) GZ_HIP(hipEventCreate(&e));
+    g->profiling = on != 0;
+    g->prof_calls = 0;
+    return GZ_OK;
+}
+
+gz_status gz_profile_last(gz_graph* g, gz_profile* out) {
+    if (!g || !out) return fail(GZ_EINVAL, "null argument");
+    if (!g->prof_calls) return fail(GZ_ESTATE, "no profiled ingest yet");
+    GZ_HIP(hipEventSynchronize(g->prof_ev[2]));
+    float a = 0, b = 0, c = 0;
+    GZ_HIP(hipEventElapsedTime(&a, g->prof_ev[0], g->prof_ev[1]));
+    GZ_HIP(hipEventElapsedTime(&b, g->prof_ev[1], g->prof_ev[2]));
+    GZ_HIP(hipEventElapsedTime(&c, g->prof_ev[0], g->prof_ev[2]));
+    out->group_ms = a;
+    out->update_ms = b;
+    out->ingest_ms = c;
+    out->calls = g->prof_calls;
+    out->reserved = 0;
     return GZ_OK;
 }
 

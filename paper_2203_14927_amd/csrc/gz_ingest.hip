@@ -5,6 +5,11 @@
 // updates so that one node's sketch is touched once per batch (Sec. 4.1, 5.1);
 // batch- and sketch-level parallelism (Sec. 5.1) become workgroups over node
 // batches and lanes over (round, column) pairs.
+//
+// Grouping is a counting sort keyed by global node id: every block counts one
+// chunk of one graph's updates in an LDS histogram, the (node, chunk) table of
+// counts is scanned, and a second pass scatters each entry through LDS cursors
+// seeded from the scanned table.  No global atomics touch the hot counters.
 #include <algorithm>
 #include <cstring>
 
@@ -21,17 +26,6 @@ __global__ void k_fill_u32(uint32_t* __restrict__ p, uint64_t n, uint32_t v) {
     for (; i < n; i += stride) p[i] = v;
 }
 
-// last graph g with offs[g] <= i (skips empty graphs)
-__device__ __forceinline__ uint32_t graph_of_update(const uint64_t* __restrict__ offs, uint32_t G,
-                                                    uint64_t i) {
-    uint32_t lo = 0, hi = G - 1;
-    while (lo < hi) {
-        uint32_t mid = (lo + hi + 1) >> 1;
-        if (offs[mid] <= i) lo = mid; else hi = mid - 1;
-    }
-    return lo;
-}
-
 // last graph g with node_base <= node
 __device__ __forceinline__ uint32_t graph_of_node(const GraphDesc* __restrict__ gd, uint32_t G,
                                                   uint32_t node) {
@@ -43,29 +37,100 @@ __device__ __forceinline__ uint32_t graph_of_node(const GraphDesc* __restrict__ 
     return lo;
 }
 
-// ctl[2]: this call saw an invalid update; ctl[3]: sticky error for gz_flush
-__global__ void k_count(const IngestArgs* __restrict__ a, const GraphDesc* __restrict__ gd,
-                        uint32_t* __restrict__ counts, uint32_t* __restrict__ ctl) {
-    const uint64_t N = a->N;
-    const uint32_t G = a->G;
+constexpr uint32_t kGroupThreads = 512;
+
+struct UnitRange {
+    uint64_t i0, i1;    // updates [i0, i1)
+    uint32_t lo, size;  // local node range [lo, lo + size)
+};
+
+__device__ __forceinline__ UnitRange unit_range(const GroupUnit& u, const GraphDesc& g,
+                                                uint32_t group_chunk, uint64_t graph_end) {
+    UnitRange r;
+    r.i0 = g.upd_base + (uint64_t)u.c * group_chunk;
+    r.i1 = min(graph_end, r.i0 + group_chunk);
+    r.lo = u.q * kGroupRange;
+    r.size = min(g.V - r.lo, kGroupRange);
+    return r;
+}
+
+// pass 1: LDS histogram of one chunk's endpoints; validation of the updates
+// (ctl[2]: this call saw an invalid update; ctl[3]: sticky error for gz_flush)
+__global__ __launch_bounds__(kGroupThreads) void k_group_count(
+    const IngestArgs* __restrict__ a, const GroupUnit* __restrict__ units,
+    const GraphDesc* __restrict__ gd, uint32_t* __restrict__ H, uint32_t* __restrict__ ctl) {
+    extern __shared__ uint32_t hist[];
+    const GroupUnit u = units[blockIdx.x];
+    const GraphDesc g = gd[u.g];
+    const uint64_t gend = u.g + 1 < a->G ? gd[u.g + 1].upd_base : a->N;
+    const UnitRange r = unit_range(u, g, a->group_chunk, gend);
     const uint32_t* __restrict__ src = a->src;
     const uint32_t* __restrict__ dst = a->dst;
-    const uint64_t* __restrict__ offs = a->offs;
-    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (; i < N; i += stride) {
-        uint32_t g = G == 1 ? 0u : graph_of_update(offs, G, i);
-        uint32_t u = src[i], v = dst[i];
-        uint32_t V = gd[g].V, base = gd[g].node_base;
-        if (u == v || u >= V || v >= V) {
-            atomicOr(&ctl[2], 1u);
-            atomicOr(&ctl[3], 1u);
+    for (uint32_t k = threadIdx.x; k < r.size; k += blockDim.x) hist[k] = 0;
+    __syncthreads();
+    bool bad = false;
+    for (uint64_t i = r.i0 + threadIdx.x; i < r.i1; i += blockDim.x) {
+        const uint32_t x = src[i], y = dst[i];
+        if (x == y || x >= g.V || y >= g.V) {
+            bad = true;
             continue;
         }
-        atomicAdd(&counts[base + u], 1u);
-        atomicAdd(&counts[base + v], 1u);
+        const uint32_t xo = x - r.lo, yo = y - r.lo;
+        if (xo < r.size) atomicAdd(&hist[xo], 1u);
+        if (yo < r.size) atomicAdd(&hist[yo], 1u);
+    }
+    if (bad && u.q == 0) {
+        atomicOr(&ctl[2], 1u);
+        atomicOr(&ctl[3], 1u);
+    }
+    __syncthreads();
+    uint32_t* out = H + g.hoff + (uint64_t)r.lo * g.nb + u.c;
+    for (uint32_t k = threadIdx.x; k < r.size; k += blockDim.x) out[(uint64_t)k * g.nb] = hist[k];
+}
+
+// node counts from the scanned table: the node's entries start at its chunk-0
+// prefix and end at the next node's
+__global__ void k_group_node_counts(const GraphDesc* __restrict__ gd, uint32_t G, uint32_t T,
+                                    const uint32_t* __restrict__ Hs, uint32_t* __restrict__ counts) {
+    for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < T; v += gridDim.x * blockDim.x) {
+        const uint32_t gi = G == 1 ? 0u : graph_of_node(gd, G, v);
+        const GraphDesc& g = gd[gi];
+        if (g.nb == 0) {
+            counts[v] = 0;
+            continue;
+        }
+        const uint64_t at = g.hoff + (uint64_t)(v - g.node_base) * g.nb;
+        counts[v] = Hs[at + g.nb] - Hs[at];
     }
 }
+
+// pass 2: scatter every endpoint entry to its slot; LDS cursors start at the
+// scanned (node, chunk) prefix, so each chunk fills its own contiguous run
+__global__ __launch_bounds__(kGroupThreads) void k_group_scatter(
+    const IngestArgs* __restrict__ a, const GroupUnit* __restrict__ units,
+    const GraphDesc* __restrict__ gd, const uint32_t* __restrict__ Hs,
+    uint32_t* __restrict__ grouped, const uint32_t* __restrict__ ctl) {
+    extern __shared__ uint32_t cur[];
+    if (ctl[2]) return;
+    const GroupUnit u = units[blockIdx.x];
+    const GraphDesc g = gd[u.g];
+    const uint64_t gend = u.g + 1 < a->G ? gd[u.g + 1].upd_base : a->N;
+    const UnitRange r = unit_range(u, g, a->group_chunk, gend);
+    const uint32_t* __restrict__ src = a->src;
+    const uint32_t* __restrict__ dst = a->dst;
+    const uint32_t* hs = Hs + g.hoff + (uint64_t)r.lo * g.nb + u.c;
+    for (uint32_t k = threadIdx.x; k < r.size; k += blockDim.x) cur[k] = hs[(uint64_t)k * g.nb];
+    __syncthreads();
+    for (uint64_t i = r.i0 + threadIdx.x; i < r.i1; i += blockDim.x) {
+        const uint32_t x = src[i], y = dst[i];
+        const uint32_t idx = edge_index(x, y);
+        const uint32_t xo = x - r.lo, yo = y - r.lo;
+        if (xo < r.size) grouped[atomicAdd(&cur[xo], 1u)] = idx;
+        if (yo < r.size) grouped[atomicAdd(&cur[yo], 1u)] = idx;
+    }
+}
+
+// ------------------------------------------------------- scans (exclusive) --
 
 constexpr uint32_t kScanThreads = 256;
 constexpr uint32_t kScanPerThread = 8;
@@ -78,22 +143,71 @@ __device__ __forceinline__ uint64_t packed_of(uint32_t c, uint32_t chunk) {
 }
 
 // exclusive scan of 256 values in LDS (Hillis-Steele), returns this thread's prefix
-__device__ uint64_t block_exclusive_scan(uint64_t v, uint64_t* sh, uint64_t* total) {
+template <typename T>
+__device__ T block_exclusive_scan(T v, T* sh, T* total) {
     const uint32_t t = threadIdx.x;
     sh[t] = v;
     __syncthreads();
     for (uint32_t off = 1; off < kScanThreads; off <<= 1) {
-        uint64_t add = t >= off ? sh[t - off] : 0;
+        T add = t >= off ? sh[t - off] : 0;
         __syncthreads();
         sh[t] += add;
         __syncthreads();
     }
-    uint64_t incl = sh[t];
+    T incl = sh[t];
     *total = sh[kScanThreads - 1];
     __syncthreads();
     return incl - v;
 }
 
+// in-place exclusive scan of a u32 array (three passes)
+__global__ __launch_bounds__(kScanThreads) void k_scan32_partial(const uint32_t* __restrict__ x,
+                                                                  uint64_t n,
+                                                                  uint32_t* __restrict__ sums) {
+    __shared__ uint32_t sh[kScanThreads];
+    const uint64_t base = (uint64_t)blockIdx.x * kScanTile + threadIdx.x * kScanPerThread;
+    uint32_t s = 0;
+    for (uint32_t k = 0; k < kScanPerThread; ++k)
+        if (base + k < n) s += x[base + k];
+    uint32_t total;
+    block_exclusive_scan<uint32_t>(s, sh, &total);
+    if (threadIdx.x == 0) sums[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan32_top(uint32_t* __restrict__ sums,
+                                                              uint32_t nblocks) {
+    __shared__ uint32_t sh[kScanThreads];
+    uint32_t carry = 0;
+    for (uint32_t b0 = 0; b0 < nblocks; b0 += kScanThreads) {
+        const uint32_t i = b0 + threadIdx.x;
+        const uint32_t v = i < nblocks ? sums[i] : 0;
+        uint32_t total;
+        const uint32_t ex = block_exclusive_scan<uint32_t>(v, sh, &total);
+        if (i < nblocks) sums[i] = carry + ex;
+        carry += total;
+    }
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan32_final(uint32_t* __restrict__ x, uint64_t n,
+                                                                const uint32_t* __restrict__ sums) {
+    __shared__ uint32_t sh[kScanThreads];
+    const uint64_t base = (uint64_t)blockIdx.x * kScanTile + threadIdx.x * kScanPerThread;
+    uint32_t vals[kScanPerThread];
+    uint32_t s = 0;
+    for (uint32_t k = 0; k < kScanPerThread; ++k) {
+        vals[k] = base + k < n ? x[base + k] : 0;
+        s += vals[k];
+    }
+    uint32_t total;
+    uint32_t pre = block_exclusive_scan<uint32_t>(s, sh, &total) + sums[blockIdx.x];
+    for (uint32_t k = 0; k < kScanPerThread; ++k) {
+        if (base + k < n) x[base + k] = pre;
+        pre += vals[k];
+    }
+}
+
+// work items: exclusive scan of (entries | items << 40) per node, then every
+// node emits ceil(entries / chunk) items
 __global__ __launch_bounds__(kScanThreads) void k_scan_partial(const uint32_t* __restrict__ counts,
                                                                 uint32_t T, uint32_t chunk,
                                                                 uint64_t* __restrict__ block_sums) {
@@ -105,7 +219,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_partial(const uint32_t* _
         if (i < T) s += packed_of(counts[i], chunk);
     }
     uint64_t total;
-    block_exclusive_scan(s, sh, &total);
+    block_exclusive_scan<uint64_t>(s, sh, &total);
     if (threadIdx.x == 0) block_sums[blockIdx.x] = total;
 }
 
@@ -113,30 +227,27 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_partial(const uint32_t* _
 // resets the work ticket
 __global__ __launch_bounds__(kScanThreads) void k_scan_top(uint64_t* __restrict__ block_sums,
                                                             uint32_t nblocks,
-                                                            uint64_t* __restrict__ packed,
-                                                            uint32_t T, uint32_t* __restrict__ ctl) {
+                                                            uint32_t* __restrict__ ctl) {
     __shared__ uint64_t sh[kScanThreads];
     uint64_t carry = 0;
     for (uint32_t b0 = 0; b0 < nblocks; b0 += kScanThreads) {
         uint32_t i = b0 + threadIdx.x;
         uint64_t v = i < nblocks ? block_sums[i] : 0;
         uint64_t total;
-        uint64_t ex = block_exclusive_scan(v, sh, &total);
+        uint64_t ex = block_exclusive_scan<uint64_t>(v, sh, &total);
         if (i < nblocks) block_sums[i] = carry + ex;
         carry += total;
     }
     if (threadIdx.x == 0) {
-        packed[T] = carry;
         ctl[0] = 0;                           // ticket
         ctl[1] = (uint32_t)(carry >> 40);     // number of work items
     }
 }
 
-__global__ __launch_bounds__(kScanThreads) void k_scan_final(
+__global__ __launch_bounds__(kScanThreads) void k_scan_items(
     const uint32_t* __restrict__ counts, uint32_t T, uint32_t chunk,
-    const uint64_t* __restrict__ block_sums, uint64_t* __restrict__ packed,
-    uint32_t* __restrict__ cursor, WorkItem* __restrict__ items, const GraphDesc* __restrict__ gd,
-    uint32_t G, const uint32_t* __restrict__ ctl) {
+    const uint64_t* __restrict__ block_sums, WorkItem* __restrict__ items,
+    const GraphDesc* __restrict__ gd, uint32_t G, const uint32_t* __restrict__ ctl) {
     __shared__ uint64_t sh[kScanThreads];
     uint64_t base = (uint64_t)blockIdx.x * kScanTile + threadIdx.x * kScanPerThread;
     uint64_t vals[kScanPerThread];
@@ -147,19 +258,17 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_final(
         s += vals[k];
     }
     uint64_t total;
-    uint64_t pre = block_exclusive_scan(s, sh, &total) + block_sums[blockIdx.x];
+    uint64_t pre = block_exclusive_scan<uint64_t>(s, sh, &total) + block_sums[blockIdx.x];
     const bool skip = ctl[2] != 0;
     for (uint32_t k = 0; k < kScanPerThread; ++k) {
         uint64_t i = base + k;
-        if (i < T) {
-            packed[i] = pre;
-            uint32_t begin = (uint32_t)(pre & kCountMask);
-            uint32_t item0 = (uint32_t)(pre >> 40);
-            uint32_t c = (uint32_t)(vals[k] & kCountMask);
-            uint32_t ni = (uint32_t)(vals[k] >> 40);
-            cursor[i] = begin;
-            if (!skip && ni) {
-                uint32_t g = G == 1 ? 0u : graph_of_node(gd, G, (uint32_t)i);
+        if (i < T && !skip) {
+            const uint32_t begin = (uint32_t)(pre & kCountMask);
+            const uint32_t item0 = (uint32_t)(pre >> 40);
+            const uint32_t c = (uint32_t)(vals[k] & kCountMask);
+            const uint32_t ni = (uint32_t)(vals[k] >> 40);
+            if (ni) {
+                const uint32_t g = G == 1 ? 0u : graph_of_node(gd, G, (uint32_t)i);
                 for (uint32_t j = 0; j < ni; ++j) {
                     WorkItem w;
                     w.begin = begin + j * chunk;
@@ -176,35 +285,39 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_final(
     }
 }
 
-__global__ void k_scatter(const IngestArgs* __restrict__ a, const GraphDesc* __restrict__ gd,
-                          uint32_t* __restrict__ cursor, uint32_t* __restrict__ grouped,
-                          const uint32_t* __restrict__ ctl) {
-    if (ctl[2]) return;
-    const uint64_t N = a->N;
-    const uint32_t G = a->G;
-    const uint32_t* __restrict__ src = a->src;
-    const uint32_t* __restrict__ dst = a->dst;
-    const uint64_t* __restrict__ offs = a->offs;
-    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (; i < N; i += stride) {
-        uint32_t g = G == 1 ? 0u : graph_of_update(offs, G, i);
-        uint32_t u = src[i], v = dst[i];
-        uint32_t base = gd[g].node_base;
-        uint32_t idx = edge_index(u, v);
-        uint32_t pu = atomicAdd(&cursor[base + u], 1u);
-        grouped[pu] = idx;
-        uint32_t pv = atomicAdd(&cursor[base + v], 1u);
-        grouped[pv] = idx;
+// ------------------------------------------------------------ sketch update --
+
+// Hash one staged entry for this lane's (round, column) pair and XOR it into
+// the exact-depth row of the LDS tile; rows >= DL (kAllRows == false only) go
+// straight to HBM with atomics.
+template <bool kAllRows>
+__device__ __forceinline__ void xor_entry(uint32_t x, const PairSeeds& s, uint32_t Bm1,
+                                          uint32_t DL, uint32_t Pst, uint32_t p, uint32_t plane,
+                                          uint32_t* __restrict__ tile, uint32_t* __restrict__ skn,
+                                          uint64_t rowp, uint32_t P) {
+    const uint32_t d = row_depth(s, x, Bm1);
+    const uint32_t hi = chk_hi(s, x);
+    const uint32_t lo = chk_lo(s, x);
+    if (kAllRows || d < DL) {
+        const uint32_t a = d * Pst + p;
+        atomicXor(&tile[a], x);
+        atomicXor(&tile[plane + a], lo);
+        atomicXor(&tile[2 * plane + a], hi);
+    } else {
+        uint32_t* w = skn + (uint64_t)d * P + p;
+        atomicXor(w, x);
+        atomicXor(w + rowp, lo);
+        atomicXor(w + 2 * rowp, hi);
     }
 }
 
 // Apply `count` staged edge indices (ent[], in LDS) to node `node` of graph `g`.
-// Lanes map to (group j, pair p): J = blockDim / P groups split the entries,
-// each lane hashes its pair's seeds and XORs into the exact-depth row of its
-// column in the LDS tile (or straight into HBM for rows >= DL).  The tile is
-// then XORed back into HBM: plain read-modify-write when this workgroup owns
-// the node for the launch, atomics when the node's entries are split.
+// Lanes map to (group j, pair p): J = blockDim / P groups each take a
+// contiguous share of the entries; each lane hashes its pair's seeds and XORs
+// into the exact-depth row of its column.  The tile is then XORed back into
+// HBM: plain read-modify-write when this workgroup owns the node for the
+// launch, atomics when the node's entries are split across workgroups.
+template <bool kAllRows>
 __device__ __forceinline__ void apply_entries(const uint32_t* __restrict__ ent, uint32_t count,
                                               uint32_t node, const GraphDesc& g, uint32_t DL,
                                               uint32_t Pst, uint32_t* __restrict__ tile,
@@ -212,42 +325,37 @@ __device__ __forceinline__ void apply_entries(const uint32_t* __restrict__ ent, 
     const uint32_t tid = threadIdx.x;
     const uint32_t P = g.P, B = g.B;
     const uint32_t J = blockDim.x / P;
+    const uint64_t rowp = (uint64_t)B * P;
+    uint32_t* skn = g.sk + (uint64_t)node * kPlanes * rowp;
     if (tid < J * P) {
         const uint32_t j = tid / P;
         const uint32_t p = tid - j * P;
         const PairSeeds s = load_pair_seeds(g.seeds, P, p);
         const uint32_t Bm1 = B - 1;
         const uint32_t plane = DL * Pst;
-        for (uint32_t e = j; e < count; e += J) {
-            const uint32_t x = ent[e];
-            const uint32_t d = row_depth(s, x, Bm1);
-            const uint32_t hi = chk_hi(s, x);
-            const uint32_t lo = chk_lo(s, x);
-            if (d < DL) {
-                const uint32_t a = d * Pst + p;
-                atomicXor(&tile[a], x);
-                atomicXor(&tile[plane + a], lo);
-                atomicXor(&tile[2 * plane + a], hi);
-            } else {
-                const uint64_t rowp = (uint64_t)B * P;
-                uint32_t* w = g.sk + (uint64_t)node * kPlanes * rowp + (uint64_t)d * P + p;
-                atomicXor(w, x);
-                atomicXor(w + rowp, lo);
-                atomicXor(w + 2 * rowp, hi);
-            }
+        const uint32_t e0 = (uint32_t)(((uint64_t)count * j) / J);
+        const uint32_t e1 = (uint32_t)(((uint64_t)count * (j + 1)) / J);
+        uint32_t e = e0;
+        for (; e + 4 <= e1; e += 4) {
+            const uint32_t x0 = ent[e], x1 = ent[e + 1], x2 = ent[e + 2], x3 = ent[e + 3];
+            xor_entry<kAllRows>(x0, s, Bm1, DL, Pst, p, plane, tile, skn, rowp, P);
+            xor_entry<kAllRows>(x1, s, Bm1, DL, Pst, p, plane, tile, skn, rowp, P);
+            xor_entry<kAllRows>(x2, s, Bm1, DL, Pst, p, plane, tile, skn, rowp, P);
+            xor_entry<kAllRows>(x3, s, Bm1, DL, Pst, p, plane, tile, skn, rowp, P);
         }
+        for (; e < e1; ++e) xor_entry<kAllRows>(ent[e], s, Bm1, DL, Pst, p, plane, tile, skn, rowp, P);
     }
     __syncthreads();
     const uint32_t nw = blockDim.x >> 6, wave = tid >> 6, lane = tid & 63;
     for (uint32_t row = wave; row < kPlanes * DL; row += nw) {
         const uint32_t pl = row / DL, d = row - pl * DL;
-        uint32_t* dstrow = g.sk + ((uint64_t)node * kPlanes + pl) * B * P + (uint64_t)d * P;
+        uint32_t* dstrow = skn + pl * rowp + (uint64_t)d * P;
         const uint32_t* srow = tile + row * Pst;
-        for (uint32_t p = lane; p < P; p += 64) {
-            const uint32_t val = srow[p];
+        for (uint32_t q = lane; q < P; q += 64) {
+            const uint32_t val = srow[q];
             if (val) {
-                if (shared) atomicXor(&dstrow[p], val);
-                else dstrow[p] ^= val;
+                if (shared) atomicXor(&dstrow[q], val);
+                else dstrow[q] ^= val;
             }
         }
     }
@@ -256,6 +364,7 @@ __device__ __forceinline__ void apply_entries(const uint32_t* __restrict__ ent, 
 // Persistent fused sketch update over a device work list (all graphs of the
 // launch).  Each workgroup takes work items by atomic ticket until the list is
 // exhausted; every workgroup exits once the ticket passes the item count.
+template <bool kAllRows>
 __global__ __launch_bounds__(1024) void k_update(const WorkItem* __restrict__ items,
                                                  uint32_t* __restrict__ ctl,
                                                  const uint32_t* __restrict__ grouped,
@@ -274,12 +383,13 @@ __global__ __launch_bounds__(1024) void k_update(const WorkItem* __restrict__ it
         if (it >= n_items) break;
         const WorkItem w = items[it];
         const GraphDesc g = gd[w.graph];
-        const uint32_t DL = min(lds_rows, g.B);
+        const uint32_t DL = kAllRows ? g.B : min(lds_rows, g.B);
         const uint32_t Pst = (g.P + 63u) & ~63u;
         for (uint32_t i = threadIdx.x; i < w.count; i += blockDim.x) ent[i] = grouped[w.begin + i];
         for (uint32_t i = threadIdx.x; i < kPlanes * DL * Pst; i += blockDim.x) tile[i] = 0;
         __syncthreads();
-        apply_entries(ent, w.count, w.gnode - g.node_base, g, DL, Pst, tile, w.shared != 0);
+        apply_entries<kAllRows>(ent, w.count, w.gnode - g.node_base, g, DL, Pst, tile,
+                                w.shared != 0);
         __syncthreads();
     }
 }
@@ -301,7 +411,7 @@ __global__ __launch_bounds__(1024) void k_update_node(const uint32_t* __restrict
     for (uint32_t i = threadIdx.x; i < cnt; i += blockDim.x) ent[i] = edge_index(node, nbrs[begin + i]);
     for (uint32_t i = threadIdx.x; i < kPlanes * DL * Pst; i += blockDim.x) tile[i] = 0;
     __syncthreads();
-    apply_entries(ent, cnt, node, g, DL, Pst, tile, gridDim.x > 1);
+    apply_entries<false>(ent, cnt, node, g, DL, Pst, tile, gridDim.x > 1);
 }
 
 __global__ void k_validate_nbrs(const uint32_t* __restrict__ nbrs, uint64_t count, uint32_t node,
@@ -322,8 +432,7 @@ __global__ void k_validate_nbrs(const uint32_t* __restrict__ nbrs, uint64_t coun
 namespace {
 
 template <typename T>
-gz_status grow(T** p, uint64_t have, uint64_t need, const char* what) {
-    if (need <= have && *p) return GZ_OK;
+gz_status grow(T** p, uint64_t need, const char* what) {
     if (*p) GZ_HIP(hipFree(*p));
     *p = nullptr;
     hipError_t e = hipMalloc((void**)p, std::max<uint64_t>(need, 1) * sizeof(T));
@@ -334,6 +443,14 @@ gz_status grow(T** p, uint64_t have, uint64_t need, const char* what) {
     return GZ_OK;
 }
 
+template <typename T>
+gz_status grow_host(T** p, uint64_t need) {
+    if (*p) GZ_HIP(hipHostFree(*p));
+    *p = nullptr;
+    GZ_HIP(hipHostMalloc((void**)p, std::max<uint64_t>(need, 1) * sizeof(T), hipHostMallocDefault));
+    return GZ_OK;
+}
+
 uint32_t grid_for(uint64_t n, uint32_t threads, uint32_t cap) {
     uint64_t b = (n + threads - 1) / threads;
     if (b < 1) b = 1;
@@ -341,46 +458,59 @@ uint32_t grid_for(uint64_t n, uint32_t threads, uint32_t cap) {
     return (uint32_t)b;
 }
 
+#define GZ_TRY(x)                 \
+    do {                          \
+        gz_status s_ = (x);       \
+        if (s_) return s_;        \
+    } while (0)
+
 gz_status ensure_scratch(IngestScratch& S, uint64_t N, uint32_t T, uint32_t G, uint32_t chunk,
-                         bool need_staging) {
+                         uint64_t H_size, uint32_t n_units, bool need_staging) {
     int dev = 0;
     GZ_HIP(hipGetDevice(&dev));
     if (S.device != -1 && S.device != dev) return fail(GZ_EINVAL, "graph used on another device");
     S.device = dev;
     if (!S.ctl) {
-        GZ_HIP(hipMalloc((void**)&S.ctl, 4 * sizeof(uint32_t)));
-        GZ_HIP(hipMemset(S.ctl, 0, 4 * sizeof(uint32_t)));
+        GZ_HIP(hipMalloc((void**)&S.ctl, 8 * sizeof(uint32_t)));
+        GZ_HIP(hipMemset(S.ctl, 0, 8 * sizeof(uint32_t)));
         GZ_HIP(hipMalloc((void**)&S.args, sizeof(IngestArgs)));
+        GZ_HIP(hipEventCreateWithFlags(&S.copied_ev, hipEventDisableTiming));
+        GZ_HIP(hipEventRecord(S.copied_ev, 0));
+        GZ_TRY(grow_host(&S.h_args, 1));
+        GZ_TRY(grow_host(&S.h_err, 4));
     }
     if (T > S.cap_nodes || !S.counts) {
-        gz_status st;
-        if ((st = grow(&S.counts, 0, T, "node counts"))) return st;
-        if ((st = grow(&S.packed, 0, (uint64_t)T + 1, "node offsets"))) return st;
-        if ((st = grow(&S.cursor, 0, T, "node cursors"))) return st;
-        if ((st = grow(&S.block_sums, 0, (uint64_t)T / kScanTile + 2, "scan partials"))) return st;
+        GZ_TRY(grow(&S.counts, T, "node counts"));
+        GZ_TRY(grow(&S.block_sums, (uint64_t)T / kScanTile + 2, "scan partials"));
         S.cap_nodes = T;
     }
     if (G > S.cap_graphs || !S.descs) {
-        gz_status st;
-        if ((st = grow(&S.descs, 0, G, "graph table"))) return st;
-        if ((st = grow(&S.offs, 0, (uint64_t)G + 1, "update offsets"))) return st;
+        GZ_TRY(grow(&S.descs, G, "graph table"));
+        GZ_TRY(grow_host(&S.h_descs, G));
         S.cap_graphs = G;
     }
-    uint64_t entries = 2 * N;
+    if (n_units > S.cap_units || !S.units) {
+        GZ_TRY(grow(&S.units, n_units, "grouping units"));
+        GZ_TRY(grow_host(&S.h_units, n_units));
+        S.cap_units = n_units;
+    }
+    if (H_size + 1 > S.cap_H || !S.H) {
+        GZ_TRY(grow(&S.H, H_size + 1, "grouping table"));
+        GZ_TRY(grow(&S.H_sums, (H_size + 1) / kScanTile + 2, "grouping scan partials"));
+        S.cap_H = H_size + 1;
+    }
+    const uint64_t entries = 2 * N;
     if (entries > S.cap_updates || !S.grouped) {
-        gz_status st;
-        if ((st = grow(&S.grouped, 0, entries, "grouped updates"))) return st;
+        GZ_TRY(grow(&S.grouped, entries, "grouped updates"));
         S.cap_updates = entries;
     }
-    uint64_t items = (uint64_t)T + entries / chunk + 1;
+    const uint64_t items = (uint64_t)T + entries / chunk + 1;
     if (items > S.cap_items || !S.items) {
-        gz_status st;
-        if ((st = grow(&S.items, 0, items, "work items"))) return st;
+        GZ_TRY(grow(&S.items, items, "work items"));
         S.cap_items = items;
     }
     if (need_staging && (2 * N > S.cap_staging || !S.staging)) {
-        gz_status st;
-        if ((st = grow(&S.staging, 0, 2 * N, "input staging"))) return st;
+        GZ_TRY(grow(&S.staging, 2 * N, "input staging"));
         S.cap_staging = 2 * N;
     }
     return GZ_OK;
@@ -397,10 +527,18 @@ gz_status set_smem_limit(const void* fn, size_t bytes) {
     return GZ_OK;
 }
 
+void scan32_inplace(uint32_t* x, uint64_t n, uint32_t* sums, hipStream_t s) {
+    const uint32_t nb = (uint32_t)((n + kScanTile - 1) / kScanTile);
+    k_scan32_partial<<<nb, kScanThreads, 0, s>>>(x, n, sums);
+    k_scan32_top<<<1, kScanThreads, 0, s>>>(sums, nb);
+    k_scan32_final<<<nb, kScanThreads, 0, s>>>(x, n, sums);
+}
+
 }  // namespace
 
 void free_ingest_scratch(IngestScratch& S) {
-    hipFree(S.counts); hipFree(S.packed); hipFree(S.block_sums); hipFree(S.cursor);
+    hipFree(S.H); hipFree(S.H_sums); hipFree(S.units); hipFree(S.counts);
+    hipFree(S.packed); hipFree(S.block_sums); hipFree(S.cursor);
     hipFree(S.grouped); hipFree(S.items); hipFree(S.ctl); hipFree(S.args); hipFree(S.offs);
     hipFree(S.descs); hipFree(S.staging);
     if (S.copied_ev) {
@@ -408,6 +546,7 @@ void free_ingest_scratch(IngestScratch& S) {
         hipEventDestroy(S.copied_ev);
     }
     hipHostFree(S.h_args); hipHostFree(S.h_descs); hipHostFree(S.h_offs); hipHostFree(S.h_err);
+    hipHostFree(S.h_units);
     S = IngestScratch{};
 }
 
@@ -424,38 +563,61 @@ gz_status ingest_fused(gz_graph* const* gs, uint32_t G, const uint64_t* offs_hos
     if (G == 0) return fail(GZ_EINVAL, "no graphs");
     if (N >= (1ull << 31)) return fail(GZ_EINVAL, "at most 2^31-1 updates per call");
     if (N && (!src || !dst)) return fail(GZ_EINVAL, "null stream arrays");
-    // descriptor table, shapes, launch parameters
-    std::vector<GraphDesc> descs(G);
-    uint64_t T = 0;
-    uint32_t Pmax = 0, DLmax = 1;
+    if (offs_host) {
+        if (offs_host[0] != 0 || offs_host[G] != N)
+            return fail(GZ_EINVAL, "update offsets must start at 0 and end at N");
+        for (uint32_t k = 0; k < G; ++k)
+            if (offs_host[k + 1] < offs_host[k])
+                return fail(GZ_EINVAL, "update offsets must be non-decreasing");
+    }
     const gz_tuning tune = gs[0]->tuning;
+    const uint32_t chunk = tune.chunk;
+    const uint32_t wg = tune.wg_size;
+    // grouping blocks: about four per CU over the whole call, at least 8192 updates each
+    const uint32_t cus = (uint32_t)device_cu_count();
+    const uint32_t group_chunk =
+        (uint32_t)std::max<uint64_t>(8192, (N + 4ull * cus - 1) / (4ull * cus));
+
+    // descriptor table, grouping plan, shapes
+    std::vector<GraphDesc> descs(G);
+    std::vector<GroupUnit> units;
+    uint64_t T = 0, H_size = 0;
+    uint32_t Pmax = 0, DLmax = 1, range_max = 1;
+    bool all_rows = true;
     for (uint32_t k = 0; k < G; ++k) {
         const gz_graph* g = gs[k];
         if (!g) return fail(GZ_EINVAL, "null graph handle");
-        descs[k].sk = g->sk;
-        descs[k].seeds = g->seeds;
-        descs[k].n = g->n;
-        descs[k].V = g->V;
-        descs[k].R = g->R;
-        descs[k].B = g->B;
-        descs[k].P = g->P;
-        descs[k].node_base = (uint32_t)T;
-        descs[k].pad = 0;
+        const uint64_t b = offs_host ? offs_host[k] : 0;
+        const uint64_t e = offs_host ? offs_host[k + 1] : N;
+        GraphDesc& d = descs[k];
+        d = GraphDesc{};
+        d.sk = g->sk;
+        d.seeds = g->seeds;
+        d.n = g->n;
+        d.V = g->V;
+        d.R = g->R;
+        d.B = g->B;
+        d.P = g->P;
+        d.node_base = (uint32_t)T;
+        d.upd_base = b;
+        d.nb = (uint32_t)((e - b + group_chunk - 1) / group_chunk);
+        d.hoff = H_size;
+        const uint32_t nq = (g->V + kGroupRange - 1) / kGroupRange;
+        for (uint32_t c = 0; c < d.nb; ++c)
+            for (uint32_t q = 0; q < nq; ++q) units.push_back(GroupUnit{k, c, q, 0});
+        H_size += (uint64_t)g->V * d.nb;
         T += g->V;
         Pmax = std::max(Pmax, g->P);
         DLmax = std::max(DLmax, std::min(tune.lds_rows, g->B));
-        if (offs_host && offs_host[k + 1] < offs_host[k])
-            return fail(GZ_EINVAL, "update offsets must be non-decreasing");
+        all_rows = all_rows && tune.lds_rows >= g->B;
+        range_max = std::max(range_max, std::min(g->V, kGroupRange));
     }
-    if (offs_host && (offs_host[0] != 0 || offs_host[G] != N))
-        return fail(GZ_EINVAL, "update offsets must start at 0 and end at N");
     if (T >= (1ull << 32)) return fail(GZ_EINVAL, "too many nodes in one call");
-    const uint32_t chunk = tune.chunk;
-    const uint32_t wg = tune.wg_size;
+    if (H_size >= (1ull << 32)) return fail(GZ_EINVAL, "call too large: split the stream");
     if (wg < Pmax || wg % 64 || wg > 1024) return fail(GZ_EINVAL, "workgroup smaller than pairs");
     const bool host_ptr = !(flags & GZ_DEVICE_PTR);
-    gz_status st = ensure_scratch(S, N, (uint32_t)T, G, chunk, host_ptr);
-    if (st) return st;
+    const uint32_t n_units = (uint32_t)units.size();
+    GZ_TRY(ensure_scratch(S, N, (uint32_t)T, G, chunk, H_size, n_units, host_ptr));
 
     // order after earlier work on these graphs (e.g. a query on another stream)
     for (uint32_t k = 0; k < G; ++k) GZ_HIP(hipStreamWaitEvent(stream, gs[k]->last, 0));
@@ -468,60 +630,71 @@ gz_status ingest_fused(gz_graph* const* gs, uint32_t G, const uint64_t* offs_hos
         dsrc = S.staging;
         ddst = S.staging + N;
     }
-    if (!S.copied_ev) {
-        GZ_HIP(hipEventCreateWithFlags(&S.copied_ev, hipEventDisableTiming));
-        GZ_HIP(hipHostMalloc((void**)&S.h_args, sizeof(IngestArgs), hipHostMallocDefault));
-        GZ_HIP(hipHostMalloc((void**)&S.h_err, 4 * sizeof(uint32_t), hipHostMallocDefault));
-    } else {
-        GZ_HIP(hipEventSynchronize(S.copied_ev));  // previous uploads have left the buffers
-    }
-    if (G > S.cap_h_graphs || !S.h_descs) {
-        if (S.h_descs) GZ_HIP(hipHostFree(S.h_descs));
-        if (S.h_offs) GZ_HIP(hipHostFree(S.h_offs));
-        S.h_descs = nullptr;
-        S.h_offs = nullptr;
-        GZ_HIP(hipHostMalloc((void**)&S.h_descs, sizeof(GraphDesc) * G, hipHostMallocDefault));
-        GZ_HIP(hipHostMalloc((void**)&S.h_offs, sizeof(uint64_t) * (G + 1), hipHostMallocDefault));
-        S.cap_h_graphs = G;
-    }
+    // per-call tables go through pinned buffers, reused once the previous
+    // call's uploads have left them
+    GZ_HIP(hipEventSynchronize(S.copied_ev));
     IngestArgs& a = *S.h_args;
     a = IngestArgs{};
     a.src = dsrc;
     a.dst = ddst;
-    a.offs = S.offs;
+    a.offs = nullptr;
     a.N = N;
     a.G = G;
     a.T = (uint32_t)T;
     a.chunk = chunk;
     a.lds_rows = tune.lds_rows;
+    a.group_chunk = group_chunk;
+    a.n_units = n_units;
+    a.H_size = H_size;
     std::memcpy(S.h_descs, descs.data(), sizeof(GraphDesc) * G);
+    if (n_units) std::memcpy(S.h_units, units.data(), sizeof(GroupUnit) * n_units);
     GZ_HIP(hipMemcpyAsync(S.args, S.h_args, sizeof(IngestArgs), hipMemcpyHostToDevice, stream));
     GZ_HIP(hipMemcpyAsync(S.descs, S.h_descs, sizeof(GraphDesc) * G, hipMemcpyHostToDevice,
                           stream));
-    if (G > 1) {
-        std::memcpy(S.h_offs, offs_host, sizeof(uint64_t) * (G + 1));
-        GZ_HIP(hipMemcpyAsync(S.offs, S.h_offs, sizeof(uint64_t) * (G + 1),
+    if (n_units)
+        GZ_HIP(hipMemcpyAsync(S.units, S.h_units, sizeof(GroupUnit) * n_units,
                               hipMemcpyHostToDevice, stream));
-    }
     GZ_HIP(hipEventRecord(S.copied_ev, stream));
 
+    gz_graph* prof = gs[0]->profiling ? gs[0] : nullptr;
+    if (prof) GZ_HIP(hipEventRecord(prof->prof_ev[0], stream));
     const uint32_t Tn = (uint32_t)T;
-    k_fill_u32<<<grid_for(Tn, 256, 4096), 256, 0, stream>>>(S.counts, Tn, 0);
     k_fill_u32<<<1, 64, 0, stream>>>(S.ctl, 3, 0);  // ticket, items, call error (sticky kept)
-    const uint32_t ugrid = grid_for(N, 256, 8192);
-    k_count<<<ugrid, 256, 0, stream>>>(S.args, S.descs, S.counts, S.ctl);
+    k_fill_u32<<<grid_for(H_size + 1, 256, 4096), 256, 0, stream>>>(S.H, H_size + 1, 0);
+    const size_t gsmem = (size_t)range_max * 4;
+    GZ_TRY(set_smem_limit((const void*)k_group_count, gsmem));
+    GZ_TRY(set_smem_limit((const void*)k_group_scatter, gsmem));
+    if (n_units)
+        k_group_count<<<n_units, kGroupThreads, gsmem, stream>>>(S.args, S.units, S.descs, S.H,
+                                                                 S.ctl);
+    scan32_inplace(S.H, H_size + 1, S.H_sums, stream);
+    k_group_node_counts<<<grid_for(Tn, 256, 8192), 256, 0, stream>>>(S.descs, G, Tn, S.H,
+                                                                      S.counts);
     const uint32_t nblocks = (uint32_t)((T + kScanTile - 1) / kScanTile);
     k_scan_partial<<<nblocks, kScanThreads, 0, stream>>>(S.counts, Tn, chunk, S.block_sums);
-    k_scan_top<<<1, kScanThreads, 0, stream>>>(S.block_sums, nblocks, S.packed, Tn, S.ctl);
-    k_scan_final<<<nblocks, kScanThreads, 0, stream>>>(S.counts, Tn, chunk, S.block_sums,
-                                                       S.packed, S.cursor, S.items, S.descs, G,
-                                                       S.ctl);
-    k_scatter<<<ugrid, 256, 0, stream>>>(S.args, S.descs, S.cursor, S.grouped, S.ctl);
+    k_scan_top<<<1, kScanThreads, 0, stream>>>(S.block_sums, nblocks, S.ctl);
+    k_scan_items<<<nblocks, kScanThreads, 0, stream>>>(S.counts, Tn, chunk, S.block_sums, S.items,
+                                                       S.descs, G, S.ctl);
+    if (n_units)
+        k_group_scatter<<<n_units, kGroupThreads, gsmem, stream>>>(S.args, S.units, S.descs, S.H,
+                                                                   S.grouped, S.ctl);
     const size_t smem = update_smem_bytes(chunk, DLmax, Pmax);
-    if ((st = set_smem_limit((const void*)k_update, smem))) return st;
-    const uint32_t pgrid = std::max(1u, tune.wgs_per_cu) * (uint32_t)device_cu_count();
-    k_update<<<pgrid, wg, smem, stream>>>(S.items, S.ctl, S.grouped, S.descs, tune.lds_rows, chunk);
+    const uint32_t pgrid = std::max(1u, tune.wgs_per_cu) * cus;
+    if (prof) GZ_HIP(hipEventRecord(prof->prof_ev[1], stream));
+    if (all_rows) {
+        GZ_TRY(set_smem_limit((const void*)k_update<true>, smem));
+        k_update<true><<<pgrid, wg, smem, stream>>>(S.items, S.ctl, S.grouped, S.descs,
+                                                    tune.lds_rows, chunk);
+    } else {
+        GZ_TRY(set_smem_limit((const void*)k_update<false>, smem));
+        k_update<false><<<pgrid, wg, smem, stream>>>(S.items, S.ctl, S.grouped, S.descs,
+                                                     tune.lds_rows, chunk);
+    }
     GZ_HIP(hipGetLastError());
+    if (prof) {
+        GZ_HIP(hipEventRecord(prof->prof_ev[2], stream));
+        prof->prof_calls++;
+    }
     for (uint32_t k = 0; k < G; ++k) GZ_HIP(hipEventRecord(gs[k]->last, stream));
 
     if (!(flags & GZ_ASYNC)) {
@@ -553,21 +726,21 @@ gz_status update_node_batch(gz_graph* g, uint32_t node, const uint32_t* nbrs, ui
             if (nbrs[k] == node || nbrs[k] >= g->V)
                 return fail(GZ_EINVAL, "invalid neighbour (self-loop or id out of range)");
     }
-    gz_status st = ensure_scratch(S, 0, g->V, 1, tune.chunk, false);
-    if (st) return st;
+    GZ_TRY(ensure_scratch(S, 0, g->V, 1, tune.chunk, 0, 0, false));
     GZ_HIP(hipStreamWaitEvent(stream, g->last, 0));
     const uint32_t* d = nbrs;
     if (host_ptr) {
         if (count > S.cap_staging || !S.staging) {
-            if ((st = grow(&S.staging, 0, count, "input staging"))) return st;
+            GZ_TRY(grow(&S.staging, count, "input staging"));
             S.cap_staging = count;
         }
         GZ_HIP(hipMemcpyAsync(S.staging, nbrs, count * 4, hipMemcpyHostToDevice, stream));
         d = S.staging;
     }
     // ctl[2] / ctl[3]: call error / sticky error, as in the fused path
-    k_fill_u32<<<1, 64, 0, stream>>>(S.ctl + 2, 1, 0);
-    if (!host_ptr)
+    const bool check = !(flags & GZ_UNCHECKED);
+    if (check) k_fill_u32<<<1, 64, 0, stream>>>(S.ctl + 2, 1, 0);
+    if (!host_ptr && check)
         k_validate_nbrs<<<grid_for(count, 256, 1024), 256, 0, stream>>>(d, count, node, g->V,
                                                                        S.ctl + 2);
     GraphDesc gd{};
@@ -581,18 +754,19 @@ gz_status update_node_batch(gz_graph* g, uint32_t node, const uint32_t* nbrs, ui
     const uint32_t chunk = tune.chunk;
     const uint32_t DL = std::min(tune.lds_rows, g->B);
     const size_t smem = update_smem_bytes(chunk, DL, g->P);
-    if ((st = set_smem_limit((const void*)k_update_node, smem))) return st;
+    GZ_TRY(set_smem_limit((const void*)k_update_node, smem));
     const uint32_t grid = (uint32_t)((count + chunk - 1) / chunk);
+    // unchecked calls point the kernel at ctl[4], a word nothing ever sets
+    const uint32_t* errp = check ? S.ctl + 2 : S.ctl + 4;
     k_update_node<<<grid, tune.wg_size, smem, stream>>>(d, (uint32_t)count, node, gd,
-                                                          tune.lds_rows, chunk, S.ctl + 2);
+                                                          tune.lds_rows, chunk, errp);
     GZ_HIP(hipGetLastError());
     GZ_HIP(hipEventRecord(g->last, stream));
-    if (!host_ptr) {
+    if (!host_ptr && check) {
         if (!(flags & GZ_ASYNC)) {
-            uint32_t err = 0;
-            GZ_HIP(hipMemcpyAsync(&err, S.ctl + 2, 4, hipMemcpyDeviceToHost, stream));
+            GZ_HIP(hipMemcpyAsync(S.h_err, S.ctl + 2, 4, hipMemcpyDeviceToHost, stream));
             GZ_HIP(hipStreamSynchronize(stream));
-            if (err) {
+            if (S.h_err[0]) {
                 k_fill_u32<<<1, 64, 0, stream>>>(S.ctl + 3, 1, 0);
                 GZ_HIP(hipStreamSynchronize(stream));
                 return fail(GZ_EINVAL, "invalid neighbour (self-loop or id out of range)");
@@ -600,7 +774,7 @@ gz_status update_node_batch(gz_graph* g, uint32_t node, const uint32_t* nbrs, ui
         } else {
             g->pending_error = true;
         }
-    } else {
+    } else if (host_ptr) {
         // the host copy must finish before the caller may reuse its buffer
         GZ_HIP(hipStreamSynchronize(stream));
     }

@@ -38,7 +38,9 @@ struct GraphDesc {
     uint64_t n;          // V(V-1)/2
     uint32_t V, R, B, P;
     uint32_t node_base;  // first global node id in a fused launch
-    uint32_t pad;
+    uint32_t nb;         // grouping chunks of this graph's updates in the launch
+    uint64_t upd_base;   // first update of this graph in the launch's stream
+    uint64_t hoff;       // start of this graph's (node, chunk) count table
 };
 
 // One unit of work of the persistent sketch-update kernel: up to `chunk`
@@ -52,6 +54,13 @@ struct WorkItem {
     uint32_t pad;
 };
 
+// One block of the grouping pass: chunk `c` of graph `g`'s updates, counted or
+// scattered for the node range [q * kGroupRange, (q+1) * kGroupRange).
+struct GroupUnit {
+    uint32_t g, c, q, pad;
+};
+constexpr uint32_t kGroupRange = 32768;  // node counters per block (128 KiB of LDS)
+
 // Arguments of a fused ingest launch sequence, read by the kernels from device
 // memory so that a captured graph can be replayed on new inputs.
 struct IngestArgs {
@@ -63,6 +72,9 @@ struct IngestArgs {
     uint32_t T;               // total nodes over all graphs
     uint32_t chunk;
     uint32_t lds_rows;
+    uint32_t group_chunk;     // updates per grouping block
+    uint32_t n_units;
+    uint64_t H_size;          // entries of the (node, chunk) count table
 };
 
 // Device scratch of the ingest path, grown on demand.
@@ -72,13 +84,20 @@ struct IngestScratch {
     uint32_t cap_nodes = 0;
     uint32_t cap_graphs = 0;
     uint64_t cap_items = 0;
+    uint32_t* H = nullptr;          // (node, chunk) counts, scanned in place (H_size + 1)
+    uint64_t cap_H = 0;
+    uint32_t* H_sums = nullptr;     // scan partials of H
+    GroupUnit* units = nullptr;
+    GroupUnit* h_units = nullptr;   // pinned
+    uint32_t cap_units = 0;
     uint32_t* counts = nullptr;     // T: entries per node (u32)
     uint64_t* packed = nullptr;     // T+1: scanned (entries | items << 40)
     uint64_t* block_sums = nullptr; // scan partials
     uint32_t* cursor = nullptr;     // T
     uint32_t* grouped = nullptr;    // 2N edge indices grouped by endpoint
     WorkItem* items = nullptr;
-    uint32_t* ctl = nullptr;        // [0] ticket, [1] n_items, [2] call error, [3] sticky errors
+    uint32_t* ctl = nullptr;        // [0] ticket, [1] n_items, [2] call error, [3] sticky errors,
+                                    // [4..7] always zero
     IngestArgs* args = nullptr;
     uint64_t* offs = nullptr;       // G+1
     GraphDesc* descs = nullptr;     // G
@@ -113,6 +132,10 @@ struct gz_graph {
     gz::IngestScratch ing;
     gz::QueryScratch* q = nullptr;
     bool pending_error = false;
+    // optional per-phase timing of the last ingest (gz_profile_enable)
+    bool profiling = false;
+    hipEvent_t prof_ev[3] = {nullptr, nullptr, nullptr};
+    uint32_t prof_calls = 0;
 };
 
 namespace gz {
@@ -127,7 +150,7 @@ gz_status hip_fail(hipError_t e, const char* what);
     } while (0)
 
 int device_cu_count();
-uint32_t default_lds_rows(uint32_t B);
+gz_tuning default_tuning(uint32_t P, uint32_t B);
 
 // ingest path (gz_ingest.hip)
 gz_status ingest_fused(gz_graph* const* gs, uint32_t G, const uint64_t* offs_host,

@@ -426,7 +426,15 @@ gz_status boruvka(gz_graph* const* gs, uint32_t G, bool want_forest, QueryResult
     for (uint32_t k = 0; k < G; ++k) {
         const gz_graph* g = gs[k];
         if (!g) return fail(GZ_EINVAL, "null graph handle");
-        descs[k] = GraphDesc{g->sk, g->seeds, g->n, g->V, g->R, g->B, g->P, (uint32_t)T64, 0};
+        descs[k] = GraphDesc{};
+        descs[k].sk = g->sk;
+        descs[k].seeds = g->seeds;
+        descs[k].n = g->n;
+        descs[k].V = g->V;
+        descs[k].R = g->R;
+        descs[k].B = g->B;
+        descs[k].P = g->P;
+        descs[k].node_base = (uint32_t)T64;
         T64 += g->V;
         Rmax = std::max(Rmax, g->R);
         Bmax = std::max(Bmax, g->B);

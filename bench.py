@@ -33,7 +33,10 @@ sys.path.insert(0, ROOT)
 # MI355X figures used by the roofline (the design doc derives them)
 PEAK_INT_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12   # VALU lane-instructions/s: 39.32 T
 PEAK_HBM_GBS = 8000.0
-OPS_PER_ENTRY_PAIR = 8  # 3 multiply-add-shift hashes (2 mads each) + ctz + clamp
+# algorithmic integer ops per (update, round-column pair): the three hashes of the
+# edge index (row hash 3, 64-bit checksum 6, depth 2) counted once per update,
+# plus one exact-depth XOR of (alpha, gamma) per endpoint (4 each)
+OPS_PER_UPDATE_PAIR = 19
 
 
 def log(msg: str) -> None:
@@ -203,7 +206,7 @@ def main() -> int:
     grp_ms = statistics.median(p["group_ms"] for p in profs)
     ing_ms = statistics.median(p["ingest_ms"] for p in profs)
     P = g.R * g.C
-    ops = stream.N * 2 * P * OPS_PER_ENTRY_PAIR
+    ops = stream.N * P * OPS_PER_UPDATE_PAIR
     achieved = ops / (upd_ms * 1e-3) / 1e12
     traffic = traffic_from_profile(kernel_source_hash())
 
@@ -234,8 +237,8 @@ def main() -> int:
                      "traffic": traffic,
                      "kernel": "k_update",
                      "ops_per_launch": ops,
-                     "ops_rule": f"{OPS_PER_ENTRY_PAIR} int ops per (endpoint entry, round-column "
-                                 f"pair): 2 entries x {P} pairs per update"},
+                     "ops_rule": f"{OPS_PER_UPDATE_PAIR} int ops per (update, round-column pair), "
+                                 f"{P} pairs per update"},
     }
     if not args.no_plain:
         rate, calls, gutter, pms = plain_pass(gz, g, stream, src_d, dst_d)

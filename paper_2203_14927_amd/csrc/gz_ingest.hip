@@ -287,22 +287,27 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_items(
 
 // ------------------------------------------------------------ sketch update --
 
-// Hash one staged entry for this lane's (round, column) pair and XOR it into
-// the exact-depth row of the LDS tile; rows >= DL (kAllRows == false only) go
+// The LDS tile interleaves the three planes bucket by bucket: word
+// (d * P + p) * 3 + plane holds plane `plane` of row d of pair p, so one
+// 24-bit multiply-add gives the address and the planes are immediate offsets.
+// Lanes of one wave with the same row touch banks 3p mod 64, all distinct.
+
+// Hash one entry for this lane's (round, column) pair and XOR it into the
+// exact-depth row of the LDS tile; rows >= DL (kAllRows == false only) go
 // straight to HBM with atomics.
 template <bool kAllRows>
 __device__ __forceinline__ void xor_entry(uint32_t x, const PairSeeds& s, uint32_t Bm1,
-                                          uint32_t DL, uint32_t Pst, uint32_t p, uint32_t plane,
-                                          uint32_t* __restrict__ tile, uint32_t* __restrict__ skn,
-                                          uint64_t rowp, uint32_t P) {
+                                          uint32_t DL, uint32_t row_bytes, uint32_t lane_bytes,
+                                          uint8_t* __restrict__ tile, uint32_t* __restrict__ skn,
+                                          uint64_t rowp, uint32_t P, uint32_t p) {
     const uint32_t d = row_depth(s, x, Bm1);
     const uint32_t hi = chk_hi(s, x);
     const uint32_t lo = chk_lo(s, x);
     if (kAllRows || d < DL) {
-        const uint32_t a = d * Pst + p;
-        atomicXor(&tile[a], x);
-        atomicXor(&tile[plane + a], lo);
-        atomicXor(&tile[2 * plane + a], hi);
+        uint32_t* a = (uint32_t*)(tile + (__umul24(d, row_bytes) + lane_bytes));
+        atomicXor(a, x);
+        atomicXor(a + 1, lo);
+        atomicXor(a + 2, hi);
     } else {
         uint32_t* w = skn + (uint64_t)d * P + p;
         atomicXor(w, x);
@@ -311,17 +316,45 @@ __device__ __forceinline__ void xor_entry(uint32_t x, const PairSeeds& s, uint32
     }
 }
 
-// Apply `count` staged edge indices (ent[], in LDS) to node `node` of graph `g`.
-// Lanes map to (group j, pair p): J = blockDim / P groups each take a
-// contiguous share of the entries; each lane hashes its pair's seeds and XORs
-// into the exact-depth row of its column.  The tile is then XORed back into
-// HBM: plain read-modify-write when this workgroup owns the node for the
+// Entry sources: the grouped edge indices of the fused path, or a node's raw
+// neighbour list in the plain per-node path (index computed on the fly).
+// Both read four consecutive entries with one 16-byte load when the address
+// is 16-byte aligned (the caller aligns the quads).
+struct GroupedEntries {
+    const uint32_t* __restrict__ p;
+    __device__ __forceinline__ uint32_t one(uint32_t e) const { return p[e]; }
+    __device__ __forceinline__ uint4 quad(uint32_t e) const {
+        return *reinterpret_cast<const uint4*>(p + e);
+    }
+    __device__ __forceinline__ uint32_t misalign() const {
+        return (uint32_t)(((uintptr_t)p >> 2) & 3u);
+    }
+};
+struct NeighbourEntries {
+    const uint32_t* __restrict__ p;
+    uint32_t node;
+    __device__ __forceinline__ uint32_t one(uint32_t e) const { return edge_index(node, p[e]); }
+    __device__ __forceinline__ uint4 quad(uint32_t e) const {
+        uint4 v = *reinterpret_cast<const uint4*>(p + e);
+        return make_uint4(edge_index(node, v.x), edge_index(node, v.y), edge_index(node, v.z),
+                          edge_index(node, v.w));
+    }
+    __device__ __forceinline__ uint32_t misalign() const {
+        return (uint32_t)(((uintptr_t)p >> 2) & 3u);
+    }
+};
+
+// Apply `count` entries to node `node` of graph `g`.  Lanes map to
+// (group j, pair p): J = blockDim / P groups each take a contiguous share of
+// the entries; each lane hashes its pair's seeds and XORs into the exact-depth
+// row of its column.  Entries arrive from HBM in 16-byte quads, eight entries
+// per iteration with the next eight in flight.  The tile is then XORed back
+// into HBM: plain read-modify-write when this workgroup owns the node for the
 // launch, atomics when the node's entries are split across workgroups.
-template <bool kAllRows>
-__device__ __forceinline__ void apply_entries(const uint32_t* __restrict__ ent, uint32_t count,
-                                              uint32_t node, const GraphDesc& g, uint32_t DL,
-                                              uint32_t Pst, uint32_t* __restrict__ tile,
-                                              bool shared) {
+template <bool kAllRows, typename Src>
+__device__ __forceinline__ void apply_entries(const Src& ent, uint32_t count, uint32_t node,
+                                              const GraphDesc& g, uint32_t DL,
+                                              uint32_t* __restrict__ tile, bool shared) {
     const uint32_t tid = threadIdx.x;
     const uint32_t P = g.P, B = g.B;
     const uint32_t J = blockDim.x / P;
@@ -332,27 +365,49 @@ __device__ __forceinline__ void apply_entries(const uint32_t* __restrict__ ent, 
         const uint32_t p = tid - j * P;
         const PairSeeds s = load_pair_seeds(g.seeds, P, p);
         const uint32_t Bm1 = B - 1;
-        const uint32_t plane = DL * Pst;
-        const uint32_t e0 = (uint32_t)(((uint64_t)count * j) / J);
-        const uint32_t e1 = (uint32_t)(((uint64_t)count * (j + 1)) / J);
-        uint32_t e = e0;
-        for (; e + 4 <= e1; e += 4) {
-            const uint32_t x0 = ent[e], x1 = ent[e + 1], x2 = ent[e + 2], x3 = ent[e + 3];
-            xor_entry<kAllRows>(x0, s, Bm1, DL, Pst, p, plane, tile, skn, rowp, P);
-            xor_entry<kAllRows>(x1, s, Bm1, DL, Pst, p, plane, tile, skn, rowp, P);
-            xor_entry<kAllRows>(x2, s, Bm1, DL, Pst, p, plane, tile, skn, rowp, P);
-            xor_entry<kAllRows>(x3, s, Bm1, DL, Pst, p, plane, tile, skn, rowp, P);
+        const uint32_t row_bytes = P * kPlanes * 4;
+        const uint32_t lane_bytes = p * kPlanes * 4;
+        uint8_t* tb = (uint8_t*)tile;
+#define GZ_XOR(x) xor_entry<kAllRows>((x), s, Bm1, DL, row_bytes, lane_bytes, tb, skn, rowp, P, p)
+        // group ranges start on 16-byte boundaries of the source array
+        const uint32_t mis = ent.misalign();
+        const uint32_t head = (4u - mis) & 3u;
+        uint32_t e0, e1;
+        if (count <= head + 8u * J) {
+            e0 = j == 0 ? 0u : count;
+            e1 = count;
+        } else {
+            const uint32_t quads = (count - head) >> 2;
+            e0 = j == 0 ? 0u : head + 4u * (uint32_t)(((uint64_t)quads * j) / J);
+            e1 = j + 1 == J ? count : head + 4u * (uint32_t)(((uint64_t)quads * (j + 1)) / J);
         }
-        for (; e < e1; ++e) xor_entry<kAllRows>(ent[e], s, Bm1, DL, Pst, p, plane, tile, skn, rowp, P);
+        uint32_t e = e0;
+        // unaligned head (group 0 only) and short ranges
+        while (e < e1 && ((e + mis) & 3u)) GZ_XOR(ent.one(e++));
+        if (e + 8 <= e1) {
+            uint4 a = ent.quad(e), b = ent.quad(e + 4);
+            for (; e + 16 <= e1; e += 8) {
+                const uint4 na = ent.quad(e + 8), nb = ent.quad(e + 12);
+                GZ_XOR(a.x); GZ_XOR(a.y); GZ_XOR(a.z); GZ_XOR(a.w);
+                GZ_XOR(b.x); GZ_XOR(b.y); GZ_XOR(b.z); GZ_XOR(b.w);
+                a = na;
+                b = nb;
+            }
+            GZ_XOR(a.x); GZ_XOR(a.y); GZ_XOR(a.z); GZ_XOR(a.w);
+            GZ_XOR(b.x); GZ_XOR(b.y); GZ_XOR(b.z); GZ_XOR(b.w);
+            e += 8;
+        }
+        for (; e < e1; ++e) GZ_XOR(ent.one(e));
+#undef GZ_XOR
     }
     __syncthreads();
     const uint32_t nw = blockDim.x >> 6, wave = tid >> 6, lane = tid & 63;
     for (uint32_t row = wave; row < kPlanes * DL; row += nw) {
         const uint32_t pl = row / DL, d = row - pl * DL;
         uint32_t* dstrow = skn + pl * rowp + (uint64_t)d * P;
-        const uint32_t* srow = tile + row * Pst;
+        const uint32_t* srow = tile + d * P * kPlanes + pl;
         for (uint32_t q = lane; q < P; q += 64) {
-            const uint32_t val = srow[q];
+            const uint32_t val = srow[q * kPlanes];
             if (val) {
                 if (shared) atomicXor(&dstrow[q], val);
                 else dstrow[q] ^= val;
@@ -369,13 +424,11 @@ __global__ __launch_bounds__(1024) void k_update(const WorkItem* __restrict__ it
                                                  uint32_t* __restrict__ ctl,
                                                  const uint32_t* __restrict__ grouped,
                                                  const GraphDesc* __restrict__ gd,
-                                                 uint32_t lds_rows, uint32_t chunk) {
-    extern __shared__ uint32_t smem[];
+                                                 uint32_t lds_rows) {
+    extern __shared__ uint32_t tile[];
     __shared__ uint32_t s_item;
     if (ctl[2]) return;
     const uint32_t n_items = ctl[1];
-    uint32_t* ent = smem;
-    uint32_t* tile = smem + chunk;
     for (;;) {
         if (threadIdx.x == 0) s_item = atomicAdd(&ctl[0], 1u);
         __syncthreads();
@@ -384,12 +437,10 @@ __global__ __launch_bounds__(1024) void k_update(const WorkItem* __restrict__ it
         const WorkItem w = items[it];
         const GraphDesc g = gd[w.graph];
         const uint32_t DL = kAllRows ? g.B : min(lds_rows, g.B);
-        const uint32_t Pst = (g.P + 63u) & ~63u;
-        for (uint32_t i = threadIdx.x; i < w.count; i += blockDim.x) ent[i] = grouped[w.begin + i];
-        for (uint32_t i = threadIdx.x; i < kPlanes * DL * Pst; i += blockDim.x) tile[i] = 0;
+        for (uint32_t i = threadIdx.x; i < kPlanes * DL * g.P; i += blockDim.x) tile[i] = 0;
         __syncthreads();
-        apply_entries<kAllRows>(ent, w.count, w.gnode - g.node_base, g, DL, Pst, tile,
-                                w.shared != 0);
+        apply_entries<kAllRows>(GroupedEntries{grouped + w.begin}, w.count,
+                                w.gnode - g.node_base, g, DL, tile, w.shared != 0);
         __syncthreads();
     }
 }
@@ -400,18 +451,15 @@ __global__ __launch_bounds__(1024) void k_update_node(const uint32_t* __restrict
                                                       uint32_t count, uint32_t node, GraphDesc g,
                                                       uint32_t lds_rows, uint32_t chunk,
                                                       const uint32_t* __restrict__ err) {
-    extern __shared__ uint32_t smem[];
+    extern __shared__ uint32_t tile[];
     if (*err) return;
-    uint32_t* ent = smem;
-    uint32_t* tile = smem + chunk;
     const uint32_t begin = blockIdx.x * chunk;
     const uint32_t cnt = min(chunk, count - begin);
     const uint32_t DL = min(lds_rows, g.B);
-    const uint32_t Pst = (g.P + 63u) & ~63u;
-    for (uint32_t i = threadIdx.x; i < cnt; i += blockDim.x) ent[i] = edge_index(node, nbrs[begin + i]);
-    for (uint32_t i = threadIdx.x; i < kPlanes * DL * Pst; i += blockDim.x) tile[i] = 0;
+    for (uint32_t i = threadIdx.x; i < kPlanes * DL * g.P; i += blockDim.x) tile[i] = 0;
     __syncthreads();
-    apply_entries<false>(ent, cnt, node, g, DL, Pst, tile, gridDim.x > 1);
+    apply_entries<false>(NeighbourEntries{nbrs + begin, node}, cnt, node, g, DL, tile,
+                         gridDim.x > 1);
 }
 
 __global__ void k_validate_nbrs(const uint32_t* __restrict__ nbrs, uint64_t count, uint32_t node,
@@ -516,9 +564,8 @@ gz_status ensure_scratch(IngestScratch& S, uint64_t N, uint32_t T, uint32_t G, u
     return GZ_OK;
 }
 
-size_t update_smem_bytes(uint32_t chunk, uint32_t DL, uint32_t Pmax) {
-    uint32_t Pst = (Pmax + 63u) & ~63u;
-    return (size_t)chunk * 4 + (size_t)kPlanes * DL * Pst * 4;
+size_t update_smem_bytes(uint32_t DL, uint32_t Pmax) {
+    return (size_t)kPlanes * DL * Pmax * 4;
 }
 
 gz_status set_smem_limit(const void* fn, size_t bytes) {
@@ -678,17 +725,17 @@ gz_status ingest_fused(gz_graph* const* gs, uint32_t G, const uint64_t* offs_hos
     if (n_units)
         k_group_scatter<<<n_units, kGroupThreads, gsmem, stream>>>(S.args, S.units, S.descs, S.H,
                                                                    S.grouped, S.ctl);
-    const size_t smem = update_smem_bytes(chunk, DLmax, Pmax);
+    const size_t smem = update_smem_bytes(DLmax, Pmax);
     const uint32_t pgrid = std::max(1u, tune.wgs_per_cu) * cus;
     if (prof) GZ_HIP(hipEventRecord(prof->prof_ev[1], stream));
     if (all_rows) {
         GZ_TRY(set_smem_limit((const void*)k_update<true>, smem));
         k_update<true><<<pgrid, wg, smem, stream>>>(S.items, S.ctl, S.grouped, S.descs,
-                                                    tune.lds_rows, chunk);
+                                                    tune.lds_rows);
     } else {
         GZ_TRY(set_smem_limit((const void*)k_update<false>, smem));
         k_update<false><<<pgrid, wg, smem, stream>>>(S.items, S.ctl, S.grouped, S.descs,
-                                                     tune.lds_rows, chunk);
+                                                     tune.lds_rows);
     }
     GZ_HIP(hipGetLastError());
     if (prof) {
@@ -753,7 +800,7 @@ gz_status update_node_batch(gz_graph* g, uint32_t node, const uint32_t* nbrs, ui
     gd.P = g->P;
     const uint32_t chunk = tune.chunk;
     const uint32_t DL = std::min(tune.lds_rows, g->B);
-    const size_t smem = update_smem_bytes(chunk, DL, g->P);
+    const size_t smem = update_smem_bytes(DL, g->P);
     GZ_TRY(set_smem_limit((const void*)k_update_node, smem));
     const uint32_t grid = (uint32_t)((count + chunk - 1) / chunk);
     // unchecked calls point the kernel at ctl[4], a word nothing ever sets

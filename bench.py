@@ -151,6 +151,10 @@ def main() -> int:
     ap.add_argument("--no-plain", action="store_true", help="skip the plain per-node pass")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default launch parameters")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run one 1 GiB device-to-device copy (a kernel of known traffic "
+                         "that scales hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"this benchmark runs on one GPU only (asked for {args.gpus}); the multi-GPU "
@@ -170,7 +174,20 @@ def main() -> int:
         f"(generated in {time.perf_counter() - t0:.1f} s)")
     src_d = torch.from_numpy(stream.src.view(np.int32)).cuda()
     dst_d = torch.from_numpy(stream.dst.view(np.int32)).cuda()
+    if args.copy_calibration:
+        a = torch.empty(1 << 28, dtype=torch.int32, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)  # reads 1 GiB, writes 1 GiB
+        torch.cuda.synchronize()
+        del a, b
     g = gz.Graph(stream.V, seed=seed)
+    tune_ms = None
+    if not args.no_autotune:
+        t0 = time.perf_counter()
+        best, tune_ms = g.autotune(src_d, dst_d)
+        log(f"[bench] autotuned in {time.perf_counter() - t0:.1f} s: {best} "
+            f"({tune_ms:.2f} ms per ingest)")
     g.profile(True)
     torch.cuda.synchronize()
 
@@ -232,6 +249,7 @@ def main() -> int:
         "cc_query_ms": cc_query_ms,
         "components": ncc,
         "tuning": g.tuning,
+        "autotuned": not args.no_autotune,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_INT_TOPS,
                      "unit": "TOP/s", "frac": achieved / PEAK_INT_TOPS,
                      "traffic": traffic,

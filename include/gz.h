@@ -222,6 +222,18 @@ gz_status gz_export_sketches(gz_graph* g, uint32_t node_lo, uint32_t node_hi, ui
  * measure traffic); the layout is private. */
 gz_status gz_sketch_storage(const gz_graph* g, void** dev_ptr, uint64_t* bytes);
 
+/* ------------------------------------------------------------------------
+ * gz_autotune -- pick the ingest launch parameters for g's shape: time a set
+ *   of candidate (workgroup size, LDS rows, chunk, workgroups per CU)
+ *   configurations on the sample stream src/dst (N updates, device memory:
+ *   flags must hold GZ_DEVICE_PTR), with HIP events on `stream`, using a
+ *   scratch graph of the same shape (g's sketches are not touched).  The
+ *   fastest configuration is set on g and returned in *best (nullable) with
+ *   its ingest time in *best_ms (nullable).  Synchronous.
+ * ---------------------------------------------------------------------- */
+gz_status gz_autotune(gz_graph* g, const uint32_t* src, const uint32_t* dst, uint64_t N,
+                      uint32_t flags, hipStream_t stream, gz_tuning* best, float* best_ms);
+
 /* Launch parameters of the ingest path for this graph (get / set). */
 gz_status gz_get_tuning(const gz_graph* g, gz_tuning* t);
 gz_status gz_set_tuning(gz_graph* g, const gz_tuning* t);

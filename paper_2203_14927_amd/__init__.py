@@ -84,6 +84,9 @@ _SIGS = {
                            ctypes.POINTER(ctypes.c_uint64)], ctypes.c_int32),
     "gz_get_tuning": ([ctypes.c_void_p, ctypes.POINTER(gz_tuning)], ctypes.c_int32),
     "gz_set_tuning": ([ctypes.c_void_p, ctypes.POINTER(gz_tuning)], ctypes.c_int32),
+    "gz_autotune": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64,
+                     ctypes.c_uint32, ctypes.c_void_p, ctypes.POINTER(gz_tuning),
+                     ctypes.POINTER(ctypes.c_float)], ctypes.c_int32),
     "gz_profile_enable": ([ctypes.c_void_p, ctypes.c_int], ctypes.c_int32),
     "gz_profile_last": ([ctypes.c_void_p, ctypes.POINTER(gz_profile)], ctypes.c_int32),
     "gz_status_str": ([ctypes.c_int32], ctypes.c_char_p),
@@ -266,6 +269,18 @@ class Graph:
         n = ctypes.c_uint64()
         check(lib().gz_sketch_storage(self._h, ctypes.byref(p), ctypes.byref(n)))
         return p.value, n.value
+
+    def autotune(self, src, dst, stream=None):
+        """Time candidate launch configurations on a device-resident sample; keep the best."""
+        ps, fs, ks = _u32_arg(src)
+        pd, fd, kd = _u32_arg(dst)
+        if not (fs & fd & GZ_DEVICE_PTR):
+            raise ValueError("autotune needs the sample in device memory")
+        best = gz_tuning()
+        ms = ctypes.c_float()
+        check(lib().gz_autotune(self._h, ps, pd, len(ks), GZ_DEVICE_PTR, _stream_handle(stream),
+                                ctypes.byref(best), ctypes.byref(ms)))
+        return best.as_dict(), float(ms.value)
 
     def profile(self, on: bool = True):
         check(lib().gz_profile_enable(self._h, int(on)))

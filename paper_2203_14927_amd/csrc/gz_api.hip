@@ -64,7 +64,7 @@ int device_cu_count() {
 gz_tuning default_tuning(uint32_t P, uint32_t B) {
     gz_tuning t{};
     t.chunk = 16384;
-    t.lds_rows = (kPlanes * B * P * 4 <= 48 * 1024) ? B : std::min<uint32_t>(B, 16u);
+    t.lds_rows = (kPlanes * B * ((P + 63) / 64 * 64) * 4 <= 48 * 1024) ? B : std::min<uint32_t>(B, 16u);
     uint32_t best = 0;
     double best_use = -1.0;
     for (uint32_t wg = 256; wg <= 512; wg += 64) {
@@ -76,7 +76,7 @@ gz_tuning default_tuning(uint32_t P, uint32_t B) {
         }
     }
     t.wg_size = best ? best : std::min<uint32_t>(1024, (P + 63) / 64 * 64);
-    const uint32_t smem = kPlanes * std::min(t.lds_rows, B) * P * 4;
+    const uint32_t smem = kPlanes * std::min(t.lds_rows, B) * ((P + 63) / 64 * 64) * 4;
     t.wgs_per_cu = std::max<uint32_t>(1, std::min<uint32_t>(8, (160 * 1024) / smem));
     return t;
 }
@@ -395,7 +395,7 @@ gz_status gz_set_tuning(gz_graph* g, const gz_tuning* t) {
     if (t->lds_rows < 1) return fail(GZ_EINVAL, "lds_rows must be >= 1");
     if (t->chunk < 1 || t->chunk > (1u << 30)) return fail(GZ_EINVAL, "chunk must be in [1, 2^30]");
     if (t->wgs_per_cu < 1 || t->wgs_per_cu > 64) return fail(GZ_EINVAL, "wgs_per_cu in [1, 64]");
-    size_t smem = (size_t)kPlanes * std::min(t->lds_rows, g->B) * g->P * 4;
+    size_t smem = (size_t)kPlanes * std::min(t->lds_rows, g->B) * ((g->P + 63) / 64 * 64) * 4;
     if (smem > 160 * 1024) return fail(GZ_EINVAL, "LDS tile exceeds 160 KiB");
     g->tuning = *t;
     return GZ_OK;

@@ -37,7 +37,7 @@ __device__ __forceinline__ uint32_t graph_of_node(const GraphDesc* __restrict__ 
     return lo;
 }
 
-constexpr uint32_t kGroupThreads = 512;
+constexpr uint32_t kGroupThreads = 1024;
 
 struct UnitRange {
     uint64_t i0, i1;    // updates [i0, i1)
@@ -84,23 +84,38 @@ __global__ __launch_bounds__(kGroupThreads) void k_group_count(
         atomicOr(&ctl[3], 1u);
     }
     __syncthreads();
-    uint32_t* out = H + g.hoff + (uint64_t)r.lo * g.nb + u.c;
-    for (uint32_t k = threadIdx.x; k < r.size; k += blockDim.x) out[(uint64_t)k * g.nb] = hist[k];
+    uint32_t* out = H + g.hoff + (uint64_t)u.c * g.V + r.lo;
+    for (uint32_t k = threadIdx.x; k < r.size; k += blockDim.x) out[k] = hist[k];
 }
 
-// node counts from the scanned table: the node's entries start at its chunk-0
-// prefix and end at the next node's
-__global__ void k_group_node_counts(const GraphDesc* __restrict__ gd, uint32_t G, uint32_t T,
-                                    const uint32_t* __restrict__ Hs, uint32_t* __restrict__ counts) {
+// The count table of a graph is chunk-major: H[hoff + c * V + v].  A node's
+// entries total the column sum over its chunks ...
+__global__ void k_group_colsum(const GraphDesc* __restrict__ gd, uint32_t G, uint32_t T,
+                               const uint32_t* __restrict__ H, uint32_t* __restrict__ counts) {
     for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < T; v += gridDim.x * blockDim.x) {
         const uint32_t gi = G == 1 ? 0u : graph_of_node(gd, G, v);
         const GraphDesc& g = gd[gi];
-        if (g.nb == 0) {
-            counts[v] = 0;
-            continue;
+        const uint32_t* col = H + g.hoff + (v - g.node_base);
+        uint32_t sum = 0;
+        for (uint32_t c = 0; c < g.nb; ++c) sum += col[(uint64_t)c * g.V];
+        counts[v] = sum;
+    }
+}
+
+// ... and, once the node's first slot is known, each chunk's run starts after
+// the runs of the earlier chunks (in-place exclusive scan down the column)
+__global__ void k_group_colscan(const GraphDesc* __restrict__ gd, uint32_t G, uint32_t T,
+                                const uint32_t* __restrict__ nodeoff, uint32_t* __restrict__ H) {
+    for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < T; v += gridDim.x * blockDim.x) {
+        const uint32_t gi = G == 1 ? 0u : graph_of_node(gd, G, v);
+        const GraphDesc& g = gd[gi];
+        uint32_t* col = H + g.hoff + (v - g.node_base);
+        uint32_t run = nodeoff[v];
+        for (uint32_t c = 0; c < g.nb; ++c) {
+            const uint32_t t = col[(uint64_t)c * g.V];
+            col[(uint64_t)c * g.V] = run;
+            run += t;
         }
-        const uint64_t at = g.hoff + (uint64_t)(v - g.node_base) * g.nb;
-        counts[v] = Hs[at + g.nb] - Hs[at];
     }
 }
 
@@ -118,8 +133,8 @@ __global__ __launch_bounds__(kGroupThreads) void k_group_scatter(
     const UnitRange r = unit_range(u, g, a->group_chunk, gend);
     const uint32_t* __restrict__ src = a->src;
     const uint32_t* __restrict__ dst = a->dst;
-    const uint32_t* hs = Hs + g.hoff + (uint64_t)r.lo * g.nb + u.c;
-    for (uint32_t k = threadIdx.x; k < r.size; k += blockDim.x) cur[k] = hs[(uint64_t)k * g.nb];
+    const uint32_t* hs = Hs + g.hoff + (uint64_t)u.c * g.V + r.lo;
+    for (uint32_t k = threadIdx.x; k < r.size; k += blockDim.x) cur[k] = hs[k];
     __syncthreads();
     for (uint64_t i = r.i0 + threadIdx.x; i < r.i1; i += blockDim.x) {
         const uint32_t x = src[i], y = dst[i];
@@ -158,52 +173,6 @@ __device__ T block_exclusive_scan(T v, T* sh, T* total) {
     *total = sh[kScanThreads - 1];
     __syncthreads();
     return incl - v;
-}
-
-// in-place exclusive scan of a u32 array (three passes)
-__global__ __launch_bounds__(kScanThreads) void k_scan32_partial(const uint32_t* __restrict__ x,
-                                                                  uint64_t n,
-                                                                  uint32_t* __restrict__ sums) {
-    __shared__ uint32_t sh[kScanThreads];
-    const uint64_t base = (uint64_t)blockIdx.x * kScanTile + threadIdx.x * kScanPerThread;
-    uint32_t s = 0;
-    for (uint32_t k = 0; k < kScanPerThread; ++k)
-        if (base + k < n) s += x[base + k];
-    uint32_t total;
-    block_exclusive_scan<uint32_t>(s, sh, &total);
-    if (threadIdx.x == 0) sums[blockIdx.x] = total;
-}
-
-__global__ __launch_bounds__(kScanThreads) void k_scan32_top(uint32_t* __restrict__ sums,
-                                                              uint32_t nblocks) {
-    __shared__ uint32_t sh[kScanThreads];
-    uint32_t carry = 0;
-    for (uint32_t b0 = 0; b0 < nblocks; b0 += kScanThreads) {
-        const uint32_t i = b0 + threadIdx.x;
-        const uint32_t v = i < nblocks ? sums[i] : 0;
-        uint32_t total;
-        const uint32_t ex = block_exclusive_scan<uint32_t>(v, sh, &total);
-        if (i < nblocks) sums[i] = carry + ex;
-        carry += total;
-    }
-}
-
-__global__ __launch_bounds__(kScanThreads) void k_scan32_final(uint32_t* __restrict__ x, uint64_t n,
-                                                                const uint32_t* __restrict__ sums) {
-    __shared__ uint32_t sh[kScanThreads];
-    const uint64_t base = (uint64_t)blockIdx.x * kScanTile + threadIdx.x * kScanPerThread;
-    uint32_t vals[kScanPerThread];
-    uint32_t s = 0;
-    for (uint32_t k = 0; k < kScanPerThread; ++k) {
-        vals[k] = base + k < n ? x[base + k] : 0;
-        s += vals[k];
-    }
-    uint32_t total;
-    uint32_t pre = block_exclusive_scan<uint32_t>(s, sh, &total) + sums[blockIdx.x];
-    for (uint32_t k = 0; k < kScanPerThread; ++k) {
-        if (base + k < n) x[base + k] = pre;
-        pre += vals[k];
-    }
 }
 
 // work items: exclusive scan of (entries | items << 40) per node, then every
@@ -247,7 +216,8 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_top(uint64_t* __restrict_
 __global__ __launch_bounds__(kScanThreads) void k_scan_items(
     const uint32_t* __restrict__ counts, uint32_t T, uint32_t chunk,
     const uint64_t* __restrict__ block_sums, WorkItem* __restrict__ items,
-    const GraphDesc* __restrict__ gd, uint32_t G, const uint32_t* __restrict__ ctl) {
+    uint32_t* __restrict__ nodeoff, const GraphDesc* __restrict__ gd, uint32_t G,
+    const uint32_t* __restrict__ ctl) {
     __shared__ uint64_t sh[kScanThreads];
     uint64_t base = (uint64_t)blockIdx.x * kScanTile + threadIdx.x * kScanPerThread;
     uint64_t vals[kScanPerThread];
@@ -262,6 +232,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_items(
     const bool skip = ctl[2] != 0;
     for (uint32_t k = 0; k < kScanPerThread; ++k) {
         uint64_t i = base + k;
+        if (i < T) nodeoff[i] = (uint32_t)(pre & kCountMask);
         if (i < T && !skip) {
             const uint32_t begin = (uint32_t)(pre & kCountMask);
             const uint32_t item0 = (uint32_t)(pre >> 40);
@@ -288,9 +259,12 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_items(
 // ------------------------------------------------------------ sketch update --
 
 // The LDS tile interleaves the three planes bucket by bucket: word
-// (d * P + p) * 3 + plane holds plane `plane` of row d of pair p, so one
+// (d * S + p) * 3 + plane holds plane `plane` of row d of pair p, so one
 // 24-bit multiply-add gives the address and the planes are immediate offsets.
-// Lanes of one wave with the same row touch banks 3p mod 64, all distinct.
+// The row stride S is P rounded up to a multiple of 64, so the bank of a lane
+// (word mod 64) is 3p + plane mod 64 whatever row its entry hashed to: the
+// lanes of a wave never collide, however their rows differ.
+__host__ __device__ __forceinline__ uint32_t tile_stride(uint32_t P) { return (P + 63u) & ~63u; }
 
 // Hash one entry for this lane's (round, column) pair and XOR it into the
 // exact-depth row of the LDS tile; rows >= DL (kAllRows == false only) go
@@ -365,7 +339,7 @@ __device__ __forceinline__ void apply_entries(const Src& ent, uint32_t count, ui
         const uint32_t p = tid - j * P;
         const PairSeeds s = load_pair_seeds(g.seeds, P, p);
         const uint32_t Bm1 = B - 1;
-        const uint32_t row_bytes = P * kPlanes * 4;
+        const uint32_t row_bytes = tile_stride(P) * kPlanes * 4;
         const uint32_t lane_bytes = p * kPlanes * 4;
         uint8_t* tb = (uint8_t*)tile;
 #define GZ_XOR(x) xor_entry<kAllRows>((x), s, Bm1, DL, row_bytes, lane_bytes, tb, skn, rowp, P, p)
@@ -385,17 +359,23 @@ __device__ __forceinline__ void apply_entries(const Src& ent, uint32_t count, ui
         // unaligned head (group 0 only) and short ranges
         while (e < e1 && ((e + mis) & 3u)) GZ_XOR(ent.one(e++));
         if (e + 8 <= e1) {
+            // two register sets in turn: while one set is hashed the other is in flight
             uint4 a = ent.quad(e), b = ent.quad(e + 4);
-            for (; e + 16 <= e1; e += 8) {
-                const uint4 na = ent.quad(e + 8), nb = ent.quad(e + 12);
+            uint4 c, d;
+            for (;;) {
+                const bool more1 = e + 16 <= e1;
+                if (more1) { c = ent.quad(e + 8); d = ent.quad(e + 12); }
                 GZ_XOR(a.x); GZ_XOR(a.y); GZ_XOR(a.z); GZ_XOR(a.w);
                 GZ_XOR(b.x); GZ_XOR(b.y); GZ_XOR(b.z); GZ_XOR(b.w);
-                a = na;
-                b = nb;
+                e += 8;
+                if (!more1) break;
+                const bool more2 = e + 16 <= e1;
+                if (more2) { a = ent.quad(e + 8); b = ent.quad(e + 12); }
+                GZ_XOR(c.x); GZ_XOR(c.y); GZ_XOR(c.z); GZ_XOR(c.w);
+                GZ_XOR(d.x); GZ_XOR(d.y); GZ_XOR(d.z); GZ_XOR(d.w);
+                e += 8;
+                if (!more2) break;
             }
-            GZ_XOR(a.x); GZ_XOR(a.y); GZ_XOR(a.z); GZ_XOR(a.w);
-            GZ_XOR(b.x); GZ_XOR(b.y); GZ_XOR(b.z); GZ_XOR(b.w);
-            e += 8;
         }
         for (; e < e1; ++e) GZ_XOR(ent.one(e));
 #undef GZ_XOR
@@ -405,7 +385,7 @@ __device__ __forceinline__ void apply_entries(const Src& ent, uint32_t count, ui
     for (uint32_t row = wave; row < kPlanes * DL; row += nw) {
         const uint32_t pl = row / DL, d = row - pl * DL;
         uint32_t* dstrow = skn + pl * rowp + (uint64_t)d * P;
-        const uint32_t* srow = tile + d * P * kPlanes + pl;
+        const uint32_t* srow = tile + d * tile_stride(P) * kPlanes + pl;
         for (uint32_t q = lane; q < P; q += 64) {
             const uint32_t val = srow[q * kPlanes];
             if (val) {
@@ -437,7 +417,8 @@ __global__ __launch_bounds__(1024) void k_update(const WorkItem* __restrict__ it
         const WorkItem w = items[it];
         const GraphDesc g = gd[w.graph];
         const uint32_t DL = kAllRows ? g.B : min(lds_rows, g.B);
-        for (uint32_t i = threadIdx.x; i < kPlanes * DL * g.P; i += blockDim.x) tile[i] = 0;
+        for (uint32_t i = threadIdx.x; i < kPlanes * DL * tile_stride(g.P); i += blockDim.x)
+            tile[i] = 0;
         __syncthreads();
         apply_entries<kAllRows>(GroupedEntries{grouped + w.begin}, w.count,
                                 w.gnode - g.node_base, g, DL, tile, w.shared != 0);
@@ -456,7 +437,7 @@ __global__ __launch_bounds__(1024) void k_update_node(const uint32_t* __restrict
     const uint32_t begin = blockIdx.x * chunk;
     const uint32_t cnt = min(chunk, count - begin);
     const uint32_t DL = min(lds_rows, g.B);
-    for (uint32_t i = threadIdx.x; i < kPlanes * DL * g.P; i += blockDim.x) tile[i] = 0;
+    for (uint32_t i = threadIdx.x; i < kPlanes * DL * tile_stride(g.P); i += blockDim.x) tile[i] = 0;
     __syncthreads();
     apply_entries<false>(NeighbourEntries{nbrs + begin, node}, cnt, node, g, DL, tile,
                          gridDim.x > 1);
@@ -529,6 +510,7 @@ gz_status ensure_scratch(IngestScratch& S, uint64_t N, uint32_t T, uint32_t G, u
     }
     if (T > S.cap_nodes || !S.counts) {
         GZ_TRY(grow(&S.counts, T, "node counts"));
+        GZ_TRY(grow(&S.cursor, T, "node offsets"));
         GZ_TRY(grow(&S.block_sums, (uint64_t)T / kScanTile + 2, "scan partials"));
         S.cap_nodes = T;
     }
@@ -544,7 +526,6 @@ gz_status ensure_scratch(IngestScratch& S, uint64_t N, uint32_t T, uint32_t G, u
     }
     if (H_size + 1 > S.cap_H || !S.H) {
         GZ_TRY(grow(&S.H, H_size + 1, "grouping table"));
-        GZ_TRY(grow(&S.H_sums, (H_size + 1) / kScanTile + 2, "grouping scan partials"));
         S.cap_H = H_size + 1;
     }
     const uint64_t entries = 2 * N;
@@ -565,7 +546,7 @@ gz_status ensure_scratch(IngestScratch& S, uint64_t N, uint32_t T, uint32_t G, u
 }
 
 size_t update_smem_bytes(uint32_t DL, uint32_t Pmax) {
-    return (size_t)kPlanes * DL * Pmax * 4;
+    return (size_t)kPlanes * DL * tile_stride(Pmax) * 4;
 }
 
 gz_status set_smem_limit(const void* fn, size_t bytes) {
@@ -574,17 +555,10 @@ gz_status set_smem_limit(const void* fn, size_t bytes) {
     return GZ_OK;
 }
 
-void scan32_inplace(uint32_t* x, uint64_t n, uint32_t* sums, hipStream_t s) {
-    const uint32_t nb = (uint32_t)((n + kScanTile - 1) / kScanTile);
-    k_scan32_partial<<<nb, kScanThreads, 0, s>>>(x, n, sums);
-    k_scan32_top<<<1, kScanThreads, 0, s>>>(sums, nb);
-    k_scan32_final<<<nb, kScanThreads, 0, s>>>(x, n, sums);
-}
-
 }  // namespace
 
 void free_ingest_scratch(IngestScratch& S) {
-    hipFree(S.H); hipFree(S.H_sums); hipFree(S.units); hipFree(S.counts);
+    hipFree(S.H); hipFree(S.units); hipFree(S.counts);
     hipFree(S.packed); hipFree(S.block_sums); hipFree(S.cursor);
     hipFree(S.grouped); hipFree(S.items); hipFree(S.ctl); hipFree(S.args); hipFree(S.offs);
     hipFree(S.descs); hipFree(S.staging);
@@ -620,10 +594,11 @@ gz_status ingest_fused(gz_graph* const* gs, uint32_t G, const uint64_t* offs_hos
     const gz_tuning tune = gs[0]->tuning;
     const uint32_t chunk = tune.chunk;
     const uint32_t wg = tune.wg_size;
-    // grouping blocks: about four per CU over the whole call, at least 8192 updates each
+    // grouping blocks: about one per CU over the whole call (at least 8192 updates
+    // each), so that every (node, block) run of the grouped array is long enough
+    // to fill whole cache lines
     const uint32_t cus = (uint32_t)device_cu_count();
-    const uint32_t group_chunk =
-        (uint32_t)std::max<uint64_t>(8192, (N + 4ull * cus - 1) / (4ull * cus));
+    const uint32_t group_chunk = (uint32_t)std::max<uint64_t>(8192, (N + cus - 1) / cus);
 
     // descriptor table, grouping plan, shapes
     std::vector<GraphDesc> descs(G);
@@ -707,21 +682,19 @@ gz_status ingest_fused(gz_graph* const* gs, uint32_t G, const uint64_t* offs_hos
     if (prof) GZ_HIP(hipEventRecord(prof->prof_ev[0], stream));
     const uint32_t Tn = (uint32_t)T;
     k_fill_u32<<<1, 64, 0, stream>>>(S.ctl, 3, 0);  // ticket, items, call error (sticky kept)
-    k_fill_u32<<<grid_for(H_size + 1, 256, 4096), 256, 0, stream>>>(S.H, H_size + 1, 0);
     const size_t gsmem = (size_t)range_max * 4;
     GZ_TRY(set_smem_limit((const void*)k_group_count, gsmem));
     GZ_TRY(set_smem_limit((const void*)k_group_scatter, gsmem));
     if (n_units)
         k_group_count<<<n_units, kGroupThreads, gsmem, stream>>>(S.args, S.units, S.descs, S.H,
                                                                  S.ctl);
-    scan32_inplace(S.H, H_size + 1, S.H_sums, stream);
-    k_group_node_counts<<<grid_for(Tn, 256, 8192), 256, 0, stream>>>(S.descs, G, Tn, S.H,
-                                                                      S.counts);
+    k_group_colsum<<<grid_for(Tn, 256, 8192), 256, 0, stream>>>(S.descs, G, Tn, S.H, S.counts);
     const uint32_t nblocks = (uint32_t)((T + kScanTile - 1) / kScanTile);
     k_scan_partial<<<nblocks, kScanThreads, 0, stream>>>(S.counts, Tn, chunk, S.block_sums);
     k_scan_top<<<1, kScanThreads, 0, stream>>>(S.block_sums, nblocks, S.ctl);
     k_scan_items<<<nblocks, kScanThreads, 0, stream>>>(S.counts, Tn, chunk, S.block_sums, S.items,
-                                                       S.descs, G, S.ctl);
+                                                       S.cursor, S.descs, G, S.ctl);
+    k_group_colscan<<<grid_for(Tn, 256, 8192), 256, 0, stream>>>(S.descs, G, Tn, S.cursor, S.H);
     if (n_units)
         k_group_scatter<<<n_units, kGroupThreads, gsmem, stream>>>(S.args, S.units, S.descs, S.H,
                                                                    S.grouped, S.ctl);

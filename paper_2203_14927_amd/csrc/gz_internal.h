@@ -84,16 +84,15 @@ struct IngestScratch {
     uint32_t cap_nodes = 0;
     uint32_t cap_graphs = 0;
     uint64_t cap_items = 0;
-    uint32_t* H = nullptr;          // (node, chunk) counts, scanned in place (H_size + 1)
+    uint32_t* H = nullptr;          // chunk-major (chunk, node) counts, then run starts
     uint64_t cap_H = 0;
-    uint32_t* H_sums = nullptr;     // scan partials of H
     GroupUnit* units = nullptr;
     GroupUnit* h_units = nullptr;   // pinned
     uint32_t cap_units = 0;
     uint32_t* counts = nullptr;     // T: entries per node (u32)
     uint64_t* packed = nullptr;     // T+1: scanned (entries | items << 40)
     uint64_t* block_sums = nullptr; // scan partials
-    uint32_t* cursor = nullptr;     // T
+    uint32_t* cursor = nullptr;     // T: first grouped slot of every node
     uint32_t* grouped = nullptr;    // 2N edge indices grouped by endpoint
     WorkItem* items = nullptr;
     uint32_t* ctl = nullptr;        // [0] ticket, [1] n_items, [2] call error, [3] sticky errors,

@@ -89,34 +89,54 @@ __global__ void k_q_select(uint32_t r, const uint32_t* __restrict__ L, uint32_t*
     }
 }
 
-// one wave per node: XOR the node's round-r rows into its component's
-// accumulator [slot][plane][d][c]
+// XOR the round-r rows of every active component's members into the
+// component's accumulator [slot][plane][d][c].  A workgroup walks a run of
+// consecutive node ids, one thread per accumulator word, keeping a running XOR
+// while the component stays the same and flushing it with one atomic per word
+// when it changes (components are large after the first round, so consecutive
+// ids mostly share one).
+constexpr uint32_t kReduceRun = 16;
+
 __global__ void k_q_reduce(uint32_t r, uint32_t T, const uint32_t* __restrict__ comp,
                            const uint32_t* __restrict__ slot, const uint32_t* __restrict__ gof,
                            const GraphDesc* __restrict__ gd, uint32_t wpr,
                            uint32_t* __restrict__ acc) {
-    const uint32_t waves = (gridDim.x * blockDim.x) >> 6;
-    const uint32_t lane = threadIdx.x & 63;
-    for (uint32_t v = (blockIdx.x * blockDim.x + threadIdx.x) >> 6; v < T; v += waves) {
+    __shared__ uint32_t s_slot[kReduceRun];
+    __shared__ const uint32_t* s_base[kReduceRun];
+    __shared__ uint32_t s_words[kReduceRun], s_P[kReduceRun];
+    const uint32_t v0 = blockIdx.x * kReduceRun;
+    const uint32_t n = min(T - v0, kReduceRun);
+    if (threadIdx.x < n) {
+        const uint32_t v = v0 + threadIdx.x;
         const uint32_t sl = slot[comp[v]];
-        if (sl == kNone) continue;
-        const GraphDesc g = gd[gof[v]];
-        const uint32_t local = v - g.node_base;
-        const uint32_t words = kPlanes * g.B * kC;
-        const uint32_t* base = g.sk + (uint64_t)local * kPlanes * g.B * g.P + r * kC;
-        uint32_t* out = acc + (uint64_t)sl * wpr;
-        for (uint32_t w = lane; w < words; w += 64) {
-            const uint32_t c = w & (kC - 1);
-            const uint32_t row = w >> 3;  // plane * B + d
-            const uint32_t val = base[(uint64_t)row * g.P + c];
-            if (val) atomicXor(&out[w], val);
+        s_slot[threadIdx.x] = sl;
+        const GraphDesc& g = gd[gof[v]];
+        s_base[threadIdx.x] = g.sk + (uint64_t)(v - g.node_base) * kPlanes * g.B * g.P + r * kC;
+        s_words[threadIdx.x] = kPlanes * g.B * kC;
+        s_P[threadIdx.x] = g.P;
+    }
+    __syncthreads();
+    for (uint32_t w0 = 0; w0 < wpr; w0 += blockDim.x) {
+        const uint32_t w = w0 + threadIdx.x;
+        const uint32_t row = w >> 3;  // plane * B + d
+        const uint32_t c = w & (kC - 1);
+        uint32_t run = 0, run_slot = kNone;
+        for (uint32_t i = 0; i < n; ++i) {
+            const uint32_t sl = s_slot[i];
+            if (sl != run_slot) {
+                if (run_slot != kNone && run) atomicXor(&acc[(uint64_t)run_slot * wpr + w], run);
+                run = 0;
+                run_slot = sl;
+            }
+            if (sl != kNone && w < s_words[i]) run ^= s_base[i][(uint64_t)row * s_P[i] + c];
         }
+        if (run_slot != kNone && run) atomicXor(&acc[(uint64_t)run_slot * wpr + w], run);
     }
 }
 
-// 8 lanes per component (one per column): walk rows from deepest to row 0,
-// accumulating the nested bucket (suffix XOR of the exact-depth rows), and
-// keep the shallowest GOOD row; then the first column with a GOOD row wins.
+// kDirect: every component is a single node (first round), read its sketch
+// rows in place instead of an accumulator
+template <bool kDirect>
 __global__ void k_q_query(uint32_t r, const uint32_t* __restrict__ A, const uint32_t* __restrict__ ctl,
                           const uint32_t* __restrict__ acc, uint32_t wpr,
                           const uint32_t* __restrict__ gof, const GraphDesc* __restrict__ gd,
@@ -133,13 +153,22 @@ __global__ void k_q_query(uint32_t r, const uint32_t* __restrict__ A, const uint
         const GraphDesc g = gd[gof[X]];
         const uint32_t p = r * kC + c;
         const PairSeeds s = load_pair_seeds(g.seeds, g.P, p);
-        const uint32_t* in = acc + (uint64_t)a * wpr;
         const uint32_t B = g.B;
+        // word (plane, row b) of column c: stride between rows of one plane
+        const uint32_t* in;
+        uint64_t rs;
+        if (kDirect) {
+            in = g.sk + (uint64_t)(X - g.node_base) * kPlanes * B * g.P + p;
+            rs = g.P;
+        } else {
+            in = acc + (uint64_t)a * wpr + c;
+            rs = kC;
+        }
         uint32_t al = 0, glo = 0, ghi = 0;
         for (int b = (int)B - 1; b >= 0; --b) {
-            al ^= in[(0 * B + b) * kC + c];
-            glo ^= in[(1 * B + b) * kC + c];
-            ghi ^= in[(2 * B + b) * kC + c];
+            al ^= in[(uint64_t)(0 * B + b) * rs];
+            glo ^= in[(uint64_t)(1 * B + b) * rs];
+            ghi ^= in[(uint64_t)(2 * B + b) * rs];
             if (al | glo | ghi) {
                 nonempty = 1;
                 if ((uint64_t)al < g.n && chk_lo(s, al) == glo && chk_hi(s, al) == ghi) {
@@ -484,12 +513,19 @@ gz_status boruvka(gz_graph* const* gs, uint32_t G, bool want_forest, QueryResult
         GZ_HIP(hipStreamSynchronize(qs));
         if (nA == 0) break;
         rounds = r + 1;
-        GZ_HIP(hipMemsetAsync(Q->acc, 0, (size_t)nA * wpr * 4, qs));
-        const uint32_t rgrid = (uint32_t)std::min<uint64_t>((T64 * 64 + 255) / 256, 65535);
-        k_q_reduce<<<rgrid, 256, 0, qs>>>(r, T, Q->comp, Q->slot, Q->gof, Q->descs, wpr, Q->acc);
-        k_q_query<<<(nA * 8 + 255) / 256, 256, 0, qs>>>(r, Q->A, Q->ctl, Q->acc, wpr, Q->gof,
-                                                         Q->descs, Q->comp, Q->hook, Q->hedge,
-                                                         Q->done);
+        if (r == 0) {
+            k_q_query<true><<<(nA * 8 + 255) / 256, 256, 0, qs>>>(
+                r, Q->A, Q->ctl, Q->acc, wpr, Q->gof, Q->descs, Q->comp, Q->hook, Q->hedge,
+                Q->done);
+        } else {
+            GZ_HIP(hipMemsetAsync(Q->acc, 0, (size_t)nA * wpr * 4, qs));
+            const uint32_t rgrid = (T + kReduceRun - 1) / kReduceRun;
+            k_q_reduce<<<rgrid, 256, 0, qs>>>(r, T, Q->comp, Q->slot, Q->gof, Q->descs, wpr,
+                                              Q->acc);
+            k_q_query<false><<<(nA * 8 + 255) / 256, 256, 0, qs>>>(
+                r, Q->A, Q->ctl, Q->acc, wpr, Q->gof, Q->descs, Q->comp, Q->hook, Q->hedge,
+                Q->done);
+        }
         k_q_double_init<<<tb, 256, 0, qs>>>(L, Q->ctl, Q->hook, s, m);
         for (uint32_t k = 0; k < K; ++k) {
             k_q_double<<<tb, 256, 0, qs>>>(L, Q->ctl, s, m, s2, m2);

@@ -91,6 +91,7 @@ typedef struct gz_tuning {
     uint32_t lds_rows;    /* rows kept in the LDS tile (1..B); deeper rows go to HBM atomics */
     uint32_t chunk;       /* max updates of one node per work item (gutter split threshold) */
     uint32_t wgs_per_cu;  /* persistent grid = wgs_per_cu * CUs */
+    uint32_t group_blocks;/* workgroups of the grouping passes per call (0 = one per CU) */
 } gz_tuning;
 
 /* ------------------------------------------------------------------------

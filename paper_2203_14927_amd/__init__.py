@@ -38,7 +38,8 @@ class gz_config(ctypes.Structure):
 
 class gz_tuning(ctypes.Structure):
     _fields_ = [("wg_size", ctypes.c_uint32), ("lds_rows", ctypes.c_uint32),
-                ("chunk", ctypes.c_uint32), ("wgs_per_cu", ctypes.c_uint32)]
+                ("chunk", ctypes.c_uint32), ("wgs_per_cu", ctypes.c_uint32),
+                ("group_blocks", ctypes.c_uint32)]
 
     def as_dict(self):
         return {f: int(getattr(self, f)) for f, _ in self._fields_}

@@ -78,6 +78,7 @@ gz_tuning default_tuning(uint32_t P, uint32_t B) {
     t.wg_size = best ? best : std::min<uint32_t>(1024, (P + 63) / 64 * 64);
     const uint32_t smem = kPlanes * std::min(t.lds_rows, B) * ((P + 63) / 64 * 64) * 4;
     t.wgs_per_cu = std::max<uint32_t>(1, std::min<uint32_t>(8, (160 * 1024) / smem));
+    t.group_blocks = 0;
     return t;
 }
 

@@ -50,7 +50,7 @@ std::vector<gz_tuning> candidates(uint32_t P, uint32_t B) {
             std::vector<uint32_t> wpc = {wmax};
             if (wmax > 1) wpc.push_back((wmax + 1) / 2);
             for (uint32_t c : chunks)
-                for (uint32_t w : wpc) out.push_back(gz_tuning{wg, dl, c, w});
+                for (uint32_t w : wpc) out.push_back(gz_tuning{wg, dl, c, w, 0});
         }
     return out;
 }
@@ -91,6 +91,34 @@ extern "C" gz_status gz_autotune(gz_graph* g, const uint32_t* src, const uint32_
     const Cand* w = &res[0];
     for (const Cand& c : res)
         if (c.ms < w->ms) w = &c;
+    // second stage: the grouping block count, with the best kernel parameters fixed
+    Cand bestc = *w;
+    if (!st) {
+        st = gz_sketch_init(&t, g->V, g->seed, &cfg);
+        if (!st) st = gz_profile_enable(t, 1);
+        const uint32_t gb_list[] = {32u, 64u, 128u, 256u, 512u};
+        for (uint32_t gb : gb_list) {
+            if (st) break;
+            gz_tuning c = w->t;
+            c.group_blocks = gb;
+            if (gz_set_tuning(t, &c) != GZ_OK) continue;
+            float bc = 1e30f;
+            for (int rep = 0; rep < 2 && !st; ++rep) {
+                gz_profile pr{};
+                st = gz_ingest(t, src, dst, N, GZ_DEVICE_PTR | GZ_ASYNC, stream);
+                if (!st) st = gz_profile_last(t, &pr);
+                if (!st) bc = std::min(bc, pr.ingest_ms);
+            }
+            if (!st && bc < bestc.ms) bestc = Cand{c, bc};
+        }
+        if (t) {
+            gz_status f2 = gz_flush(t);
+            gz_free(t);
+            if (!st) st = f2;
+        }
+        if (st) return st;
+    }
+    w = &bestc;
     g->tuning = w->t;
     if (best) *best = w->t;
     if (best_ms) *best_ms = w->ms;

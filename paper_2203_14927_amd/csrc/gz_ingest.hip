@@ -598,7 +598,8 @@ gz_status ingest_fused(gz_graph* const* gs, uint32_t G, const uint64_t* offs_hos
     // each), so that every (node, block) run of the grouped array is long enough
     // to fill whole cache lines
     const uint32_t cus = (uint32_t)device_cu_count();
-    const uint32_t group_chunk = (uint32_t)std::max<uint64_t>(8192, (N + cus - 1) / cus);
+    const uint32_t gblocks = tune.group_blocks ? tune.group_blocks : cus;
+    const uint32_t group_chunk = (uint32_t)std::max<uint64_t>(8192, (N + gblocks - 1) / gblocks);
 
     // descriptor table, grouping plan, shapes
     std::vector<GraphDesc> descs(G);

@@ -161,6 +161,28 @@ gz_status gz_ingest_multi(gz_graph* const* gs, uint32_t G, const uint64_t* offs,
                           hipStream_t stream);
 
 /* ------------------------------------------------------------------------
+ * Captured ingest plans: the fused launch sequence of gz_ingest_multi over a
+ *   fixed set of graphs, recorded once into a HIP graph and replayed per call.
+ *   Every per-call value (inputs, offsets, N) is read by the kernels from
+ *   device memory, so one plan serves any call within its capacities.
+ * gz_plan_create -- gs: G distinct graphs; caps[k]: the most updates graph k
+ *   may receive in one call (sum < 2^31).  Allocates the plan's scratch;
+ *   `stream` is used for the one-time uploads.  The graphs must outlive it.
+ * gz_plan_ingest -- one call: offs (host, G+1 entries, offs[0] = 0,
+ *   non-decreasing, offs[k+1]-offs[k] <= caps[k]); src/dst device arrays
+ *   (flags must hold GZ_DEVICE_PTR; GZ_ASYNC as for gz_ingest).  Same result as
+ *   gz_ingest_multi on the same arguments.  GZ_EINVAL on an invalid update
+ *   (nothing applied) or an offset table outside the capacities.
+ * gz_plan_free -- waits for the plan's work and releases it.
+ * ---------------------------------------------------------------------- */
+typedef struct gz_plan gz_plan;
+gz_status gz_plan_create(gz_graph* const* gs, uint32_t G, const uint64_t* caps, hipStream_t stream,
+                         gz_plan** out);
+gz_status gz_plan_ingest(gz_plan* p, const uint64_t* offs, const uint32_t* src, const uint32_t* dst,
+                         uint32_t flags, hipStream_t stream);
+gz_status gz_plan_free(gz_plan* p);
+
+/* ------------------------------------------------------------------------
  * gz_flush -- the paper's cleanup() step (Sec. 5.2): wait until every update
  *   submitted to g has been applied.  Returns GZ_EINVAL if an asynchronous
  *   call on g carried an invalid update since the last flush.
@@ -252,6 +274,54 @@ typedef struct gz_profile {
 } gz_profile;
 gz_status gz_profile_enable(gz_graph* g, int on);
 gz_status gz_profile_last(gz_graph* g, gz_profile* out);
+
+/* ------------------------------------------------------------------------
+ * Serving: many graph sessions on one GPU.
+ *   A server thread admits sessions while the device bytes of their sketches
+ *   (plus query scratch) fit `hbm_budget`; a session opened beyond the budget
+ *   waits, with its requests queued, until closed sessions free memory.  Each
+ *   tick packs the update batches queued by every admitted session (up to
+ *   `tick_updates` updates, 0 = 16 Mi) into one fused multi-graph ingest
+ *   (continuous batching: batches submitted while a tick runs join the next);
+ *   a query runs once every update submitted before it in its session has been
+ *   issued, on that session's stream, overlapping the next tick's ingest.
+ *   A session's requests take effect in submission order, so every result is
+ *   the one the session would get alone.  All calls are thread-safe.
+ * gz_submit_updates copies the host arrays (validated: GZ_EINVAL applies
+ *   nothing); gz_submit_query writes V labels into `labels` (host, nullable)
+ *   before its ticket completes.  gz_wait blocks until the ticket completes,
+ *   fills *res (nullable) and releases the ticket; it returns the request's
+ *   status (a query whose sketches ran out of rounds reports GZ_ESKETCH_FAIL in
+ *   res->status only).  Timestamps are steady-clock nanoseconds: submit, start
+ *   of processing, completion.
+ * gz_session_close waits for the session's requests and frees its sketches;
+ *   gz_server_destroy stops the server and frees every session.
+ * ---------------------------------------------------------------------- */
+typedef struct gz_server gz_server;
+typedef struct gz_session gz_session;
+typedef struct gz_ticket gz_ticket;
+typedef struct gz_result {
+    int32_t status;
+    uint32_t num_cc;      /* queries: number of components */
+    uint32_t kind;        /* 0 = update batch, 1 = query */
+    uint32_t reserved;
+    uint64_t updates;     /* update batches: number of updates */
+    uint64_t submit_ns, start_ns, done_ns;
+} gz_result;
+typedef struct gz_server_stats {
+    uint64_t ticks, updates, queries;
+    uint64_t sessions_admitted, sessions_active, sessions_waiting;
+    uint64_t hbm_used, hbm_budget;
+} gz_server_stats;
+gz_status gz_server_create(uint64_t hbm_budget, uint64_t tick_updates, gz_server** out);
+gz_status gz_session_open(gz_server* srv, uint32_t V, uint64_t seed, gz_session** out);
+gz_status gz_submit_updates(gz_session* s, const uint32_t* src, const uint32_t* dst, uint64_t N,
+                            gz_ticket** out);
+gz_status gz_submit_query(gz_session* s, uint32_t* labels, gz_ticket** out);
+gz_status gz_wait(gz_ticket* t, gz_result* res);
+gz_status gz_session_close(gz_session* s);
+gz_status gz_server_get_stats(gz_server* srv, gz_server_stats* out);
+gz_status gz_server_destroy(gz_server* srv);
 
 /* Human-readable name of a status code, and the last error message of this thread. */
 const char* gz_status_str(gz_status s);

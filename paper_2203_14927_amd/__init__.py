@@ -90,6 +90,12 @@ _SIGS = {
                      ctypes.POINTER(ctypes.c_float)], ctypes.c_int32),
     "gz_profile_enable": ([ctypes.c_void_p, ctypes.c_int], ctypes.c_int32),
     "gz_profile_last": ([ctypes.c_void_p, ctypes.POINTER(gz_profile)], ctypes.c_int32),
+    "gz_plan_create": ([ctypes.POINTER(ctypes.c_void_p), ctypes.c_uint32,
+                        ctypes.POINTER(ctypes.c_uint64), ctypes.c_void_p,
+                        ctypes.POINTER(ctypes.c_void_p)], ctypes.c_int32),
+    "gz_plan_ingest": ([ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint64), ctypes.c_void_p,
+                        ctypes.c_void_p, ctypes.c_uint32, ctypes.c_void_p], ctypes.c_int32),
+    "gz_plan_free": ([ctypes.c_void_p], ctypes.c_int32),
     "gz_status_str": ([ctypes.c_int32], ctypes.c_char_p),
     "gz_last_error": ([], ctypes.c_char_p),
 }
@@ -342,3 +348,39 @@ def connected_components_multi(graphs):
         out.append(labels[o:o + g.V])
         o += g.V
     return out, ncc, stt
+
+
+class Plan:
+    """A captured (HIP graph) ingest sequence over a fixed set of graphs."""
+
+    def __init__(self, graphs, caps, stream=None):
+        self.graphs = list(graphs)  # keep the graphs alive
+        c = np.ascontiguousarray(caps, np.uint64)
+        if len(c) != len(self.graphs):
+            raise ValueError("one capacity per graph")
+        h = ctypes.c_void_p()
+        check(lib().gz_plan_create(_handles(self.graphs), len(self.graphs),
+                                   c.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
+                                   _stream_handle(stream), ctypes.byref(h)))
+        self._h = h
+
+    def ingest(self, offs, src, dst, flags: int = 0, stream=None):
+        ps, fs, ks = _u32_arg(src)
+        pd, fd, kd = _u32_arg(dst)
+        if not (fs & fd & GZ_DEVICE_PTR):
+            raise ValueError("plans take device arrays")
+        o = np.ascontiguousarray(offs, np.uint64)
+        return check(lib().gz_plan_ingest(self._h, o.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
+                                          ps, pd, GZ_DEVICE_PTR | flags, _stream_handle(stream)))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().gz_plan_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+

@@ -44,11 +44,22 @@ struct UnitRange {
     uint32_t lo, size;  // local node range [lo, lo + size)
 };
 
-__device__ __forceinline__ UnitRange unit_range(const GroupUnit& u, const GraphDesc& g,
-                                                uint32_t group_chunk, uint64_t graph_end) {
+// Updates of graph g: from the per-call offset table when the launch has one
+// (captured plans), else from the descriptor table.
+__device__ __forceinline__ UnitRange unit_range(const IngestArgs* __restrict__ a,
+                                                const GraphDesc* __restrict__ gd,
+                                                const GroupUnit& u, const GraphDesc& g) {
+    uint64_t b, e;
+    if (a->offs) {
+        b = a->offs[u.g];
+        e = a->offs[u.g + 1];
+    } else {
+        b = g.upd_base;
+        e = u.g + 1 < a->G ? gd[u.g + 1].upd_base : a->N;
+    }
     UnitRange r;
-    r.i0 = g.upd_base + (uint64_t)u.c * group_chunk;
-    r.i1 = min(graph_end, r.i0 + group_chunk);
+    r.i0 = b + (uint64_t)u.c * a->group_chunk;
+    r.i1 = min(e, r.i0 + a->group_chunk);  // below i0 for chunks past the graph's end
     r.lo = u.q * kGroupRange;
     r.size = min(g.V - r.lo, kGroupRange);
     return r;
@@ -62,8 +73,7 @@ __global__ __launch_bounds__(kGroupThreads) void k_group_count(
     extern __shared__ uint32_t hist[];
     const GroupUnit u = units[blockIdx.x];
     const GraphDesc g = gd[u.g];
-    const uint64_t gend = u.g + 1 < a->G ? gd[u.g + 1].upd_base : a->N;
-    const UnitRange r = unit_range(u, g, a->group_chunk, gend);
+    const UnitRange r = unit_range(a, gd, u, g);
     const uint32_t* __restrict__ src = a->src;
     const uint32_t* __restrict__ dst = a->dst;
     for (uint32_t k = threadIdx.x; k < r.size; k += blockDim.x) hist[k] = 0;
@@ -129,8 +139,7 @@ __global__ __launch_bounds__(kGroupThreads) void k_group_scatter(
     if (ctl[2]) return;
     const GroupUnit u = units[blockIdx.x];
     const GraphDesc g = gd[u.g];
-    const uint64_t gend = u.g + 1 < a->G ? gd[u.g + 1].upd_base : a->N;
-    const UnitRange r = unit_range(u, g, a->group_chunk, gend);
+    const UnitRange r = unit_range(a, gd, u, g);
     const uint32_t* __restrict__ src = a->src;
     const uint32_t* __restrict__ dst = a->dst;
     const uint32_t* hs = Hs + g.hoff + (uint64_t)u.c * g.V + r.lo;
@@ -462,7 +471,11 @@ namespace {
 
 template <typename T>
 gz_status grow(T** p, uint64_t need, const char* what) {
-    if (*p) GZ_HIP(hipFree(*p));
+    if (*p) {
+        // kernels of earlier calls may still read the old buffer
+        GZ_HIP(hipDeviceSynchronize());
+        GZ_HIP(hipFree(*p));
+    }
     *p = nullptr;
     hipError_t e = hipMalloc((void**)p, std::max<uint64_t>(need, 1) * sizeof(T));
     if (e != hipSuccess) {
@@ -474,7 +487,10 @@ gz_status grow(T** p, uint64_t need, const char* what) {
 
 template <typename T>
 gz_status grow_host(T** p, uint64_t need) {
-    if (*p) GZ_HIP(hipHostFree(*p));
+    if (*p) {
+        GZ_HIP(hipDeviceSynchronize());
+        GZ_HIP(hipHostFree(*p));
+    }
     *p = nullptr;
     GZ_HIP(hipHostMalloc((void**)p, std::max<uint64_t>(need, 1) * sizeof(T), hipHostMallocDefault));
     return GZ_OK;
@@ -578,41 +594,40 @@ IngestScratch& shared_ingest_scratch(int device, std::unique_lock<std::mutex>& l
     return per_dev[(size_t)device % per_dev.size()];
 }
 
-gz_status ingest_fused(gz_graph* const* gs, uint32_t G, const uint64_t* offs_host,
-                       const uint32_t* src, const uint32_t* dst, uint64_t N, uint32_t flags,
-                       hipStream_t stream, IngestScratch& S) {
-    if (G == 0) return fail(GZ_EINVAL, "no graphs");
-    if (N >= (1ull << 31)) return fail(GZ_EINVAL, "at most 2^31-1 updates per call");
-    if (N && (!src || !dst)) return fail(GZ_EINVAL, "null stream arrays");
-    if (offs_host) {
-        if (offs_host[0] != 0 || offs_host[G] != N)
-            return fail(GZ_EINVAL, "update offsets must start at 0 and end at N");
-        for (uint32_t k = 0; k < G; ++k)
-            if (offs_host[k + 1] < offs_host[k])
-                return fail(GZ_EINVAL, "update offsets must be non-decreasing");
-    }
+// Static shape of a fused launch sequence: descriptor table, grouping units
+// and launch parameters.  `ranges` gives each graph's update range [b, e) (the
+// actual call, or the capacities of a captured plan).
+struct LaunchShape {
+    uint32_t G = 0, T = 0, n_units = 0, nblocks = 0, range_max = 1, pgrid = 0;
+    uint32_t wg = 0, DLmax = 1, Pmax = 0, chunk = 0, lds_rows = 0, group_chunk = 0;
+    uint64_t H_size = 0, N = 0;
+    bool all_rows = true;
+    size_t gsmem = 0, smem = 0;
+    std::vector<GraphDesc> descs;
+    std::vector<GroupUnit> units;
+};
+
+gz_status build_shape(gz_graph* const* gs, uint32_t G, const uint64_t* ranges, uint64_t N,
+                      LaunchShape& L) {
     const gz_tuning tune = gs[0]->tuning;
-    const uint32_t chunk = tune.chunk;
-    const uint32_t wg = tune.wg_size;
+    L = LaunchShape{};
+    L.G = G;
+    L.N = N;
+    L.chunk = tune.chunk;
+    L.lds_rows = tune.lds_rows;
+    L.wg = tune.wg_size;
     // grouping blocks: about one per CU over the whole call (at least 8192 updates
-    // each), so that every (node, block) run of the grouped array is long enough
-    // to fill whole cache lines
+    // each) unless tuned otherwise
     const uint32_t cus = (uint32_t)device_cu_count();
     const uint32_t gblocks = tune.group_blocks ? tune.group_blocks : cus;
-    const uint32_t group_chunk = (uint32_t)std::max<uint64_t>(8192, (N + gblocks - 1) / gblocks);
-
-    // descriptor table, grouping plan, shapes
-    std::vector<GraphDesc> descs(G);
-    std::vector<GroupUnit> units;
-    uint64_t T = 0, H_size = 0;
-    uint32_t Pmax = 0, DLmax = 1, range_max = 1;
-    bool all_rows = true;
+    L.group_chunk = (uint32_t)std::max<uint64_t>(8192, (N + gblocks - 1) / gblocks);
+    L.descs.resize(G);
+    uint64_t T = 0;
     for (uint32_t k = 0; k < G; ++k) {
         const gz_graph* g = gs[k];
         if (!g) return fail(GZ_EINVAL, "null graph handle");
-        const uint64_t b = offs_host ? offs_host[k] : 0;
-        const uint64_t e = offs_host ? offs_host[k + 1] : N;
-        GraphDesc& d = descs[k];
+        const uint64_t b = ranges[k], e = ranges[k + 1];
+        GraphDesc& d = L.descs[k];
         d = GraphDesc{};
         d.sk = g->sk;
         d.seeds = g->seeds;
@@ -623,24 +638,141 @@ gz_status ingest_fused(gz_graph* const* gs, uint32_t G, const uint64_t* offs_hos
         d.P = g->P;
         d.node_base = (uint32_t)T;
         d.upd_base = b;
-        d.nb = (uint32_t)((e - b + group_chunk - 1) / group_chunk);
-        d.hoff = H_size;
+        d.nb = (uint32_t)((e - b + L.group_chunk - 1) / L.group_chunk);
+        d.hoff = L.H_size;
         const uint32_t nq = (g->V + kGroupRange - 1) / kGroupRange;
         for (uint32_t c = 0; c < d.nb; ++c)
-            for (uint32_t q = 0; q < nq; ++q) units.push_back(GroupUnit{k, c, q, 0});
-        H_size += (uint64_t)g->V * d.nb;
+            for (uint32_t q = 0; q < nq; ++q) L.units.push_back(GroupUnit{k, c, q, 0});
+        L.H_size += (uint64_t)g->V * d.nb;
         T += g->V;
-        Pmax = std::max(Pmax, g->P);
-        DLmax = std::max(DLmax, std::min(tune.lds_rows, g->B));
-        all_rows = all_rows && tune.lds_rows >= g->B;
-        range_max = std::max(range_max, std::min(g->V, kGroupRange));
+        L.Pmax = std::max(L.Pmax, g->P);
+        L.DLmax = std::max(L.DLmax, std::min(tune.lds_rows, g->B));
+        L.all_rows = L.all_rows && tune.lds_rows >= g->B;
+        L.range_max = std::max(L.range_max, std::min(g->V, kGroupRange));
     }
     if (T >= (1ull << 32)) return fail(GZ_EINVAL, "too many nodes in one call");
-    if (H_size >= (1ull << 32)) return fail(GZ_EINVAL, "call too large: split the stream");
-    if (wg < Pmax || wg % 64 || wg > 1024) return fail(GZ_EINVAL, "workgroup smaller than pairs");
+    if (L.H_size >= (1ull << 32)) return fail(GZ_EINVAL, "call too large: split the stream");
+    if (L.wg < L.Pmax || L.wg % 64 || L.wg > 1024)
+        return fail(GZ_EINVAL, "workgroup smaller than pairs");
+    L.T = (uint32_t)T;
+    L.n_units = (uint32_t)L.units.size();
+    L.nblocks = (uint32_t)((T + kScanTile - 1) / kScanTile);
+    L.gsmem = (size_t)L.range_max * 4;
+    L.smem = update_smem_bytes(L.DLmax, L.Pmax);
+    L.pgrid = std::max(1u, tune.wgs_per_cu) * cus;
+    GZ_TRY(set_smem_limit((const void*)k_group_count, L.gsmem));
+    GZ_TRY(set_smem_limit((const void*)k_group_scatter, L.gsmem));
+    GZ_TRY(set_smem_limit(L.all_rows ? (const void*)k_update<true> : (const void*)k_update<false>,
+                          L.smem));
+    return GZ_OK;
+}
+
+// upload the shape's static tables (descriptors, grouping units)
+gz_status upload_shape(IngestScratch& S, const LaunchShape& L, hipStream_t stream) {
+    std::memcpy(S.h_descs, L.descs.data(), sizeof(GraphDesc) * L.G);
+    if (L.n_units) std::memcpy(S.h_units, L.units.data(), sizeof(GroupUnit) * L.n_units);
+    GZ_HIP(hipMemcpyAsync(S.descs, S.h_descs, sizeof(GraphDesc) * L.G, hipMemcpyHostToDevice,
+                          stream));
+    if (L.n_units)
+        GZ_HIP(hipMemcpyAsync(S.units, S.h_units, sizeof(GroupUnit) * L.n_units,
+                              hipMemcpyHostToDevice, stream));
+    return GZ_OK;
+}
+
+// The device-side sequence of one fused ingest: every argument it reads per
+// call (inputs, N, offsets) comes from S.args, so the sequence can be captured
+// once and replayed.  The profiling events mark the start of grouping and the
+// start and end of the sketch update when `prof` is given.
+gz_status launch_sequence(IngestScratch& S, const LaunchShape& L, hipStream_t stream,
+                          gz_graph* prof) {
+    const uint32_t Tn = L.T;
+    if (prof) GZ_HIP(hipEventRecord(prof->prof_ev[0], stream));
+    k_fill_u32<<<1, 64, 0, stream>>>(S.ctl, 3, 0);  // ticket, items, call error (sticky kept)
+    if (L.n_units)
+        k_group_count<<<L.n_units, kGroupThreads, L.gsmem, stream>>>(S.args, S.units, S.descs,
+                                                                     S.H, S.ctl);
+    k_group_colsum<<<grid_for(Tn, 256, 8192), 256, 0, stream>>>(S.descs, L.G, Tn, S.H, S.counts);
+    k_scan_partial<<<L.nblocks, kScanThreads, 0, stream>>>(S.counts, Tn, L.chunk, S.block_sums);
+    k_scan_top<<<1, kScanThreads, 0, stream>>>(S.block_sums, L.nblocks, S.ctl);
+    k_scan_items<<<L.nblocks, kScanThreads, 0, stream>>>(S.counts, Tn, L.chunk, S.block_sums,
+                                                         S.items, S.cursor, S.descs, L.G, S.ctl);
+    k_group_colscan<<<grid_for(Tn, 256, 8192), 256, 0, stream>>>(S.descs, L.G, Tn, S.cursor,
+                                                                  S.H);
+    if (L.n_units)
+        k_group_scatter<<<L.n_units, kGroupThreads, L.gsmem, stream>>>(S.args, S.units, S.descs,
+                                                                       S.H, S.grouped, S.ctl);
+    if (prof) GZ_HIP(hipEventRecord(prof->prof_ev[1], stream));
+    if (L.all_rows)
+        k_update<true><<<L.pgrid, L.wg, L.smem, stream>>>(S.items, S.ctl, S.grouped, S.descs,
+                                                          L.lds_rows);
+    else
+        k_update<false><<<L.pgrid, L.wg, L.smem, stream>>>(S.items, S.ctl, S.grouped, S.descs,
+                                                           L.lds_rows);
+    GZ_HIP(hipGetLastError());
+    if (prof) {
+        GZ_HIP(hipEventRecord(prof->prof_ev[2], stream));
+        prof->prof_calls++;
+    }
+    return GZ_OK;
+}
+
+// per-call arguments through the pinned buffer, reused once the previous
+// call's uploads have left it
+gz_status upload_args(IngestScratch& S, const LaunchShape& L, const uint32_t* src,
+                      const uint32_t* dst, uint64_t N, const uint64_t* offs_dev,
+                      hipStream_t stream) {
+    GZ_HIP(hipEventSynchronize(S.copied_ev));
+    IngestArgs& a = *S.h_args;
+    a = IngestArgs{};
+    a.src = src;
+    a.dst = dst;
+    a.offs = offs_dev;
+    a.N = N;
+    a.G = L.G;
+    a.T = L.T;
+    a.chunk = L.chunk;
+    a.lds_rows = L.lds_rows;
+    a.group_chunk = L.group_chunk;
+    a.n_units = L.n_units;
+    a.H_size = L.H_size;
+    GZ_HIP(hipMemcpyAsync(S.args, S.h_args, sizeof(IngestArgs), hipMemcpyHostToDevice, stream));
+    return GZ_OK;
+}
+
+gz_status check_call_error(IngestScratch& S, hipStream_t stream) {
+    GZ_HIP(hipMemcpyAsync(S.h_err, S.ctl + 2, 4, hipMemcpyDeviceToHost, stream));
+    GZ_HIP(hipStreamSynchronize(stream));
+    if (S.h_err[0]) {
+        // the sticky flag is for asynchronous callers; this one is reported now
+        k_fill_u32<<<1, 64, 0, stream>>>(S.ctl + 3, 1, 0);
+        GZ_HIP(hipStreamSynchronize(stream));
+        return fail(GZ_EINVAL, "invalid update (self-loop or node id out of range)");
+    }
+    return GZ_OK;
+}
+
+gz_status ingest_fused(gz_graph* const* gs, uint32_t G, const uint64_t* offs_host,
+                       const uint32_t* src, const uint32_t* dst, uint64_t N, uint32_t flags,
+                       hipStream_t stream, IngestScratch& S) {
+    if (G == 0) return fail(GZ_EINVAL, "no graphs");
+    if (N >= (1ull << 31)) return fail(GZ_EINVAL, "at most 2^31-1 updates per call");
+    if (N && (!src || !dst)) return fail(GZ_EINVAL, "null stream arrays");
+    std::vector<uint64_t> ranges(G + 1, 0);
+    if (offs_host) {
+        if (offs_host[0] != 0 || offs_host[G] != N)
+            return fail(GZ_EINVAL, "update offsets must start at 0 and end at N");
+        for (uint32_t k = 0; k < G; ++k)
+            if (offs_host[k + 1] < offs_host[k])
+                return fail(GZ_EINVAL, "update offsets must be non-decreasing");
+        std::memcpy(ranges.data(), offs_host, sizeof(uint64_t) * (G + 1));
+    } else {
+        ranges[G] = N;
+        for (uint32_t k = 1; k < G; ++k) ranges[k] = N;
+    }
+    LaunchShape L;
+    GZ_TRY(build_shape(gs, G, ranges.data(), N, L));
     const bool host_ptr = !(flags & GZ_DEVICE_PTR);
-    const uint32_t n_units = (uint32_t)units.size();
-    GZ_TRY(ensure_scratch(S, N, (uint32_t)T, G, chunk, H_size, n_units, host_ptr));
+    GZ_TRY(ensure_scratch(S, N, L.T, G, L.chunk, L.H_size, L.n_units, host_ptr));
 
     // order after earlier work on these graphs (e.g. a query on another stream)
     for (uint32_t k = 0; k < G; ++k) GZ_HIP(hipStreamWaitEvent(stream, gs[k]->last, 0));
@@ -653,83 +785,14 @@ gz_status ingest_fused(gz_graph* const* gs, uint32_t G, const uint64_t* offs_hos
         dsrc = S.staging;
         ddst = S.staging + N;
     }
-    // per-call tables go through pinned buffers, reused once the previous
-    // call's uploads have left them
-    GZ_HIP(hipEventSynchronize(S.copied_ev));
-    IngestArgs& a = *S.h_args;
-    a = IngestArgs{};
-    a.src = dsrc;
-    a.dst = ddst;
-    a.offs = nullptr;
-    a.N = N;
-    a.G = G;
-    a.T = (uint32_t)T;
-    a.chunk = chunk;
-    a.lds_rows = tune.lds_rows;
-    a.group_chunk = group_chunk;
-    a.n_units = n_units;
-    a.H_size = H_size;
-    std::memcpy(S.h_descs, descs.data(), sizeof(GraphDesc) * G);
-    if (n_units) std::memcpy(S.h_units, units.data(), sizeof(GroupUnit) * n_units);
-    GZ_HIP(hipMemcpyAsync(S.args, S.h_args, sizeof(IngestArgs), hipMemcpyHostToDevice, stream));
-    GZ_HIP(hipMemcpyAsync(S.descs, S.h_descs, sizeof(GraphDesc) * G, hipMemcpyHostToDevice,
-                          stream));
-    if (n_units)
-        GZ_HIP(hipMemcpyAsync(S.units, S.h_units, sizeof(GroupUnit) * n_units,
-                              hipMemcpyHostToDevice, stream));
+    GZ_TRY(upload_args(S, L, dsrc, ddst, N, nullptr, stream));
+    GZ_TRY(upload_shape(S, L, stream));
     GZ_HIP(hipEventRecord(S.copied_ev, stream));
-
-    gz_graph* prof = gs[0]->profiling ? gs[0] : nullptr;
-    if (prof) GZ_HIP(hipEventRecord(prof->prof_ev[0], stream));
-    const uint32_t Tn = (uint32_t)T;
-    k_fill_u32<<<1, 64, 0, stream>>>(S.ctl, 3, 0);  // ticket, items, call error (sticky kept)
-    const size_t gsmem = (size_t)range_max * 4;
-    GZ_TRY(set_smem_limit((const void*)k_group_count, gsmem));
-    GZ_TRY(set_smem_limit((const void*)k_group_scatter, gsmem));
-    if (n_units)
-        k_group_count<<<n_units, kGroupThreads, gsmem, stream>>>(S.args, S.units, S.descs, S.H,
-                                                                 S.ctl);
-    k_group_colsum<<<grid_for(Tn, 256, 8192), 256, 0, stream>>>(S.descs, G, Tn, S.H, S.counts);
-    const uint32_t nblocks = (uint32_t)((T + kScanTile - 1) / kScanTile);
-    k_scan_partial<<<nblocks, kScanThreads, 0, stream>>>(S.counts, Tn, chunk, S.block_sums);
-    k_scan_top<<<1, kScanThreads, 0, stream>>>(S.block_sums, nblocks, S.ctl);
-    k_scan_items<<<nblocks, kScanThreads, 0, stream>>>(S.counts, Tn, chunk, S.block_sums, S.items,
-                                                       S.cursor, S.descs, G, S.ctl);
-    k_group_colscan<<<grid_for(Tn, 256, 8192), 256, 0, stream>>>(S.descs, G, Tn, S.cursor, S.H);
-    if (n_units)
-        k_group_scatter<<<n_units, kGroupThreads, gsmem, stream>>>(S.args, S.units, S.descs, S.H,
-                                                                   S.grouped, S.ctl);
-    const size_t smem = update_smem_bytes(DLmax, Pmax);
-    const uint32_t pgrid = std::max(1u, tune.wgs_per_cu) * cus;
-    if (prof) GZ_HIP(hipEventRecord(prof->prof_ev[1], stream));
-    if (all_rows) {
-        GZ_TRY(set_smem_limit((const void*)k_update<true>, smem));
-        k_update<true><<<pgrid, wg, smem, stream>>>(S.items, S.ctl, S.grouped, S.descs,
-                                                    tune.lds_rows);
-    } else {
-        GZ_TRY(set_smem_limit((const void*)k_update<false>, smem));
-        k_update<false><<<pgrid, wg, smem, stream>>>(S.items, S.ctl, S.grouped, S.descs,
-                                                     tune.lds_rows);
-    }
-    GZ_HIP(hipGetLastError());
-    if (prof) {
-        GZ_HIP(hipEventRecord(prof->prof_ev[2], stream));
-        prof->prof_calls++;
-    }
+    GZ_TRY(launch_sequence(S, L, stream, gs[0]->profiling ? gs[0] : nullptr));
     for (uint32_t k = 0; k < G; ++k) GZ_HIP(hipEventRecord(gs[k]->last, stream));
 
-    if (!(flags & GZ_ASYNC)) {
-        GZ_HIP(hipMemcpyAsync(S.h_err, S.ctl + 2, 4, hipMemcpyDeviceToHost, stream));
-        GZ_HIP(hipStreamSynchronize(stream));
-        if (S.h_err[0]) {
-            // the sticky flag is for asynchronous callers; this one is reported now
-            k_fill_u32<<<1, 64, 0, stream>>>(S.ctl + 3, 1, 0);
-            GZ_HIP(hipStreamSynchronize(stream));
-            return fail(GZ_EINVAL, "invalid update (self-loop or node id out of range)");
-        }
-    } else {
-        for (uint32_t k = 0; k < G; ++k) gs[k]->pending_error = true;  // flush must check
-    }
+    if (!(flags & GZ_ASYNC)) return check_call_error(S, stream);
+    for (uint32_t k = 0; k < G; ++k) gs[k]->pending_error = true;  // flush must check
     return GZ_OK;
 }
 
@@ -803,3 +866,120 @@ gz_status update_node_batch(gz_graph* g, uint32_t node, const uint32_t* nbrs, ui
 }
 
 }  // namespace gz
+
+// ------------------------------------------------------ captured ingest plan --
+
+struct gz_plan {
+    std::vector<gz_graph*> gs;
+    std::vector<uint64_t> caps;
+    gz::IngestScratch S;
+    gz::LaunchShape L;
+    uint64_t* offs_dev = nullptr;
+    uint64_t* h_offs = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipStream_t cap_stream = nullptr;
+};
+
+using namespace gz;
+
+extern "C" {
+
+gz_status gz_plan_create(gz_graph* const* gs, uint32_t G, const uint64_t* caps, hipStream_t stream,
+                         gz_plan** out) {
+    if (!out || !gs || !caps || G == 0) return fail(GZ_EINVAL, "null argument");
+    *out = nullptr;
+    std::vector<uint64_t> ranges(G + 1, 0);
+    for (uint32_t k = 0; k < G; ++k) {
+        if (!gs[k]) return fail(GZ_EINVAL, "null graph handle");
+        for (uint32_t j = 0; j < k; ++j)
+            if (gs[j] == gs[k]) return fail(GZ_EINVAL, "graph listed twice");
+        ranges[k + 1] = ranges[k] + caps[k];
+    }
+    if (ranges[G] >= (1ull << 31)) return fail(GZ_EINVAL, "capacities sum to 2^31 or more");
+    gz_plan* p = new gz_plan();
+    p->gs.assign(gs, gs + G);
+    p->caps.assign(caps, caps + G);
+    gz_status st = build_shape(gs, G, ranges.data(), ranges[G], p->L);
+    if (!st) st = ensure_scratch(p->S, ranges[G], p->L.T, G, p->L.chunk, p->L.H_size,
+                                 p->L.n_units, false);
+    hipError_t e = hipSuccess;
+    if (!st) {
+        e = hipMalloc((void**)&p->offs_dev, sizeof(uint64_t) * (G + 1));
+        if (e == hipSuccess)
+            e = hipHostMalloc((void**)&p->h_offs, sizeof(uint64_t) * (G + 1), hipHostMallocDefault);
+        if (e == hipSuccess) e = hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking);
+        if (e != hipSuccess) st = hip_fail(e, "plan buffers");
+    }
+    if (!st) st = upload_shape(p->S, p->L, stream);
+    if (!st) {
+        e = hipStreamSynchronize(stream);
+        if (e != hipSuccess) st = hip_fail(e, "plan upload");
+    }
+    if (!st) {
+        e = hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) st = hip_fail(e, "begin capture");
+        if (!st) {
+            gz_status lst = launch_sequence(p->S, p->L, p->cap_stream, nullptr);
+            e = hipStreamEndCapture(p->cap_stream, &p->graph);
+            if (lst) st = lst;
+            else if (e != hipSuccess) st = hip_fail(e, "end capture");
+        }
+        if (!st) {
+            e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
+            if (e != hipSuccess) st = hip_fail(e, "graph instantiate");
+        }
+    }
+    if (st) {
+        gz_plan_free(p);
+        return st;
+    }
+    *out = p;
+    return GZ_OK;
+}
+
+gz_status gz_plan_ingest(gz_plan* p, const uint64_t* offs, const uint32_t* src, const uint32_t* dst,
+                         uint32_t flags, hipStream_t stream) {
+    if (!p || !offs) return fail(GZ_EINVAL, "null argument");
+    if (!(flags & GZ_DEVICE_PTR)) return fail(GZ_EINVAL, "plans take device arrays");
+    const uint32_t G = (uint32_t)p->gs.size();
+    if (offs[0] != 0) return fail(GZ_EINVAL, "update offsets must start at 0");
+    for (uint32_t k = 0; k < G; ++k) {
+        if (offs[k + 1] < offs[k]) return fail(GZ_EINVAL, "update offsets must be non-decreasing");
+        if (offs[k + 1] - offs[k] > p->caps[k])
+            return fail(GZ_EINVAL, "a graph's updates exceed its capacity in the plan");
+    }
+    const uint64_t N = offs[G];
+    if (N && (!src || !dst)) return fail(GZ_EINVAL, "null stream arrays");
+    IngestScratch& S = p->S;
+    for (gz_graph* g : p->gs) GZ_HIP(hipStreamWaitEvent(stream, g->last, 0));
+    GZ_TRY(upload_args(S, p->L, src, dst, N, p->offs_dev, stream));
+    std::memcpy(p->h_offs, offs, sizeof(uint64_t) * (G + 1));
+    GZ_HIP(hipMemcpyAsync(p->offs_dev, p->h_offs, sizeof(uint64_t) * (G + 1),
+                          hipMemcpyHostToDevice, stream));
+    GZ_HIP(hipEventRecord(S.copied_ev, stream));
+    GZ_HIP(hipGraphLaunch(p->exec, stream));
+    for (gz_graph* g : p->gs) GZ_HIP(hipEventRecord(g->last, stream));
+    if (!(flags & GZ_ASYNC)) return check_call_error(S, stream);
+    for (gz_graph* g : p->gs) g->pending_error = true;
+    return GZ_OK;
+}
+
+gz_status gz_plan_free(gz_plan* p) {
+    if (!p) return GZ_OK;
+    if (p->cap_stream) hipStreamSynchronize(p->cap_stream);
+    if (p->S.copied_ev) hipEventSynchronize(p->S.copied_ev);
+    for (gz_graph* g : p->gs)
+        if (g && g->last) hipEventSynchronize(g->last);
+    if (p->exec) hipGraphExecDestroy(p->exec);
+    if (p->graph) hipGraphDestroy(p->graph);
+    if (p->cap_stream) hipStreamDestroy(p->cap_stream);
+    hipFree(p->offs_dev);
+    hipHostFree(p->h_offs);
+    free_ingest_scratch(p->S);
+    delete p;
+    return GZ_OK;
+}
+
+}  // extern "C"
+

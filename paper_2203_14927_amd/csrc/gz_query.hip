@@ -120,15 +120,24 @@ __global__ void k_q_reduce(uint32_t r, uint32_t T, const uint32_t* __restrict__ 
         const uint32_t w = w0 + threadIdx.x;
         const uint32_t row = w >> 3;  // plane * B + d
         const uint32_t c = w & (kC - 1);
+        // all loads of the run first (independent, in flight together) ...
+        uint32_t val[kReduceRun];
+#pragma unroll
+        for (uint32_t i = 0; i < kReduceRun; ++i)
+            val[i] = (i < n && s_slot[i] != kNone && w < s_words[i])
+                         ? s_base[i][(uint64_t)row * s_P[i] + c]
+                         : 0u;
+        // ... then the XOR runs over equal components, one atomic per run
         uint32_t run = 0, run_slot = kNone;
-        for (uint32_t i = 0; i < n; ++i) {
-            const uint32_t sl = s_slot[i];
+#pragma unroll
+        for (uint32_t i = 0; i < kReduceRun; ++i) {
+            const uint32_t sl = i < n ? s_slot[i] : kNone;
             if (sl != run_slot) {
                 if (run_slot != kNone && run) atomicXor(&acc[(uint64_t)run_slot * wpr + w], run);
                 run = 0;
                 run_slot = sl;
             }
-            if (sl != kNone && w < s_words[i]) run ^= s_base[i][(uint64_t)row * s_P[i] + c];
+            run ^= val[i];
         }
         if (run_slot != kNone && run) atomicXor(&acc[(uint64_t)run_slot * wpr + w], run);
     }
@@ -224,6 +233,29 @@ __global__ void k_q_double(const uint32_t* __restrict__ L, const uint32_t* __res
         const uint32_t y = s[X];
         s2[X] = s[y];
         m2[X] = min(m[X], m[y]);
+    }
+}
+
+// all K doubling steps in one workgroup (lists of up to a few ten thousand
+// components): the arrays stay in global memory, visible to the whole
+// workgroup after each barrier; ping-pong between (s, m) and (s2, m2)
+__global__ __launch_bounds__(1024) void k_q_double_all(const uint32_t* __restrict__ L,
+                                                        const uint32_t* __restrict__ ctl,
+                                                        uint32_t K, uint32_t* s, uint32_t* m,
+                                                        uint32_t* s2, uint32_t* m2) {
+    const uint32_t nL = ctl[Q_NL];
+    for (uint32_t k = 0; k < K; ++k) {
+        uint32_t* si = (k & 1) ? s2 : s;
+        uint32_t* mi = (k & 1) ? m2 : m;
+        uint32_t* so = (k & 1) ? s : s2;
+        uint32_t* mo = (k & 1) ? m : m2;
+        for (uint32_t i = threadIdx.x; i < nL; i += blockDim.x) {
+            const uint32_t X = L[i];
+            const uint32_t y = si[X];
+            so[X] = si[y];
+            mo[X] = min(mi[X], mi[y]);
+        }
+        __syncthreads();
     }
 }
 
@@ -329,6 +361,7 @@ __global__ void k_q_fscatter(const uint64_t* __restrict__ forest, const uint32_t
 }
 
 constexpr uint32_t kRankThreads = 256;
+constexpr uint32_t kSingleBlockDoubling = 65536;  // component lists up to this length
 
 __global__ __launch_bounds__(kRankThreads) void k_q_frank(const uint64_t* __restrict__ keys,
                                                            const uint32_t* __restrict__ ctl,
@@ -527,10 +560,18 @@ gz_status boruvka(gz_graph* const* gs, uint32_t G, bool want_forest, QueryResult
                 Q->done);
         }
         k_q_double_init<<<tb, 256, 0, qs>>>(L, Q->ctl, Q->hook, s, m);
-        for (uint32_t k = 0; k < K; ++k) {
-            k_q_double<<<tb, 256, 0, qs>>>(L, Q->ctl, s, m, s2, m2);
-            std::swap(s, s2);
-            std::swap(m, m2);
+        if (T <= kSingleBlockDoubling) {
+            k_q_double_all<<<1, 1024, 0, qs>>>(L, Q->ctl, K, s, m, s2, m2);
+            if (K & 1) {
+                std::swap(s, s2);
+                std::swap(m, m2);
+            }
+        } else {
+            for (uint32_t k = 0; k < K; ++k) {
+                k_q_double<<<tb, 256, 0, qs>>>(L, Q->ctl, s, m, s2, m2);
+                std::swap(s, s2);
+                std::swap(m, m2);
+            }
         }
         k_q_root<<<tb, 256, 0, qs>>>(L, Q->ctl, s, m, Q->hook, Q->hedge, Q->gof, Q->rootOf,
                                      Q->newlab, Q->merged, Q->forest);

@@ -34,6 +34,20 @@ uint32_t host_hash(uint64_t mult, uint64_t incr, uint64_t x) {
 }
 }  // namespace
 
+// the graph's query stream, created on first use (many-graph sets never query
+// most graphs one by one)
+hipError_t query_stream(gz_graph* g, hipStream_t* out) {
+    if (!g->qstream) {
+        hipError_t e = hipStreamCreateWithFlags(&g->qstream, hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            g->qstream = nullptr;
+            return e;
+        }
+    }
+    *out = g->qstream;
+    return hipSuccess;
+}
+
 gz_status fail(gz_status s, const std::string& msg) {
     g_last_error = msg;
     return s;
@@ -113,8 +127,9 @@ gz_status export_nested(gz_graph* g, uint32_t lo, uint32_t hi, uint64_t* alpha, 
         hipFree(da);
         return fail(GZ_ENOMEM, "export buffer");
     }
-    hipStream_t s = g->qstream;
-    hipError_t e = hipStreamWaitEvent(s, g->last, 0);
+    hipStream_t s = nullptr;
+    hipError_t e = query_stream(g, &s);
+    if (e == hipSuccess) e = hipStreamWaitEvent(s, g->last, 0);
     if (e == hipSuccess) {
         const uint64_t total = (uint64_t)(hi - lo) * g->P;
         const uint32_t blocks = (uint32_t)std::min<uint64_t>((total + 255) / 256, 65535);
@@ -178,9 +193,8 @@ gz_status init_graph(gz_graph** out, uint32_t V, uint64_t seed, const gz_config*
     e = hipMalloc((void**)&g->seeds, soa.size() * 4);
     if (e == hipSuccess) e = hipMemcpy(g->seeds, soa.data(), soa.size() * 4, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemset(g->sk, 0, g->sk_words * 4);
-    if (e == hipSuccess) e = hipStreamCreateWithFlags(&g->qstream, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&g->last, hipEventDisableTiming);
-    if (e == hipSuccess) e = hipEventRecord(g->last, g->qstream);
+    if (e == hipSuccess) e = hipEventRecord(g->last, 0);
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) {
         gz_status s = hip_fail(e, "graph init");
@@ -206,7 +220,7 @@ gz_status gz_sketch_init(gz_graph** out, uint32_t V, uint64_t seed, const gz_con
 
 gz_status gz_free(gz_graph* g) {
     if (!g) return GZ_OK;
-    hipStreamSynchronize(g->qstream);
+    if (g->qstream) hipStreamSynchronize(g->qstream);
     hipEventSynchronize(g->last);
     free_ingest_scratch(g->ing);
     free_query_scratch(g->q);
@@ -215,7 +229,7 @@ gz_status gz_free(gz_graph* g) {
     hipEventDestroy(g->last);
     for (hipEvent_t e : g->prof_ev)
         if (e) hipEventDestroy(e);
-    hipStreamDestroy(g->qstream);
+    if (g->qstream) hipStreamDestroy(g->qstream);
     delete g;
     return GZ_OK;
 }

@@ -149,6 +149,7 @@ gz_status hip_fail(hipError_t e, const char* what);
     } while (0)
 
 int device_cu_count();
+hipError_t query_stream(gz_graph* g, hipStream_t* out);
 gz_tuning default_tuning(uint32_t P, uint32_t B);
 
 // ingest path (gz_ingest.hip)

@@ -524,7 +524,8 @@ gz_status boruvka(gz_graph* const* gs, uint32_t G, bool want_forest, QueryResult
     gz_status st = ensure_query(*Q, T, G, wpr);
     if (st) return st;
 
-    hipStream_t qs = gs[0]->qstream;
+    hipStream_t qs = nullptr;
+    GZ_HIP(query_stream(gs[0], &qs));
     for (uint32_t k = 0; k < G; ++k) GZ_HIP(hipStreamWaitEvent(qs, gs[k]->last, 0));
     GZ_HIP(hipMemcpyAsync(Q->descs, descs.data(), sizeof(GraphDesc) * G, hipMemcpyHostToDevice, qs));
     const uint32_t tb = blocks_for(T, 256);

@@ -1,0 +1,141 @@
+"""Parity at the full workload sizes, in the launch configuration the benchmark times.
+
+The oracle cannot hold every node sketch of these graphs, so it recomputes a
+sample of nodes one by one (only the updates touching them); component labels
+are checked for every node against connected components of the final graph,
+and the forest against the final graph's edges.
+"""
+import sys
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from helpers import check_forest_valid, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def gz(built):
+    import torch
+
+    assert torch.cuda.is_available()
+    import paper_2203_14927_amd as gz
+
+    gz.lib()
+    return gz
+
+
+def _sample_nodes(stream, k, seed):
+    deg = np.bincount(np.concatenate([stream.src, stream.dst]), minlength=stream.V)
+    rng = np.random.default_rng(seed)
+    pick = set(rng.choice(stream.V, k, replace=False).tolist())
+    pick |= {0, stream.V - 1, int(np.argmax(deg)), int(np.argmin(deg))}
+    return sorted(pick)
+
+
+def _final_sorted_keys(stream):
+    fu, fv = workloads.final_edges(stream)
+    return fu, fv
+
+
+def _check_forest_against_final(V, labels, forest, fu, fv):
+    keys = np.sort(fu.astype(np.int64) * V + fv.astype(np.int64))
+    fk = forest[:, 0].astype(np.int64) * V + forest[:, 1].astype(np.int64)
+    pos = np.searchsorted(keys, fk)
+    assert (pos < len(keys)).all() and (keys[np.minimum(pos, len(keys) - 1)] == fk).all(), \
+        "forest edge not in the final graph"
+    assert (forest[:, 0] < forest[:, 1]).all()
+    assert len(forest) == V - len(np.unique(labels))
+    # acyclic and inside components: union-find over the forest reproduces the labels
+    ref = workloads.scipy_labels(V, forest[:, 0], forest[:, 1])
+    assert (ref == labels).all()
+    idx = forest[:, 1].astype(np.int64) * (forest[:, 1].astype(np.int64) - 1) // 2 + forest[:, 0]
+    assert (np.diff(idx) > 0).all()
+
+
+def _full_single(gz, stream, seed, sample=48):
+    t0 = time.time()
+    g = gz.Graph(stream.V, seed=seed)
+    src, dst = to_dev(stream.src), to_dev(stream.dst)
+    best, ms = g.autotune(src, dst)
+    log(f"  autotuned {best} ({ms:.2f} ms/ingest)")
+    g.ingest(src, dst)
+    st, labels, ncc, forest = g.query()
+    assert st == gz.GZ_OK
+    log(f"  GPU ingest + query done ({time.time() - t0:.1f} s), components={ncc}")
+    nodes = _sample_nodes(stream, sample, seed)
+    O = oracle.Oracle(stream.V, seed)
+    O.ingest_nodes(stream.src, stream.dst, nodes)
+    for v in nodes:
+        a, b = g.export(v, v + 1)
+        assert (a[0] == O.alpha[v]).all() and (b[0] == O.gamma[v]).all(), f"node {v} differs"
+    log(f"  {len(nodes)} sampled node sketches bit-exact ({time.time() - t0:.1f} s)")
+    fu, fv = _final_sorted_keys(stream)
+    ref = workloads.scipy_labels(stream.V, fu, fv)
+    assert (labels == ref).all()
+    _check_forest_against_final(stream.V, labels, forest, fu, fv)
+    log(f"  labels and forest checked against the final graph ({time.time() - t0:.1f} s)")
+
+
+def test_full_dense_rmat(gz):
+    """V=2^14 R-MAT (0.57,0.19,0.19,0.05), ~55M updates, the benchmark's workload."""
+    s = workloads.config_rmat_dense()
+    log(f"dense R-MAT: V={s.V} N={s.N}")
+    _full_single(gz, s, 2)
+
+
+def test_full_skewed_rmat(gz):
+    """V=2^15 skewed R-MAT (0.7,0.1,0.1,0.1), ~150M updates with 20% deletes interleaved."""
+    s = workloads.config_rmat_skewed()
+    log(f"skewed R-MAT: V={s.V} N={s.N}")
+    _full_single(gz, s, 3, sample=32)
+
+
+def test_full_many_gnp_plan(gz):
+    """4096 G(n,p) graphs through one captured plan, components of every graph."""
+    import torch
+
+    t0 = time.time()
+    streams = workloads.config_many_gnp()
+    seeds = [workloads.many_graph_seed(4, k) for k in range(len(streams))]
+    offs = np.zeros(len(streams) + 1, np.uint64)
+    offs[1:] = np.cumsum([s.N for s in streams])
+    src = np.concatenate([s.src for s in streams])
+    dst = np.concatenate([s.dst for s in streams])
+    log(f"many G(n,p): {len(streams)} graphs, {int(offs[-1])} updates "
+        f"({time.time() - t0:.1f} s)")
+    graphs = [gz.Graph(s.V, seed=sd) for s, sd in zip(streams, seeds)]
+    plan = gz.Plan(graphs, [s.N for s in streams])
+    plan.ingest(offs, to_dev(src), to_dev(dst))
+    torch.cuda.synchronize()
+    labels, ncc, stt = gz.connected_components_multi(graphs)
+    assert (stt == gz.GZ_OK).all()
+    log(f"  GPU plan ingest + fused query done ({time.time() - t0:.1f} s)")
+    for k, s in enumerate(streams):
+        fu, fv = workloads.final_edges(s)
+        ref = workloads.scipy_labels(s.V, fu, fv)
+        assert (labels[k] == ref).all(), f"graph {k}"
+        assert ncc[k] == len(np.unique(ref))
+    log(f"  labels of all graphs checked ({time.time() - t0:.1f} s)")
+    rng = np.random.default_rng(4)
+    for k in sorted(set(rng.choice(len(streams), 12, replace=False).tolist()) | {0}):
+        s = streams[k]
+        O = oracle.Oracle(s.V, seeds[k])
+        O.ingest(s.src, s.dst)
+        a, b = graphs[k].export()
+        assert (a == O.alpha).all() and (b == O.gamma).all(), f"graph {k} sketches differ"
+        st, lab, fo, _ = O.connected_components()
+        st2, lab2, nc2, fo2 = graphs[k].query()
+        assert (fo2 == fo).all() and (lab2 == lab).all()
+    log(f"  sampled graphs bit-exact with the oracle ({time.time() - t0:.1f} s)")
+    plan.close()
+    for g in graphs:
+        g.close()

@@ -152,6 +152,9 @@ def main() -> int:
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch parameters")
+    ap.add_argument("--tuning", default="",
+                    help="explicit launch parameters wg_size,lds_rows,chunk,wgs_per_cu,group_blocks "
+                         "(skips the autotuner)")
     ap.add_argument("--sessions", type=int, default=256, help="serving: number of sessions")
     ap.add_argument("--batches", type=int, default=100, help="serving: batches per session")
     ap.add_argument("--hbm-budget-gb", type=float, default=120.0, help="serving: admission budget")
@@ -362,6 +365,10 @@ def run_single(args) -> dict:
         del a, b
     g = gz.Graph(stream.V, seed=seed)
     tune_ms = None
+    if args.tuning:
+        keys = ["wg_size", "lds_rows", "chunk", "wgs_per_cu", "group_blocks"]
+        g.set_tuning(**dict(zip(keys, (int(x) for x in args.tuning.split(",")))))
+        args.no_autotune = True
     if not args.no_autotune:
         t0 = time.perf_counter()
         best, tune_ms = g.autotune(src_d, dst_d)
@@ -428,7 +435,7 @@ def run_single(args) -> dict:
         "cc_query_ms": cc_query_ms,
         "components": ncc,
         "tuning": g.tuning,
-        "autotuned": not args.no_autotune,
+        "autotuned": not args.no_autotune and not args.tuning,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_INT_TOPS,
                      "unit": "TOP/s", "frac": achieved / PEAK_INT_TOPS,
                      "traffic": traffic,

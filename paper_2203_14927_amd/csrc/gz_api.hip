@@ -72,6 +72,34 @@ int device_cu_count() {
     return cached[dev % 64];
 }
 
+hipError_t fence_wait(hipStream_t stream, gz_graph* const* gs, uint32_t G) {
+    const Fence* prev = nullptr;
+    std::vector<const Fence*> seen;
+    for (uint32_t k = 0; k < G; ++k) {
+        const Fence* f = gs[k]->last.get();
+        if (!f || f == prev) continue;
+        prev = f;
+        if (G > 1) {
+            if (std::find(seen.begin(), seen.end(), f) != seen.end()) continue;
+            if (seen.size() < 64) seen.push_back(f);
+        }
+        hipError_t e = hipStreamWaitEvent(stream, f->ev, 0);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t fence_record(hipStream_t stream, gz_graph* const* gs, uint32_t G) {
+    if (G == 1 && gs[0]->last && gs[0]->last.use_count() == 1)
+        return hipEventRecord(gs[0]->last->ev, stream);  // sole owner: reuse the event
+    FenceRef f = std::make_shared<Fence>();
+    hipError_t e = hipEventCreateWithFlags(&f->ev, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventRecord(f->ev, stream);
+    if (e != hipSuccess) return e;
+    for (uint32_t k = 0; k < G; ++k) gs[k]->last = f;
+    return hipSuccess;
+}
+
 // Defaults before autotuning: the whole tile in LDS when it takes at most 48 KiB,
 // the workgroup (multiple of 64, 256..512 lanes) with the best lane use for P
 // pairs, and as many resident workgroups per CU as 160 KiB of LDS allows.
@@ -105,13 +133,13 @@ __global__ void k_export(const uint32_t* __restrict__ sk, uint32_t lo, uint32_t 
          t += (uint64_t)gridDim.x * blockDim.x) {
         const uint32_t v = lo + (uint32_t)(t / P);
         const uint32_t p = (uint32_t)(t % P);  // p = r * C + c
-        const uint32_t* base = sk + (uint64_t)v * kPlanes * B * P + p;
+        const uint32_t* base = sk + (uint64_t)v * kPlanes * B * P + sk_word(B, p / kC, 0, 0, p % kC);
         const uint64_t out0 = (t / P) * (uint64_t)R * kC * B + (uint64_t)p * B;
         uint32_t a = 0, gl = 0, gh = 0;
         for (int b = (int)B - 1; b >= 0; --b) {
-            a ^= base[(uint64_t)(0 * B + b) * P];
-            gl ^= base[(uint64_t)(1 * B + b) * P];
-            gh ^= base[(uint64_t)(2 * B + b) * P];
+            a ^= base[(0 * B + b) * kC];
+            gl ^= base[(1 * B + b) * kC];
+            gh ^= base[(2 * B + b) * kC];
             alpha[out0 + b] = a;
             gamma[out0 + b] = ((uint64_t)gh << 32) | gl;
         }
@@ -129,7 +157,7 @@ gz_status export_nested(gz_graph* g, uint32_t lo, uint32_t hi, uint64_t* alpha, 
     }
     hipStream_t s = nullptr;
     hipError_t e = query_stream(g, &s);
-    if (e == hipSuccess) e = hipStreamWaitEvent(s, g->last, 0);
+    if (e == hipSuccess) e = fence_wait(s, g);
     if (e == hipSuccess) {
         const uint64_t total = (uint64_t)(hi - lo) * g->P;
         const uint32_t blocks = (uint32_t)std::min<uint64_t>((total + 255) / 256, 65535);
@@ -193,8 +221,7 @@ gz_status init_graph(gz_graph** out, uint32_t V, uint64_t seed, const gz_config*
     e = hipMalloc((void**)&g->seeds, soa.size() * 4);
     if (e == hipSuccess) e = hipMemcpy(g->seeds, soa.data(), soa.size() * 4, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemset(g->sk, 0, g->sk_words * 4);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&g->last, hipEventDisableTiming);
-    if (e == hipSuccess) e = hipEventRecord(g->last, 0);
+    if (e == hipSuccess) e = fence_record(0, g);
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) {
         gz_status s = hip_fail(e, "graph init");
@@ -221,12 +248,11 @@ gz_status gz_sketch_init(gz_graph** out, uint32_t V, uint64_t seed, const gz_con
 gz_status gz_free(gz_graph* g) {
     if (!g) return GZ_OK;
     if (g->qstream) hipStreamSynchronize(g->qstream);
-    hipEventSynchronize(g->last);
+    if (g->last) hipEventSynchronize(g->last->ev);
     free_ingest_scratch(g->ing);
     free_query_scratch(g->q);
     hipFree(g->sk);
     hipFree(g->seeds);
-    hipEventDestroy(g->last);
     for (hipEvent_t e : g->prof_ev)
         if (e) hipEventDestroy(e);
     if (g->qstream) hipStreamDestroy(g->qstream);
@@ -272,9 +298,9 @@ gz_status gz_shape(const gz_graph* g, uint32_t* V, uint32_t* R, uint32_t* C, uin
 
 gz_status gz_reset(gz_graph* g, hipStream_t stream) {
     if (!g) return fail(GZ_EINVAL, "null graph");
-    GZ_HIP(hipStreamWaitEvent(stream, g->last, 0));
+    GZ_HIP(fence_wait(stream, g));
     GZ_HIP(hipMemsetAsync(g->sk, 0, g->sk_words * 4, stream));
-    GZ_HIP(hipEventRecord(g->last, stream));
+    GZ_HIP(fence_record(stream, g));
     return GZ_OK;
 }
 
@@ -296,11 +322,7 @@ gz_status gz_ingest_multi(gz_graph* const* gs, uint32_t G, const uint64_t* offs,
                           const uint32_t* src, const uint32_t* dst, uint32_t flags,
                           hipStream_t stream) {
     if (!gs || !offs || G == 0) return fail(GZ_EINVAL, "null argument");
-    for (uint32_t k = 0; k < G; ++k) {
-        if (!gs[k]) return fail(GZ_EINVAL, "null graph handle");
-        for (uint32_t j = 0; j < k; ++j)
-            if (gs[j] == gs[k]) return fail(GZ_EINVAL, "graph listed twice");
-    }
+    if (bad_graph_list(gs, G)) return fail(GZ_EINVAL, "null graph handle or graph listed twice");
     const uint64_t N = offs[G];
     if (N == 0) return GZ_OK;
     std::unique_lock<std::mutex> lock;
@@ -310,7 +332,7 @@ gz_status gz_ingest_multi(gz_graph* const* gs, uint32_t G, const uint64_t* offs,
 
 gz_status gz_flush(gz_graph* g) {
     if (!g) return fail(GZ_EINVAL, "null graph");
-    GZ_HIP(hipEventSynchronize(g->last));
+    GZ_HIP(hipEventSynchronize(g->last->ev));
     if (g->pending_error) {
         g->pending_error = false;
         uint32_t sticky = 0;

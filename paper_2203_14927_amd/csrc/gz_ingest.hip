@@ -275,27 +275,51 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_items(
 // lanes of a wave never collide, however their rows differ.
 __host__ __device__ __forceinline__ uint32_t tile_stride(uint32_t P) { return (P + 63u) & ~63u; }
 
-// Hash one entry for this lane's (round, column) pair and XOR it into the
-// exact-depth row of the LDS tile; rows >= DL (kAllRows == false only) go
-// straight to HBM with atomics.
+// Per-lane state of the update: the lane's (round, column) pair p within group
+// j of J, the pair's seeds, and the lane's offsets in a tile row and in a
+// node's HBM block.  It depends only on the graph, so a workgroup keeps it
+// across consecutive work items of one graph.
+struct Lane {
+    PairSeeds s;
+    uint32_t j, J, p;
+    uint32_t tile_bytes;  // byte offset of the lane's bucket in a tile row
+    uint32_t hbm_word;    // word of (round, plane 0, row 0, column) in a node block
+    bool active;
+};
+
+__device__ __forceinline__ Lane make_lane(const GraphDesc& g) {
+    Lane ln{};
+    const uint32_t tid = threadIdx.x;
+    ln.J = blockDim.x / g.P;
+    ln.j = tid / g.P;
+    ln.p = tid - ln.j * g.P;
+    ln.active = tid < ln.J * g.P;
+    if (ln.active) ln.s = load_pair_seeds(g.seeds, g.P, ln.p);
+    ln.tile_bytes = ln.p * kPlanes * 4;
+    ln.hbm_word = sk_word(g.B, ln.p / kC, 0, 0, ln.p % kC);
+    return ln;
+}
+
+// Hash one entry for this lane's pair and XOR it into the exact-depth row of
+// the LDS tile; rows >= DL (kAllRows == false only) go straight to HBM with
+// atomics (`skl` is the lane's bucket of row 0, plane 0, in the node block).
 template <bool kAllRows>
-__device__ __forceinline__ void xor_entry(uint32_t x, const PairSeeds& s, uint32_t Bm1,
-                                          uint32_t DL, uint32_t row_bytes, uint32_t lane_bytes,
-                                          uint8_t* __restrict__ tile, uint32_t* __restrict__ skn,
-                                          uint64_t rowp, uint32_t P, uint32_t p) {
-    const uint32_t d = row_depth(s, x, Bm1);
-    const uint32_t hi = chk_hi(s, x);
-    const uint32_t lo = chk_lo(s, x);
+__device__ __forceinline__ void xor_entry(uint32_t x, const Lane& ln, uint32_t Bm1, uint32_t DL,
+                                          uint32_t row_bytes, uint8_t* __restrict__ tile,
+                                          uint32_t* __restrict__ skl, uint32_t plane_words) {
+    const uint32_t d = row_depth(ln.s, x, Bm1);
+    const uint32_t hi = chk_hi(ln.s, x);
+    const uint32_t lo = chk_lo(ln.s, x);
     if (kAllRows || d < DL) {
-        uint32_t* a = (uint32_t*)(tile + (__umul24(d, row_bytes) + lane_bytes));
+        uint32_t* a = (uint32_t*)(tile + (__umul24(d, row_bytes) + ln.tile_bytes));
         atomicXor(a, x);
         atomicXor(a + 1, lo);
         atomicXor(a + 2, hi);
     } else {
-        uint32_t* w = skn + (uint64_t)d * P + p;
+        uint32_t* w = skl + d * kC;
         atomicXor(w, x);
-        atomicXor(w + rowp, lo);
-        atomicXor(w + 2 * rowp, hi);
+        atomicXor(w + plane_words, lo);
+        atomicXor(w + 2 * plane_words, hi);
     }
 }
 
@@ -327,50 +351,111 @@ struct NeighbourEntries {
     }
 };
 
-// Apply `count` entries to node `node` of graph `g`.  Lanes map to
-// (group j, pair p): J = blockDim / P groups each take a contiguous share of
-// the entries; each lane hashes its pair's seeds and XORs into the exact-depth
-// row of its column.  Entries arrive from HBM in 16-byte quads, eight entries
-// per iteration with the next eight in flight.  The tile is then XORed back
-// into HBM: plain read-modify-write when this workgroup owns the node for the
-// launch, atomics when the node's entries are split across workgroups.
+// Walk over the tile rows d < DL of a node in HBM order of the round-major
+// block: flat index i over 3 * DL * P words, row = i / P (by a reciprocal
+// multiply, exact for i * P < 2^32), p = i mod P, d = row / 3, plane = row mod 3.
+// Consecutive lanes take consecutive pairs of one (plane, row), so their LDS
+// words fall in distinct banks and their HBM words form runs of C columns.
+struct TileWalk {
+    uint32_t P, B, S, n, recip;
+    __device__ __forceinline__ TileWalk(uint32_t P_, uint32_t B_, uint32_t DL)
+        : P(P_), B(B_), S(tile_stride(P_)), n(kPlanes * DL * P_), recip(0xFFFFFFFFu / P_ + 1u) {}
+    __device__ __forceinline__ void at(uint32_t i, uint32_t* t, uint32_t* h) const {
+        const uint32_t row = __umulhi(i, recip);
+        const uint32_t p = i - row * P;
+        const uint32_t d = row / kPlanes;
+        const uint32_t pl = row - d * kPlanes;
+        *t = (d * S + p) * kPlanes + pl;
+        *h = sk_word(B, p / kC, pl, d, p % kC);
+    }
+};
+
+// Tile set-up.  A node this workgroup owns for the launch starts from its HBM
+// rows (loads batched four per lane so they overlap); a node shared with other
+// workgroups starts from zero and is merged with atomics.
+__device__ __forceinline__ void tile_load(uint32_t* __restrict__ tile,
+                                          const uint32_t* __restrict__ skn, const TileWalk& tw) {
+    for (uint32_t base = threadIdx.x; base < tw.n; base += 4 * blockDim.x) {
+        uint32_t v[4], t[4];
+#pragma unroll
+        for (uint32_t k = 0; k < 4; ++k) {
+            const uint32_t i = base + k * blockDim.x;
+            uint32_t h = 0;
+            t[k] = kNone;
+            if (i < tw.n) tw.at(i, &t[k], &h);
+            v[k] = i < tw.n ? skn[h] : 0u;
+        }
+#pragma unroll
+        for (uint32_t k = 0; k < 4; ++k)
+            if (t[k] != kNone) tile[t[k]] = v[k];
+    }
+}
+
+__device__ __forceinline__ void tile_zero(uint32_t* __restrict__ tile, uint32_t DL, uint32_t P) {
+    for (uint32_t i = threadIdx.x; i < kPlanes * DL * tile_stride(P); i += blockDim.x) tile[i] = 0;
+}
+
+// Write-back: owned nodes store the whole tile, shared nodes XOR non-zero words
+// in with atomics.
+__device__ __forceinline__ void tile_store(const uint32_t* __restrict__ tile,
+                                           uint32_t* __restrict__ skn, const TileWalk& tw,
+                                           bool shared) {
+    for (uint32_t i = threadIdx.x; i < tw.n; i += blockDim.x) {
+        uint32_t t, h;
+        tw.at(i, &t, &h);
+        const uint32_t val = tile[t];
+        if (!shared) skn[h] = val;
+        else if (val) atomicXor(&skn[h], val);
+    }
+}
+
+// Apply `count` entries to one node.  The J groups of P lanes each take a
+// contiguous share of the entries, read in 16-byte quads, eight entries per
+// iteration with the next eight in flight.  The first quads are issued before
+// the tile set-up so that both loads overlap; the barriers around the XOR
+// phase are inside (every thread of the workgroup calls this).
 template <bool kAllRows, typename Src>
-__device__ __forceinline__ void apply_entries(const Src& ent, uint32_t count, uint32_t node,
+__device__ __forceinline__ void apply_entries(const Src& ent, uint32_t count, const Lane& ln,
                                               const GraphDesc& g, uint32_t DL,
-                                              uint32_t* __restrict__ tile, bool shared) {
-    const uint32_t tid = threadIdx.x;
-    const uint32_t P = g.P, B = g.B;
-    const uint32_t J = blockDim.x / P;
-    const uint64_t rowp = (uint64_t)B * P;
-    uint32_t* skn = g.sk + (uint64_t)node * kPlanes * rowp;
-    if (tid < J * P) {
-        const uint32_t j = tid / P;
-        const uint32_t p = tid - j * P;
-        const PairSeeds s = load_pair_seeds(g.seeds, P, p);
-        const uint32_t Bm1 = B - 1;
-        const uint32_t row_bytes = tile_stride(P) * kPlanes * 4;
-        const uint32_t lane_bytes = p * kPlanes * 4;
-        uint8_t* tb = (uint8_t*)tile;
-#define GZ_XOR(x) xor_entry<kAllRows>((x), s, Bm1, DL, row_bytes, lane_bytes, tb, skn, rowp, P, p)
+                                              uint32_t* __restrict__ tile,
+                                              uint32_t* __restrict__ skn, bool shared) {
+    const TileWalk tw(g.P, g.B, DL);
+    uint32_t e = 0, ea = 0, e1 = 0;
+    bool pipe = false;
+    uint4 a = make_uint4(0, 0, 0, 0), b = a, c = a, d = a;
+    const uint32_t mis = ent.misalign();
+    if (ln.active) {
         // group ranges start on 16-byte boundaries of the source array
-        const uint32_t mis = ent.misalign();
+        const uint32_t J = ln.J, j = ln.j;
         const uint32_t head = (4u - mis) & 3u;
-        uint32_t e0, e1;
         if (count <= head + 8u * J) {
-            e0 = j == 0 ? 0u : count;
+            e = j == 0 ? 0u : count;
             e1 = count;
         } else {
             const uint32_t quads = (count - head) >> 2;
-            e0 = j == 0 ? 0u : head + 4u * (uint32_t)(((uint64_t)quads * j) / J);
+            e = j == 0 ? 0u : head + 4u * (uint32_t)(((uint64_t)quads * j) / J);
             e1 = j + 1 == J ? count : head + 4u * (uint32_t)(((uint64_t)quads * (j + 1)) / J);
         }
-        uint32_t e = e0;
-        // unaligned head (group 0 only) and short ranges
-        while (e < e1 && ((e + mis) & 3u)) GZ_XOR(ent.one(e++));
-        if (e + 8 <= e1) {
+        ea = min(e1, e + ((4u - ((e + mis) & 3u)) & 3u));
+        pipe = ea + 8 <= e1;
+        if (pipe) {
+            a = ent.quad(ea);
+            b = ent.quad(ea + 4);
+        }
+    }
+    if (shared) tile_zero(tile, DL, g.P);
+    else tile_load(tile, skn, tw);
+    __syncthreads();
+    if (ln.active) {
+        const uint32_t Bm1 = g.B - 1;
+        const uint32_t row_bytes = tile_stride(g.P) * kPlanes * 4;
+        const uint32_t plane_words = g.B * kC;
+        uint8_t* tb = (uint8_t*)tile;
+        uint32_t* skl = skn + ln.hbm_word;
+#define GZ_XOR(x) xor_entry<kAllRows>((x), ln, Bm1, DL, row_bytes, tb, skl, plane_words)
+        for (; e < ea; ++e) GZ_XOR(ent.one(e));  // unaligned head (group 0 only)
+        if (pipe) {
             // two register sets in turn: while one set is hashed the other is in flight
-            uint4 a = ent.quad(e), b = ent.quad(e + 4);
-            uint4 c, d;
             for (;;) {
                 const bool more1 = e + 16 <= e1;
                 if (more1) { c = ent.quad(e + 8); d = ent.quad(e + 12); }
@@ -390,48 +475,68 @@ __device__ __forceinline__ void apply_entries(const Src& ent, uint32_t count, ui
 #undef GZ_XOR
     }
     __syncthreads();
-    const uint32_t nw = blockDim.x >> 6, wave = tid >> 6, lane = tid & 63;
-    for (uint32_t row = wave; row < kPlanes * DL; row += nw) {
-        const uint32_t pl = row / DL, d = row - pl * DL;
-        uint32_t* dstrow = skn + pl * rowp + (uint64_t)d * P;
-        const uint32_t* srow = tile + d * tile_stride(P) * kPlanes + pl;
-        for (uint32_t q = lane; q < P; q += 64) {
-            const uint32_t val = srow[q * kPlanes];
-            if (val) {
-                if (shared) atomicXor(&dstrow[q], val);
-                else dstrow[q] ^= val;
-            }
-        }
-    }
+    tile_store(tile, skn, tw, shared);
+}
+
+// Rows an item keeps in LDS: an entry reaches depth d with probability
+// 2^-(d+1), so an item of `count` entries puts about count * 2^-(bitlen(count)+k)
+// entries per pair below row bitlen(count) + k.  Rows up to that depth stay in
+// LDS; the few deeper entries go straight to HBM with atomics, which is cheaper
+// than reading and writing mostly empty rows.
+constexpr uint32_t kDepthSlack = 3;
+
+__device__ __forceinline__ uint32_t item_rows(uint32_t count, uint32_t B, uint32_t lds_rows) {
+    const uint32_t need = (32u - __builtin_clz(count | 1u)) + kDepthSlack;
+    return min(min(need, B), lds_rows);
 }
 
 // Persistent fused sketch update over a device work list (all graphs of the
-// launch).  Each workgroup takes work items by atomic ticket until the list is
-// exhausted; every workgroup exits once the ticket passes the item count.
-template <bool kAllRows>
+// launch).  Each workgroup takes runs of consecutive work items by atomic
+// ticket until the list is exhausted (a run is one item when items are few,
+// longer when there are millions of small ones, so that the ticket counter is
+// not the bottleneck); every workgroup exits once the ticket passes the list.
+// The next item's descriptor is loaded while the current one is processed,
+// and the lane state is kept while the graph stays the same.  Items whose
+// tile holds every row take the branch-free path.
 __global__ __launch_bounds__(1024) void k_update(const WorkItem* __restrict__ items,
                                                  uint32_t* __restrict__ ctl,
                                                  const uint32_t* __restrict__ grouped,
                                                  const GraphDesc* __restrict__ gd,
                                                  uint32_t lds_rows) {
     extern __shared__ uint32_t tile[];
-    __shared__ uint32_t s_item;
+    __shared__ uint32_t s_ticket;
     if (ctl[2]) return;
     const uint32_t n_items = ctl[1];
+    const uint32_t run = max(1u, n_items / (gridDim.x * 16u));
+    uint32_t it = 0, it_end = 0, cur = kNone;
+    WorkItem nxt{};
+    GraphDesc g{};
+    Lane ln{};
     for (;;) {
-        if (threadIdx.x == 0) s_item = atomicAdd(&ctl[0], 1u);
-        __syncthreads();
-        const uint32_t it = uniform(s_item);
-        if (it >= n_items) break;
-        const WorkItem w = items[it];
-        const GraphDesc g = gd[w.graph];
-        const uint32_t DL = kAllRows ? g.B : min(lds_rows, g.B);
-        for (uint32_t i = threadIdx.x; i < kPlanes * DL * tile_stride(g.P); i += blockDim.x)
-            tile[i] = 0;
-        __syncthreads();
-        apply_entries<kAllRows>(GroupedEntries{grouped + w.begin}, w.count,
-                                w.gnode - g.node_base, g, DL, tile, w.shared != 0);
-        __syncthreads();
+        if (it == it_end) {
+            if (threadIdx.x == 0) s_ticket = atomicAdd(&ctl[0], 1u);
+            __syncthreads();
+            const uint32_t t = uniform(s_ticket);
+            if ((uint64_t)t * run >= n_items) break;
+            it = t * run;
+            it_end = min(n_items, it + run);
+            nxt = items[it];
+        }
+        const WorkItem w = nxt;
+        if (++it < it_end) nxt = items[it];  // in flight during this item
+        if (w.graph != cur) {
+            cur = w.graph;
+            g = gd[cur];
+            ln = make_lane(g);
+        }
+        const uint32_t DL = uniform(item_rows(w.count, g.B, lds_rows));
+        const GroupedEntries src{grouped + w.begin};
+        uint32_t* skn = g.sk + (uint64_t)(w.gnode - g.node_base) * kPlanes * g.B * g.P;
+        if (DL == g.B)
+            apply_entries<true>(src, w.count, ln, g, DL, tile, skn, w.shared != 0);
+        else
+            apply_entries<false>(src, w.count, ln, g, DL, tile, skn, w.shared != 0);
+        __syncthreads();  // the tile is reused by the next item
     }
 }
 
@@ -446,9 +551,9 @@ __global__ __launch_bounds__(1024) void k_update_node(const uint32_t* __restrict
     const uint32_t begin = blockIdx.x * chunk;
     const uint32_t cnt = min(chunk, count - begin);
     const uint32_t DL = min(lds_rows, g.B);
-    for (uint32_t i = threadIdx.x; i < kPlanes * DL * tile_stride(g.P); i += blockDim.x) tile[i] = 0;
-    __syncthreads();
-    apply_entries<false>(NeighbourEntries{nbrs + begin, node}, cnt, node, g, DL, tile,
+    const Lane ln = make_lane(g);
+    uint32_t* skn = g.sk + (uint64_t)node * kPlanes * g.B * g.P;
+    apply_entries<false>(NeighbourEntries{nbrs + begin, node}, cnt, ln, g, DL, tile, skn,
                          gridDim.x > 1);
 }
 
@@ -662,8 +767,7 @@ gz_status build_shape(gz_graph* const* gs, uint32_t G, const uint64_t* ranges, u
     L.pgrid = std::max(1u, tune.wgs_per_cu) * cus;
     GZ_TRY(set_smem_limit((const void*)k_group_count, L.gsmem));
     GZ_TRY(set_smem_limit((const void*)k_group_scatter, L.gsmem));
-    GZ_TRY(set_smem_limit(L.all_rows ? (const void*)k_update<true> : (const void*)k_update<false>,
-                          L.smem));
+    GZ_TRY(set_smem_limit((const void*)k_update, L.smem));
     return GZ_OK;
 }
 
@@ -702,12 +806,7 @@ gz_status launch_sequence(IngestScratch& S, const LaunchShape& L, hipStream_t st
         k_group_scatter<<<L.n_units, kGroupThreads, L.gsmem, stream>>>(S.args, S.units, S.descs,
                                                                        S.H, S.grouped, S.ctl);
     if (prof) GZ_HIP(hipEventRecord(prof->prof_ev[1], stream));
-    if (L.all_rows)
-        k_update<true><<<L.pgrid, L.wg, L.smem, stream>>>(S.items, S.ctl, S.grouped, S.descs,
-                                                          L.lds_rows);
-    else
-        k_update<false><<<L.pgrid, L.wg, L.smem, stream>>>(S.items, S.ctl, S.grouped, S.descs,
-                                                           L.lds_rows);
+    k_update<<<L.pgrid, L.wg, L.smem, stream>>>(S.items, S.ctl, S.grouped, S.descs, L.lds_rows);
     GZ_HIP(hipGetLastError());
     if (prof) {
         GZ_HIP(hipEventRecord(prof->prof_ev[2], stream));
@@ -775,7 +874,7 @@ gz_status ingest_fused(gz_graph* const* gs, uint32_t G, const uint64_t* offs_hos
     GZ_TRY(ensure_scratch(S, N, L.T, G, L.chunk, L.H_size, L.n_units, host_ptr));
 
     // order after earlier work on these graphs (e.g. a query on another stream)
-    for (uint32_t k = 0; k < G; ++k) GZ_HIP(hipStreamWaitEvent(stream, gs[k]->last, 0));
+    GZ_HIP(fence_wait(stream, gs, G));
 
     const uint32_t* dsrc = src;
     const uint32_t* ddst = dst;
@@ -789,7 +888,7 @@ gz_status ingest_fused(gz_graph* const* gs, uint32_t G, const uint64_t* offs_hos
     GZ_TRY(upload_shape(S, L, stream));
     GZ_HIP(hipEventRecord(S.copied_ev, stream));
     GZ_TRY(launch_sequence(S, L, stream, gs[0]->profiling ? gs[0] : nullptr));
-    for (uint32_t k = 0; k < G; ++k) GZ_HIP(hipEventRecord(gs[k]->last, stream));
+    GZ_HIP(fence_record(stream, gs, G));
 
     if (!(flags & GZ_ASYNC)) return check_call_error(S, stream);
     for (uint32_t k = 0; k < G; ++k) gs[k]->pending_error = true;  // flush must check
@@ -811,7 +910,7 @@ gz_status update_node_batch(gz_graph* g, uint32_t node, const uint32_t* nbrs, ui
                 return fail(GZ_EINVAL, "invalid neighbour (self-loop or id out of range)");
     }
     GZ_TRY(ensure_scratch(S, 0, g->V, 1, tune.chunk, 0, 0, false));
-    GZ_HIP(hipStreamWaitEvent(stream, g->last, 0));
+    GZ_HIP(fence_wait(stream, g));
     const uint32_t* d = nbrs;
     if (host_ptr) {
         if (count > S.cap_staging || !S.staging) {
@@ -845,7 +944,7 @@ gz_status update_node_batch(gz_graph* g, uint32_t node, const uint32_t* nbrs, ui
     k_update_node<<<grid, tune.wg_size, smem, stream>>>(d, (uint32_t)count, node, gd,
                                                           tune.lds_rows, chunk, errp);
     GZ_HIP(hipGetLastError());
-    GZ_HIP(hipEventRecord(g->last, stream));
+    GZ_HIP(fence_record(stream, g));
     if (!host_ptr && check) {
         if (!(flags & GZ_ASYNC)) {
             GZ_HIP(hipMemcpyAsync(S.h_err, S.ctl + 2, 4, hipMemcpyDeviceToHost, stream));
@@ -890,12 +989,8 @@ gz_status gz_plan_create(gz_graph* const* gs, uint32_t G, const uint64_t* caps, 
     if (!out || !gs || !caps || G == 0) return fail(GZ_EINVAL, "null argument");
     *out = nullptr;
     std::vector<uint64_t> ranges(G + 1, 0);
-    for (uint32_t k = 0; k < G; ++k) {
-        if (!gs[k]) return fail(GZ_EINVAL, "null graph handle");
-        for (uint32_t j = 0; j < k; ++j)
-            if (gs[j] == gs[k]) return fail(GZ_EINVAL, "graph listed twice");
-        ranges[k + 1] = ranges[k] + caps[k];
-    }
+    if (bad_graph_list(gs, G)) return fail(GZ_EINVAL, "null graph handle or graph listed twice");
+    for (uint32_t k = 0; k < G; ++k) ranges[k + 1] = ranges[k] + caps[k];
     if (ranges[G] >= (1ull << 31)) return fail(GZ_EINVAL, "capacities sum to 2^31 or more");
     gz_plan* p = new gz_plan();
     p->gs.assign(gs, gs + G);
@@ -952,14 +1047,14 @@ gz_status gz_plan_ingest(gz_plan* p, const uint64_t* offs, const uint32_t* src, 
     const uint64_t N = offs[G];
     if (N && (!src || !dst)) return fail(GZ_EINVAL, "null stream arrays");
     IngestScratch& S = p->S;
-    for (gz_graph* g : p->gs) GZ_HIP(hipStreamWaitEvent(stream, g->last, 0));
+    GZ_HIP(fence_wait(stream, p->gs.data(), G));
     GZ_TRY(upload_args(S, p->L, src, dst, N, p->offs_dev, stream));
     std::memcpy(p->h_offs, offs, sizeof(uint64_t) * (G + 1));
     GZ_HIP(hipMemcpyAsync(p->offs_dev, p->h_offs, sizeof(uint64_t) * (G + 1),
                           hipMemcpyHostToDevice, stream));
     GZ_HIP(hipEventRecord(S.copied_ev, stream));
     GZ_HIP(hipGraphLaunch(p->exec, stream));
-    for (gz_graph* g : p->gs) GZ_HIP(hipEventRecord(g->last, stream));
+    GZ_HIP(fence_record(stream, p->gs.data(), G));
     if (!(flags & GZ_ASYNC)) return check_call_error(S, stream);
     for (gz_graph* g : p->gs) g->pending_error = true;
     return GZ_OK;
@@ -970,7 +1065,7 @@ gz_status gz_plan_free(gz_plan* p) {
     if (p->cap_stream) hipStreamSynchronize(p->cap_stream);
     if (p->S.copied_ev) hipEventSynchronize(p->S.copied_ev);
     for (gz_graph* g : p->gs)
-        if (g && g->last) hipEventSynchronize(g->last);
+        if (g && g->last) hipEventSynchronize(g->last->ev);
     if (p->exec) hipGraphExecDestroy(p->exec);
     if (p->graph) hipGraphDestroy(p->graph);
     if (p->cap_stream) hipStreamDestroy(p->cap_stream);

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -24,14 +26,21 @@ enum SeedWord : uint32_t {
     S_CLO_MLO, S_CLO_MHI, S_CLO_ILO, S_CLO_IHI
 };
 
-// Per-graph data a kernel needs; kept in a device table for fused launches.
-//
-// Sketch words of node v (32-bit, "exact-depth" basis: row d holds the XOR of
+// Sketch words of a node (32-bit, "exact-depth" basis: row d holds the XOR of
 // the indices whose depth is exactly d, so each update touches one row per
-// column):  sk[((v * kPlanes + plane) * B + d) * P + p],  p = r * C + c.
-// Planes: 0 = alpha (indices are < 2^31, the high word is always zero),
-// 1 = gamma low word, 2 = gamma high word.  The nested rows of the paper are
-// the suffix XORs over d >= b of this basis (a linear, invertible change).
+// column).  Node v owns the block sk[v * 3 * B * P ...], P = R * C, laid out
+// round-major: word ((r * 3 + plane) * B + d) * C + c.  One round's rows of a
+// node are thus contiguous (3 * B * C words), which is what a Boruvka round
+// reads.  Planes: 0 = alpha (indices are < 2^31, the high word is always
+// zero), 1 = gamma low word, 2 = gamma high word.  The nested rows of the
+// paper are the suffix XORs over d >= b of this basis (a linear, invertible
+// change).
+__host__ __device__ __forceinline__ uint32_t sk_word(uint32_t B, uint32_t r, uint32_t plane,
+                                                     uint32_t d, uint32_t c) {
+    return ((r * kPlanes + plane) * B + d) * kC + c;
+}
+
+// Per-graph data a kernel needs; kept in a device table for fused launches.
 struct GraphDesc {
     uint32_t* sk;
     const uint32_t* seeds;
@@ -114,6 +123,17 @@ struct IngestScratch {
 
 struct QueryScratch;
 
+// Completion marker of the last device work submitted on a graph.  One call
+// over many graphs records a single marker that all of them share, so a fused
+// launch over thousands of graphs records, and later waits on, one event.
+struct Fence {
+    hipEvent_t ev = nullptr;
+    ~Fence() {
+        if (ev) hipEventDestroy(ev);
+    }
+};
+using FenceRef = std::shared_ptr<Fence>;
+
 }  // namespace gz
 
 struct gz_graph {
@@ -127,7 +147,7 @@ struct gz_graph {
     std::vector<uint64_t> seeds_host;  // [R][C][3][2]
     gz_tuning tuning{};
     hipStream_t qstream = nullptr;     // query stream
-    hipEvent_t last = nullptr;         // last submitted work on this graph
+    gz::FenceRef last;                 // last submitted work on this graph
     gz::IngestScratch ing;
     gz::QueryScratch* q = nullptr;
     bool pending_error = false;
@@ -149,6 +169,20 @@ gz_status hip_fail(hipError_t e, const char* what);
     } while (0)
 
 int device_cu_count();
+// true if a handle is null or listed twice
+inline bool bad_graph_list(gz_graph* const* gs, uint32_t G) {
+    std::vector<gz_graph*> v(gs, gs + G);
+    std::sort(v.begin(), v.end());
+    return (!v.empty() && v[0] == nullptr) || std::adjacent_find(v.begin(), v.end()) != v.end();
+}
+// make `stream` wait for the last work of every listed graph (one wait per
+// distinct marker), and mark the work enqueued next on `stream` as theirs
+hipError_t fence_wait(hipStream_t stream, gz_graph* const* gs, uint32_t G);
+hipError_t fence_record(hipStream_t stream, gz_graph* const* gs, uint32_t G);
+inline hipError_t fence_wait(hipStream_t stream, gz_graph* g) { return fence_wait(stream, &g, 1); }
+inline hipError_t fence_record(hipStream_t stream, gz_graph* g) {
+    return fence_record(stream, &g, 1);
+}
 hipError_t query_stream(gz_graph* g, hipStream_t* out);
 gz_tuning default_tuning(uint32_t P, uint32_t B);
 

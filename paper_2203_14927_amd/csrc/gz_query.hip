@@ -103,7 +103,7 @@ __global__ void k_q_reduce(uint32_t r, uint32_t T, const uint32_t* __restrict__ 
                            uint32_t* __restrict__ acc) {
     __shared__ uint32_t s_slot[kReduceRun];
     __shared__ const uint32_t* s_base[kReduceRun];
-    __shared__ uint32_t s_words[kReduceRun], s_P[kReduceRun];
+    __shared__ uint32_t s_words[kReduceRun];
     const uint32_t v0 = blockIdx.x * kReduceRun;
     const uint32_t n = min(T - v0, kReduceRun);
     if (threadIdx.x < n) {
@@ -111,22 +111,19 @@ __global__ void k_q_reduce(uint32_t r, uint32_t T, const uint32_t* __restrict__ 
         const uint32_t sl = slot[comp[v]];
         s_slot[threadIdx.x] = sl;
         const GraphDesc& g = gd[gof[v]];
-        s_base[threadIdx.x] = g.sk + (uint64_t)(v - g.node_base) * kPlanes * g.B * g.P + r * kC;
+        s_base[threadIdx.x] =
+            g.sk + (uint64_t)(v - g.node_base) * kPlanes * g.B * g.P + sk_word(g.B, r, 0, 0, 0);
         s_words[threadIdx.x] = kPlanes * g.B * kC;
-        s_P[threadIdx.x] = g.P;
     }
     __syncthreads();
     for (uint32_t w0 = 0; w0 < wpr; w0 += blockDim.x) {
+        // word w = (plane * B + d) * C + c of the round's contiguous rows
         const uint32_t w = w0 + threadIdx.x;
-        const uint32_t row = w >> 3;  // plane * B + d
-        const uint32_t c = w & (kC - 1);
         // all loads of the run first (independent, in flight together) ...
         uint32_t val[kReduceRun];
 #pragma unroll
         for (uint32_t i = 0; i < kReduceRun; ++i)
-            val[i] = (i < n && s_slot[i] != kNone && w < s_words[i])
-                         ? s_base[i][(uint64_t)row * s_P[i] + c]
-                         : 0u;
+            val[i] = (i < n && s_slot[i] != kNone && w < s_words[i]) ? s_base[i][w] : 0u;
         // ... then the XOR runs over equal components, one atomic per run
         uint32_t run = 0, run_slot = kNone;
 #pragma unroll
@@ -167,8 +164,8 @@ __global__ void k_q_query(uint32_t r, const uint32_t* __restrict__ A, const uint
         const uint32_t* in;
         uint64_t rs;
         if (kDirect) {
-            in = g.sk + (uint64_t)(X - g.node_base) * kPlanes * B * g.P + p;
-            rs = g.P;
+            in = g.sk + (uint64_t)(X - g.node_base) * kPlanes * B * g.P + sk_word(B, r, 0, 0, c);
+            rs = kC;
         } else {
             in = acc + (uint64_t)a * wpr + c;
             rs = kC;
@@ -526,7 +523,7 @@ gz_status boruvka(gz_graph* const* gs, uint32_t G, bool want_forest, QueryResult
 
     hipStream_t qs = nullptr;
     GZ_HIP(query_stream(gs[0], &qs));
-    for (uint32_t k = 0; k < G; ++k) GZ_HIP(hipStreamWaitEvent(qs, gs[k]->last, 0));
+    GZ_HIP(fence_wait(qs, gs, G));
     GZ_HIP(hipMemcpyAsync(Q->descs, descs.data(), sizeof(GraphDesc) * G, hipMemcpyHostToDevice, qs));
     const uint32_t tb = blocks_for(T, 256);
     k_q_init<<<(T + 255) / 256, 256, 0, qs>>>(T, Q->descs, G, Q->comp, Q->L, Q->done, Q->gof,

@@ -482,12 +482,16 @@ __device__ __forceinline__ void apply_entries(const Src& ent, uint32_t count, co
 // 2^-(d+1), so an item of `count` entries puts about count * 2^-(bitlen(count)+k)
 // entries per pair below row bitlen(count) + k.  Rows up to that depth stay in
 // LDS; the few deeper entries go straight to HBM with atomics, which is cheaper
-// than reading and writing mostly empty rows.
+// than reading and writing mostly empty rows.  Items large enough that the
+// extra rows cost little next to their entries keep every row (when the tile
+// allows) and take the branch-free path.
 constexpr uint32_t kDepthSlack = 3;
+constexpr uint32_t kAllRowsPerRow = 16;  // entries per extra row that justify all rows
 
 __device__ __forceinline__ uint32_t item_rows(uint32_t count, uint32_t B, uint32_t lds_rows) {
     const uint32_t need = (32u - __builtin_clz(count | 1u)) + kDepthSlack;
-    return min(min(need, B), lds_rows);
+    if (need >= B || (B <= lds_rows && count >= kAllRowsPerRow * (B - need))) return min(B, lds_rows);
+    return min(need, lds_rows);
 }
 
 // Persistent fused sketch update over a device work list (all graphs of the

@@ -208,6 +208,9 @@ def run_many(args) -> dict:
     log(f"[bench] many G(n,p): {len(streams)} graphs, {N} updates, "
         f"{sum(s.V for s in streams)} nodes (generated in {time.perf_counter() - t0:.1f} s)")
     graphs = [gz.Graph(s.V, seed=sd) for s, sd in zip(streams, seeds)]
+    if args.tuning:  # a fused launch takes the first graph's launch parameters
+        keys = ["wg_size", "lds_rows", "chunk", "wgs_per_cu", "group_blocks"]
+        graphs[0].set_tuning(**dict(zip(keys, (int(x) for x in args.tuning.split(",")))))
     sketch_bytes = sum(g.storage()[1] for g in graphs)
     plan = gz.Plan(graphs, [s.N for s in streams])
     stream_t = torch.cuda.current_stream()

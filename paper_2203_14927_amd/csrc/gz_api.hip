@@ -361,9 +361,8 @@ gz_status gz_query(gz_graph* g, uint32_t* labels, uint32_t* num_cc, uint32_t* ed
     if (st) return st;
     QueryResult res;
     gz_graph* gs[1] = {g};
-    st = boruvka(gs, 1, edges != nullptr || num_edges != nullptr, res);
+    st = boruvka(gs, 1, edges != nullptr || num_edges != nullptr, res, labels);
     if (st) return st;
-    if (labels) std::memcpy(labels, res.labels.data(), 4ull * g->V);
     if (num_cc) *num_cc = res.num_cc[0];
     if (edges) std::memcpy(edges, res.forest.data(), 4ull * res.forest.size());
     if (num_edges) *num_edges = res.forest.size() / 2;
@@ -390,9 +389,8 @@ gz_status gz_connected_components_multi(gz_graph* const* gs, uint32_t G, uint32_
         if (st) return st;
     }
     QueryResult res;
-    gz_status st = boruvka(gs, G, false, res);
+    gz_status st = boruvka(gs, G, false, res, labels);
     if (st) return st;
-    std::memcpy(labels, res.labels.data(), 4ull * res.labels.size());
     bool any_fail = false;
     for (uint32_t k = 0; k < G; ++k) {
         if (num_cc) num_cc[k] = res.num_cc[k];

@@ -129,6 +129,8 @@ __global__ void k_group_colscan(const GraphDesc* __restrict__ gd, uint32_t G, ui
     }
 }
 
+constexpr uint32_t kScatterBatch = 4;  // updates loaded per thread before placing any
+
 // pass 2: scatter every endpoint entry to its slot; LDS cursors start at the
 // scanned (node, chunk) prefix, so each chunk fills its own contiguous run
 __global__ __launch_bounds__(kGroupThreads) void k_group_scatter(
@@ -145,12 +147,223 @@ __global__ __launch_bounds__(kGroupThreads) void k_group_scatter(
     const uint32_t* hs = Hs + g.hoff + (uint64_t)u.c * g.V + r.lo;
     for (uint32_t k = threadIdx.x; k < r.size; k += blockDim.x) cur[k] = hs[k];
     __syncthreads();
-    for (uint64_t i = r.i0 + threadIdx.x; i < r.i1; i += blockDim.x) {
-        const uint32_t x = src[i], y = dst[i];
-        const uint32_t idx = edge_index(x, y);
-        const uint32_t xo = x - r.lo, yo = y - r.lo;
-        if (xo < r.size) grouped[atomicAdd(&cur[xo], 1u)] = idx;
-        if (yo < r.size) grouped[atomicAdd(&cur[yo], 1u)] = idx;
+    for (uint64_t i0 = r.i0; i0 < r.i1; i0 += (uint64_t)kScatterBatch * blockDim.x) {
+        uint32_t x[kScatterBatch], y[kScatterBatch];
+#pragma unroll
+        for (uint32_t k = 0; k < kScatterBatch; ++k) {
+            const uint64_t i = i0 + threadIdx.x + (uint64_t)k * blockDim.x;
+            x[k] = i < r.i1 ? src[i] : kNone;
+            y[k] = i < r.i1 ? dst[i] : kNone;
+        }
+#pragma unroll
+        for (uint32_t k = 0; k < kScatterBatch; ++k) {
+            if (x[k] == kNone) continue;
+            const uint32_t idx = edge_index(x[k], y[k]);
+            const uint32_t xo = x[k] - r.lo, yo = y[k] - r.lo;
+            if (xo < r.size) grouped[atomicAdd(&cur[xo], 1u)] = idx;
+            if (yo < r.size) grouped[atomicAdd(&cur[yo], 1u)] = idx;
+        }
+    }
+}
+
+// Two-pass placement for large single-graph calls.  The one-pass scatter
+// above writes every chunk's entries into V node runs, far more open lines
+// than L2 holds, so each 4-byte store becomes a partial-line HBM write.  Here
+// pass A moves each chunk's entries into at most kMaxBuckets buckets of 2^S
+// consecutive nodes (a bucket's region is the range its nodes take in the
+// final array, and every chunk fills its own sub-range of it), then pass B
+// places each bucket's entries into the runs of its nodes.  Both passes sort
+// a batch of entries by destination run in LDS first and then write each run's
+// share of the batch with consecutive stores, so HBM sees whole lines.  A
+// bucket entry packs the node's offset in its bucket with the other endpoint:
+// (fine << 16) | neighbour (node ids are below 2^16).
+constexpr uint32_t kMaxBuckets = 256;      // runs per block (keys of a batch)
+constexpr uint32_t kMaxBucketNodes = 256;  // 2^S: V <= 2^16 spread over <= 256 buckets
+constexpr uint32_t kSortPerThread = 8;     // entries per thread and batch
+constexpr uint32_t kSortBatch = kSortPerThread * kGroupThreads;
+
+struct SortSmem {
+    uint32_t val[kSortBatch];
+    uint8_t key[kSortBatch];
+    uint32_t cnt[kMaxBuckets];   // batch counts, then local cursors
+    uint32_t loff[kMaxBuckets];  // first local slot of each key
+    uint32_t gpos[kMaxBuckets];  // first global slot of each key's share
+    uint32_t total;
+};
+
+// Lanes of the wave holding the same key (key < 2^bits), found by voting on
+// the key's bits: the lowest of them (leader), this lane's rank among them and
+// their number.  Every lane of the wave must call it.
+struct Peers {
+    uint32_t leader, rank, count;
+};
+
+__device__ __forceinline__ Peers wave_peers(uint32_t key, uint32_t bits, bool valid) {
+    uint64_t m = __ballot(valid);
+    for (uint32_t b = 0; b < bits; ++b) {
+        const bool bit = (key >> b) & 1u;
+        const uint64_t ones = __ballot(bit);
+        m &= bit ? ones : ~ones;
+    }
+    const uint32_t lane = __lane_id();
+    Peers p;
+    p.leader = valid ? (uint32_t)__ffsll((unsigned long long)m) - 1u : lane;
+    p.rank = (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+    p.count = (uint32_t)__popcll(m);
+    return p;
+}
+
+// Append one batch of (key, value) pairs, kSortPerThread per thread, to the
+// runs of `out` whose next free slots are cur[key] (block-private LDS
+// cursors, advanced here).  LDS atomics are taken once per distinct key of a
+// wave, so hot keys do not serialise.  Every thread of the block must call it.
+__device__ __forceinline__ void batch_append(const uint32_t (&key)[kSortPerThread],
+                                             const uint32_t (&val)[kSortPerThread],
+                                             uint32_t valid_mask, uint32_t bits, uint32_t nkeys,
+                                             uint32_t* __restrict__ cur, SortSmem& sm,
+                                             uint32_t* __restrict__ out) {
+    const uint32_t tid = threadIdx.x;
+    const uint32_t lane = __lane_id();
+    for (uint32_t k = tid; k < nkeys; k += blockDim.x) sm.cnt[k] = 0;
+    __syncthreads();
+    Peers pe[kSortPerThread];
+#pragma unroll
+    for (uint32_t j = 0; j < kSortPerThread; ++j) {
+        const bool ok = (valid_mask >> j) & 1u;
+        pe[j] = wave_peers(key[j], bits, ok);
+        if (ok && lane == pe[j].leader) atomicAdd(&sm.cnt[key[j]], pe[j].count);
+    }
+    __syncthreads();
+    if (tid < 64) {  // one wave scans the (at most 256) counts, four per lane
+        uint32_t c[4], run = 0;
+#pragma unroll
+        for (uint32_t i = 0; i < 4; ++i) {
+            const uint32_t k = tid * 4 + i;
+            c[i] = k < nkeys ? sm.cnt[k] : 0u;
+            run += c[i];
+        }
+        uint32_t incl = run;
+        for (uint32_t off = 1; off < 64; off <<= 1) {
+            const uint32_t t = __shfl_up(incl, off);
+            if (tid >= off) incl += t;
+        }
+        uint32_t at = incl - run;
+#pragma unroll
+        for (uint32_t i = 0; i < 4; ++i) {
+            const uint32_t k = tid * 4 + i;
+            if (k < nkeys) {
+                sm.loff[k] = at;
+                sm.cnt[k] = at;  // local cursor
+                sm.gpos[k] = cur[k];
+                cur[k] += c[i];
+            }
+            at += c[i];
+        }
+        if (tid == 63) sm.total = incl;
+    }
+    __syncthreads();
+#pragma unroll
+    for (uint32_t j = 0; j < kSortPerThread; ++j) {
+        const bool ok = (valid_mask >> j) & 1u;
+        uint32_t base = 0;
+        if (ok && lane == pe[j].leader) base = atomicAdd(&sm.cnt[key[j]], pe[j].count);
+        base = __shfl(base, (int)pe[j].leader);
+        if (ok) {
+            const uint32_t p = base + pe[j].rank;
+            sm.val[p] = val[j];
+            sm.key[p] = (uint8_t)key[j];
+        }
+    }
+    __syncthreads();
+    const uint32_t total = sm.total;
+    for (uint32_t p = tid; p < total; p += blockDim.x) {
+        const uint32_t k = sm.key[p];
+        out[sm.gpos[k] + (p - sm.loff[k])] = sm.val[p];
+    }
+    __syncthreads();
+}
+
+// base[c * nbk + b], c <= nb: first slot of chunk c's entries of bucket b
+// (c = nb: the end of the bucket's region)
+__global__ void k_group_bucket_base(const uint32_t* __restrict__ H,
+                                    const uint32_t* __restrict__ nodeoff,
+                                    const uint32_t* __restrict__ counts, uint32_t V, uint32_t S,
+                                    uint32_t nbk, uint32_t nb, uint32_t* __restrict__ base) {
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (nb + 1) * nbk) return;
+    const uint32_t c = t / nbk, b = t - c * nbk;
+    const uint32_t v0 = b << S, v1 = min(V, (b + 1) << S);
+    uint32_t sum = nodeoff[v0];
+    if (c < nb) {
+        const uint32_t* row = H + (uint64_t)c * V;
+        for (uint32_t v = v0; v < v1; ++v) sum += row[v] - nodeoff[v];  // earlier chunks' entries
+    } else {
+        for (uint32_t v = v0; v < v1; ++v) sum += counts[v];
+    }
+    base[t] = sum;
+}
+
+// pass A: one block per chunk of the single graph's updates
+__global__ __launch_bounds__(kGroupThreads) void k_group_partition(
+    const IngestArgs* __restrict__ a, const GraphDesc* __restrict__ gd,
+    const uint32_t* __restrict__ base, uint32_t S, uint32_t nbk, uint32_t* __restrict__ tmp,
+    const uint32_t* __restrict__ ctl) {
+    __shared__ uint32_t cur[kMaxBuckets];
+    __shared__ SortSmem sm;
+    if (ctl[2]) return;
+    const GraphDesc g = gd[0];
+    const UnitRange r = unit_range(a, gd, GroupUnit{0, blockIdx.x, 0, 0}, g);
+    const uint32_t* __restrict__ src = a->src;
+    const uint32_t* __restrict__ dst = a->dst;
+    for (uint32_t k = threadIdx.x; k < nbk; k += blockDim.x) cur[k] = base[blockIdx.x * nbk + k];
+    __syncthreads();
+    const uint32_t mask = (1u << S) - 1u;
+    const uint32_t kbits = 32u - __builtin_clz((nbk - 1u) | 1u);  // bucket ids < 2^kbits
+    constexpr uint32_t kUpd = kSortPerThread / 2;                  // two entries per update
+    for (uint64_t i0 = r.i0; i0 < r.i1; i0 += (uint64_t)kUpd * blockDim.x) {
+        uint32_t key[kSortPerThread], val[kSortPerThread], ok = 0;
+#pragma unroll
+        for (uint32_t k = 0; k < kUpd; ++k) {
+            const uint64_t i = i0 + threadIdx.x + (uint64_t)k * blockDim.x;
+            const uint32_t x = i < r.i1 ? src[i] : 0u, y = i < r.i1 ? dst[i] : 0u;
+            if (i < r.i1) ok |= 3u << (2 * k);
+            key[2 * k] = x >> S;
+            val[2 * k] = ((x & mask) << 16) | y;
+            key[2 * k + 1] = y >> S;
+            val[2 * k + 1] = ((y & mask) << 16) | x;
+        }
+        batch_append(key, val, ok, kbits, nbk, cur, sm, tmp);
+    }
+}
+
+// pass B: one block per (bucket, range of cr chunks); node cursors start at the
+// runs of the range's first chunk, so blocks of one bucket fill disjoint slots
+__global__ __launch_bounds__(kGroupThreads) void k_group_place(
+    const uint32_t* __restrict__ base, const uint32_t* __restrict__ H, uint32_t V, uint32_t S,
+    uint32_t nbk, uint32_t nb, uint32_t cr, const uint32_t* __restrict__ tmp,
+    uint32_t* __restrict__ grouped, const uint32_t* __restrict__ ctl) {
+    __shared__ uint32_t cur[kMaxBucketNodes];
+    __shared__ SortSmem sm;
+    if (ctl[2]) return;
+    const uint32_t b = blockIdx.x % nbk;
+    const uint32_t c0 = (blockIdx.x / nbk) * cr;
+    const uint32_t c1 = min(nb, c0 + cr);
+    const uint32_t v0 = b << S, n = min(V, (b + 1) << S) - v0;
+    const uint32_t* row = H + (uint64_t)c0 * V + v0;
+    for (uint32_t f = threadIdx.x; f < n; f += blockDim.x) cur[f] = row[f];
+    __syncthreads();
+    const uint32_t e1 = base[c1 * nbk + b];
+    for (uint32_t e0 = base[c0 * nbk + b]; e0 < e1; e0 += kSortPerThread * blockDim.x) {
+        uint32_t key[kSortPerThread], val[kSortPerThread], ok = 0;
+#pragma unroll
+        for (uint32_t k = 0; k < kSortPerThread; ++k) {
+            const uint32_t e = e0 + threadIdx.x + k * blockDim.x;
+            const uint32_t w = e < e1 ? tmp[e] : 0u;
+            if (e < e1) ok |= 1u << k;
+            key[k] = w >> 16;
+            val[k] = edge_index(v0 + (w >> 16), w & 0xFFFFu);
+        }
+        batch_append(key, val, ok, S, n, cur, sm, grouped);
     }
 }
 
@@ -619,7 +832,8 @@ uint32_t grid_for(uint64_t n, uint32_t threads, uint32_t cap) {
     } while (0)
 
 gz_status ensure_scratch(IngestScratch& S, uint64_t N, uint32_t T, uint32_t G, uint32_t chunk,
-                         uint64_t H_size, uint32_t n_units, bool need_staging) {
+                         uint64_t H_size, uint32_t n_units, bool need_staging,
+                         uint64_t bucket_entries = 0, uint64_t bbase_words = 0) {
     int dev = 0;
     GZ_HIP(hipGetDevice(&dev));
     if (S.device != -1 && S.device != dev) return fail(GZ_EINVAL, "graph used on another device");
@@ -663,6 +877,14 @@ gz_status ensure_scratch(IngestScratch& S, uint64_t N, uint32_t T, uint32_t G, u
         GZ_TRY(grow(&S.items, items, "work items"));
         S.cap_items = items;
     }
+    if (bucket_entries && (bucket_entries > S.cap_buckets || !S.buckets)) {
+        GZ_TRY(grow(&S.buckets, bucket_entries, "bucket entries"));
+        S.cap_buckets = bucket_entries;
+    }
+    if (bbase_words && (bbase_words > S.cap_bbase || !S.bbase)) {
+        GZ_TRY(grow(&S.bbase, bbase_words, "bucket table"));
+        S.cap_bbase = bbase_words;
+    }
     if (need_staging && (2 * N > S.cap_staging || !S.staging)) {
         GZ_TRY(grow(&S.staging, 2 * N, "input staging"));
         S.cap_staging = 2 * N;
@@ -686,7 +908,7 @@ void free_ingest_scratch(IngestScratch& S) {
     hipFree(S.H); hipFree(S.units); hipFree(S.counts);
     hipFree(S.packed); hipFree(S.block_sums); hipFree(S.cursor);
     hipFree(S.grouped); hipFree(S.items); hipFree(S.ctl); hipFree(S.args); hipFree(S.offs);
-    hipFree(S.descs); hipFree(S.staging);
+    hipFree(S.descs); hipFree(S.staging); hipFree(S.buckets); hipFree(S.bbase);
     if (S.copied_ev) {
         hipEventSynchronize(S.copied_ev);
         hipEventDestroy(S.copied_ev);
@@ -711,6 +933,10 @@ struct LaunchShape {
     uint32_t wg = 0, DLmax = 1, Pmax = 0, chunk = 0, lds_rows = 0, group_chunk = 0;
     uint64_t H_size = 0, N = 0;
     bool all_rows = true;
+    // two-pass placement (single large graph): bucket shift, buckets, chunks,
+    // chunks per pass-B block, pass-B blocks
+    bool two_pass = false;
+    uint32_t bS = 0, nbk = 0, nbc = 0, bcr = 1, bblocks = 0;
     size_t gsmem = 0, smem = 0;
     std::vector<GraphDesc> descs;
     std::vector<GroupUnit> units;
@@ -765,6 +991,17 @@ gz_status build_shape(gz_graph* const* gs, uint32_t G, const uint64_t* ranges, u
         return fail(GZ_EINVAL, "workgroup smaller than pairs");
     L.T = (uint32_t)T;
     L.n_units = (uint32_t)L.units.size();
+    // single graphs large enough that one-pass placement would keep too many
+    // runs open per block take the two-pass placement
+    if (G == 1 && gs[0]->V > 4096 && L.descs[0].nb > 0) {
+        L.two_pass = true;
+        while (((gs[0]->V + (1u << L.bS) - 1) >> L.bS) > kMaxBuckets) ++L.bS;
+        L.nbk = (gs[0]->V + (1u << L.bS) - 1) >> L.bS;
+        L.nbc = L.descs[0].nb;
+        const uint32_t per_bucket = std::max(1u, 4 * cus / L.nbk);
+        L.bcr = (L.nbc + per_bucket - 1) / per_bucket;
+        L.bblocks = L.nbk * ((L.nbc + L.bcr - 1) / L.bcr);
+    }
     L.nblocks = (uint32_t)((T + kScanTile - 1) / kScanTile);
     L.gsmem = (size_t)L.range_max * 4;
     L.smem = update_smem_bytes(L.DLmax, L.Pmax);
@@ -806,9 +1043,18 @@ gz_status launch_sequence(IngestScratch& S, const LaunchShape& L, hipStream_t st
                                                          S.items, S.cursor, S.descs, L.G, S.ctl);
     k_group_colscan<<<grid_for(Tn, 256, 8192), 256, 0, stream>>>(S.descs, L.G, Tn, S.cursor,
                                                                   S.H);
-    if (L.n_units)
+    if (L.two_pass) {
+        const uint32_t nbase = (L.nbc + 1) * L.nbk;
+        k_group_bucket_base<<<(nbase + 255) / 256, 256, 0, stream>>>(
+            S.H, S.cursor, S.counts, Tn, L.bS, L.nbk, L.nbc, S.bbase);
+        k_group_partition<<<L.nbc, kGroupThreads, 0, stream>>>(S.args, S.descs, S.bbase, L.bS,
+                                                               L.nbk, S.buckets, S.ctl);
+        k_group_place<<<L.bblocks, kGroupThreads, 0, stream>>>(
+            S.bbase, S.H, Tn, L.bS, L.nbk, L.nbc, L.bcr, S.buckets, S.grouped, S.ctl);
+    } else if (L.n_units) {
         k_group_scatter<<<L.n_units, kGroupThreads, L.gsmem, stream>>>(S.args, S.units, S.descs,
                                                                        S.H, S.grouped, S.ctl);
+    }
     if (prof) GZ_HIP(hipEventRecord(prof->prof_ev[1], stream));
     k_update<<<L.pgrid, L.wg, L.smem, stream>>>(S.items, S.ctl, S.grouped, S.descs, L.lds_rows);
     GZ_HIP(hipGetLastError());
@@ -875,7 +1121,8 @@ gz_status ingest_fused(gz_graph* const* gs, uint32_t G, const uint64_t* offs_hos
     LaunchShape L;
     GZ_TRY(build_shape(gs, G, ranges.data(), N, L));
     const bool host_ptr = !(flags & GZ_DEVICE_PTR);
-    GZ_TRY(ensure_scratch(S, N, L.T, G, L.chunk, L.H_size, L.n_units, host_ptr));
+    GZ_TRY(ensure_scratch(S, N, L.T, G, L.chunk, L.H_size, L.n_units, host_ptr,
+                          L.two_pass ? 2 * N : 0, L.two_pass ? (uint64_t)(L.nbc + 1) * L.nbk : 0));
 
     // order after earlier work on these graphs (e.g. a query on another stream)
     GZ_HIP(fence_wait(stream, gs, G));
@@ -1000,8 +1247,10 @@ gz_status gz_plan_create(gz_graph* const* gs, uint32_t G, const uint64_t* caps, 
     p->gs.assign(gs, gs + G);
     p->caps.assign(caps, caps + G);
     gz_status st = build_shape(gs, G, ranges.data(), ranges[G], p->L);
-    if (!st) st = ensure_scratch(p->S, ranges[G], p->L.T, G, p->L.chunk, p->L.H_size,
-                                 p->L.n_units, false);
+    if (!st)
+        st = ensure_scratch(p->S, ranges[G], p->L.T, G, p->L.chunk, p->L.H_size, p->L.n_units,
+                            false, p->L.two_pass ? 2 * ranges[G] : 0,
+                            p->L.two_pass ? (uint64_t)(p->L.nbc + 1) * p->L.nbk : 0);
     hipError_t e = hipSuccess;
     if (!st) {
         e = hipMalloc((void**)&p->offs_dev, sizeof(uint64_t) * (G + 1));

@@ -103,6 +103,10 @@ struct IngestScratch {
     uint64_t* block_sums = nullptr; // scan partials
     uint32_t* cursor = nullptr;     // T: first grouped slot of every node
     uint32_t* grouped = nullptr;    // 2N edge indices grouped by endpoint
+    uint32_t* buckets = nullptr;    // 2N bucket entries of the two-pass placement
+    uint64_t cap_buckets = 0;
+    uint32_t* bbase = nullptr;      // (chunks + 1) x buckets region starts
+    uint64_t cap_bbase = 0;
     WorkItem* items = nullptr;
     uint32_t* ctl = nullptr;        // [0] ticket, [1] n_items, [2] call error, [3] sticky errors,
                                     // [4..7] always zero
@@ -197,14 +201,15 @@ IngestScratch& shared_ingest_scratch(int device, std::unique_lock<std::mutex>& l
 
 // query path (gz_query.hip)
 struct QueryResult {
-    std::vector<uint32_t> labels;    // sum V, local ids
     std::vector<uint32_t> num_cc;    // per graph
     std::vector<int32_t> status;     // per graph: GZ_OK / GZ_ESKETCH_FAIL
     std::vector<uint32_t> forest;    // per graph pairs, concatenated
     std::vector<uint64_t> forest_off;  // G+1 offsets into forest pairs
     uint32_t rounds = 0;
 };
-gz_status boruvka(gz_graph* const* gs, uint32_t G, bool want_forest, QueryResult& out);
+// labels_out (host, may be null): sum of V labels, local ids, graph after graph
+gz_status boruvka(gz_graph* const* gs, uint32_t G, bool want_forest, QueryResult& out,
+                  uint32_t* labels_out);
 void free_query_scratch(QueryScratch* q);
 
 // sketch export (gz_api.hip)

@@ -32,10 +32,16 @@ struct QueryScratch {
     uint32_t *fpairs = nullptr;
     uint64_t *forest = nullptr, *fsorted = nullptr;
     GraphDesc* descs = nullptr;
+    uint32_t* pos = nullptr;      // list position of every current component
+    uint32_t* host_na = nullptr;  // pinned: active components of each round
+    hipEvent_t round_ev[2] = {nullptr, nullptr};
 };
 
 // ctl words
-enum : uint32_t { Q_NL = 0, Q_NA = 1, Q_NL2 = 2, Q_NF = 3 };
+// Q_STOP is set at the end of the first round with no active component; every
+// round kernel then returns at once, so the host may enqueue rounds ahead of
+// the device without waiting for each round's outcome.
+enum : uint32_t { Q_NL = 0, Q_NA = 1, Q_NL2 = 2, Q_NF = 3, Q_STOP = 4, Q_ROUNDS = 5 };
 
 // ---------------------------------------------------------------- kernels --
 
@@ -59,6 +65,8 @@ __global__ void k_q_init(uint32_t T, const GraphDesc* __restrict__ gd, uint32_t 
         ctl[Q_NA] = 0;
         ctl[Q_NL2] = 0;
         ctl[Q_NF] = 0;
+        ctl[Q_STOP] = 0;
+        ctl[Q_ROUNDS] = 0;
     }
     if (v < T) {
         comp[v] = v;
@@ -72,10 +80,13 @@ __global__ void k_q_select(uint32_t r, const uint32_t* __restrict__ L, uint32_t*
                            const uint32_t* __restrict__ done, const uint32_t* __restrict__ gof,
                            const GraphDesc* __restrict__ gd, uint32_t* __restrict__ slot,
                            uint32_t* __restrict__ A, uint32_t* __restrict__ hook,
-                           uint32_t* __restrict__ newlab, uint32_t* __restrict__ merged) {
+                           uint32_t* __restrict__ newlab, uint32_t* __restrict__ merged,
+                           uint32_t* __restrict__ pos) {
+    if (ctl[Q_STOP]) return;
     const uint32_t nL = ctl[Q_NL];
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nL; i += gridDim.x * blockDim.x) {
         const uint32_t X = L[i];
+        pos[X] = i;
         hook[X] = kNone;
         newlab[X] = kNone;
         merged[X] = 0;
@@ -90,22 +101,30 @@ __global__ void k_q_select(uint32_t r, const uint32_t* __restrict__ L, uint32_t*
 }
 
 // XOR the round-r rows of every active component's members into the
-// component's accumulator [slot][plane][d][c].  A workgroup walks a run of
+// component's accumulator [slot][plane][d][c].  A workgroup walks a span of
 // consecutive node ids, one thread per accumulator word, keeping a running XOR
 // while the component stays the same and flushing it with one atomic per word
 // when it changes (components are large after the first round, so consecutive
-// ids mostly share one).
+// ids mostly share one and a span costs one atomic per word).  Loads are issued
+// kReduceRun nodes at a time so that they are in flight together; blockIdx.y
+// picks the block of accumulator words, so a round runs ceil(T / kReduceSpan)
+// x ceil(words / blockDim) workgroups.
 constexpr uint32_t kReduceRun = 16;
+constexpr uint32_t kReduceSpan = 64;
 
-__global__ void k_q_reduce(uint32_t r, uint32_t T, const uint32_t* __restrict__ comp,
-                           const uint32_t* __restrict__ slot, const uint32_t* __restrict__ gof,
-                           const GraphDesc* __restrict__ gd, uint32_t wpr,
-                           uint32_t* __restrict__ acc) {
-    __shared__ uint32_t s_slot[kReduceRun];
-    __shared__ const uint32_t* s_base[kReduceRun];
-    __shared__ uint32_t s_words[kReduceRun];
-    const uint32_t v0 = blockIdx.x * kReduceRun;
-    const uint32_t n = min(T - v0, kReduceRun);
+__global__ __launch_bounds__(256) void k_q_reduce(uint32_t r, uint32_t T,
+                                                  const uint32_t* __restrict__ comp,
+                                                  const uint32_t* __restrict__ slot,
+                                                  const uint32_t* __restrict__ gof,
+                                                  const GraphDesc* __restrict__ gd, uint32_t wpr,
+                                                  uint32_t* __restrict__ acc,
+                                                  const uint32_t* __restrict__ ctl) {
+    __shared__ uint32_t s_slot[kReduceSpan];
+    __shared__ const uint32_t* s_base[kReduceSpan];
+    __shared__ uint32_t s_words[kReduceSpan];
+    if (ctl[Q_STOP]) return;
+    const uint32_t v0 = blockIdx.x * kReduceSpan;
+    const uint32_t n = min(T - v0, kReduceSpan);
     if (threadIdx.x < n) {
         const uint32_t v = v0 + threadIdx.x;
         const uint32_t sl = slot[comp[v]];
@@ -116,40 +135,60 @@ __global__ void k_q_reduce(uint32_t r, uint32_t T, const uint32_t* __restrict__ 
         s_words[threadIdx.x] = kPlanes * g.B * kC;
     }
     __syncthreads();
-    for (uint32_t w0 = 0; w0 < wpr; w0 += blockDim.x) {
+    {
         // word w = (plane * B + d) * C + c of the round's contiguous rows
-        const uint32_t w = w0 + threadIdx.x;
-        // all loads of the run first (independent, in flight together) ...
-        uint32_t val[kReduceRun];
-#pragma unroll
-        for (uint32_t i = 0; i < kReduceRun; ++i)
-            val[i] = (i < n && s_slot[i] != kNone && w < s_words[i]) ? s_base[i][w] : 0u;
-        // ... then the XOR runs over equal components, one atomic per run
+        const uint32_t w = blockIdx.y * blockDim.x + threadIdx.x;
         uint32_t run = 0, run_slot = kNone;
+        for (uint32_t b = 0; b < n; b += kReduceRun) {
+            uint32_t val[kReduceRun];
 #pragma unroll
-        for (uint32_t i = 0; i < kReduceRun; ++i) {
-            const uint32_t sl = i < n ? s_slot[i] : kNone;
-            if (sl != run_slot) {
-                if (run_slot != kNone && run) atomicXor(&acc[(uint64_t)run_slot * wpr + w], run);
-                run = 0;
-                run_slot = sl;
+            for (uint32_t i = 0; i < kReduceRun; ++i) {
+                const uint32_t j = b + i;
+                val[i] = (j < n && s_slot[j] != kNone && w < s_words[j]) ? s_base[j][w] : 0u;
             }
-            run ^= val[i];
+#pragma unroll
+            for (uint32_t i = 0; i < kReduceRun; ++i) {
+                const uint32_t j = b + i;
+                const uint32_t sl = j < n ? s_slot[j] : kNone;
+                if (sl != run_slot) {
+                    if (run_slot != kNone && run)
+                        atomicXor(&acc[(uint64_t)run_slot * wpr + w], run);
+                    run = 0;
+                    run_slot = sl;
+                }
+                run ^= val[i];
+            }
         }
         if (run_slot != kNone && run) atomicXor(&acc[(uint64_t)run_slot * wpr + w], run);
     }
 }
 
+// zero the accumulators of this round's active components (count on the device)
+__global__ void k_q_zero_acc(const uint32_t* __restrict__ ctl, uint32_t wpr,
+                             uint32_t* __restrict__ acc) {
+    if (ctl[Q_STOP]) return;
+    const uint64_t n = (uint64_t)ctl[Q_NA] * wpr;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        acc[i] = 0;
+}
+
 // kDirect: every component is a single node (first round), read its sketch
 // rows in place instead of an accumulator
+// One component per 8 lanes (one lane per column): scan the column's nested
+// rows from the deepest up (suffix XOR of the exact-depth basis) and keep the
+// first good bucket in column-major, row-ascending order; ZERO marks the
+// component done, FAIL leaves it without a hook.
 template <bool kDirect>
-__global__ void k_q_query(uint32_t r, const uint32_t* __restrict__ A, const uint32_t* __restrict__ ctl,
-                          const uint32_t* __restrict__ acc, uint32_t wpr,
-                          const uint32_t* __restrict__ gof, const GraphDesc* __restrict__ gd,
-                          const uint32_t* __restrict__ comp, uint32_t* __restrict__ hook,
-                          uint32_t* __restrict__ hedge, uint32_t* __restrict__ done) {
-    const uint32_t nA = ctl[Q_NA];
-    const uint32_t gtid = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void query_component(uint32_t r, uint32_t gtid, uint32_t nA,
+                                                const uint32_t* __restrict__ A,
+                                                const uint32_t* __restrict__ acc, uint32_t wpr,
+                                                const uint32_t* __restrict__ gof,
+                                                const GraphDesc* __restrict__ gd,
+                                                const uint32_t* __restrict__ comp,
+                                                uint32_t* __restrict__ hook,
+                                                uint32_t* __restrict__ hedge,
+                                                uint32_t* __restrict__ done) {
     const uint32_t a = gtid >> 3;
     const uint32_t c = gtid & 7;
     const bool valid = a < nA;
@@ -162,19 +201,15 @@ __global__ void k_q_query(uint32_t r, const uint32_t* __restrict__ A, const uint
         const uint32_t B = g.B;
         // word (plane, row b) of column c: stride between rows of one plane
         const uint32_t* in;
-        uint64_t rs;
-        if (kDirect) {
+        if (kDirect)
             in = g.sk + (uint64_t)(X - g.node_base) * kPlanes * B * g.P + sk_word(B, r, 0, 0, c);
-            rs = kC;
-        } else {
+        else
             in = acc + (uint64_t)a * wpr + c;
-            rs = kC;
-        }
         uint32_t al = 0, glo = 0, ghi = 0;
         for (int b = (int)B - 1; b >= 0; --b) {
-            al ^= in[(uint64_t)(0 * B + b) * rs];
-            glo ^= in[(uint64_t)(1 * B + b) * rs];
-            ghi ^= in[(uint64_t)(2 * B + b) * rs];
+            al ^= in[(0 * B + b) * kC];
+            glo ^= in[(1 * B + b) * kC];
+            ghi ^= in[(2 * B + b) * kC];
             if (al | glo | ghi) {
                 nonempty = 1;
                 if ((uint64_t)al < g.n && chk_lo(s, al) == glo && chk_hi(s, al) == ghi) {
@@ -208,10 +243,30 @@ __global__ void k_q_query(uint32_t r, const uint32_t* __restrict__ A, const uint
     hedge[X] = alpha_best;
 }
 
+// kDirect: every component is a single node (first round), read its sketch
+// rows in place instead of an accumulator.  The grid strides over the active
+// components (their count is known only on the device).
+template <bool kDirect>
+__global__ void k_q_query(uint32_t r, const uint32_t* __restrict__ A, const uint32_t* __restrict__ ctl,
+                          const uint32_t* __restrict__ acc, uint32_t wpr,
+                          const uint32_t* __restrict__ gof, const GraphDesc* __restrict__ gd,
+                          const uint32_t* __restrict__ comp, uint32_t* __restrict__ hook,
+                          uint32_t* __restrict__ hedge, uint32_t* __restrict__ done) {
+    if (ctl[Q_STOP]) return;
+    const uint32_t nA = ctl[Q_NA];
+    const uint64_t lanes = (uint64_t)nA * 8;
+    for (uint64_t base = (uint64_t)blockIdx.x * blockDim.x; base < lanes;
+         base += (uint64_t)gridDim.x * blockDim.x)
+        query_component<kDirect>(r, (uint32_t)(base + threadIdx.x), nA, A, acc, wpr, gof, gd, comp,
+                                 hook, hedge, done);
+}
+
 __global__ void k_q_double_init(const uint32_t* __restrict__ L, const uint32_t* __restrict__ ctl,
                                 const uint32_t* __restrict__ hook, uint32_t* __restrict__ s,
-                                uint32_t* __restrict__ m) {
+                                uint32_t* __restrict__ m, uint32_t lds_cap) {
+    if (ctl[Q_STOP]) return;
     const uint32_t nL = ctl[Q_NL];
+    if (nL <= lds_cap) return;
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nL; i += gridDim.x * blockDim.x) {
         const uint32_t X = L[i];
         const uint32_t h = hook[X];
@@ -223,8 +278,11 @@ __global__ void k_q_double_init(const uint32_t* __restrict__ L, const uint32_t* 
 // one doubling step: s2 = s o s, m2 = min(m, m o s)
 __global__ void k_q_double(const uint32_t* __restrict__ L, const uint32_t* __restrict__ ctl,
                            const uint32_t* __restrict__ s, const uint32_t* __restrict__ m,
-                           uint32_t* __restrict__ s2, uint32_t* __restrict__ m2) {
+                           uint32_t* __restrict__ s2, uint32_t* __restrict__ m2,
+                           uint32_t lds_cap) {
+    if (ctl[Q_STOP]) return;
     const uint32_t nL = ctl[Q_NL];
+    if (nL <= lds_cap) return;
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nL; i += gridDim.x * blockDim.x) {
         const uint32_t X = L[i];
         const uint32_t y = s[X];
@@ -239,8 +297,11 @@ __global__ void k_q_double(const uint32_t* __restrict__ L, const uint32_t* __res
 __global__ __launch_bounds__(1024) void k_q_double_all(const uint32_t* __restrict__ L,
                                                         const uint32_t* __restrict__ ctl,
                                                         uint32_t K, uint32_t* s, uint32_t* m,
-                                                        uint32_t* s2, uint32_t* m2) {
+                                                        uint32_t* s2, uint32_t* m2,
+                                                        uint32_t lds_cap) {
+    if (ctl[Q_STOP]) return;
     const uint32_t nL = ctl[Q_NL];
+    if (nL <= lds_cap) return;
     for (uint32_t k = 0; k < K; ++k) {
         uint32_t* si = (k & 1) ? s2 : s;
         uint32_t* mi = (k & 1) ? m2 : m;
@@ -263,11 +324,61 @@ __global__ void k_q_root(const uint32_t* __restrict__ L, uint32_t* __restrict__ 
                          const uint32_t* __restrict__ hook, const uint32_t* __restrict__ hedge,
                          const uint32_t* __restrict__ gof, uint32_t* __restrict__ rootOf,
                          uint32_t* __restrict__ newlab, uint32_t* __restrict__ merged,
-                         uint64_t* __restrict__ forest) {
+                         uint64_t* __restrict__ forest, uint32_t lds_cap) {
+    if (ctl[Q_STOP]) return;
     const uint32_t nL = ctl[Q_NL];
+    if (nL <= lds_cap) return;
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nL; i += gridDim.x * blockDim.x) {
         const uint32_t X = L[i];
         const uint32_t R = m[s[X]];
+        rootOf[X] = R;
+        atomicMin(&newlab[R], X);
+        if (hook[X] != kNone && X != R) {
+            merged[R] = 1;
+            const uint32_t f = atomicAdd(&ctl[Q_NF], 1u);
+            forest[f] = ((uint64_t)gof[X] << 32) | hedge[X];
+        }
+    }
+}
+
+// The same resolution for lists of up to kLdsResolve components in one
+// workgroup, with the successor and running minimum packed in one 64-bit LDS
+// word per component (list position of the successor, minimum id above it).
+// Doubling runs in place: a lane reads its successor's (position, minimum)
+// pair in one access, so its word always describes one path segment
+// [X, successor) and its minimum; in-place steps advance at least as far as
+// synchronous ones, so K steps still reach every terminal cycle.
+constexpr uint32_t kLdsResolve = 16384;
+
+__global__ __launch_bounds__(1024) void k_q_resolve_lds(
+    const uint32_t* __restrict__ L, uint32_t* __restrict__ ctl, uint32_t K,
+    const uint32_t* __restrict__ hook, const uint32_t* __restrict__ hedge,
+    const uint32_t* __restrict__ pos, const uint32_t* __restrict__ gof,
+    uint32_t* __restrict__ rootOf, uint32_t* __restrict__ newlab, uint32_t* __restrict__ merged,
+    uint64_t* __restrict__ forest) {
+    __shared__ uint64_t st[kLdsResolve];
+    if (ctl[Q_STOP]) return;
+    const uint32_t nL = ctl[Q_NL];
+    if (nL > kLdsResolve) return;
+    for (uint32_t i = threadIdx.x; i < nL; i += blockDim.x) {
+        const uint32_t X = L[i];
+        const uint32_t h = hook[X];
+        const uint32_t sp = h == kNone ? i : pos[h];
+        st[i] = ((uint64_t)X << 32) | sp;
+    }
+    __syncthreads();
+    for (uint32_t k = 0; k < K; ++k) {
+        for (uint32_t i = threadIdx.x; i < nL; i += blockDim.x) {
+            const uint64_t v = st[i];
+            const uint64_t w = st[(uint32_t)v];
+            const uint64_t mn = min(v >> 32, w >> 32);
+            st[i] = (mn << 32) | (uint32_t)w;
+        }
+        __syncthreads();
+    }
+    for (uint32_t i = threadIdx.x; i < nL; i += blockDim.x) {
+        const uint32_t X = L[i];
+        const uint32_t R = (uint32_t)(st[(uint32_t)st[i]] >> 32);
         rootOf[X] = R;
         atomicMin(&newlab[R], X);
         if (hook[X] != kNone && X != R) {
@@ -283,6 +394,7 @@ __global__ void k_q_newcomps(const uint32_t* __restrict__ L, uint32_t* __restric
                              const uint32_t* __restrict__ newlab,
                              const uint32_t* __restrict__ merged, uint32_t* __restrict__ done,
                              uint32_t* __restrict__ L2) {
+    if (ctl[Q_STOP]) return;
     const uint32_t nL = ctl[Q_NL];
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nL; i += gridDim.x * blockDim.x) {
         const uint32_t X = L[i];
@@ -296,15 +408,34 @@ __global__ void k_q_newcomps(const uint32_t* __restrict__ L, uint32_t* __restric
 
 __global__ void k_q_relabel(uint32_t T, uint32_t* __restrict__ comp,
                             const uint32_t* __restrict__ rootOf,
-                            const uint32_t* __restrict__ newlab) {
+                            const uint32_t* __restrict__ newlab,
+                            const uint32_t* __restrict__ ctl) {
+    if (ctl[Q_STOP]) return;
     for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < T; v += gridDim.x * blockDim.x)
         comp[v] = newlab[rootOf[comp[v]]];
 }
 
-__global__ void k_q_next_round(uint32_t* __restrict__ ctl) {
+// the next round's component list is this round's new list
+__global__ void k_q_copy_list(uint32_t* __restrict__ L, const uint32_t* __restrict__ L2,
+                              const uint32_t* __restrict__ ctl) {
+    if (ctl[Q_STOP]) return;
+    const uint32_t n = ctl[Q_NL2];
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+        L[i] = L2[i];
+}
+
+// End of round r: publish its active count to the host (pinned memory) and
+// stop once a round had none.
+__global__ void k_q_next_round(uint32_t r, uint32_t* __restrict__ ctl,
+                               uint32_t* __restrict__ host_na) {
+    if (ctl[Q_STOP]) return;
+    const uint32_t na = ctl[Q_NA];
+    if (na == 0) ctl[Q_STOP] = 1;
+    else ctl[Q_ROUNDS] = r + 1;
     ctl[Q_NL] = ctl[Q_NL2];
     ctl[Q_NL2] = 0;
     ctl[Q_NA] = 0;
+    host_na[r] = na;
 }
 
 __global__ void k_q_finish(const uint32_t* __restrict__ L, const uint32_t* __restrict__ ctl,
@@ -358,6 +489,7 @@ __global__ void k_q_fscatter(const uint64_t* __restrict__ forest, const uint32_t
 }
 
 constexpr uint32_t kRankThreads = 256;
+constexpr uint32_t kMaxRounds = 64;  // R <= 17 for V <= 2^16
 constexpr uint32_t kSingleBlockDoubling = 65536;  // component lists up to this length
 
 __global__ __launch_bounds__(kRankThreads) void k_q_frank(const uint64_t* __restrict__ keys,
@@ -423,13 +555,16 @@ gz_status ensure_query(QueryScratch& Q, uint32_t T, uint32_t G, uint32_t wpr) {
     if (T > Q.cap_nodes || !Q.comp) {
         uint32_t** arrs[] = {&Q.comp, &Q.L, &Q.L2, &Q.A, &Q.slot, &Q.done, &Q.hook, &Q.hedge,
                              &Q.s, &Q.s2, &Q.m, &Q.m2, &Q.rootOf, &Q.newlab, &Q.merged, &Q.gof,
-                             &Q.labels};
+                             &Q.labels, &Q.pos};
         for (auto a : arrs)
             if ((st = qalloc(a, T))) return st;
         if ((st = qalloc(&Q.fpairs, 2ull * T))) return st;
         if ((st = qalloc(&Q.forest, T))) return st;
         if ((st = qalloc(&Q.fsorted, T))) return st;
         if (!Q.ctl && (st = qalloc(&Q.ctl, 8))) return st;
+        if (!Q.host_na) GZ_HIP(hipHostMalloc((void**)&Q.host_na, 4 * kMaxRounds, hipHostMallocDefault));
+        for (hipEvent_t& e : Q.round_ev)
+            if (!e) GZ_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
         Q.cap_nodes = T;
         Q.cap_wpr = 0;
     }
@@ -469,15 +604,27 @@ void free_query_scratch(QueryScratch* q) {
     uint32_t* arrs[] = {q->comp, q->L, q->L2, q->A, q->slot, q->done, q->hook, q->hedge, q->s,
                         q->s2, q->m, q->m2, q->rootOf, q->newlab, q->merged, q->gof, q->acc,
                         q->ctl, q->labels, q->gcount, q->gfail, q->foff, q->fcur, q->fpairs,
-                        q->fcnt};
+                        q->fcnt, q->pos};
     for (auto a : arrs) hipFree(a);
     hipFree(q->forest);
     hipFree(q->fsorted);
     hipFree(q->descs);
+    if (q->host_na) hipHostFree(q->host_na);
+    for (hipEvent_t e : q->round_ev)
+        if (e) hipEventDestroy(e);
     delete q;
 }
 
-gz_status boruvka(gz_graph* const* gs, uint32_t G, bool want_forest, QueryResult& out) {
+// Fused queries over several graphs share one scratch per device.
+QueryScratch& shared_query_scratch(int device, std::unique_lock<std::mutex>& lock) {
+    static std::mutex mu;
+    static std::vector<QueryScratch> per_dev(64);
+    lock = std::unique_lock<std::mutex>(mu);
+    return per_dev[(size_t)device % per_dev.size()];
+}
+
+gz_status boruvka(gz_graph* const* gs, uint32_t G, bool want_forest, QueryResult& out,
+                  uint32_t* labels_out) {
     if (G == 0) return fail(GZ_EINVAL, "no graphs");
     std::vector<GraphDesc> descs(G);
     uint64_t T64 = 0;
@@ -500,24 +647,21 @@ gz_status boruvka(gz_graph* const* gs, uint32_t G, bool want_forest, QueryResult
         Vmax = std::max(Vmax, g->V);
     }
     if (T64 >= (1ull << 31)) return fail(GZ_EINVAL, "too many nodes in one query");
+    if (Rmax > kMaxRounds) return fail(GZ_EINVAL, "too many rounds");
     const uint32_t T = (uint32_t)T64;
     const uint32_t wpr = kPlanes * Bmax * kC;
 
-    // single graphs keep their scratch; fused queries use a temporary one
+    // single graphs keep their own scratch; fused queries share one per device
+    std::unique_lock<std::mutex> lock;
     QueryScratch* Q = nullptr;
-    bool owned = false;
     if (G == 1) {
         if (!gs[0]->q) gs[0]->q = new QueryScratch();
         Q = gs[0]->q;
     } else {
-        Q = new QueryScratch();
-        owned = true;
+        int dev = 0;
+        GZ_HIP(hipGetDevice(&dev));
+        Q = &shared_query_scratch(dev, lock);
     }
-    struct Guard {
-        QueryScratch* q;
-        bool own;
-        ~Guard() { if (own) free_query_scratch(q); }
-    } guard{Q, owned};
     gz_status st = ensure_query(*Q, T, G, wpr);
     if (st) return st;
 
@@ -533,63 +677,74 @@ gz_status boruvka(gz_graph* const* gs, uint32_t G, bool want_forest, QueryResult
     uint32_t* s2 = Q->s2;
     uint32_t* m = Q->m;
     uint32_t* m2 = Q->m2;
-    uint32_t* L = Q->L;
-    uint32_t* L2 = Q->L2;
-    uint32_t rounds = 0;
+    const uint32_t qgrid = blocks_for(8ull * T, 256);
+    const uint32_t zgrid = 2048;
+    const uint32_t rgrid = (T + kReduceSpan - 1) / kReduceSpan;
+    for (uint32_t r = 0; r < Rmax; ++r) Q->host_na[r] = kNone;
+    // Rounds are enqueued ahead of the device; before round r the host waits
+    // for the end of round r-2 and stops once a round had no active component
+    // (kernels of rounds after that one return at once).
     for (uint32_t r = 0; r < Rmax; ++r) {
-        k_q_select<<<tb, 256, 0, qs>>>(r, L, Q->ctl, Q->done, Q->gof, Q->descs, Q->slot, Q->A,
-                                       Q->hook, Q->newlab, Q->merged);
-        uint32_t nA = 0;
-        GZ_HIP(hipMemcpyAsync(&nA, Q->ctl + Q_NA, 4, hipMemcpyDeviceToHost, qs));
-        GZ_HIP(hipStreamSynchronize(qs));
-        if (nA == 0) break;
-        rounds = r + 1;
+        if (r >= 2) {
+            GZ_HIP(hipEventSynchronize(Q->round_ev[r & 1]));
+            if (Q->host_na[r - 2] == 0) break;
+        }
+        k_q_select<<<tb, 256, 0, qs>>>(r, Q->L, Q->ctl, Q->done, Q->gof, Q->descs, Q->slot, Q->A,
+                                       Q->hook, Q->newlab, Q->merged, Q->pos);
         if (r == 0) {
-            k_q_query<true><<<(nA * 8 + 255) / 256, 256, 0, qs>>>(
-                r, Q->A, Q->ctl, Q->acc, wpr, Q->gof, Q->descs, Q->comp, Q->hook, Q->hedge,
-                Q->done);
+            k_q_query<true><<<qgrid, 256, 0, qs>>>(r, Q->A, Q->ctl, Q->acc, wpr, Q->gof,
+                                                   Q->descs, Q->comp, Q->hook, Q->hedge, Q->done);
         } else {
-            GZ_HIP(hipMemsetAsync(Q->acc, 0, (size_t)nA * wpr * 4, qs));
-            const uint32_t rgrid = (T + kReduceRun - 1) / kReduceRun;
-            k_q_reduce<<<rgrid, 256, 0, qs>>>(r, T, Q->comp, Q->slot, Q->gof, Q->descs, wpr,
-                                              Q->acc);
-            k_q_query<false><<<(nA * 8 + 255) / 256, 256, 0, qs>>>(
-                r, Q->A, Q->ctl, Q->acc, wpr, Q->gof, Q->descs, Q->comp, Q->hook, Q->hedge,
-                Q->done);
+            k_q_zero_acc<<<zgrid, 256, 0, qs>>>(Q->ctl, wpr, Q->acc);
+            k_q_reduce<<<dim3(rgrid, (wpr + 255) / 256), 256, 0, qs>>>(
+                r, T, Q->comp, Q->slot, Q->gof, Q->descs, wpr, Q->acc, Q->ctl);
+            k_q_query<false><<<qgrid, 256, 0, qs>>>(r, Q->A, Q->ctl, Q->acc, wpr, Q->gof,
+                                                    Q->descs, Q->comp, Q->hook, Q->hedge,
+                                                    Q->done);
         }
-        k_q_double_init<<<tb, 256, 0, qs>>>(L, Q->ctl, Q->hook, s, m);
-        if (T <= kSingleBlockDoubling) {
-            k_q_double_all<<<1, 1024, 0, qs>>>(L, Q->ctl, K, s, m, s2, m2);
-            if (K & 1) {
-                std::swap(s, s2);
-                std::swap(m, m2);
+        // hooks -> roots: in LDS when the list is short (on the device's count),
+        // else by grid-wide pointer doubling
+        k_q_resolve_lds<<<1, 1024, 0, qs>>>(Q->L, Q->ctl, K, Q->hook, Q->hedge, Q->pos, Q->gof,
+                                            Q->rootOf, Q->newlab, Q->merged, Q->forest);
+        if (T > kLdsResolve) {
+            const uint32_t cap = kLdsResolve;
+            k_q_double_init<<<tb, 256, 0, qs>>>(Q->L, Q->ctl, Q->hook, s, m, cap);
+            if (T <= kSingleBlockDoubling) {
+                k_q_double_all<<<1, 1024, 0, qs>>>(Q->L, Q->ctl, K, s, m, s2, m2, cap);
+                if (K & 1) {
+                    std::swap(s, s2);
+                    std::swap(m, m2);
+                }
+            } else {
+                for (uint32_t k = 0; k < K; ++k) {
+                    k_q_double<<<tb, 256, 0, qs>>>(Q->L, Q->ctl, s, m, s2, m2, cap);
+                    std::swap(s, s2);
+                    std::swap(m, m2);
+                }
             }
-        } else {
-            for (uint32_t k = 0; k < K; ++k) {
-                k_q_double<<<tb, 256, 0, qs>>>(L, Q->ctl, s, m, s2, m2);
-                std::swap(s, s2);
-                std::swap(m, m2);
-            }
+            k_q_root<<<tb, 256, 0, qs>>>(Q->L, Q->ctl, s, m, Q->hook, Q->hedge, Q->gof, Q->rootOf,
+                                         Q->newlab, Q->merged, Q->forest, cap);
         }
-        k_q_root<<<tb, 256, 0, qs>>>(L, Q->ctl, s, m, Q->hook, Q->hedge, Q->gof, Q->rootOf,
-                                     Q->newlab, Q->merged, Q->forest);
-        k_q_newcomps<<<tb, 256, 0, qs>>>(L, Q->ctl, Q->rootOf, Q->newlab, Q->merged, Q->done, L2);
-        k_q_relabel<<<tb, 256, 0, qs>>>(T, Q->comp, Q->rootOf, Q->newlab);
-        k_q_next_round<<<1, 1, 0, qs>>>(Q->ctl);
-        std::swap(L, L2);
+        k_q_newcomps<<<tb, 256, 0, qs>>>(Q->L, Q->ctl, Q->rootOf, Q->newlab, Q->merged, Q->done,
+                                         Q->L2);
+        k_q_relabel<<<tb, 256, 0, qs>>>(T, Q->comp, Q->rootOf, Q->newlab, Q->ctl);
+        k_q_copy_list<<<tb, 256, 0, qs>>>(Q->L, Q->L2, Q->ctl);
+        k_q_next_round<<<1, 1, 0, qs>>>(r, Q->ctl, Q->host_na);
+        GZ_HIP(hipEventRecord(Q->round_ev[r & 1], qs));
     }
     GZ_HIP(hipMemsetAsync(Q->gcount, 0, 4ull * G, qs));
     GZ_HIP(hipMemsetAsync(Q->gfail, 0, 4ull * G, qs));
-    k_q_finish<<<tb, 256, 0, qs>>>(L, Q->ctl, Q->done, Q->gof, Q->gcount, Q->gfail);
-    k_q_labels<<<tb, 256, 0, qs>>>(T, Q->comp, Q->gof, Q->descs, Q->labels);
-    out.labels.resize(T);
+    k_q_finish<<<tb, 256, 0, qs>>>(Q->L, Q->ctl, Q->done, Q->gof, Q->gcount, Q->gfail);
+    if (labels_out) {
+        k_q_labels<<<tb, 256, 0, qs>>>(T, Q->comp, Q->gof, Q->descs, Q->labels);
+        GZ_HIP(hipMemcpyAsync(labels_out, Q->labels, 4ull * T, hipMemcpyDeviceToHost, qs));
+    }
     out.num_cc.resize(G);
     std::vector<uint32_t> gfail(G);
-    GZ_HIP(hipMemcpyAsync(out.labels.data(), Q->labels, 4ull * T, hipMemcpyDeviceToHost, qs));
     GZ_HIP(hipMemcpyAsync(out.num_cc.data(), Q->gcount, 4ull * G, hipMemcpyDeviceToHost, qs));
     GZ_HIP(hipMemcpyAsync(gfail.data(), Q->gfail, 4ull * G, hipMemcpyDeviceToHost, qs));
-    uint32_t nF = 0;
-    GZ_HIP(hipMemcpyAsync(&nF, Q->ctl + Q_NF, 4, hipMemcpyDeviceToHost, qs));
+    uint32_t tail[Q_ROUNDS + 1] = {};
+    GZ_HIP(hipMemcpyAsync(tail, Q->ctl, sizeof(tail), hipMemcpyDeviceToHost, qs));
     if (want_forest) {
         GZ_HIP(hipMemsetAsync(Q->fcnt, 0, 4ull * G, qs));
         k_q_fcount<<<tb, 256, 0, qs>>>(Q->forest, Q->ctl, Q->fcnt);
@@ -600,6 +755,7 @@ gz_status boruvka(gz_graph* const* gs, uint32_t G, bool want_forest, QueryResult
     }
     GZ_HIP(hipGetLastError());
     GZ_HIP(hipStreamSynchronize(qs));
+    const uint32_t nF = tail[Q_NF];
     if (want_forest) {
         std::vector<uint32_t> foff(G + 1);
         GZ_HIP(hipMemcpy(foff.data(), Q->foff, 4ull * (G + 1), hipMemcpyDeviceToHost));
@@ -613,7 +769,7 @@ gz_status boruvka(gz_graph* const* gs, uint32_t G, bool want_forest, QueryResult
     }
     out.status.resize(G);
     for (uint32_t k = 0; k < G; ++k) out.status[k] = gfail[k] ? GZ_ESKETCH_FAIL : GZ_OK;
-    out.rounds = rounds;
+    out.rounds = tail[Q_ROUNDS];
     return GZ_OK;
 }
 

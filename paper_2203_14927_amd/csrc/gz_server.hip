@@ -1,11 +1,12 @@
 // Serving: many graph sessions share one GPU.  A server thread admits
-// sessions while their sketches fit an HBM budget, packs the update batches
+// sessions while their sketches fit an HBM budget and packs the update batches
 // queued by all admitted sessions into one fused multi-graph ingest per tick
 // (continuous batching: a batch submitted while a tick runs joins the next
-// one), and answers connectivity queries on each session's own stream, so that
-// queries overlap the next tick's ingest on the device.  Requests of one
-// session are applied in submission order; a query sees exactly the updates
-// submitted before it.
+// one).  Connectivity queries go to a small pool of query threads, each query
+// on its session's own stream, so that queries of different sessions and the
+// next ticks' ingests overlap on the device.  Requests of one session are
+// applied in submission order: a query is taken once the session's earlier
+// batches are applied, and the session's later batches wait for the query.
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
@@ -18,6 +19,8 @@
 #include "gz_internal.h"
 
 namespace {
+
+constexpr int kQueryThreads = 4;
 
 uint64_t now_ns() {
     return (uint64_t)std::chrono::duration_cast<std::chrono::nanoseconds>(
@@ -58,7 +61,9 @@ struct gz_session {
     uint64_t bytes = 0;
     gz_graph* g = nullptr;            // non-null once admitted
     std::deque<gz_ticket*> queue;     // submitted, not yet taken by a tick
-    uint32_t inflight = 0;            // taken, not yet completed
+    uint32_t inflight = 0;            // taken, not yet completed (batches and query)
+    uint32_t upd_inflight = 0;        // batches taken, not yet completed
+    bool query_busy = false;          // a query of this session is running
     bool closing = false;
     std::vector<uint32_t> scratch_labels;
 };
@@ -67,7 +72,11 @@ struct gz_server {
     int device = 0;
     uint64_t budget = 0, used = 0, tick_cap = 0;
     std::mutex mu;
-    std::condition_variable cv_work, cv_done;
+    std::condition_variable cv_work, cv_done, cv_query;
+    std::deque<gz_ticket*> qq;        // queries handed to the query threads
+    std::vector<std::thread> query_threads;
+    uint32_t queries_running = 0;
+    bool stop_queries = false;
     std::vector<gz_session*> admitted;
     std::deque<gz_session*> waiting;
     std::thread worker;
@@ -95,6 +104,7 @@ struct Tick {
 
 void take_tick(gz_server* S, Tick& t) {
     for (gz_session* s : S->admitted) {
+        if (s->query_busy) continue;  // later batches wait for the running query
         std::vector<gz_ticket*> mine;
         while (!s->queue.empty() && s->queue.front()->kind == gz_ticket::UPDATES) {
             gz_ticket* k = s->queue.front();
@@ -106,12 +116,17 @@ void take_tick(gz_server* S, Tick& t) {
         if (!mine.empty()) {
             t.upd_sessions.push_back(s);
             s->inflight += (uint32_t)mine.size();
+            s->upd_inflight += (uint32_t)mine.size();
             t.upd.push_back(std::move(mine));
         }
-        if (!s->queue.empty() && s->queue.front()->kind == gz_ticket::QUERY) {
+        // a query runs once every earlier batch of its session is applied
+        if (!s->queue.empty() && s->queue.front()->kind == gz_ticket::QUERY &&
+            s->upd_inflight == 0) {
             t.queries.push_back(s->queue.front());
             s->queue.pop_front();
             s->inflight += 1;
+            s->query_busy = true;
+            S->queries_running++;
         }
     }
 }
@@ -131,7 +146,9 @@ void admit(gz_server* S) {
 
 bool has_work(gz_server* S) {
     for (gz_session* s : S->admitted)
-        if (!s->queue.empty()) return true;
+        if (!s->query_busy && !s->queue.empty() &&
+            (s->queue.front()->kind == gz_ticket::UPDATES || s->upd_inflight == 0))
+            return true;
     if (!S->waiting.empty() && S->used + S->waiting.front()->bytes <= S->budget) return true;
     return false;
 }
@@ -142,7 +159,46 @@ void complete(gz_server* S, gz_ticket* k, gz_status st) {
     std::lock_guard<std::mutex> lk(S->mu);
     k->done = true;
     k->sess->inflight -= 1;
+    if (k->kind == gz_ticket::UPDATES) k->sess->upd_inflight -= 1;
     S->cv_done.notify_all();
+}
+
+// Query threads: run the queries the tick loop hands over, each on its
+// session's query stream; the session's next batches are released afterwards.
+void query_main(gz_server* S) {
+    hipSetDevice(S->device);
+    for (;;) {
+        gz_ticket* k = nullptr;
+        {
+            std::unique_lock<std::mutex> lk(S->mu);
+            S->cv_query.wait(lk, [&] { return S->stop_queries || !S->qq.empty(); });
+            if (S->qq.empty()) return;
+            k = S->qq.front();
+            S->qq.pop_front();
+        }
+        gz_session* s = k->sess;
+        k->res.start_ns = now_ns();
+        uint32_t* out = k->labels;
+        if (!out) {
+            s->scratch_labels.resize(s->V);
+            out = s->scratch_labels.data();
+        }
+        uint32_t ncc = 0;
+        const gz_status q = gz_connected_components(s->g, out, &ncc);
+        k->res.num_cc = ncc;
+        k->res.status = q;
+        k->res.done_ns = now_ns();
+        {
+            std::lock_guard<std::mutex> lk(S->mu);
+            S->stats.queries++;
+            k->done = true;
+            s->inflight -= 1;
+            s->query_busy = false;
+            S->queries_running--;
+            S->cv_done.notify_all();
+        }
+        S->cv_work.notify_one();
+    }
 }
 
 void worker_main(gz_server* S) {
@@ -159,9 +215,11 @@ void worker_main(gz_server* S) {
             std::unique_lock<std::mutex> lk(S->mu);
             admit(S);
             if (prev.buf < 0)
-                S->cv_work.wait(lk, [&] { return S->stop || has_work(S); });
+                S->cv_work.wait(lk, [&] {
+                    return (S->stop && S->queries_running == 0) || has_work(S);
+                });
             admit(S);
-            if (S->stop && !has_work(S) && prev.buf < 0) break;
+            if (S->stop && !has_work(S) && prev.buf < 0 && S->queries_running == 0) break;
             take_tick(S, t);
         }
         // 1. launch this tick's fused ingest (host staging -> device, async)
@@ -208,23 +266,13 @@ void worker_main(gz_server* S) {
                 }
             }
         }
-        // 2. queries, each on its session's stream (overlapping this tick's ingest)
-        for (gz_ticket* k : t.queries) {
-            gz_session* s = k->sess;
-            k->res.start_ns = now_ns();
-            uint32_t* out = k->labels;
-            if (!out) {
-                s->scratch_labels.resize(s->V);
-                out = s->scratch_labels.data();
-            }
-            uint32_t ncc = 0;
-            gz_status q = gz_connected_components(s->g, out, &ncc);
-            k->res.num_cc = ncc;
+        // 2. hand the queries to the query threads
+        if (!t.queries.empty()) {
             {
                 std::lock_guard<std::mutex> lk(S->mu);
-                S->stats.queries++;
+                for (gz_ticket* k : t.queries) S->qq.push_back(k);
             }
-            complete(S, k, q);
+            S->cv_query.notify_all();
         }
         // 3. the previous tick's updates are applied once its ingest is done
         if (prev.buf >= 0) {
@@ -270,6 +318,7 @@ gz_status gz_server_create(uint64_t hbm_budget, uint64_t tick_updates, gz_server
     S->tick_cap = tick_updates ? tick_updates : (16ull << 20);
     S->stats.hbm_budget = hbm_budget;
     S->worker = std::thread(worker_main, S);
+    for (int i = 0; i < kQueryThreads; ++i) S->query_threads.emplace_back(query_main, S);
     *out = S;
     return GZ_OK;
 }
@@ -367,7 +416,7 @@ gz_status gz_session_close(gz_session* s) {
         S->cv_done.notify_all();
     }
     S->cv_work.notify_one();
-    S->cv_done.wait(lk, [&] { return s->queue.empty() && s->inflight == 0; });
+    S->cv_done.wait(lk, [&] { return s->queue.empty() && s->inflight == 0 && !s->query_busy; });
     auto it = std::find(S->admitted.begin(), S->admitted.end(), s);
     if (it != S->admitted.end()) {
         S->admitted.erase(it);
@@ -401,6 +450,12 @@ gz_status gz_server_destroy(gz_server* S) {
     }
     S->cv_work.notify_one();
     S->worker.join();
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->stop_queries = true;
+    }
+    S->cv_query.notify_all();
+    for (std::thread& t : S->query_threads) t.join();
     std::vector<gz_session*> left;
     for (gz_session* s : S->admitted) left.push_back(s);
     for (gz_session* s : S->waiting) left.push_back(s);

@@ -219,3 +219,34 @@ def test_many_graphs_fused_equals_separate(gz):
         ost, olabels, _, _ = O.connected_components()
         assert stt[k] == gz_status_of(ost) and (labels[k] == olabels).all()
         assert_query_equal(g, O)
+
+
+def test_two_pass_grouping_full_parity(gz):
+    """V > 4096 takes the two-pass placement: 150k updates over many grouping chunks."""
+    s = _stream(5000, 150000, 21)
+    g = gz.Graph(5000, seed=4242)
+    g.ingest(to_dev(s.src), to_dev(s.dst))
+    O = oracle_for(s, 4242)
+    assert_sketch_equal(g, O)
+    assert_query_equal(g, O)
+
+
+@pytest.mark.parametrize("V,n,seed", [(4097, 40000, 22), (65536, 300000, 23)])
+def test_two_pass_grouping_edge_shapes(gz, V, n, seed):
+    """Smallest two-pass graph and the largest V (256 buckets of 256 nodes): sampled node
+    sketches against the oracle, labels against union-find on the final graph."""
+    s = _stream(V, n, seed)
+    g = gz.Graph(V, seed=seed)
+    g.ingest(to_dev(s.src), to_dev(s.dst))
+    rng = np.random.default_rng(seed)
+    nodes = sorted(set(rng.choice(V, 24, replace=False).tolist()) | {0, V - 1, int(s.src[0])})
+    O = oracle.Oracle(V, seed)
+    O.ingest_nodes(s.src, s.dst, nodes)
+    for v in nodes:
+        a, b = g.export(v, v + 1)
+        assert (a[0] == O.alpha[v]).all() and (b[0] == O.gamma[v]).all(), f"node {v}"
+    st, labels, ncc, forest = g.query()
+    assert st == gz.GZ_OK
+    ref, fu, fv = final_labels(s)
+    assert (labels == ref).all()
+    check_forest_valid(V, labels, forest, fu, fv)

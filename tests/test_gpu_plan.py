@@ -93,3 +93,24 @@ def test_plan_with_empty_graphs_and_empty_calls(gz):
     a, b = g_empty.export()
     assert not a.any() and not b.any()
     plan.close()
+
+
+def test_single_large_graph_plan_replays(gz):
+    """A captured plan over one graph with V > 4096 (two-pass placement), replayed on
+    three parts of a stream, equals one eager ingest of the whole stream."""
+    import torch
+
+    s = workloads.uniform_stream(6000, 120000, 30000, seed=31)
+    g_eager, g_plan = gz.Graph(6000, seed=12), gz.Graph(6000, seed=12)
+    g_eager.ingest(to_dev(s.src), to_dev(s.dst))
+    parts = 3
+    plan = gz.Plan([g_plan], [s.N // parts + 1])
+    for k in range(parts):
+        lo, hi = s.N * k // parts, s.N * (k + 1) // parts
+        plan.ingest([0, hi - lo], to_dev(s.src[lo:hi]), to_dev(s.dst[lo:hi]))
+        torch.cuda.synchronize()
+        g_plan.connected_components()  # eager work between replays
+    a1, b1 = g_eager.export()
+    a2, b2 = g_plan.export()
+    assert (a1 == a2).all() and (b1 == b2).all()
+    plan.close()

@@ -85,7 +85,7 @@ def traffic_from_profile(kernel_src_hash: str):
 
 
 def kernel_source_hash() -> str:
-    p = os.path.join(ROOT, "paper_2203_14927_amd", "csrc", "gz_ingest.hip")
+    p = os.path.join(ROOT, "paper_2203_14927_amd", "csrc", "gz_update.hip")
     return hashlib.sha256(open(p, "rb").read()).hexdigest()
 
 

@@ -40,6 +40,9 @@ __host__ __device__ __forceinline__ uint32_t sk_word(uint32_t B, uint32_t r, uin
     return ((r * kPlanes + plane) * B + d) * kC + c;
 }
 
+// Row stride of an LDS node tile: P rounded up to a multiple of 64 words.
+__host__ __device__ __forceinline__ uint32_t tile_stride(uint32_t P) { return (P + 63u) & ~63u; }
+
 // Per-graph data a kernel needs; kept in a device table for fused launches.
 struct GraphDesc {
     uint32_t* sk;
@@ -126,6 +129,14 @@ struct IngestScratch {
 };
 
 struct QueryScratch;
+
+// sketch update kernels (gz_update.hip)
+__global__ void k_update(const WorkItem* __restrict__ items, uint32_t* __restrict__ ctl,
+                         const uint32_t* __restrict__ grouped, const GraphDesc* __restrict__ gd,
+                         uint32_t lds_rows);
+__global__ void k_update_node(const uint32_t* __restrict__ nbrs, uint32_t count, uint32_t node,
+                              GraphDesc g, uint32_t lds_rows, uint32_t chunk,
+                              const uint32_t* __restrict__ err);
 
 // Completion marker of the last device work submitted on a graph.  One call
 // over many graphs records a single marker that all of them share, so a fused

@@ -420,6 +420,17 @@ def run_single(args) -> dict:
         qms.append((time.perf_counter() - q0) * 1e3)
     cc_query_ms = statistics.median(qms)
 
+    # the same ingest from host (pageable numpy) arrays: includes the PCIe copy
+    hms = []
+    for _ in range(3):
+        g.reset()
+        torch.cuda.synchronize()
+        h0 = time.perf_counter()
+        g.ingest(stream.src, stream.dst)
+        torch.cuda.synchronize()
+        hms.append((time.perf_counter() - h0) * 1e3)
+    host_ingest_ms = statistics.median(hms)
+
     upd_ms = statistics.median(p["update_ms"] for p in profs)
     grp_ms = statistics.median(p["group_ms"] for p in profs)
     ing_ms = statistics.median(p["ingest_ms"] for p in profs)
@@ -448,6 +459,7 @@ def run_single(args) -> dict:
         "group_ms": grp_ms,
         "update_kernel_ms": upd_ms,
         "cc_query_ms": cc_query_ms,
+        "host_input_ingest_updates_per_s": stream.N / (host_ingest_ms * 1e-3),
         "components": ncc,
         "tuning": g.tuning,
         "tuning_source": tuned_from,

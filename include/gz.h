@@ -283,10 +283,12 @@ gz_status gz_profile_last(gz_graph* g, gz_profile* out);
  *   tick packs the update batches queued by every admitted session (up to
  *   `tick_updates` updates, 0 = 16 Mi) into one fused multi-graph ingest
  *   (continuous batching: batches submitted while a tick runs join the next);
- *   a query runs once every update submitted before it in its session has been
- *   issued, on that session's stream, overlapping the next tick's ingest.
- *   A session's requests take effect in submission order, so every result is
- *   the one the session would get alone.  All calls are thread-safe.
+ *   a query runs on one of four query threads, on its session's own stream,
+ *   once every batch submitted before it in its session has been applied, and
+ *   the session's later batches wait for it; queries of different sessions
+ *   and the next ticks' ingests overlap on the device.  A session's requests
+ *   take effect in submission order, so every result is the one the session
+ *   would get alone.  All calls are thread-safe.
  * gz_submit_updates copies the host arrays (validated: GZ_EINVAL applies
  *   nothing); gz_submit_query writes V labels into `labels` (host, nullable)
  *   before its ticket completes.  gz_wait blocks until the ticket completes,

@@ -80,10 +80,21 @@ typedef struct gz_graph gz_graph;
 
 /* Optional overrides; zero fields keep the shape rule / library defaults. */
 typedef struct gz_config {
-    uint32_t rounds;      /* R override (tests force failures with a small R); 0 = rule */
-    uint32_t reserved0;
-    uint64_t reserved1;
+    uint32_t rounds;        /* R override (tests force failures with a small R); 0 = rule */
+    uint32_t tier;          /* GZ_TIER_HBM (0) or GZ_TIER_HOST (1) */
+    uint64_t staging_bytes; /* host tier: device bytes of the two slab buffers (0 = 512 MiB) */
 } gz_config;
+
+/* Sketch residency.  GZ_TIER_HOST keeps a graph's sketches in pinned host
+ * memory (capacity beyond HBM; the paper keeps sketches on disk when they
+ * outgrow RAM, Sec. 4): an ingest call is grouped on the device, then the node
+ * blocks that received entries stream through two device slab buffers (copy in,
+ * update, copy out, overlapped); a query copies one round of every node into
+ * HBM per Boruvka round.  Results are bit-identical to GZ_TIER_HBM.  Host-tier
+ * graphs take single-graph calls only (gz_ingest_multi, plans and fused
+ * queries over several graphs return GZ_EINVAL for them). */
+#define GZ_TIER_HBM 0u
+#define GZ_TIER_HOST 1u
 
 /* Kernel launch parameters of the ingest path; gz_autotune picks them. */
 typedef struct gz_tuning {
@@ -242,7 +253,8 @@ gz_status gz_export_sketches(gz_graph* g, uint32_t node_lo, uint32_t node_hi, ui
                              uint64_t* gamma);
 
 /* Device address and byte size of the internal sketch array (for tools that
- * measure traffic); the layout is private. */
+ * measure traffic); the layout is private.  A host-tier graph has no device
+ * sketch array: *dev_ptr receives NULL, *bytes the size of its host copy. */
 gz_status gz_sketch_storage(const gz_graph* g, void** dev_ptr, uint64_t* bytes);
 
 /* ------------------------------------------------------------------------

@@ -32,8 +32,12 @@ class GzError(RuntimeError):
 
 
 class gz_config(ctypes.Structure):
-    _fields_ = [("rounds", ctypes.c_uint32), ("reserved0", ctypes.c_uint32),
-                ("reserved1", ctypes.c_uint64)]
+    _fields_ = [("rounds", ctypes.c_uint32), ("tier", ctypes.c_uint32),
+                ("staging_bytes", ctypes.c_uint64)]
+
+
+GZ_TIER_HBM = 0
+GZ_TIER_HOST = 1
 
 
 class gz_tuning(ctypes.Structure):
@@ -177,12 +181,13 @@ def _u32_arg(x):
 
 
 class Graph:
-    """One graph's device-resident node sketches."""
+    """One graph's node sketches (in HBM, or in pinned host memory with host_tier=True)."""
 
-    def __init__(self, V: int, seed: int, rounds: int = 0):
+    def __init__(self, V: int, seed: int, rounds: int = 0, host_tier: bool = False,
+                 staging_bytes: int = 0):
         L = lib()
         h = ctypes.c_void_p()
-        cfg = gz_config(rounds, 0, 0)
+        cfg = gz_config(rounds, GZ_TIER_HOST if host_tier else GZ_TIER_HBM, int(staging_bytes))
         check(L.gz_sketch_init(ctypes.byref(h), V, seed & 0xFFFFFFFFFFFFFFFF, ctypes.byref(cfg)))
         self._h = h
         self.seed = seed

@@ -125,15 +125,17 @@ gz_tuning default_tuning(uint32_t P, uint32_t B) {
 }
 
 // exact-depth rows -> nested rows (row b = XOR of rows d >= b), widened to 64 bits
-__global__ void k_export(const uint32_t* __restrict__ sk, uint32_t lo, uint32_t hi, uint32_t R,
-                         uint32_t B, uint32_t P, uint64_t* __restrict__ alpha,
+// (sk holds the node blocks from node `first` on)
+__global__ void k_export(const uint32_t* __restrict__ sk, uint32_t first, uint32_t lo, uint32_t hi,
+                         uint32_t R, uint32_t B, uint32_t P, uint64_t* __restrict__ alpha,
                          uint64_t* __restrict__ gamma) {
     const uint64_t total = (uint64_t)(hi - lo) * P;
     for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
          t += (uint64_t)gridDim.x * blockDim.x) {
         const uint32_t v = lo + (uint32_t)(t / P);
         const uint32_t p = (uint32_t)(t % P);  // p = r * C + c
-        const uint32_t* base = sk + (uint64_t)v * kPlanes * B * P + sk_word(B, p / kC, 0, 0, p % kC);
+        const uint32_t* base =
+            sk + (uint64_t)(v - first) * kPlanes * B * P + sk_word(B, p / kC, 0, 0, p % kC);
         const uint64_t out0 = (t / P) * (uint64_t)R * kC * B + (uint64_t)p * B;
         uint32_t a = 0, gl = 0, gh = 0;
         for (int b = (int)B - 1; b >= 0; --b) {
@@ -158,15 +160,29 @@ gz_status export_nested(gz_graph* g, uint32_t lo, uint32_t hi, uint64_t* alpha, 
     hipStream_t s = nullptr;
     hipError_t e = query_stream(g, &s);
     if (e == hipSuccess) e = fence_wait(s, g);
+    const uint32_t* src = g->sk;
+    uint32_t first = 0;
+    uint32_t* fetched = nullptr;
+    if (e == hipSuccess && g->tier) {  // the host tier's blocks come in through a device copy
+        const gz_status fs = tier_fetch(g, lo, hi, s, &fetched);
+        if (fs != GZ_OK) {
+            hipFree(da);
+            hipFree(dg);
+            return fs;
+        }
+        src = fetched;
+        first = lo;
+    }
     if (e == hipSuccess) {
         const uint64_t total = (uint64_t)(hi - lo) * g->P;
         const uint32_t blocks = (uint32_t)std::min<uint64_t>((total + 255) / 256, 65535);
-        k_export<<<blocks, 256, 0, s>>>(g->sk, lo, hi, g->R, g->B, g->P, da, dg);
+        k_export<<<blocks, 256, 0, s>>>(src, first, lo, hi, g->R, g->B, g->P, da, dg);
         e = hipGetLastError();
     }
     if (e == hipSuccess) e = hipMemcpyAsync(alpha, da, n * 8, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipMemcpyAsync(gamma, dg, n * 8, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
+    hipFree(fetched);
     hipFree(da);
     hipFree(dg);
     if (e != hipSuccess) return hip_fail(e, "export");
@@ -213,18 +229,36 @@ gz_status init_graph(gz_graph** out, uint32_t V, uint64_t seed, const gz_config*
         }
     }
     g->sk_words = (uint64_t)V * kPlanes * g->B * g->P;
-    hipError_t e = hipMalloc((void**)&g->sk, g->sk_words * 4);
-    if (e != hipSuccess) {
+    const uint32_t tier = cfg ? cfg->tier : GZ_TIER_HBM;
+    if (tier > GZ_TIER_HOST) {
         delete g;
-        return fail(GZ_ENOMEM, "out of device memory for the sketches");
+        return fail(GZ_EINVAL, "unknown sketch tier");
+    }
+    hipError_t e = hipSuccess;
+    if (tier == GZ_TIER_HBM) {
+        e = hipMalloc((void**)&g->sk, g->sk_words * 4);
+        if (e != hipSuccess) {
+            delete g;
+            return fail(GZ_ENOMEM, "out of device memory for the sketches");
+        }
     }
     e = hipMalloc((void**)&g->seeds, soa.size() * 4);
     if (e == hipSuccess) e = hipMemcpy(g->seeds, soa.data(), soa.size() * 4, hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemset(g->sk, 0, g->sk_words * 4);
+    if (e == hipSuccess && g->sk) e = hipMemset(g->sk, 0, g->sk_words * 4);
+    if (e == hipSuccess && tier == GZ_TIER_HOST) {
+        const gz_status ts = tier_create(g, cfg->staging_bytes);
+        if (ts != GZ_OK) {
+            tier_free(g);
+            hipFree(g->seeds);
+            delete g;
+            return ts;
+        }
+    }
     if (e == hipSuccess) e = fence_record(0, g);
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) {
         gz_status s = hip_fail(e, "graph init");
+        tier_free(g);
         hipFree(g->sk);
         hipFree(g->seeds);
         delete g;
@@ -251,6 +285,7 @@ gz_status gz_free(gz_graph* g) {
     if (g->last) hipEventSynchronize(g->last->ev);
     free_ingest_scratch(g->ing);
     free_query_scratch(g->q);
+    tier_free(g);
     hipFree(g->sk);
     hipFree(g->seeds);
     for (hipEvent_t e : g->prof_ev)
@@ -298,6 +333,7 @@ gz_status gz_shape(const gz_graph* g, uint32_t* V, uint32_t* R, uint32_t* C, uin
 
 gz_status gz_reset(gz_graph* g, hipStream_t stream) {
     if (!g) return fail(GZ_EINVAL, "null graph");
+    if (g->tier) return tier_reset(g);
     GZ_HIP(fence_wait(stream, g));
     GZ_HIP(hipMemsetAsync(g->sk, 0, g->sk_words * 4, stream));
     GZ_HIP(fence_record(stream, g));
@@ -412,7 +448,7 @@ gz_status gz_export_sketches(gz_graph* g, uint32_t node_lo, uint32_t node_hi, ui
 
 gz_status gz_sketch_storage(const gz_graph* g, void** dev_ptr, uint64_t* bytes) {
     if (!g) return fail(GZ_EINVAL, "null graph");
-    if (dev_ptr) *dev_ptr = g->sk;
+    if (dev_ptr) *dev_ptr = g->tier ? (void*)nullptr : (void*)g->sk;
     if (bytes) *bytes = g->sk_words * 4;
     return GZ_OK;
 }

@@ -529,11 +529,6 @@ uint32_t grid_for(uint64_t n, uint32_t threads, uint32_t cap) {
     return (uint32_t)b;
 }
 
-#define GZ_TRY(x)                 \
-    do {                          \
-        gz_status s_ = (x);       \
-        if (s_) return s_;        \
-    } while (0)
 
 gz_status ensure_scratch(IngestScratch& S, uint64_t N, uint32_t T, uint32_t G, uint32_t chunk,
                          uint64_t H_size, uint32_t n_units, bool need_staging,
@@ -596,6 +591,8 @@ gz_status ensure_scratch(IngestScratch& S, uint64_t N, uint32_t T, uint32_t G, u
     return GZ_OK;
 }
 
+}  // namespace
+
 size_t update_smem_bytes(uint32_t DL, uint32_t Pmax) {
     return (size_t)kPlanes * DL * tile_stride(Pmax) * 4;
 }
@@ -605,8 +602,6 @@ gz_status set_smem_limit(const void* fn, size_t bytes) {
                                                   (int)bytes));
     return GZ_OK;
 }
-
-}  // namespace
 
 void free_ingest_scratch(IngestScratch& S) {
     hipFree(S.H); hipFree(S.units); hipFree(S.counts);
@@ -676,6 +671,7 @@ gz_status build_shape(gz_graph* const* gs, uint32_t G, const uint64_t* ranges, u
         d.B = g->B;
         d.P = g->P;
         d.node_base = (uint32_t)T;
+        d.node_words = kPlanes * g->B * g->P;
         d.upd_base = b;
         d.nb = (uint32_t)((e - b + L.group_chunk - 1) / L.group_chunk);
         d.hoff = L.H_size;
@@ -733,7 +729,7 @@ gz_status upload_shape(IngestScratch& S, const LaunchShape& L, hipStream_t strea
 // once and replayed.  The profiling events mark the start of grouping and the
 // start and end of the sketch update when `prof` is given.
 gz_status launch_sequence(IngestScratch& S, const LaunchShape& L, hipStream_t stream,
-                          gz_graph* prof) {
+                          gz_graph* prof, bool with_update = true) {
     const uint32_t Tn = L.T;
     if (prof) GZ_HIP(hipEventRecord(prof->prof_ev[0], stream));
     k_fill_u32<<<1, 64, 0, stream>>>(S.ctl, 3, 0);  // ticket, items, call error (sticky kept)
@@ -760,7 +756,9 @@ gz_status launch_sequence(IngestScratch& S, const LaunchShape& L, hipStream_t st
                                                                        S.H, S.grouped, S.ctl);
     }
     if (prof) GZ_HIP(hipEventRecord(prof->prof_ev[1], stream));
-    k_update<<<L.pgrid, L.wg, L.smem, stream>>>(S.items, S.ctl, S.grouped, S.descs, L.lds_rows);
+    if (with_update)
+        k_update<<<L.pgrid, L.wg, L.smem, stream>>>(S.items, S.ctl, S.grouped, S.descs,
+                                                    L.lds_rows);
     GZ_HIP(hipGetLastError());
     if (prof) {
         GZ_HIP(hipEventRecord(prof->prof_ev[2], stream));
@@ -808,6 +806,11 @@ gz_status ingest_fused(gz_graph* const* gs, uint32_t G, const uint64_t* offs_hos
                        const uint32_t* src, const uint32_t* dst, uint64_t N, uint32_t flags,
                        hipStream_t stream, IngestScratch& S) {
     if (G == 0) return fail(GZ_EINVAL, "no graphs");
+    for (uint32_t k = 0; k < G; ++k)
+        if (gs[k]->tier) {
+            if (G > 1) return fail(GZ_EINVAL, "host-tier graphs are ingested one call each");
+            return tier_ingest(gs[0], src, dst, N, flags, stream);
+        }
     if (N >= (1ull << 31)) return fail(GZ_EINVAL, "at most 2^31-1 updates per call");
     if (N && (!src || !dst)) return fail(GZ_EINVAL, "null stream arrays");
     std::vector<uint64_t> ranges(G + 1, 0);
@@ -850,6 +853,39 @@ gz_status ingest_fused(gz_graph* const* gs, uint32_t G, const uint64_t* offs_hos
     return GZ_OK;
 }
 
+gz_status group_only(gz_graph* g, const uint32_t* src, const uint32_t* dst, uint64_t N,
+                     uint32_t flags, hipStream_t stream, UpdateLaunch* out) {
+    if (N >= (1ull << 31)) return fail(GZ_EINVAL, "at most 2^31-1 updates per call");
+    if (N && (!src || !dst)) return fail(GZ_EINVAL, "null stream arrays");
+    IngestScratch& S = g->ing;
+    const uint64_t ranges[2] = {0, N};
+    gz_graph* gs[1] = {g};
+    LaunchShape L;
+    GZ_TRY(build_shape(gs, 1, ranges, N, L));
+    const bool host_ptr = !(flags & GZ_DEVICE_PTR);
+    GZ_TRY(ensure_scratch(S, N, L.T, 1, L.chunk, L.H_size, L.n_units, host_ptr,
+                          L.two_pass ? 2 * N : 0, L.two_pass ? (uint64_t)(L.nbc + 1) * L.nbk : 0));
+    GZ_HIP(fence_wait(stream, g));
+    const uint32_t* dsrc = src;
+    const uint32_t* ddst = dst;
+    if (host_ptr && N) {
+        GZ_HIP(hipMemcpyAsync(S.staging, src, N * 4, hipMemcpyHostToDevice, stream));
+        GZ_HIP(hipMemcpyAsync(S.staging + N, dst, N * 4, hipMemcpyHostToDevice, stream));
+        dsrc = S.staging;
+        ddst = S.staging + N;
+    }
+    GZ_TRY(upload_args(S, L, dsrc, ddst, N, nullptr, stream));
+    GZ_TRY(upload_shape(S, L, stream));
+    GZ_HIP(hipEventRecord(S.copied_ev, stream));
+    GZ_TRY(launch_sequence(S, L, stream, nullptr, false));
+    GZ_TRY(check_call_error(S, stream));
+    out->wg = L.wg;
+    out->grid = L.pgrid;
+    out->smem = L.smem;
+    out->lds_rows = L.lds_rows;
+    return GZ_OK;
+}
+
 gz_status update_node_batch(gz_graph* g, uint32_t node, const uint32_t* nbrs, uint64_t count,
                             uint32_t flags, hipStream_t stream) {
     if (node >= g->V) return fail(GZ_EINVAL, "node id out of range");
@@ -881,23 +917,28 @@ gz_status update_node_batch(gz_graph* g, uint32_t node, const uint32_t* nbrs, ui
     if (!host_ptr && check)
         k_validate_nbrs<<<grid_for(count, 256, 1024), 256, 0, stream>>>(d, count, node, g->V,
                                                                        S.ctl + 2);
-    GraphDesc gd{};
-    gd.sk = g->sk;
-    gd.seeds = g->seeds;
-    gd.n = g->n;
-    gd.V = g->V;
-    gd.R = g->R;
-    gd.B = g->B;
-    gd.P = g->P;
-    const uint32_t chunk = tune.chunk;
-    const uint32_t DL = std::min(tune.lds_rows, g->B);
-    const size_t smem = update_smem_bytes(DL, g->P);
-    GZ_TRY(set_smem_limit((const void*)k_update_node, smem));
-    const uint32_t grid = (uint32_t)((count + chunk - 1) / chunk);
     // unchecked calls point the kernel at ctl[4], a word nothing ever sets
     const uint32_t* errp = check ? S.ctl + 2 : S.ctl + 4;
-    k_update_node<<<grid, tune.wg_size, smem, stream>>>(d, (uint32_t)count, node, gd,
-                                                          tune.lds_rows, chunk, errp);
+    if (g->tier) {
+        GZ_TRY(tier_update_node(g, node, d, (uint32_t)count, errp, stream));
+    } else {
+        GraphDesc gd{};
+        gd.sk = g->sk;
+        gd.seeds = g->seeds;
+        gd.n = g->n;
+        gd.V = g->V;
+        gd.R = g->R;
+        gd.B = g->B;
+        gd.P = g->P;
+        gd.node_words = kPlanes * g->B * g->P;
+        const uint32_t chunk = tune.chunk;
+        const uint32_t DL = std::min(tune.lds_rows, g->B);
+        const size_t smem = update_smem_bytes(DL, g->P);
+        GZ_TRY(set_smem_limit((const void*)k_update_node, smem));
+        const uint32_t grid = (uint32_t)((count + chunk - 1) / chunk);
+        k_update_node<<<grid, tune.wg_size, smem, stream>>>(d, (uint32_t)count, node, gd,
+                                                              tune.lds_rows, chunk, errp);
+    }
     GZ_HIP(hipGetLastError());
     GZ_HIP(fence_record(stream, g));
     if (!host_ptr && check) {
@@ -945,6 +986,8 @@ gz_status gz_plan_create(gz_graph* const* gs, uint32_t G, const uint64_t* caps, 
     *out = nullptr;
     std::vector<uint64_t> ranges(G + 1, 0);
     if (bad_graph_list(gs, G)) return fail(GZ_EINVAL, "null graph handle or graph listed twice");
+    for (uint32_t k = 0; k < G; ++k)
+        if (gs[k]->tier) return fail(GZ_EINVAL, "plans take graphs whose sketches live in HBM");
     for (uint32_t k = 0; k < G; ++k) ranges[k + 1] = ranges[k] + caps[k];
     if (ranges[G] >= (1ull << 31)) return fail(GZ_EINVAL, "capacities sum to 2^31 or more");
     gz_plan* p = new gz_plan();

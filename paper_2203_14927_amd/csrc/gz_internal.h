@@ -45,14 +45,16 @@ __host__ __device__ __forceinline__ uint32_t tile_stride(uint32_t P) { return (P
 
 // Per-graph data a kernel needs; kept in a device table for fused launches.
 struct GraphDesc {
-    uint32_t* sk;
+    uint32_t* sk;        // node blocks of nodes node_base.. (a slab of them for host-tier graphs)
     const uint32_t* seeds;
     uint64_t n;          // V(V-1)/2
     uint32_t V, R, B, P;
-    uint32_t node_base;  // first global node id in a fused launch
+    uint32_t node_base;  // first global node id in a fused launch (of the slab in sk)
     uint32_t nb;         // grouping chunks of this graph's updates in the launch
     uint64_t upd_base;   // first update of this graph in the launch's stream
     uint64_t hoff;       // start of this graph's (node, chunk) count table
+    uint32_t node_words; // words between consecutive node blocks in sk
+    uint32_t round_view; // query only: sk holds one round's slab per node (stride 3*B*C)
 };
 
 // One unit of work of the persistent sketch-update kernel: up to `chunk`
@@ -129,6 +131,7 @@ struct IngestScratch {
 };
 
 struct QueryScratch;
+struct HostTier;
 
 // sketch update kernels (gz_update.hip)
 __global__ void k_update(const WorkItem* __restrict__ items, uint32_t* __restrict__ ctl,
@@ -165,6 +168,7 @@ struct gz_graph {
     gz::FenceRef last;                 // last submitted work on this graph
     gz::IngestScratch ing;
     gz::QueryScratch* q = nullptr;
+    gz::HostTier* tier = nullptr;      // non-null: sketches live in host DRAM
     bool pending_error = false;
     // optional per-phase timing of the last ingest (gz_profile_enable)
     bool profiling = false;
@@ -208,6 +212,36 @@ gz_status ingest_fused(gz_graph* const* gs, uint32_t G, const uint64_t* offs_hos
 gz_status update_node_batch(gz_graph* g, uint32_t node, const uint32_t* nbrs, uint64_t count,
                             uint32_t flags, hipStream_t stream);
 void free_ingest_scratch(IngestScratch& S);
+
+// dynamic LDS of an update launch, and raising a kernel's LDS limit above 64 KiB
+size_t update_smem_bytes(uint32_t DL, uint32_t Pmax);
+gz_status set_smem_limit(const void* fn, size_t bytes);
+#define GZ_TRY(call)                  \
+    do {                              \
+        gz_status s_ = (call);        \
+        if (s_ != GZ_OK) return s_;   \
+    } while (0)
+
+// host-DRAM sketch tier (gz_tier.hip).  The grouping of a call runs as usual;
+// group_only leaves the grouped entries and the node-sorted work items of one
+// graph in g->ing and reports the launch shape of the update kernel.
+struct UpdateLaunch {
+    uint32_t wg, grid, lds_rows;
+    size_t smem;
+};
+gz_status group_only(gz_graph* g, const uint32_t* src, const uint32_t* dst, uint64_t N,
+                     uint32_t flags, hipStream_t stream, UpdateLaunch* out);
+gz_status tier_create(gz_graph* g, uint64_t staging_bytes);
+void tier_free(gz_graph* g);
+gz_status tier_ingest(gz_graph* g, const uint32_t* src, const uint32_t* dst, uint64_t N,
+                      uint32_t flags, hipStream_t stream);
+gz_status tier_update_node(gz_graph* g, uint32_t node, const uint32_t* nbrs, uint32_t count,
+                           const uint32_t* errp, hipStream_t stream);
+gz_status tier_reset(gz_graph* g);
+// device copy of the node blocks [lo, hi) of a host-tier graph (caller frees)
+gz_status tier_fetch(gz_graph* g, uint32_t lo, uint32_t hi, hipStream_t stream, uint32_t** out);
+// round r's slab of every node into the device round buffer (query, on `stream`)
+gz_status tier_round(gz_graph* g, uint32_t r, hipStream_t stream, uint32_t** round_buf);
 IngestScratch& shared_ingest_scratch(int device, std::unique_lock<std::mutex>& lock);
 
 // query path (gz_query.hip)

@@ -130,8 +130,8 @@ __global__ __launch_bounds__(256) void k_q_reduce(uint32_t r, uint32_t T,
         const uint32_t sl = slot[comp[v]];
         s_slot[threadIdx.x] = sl;
         const GraphDesc& g = gd[gof[v]];
-        s_base[threadIdx.x] =
-            g.sk + (uint64_t)(v - g.node_base) * kPlanes * g.B * g.P + sk_word(g.B, r, 0, 0, 0);
+        s_base[threadIdx.x] = g.sk + (uint64_t)(v - g.node_base) * g.node_words +
+                              (g.round_view ? 0u : sk_word(g.B, r, 0, 0, 0));
         s_words[threadIdx.x] = kPlanes * g.B * kC;
     }
     __syncthreads();
@@ -202,7 +202,8 @@ __device__ __forceinline__ void query_component(uint32_t r, uint32_t gtid, uint3
         // word (plane, row b) of column c: stride between rows of one plane
         const uint32_t* in;
         if (kDirect)
-            in = g.sk + (uint64_t)(X - g.node_base) * kPlanes * B * g.P + sk_word(B, r, 0, 0, c);
+            in = g.sk + (uint64_t)(X - g.node_base) * g.node_words +
+                 (g.round_view ? c : sk_word(B, r, 0, 0, c));
         else
             in = acc + (uint64_t)a * wpr + c;
         uint32_t al = 0, glo = 0, ghi = 0;
@@ -641,12 +642,20 @@ gz_status boruvka(gz_graph* const* gs, uint32_t G, bool want_forest, QueryResult
         descs[k].B = g->B;
         descs[k].P = g->P;
         descs[k].node_base = (uint32_t)T64;
+        descs[k].node_words = kPlanes * g->B * g->P;
         T64 += g->V;
         Rmax = std::max(Rmax, g->R);
         Bmax = std::max(Bmax, g->B);
         Vmax = std::max(Vmax, g->V);
     }
     if (T64 >= (1ull << 31)) return fail(GZ_EINVAL, "too many nodes in one query");
+    // a host-tier graph is queried alone: every round its round slabs are
+    // copied into a device buffer that the round's kernels read in place of
+    // the node blocks
+    gz_graph* tier_g = G == 1 && gs[0]->tier ? gs[0] : nullptr;
+    if (!tier_g)
+        for (uint32_t k = 0; k < G; ++k)
+            if (gs[k]->tier) return fail(GZ_EINVAL, "host-tier graphs are queried one at a time");
     if (Rmax > kMaxRounds) return fail(GZ_EINVAL, "too many rounds");
     const uint32_t T = (uint32_t)T64;
     const uint32_t wpr = kPlanes * Bmax * kC;
@@ -668,6 +677,13 @@ gz_status boruvka(gz_graph* const* gs, uint32_t G, bool want_forest, QueryResult
     hipStream_t qs = nullptr;
     GZ_HIP(query_stream(gs[0], &qs));
     GZ_HIP(fence_wait(qs, gs, G));
+    if (tier_g) {
+        uint32_t* buf = nullptr;
+        GZ_TRY(tier_round(tier_g, 0, qs, &buf));
+        descs[0].sk = buf;
+        descs[0].node_words = kPlanes * tier_g->B * kC;
+        descs[0].round_view = 1;
+    }
     GZ_HIP(hipMemcpyAsync(Q->descs, descs.data(), sizeof(GraphDesc) * G, hipMemcpyHostToDevice, qs));
     const uint32_t tb = blocks_for(T, 256);
     k_q_init<<<(T + 255) / 256, 256, 0, qs>>>(T, Q->descs, G, Q->comp, Q->L, Q->done, Q->gof,
@@ -688,6 +704,10 @@ gz_status boruvka(gz_graph* const* gs, uint32_t G, bool want_forest, QueryResult
         if (r >= 2) {
             GZ_HIP(hipEventSynchronize(Q->round_ev[r & 1]));
             if (Q->host_na[r - 2] == 0) break;
+        }
+        if (tier_g && r > 0) {
+            uint32_t* buf = nullptr;
+            GZ_TRY(tier_round(tier_g, r, qs, &buf));  // after round r-1's kernels on qs
         }
         k_q_select<<<tb, 256, 0, qs>>>(r, Q->L, Q->ctl, Q->done, Q->gof, Q->descs, Q->slot, Q->A,
                                        Q->hook, Q->newlab, Q->merged, Q->pos);

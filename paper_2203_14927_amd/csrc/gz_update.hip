@@ -300,7 +300,7 @@ __global__ __launch_bounds__(1024) void k_update_node(const uint32_t* __restrict
     const uint32_t cnt = min(chunk, count - begin);
     const uint32_t DL = min(lds_rows, g.B);
     const Lane ln = make_lane(g);
-    uint32_t* skn = g.sk + (uint64_t)node * kPlanes * g.B * g.P;
+    uint32_t* skn = g.sk + (uint64_t)(node - g.node_base) * kPlanes * g.B * g.P;
     apply_entries<false>(NeighbourEntries{nbrs + begin, node}, cnt, ln, g, DL, tile, skn,
                          gridDim.x > 1);
 }

@@ -194,11 +194,9 @@ struct SortSmem {
 // Lanes of the wave holding the same key (key < 2^bits), found by voting on
 // the key's bits: the lowest of them (leader), this lane's rank among them and
 // their number.  Every lane of the wave must call it.
-struct Peers {
-    uint32_t leader, rank, count;
-};
-
-__device__ __forceinline__ Peers wave_peers(uint32_t key, uint32_t bits, bool valid) {
+// Peers of a lane, packed: leader lane (bits 0..5), this lane's rank among
+// the peers (bits 6..11), number of peers (bits 12..18).
+__device__ __forceinline__ uint32_t wave_peers(uint32_t key, uint32_t bits, bool valid) {
     uint64_t m = __ballot(valid);
     for (uint32_t b = 0; b < bits; ++b) {
         const bool bit = (key >> b) & 1u;
@@ -206,11 +204,28 @@ __device__ __forceinline__ Peers wave_peers(uint32_t key, uint32_t bits, bool va
         m &= bit ? ones : ~ones;
     }
     const uint32_t lane = __lane_id();
-    Peers p;
-    p.leader = valid ? (uint32_t)__ffsll((unsigned long long)m) - 1u : lane;
-    p.rank = (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
-    p.count = (uint32_t)__popcll(m);
-    return p;
+    const uint32_t leader = valid ? (uint32_t)__ffsll((unsigned long long)m) - 1u : lane;
+    const uint32_t rank = (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+    const uint32_t count = (uint32_t)__popcll(m);
+    return leader | (rank << 6) | (count << 12);
+}
+__device__ __forceinline__ uint32_t peer_leader(uint32_t p) { return p & 63u; }
+__device__ __forceinline__ uint32_t peer_rank(uint32_t p) { return (p >> 6) & 63u; }
+__device__ __forceinline__ uint32_t peer_count(uint32_t p) { return p >> 12; }
+
+// Keys and values of a batch computed into registers here, before the next
+// batch's loads are issued (so that the sort never waits on those loads).
+__device__ __forceinline__ void materialise(uint32_t (&key)[kSortPerThread],
+                                            uint32_t (&val)[kSortPerThread]) {
+#pragma unroll
+    for (uint32_t k = 0; k < kSortPerThread; ++k) asm volatile("" : "+v"(key[k]), "+v"(val[k]) :: "memory");
+}
+
+// Workgroup barrier for LDS traffic only: this wave's LDS operations complete
+// first, its global loads may stay in flight across it (the next batch's
+// loads overlap this batch's sort).
+__device__ __forceinline__ void lds_barrier() {
+    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
 }
 
 // Append one batch of (key, value) pairs, kSortPerThread per thread, to the
@@ -225,15 +240,15 @@ __device__ __forceinline__ void batch_append(const uint32_t (&key)[kSortPerThrea
     const uint32_t tid = threadIdx.x;
     const uint32_t lane = __lane_id();
     for (uint32_t k = tid; k < nkeys; k += blockDim.x) sm.cnt[k] = 0;
-    __syncthreads();
-    Peers pe[kSortPerThread];
+    lds_barrier();
+    uint32_t pe[kSortPerThread];
 #pragma unroll
     for (uint32_t j = 0; j < kSortPerThread; ++j) {
         const bool ok = (valid_mask >> j) & 1u;
         pe[j] = wave_peers(key[j], bits, ok);
-        if (ok && lane == pe[j].leader) atomicAdd(&sm.cnt[key[j]], pe[j].count);
+        if (ok && lane == peer_leader(pe[j])) atomicAdd(&sm.cnt[key[j]], peer_count(pe[j]));
     }
-    __syncthreads();
+    lds_barrier();
     if (tid < 64) {  // one wave scans the (at most 256) counts, four per lane
         uint32_t c[4], run = 0;
 #pragma unroll
@@ -261,26 +276,26 @@ __device__ __forceinline__ void batch_append(const uint32_t (&key)[kSortPerThrea
         }
         if (tid == 63) sm.total = incl;
     }
-    __syncthreads();
+    lds_barrier();
 #pragma unroll
     for (uint32_t j = 0; j < kSortPerThread; ++j) {
         const bool ok = (valid_mask >> j) & 1u;
         uint32_t base = 0;
-        if (ok && lane == pe[j].leader) base = atomicAdd(&sm.cnt[key[j]], pe[j].count);
-        base = __shfl(base, (int)pe[j].leader);
+        if (ok && lane == peer_leader(pe[j])) base = atomicAdd(&sm.cnt[key[j]], peer_count(pe[j]));
+        base = __shfl(base, (int)peer_leader(pe[j]));
         if (ok) {
-            const uint32_t p = base + pe[j].rank;
+            const uint32_t p = base + peer_rank(pe[j]);
             sm.val[p] = val[j];
             sm.key[p] = (uint8_t)key[j];
         }
     }
-    __syncthreads();
+    lds_barrier();
     const uint32_t total = sm.total;
     for (uint32_t p = tid; p < total; p += blockDim.x) {
         const uint32_t k = sm.key[p];
         out[sm.gpos[k] + (p - sm.loff[k])] = sm.val[p];
     }
-    __syncthreads();
+    lds_barrier();
 }
 
 // base[c * nbk + b], c <= nb: first slot of chunk c's entries of bucket b
@@ -313,24 +328,43 @@ __global__ __launch_bounds__(kGroupThreads) void k_group_partition(
     if (ctl[2]) return;
     const GraphDesc g = gd[0];
     const UnitRange r = unit_range(a, gd, GroupUnit{0, blockIdx.x, 0, 0}, g);
-    const uint32_t* __restrict__ src = a->src;
-    const uint32_t* __restrict__ dst = a->dst;
+    // global-memory views of the stream (pointers read from memory would load
+    // through flat instructions, which also count against the LDS wait)
+    typedef const __attribute__((address_space(1))) uint32_t* gsrc_t;
+    const gsrc_t src = (gsrc_t)a->src;
+    const gsrc_t dst = (gsrc_t)a->dst;
     for (uint32_t k = threadIdx.x; k < nbk; k += blockDim.x) cur[k] = base[blockIdx.x * nbk + k];
     __syncthreads();
     const uint32_t mask = (1u << S) - 1u;
     const uint32_t kbits = 32u - __builtin_clz((nbk - 1u) | 1u);  // bucket ids < 2^kbits
     constexpr uint32_t kUpd = kSortPerThread / 2;                  // two entries per update
-    for (uint64_t i0 = r.i0; i0 < r.i1; i0 += (uint64_t)kUpd * blockDim.x) {
+    const uint64_t step = (uint64_t)kUpd * blockDim.x;
+    // the next batch's updates are loaded while this batch is sorted
+    uint32_t xs[kUpd], ys[kUpd];
+#pragma unroll
+    for (uint32_t k = 0; k < kUpd; ++k) {
+        const uint64_t i = r.i0 + threadIdx.x + (uint64_t)k * blockDim.x;
+        xs[k] = i < r.i1 ? src[i] : 0u;
+        ys[k] = i < r.i1 ? dst[i] : 0u;
+    }
+    for (uint64_t i0 = r.i0; i0 < r.i1; i0 += step) {
         uint32_t key[kSortPerThread], val[kSortPerThread], ok = 0;
 #pragma unroll
         for (uint32_t k = 0; k < kUpd; ++k) {
             const uint64_t i = i0 + threadIdx.x + (uint64_t)k * blockDim.x;
-            const uint32_t x = i < r.i1 ? src[i] : 0u, y = i < r.i1 ? dst[i] : 0u;
+            const uint32_t x = xs[k], y = ys[k];
             if (i < r.i1) ok |= 3u << (2 * k);
             key[2 * k] = x >> S;
             val[2 * k] = ((x & mask) << 16) | y;
             key[2 * k + 1] = y >> S;
             val[2 * k + 1] = ((y & mask) << 16) | x;
+        }
+        materialise(key, val);
+#pragma unroll
+        for (uint32_t k = 0; k < kUpd; ++k) {
+            const uint64_t in = i0 + step + threadIdx.x + (uint64_t)k * blockDim.x;
+            xs[k] = in < r.i1 ? src[in] : 0u;
+            ys[k] = in < r.i1 ? dst[in] : 0u;
         }
         batch_append(key, val, ok, kbits, nbk, cur, sm, tmp);
     }
@@ -353,15 +387,30 @@ __global__ __launch_bounds__(kGroupThreads) void k_group_place(
     for (uint32_t f = threadIdx.x; f < n; f += blockDim.x) cur[f] = row[f];
     __syncthreads();
     const uint32_t e1 = base[c1 * nbk + b];
-    for (uint32_t e0 = base[c0 * nbk + b]; e0 < e1; e0 += kSortPerThread * blockDim.x) {
+    const uint32_t step = kSortPerThread * blockDim.x;
+    // the next batch's entries are loaded while this batch is sorted
+    uint32_t ws[kSortPerThread];
+    const uint32_t e_first = base[c0 * nbk + b];
+#pragma unroll
+    for (uint32_t k = 0; k < kSortPerThread; ++k) {
+        const uint32_t e = e_first + threadIdx.x + k * blockDim.x;
+        ws[k] = e < e1 ? tmp[e] : 0u;
+    }
+    for (uint32_t e0 = e_first; e0 < e1; e0 += step) {
         uint32_t key[kSortPerThread], val[kSortPerThread], ok = 0;
 #pragma unroll
         for (uint32_t k = 0; k < kSortPerThread; ++k) {
             const uint32_t e = e0 + threadIdx.x + k * blockDim.x;
-            const uint32_t w = e < e1 ? tmp[e] : 0u;
+            const uint32_t w = ws[k];
             if (e < e1) ok |= 1u << k;
             key[k] = w >> 16;
             val[k] = edge_index(v0 + (w >> 16), w & 0xFFFFu);
+        }
+        materialise(key, val);
+#pragma unroll
+        for (uint32_t k = 0; k < kSortPerThread; ++k) {
+            const uint32_t en = e0 + step + threadIdx.x + k * blockDim.x;
+            ws[k] = en < e1 ? tmp[en] : 0u;
         }
         batch_append(key, val, ok, S, n, cur, sm, grouped);
     }

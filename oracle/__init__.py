@@ -93,6 +93,22 @@ def _load():
     L.oracle_query_node.restype = i32
     L.oracle_connected_components.argtypes = [vp, u32p, u32p, u64p, u32p]
     L.oracle_connected_components.restype = i32
+    L.oracle_is_wide.argtypes = [u32]
+    L.oracle_is_wide.restype = i32
+    L.oracle_wide.argtypes = [vp]
+    L.oracle_wide.restype = i32
+    L.oracle_seed_table_wide.argtypes = [u64, u32, u64p]
+    L.oracle_seed_table_wide.restype = None
+    L.oracle_hash32_pair.argtypes = [u64, u64, u64, u32, u32]
+    L.oracle_hash32_pair.restype = u32
+    L.oracle_row_hash_pair.argtypes = [u64p, u32, u32, u32, u32]
+    L.oracle_row_hash_pair.restype = u32
+    L.oracle_checksum_pair.argtypes = [u64p, u32, u32, u32, u32]
+    L.oracle_checksum_pair.restype = u64
+    L.oracle_bucket_class_wide.argtypes = [u64p, u32, u32, u64, u64, u64]
+    L.oracle_bucket_class_wide.restype = i32
+    L.oracle_query_wide.argtypes = [u64p, u32, u32, u32, u64, u64p, u64p, u64p]
+    L.oracle_query_wide.restype = i32
     _lib = L
     return L
 
@@ -133,6 +149,20 @@ def seed_table(seed: int, R: int) -> np.ndarray:
     return tab.reshape(R, C_COLUMNS, 3, 2)
 
 
+def hash32_pair(a: int, a2: int, b: int, u: int, v: int) -> int:
+    return int(_load().oracle_hash32_pair(a, a2, b, u, v))
+
+
+def seed_table_wide(seed: int, R: int) -> np.ndarray:
+    tab = np.zeros(R * 8 * 9, np.uint64)
+    _load().oracle_seed_table_wide(seed, R, _p(tab, ctypes.c_uint64))
+    return tab.reshape(R, 8, 3, 3)
+
+
+def is_wide(V: int) -> bool:
+    return bool(_load().oracle_is_wide(V))
+
+
 def hash32(a: int, b: int, x: int) -> int:
     return int(_load().oracle_hash32(a, b, x))
 
@@ -165,9 +195,16 @@ class Oracle:
             self._h = None
 
     @property
+    def wide(self) -> bool:
+        """V > 2^16: hashes keyed by the node pair, seeds (a, a2, b) per hash."""
+        return bool(_load().oracle_wide(self._h))
+
+    @property
     def seeds(self) -> np.ndarray:
-        n = self.R * self.C * 6
-        return np.ctypeslib.as_array(self._tab, shape=(n,)).reshape(self.R, self.C, 3, 2).copy()
+        """[R, C, 3, 2] (multiplier, increment) or, for wide graphs, [R, C, 3, 3] (a, a2, b)."""
+        w = 3 if self.wide else 2
+        n = self.R * self.C * 3 * w
+        return np.ctypeslib.as_array(self._tab, shape=(n,)).reshape(self.R, self.C, 3, w).copy()
 
     def seeds_valid(self) -> bool:
         return bool(_load().oracle_seeds_valid(self._h))
@@ -195,21 +232,29 @@ class Oracle:
             raise ValueError("invalid update in stream")
 
     def row_hash(self, r: int, c: int, idx: int) -> int:
+        if self.wide:
+            u, v = edge_decode(idx)
+            return int(_load().oracle_row_hash_pair(self._tab, r, c, u, v))
         return int(_load().oracle_row_hash(self._tab, r, c, idx))
 
     def checksum(self, r: int, c: int, idx: int) -> int:
+        if self.wide:
+            u, v = edge_decode(idx)
+            return int(_load().oracle_checksum_pair(self._tab, r, c, u, v))
         return int(_load().oracle_checksum(self._tab, r, c, idx))
 
     def bucket_class(self, r: int, c: int, alpha: int, gamma: int) -> int:
-        return int(_load().oracle_bucket_class(self._tab, r, c, self.n, alpha, gamma))
+        f = _load().oracle_bucket_class_wide if self.wide else _load().oracle_bucket_class
+        return int(f(self._tab, r, c, self.n, alpha, gamma))
 
     def query(self, r: int, alpha_cb: np.ndarray, gamma_cb: np.ndarray):
         """Query a round-r CubeSketch given as [C, B] arrays -> (ZERO|SAMPLE|FAIL, idx)."""
         a = np.ascontiguousarray(alpha_cb, np.uint64)
         g = np.ascontiguousarray(gamma_cb, np.uint64)
         out = ctypes.c_uint64(0)
-        k = _load().oracle_query(self._tab, r, self.C, self.B, self.n, _p(a, ctypes.c_uint64),
-                                 _p(g, ctypes.c_uint64), ctypes.byref(out))
+        f = _load().oracle_query_wide if self.wide else _load().oracle_query
+        k = f(self._tab, r, self.C, self.B, self.n, _p(a, ctypes.c_uint64), _p(g, ctypes.c_uint64),
+              ctypes.byref(out))
         return int(k), int(out.value)
 
     def query_node(self, v: int, r: int):

@@ -16,13 +16,18 @@
  *
  * Readings where the paper leaves a choice open (all shared with the GPU side
  * only through this written contract, never through code):
- *   - shape: C = 8 columns, R = bitlen(V-1)+1 rounds, B = bitlen(n-1)+1 rows,
- *     n = V(V-1)/2;
+ *   - shape: C = 8 columns, R = bitlen(V-1)+1 rounds, n = V(V-1)/2,
+ *     B = min(bitlen(n-1)+1, 33) rows (the row hash has 32 bits, so no update
+ *     reaches a row past 32; the cap only binds for V > 2^16);
  *   - the row loop of the update stops at row B-1;
  *   - seeds: a SplitMix64 stream started at the graph seed yields, for every
  *     round r, column c and hash k in (h1, h2hi, h2lo), a multiplier then an
  *     increment;
  *   - hash (2-independent, multiply-add-shift): h(x) = ((a*x + b) mod 2^64) >> 32;
+ *   - graphs with V > 2^16 ("wide": indices need more than 31 bits) hash the
+ *     node pair instead of the index, with the vector form of the same family:
+ *     h(u, v) = ((a*u + a2*v + b) mod 2^64) >> 32 for u < v, and their seed
+ *     stream yields, per (round, column, hash), a, a2, then b;
  *   - checksum = h2hi(x) * 2^32 + h2lo(x);
  *   - bucket classes: EMPTY (alpha = gamma = 0), GOOD (not EMPTY, gamma equals
  *     the checksum of alpha, alpha < n), otherwise BAD; the query scans columns
@@ -50,15 +55,21 @@ static uint32_t bitlen(uint64_t x) {
     return n;
 }
 
+#define ORACLE_MAX_NARROW 65536u
+#define ORACLE_MAX_NODES (1u << 24)
+
 int oracle_shape(uint32_t V, uint32_t *R, uint32_t *C, uint32_t *B, uint64_t *n) {
-    if (V < 2 || V > 65536u) return OR_EINVAL;
+    if (V < 2 || V > ORACLE_MAX_NODES) return OR_EINVAL;
     uint64_t pairs = (uint64_t)V * (uint64_t)(V - 1) / 2;
     *n = pairs;
     *R = bitlen((uint64_t)V - 1) + 1;
     *C = ORACLE_C;
     *B = bitlen(pairs - 1) + 1;
+    if (*B > 33) *B = 33;
     return OR_OK;
 }
+
+int oracle_is_wide(uint32_t V) { return V > ORACLE_MAX_NARROW; }
 
 /* ----------------------------------------------------------- edge index --- */
 
@@ -68,9 +79,10 @@ uint64_t oracle_edge_index(uint32_t u, uint32_t v) {
     return (uint64_t)v * (uint64_t)(v - 1) / 2 + u;
 }
 
-/* inverse: the largest v with v(v-1)/2 <= i, found by bisection */
+/* inverse: the largest v with v(v-1)/2 <= i, found by bisection over v <= 2^25
+ * (node ids are below 2^24, and mid*(mid-1) stays far from 2^64) */
 void oracle_edge_decode(uint64_t i, uint32_t *u, uint32_t *v) {
-    uint64_t lo = 1, hi = (1ull << 33);
+    uint64_t lo = 1, hi = (1ull << 25);
     while (lo < hi) {
         uint64_t mid = (lo + hi + 1) / 2;
         if (mid * (mid - 1) / 2 <= i) lo = mid; else hi = mid - 1;
@@ -106,12 +118,52 @@ void oracle_seed_table(uint64_t seed, uint32_t R, uint64_t *tab) {
             }
 }
 
+/*
+ * Wide graphs: tab3[((r*C + c)*3 + k)*3 + j], j = 0: a (multiplier of the
+ * smaller endpoint), 1: a2 (multiplier of the larger endpoint), 2: b.
+ */
+void oracle_seed_table_wide(uint64_t seed, uint32_t R, uint64_t *tab3) {
+    uint64_t st = seed;
+    for (uint32_t r = 0; r < R; ++r)
+        for (uint32_t c = 0; c < ORACLE_C; ++c)
+            for (uint32_t k = 0; k < 3; ++k)
+                for (uint32_t j = 0; j < 3; ++j)
+                    tab3[((r * ORACLE_C + c) * 3 + k) * 3 + j] = oracle_splitmix64_next(&st);
+}
+
 /* ----------------------------------------------------------------- hash --- */
 
 /* multiply-add-shift (Dietzfelbinger 1996): strongly universal for x < 2^32 */
 uint32_t oracle_hash32(uint64_t a, uint64_t b, uint64_t x) {
     uint64_t t = a * x + b; /* arithmetic modulo 2^64 */
     return (uint32_t)(t >> 32);
+}
+
+/*
+ * Vector multiply-add-shift over the pair (u, v), u < v < 2^32: strongly
+ * universal into 32 bits because 64 >= 32 + 32 - 1 (Dietzfelbinger 1996;
+ * Thorup, High Speed Hashing for Integers and Strings, multiply-shift for
+ * vectors).
+ */
+uint32_t oracle_hash32_pair(uint64_t a, uint64_t a2, uint64_t b, uint32_t u, uint32_t v) {
+    uint64_t t = a * (uint64_t)u + a2 * (uint64_t)v + b; /* modulo 2^64 */
+    return (uint32_t)(t >> 32);
+}
+
+static const uint64_t *seed3_of(const uint64_t *tab3, uint32_t r, uint32_t c, uint32_t k) {
+    return tab3 + ((r * ORACLE_C + c) * 3 + k) * 3;
+}
+
+uint32_t oracle_row_hash_pair(const uint64_t *tab3, uint32_t r, uint32_t c, uint32_t u, uint32_t v) {
+    const uint64_t *s = seed3_of(tab3, r, c, 0);
+    return oracle_hash32_pair(s[0], s[1], s[2], u, v);
+}
+
+uint64_t oracle_checksum_pair(const uint64_t *tab3, uint32_t r, uint32_t c, uint32_t u, uint32_t v) {
+    const uint64_t *hi = seed3_of(tab3, r, c, 1);
+    const uint64_t *lo = seed3_of(tab3, r, c, 2);
+    return ((uint64_t)oracle_hash32_pair(hi[0], hi[1], hi[2], u, v) << 32) |
+           (uint64_t)oracle_hash32_pair(lo[0], lo[1], lo[2], u, v);
 }
 
 static const uint64_t *seed_of(const uint64_t *tab, uint32_t r, uint32_t c, uint32_t k) {
@@ -135,6 +187,7 @@ uint64_t oracle_checksum(const uint64_t *tab, uint32_t r, uint32_t c, uint64_t i
 typedef struct {
     uint32_t V, R, C, B;
     uint64_t n;
+    uint32_t wide;   /* V > 2^16: pair-keyed hashes (tab holds R*C*3*3 words) */
     uint64_t *tab;   /* R*C*3*2 */
     uint64_t *alpha; /* [V][R][C][B] */
     uint64_t *gamma; /* [V][R][C][B] */
@@ -153,7 +206,8 @@ oracle_t *oracle_new(uint32_t V, uint64_t seed, uint32_t R_override) {
     oracle_t *O = (oracle_t *)calloc(1, sizeof(oracle_t));
     if (!O) return NULL;
     O->V = V; O->R = R; O->C = C; O->B = B; O->n = n;
-    O->tab = (uint64_t *)malloc(sizeof(uint64_t) * R * C * 6);
+    O->wide = (uint32_t)oracle_is_wide(V);
+    O->tab = (uint64_t *)malloc(sizeof(uint64_t) * R * C * (O->wide ? 9 : 6));
     size_t cells = (size_t)V * R * C * B;
     O->alpha = (uint64_t *)calloc(cells, sizeof(uint64_t));
     O->gamma = (uint64_t *)calloc(cells, sizeof(uint64_t));
@@ -161,7 +215,8 @@ oracle_t *oracle_new(uint32_t V, uint64_t seed, uint32_t R_override) {
         free(O->tab); free(O->alpha); free(O->gamma); free(O);
         return NULL;
     }
-    oracle_seed_table(seed, R, O->tab);
+    if (O->wide) oracle_seed_table_wide(seed, R, O->tab);
+    else oracle_seed_table(seed, R, O->tab);
     return O;
 }
 
@@ -176,6 +231,18 @@ void oracle_dims(const oracle_t *O, uint32_t *dims /* V R C B */, uint64_t *n) {
 }
 
 const uint64_t *oracle_seed_ptr(const oracle_t *O) { return O->tab; }
+int oracle_wide(const oracle_t *O) { return (int)O->wide; }
+
+/* row hash and checksum of edge {u, v} (u < v, idx its index) under O's contract */
+static uint32_t key_row_hash(const oracle_t *O, uint32_t r, uint32_t c, uint64_t idx, uint32_t u,
+                             uint32_t v) {
+    return O->wide ? oracle_row_hash_pair(O->tab, r, c, u, v) : oracle_row_hash(O->tab, r, c, idx);
+}
+
+static uint64_t key_checksum(const oracle_t *O, uint32_t r, uint32_t c, uint64_t idx, uint32_t u,
+                             uint32_t v) {
+    return O->wide ? oracle_checksum_pair(O->tab, r, c, u, v) : oracle_checksum(O->tab, r, c, idx);
+}
 uint64_t *oracle_alpha_ptr(oracle_t *O) { return O->alpha; }
 uint64_t *oracle_gamma_ptr(oracle_t *O) { return O->gamma; }
 
@@ -183,7 +250,7 @@ uint64_t *oracle_gamma_ptr(oracle_t *O) { return O->gamma; }
 int oracle_seeds_valid(const oracle_t *O) {
     for (uint32_t r = 0; r < O->R; ++r)
         for (uint32_t c = 0; c < O->C; ++c)
-            if (oracle_checksum(O->tab, r, c, 0) == 0) return 0;
+            if (key_checksum(O, r, c, 0, 0, 1) == 0) return 0;
     return 1;
 }
 
@@ -194,11 +261,11 @@ int oracle_seeds_valid(const oracle_t *O) {
  * column, row 0 always takes the update and row k+1 takes it while bit k of
  * the row hash is zero (Fig. "cube_code"), here bounded by the B rows.
  */
-static void toggle(oracle_t *O, uint32_t w, uint64_t idx) {
+static void toggle(oracle_t *O, uint32_t w, uint64_t idx, uint32_t u, uint32_t v) {
     for (uint32_t r = 0; r < O->R; ++r)
         for (uint32_t c = 0; c < O->C; ++c) {
-            uint32_t col_hash = oracle_row_hash(O->tab, r, c, idx);
-            uint64_t checksum = oracle_checksum(O->tab, r, c, idx);
+            uint32_t col_hash = key_row_hash(O, r, c, idx, u, v);
+            uint64_t checksum = key_checksum(O, r, c, idx, u, v);
             uint32_t row = 0;
             while (row < O->B && (row == 0 || ((col_hash >> (row - 1)) & 1u) == 0)) {
                 O->alpha[slot(O, w, r, c, row)] ^= idx;
@@ -212,8 +279,9 @@ static void toggle(oracle_t *O, uint32_t w, uint64_t idx) {
 int oracle_update(oracle_t *O, uint32_t u, uint32_t v) {
     if (u == v || u >= O->V || v >= O->V) return OR_EINVAL;
     uint64_t idx = oracle_edge_index(u, v);
-    toggle(O, u, idx);
-    toggle(O, v, idx);
+    uint32_t lo = u < v ? u : v, hi = u < v ? v : u;
+    toggle(O, u, idx, lo, hi);
+    toggle(O, v, idx, lo, hi);
     return OR_OK;
 }
 
@@ -232,8 +300,9 @@ int oracle_ingest_nodes(oracle_t *O, const uint32_t *src, const uint32_t *dst, u
         if (src[i] == dst[i] || src[i] >= O->V || dst[i] >= O->V) return OR_EINVAL;
     for (uint64_t i = 0; i < N; ++i) {
         uint64_t idx = oracle_edge_index(src[i], dst[i]);
-        if (keep[src[i]]) toggle(O, src[i], idx);
-        if (keep[dst[i]]) toggle(O, dst[i], idx);
+        uint32_t lo = src[i] < dst[i] ? src[i] : dst[i], hi = src[i] < dst[i] ? dst[i] : src[i];
+        if (keep[src[i]]) toggle(O, src[i], idx, lo, hi);
+        if (keep[dst[i]]) toggle(O, dst[i], idx, lo, hi);
     }
     return OR_OK;
 }
@@ -247,25 +316,49 @@ int oracle_bucket_class(const uint64_t *tab, uint32_t r, uint32_t c, uint64_t n,
     return OR_BAD;
 }
 
+/* wide graphs: the checksum of the pair alpha encodes */
+int oracle_bucket_class_wide(const uint64_t *tab3, uint32_t r, uint32_t c, uint64_t n,
+                             uint64_t alpha, uint64_t gamma) {
+    if (alpha == 0 && gamma == 0) return OR_EMPTY;
+    if (alpha < n) {
+        uint32_t u, v;
+        oracle_edge_decode(alpha, &u, &v);
+        if (gamma == oracle_checksum_pair(tab3, r, c, u, v)) return OR_GOOD;
+    }
+    return OR_BAD;
+}
+
 /*
  * Query one CubeSketch given as alpha[C][B], gamma[C][B] (round r's seeds):
  * columns in order, rows ascending, first GOOD bucket wins.
  */
-int oracle_query(const uint64_t *tab, uint32_t r, uint32_t C, uint32_t B, uint64_t n,
-                 const uint64_t *alpha, const uint64_t *gamma, uint64_t *out_idx) {
+static int query_sketch(const uint64_t *tab, int wide, uint32_t r, uint32_t C, uint32_t B,
+                        uint64_t n, const uint64_t *alpha, const uint64_t *gamma,
+                        uint64_t *out_idx) {
     int all_empty = 1;
     for (uint32_t c = 0; c < C; ++c)
         for (uint32_t b = 0; b < B; ++b) {
-            int k = oracle_bucket_class(tab, r, c, n, alpha[c * B + b], gamma[c * B + b]);
+            int k = wide ? oracle_bucket_class_wide(tab, r, c, n, alpha[c * B + b], gamma[c * B + b])
+                         : oracle_bucket_class(tab, r, c, n, alpha[c * B + b], gamma[c * B + b]);
             if (k == OR_GOOD) { *out_idx = alpha[c * B + b]; return OR_SAMPLE; }
             if (k != OR_EMPTY) all_empty = 0;
         }
     return all_empty ? OR_ZERO : OR_FAIL;
 }
 
+int oracle_query(const uint64_t *tab, uint32_t r, uint32_t C, uint32_t B, uint64_t n,
+                 const uint64_t *alpha, const uint64_t *gamma, uint64_t *out_idx) {
+    return query_sketch(tab, 0, r, C, B, n, alpha, gamma, out_idx);
+}
+
+int oracle_query_wide(const uint64_t *tab3, uint32_t r, uint32_t C, uint32_t B, uint64_t n,
+                      const uint64_t *alpha, const uint64_t *gamma, uint64_t *out_idx) {
+    return query_sketch(tab3, 1, r, C, B, n, alpha, gamma, out_idx);
+}
+
 /* query node v's round-r CubeSketch */
 int oracle_query_node(const oracle_t *O, uint32_t v, uint32_t r, uint64_t *out_idx) {
-    return oracle_query(O->tab, r, O->C, O->B, O->n, O->alpha + slot(O, v, r, 0, 0),
+    return query_sketch(O->tab, (int)O->wide, r, O->C, O->B, O->n, O->alpha + slot(O, v, r, 0, 0),
                         O->gamma + slot(O, v, r, 0, 0), out_idx);
 }
 
@@ -298,10 +391,13 @@ int oracle_connected_components(const oracle_t *O, uint32_t *labels, uint32_t *f
     uint64_t *acc_a = (uint64_t *)malloc(sizeof(uint64_t) * C * B);
     uint64_t *acc_g = (uint64_t *)malloc(sizeof(uint64_t) * C * B);
     uint64_t *fidx = (uint64_t *)malloc(sizeof(uint64_t) * (V ? V : 1));
+    uint32_t *first = (uint32_t *)malloc(sizeof(uint32_t) * (V + 1)); /* members by label */
+    uint32_t *members = (uint32_t *)malloc(sizeof(uint32_t) * V);
     if (!comp || !done || !hook || !hedge || !color || !path || !root || !newlab || !merged ||
-        !acc_a || !acc_g || !fidx) {
+        !acc_a || !acc_g || !fidx || !first || !members) {
         free(comp); free(done); free(hook); free(hedge); free(color); free(path); free(root);
-        free(newlab); free(merged); free(acc_a); free(acc_g); free(fidx);
+        free(newlab); free(merged); free(acc_a); free(acc_g); free(fidx); free(first);
+        free(members);
         return OR_ENOMEM;
     }
     for (uint32_t v = 0; v < V; ++v) comp[v] = v;
@@ -316,14 +412,22 @@ int oracle_connected_components(const oracle_t *O, uint32_t *labels, uint32_t *f
         if (!active) { status = OR_OK; break; }
         used = r + 1;
 
+        /* members of every component, listed by label (a counting sort of node ids) */
+        memset(first, 0, sizeof(uint32_t) * (V + 1));
+        for (uint32_t v = 0; v < V; ++v) first[comp[v] + 1]++;
+        for (uint32_t X = 0; X < V; ++X) first[X + 1] += first[X];
+        for (uint32_t v = 0; v < V; ++v) members[first[comp[v]]++] = v;
+        for (uint32_t X = V; X > 0; --X) first[X] = first[X - 1];
+        first[0] = 0;
+
         /* phase 1: one sample per active component from the XOR of its members */
         for (uint32_t X = 0; X < V; ++X) hook[X] = -1;
         for (uint32_t X = 0; X < V; ++X) {
             if (comp[X] != X || done[X]) continue;
             memset(acc_a, 0, sizeof(uint64_t) * C * B);
             memset(acc_g, 0, sizeof(uint64_t) * C * B);
-            for (uint32_t v = 0; v < V; ++v) {
-                if (comp[v] != X) continue;
+            for (uint32_t m = first[X]; m < first[X + 1]; ++m) {
+                const uint32_t v = members[m];
                 for (uint32_t c = 0; c < C; ++c)
                     for (uint32_t b = 0; b < B; ++b) {
                         acc_a[c * B + b] ^= O->alpha[slot(O, v, r, c, b)];
@@ -331,7 +435,7 @@ int oracle_connected_components(const oracle_t *O, uint32_t *labels, uint32_t *f
                     }
             }
             uint64_t idx = 0;
-            int q = oracle_query(O->tab, r, C, B, O->n, acc_a, acc_g, &idx);
+            int q = query_sketch(O->tab, (int)O->wide, r, C, B, O->n, acc_a, acc_g, &idx);
             if (q == OR_ZERO) { done[X] = 1; continue; }
             if (q == OR_FAIL) continue;
             uint32_t a, b;
@@ -410,6 +514,6 @@ int oracle_connected_components(const oracle_t *O, uint32_t *labels, uint32_t *f
     if (rounds_used) *rounds_used = used;
     memcpy(labels, comp, sizeof(uint32_t) * V);
     free(comp); free(done); free(hook); free(hedge); free(color); free(path); free(root);
-    free(newlab); free(merged); free(acc_a); free(acc_g); free(fidx);
+    free(newlab); free(merged); free(acc_a); free(acc_g); free(fidx); free(first); free(members);
     return status;
 }

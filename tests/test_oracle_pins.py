@@ -45,7 +45,7 @@ def test_shape_rule_closed_form(built):
 
 
 def test_shape_rejects_out_of_range(built):
-    for V in [0, 1, 65537]:
+    for V in [0, 1, (1 << 24) + 1]:
         with pytest.raises(ValueError):
             oracle.shape(V)
 
@@ -388,3 +388,132 @@ def test_invalid_updates_rejected_atomically(built):
     assert not O.alpha.any()
     with pytest.raises(ValueError):
         O.ingest(np.array([1], np.uint32), np.array([10], np.uint32))
+
+
+# ------------------------------------------------------- wide graphs (V > 2^16) ---
+
+def test_wide_shape_caps_rows_at_the_row_hash_width(built):
+    """B = min(bitlen(n-1)+1, 33): a 32-bit row hash reaches rows 0..32 only."""
+    assert not oracle.is_wide(1 << 16) and oracle.is_wide((1 << 16) + 1)
+    assert oracle.shape(1 << 16)[2] == 32
+    for V, R in [((1 << 16) + 1, 18), (100000, 18), (1 << 18, 19), (1 << 20, 21), (1 << 24, 25)]:
+        r, c, b, n = oracle.shape(V)
+        assert (r, c, b, n) == (R, 8, 33, V * (V - 1) // 2)
+
+
+def test_wide_seed_table_is_the_splitmix_stream(built):
+    R = 4
+    tab = oracle.seed_table_wide(4242, R)
+    assert tab.reshape(-1).tolist() == oracle.splitmix64(4242, R * 8 * 9)
+    O = oracle.Oracle(70000, 4242, R=R)
+    assert O.wide and (O.seeds == tab).all()
+
+
+def test_wide_pair_hash_closed_form(built):
+    rng = random.Random(17)
+    for _ in range(3000):
+        a, a2, b = rng.getrandbits(64), rng.getrandbits(64), rng.getrandbits(64)
+        u = rng.randrange(1 << 24)
+        v = rng.randrange(1 << 24)
+        assert oracle.hash32_pair(a, a2, b, u, v) == ((a * u + a2 * v + b) & M64) >> 32
+
+
+@pytest.mark.parametrize("p,q", [((0, 1), (0, 2)), ((5, 70000), (6, 70000)),
+                                 ((65536, 65537), (65537, 65538)), ((1, 1 << 23), (2, 1 << 22))])
+def test_wide_pair_hash_pairwise_uniform(built, p, q):
+    """2-wise independence over random seeds for two distinct pairs (Sec. 3.2)."""
+    rng = random.Random(p[1] * 7 + q[0])
+    cells = np.zeros(16)
+    trials = 16000
+    for _ in range(trials):
+        a, a2, b = rng.getrandbits(64), rng.getrandbits(64), rng.getrandbits(64)
+        hx = oracle.hash32_pair(a, a2, b, *p)
+        hy = oracle.hash32_pair(a, a2, b, *q)
+        cells[(hx & 3) * 4 + (hy & 3)] += 1
+    exp = trials / 16
+    chi2 = float(((cells - exp) ** 2 / exp).sum())
+    assert chi2 < 45.0, chi2
+
+
+def _wide_edges(V, k, rng, hubs):
+    edges = set()
+    while len(edges) < k:
+        u, v = rng.choice(hubs), rng.randrange(V)
+        if u != v:
+            edges.add((min(u, v), max(u, v)))
+    return sorted(edges)
+
+
+def test_wide_sketch_equals_closed_form_eq_1_2(built):
+    """Eq. (1)-(2) with the pair-keyed hashes, for nodes far above 2^16."""
+    V, seed, R = 90000, 31, 3
+    rng = random.Random(31)
+    hubs = [0, 1, 65535, 65536, 70001, 89999]
+    edges = _wide_edges(V, 60, rng, hubs)
+    O = oracle.Oracle(V, seed, R=R)
+    src = np.array([e[1] for e in edges] + [edges[0][0]], np.uint32)
+    dst = np.array([e[0] for e in edges] + [edges[0][1]], np.uint32)
+    src = np.concatenate([src, dst[-1:]])  # the first edge three times: net present once
+    dst = np.concatenate([dst, src[-2:-1]])
+    O.ingest(src, dst)
+    tab = oracle.seed_table_wide(seed, R)
+    B = O.B
+    for w in hubs:
+        al = np.zeros((R, 8, B), np.uint64)
+        ga = np.zeros((R, 8, B), np.uint64)
+        for (u, v) in edges:
+            if w not in (u, v):
+                continue
+            i = v * (v - 1) // 2 + u
+            for r in range(R):
+                for c in range(8):
+                    (a1, a1b, b1), (ah, ahb, bh), (al_, alb, bl) = [
+                        tuple(int(t) for t in tab[r, c, k]) for k in range(3)]
+                    h1 = ((a1 * u + a1b * v + b1) & M64) >> 32
+                    chk = ((((ah * u + ahb * v + bh) & M64) >> 32) << 32) | \
+                        (((al_ * u + alb * v + bl) & M64) >> 32)
+                    for b in range(B):
+                        if h1 % (1 << b) == 0:
+                            al[r, c, b] ^= np.uint64(i)
+                            ga[r, c, b] ^= np.uint64(chk)
+        assert (O.alpha[w] == al).all() and (O.gamma[w] == ga).all(), w
+
+
+def test_wide_support_one_is_recovered(built):
+    """Lemma "goodcheck": a lone edge between nodes above 2^16 is sampled exactly."""
+    V = 200000
+    O = oracle.Oracle(V, 5)
+    u, v = 123456, 199999
+    O.update(u, v)
+    i = oracle.edge_index(u, v)
+    assert i >= 1 << 32
+    for r in range(O.R):
+        for w in (u, v):
+            k, got = O.query_node(w, r)
+            assert (k, got) == (1, i)
+
+
+def test_wide_components_match_union_find(built):
+    """Borůvka over pair-keyed sketches: labels equal union-find on the final graph."""
+    V, R = 70000, 5
+    rng = random.Random(77)
+    edges = []
+    # small stars and paths around nodes on both sides of 2^16; everything else isolated
+    for k in range(300):
+        c = rng.randrange(V)
+        for _ in range(rng.randrange(1, 4)):
+            x = rng.randrange(V)
+            if x != c:
+                edges.append((c, x))
+    src = np.array([e[0] for e in edges], np.uint32)
+    dst = np.array([e[1] for e in edges], np.uint32)
+    O = oracle.Oracle(V, 12, R=R)
+    O.ingest(src, dst)
+    st, labels, forest, used = O.connected_components()
+    s = workloads.Stream(V, src, dst, np.ones(len(src), np.uint8))
+    fu, fv = workloads.final_edges(s)
+    ref = workloads.union_find_labels(V, fu, fv)
+    assert st == 0 and (labels == ref).all()
+    assert len(forest) == V - len(np.unique(ref))
+    keys = set(zip(fu.tolist(), fv.tolist()))
+    assert all((int(a), int(b)) in keys for a, b in forest)

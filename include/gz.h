@@ -43,6 +43,19 @@
  *           column, rows ascending, and yields the first GOOD alpha, else ZERO
  *           when every bucket is EMPTY, else FAIL (Sec. 3.2, result rule after
  *           Eq. (1)-(2)).
+ *
+ * Wide graphs (65536 < V <= 2^24): n reaches 2^47, so indices are 64-bit and a
+ * hash keyed by a 32-bit index no longer covers them.  The hashes are keyed by
+ * the pair instead:
+ *   shape   as above, but B = min(bitlen(n-1)+1, 33): the row hash has 32 bits,
+ *           so no update goes deeper than row 32;
+ *   seeds   the same stream gives, for r, c, k as above, three words a, a2, b;
+ *   hash    h(u, v) = ((a*u + a2*v + b) mod 2^64) >> 32 for u < v (strongly
+ *           universal on pairs of 32-bit words);
+ *   depth   d = min(ctz(h_row(u, v)), B-1);
+ *   bucket  alpha ^= idx(u, v) (64-bit), gamma ^= h_hi(u, v) << 32 | h_lo(u, v);
+ *   query   GOOD if not EMPTY, alpha < n and gamma equals the checksum of the
+ *           pair alpha encodes; otherwise as above.
  */
 #ifndef GZ_H
 #define GZ_H
@@ -74,7 +87,8 @@ enum {
                               node's own sketch, never other memory) */
 
 #define GZ_COLUMNS 8u
-#define GZ_MAX_NODES 65536u
+#define GZ_MAX_NODES 65536u         /* largest V under the index-keyed contract */
+#define GZ_MAX_NODES_WIDE 16777216u /* largest V at all (2^24): pair-keyed contract */
 
 typedef struct gz_graph gz_graph;
 
@@ -110,10 +124,12 @@ typedef struct gz_tuning {
  *   Paper: node sketches of O(log V) CubeSketches, one per Boruvka round
  *   (Sec. 2.2); CubeSketch layout of Sec. 3.2; all-zero start = empty graph.
  *   out   receives the handle (library-owned until gz_free);
- *   V     2 .. 65536 (keys idx < 2^31 for the 32-bit hash); else GZ_EINVAL;
+ *   V     2 .. 2^24 (up to 65536 the index-keyed contract, above it the
+ *         pair-keyed one); else GZ_EINVAL;
  *   seed  graph seed of the hash contract above;
  *   cfg   NULL or overrides.
- *   Allocates 12*B*R*C bytes per node of HBM on the current device
+ *   Allocates 12*B*R*C bytes per node (16*B*R*C for V > 65536) of HBM on the
+ *   current device
  *   (GZ_ENOMEM if that fails).  GZ_EINVAL also if the seed yields a zero
  *   checksum for index 0 (probability 2^-64): edge (0,1) would be unsampleable.
  * ---------------------------------------------------------------------- */
@@ -165,7 +181,8 @@ gz_status gz_ingest(gz_graph* g, const uint32_t* src, const uint32_t* dst, uint6
  *   launch sequence.  Updates offs[k] .. offs[k+1]-1 of src/dst belong to gs[k]
  *   (ids local to that graph).  offs is host memory (G+1 entries, offs[0]=0,
  *   non-decreasing); src/dst as in gz_ingest.  The result equals G separate
- *   gz_ingest calls.  The graphs must be distinct and on the current device.
+ *   gz_ingest calls.  The graphs must be distinct and on the current device,
+ *   and all of one contract (all V <= 65536 or all V > 65536; else GZ_EINVAL).
  * ---------------------------------------------------------------------- */
 gz_status gz_ingest_multi(gz_graph* const* gs, uint32_t G, const uint64_t* offs,
                           const uint32_t* src, const uint32_t* dst, uint32_t flags,
@@ -237,7 +254,8 @@ gz_status gz_query(gz_graph* g, uint32_t* labels, uint32_t* num_cc, uint32_t* ed
  *   many-graph form of gz_connected_components).  labels: host array of
  *   sum(V_k) entries, graph k's labels at offset sum_{j<k} V_j, local ids;
  *   num_cc, status: host arrays of G entries (nullable).  Returns GZ_OK if
- *   every graph finished, GZ_ESKETCH_FAIL if any did not.
+ *   every graph finished, GZ_ESKETCH_FAIL if any did not.  Graphs with
+ *   V > 65536 are queried one at a time (GZ_EINVAL here when G > 1).
  * ---------------------------------------------------------------------- */
 gz_status gz_connected_components_multi(gz_graph* const* gs, uint32_t G, uint32_t* labels,
                                         uint32_t* num_cc, int32_t* status);
@@ -308,6 +326,8 @@ gz_status gz_profile_last(gz_graph* g, gz_profile* out);
  *   status (a query whose sketches ran out of rounds reports GZ_ESKETCH_FAIL in
  *   res->status only).  Timestamps are steady-clock nanoseconds: submit, start
  *   of processing, completion.
+ * gz_session_open takes 2 <= V <= 65536 (sessions share fused calls); else
+ *   GZ_EINVAL.
  * gz_session_close waits for the session's requests and frees its sketches;
  *   gz_server_destroy stops the server and frees every session.
  * ---------------------------------------------------------------------- */

@@ -29,6 +29,11 @@ uint64_t splitmix64(uint64_t& st) {
     return z ^ (z >> 31);
 }
 
+// the pair-keyed form of wide graphs: ((a*u + a2*v + b) mod 2^64) >> 32
+uint32_t host_hash_pair(uint64_t a, uint64_t a2, uint64_t b, uint32_t u, uint32_t v) {
+    return (uint32_t)((a * u + a2 * v + b) >> 32);
+}
+
 uint32_t host_hash(uint64_t mult, uint64_t incr, uint64_t x) {
     return (uint32_t)((mult * x + incr) >> 32);
 }
@@ -103,10 +108,10 @@ hipError_t fence_record(hipStream_t stream, gz_graph* const* gs, uint32_t G) {
 // Defaults before autotuning: the whole tile in LDS when it takes at most 48 KiB,
 // the workgroup (multiple of 64, 256..512 lanes) with the best lane use for P
 // pairs, and as many resident workgroups per CU as 160 KiB of LDS allows.
-gz_tuning default_tuning(uint32_t P, uint32_t B) {
+gz_tuning default_tuning(uint32_t P, uint32_t B, bool wide) {
     gz_tuning t{};
     t.chunk = 16384;
-    t.lds_rows = (kPlanes * B * ((P + 63) / 64 * 64) * 4 <= 48 * 1024) ? B : std::min<uint32_t>(B, 16u);
+    t.lds_rows = (B * tile_row_words(P, wide) * 4 <= 48 * 1024) ? B : std::min<uint32_t>(B, 16u);
     uint32_t best = 0;
     double best_use = -1.0;
     for (uint32_t wg = 256; wg <= 512; wg += 64) {
@@ -118,31 +123,34 @@ gz_tuning default_tuning(uint32_t P, uint32_t B) {
         }
     }
     t.wg_size = best ? best : std::min<uint32_t>(1024, (P + 63) / 64 * 64);
-    const uint32_t smem = kPlanes * std::min(t.lds_rows, B) * ((P + 63) / 64 * 64) * 4;
+    const uint32_t smem = std::min(t.lds_rows, B) * tile_row_words(P, wide) * 4;
     t.wgs_per_cu = std::max<uint32_t>(1, std::min<uint32_t>(8, (160 * 1024) / smem));
     t.group_blocks = 0;
     return t;
 }
 
 // exact-depth rows -> nested rows (row b = XOR of rows d >= b), widened to 64 bits
-// (sk holds the node blocks from node `first` on)
+// (sk holds the node blocks from node `first` on; `planes` = 4 for wide
+// graphs, whose alpha has a low and a high word)
 __global__ void k_export(const uint32_t* __restrict__ sk, uint32_t first, uint32_t lo, uint32_t hi,
-                         uint32_t R, uint32_t B, uint32_t P, uint64_t* __restrict__ alpha,
-                         uint64_t* __restrict__ gamma) {
+                         uint32_t R, uint32_t B, uint32_t P, uint32_t planes,
+                         uint64_t* __restrict__ alpha, uint64_t* __restrict__ gamma) {
     const uint64_t total = (uint64_t)(hi - lo) * P;
     for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
          t += (uint64_t)gridDim.x * blockDim.x) {
         const uint32_t v = lo + (uint32_t)(t / P);
         const uint32_t p = (uint32_t)(t % P);  // p = r * C + c
-        const uint32_t* base =
-            sk + (uint64_t)(v - first) * kPlanes * B * P + sk_word(B, p / kC, 0, 0, p % kC);
+        const uint32_t* base = sk + (uint64_t)(v - first) * planes * B * P +
+                               sk_word_n(planes, B, p / kC, 0, 0, p % kC);
         const uint64_t out0 = (t / P) * (uint64_t)R * kC * B + (uint64_t)p * B;
-        uint32_t a = 0, gl = 0, gh = 0;
+        const uint32_t pg = planes - 2;  // first gamma plane
+        uint32_t a = 0, ah = 0, gl = 0, gh = 0;
         for (int b = (int)B - 1; b >= 0; --b) {
             a ^= base[(0 * B + b) * kC];
-            gl ^= base[(1 * B + b) * kC];
-            gh ^= base[(2 * B + b) * kC];
-            alpha[out0 + b] = a;
+            if (planes == kPlanesWide) ah ^= base[(1 * B + b) * kC];
+            gl ^= base[(pg * B + b) * kC];
+            gh ^= base[((pg + 1) * B + b) * kC];
+            alpha[out0 + b] = ((uint64_t)ah << 32) | a;
             gamma[out0 + b] = ((uint64_t)gh << 32) | gl;
         }
     }
@@ -176,7 +184,7 @@ gz_status export_nested(gz_graph* g, uint32_t lo, uint32_t hi, uint64_t* alpha, 
     if (e == hipSuccess) {
         const uint64_t total = (uint64_t)(hi - lo) * g->P;
         const uint32_t blocks = (uint32_t)std::min<uint64_t>((total + 255) / 256, 65535);
-        k_export<<<blocks, 256, 0, s>>>(src, first, lo, hi, g->R, g->B, g->P, da, dg);
+        k_export<<<blocks, 256, 0, s>>>(src, first, lo, hi, g->R, g->B, g->P, g->planes, da, dg);
         e = hipGetLastError();
     }
     if (e == hipSuccess) e = hipMemcpyAsync(alpha, da, n * 8, hipMemcpyDeviceToHost, s);
@@ -192,14 +200,17 @@ gz_status export_nested(gz_graph* g, uint32_t lo, uint32_t hi, uint64_t* alpha, 
 gz_status init_graph(gz_graph** out, uint32_t V, uint64_t seed, const gz_config* cfg) {
     if (!out) return fail(GZ_EINVAL, "null output handle");
     *out = nullptr;
-    if (V < 2 || V > GZ_MAX_NODES) return fail(GZ_EINVAL, "V must be in [2, 65536]");
+    if (V < 2 || V > GZ_MAX_NODES_WIDE) return fail(GZ_EINVAL, "V must be in [2, 2^24]");
     gz_graph* g = new gz_graph();
     GZ_HIP(hipGetDevice(&g->device));
     g->V = V;
     g->n = (uint64_t)V * (V - 1) / 2;
     g->R = bitlen64((uint64_t)V - 1) + 1;
     g->C = kC;
-    g->B = bitlen64(g->n - 1) + 1;
+    // a 32-bit row hash reaches rows 0..32 only (binds for V > 2^16 alone)
+    g->B = std::min<uint32_t>(bitlen64(g->n - 1) + 1, 33);
+    g->wide = V > kMaxNarrow;
+    g->planes = g->wide ? kPlanesWide : kPlanes;
     if (cfg && cfg->rounds) g->R = cfg->rounds;
     if (g->R > 64) {
         delete g;
@@ -207,28 +218,37 @@ gz_status init_graph(gz_graph** out, uint32_t V, uint64_t seed, const gz_config*
     }
     g->P = g->R * kC;
     g->seed = seed;
-    // seeds: SplitMix64 stream in (round, column, hash) order, multiplier then increment
-    g->seeds_host.resize((size_t)g->P * 6);
+    // seeds: SplitMix64 stream in (round, column, hash) order; per hash a
+    // multiplier then an increment, or for wide graphs a, a2 then b
+    const uint32_t per_pair = g->wide ? 9 : 6;
+    g->seeds_host.resize((size_t)g->P * per_pair);
     uint64_t st = seed;
     for (uint32_t p = 0; p < g->P; ++p)
-        for (uint32_t k = 0; k < 6; ++k) g->seeds_host[(size_t)p * 6 + k] = splitmix64(st);
+        for (uint32_t k = 0; k < per_pair; ++k)
+            g->seeds_host[(size_t)p * per_pair + k] = splitmix64(st);
     for (uint32_t p = 0; p < g->P; ++p) {
-        const uint64_t* s = &g->seeds_host[(size_t)p * 6];
-        uint64_t chk0 = ((uint64_t)host_hash(s[2], s[3], 0) << 32) | host_hash(s[4], s[5], 0);
+        const uint64_t* s = &g->seeds_host[(size_t)p * per_pair];
+        // edge 0 = pair (0, 1) must keep a non-zero checksum
+        const uint64_t chk0 =
+            g->wide ? ((uint64_t)host_hash_pair(s[3], s[4], s[5], 0, 1) << 32) |
+                          host_hash_pair(s[6], s[7], s[8], 0, 1)
+                    : ((uint64_t)host_hash(s[2], s[3], 0) << 32) | host_hash(s[4], s[5], 0);
         if (chk0 == 0) {
             delete g;
             return fail(GZ_EINVAL, "seed gives a zero checksum for index 0; pick another seed");
         }
     }
-    std::vector<uint32_t> soa((size_t)kSeedWords * g->P);
+    // device table: word w of pair p at [w * P + p] (the 64-bit seeds split in halves)
+    const uint32_t words = 2 * per_pair;
+    std::vector<uint32_t> soa((size_t)words * g->P);
     for (uint32_t p = 0; p < g->P; ++p) {
-        const uint64_t* s = &g->seeds_host[(size_t)p * 6];
-        for (uint32_t k = 0; k < 6; ++k) {
+        const uint64_t* s = &g->seeds_host[(size_t)p * per_pair];
+        for (uint32_t k = 0; k < per_pair; ++k) {
             soa[(size_t)(2 * k) * g->P + p] = (uint32_t)s[k];
             soa[(size_t)(2 * k + 1) * g->P + p] = (uint32_t)(s[k] >> 32);
         }
     }
-    g->sk_words = (uint64_t)V * kPlanes * g->B * g->P;
+    g->sk_words = (uint64_t)V * g->planes * g->B * g->P;
     const uint32_t tier = cfg ? cfg->tier : GZ_TIER_HBM;
     if (tier > GZ_TIER_HOST) {
         delete g;
@@ -264,7 +284,7 @@ gz_status init_graph(gz_graph** out, uint32_t V, uint64_t seed, const gz_config*
         delete g;
         return s;
     }
-    g->tuning = default_tuning(g->P, g->B);
+    g->tuning = default_tuning(g->P, g->B, g->wide);
     *out = g;
     return GZ_OK;
 }
@@ -466,7 +486,7 @@ gz_status gz_set_tuning(gz_graph* g, const gz_tuning* t) {
     if (t->lds_rows < 1) return fail(GZ_EINVAL, "lds_rows must be >= 1");
     if (t->chunk < 1 || t->chunk > (1u << 30)) return fail(GZ_EINVAL, "chunk must be in [1, 2^30]");
     if (t->wgs_per_cu < 1 || t->wgs_per_cu > 64) return fail(GZ_EINVAL, "wgs_per_cu in [1, 64]");
-    size_t smem = (size_t)kPlanes * std::min(t->lds_rows, g->B) * ((g->P + 63) / 64 * 64) * 4;
+    size_t smem = (size_t)std::min(t->lds_rows, g->B) * tile_row_words(g->P, g->wide) * 4;
     if (smem > 160 * 1024) return fail(GZ_EINVAL, "LDS tile exceeds 160 KiB");
     g->tuning = *t;
     return GZ_OK;

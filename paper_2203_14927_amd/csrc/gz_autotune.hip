@@ -15,7 +15,7 @@ struct Cand {
     float ms;
 };
 
-std::vector<gz_tuning> candidates(uint32_t P, uint32_t B) {
+std::vector<gz_tuning> candidates(uint32_t P, uint32_t B, bool wide) {
     // workgroup sizes with at least 85% of lanes busy (J = wg / P groups of P lanes)
     std::vector<std::pair<double, uint32_t>> wgs;
     for (uint32_t wg = 64; wg <= 1024; wg += 64) {
@@ -42,7 +42,7 @@ std::vector<gz_tuning> candidates(uint32_t P, uint32_t B) {
     std::vector<gz_tuning> out;
     for (uint32_t wg : wg_list)
         for (uint32_t dl : rows) {
-            const uint32_t smem = kPlanes * dl * ((P + 63) / 64 * 64) * 4;
+            const uint32_t smem = dl * tile_row_words(P, wide) * 4;
             if (smem > 160 * 1024) continue;
             const uint32_t by_lds = std::max<uint32_t>(1, (160 * 1024) / smem);
             const uint32_t by_threads = std::max<uint32_t>(1, 2048 / wg);
@@ -70,7 +70,7 @@ extern "C" gz_status gz_autotune(gz_graph* g, const uint32_t* src, const uint32_
     st = gz_profile_enable(t, 1);
     std::vector<Cand> res;
     if (!st) {
-        for (const gz_tuning& c : candidates(g->P, g->B)) {
+        for (const gz_tuning& c : candidates(g->P, g->B, g->wide)) {
             if (gz_set_tuning(t, &c) != GZ_OK) continue;
             float bestc = 1e30f;
             for (int rep = 0; rep < 2 && !st; ++rep) {

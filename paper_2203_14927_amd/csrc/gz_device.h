@@ -53,6 +53,64 @@ __device__ __forceinline__ uint32_t chk_lo(const PairSeeds& s, uint32_t x) {
     return mas_hash(s.clo_mlo, s.clo_mhi, s.clo_inc, x);
 }
 
+// Wide graphs (V > 2^16) hash the node pair (u < v) with the vector form of
+// the family: h(u, v) = ((a*u + a2*v + b) mod 2^64) >> 32.  Per hash the seeds
+// a, a2, b are 64-bit; on the device, word w = (k*3 + j)*2 + half of pair p
+// (k: row / checksum-high / checksum-low, j: a / a2 / b) sits at seeds[w*P + p].
+// (a*u + a2*v + b) mod 2^64 has high word hi32(alo*u + a2lo*v + b) + ahi*u + a2hi*v
+// (mod 2^32): two 64-bit multiply-adds in a chain plus two low multiplies.
+struct WideHashSeeds {
+    uint32_t alo, ahi, a2lo, a2hi;
+    uint64_t b;
+};
+struct WideSeeds {
+    WideHashSeeds h[3];  // row, checksum high word, checksum low word
+};
+
+__device__ __forceinline__ WideSeeds load_wide_seeds(const uint32_t* __restrict__ seeds,
+                                                     uint32_t P, uint32_t p) {
+    WideSeeds s;
+#pragma unroll
+    for (uint32_t k = 0; k < 3; ++k) {
+        const uint32_t w = k * 6;
+        s.h[k].alo = seeds[(w + 0) * P + p];
+        s.h[k].ahi = seeds[(w + 1) * P + p];
+        s.h[k].a2lo = seeds[(w + 2) * P + p];
+        s.h[k].a2hi = seeds[(w + 3) * P + p];
+        s.h[k].b = (uint64_t)seeds[(w + 4) * P + p] | ((uint64_t)seeds[(w + 5) * P + p] << 32);
+    }
+    return s;
+}
+
+__device__ __forceinline__ uint32_t pair_hash(const WideHashSeeds& s, uint32_t u, uint32_t v) {
+    uint64_t t = (uint64_t)s.alo * u + s.b;
+    t = (uint64_t)s.a2lo * v + t;
+    return (uint32_t)(t >> 32) + s.ahi * u + s.a2hi * v;
+}
+
+__device__ __forceinline__ uint32_t wide_row_depth(const WideSeeds& s, uint32_t u, uint32_t v,
+                                                   uint32_t Bm1) {
+    const uint32_t h = pair_hash(s.h[0], u, v);
+    const uint32_t tz = __builtin_ctzg(h, 32);
+    return tz < Bm1 ? tz : Bm1;
+}
+
+// 64-bit position of pair {u, v} (ids up to 2^24)
+__device__ __forceinline__ uint64_t edge_index64(uint32_t u, uint32_t v) {
+    const uint32_t lo = u < v ? u : v;
+    const uint32_t hi = u < v ? v : u;
+    return (((uint64_t)hi * (hi - 1u)) >> 1) + lo;
+}
+
+// inverse of edge_index64: hi = largest v with v(v-1)/2 <= i (i < 2^47)
+__device__ __forceinline__ void edge_pair64(uint64_t i, uint32_t* u, uint32_t* v) {
+    uint64_t hi = (uint64_t)((1.0 + sqrt(1.0 + 8.0 * (double)i)) * 0.5);
+    while (hi * (hi - 1) / 2 > i) --hi;
+    while ((hi + 1) * hi / 2 <= i) ++hi;
+    *v = (uint32_t)hi;
+    *u = (uint32_t)(i - hi * (hi - 1) / 2);
+}
+
 // position of pair {u, v} in the characteristic vector; ids < 2^16 keep it in 32 bits
 __device__ __forceinline__ uint32_t edge_index(uint32_t u, uint32_t v) {
     uint32_t lo = u < v ? u : v;

@@ -158,10 +158,11 @@ __global__ __launch_bounds__(kGroupThreads) void k_group_scatter(
 #pragma unroll
         for (uint32_t k = 0; k < kScatterBatch; ++k) {
             if (x[k] == kNone) continue;
-            const uint32_t idx = edge_index(x[k], y[k]);
+            // an entry is the edge index, or for wide graphs the other endpoint
+            const uint32_t idx = g.wide ? 0u : edge_index(x[k], y[k]);
             const uint32_t xo = x[k] - r.lo, yo = y[k] - r.lo;
-            if (xo < r.size) grouped[atomicAdd(&cur[xo], 1u)] = idx;
-            if (yo < r.size) grouped[atomicAdd(&cur[yo], 1u)] = idx;
+            if (xo < r.size) grouped[atomicAdd(&cur[xo], 1u)] = g.wide ? y[k] : idx;
+            if (yo < r.size) grouped[atomicAdd(&cur[yo], 1u)] = g.wide ? x[k] : idx;
         }
     }
 }
@@ -642,8 +643,8 @@ gz_status ensure_scratch(IngestScratch& S, uint64_t N, uint32_t T, uint32_t G, u
 
 }  // namespace
 
-size_t update_smem_bytes(uint32_t DL, uint32_t Pmax) {
-    return (size_t)kPlanes * DL * tile_stride(Pmax) * 4;
+size_t update_smem_bytes(uint32_t DL, uint32_t Pmax, bool wide) {
+    return (size_t)DL * tile_row_words(Pmax, wide) * 4;
 }
 
 gz_status set_smem_limit(const void* fn, size_t bytes) {
@@ -684,11 +685,14 @@ struct LaunchShape {
     // two-pass placement (single large graph): bucket shift, buckets, chunks,
     // chunks per pass-B block, pass-B blocks
     bool two_pass = false;
+    bool wide = false;  // graphs with V > 2^16 (pair-keyed hashes, four planes)
     uint32_t bS = 0, nbk = 0, nbc = 0, bcr = 1, bblocks = 0;
     size_t gsmem = 0, smem = 0;
     std::vector<GraphDesc> descs;
     std::vector<GroupUnit> units;
 };
+
+constexpr uint64_t kTableWords = 1ull << 28;
 
 gz_status build_shape(gz_graph* const* gs, uint32_t G, const uint64_t* ranges, uint64_t N,
                       LaunchShape& L) {
@@ -703,7 +707,16 @@ gz_status build_shape(gz_graph* const* gs, uint32_t G, const uint64_t* ranges, u
     // each) unless tuned otherwise
     const uint32_t cus = (uint32_t)device_cu_count();
     const uint32_t gblocks = tune.group_blocks ? tune.group_blocks : cus;
-    L.group_chunk = (uint32_t)std::max<uint64_t>(8192, (N + gblocks - 1) / gblocks);
+    uint64_t gchunk = std::max<uint64_t>(8192, (N + gblocks - 1) / gblocks);
+    if (gs[0] && gs[0]->wide) {
+        // the (chunk, node) count table holds V words per chunk: graphs with
+        // millions of nodes take fewer, longer chunks so that it stays within
+        // 2^28 words
+        uint64_t vsum = 0;
+        for (uint32_t k = 0; k < G; ++k) vsum += gs[k] ? gs[k]->V : 0;
+        gchunk = std::max<uint64_t>(gchunk, (N * vsum + kTableWords - 1) / kTableWords);
+    }
+    L.group_chunk = (uint32_t)gchunk;
     L.descs.resize(G);
     uint64_t T = 0;
     for (uint32_t k = 0; k < G; ++k) {
@@ -720,7 +733,9 @@ gz_status build_shape(gz_graph* const* gs, uint32_t G, const uint64_t* ranges, u
         d.B = g->B;
         d.P = g->P;
         d.node_base = (uint32_t)T;
-        d.node_words = kPlanes * g->B * g->P;
+        d.node_words = g->planes * g->B * g->P;
+        d.wide = g->wide;
+        d.planes = g->planes;
         d.upd_base = b;
         d.nb = (uint32_t)((e - b + L.group_chunk - 1) / L.group_chunk);
         d.hoff = L.H_size;
@@ -738,11 +753,15 @@ gz_status build_shape(gz_graph* const* gs, uint32_t G, const uint64_t* ranges, u
     if (L.H_size >= (1ull << 32)) return fail(GZ_EINVAL, "call too large: split the stream");
     if (L.wg < L.Pmax || L.wg % 64 || L.wg > 1024)
         return fail(GZ_EINVAL, "workgroup smaller than pairs");
+    L.wide = gs[0]->wide;
+    for (uint32_t k = 1; k < G; ++k)
+        if (gs[k]->wide != L.wide)
+            return fail(GZ_EINVAL, "one call takes graphs of one kind (V <= 65536, or larger)");
     L.T = (uint32_t)T;
     L.n_units = (uint32_t)L.units.size();
     // single graphs large enough that one-pass placement would keep too many
     // runs open per block take the two-pass placement
-    if (G == 1 && gs[0]->V > 4096 && L.descs[0].nb > 0) {
+    if (G == 1 && !L.wide && gs[0]->V > 4096 && L.descs[0].nb > 0) {
         L.two_pass = true;
         while (((gs[0]->V + (1u << L.bS) - 1) >> L.bS) > kMaxBuckets) ++L.bS;
         L.nbk = (gs[0]->V + (1u << L.bS) - 1) >> L.bS;
@@ -753,11 +772,11 @@ gz_status build_shape(gz_graph* const* gs, uint32_t G, const uint64_t* ranges, u
     }
     L.nblocks = (uint32_t)((T + kScanTile - 1) / kScanTile);
     L.gsmem = (size_t)L.range_max * 4;
-    L.smem = update_smem_bytes(L.DLmax, L.Pmax);
+    L.smem = update_smem_bytes(L.DLmax, L.Pmax, L.wide);
     L.pgrid = std::max(1u, tune.wgs_per_cu) * cus;
     GZ_TRY(set_smem_limit((const void*)k_group_count, L.gsmem));
     GZ_TRY(set_smem_limit((const void*)k_group_scatter, L.gsmem));
-    GZ_TRY(set_smem_limit((const void*)k_update, L.smem));
+    GZ_TRY(set_smem_limit(L.wide ? (const void*)k_update_wide : (const void*)k_update, L.smem));
     return GZ_OK;
 }
 
@@ -805,7 +824,10 @@ gz_status launch_sequence(IngestScratch& S, const LaunchShape& L, hipStream_t st
                                                                        S.H, S.grouped, S.ctl);
     }
     if (prof) GZ_HIP(hipEventRecord(prof->prof_ev[1], stream));
-    if (with_update)
+    if (with_update && L.wide)
+        k_update_wide<<<L.pgrid, L.wg, L.smem, stream>>>(S.items, S.ctl, S.grouped, S.descs,
+                                                         L.lds_rows);
+    else if (with_update)
         k_update<<<L.pgrid, L.wg, L.smem, stream>>>(S.items, S.ctl, S.grouped, S.descs,
                                                     L.lds_rows);
     GZ_HIP(hipGetLastError());
@@ -932,6 +954,7 @@ gz_status group_only(gz_graph* g, const uint32_t* src, const uint32_t* dst, uint
     out->grid = L.pgrid;
     out->smem = L.smem;
     out->lds_rows = L.lds_rows;
+    out->wide = L.wide;
     return GZ_OK;
 }
 
@@ -979,14 +1002,21 @@ gz_status update_node_batch(gz_graph* g, uint32_t node, const uint32_t* nbrs, ui
         gd.R = g->R;
         gd.B = g->B;
         gd.P = g->P;
-        gd.node_words = kPlanes * g->B * g->P;
+        gd.node_words = g->planes * g->B * g->P;
+        gd.wide = g->wide;
+        gd.planes = g->planes;
         const uint32_t chunk = tune.chunk;
         const uint32_t DL = std::min(tune.lds_rows, g->B);
-        const size_t smem = update_smem_bytes(DL, g->P);
-        GZ_TRY(set_smem_limit((const void*)k_update_node, smem));
+        const size_t smem = update_smem_bytes(DL, g->P, g->wide);
+        const void* fn = g->wide ? (const void*)k_update_node_wide : (const void*)k_update_node;
+        GZ_TRY(set_smem_limit(fn, smem));
         const uint32_t grid = (uint32_t)((count + chunk - 1) / chunk);
-        k_update_node<<<grid, tune.wg_size, smem, stream>>>(d, (uint32_t)count, node, gd,
-                                                              tune.lds_rows, chunk, errp);
+        if (g->wide)
+            k_update_node_wide<<<grid, tune.wg_size, smem, stream>>>(d, (uint32_t)count, node, gd,
+                                                                       tune.lds_rows, chunk, errp);
+        else
+            k_update_node<<<grid, tune.wg_size, smem, stream>>>(d, (uint32_t)count, node, gd,
+                                                                  tune.lds_rows, chunk, errp);
     }
     GZ_HIP(hipGetLastError());
     GZ_HIP(fence_record(stream, g));

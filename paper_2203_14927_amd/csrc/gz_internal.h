@@ -40,21 +40,34 @@ __host__ __device__ __forceinline__ uint32_t sk_word(uint32_t B, uint32_t r, uin
     return ((r * kPlanes + plane) * B + d) * kC + c;
 }
 
+// Graphs with V > 2^16 ("wide") need 64-bit indices: four planes (alpha low,
+// alpha high, gamma low, gamma high), the same round-major order.
+constexpr uint32_t kPlanesWide = 4;
+constexpr uint32_t kMaxNarrow = 65536;
+__host__ __device__ __forceinline__ uint32_t sk_word_n(uint32_t planes, uint32_t B, uint32_t r,
+                                                       uint32_t plane, uint32_t d, uint32_t c) {
+    return ((r * planes + plane) * B + d) * kC + c;
+}
+
 // Row stride of an LDS node tile: P rounded up to a multiple of 64 words.
 __host__ __device__ __forceinline__ uint32_t tile_stride(uint32_t P) { return (P + 63u) & ~63u; }
 
 // Per-graph data a kernel needs; kept in a device table for fused launches.
 struct GraphDesc {
-    uint32_t* sk;        // node blocks of nodes node_base.. (a slab of them for host-tier graphs)
+    uint32_t* sk;        // node blocks from graph-local node sk_first on
     const uint32_t* seeds;
     uint64_t n;          // V(V-1)/2
     uint32_t V, R, B, P;
-    uint32_t node_base;  // first global node id in a fused launch (of the slab in sk)
+    uint32_t node_base;  // global id of the graph's node 0 in a fused launch
     uint32_t nb;         // grouping chunks of this graph's updates in the launch
     uint64_t upd_base;   // first update of this graph in the launch's stream
     uint64_t hoff;       // start of this graph's (node, chunk) count table
     uint32_t node_words; // words between consecutive node blocks in sk
-    uint32_t round_view; // query only: sk holds one round's slab per node (stride 3*B*C)
+    uint32_t round_view; // query only: sk holds one round's slab per node (stride planes*B*C)
+    uint32_t wide;       // V > 2^16: pair-keyed hashes, four planes
+    uint32_t planes;     // 3, or 4 when wide
+    uint32_t sk_first;   // graph-local node of the first block in sk (a host-tier slab's first
+                         // node; 0 when sk holds the whole graph)
 };
 
 // One unit of work of the persistent sketch-update kernel: up to `chunk`
@@ -140,6 +153,19 @@ __global__ void k_update(const WorkItem* __restrict__ items, uint32_t* __restric
 __global__ void k_update_node(const uint32_t* __restrict__ nbrs, uint32_t count, uint32_t node,
                               GraphDesc g, uint32_t lds_rows, uint32_t chunk,
                               const uint32_t* __restrict__ err);
+// the same for wide graphs (grouped entries are neighbour ids, four planes)
+__global__ void k_update_wide(const WorkItem* __restrict__ items, uint32_t* __restrict__ ctl,
+                              const uint32_t* __restrict__ grouped,
+                              const GraphDesc* __restrict__ gd, uint32_t lds_rows);
+__global__ void k_update_node_wide(const uint32_t* __restrict__ nbrs, uint32_t count,
+                                   uint32_t node, GraphDesc g, uint32_t lds_rows, uint32_t chunk,
+                                   const uint32_t* __restrict__ err);
+// LDS words of one tile row of P pairs (three planes interleaved, or four
+// with one pad word per 16 pairs so that lanes keep distinct banks)
+__host__ __device__ __forceinline__ uint32_t tile_row_words(uint32_t P, bool wide) {
+    const uint32_t S = tile_stride(P);
+    return wide ? kPlanesWide * S + S / 16 : kPlanes * S;
+}
 
 // Completion marker of the last device work submitted on a graph.  One call
 // over many graphs records a single marker that all of them share, so a fused
@@ -157,6 +183,8 @@ using FenceRef = std::shared_ptr<Fence>;
 struct gz_graph {
     int device = 0;
     uint32_t V = 0, R = 0, C = 0, B = 0, P = 0;
+    bool wide = false;                 // V > 2^16: pair-keyed hashes, 64-bit indices
+    uint32_t planes = 3;               // sketch planes per bucket (4 when wide)
     uint64_t n = 0;
     uint64_t seed = 0;
     uint32_t* sk = nullptr;            // device sketch words
@@ -203,7 +231,7 @@ inline hipError_t fence_record(hipStream_t stream, gz_graph* g) {
     return fence_record(stream, &g, 1);
 }
 hipError_t query_stream(gz_graph* g, hipStream_t* out);
-gz_tuning default_tuning(uint32_t P, uint32_t B);
+gz_tuning default_tuning(uint32_t P, uint32_t B, bool wide);
 
 // ingest path (gz_ingest.hip)
 gz_status ingest_fused(gz_graph* const* gs, uint32_t G, const uint64_t* offs_host,
@@ -214,7 +242,7 @@ gz_status update_node_batch(gz_graph* g, uint32_t node, const uint32_t* nbrs, ui
 void free_ingest_scratch(IngestScratch& S);
 
 // dynamic LDS of an update launch, and raising a kernel's LDS limit above 64 KiB
-size_t update_smem_bytes(uint32_t DL, uint32_t Pmax);
+size_t update_smem_bytes(uint32_t DL, uint32_t Pmax, bool wide = false);
 gz_status set_smem_limit(const void* fn, size_t bytes);
 #define GZ_TRY(call)                  \
     do {                              \
@@ -228,6 +256,7 @@ gz_status set_smem_limit(const void* fn, size_t bytes);
 struct UpdateLaunch {
     uint32_t wg, grid, lds_rows;
     size_t smem;
+    bool wide;
 };
 gz_status group_only(gz_graph* g, const uint32_t* src, const uint32_t* dst, uint64_t N,
                      uint32_t flags, hipStream_t stream, UpdateLaunch* out);

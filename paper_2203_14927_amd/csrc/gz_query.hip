@@ -24,7 +24,8 @@ struct QueryScratch {
     int device = -1;
     uint32_t cap_nodes = 0, cap_graphs = 0, cap_wpr = 0;
     uint32_t *comp = nullptr, *L = nullptr, *L2 = nullptr, *A = nullptr, *slot = nullptr;
-    uint32_t *done = nullptr, *hook = nullptr, *hedge = nullptr, *s = nullptr, *s2 = nullptr;
+    uint32_t *done = nullptr, *hook = nullptr, *s = nullptr, *s2 = nullptr;
+    uint64_t* hedge = nullptr;  // index of each component's hook edge
     uint32_t *m = nullptr, *m2 = nullptr, *rootOf = nullptr, *newlab = nullptr, *merged = nullptr;
     uint32_t *gof = nullptr, *acc = nullptr, *ctl = nullptr, *labels = nullptr;
     uint32_t *gcount = nullptr, *gfail = nullptr, *foff = nullptr, *fcur = nullptr;
@@ -41,7 +42,20 @@ struct QueryScratch {
 // Q_STOP is set at the end of the first round with no active component; every
 // round kernel then returns at once, so the host may enqueue rounds ahead of
 // the device without waiting for each round's outcome.
-enum : uint32_t { Q_NL = 0, Q_NA = 1, Q_NL2 = 2, Q_NF = 3, Q_STOP = 4, Q_ROUNDS = 5 };
+// Q_MULTI: the query spans several graphs; a forest key is then (graph << 32 |
+// index), else the 64-bit index alone (wide graphs are queried one at a time).
+enum : uint32_t { Q_NL = 0, Q_NA = 1, Q_NL2 = 2, Q_NF = 3, Q_STOP = 4, Q_ROUNDS = 5, Q_MULTI = 6 };
+
+__device__ __forceinline__ uint64_t forest_key(const uint32_t* __restrict__ ctl, uint32_t graph,
+                                               uint64_t idx) {
+    return ctl[Q_MULTI] ? ((uint64_t)graph << 32) | idx : idx;
+}
+__device__ __forceinline__ uint32_t key_graph(const uint32_t* __restrict__ ctl, uint64_t key) {
+    return ctl[Q_MULTI] ? (uint32_t)(key >> 32) : 0u;
+}
+__device__ __forceinline__ uint64_t key_index(const uint32_t* __restrict__ ctl, uint64_t key) {
+    return ctl[Q_MULTI] ? (key & 0xFFFFFFFFull) : key;
+}
 
 // ---------------------------------------------------------------- kernels --
 
@@ -67,6 +81,7 @@ __global__ void k_q_init(uint32_t T, const GraphDesc* __restrict__ gd, uint32_t 
         ctl[Q_NF] = 0;
         ctl[Q_STOP] = 0;
         ctl[Q_ROUNDS] = 0;
+        ctl[Q_MULTI] = G > 1 ? 1u : 0u;
     }
     if (v < T) {
         comp[v] = v;
@@ -131,8 +146,8 @@ __global__ __launch_bounds__(256) void k_q_reduce(uint32_t r, uint32_t T,
         s_slot[threadIdx.x] = sl;
         const GraphDesc& g = gd[gof[v]];
         s_base[threadIdx.x] = g.sk + (uint64_t)(v - g.node_base) * g.node_words +
-                              (g.round_view ? 0u : sk_word(g.B, r, 0, 0, 0));
-        s_words[threadIdx.x] = kPlanes * g.B * kC;
+                              (g.round_view ? 0u : sk_word_n(g.planes, g.B, r, 0, 0, 0));
+        s_words[threadIdx.x] = g.planes * g.B * kC;
     }
     __syncthreads();
     {
@@ -187,35 +202,60 @@ __device__ __forceinline__ void query_component(uint32_t r, uint32_t gtid, uint3
                                                 const GraphDesc* __restrict__ gd,
                                                 const uint32_t* __restrict__ comp,
                                                 uint32_t* __restrict__ hook,
-                                                uint32_t* __restrict__ hedge,
+                                                uint64_t* __restrict__ hedge,
                                                 uint32_t* __restrict__ done) {
     const uint32_t a = gtid >> 3;
     const uint32_t c = gtid & 7;
     const bool valid = a < nA;
-    uint32_t X = 0, key = kNone, alpha_best = 0, nonempty = 0;
+    uint32_t X = 0, key = kNone, nonempty = 0;
+    uint64_t alpha_best = 0;
     if (valid) {
         X = A[a];
         const GraphDesc g = gd[gof[X]];
         const uint32_t p = r * kC + c;
-        const PairSeeds s = load_pair_seeds(g.seeds, g.P, p);
         const uint32_t B = g.B;
         // word (plane, row b) of column c: stride between rows of one plane
         const uint32_t* in;
         if (kDirect)
             in = g.sk + (uint64_t)(X - g.node_base) * g.node_words +
-                 (g.round_view ? c : sk_word(B, r, 0, 0, c));
+                 (g.round_view ? c : sk_word_n(g.planes, B, r, 0, 0, c));
         else
             in = acc + (uint64_t)a * wpr + c;
-        uint32_t al = 0, glo = 0, ghi = 0;
-        for (int b = (int)B - 1; b >= 0; --b) {
-            al ^= in[(0 * B + b) * kC];
-            glo ^= in[(1 * B + b) * kC];
-            ghi ^= in[(2 * B + b) * kC];
-            if (al | glo | ghi) {
-                nonempty = 1;
-                if ((uint64_t)al < g.n && chk_lo(s, al) == glo && chk_hi(s, al) == ghi) {
-                    key = c * B + (uint32_t)b;
-                    alpha_best = al;
+        if (!g.wide) {
+            const PairSeeds s = load_pair_seeds(g.seeds, g.P, p);
+            uint32_t al = 0, glo = 0, ghi = 0;
+            for (int b = (int)B - 1; b >= 0; --b) {
+                al ^= in[(0 * B + b) * kC];
+                glo ^= in[(1 * B + b) * kC];
+                ghi ^= in[(2 * B + b) * kC];
+                if (al | glo | ghi) {
+                    nonempty = 1;
+                    if ((uint64_t)al < g.n && chk_lo(s, al) == glo && chk_hi(s, al) == ghi) {
+                        key = c * B + (uint32_t)b;
+                        alpha_best = al;
+                    }
+                }
+            }
+        } else {
+            // 64-bit alpha; the checksum is of the pair the index encodes
+            const WideSeeds s = load_wide_seeds(g.seeds, g.P, p);
+            uint32_t al = 0, ah = 0, glo = 0, ghi = 0;
+            for (int b = (int)B - 1; b >= 0; --b) {
+                al ^= in[(0 * B + b) * kC];
+                ah ^= in[(1 * B + b) * kC];
+                glo ^= in[(2 * B + b) * kC];
+                ghi ^= in[(3 * B + b) * kC];
+                if (al | ah | glo | ghi) {
+                    nonempty = 1;
+                    const uint64_t i = ((uint64_t)ah << 32) | al;
+                    if (i < g.n) {
+                        uint32_t u, v;
+                        edge_pair64(i, &u, &v);
+                        if (pair_hash(s.h[2], u, v) == glo && pair_hash(s.h[1], u, v) == ghi) {
+                            key = c * B + (uint32_t)b;
+                            alpha_best = i;
+                        }
+                    }
                 }
             }
         }
@@ -223,9 +263,13 @@ __device__ __forceinline__ void query_component(uint32_t r, uint32_t gtid, uint3
     // reduce over the 8 lanes of this component: smallest key, any non-empty
     for (uint32_t off = 1; off < 8; off <<= 1) {
         const uint32_t k2 = __shfl_xor(key, off, 8);
-        const uint32_t a2 = __shfl_xor(alpha_best, off, 8);
+        const uint32_t alo2 = __shfl_xor((uint32_t)alpha_best, off, 8);
+        const uint32_t ahi2 = __shfl_xor((uint32_t)(alpha_best >> 32), off, 8);
         const uint32_t n2 = __shfl_xor(nonempty, off, 8);
-        if (k2 < key) { key = k2; alpha_best = a2; }
+        if (k2 < key) {
+            key = k2;
+            alpha_best = ((uint64_t)ahi2 << 32) | alo2;
+        }
         nonempty |= n2;
     }
     if (!valid || c != 0) return;
@@ -235,7 +279,7 @@ __device__ __forceinline__ void query_component(uint32_t r, uint32_t gtid, uint3
     }
     if (key == kNone) return;  // FAIL
     uint32_t u, v;
-    edge_pair(alpha_best, &u, &v);
+    edge_pair64(alpha_best, &u, &v);
     const GraphDesc g = gd[gof[X]];
     const uint32_t cu = comp[g.node_base + u], cv = comp[g.node_base + v];
     const bool iu = cu == X, iv = cv == X;
@@ -252,7 +296,7 @@ __global__ void k_q_query(uint32_t r, const uint32_t* __restrict__ A, const uint
                           const uint32_t* __restrict__ acc, uint32_t wpr,
                           const uint32_t* __restrict__ gof, const GraphDesc* __restrict__ gd,
                           const uint32_t* __restrict__ comp, uint32_t* __restrict__ hook,
-                          uint32_t* __restrict__ hedge, uint32_t* __restrict__ done) {
+                          uint64_t* __restrict__ hedge, uint32_t* __restrict__ done) {
     if (ctl[Q_STOP]) return;
     const uint32_t nA = ctl[Q_NA];
     const uint64_t lanes = (uint64_t)nA * 8;
@@ -322,7 +366,7 @@ __global__ __launch_bounds__(1024) void k_q_double_all(const uint32_t* __restric
 // that cycle's smallest component: the root of X's tree once its edge is cut
 __global__ void k_q_root(const uint32_t* __restrict__ L, uint32_t* __restrict__ ctl,
                          const uint32_t* __restrict__ s, const uint32_t* __restrict__ m,
-                         const uint32_t* __restrict__ hook, const uint32_t* __restrict__ hedge,
+                         const uint32_t* __restrict__ hook, const uint64_t* __restrict__ hedge,
                          const uint32_t* __restrict__ gof, uint32_t* __restrict__ rootOf,
                          uint32_t* __restrict__ newlab, uint32_t* __restrict__ merged,
                          uint64_t* __restrict__ forest, uint32_t lds_cap) {
@@ -337,7 +381,7 @@ __global__ void k_q_root(const uint32_t* __restrict__ L, uint32_t* __restrict__ 
         if (hook[X] != kNone && X != R) {
             merged[R] = 1;
             const uint32_t f = atomicAdd(&ctl[Q_NF], 1u);
-            forest[f] = ((uint64_t)gof[X] << 32) | hedge[X];
+            forest[f] = forest_key(ctl, gof[X], hedge[X]);
         }
     }
 }
@@ -353,7 +397,7 @@ constexpr uint32_t kLdsResolve = 16384;
 
 __global__ __launch_bounds__(1024) void k_q_resolve_lds(
     const uint32_t* __restrict__ L, uint32_t* __restrict__ ctl, uint32_t K,
-    const uint32_t* __restrict__ hook, const uint32_t* __restrict__ hedge,
+    const uint32_t* __restrict__ hook, const uint64_t* __restrict__ hedge,
     const uint32_t* __restrict__ pos, const uint32_t* __restrict__ gof,
     uint32_t* __restrict__ rootOf, uint32_t* __restrict__ newlab, uint32_t* __restrict__ merged,
     uint64_t* __restrict__ forest) {
@@ -385,7 +429,7 @@ __global__ __launch_bounds__(1024) void k_q_resolve_lds(
         if (hook[X] != kNone && X != R) {
             merged[R] = 1;
             const uint32_t f = atomicAdd(&ctl[Q_NF], 1u);
-            forest[f] = ((uint64_t)gof[X] << 32) | hedge[X];
+            forest[f] = forest_key(ctl, gof[X], hedge[X]);
         }
     }
 }
@@ -457,13 +501,12 @@ __global__ void k_q_labels(uint32_t T, const uint32_t* __restrict__ comp,
         out[v] = comp[v] - gd[gof[v]].node_base;
 }
 
-// forest: count per graph, scan, scatter into per-graph segments, then rank
-// each key inside its segment (keys are distinct) to sort by edge index
+// forest: keys per graph (their offsets in the output), then the keys sorted
 __global__ void k_q_fcount(const uint64_t* __restrict__ forest, const uint32_t* __restrict__ ctl,
                            uint32_t* __restrict__ fcnt) {
     const uint32_t nF = ctl[Q_NF];
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nF; i += gridDim.x * blockDim.x)
-        atomicAdd(&fcnt[(uint32_t)(forest[i] >> 32)], 1u);
+        atomicAdd(&fcnt[key_graph(ctl, forest[i])], 1u);
 }
 
 __global__ void k_q_fscan(const uint32_t* __restrict__ fcnt, uint32_t G, uint32_t* __restrict__ foff,
@@ -480,56 +523,75 @@ __global__ void k_q_fscan(const uint32_t* __restrict__ fcnt, uint32_t G, uint32_
     }
 }
 
-__global__ void k_q_fscatter(const uint64_t* __restrict__ forest, const uint32_t* __restrict__ ctl,
-                             uint32_t* __restrict__ fcur, uint64_t* __restrict__ out) {
+constexpr uint32_t kMaxRounds = 64;  // R <= 25 for V <= 2^24
+constexpr uint32_t kSingleBlockDoubling = 65536;  // component lists up to this length
+
+// The forest keys (distinct: the graph above the edge index when several graphs
+// are queried) are sorted ascending, which orders them by graph and, within a
+// graph, by edge index: tiles of kFTile keys are sorted in LDS by a bitonic
+// network, then runs of width w, 2w, ... are merged pairwise, each key placed
+// at its index in its run plus the number of keys of the partner run below it
+// (a binary search), so every pass is one read and one write per key.
+constexpr uint32_t kFTile = 2048;
+
+__global__ __launch_bounds__(1024) void k_q_fsort_tile(uint64_t* __restrict__ keys,
+                                                         const uint32_t* __restrict__ ctl) {
+    __shared__ uint64_t t[kFTile];
+    const uint32_t nF = ctl[Q_NF];
+    const uint32_t base = blockIdx.x * kFTile;
+    if (base >= nF) return;
+    const uint32_t n = min(kFTile, nF - base);
+    for (uint32_t i = threadIdx.x; i < kFTile; i += blockDim.x)
+        t[i] = i < n ? keys[base + i] : ~0ull;
+    __syncthreads();
+    for (uint32_t k = 2; k <= kFTile; k <<= 1) {
+        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+            for (uint32_t q = threadIdx.x; q < kFTile / 2; q += blockDim.x) {
+                const uint32_t i = 2 * q - (q & (j - 1));  // lower element of the pair
+                const uint64_t x = t[i], y = t[i + j];
+                const bool up = (i & k) == 0;
+                if ((x > y) == up) {
+                    t[i] = y;
+                    t[i + j] = x;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) keys[base + i] = t[i];
+}
+
+__global__ void k_q_fmerge(const uint64_t* __restrict__ in, uint64_t* __restrict__ out,
+                           const uint32_t* __restrict__ ctl, uint32_t w) {
     const uint32_t nF = ctl[Q_NF];
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nF; i += gridDim.x * blockDim.x) {
-        const uint64_t k = forest[i];
-        out[atomicAdd(&fcur[(uint32_t)(k >> 32)], 1u)] = k;
+        const uint32_t run = i / w;
+        const uint32_t a0 = (run & ~1u) * w;
+        const uint32_t b0 = min(a0 + w, nF), b1 = min(b0 + w, nF);
+        const uint64_t x = in[i];
+        // the partner run: B for keys of A, A for keys of B
+        uint32_t lo = (run & 1u) ? a0 : b0;
+        uint32_t hi = (run & 1u) ? b0 : b1;
+        const uint32_t first = lo;
+        while (lo < hi) {  // first partner key above x (keys are distinct)
+            const uint32_t mid = (lo + hi) >> 1;
+            if (in[mid] < x) lo = mid + 1;
+            else hi = mid;
+        }
+        const uint32_t own = (run & 1u) ? i - b0 : i - a0;
+        out[a0 + own + (lo - first)] = x;
     }
 }
 
-constexpr uint32_t kRankThreads = 256;
-constexpr uint32_t kMaxRounds = 64;  // R <= 17 for V <= 2^16
-constexpr uint32_t kSingleBlockDoubling = 65536;  // component lists up to this length
-
-__global__ __launch_bounds__(kRankThreads) void k_q_frank(const uint64_t* __restrict__ keys,
-                                                           const uint32_t* __restrict__ ctl,
-                                                           const uint32_t* __restrict__ foff,
-                                                           uint32_t* __restrict__ pairs) {
-    __shared__ uint64_t tile[kRankThreads];
-    __shared__ uint32_t s_lo, s_hi;
+// sorted keys -> (u, v) pairs
+__global__ void k_q_fpairs(const uint64_t* __restrict__ keys, const uint32_t* __restrict__ ctl,
+                           uint32_t* __restrict__ pairs) {
     const uint32_t nF = ctl[Q_NF];
-    const uint32_t i0 = blockIdx.x * kRankThreads;
-    if (i0 >= nF) return;
-    const uint32_t i = i0 + threadIdx.x;
-    const bool valid = i < nF;
-    const uint64_t key = valid ? keys[i] : 0;
-    const uint32_t g = (uint32_t)(key >> 32);
-    const uint32_t lo = valid ? foff[g] : 0, hi = valid ? foff[g + 1] : 0;
-    if (threadIdx.x == 0) {
-        s_lo = foff[(uint32_t)(keys[i0] >> 32)];
-        const uint32_t last = min(i0 + kRankThreads, nF) - 1;
-        s_hi = foff[(uint32_t)(keys[last] >> 32) + 1];
-    }
-    __syncthreads();
-    uint32_t rank = 0;
-    for (uint32_t j0 = s_lo; j0 < s_hi; j0 += kRankThreads) {
-        const uint32_t j = j0 + threadIdx.x;
-        tile[threadIdx.x] = j < s_hi ? keys[j] : ~0ull;
-        __syncthreads();
-        const uint32_t n = min(kRankThreads, s_hi - j0);
-        for (uint32_t t = 0; t < n; ++t) {
-            const uint32_t jj = j0 + t;
-            if (jj >= lo && jj < hi && tile[t] < key) ++rank;
-        }
-        __syncthreads();
-    }
-    if (valid) {
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nF; i += gridDim.x * blockDim.x) {
         uint32_t u, v;
-        edge_pair((uint32_t)key, &u, &v);
-        pairs[2 * (lo + rank)] = u;
-        pairs[2 * (lo + rank) + 1] = v;
+        edge_pair64(key_index(ctl, keys[i]), &u, &v);
+        pairs[2 * i] = u;
+        pairs[2 * i + 1] = v;
     }
 }
 
@@ -554,12 +616,13 @@ gz_status ensure_query(QueryScratch& Q, uint32_t T, uint32_t G, uint32_t wpr) {
     Q.device = dev;
     gz_status st;
     if (T > Q.cap_nodes || !Q.comp) {
-        uint32_t** arrs[] = {&Q.comp, &Q.L, &Q.L2, &Q.A, &Q.slot, &Q.done, &Q.hook, &Q.hedge,
+        uint32_t** arrs[] = {&Q.comp, &Q.L, &Q.L2, &Q.A, &Q.slot, &Q.done, &Q.hook,
                              &Q.s, &Q.s2, &Q.m, &Q.m2, &Q.rootOf, &Q.newlab, &Q.merged, &Q.gof,
                              &Q.labels, &Q.pos};
         for (auto a : arrs)
             if ((st = qalloc(a, T))) return st;
         if ((st = qalloc(&Q.fpairs, 2ull * T))) return st;
+        if ((st = qalloc(&Q.hedge, T))) return st;
         if ((st = qalloc(&Q.forest, T))) return st;
         if ((st = qalloc(&Q.fsorted, T))) return st;
         if (!Q.ctl && (st = qalloc(&Q.ctl, 8))) return st;
@@ -602,7 +665,8 @@ uint32_t bitlen32(uint32_t x) {
 
 void free_query_scratch(QueryScratch* q) {
     if (!q) return;
-    uint32_t* arrs[] = {q->comp, q->L, q->L2, q->A, q->slot, q->done, q->hook, q->hedge, q->s,
+    hipFree(q->hedge);
+    uint32_t* arrs[] = {q->comp, q->L, q->L2, q->A, q->slot, q->done, q->hook, q->s,
                         q->s2, q->m, q->m2, q->rootOf, q->newlab, q->merged, q->gof, q->acc,
                         q->ctl, q->labels, q->gcount, q->gfail, q->foff, q->fcur, q->fpairs,
                         q->fcnt, q->pos};
@@ -629,7 +693,7 @@ gz_status boruvka(gz_graph* const* gs, uint32_t G, bool want_forest, QueryResult
     if (G == 0) return fail(GZ_EINVAL, "no graphs");
     std::vector<GraphDesc> descs(G);
     uint64_t T64 = 0;
-    uint32_t Rmax = 0, Bmax = 0, Vmax = 0;
+    uint32_t Rmax = 0, Bmax = 0, Vmax = 0, PLmax = 0;
     for (uint32_t k = 0; k < G; ++k) {
         const gz_graph* g = gs[k];
         if (!g) return fail(GZ_EINVAL, "null graph handle");
@@ -642,11 +706,16 @@ gz_status boruvka(gz_graph* const* gs, uint32_t G, bool want_forest, QueryResult
         descs[k].B = g->B;
         descs[k].P = g->P;
         descs[k].node_base = (uint32_t)T64;
-        descs[k].node_words = kPlanes * g->B * g->P;
+        descs[k].node_words = g->planes * g->B * g->P;
+        descs[k].wide = g->wide;
+        descs[k].planes = g->planes;
         T64 += g->V;
         Rmax = std::max(Rmax, g->R);
         Bmax = std::max(Bmax, g->B);
         Vmax = std::max(Vmax, g->V);
+        PLmax = std::max(PLmax, g->planes);
+        if (G > 1 && g->wide)
+            return fail(GZ_EINVAL, "graphs with V > 65536 are queried one at a time");
     }
     if (T64 >= (1ull << 31)) return fail(GZ_EINVAL, "too many nodes in one query");
     // a host-tier graph is queried alone: every round its round slabs are
@@ -658,7 +727,7 @@ gz_status boruvka(gz_graph* const* gs, uint32_t G, bool want_forest, QueryResult
             if (gs[k]->tier) return fail(GZ_EINVAL, "host-tier graphs are queried one at a time");
     if (Rmax > kMaxRounds) return fail(GZ_EINVAL, "too many rounds");
     const uint32_t T = (uint32_t)T64;
-    const uint32_t wpr = kPlanes * Bmax * kC;
+    const uint32_t wpr = PLmax * Bmax * kC;
 
     // single graphs keep their own scratch; fused queries share one per device
     std::unique_lock<std::mutex> lock;
@@ -681,7 +750,7 @@ gz_status boruvka(gz_graph* const* gs, uint32_t G, bool want_forest, QueryResult
         uint32_t* buf = nullptr;
         GZ_TRY(tier_round(tier_g, 0, qs, &buf));
         descs[0].sk = buf;
-        descs[0].node_words = kPlanes * tier_g->B * kC;
+        descs[0].node_words = tier_g->planes * tier_g->B * kC;
         descs[0].round_view = 1;
     }
     GZ_HIP(hipMemcpyAsync(Q->descs, descs.data(), sizeof(GraphDesc) * G, hipMemcpyHostToDevice, qs));
@@ -769,9 +838,17 @@ gz_status boruvka(gz_graph* const* gs, uint32_t G, bool want_forest, QueryResult
         GZ_HIP(hipMemsetAsync(Q->fcnt, 0, 4ull * G, qs));
         k_q_fcount<<<tb, 256, 0, qs>>>(Q->forest, Q->ctl, Q->fcnt);
         k_q_fscan<<<1, 1, 0, qs>>>(Q->fcnt, G, Q->foff, Q->fcur);
-        k_q_fscatter<<<tb, 256, 0, qs>>>(Q->forest, Q->ctl, Q->fcur, Q->fsorted);
-        k_q_frank<<<(T + kRankThreads - 1) / kRankThreads, kRankThreads, 0, qs>>>(
-            Q->fsorted, Q->ctl, Q->foff, Q->fpairs);
+        // passes for the largest possible forest; kernels past the device's
+        // count return at once
+        const uint32_t fgrid = blocks_for(T, 256) < 2048 ? blocks_for(T, 256) : 2048;
+        k_q_fsort_tile<<<(T + kFTile - 1) / kFTile, 1024, 0, qs>>>(Q->forest, Q->ctl);
+        uint64_t* fin = Q->forest;
+        uint64_t* fout = Q->fsorted;
+        for (uint64_t w = kFTile; w < T; w <<= 1) {
+            k_q_fmerge<<<fgrid, 256, 0, qs>>>(fin, fout, Q->ctl, (uint32_t)w);
+            std::swap(fin, fout);
+        }
+        k_q_fpairs<<<fgrid, 256, 0, qs>>>(fin, Q->ctl, Q->fpairs);
     }
     GZ_HIP(hipGetLastError());
     GZ_HIP(hipStreamSynchronize(qs));

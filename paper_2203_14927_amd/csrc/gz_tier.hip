@@ -80,8 +80,11 @@ GraphDesc slab_desc(const gz_graph* g, uint32_t* sk, uint32_t first_node) {
     d.R = g->R;
     d.B = g->B;
     d.P = g->P;
-    d.node_base = first_node;
-    d.node_words = kPlanes * g->B * g->P;
+    d.node_base = 0;  // the graph is alone in its launches
+    d.sk_first = first_node;
+    d.node_words = g->planes * g->B * g->P;
+    d.wide = g->wide;
+    d.planes = g->planes;
     return d;
 }
 
@@ -90,7 +93,7 @@ GraphDesc slab_desc(const gz_graph* g, uint32_t* sk, uint32_t first_node) {
 gz_status tier_create(gz_graph* g, uint64_t staging_bytes) {
     HostTier* t = new HostTier();
     g->tier = t;
-    t->node_words = (uint64_t)kPlanes * g->B * g->P;
+    t->node_words = (uint64_t)g->planes * g->B * g->P;
     const uint64_t node_bytes = t->node_words * 4;
     const uint64_t budget = staging_bytes ? staging_bytes : kDefaultStaging;
     t->slab_nodes = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(g->V, budget / 2 / node_bytes));
@@ -164,7 +167,8 @@ gz_status tier_ingest(gz_graph* g, const uint32_t* src, const uint32_t* dst, uin
     }
     GZ_HIP(hipMemcpyAsync(t->d_descs, t->h_descs, sizeof(GraphDesc) * t->nslabs,
                           hipMemcpyHostToDevice, stream));
-    GZ_TRY(set_smem_limit((const void*)k_update, U.smem));
+    const void* upd = U.wide ? (const void*)k_update_wide : (const void*)k_update;
+    GZ_TRY(set_smem_limit(upd, U.smem));
     const uint64_t node_bytes = t->node_words * 4;
     buf = 0;
     for (uint32_t k = 0; k < t->nslabs; ++k) {
@@ -178,8 +182,12 @@ gz_status tier_ingest(gz_graph* g, const uint32_t* src, const uint32_t* dst, uin
         GZ_HIP(hipEventRecord(t->in_ev[buf], t->h2d));
         GZ_HIP(hipStreamWaitEvent(stream, t->in_ev[buf], 0));
         k_tier_slab_ctl<<<1, 64, 0, stream>>>(t->d_slab_ctl + 4 * k, ib - ia);
-        k_update<<<U.grid, U.wg, U.smem, stream>>>(S.items + ia, t->d_slab_ctl + 4 * k, S.grouped,
-                                                   t->d_descs + k, U.lds_rows);
+        if (U.wide)
+            k_update_wide<<<U.grid, U.wg, U.smem, stream>>>(S.items + ia, t->d_slab_ctl + 4 * k,
+                                                            S.grouped, t->d_descs + k, U.lds_rows);
+        else
+            k_update<<<U.grid, U.wg, U.smem, stream>>>(S.items + ia, t->d_slab_ctl + 4 * k,
+                                                       S.grouped, t->d_descs + k, U.lds_rows);
         GZ_HIP(hipGetLastError());
         GZ_HIP(hipEventRecord(t->upd_ev[buf], stream));
         GZ_HIP(hipStreamWaitEvent(t->d2h, t->upd_ev[buf], 0));
@@ -206,11 +214,16 @@ gz_status tier_update_node(gz_graph* g, uint32_t node, const uint32_t* nbrs, uin
     const GraphDesc gd = slab_desc(g, t->stage[0], node);
     const uint32_t chunk = tune.chunk;
     const uint32_t DL = std::min(tune.lds_rows, g->B);
-    const size_t smem = update_smem_bytes(DL, g->P);
-    GZ_TRY(set_smem_limit((const void*)k_update_node, smem));
+    const size_t smem = update_smem_bytes(DL, g->P, g->wide);
+    const void* fn = g->wide ? (const void*)k_update_node_wide : (const void*)k_update_node;
+    GZ_TRY(set_smem_limit(fn, smem));
     const uint32_t grid = (count + chunk - 1) / chunk;
-    k_update_node<<<grid, tune.wg_size, smem, stream>>>(nbrs, count, node, gd, tune.lds_rows, chunk,
-                                                          errp);
+    if (g->wide)
+        k_update_node_wide<<<grid, tune.wg_size, smem, stream>>>(nbrs, count, node, gd,
+                                                                   tune.lds_rows, chunk, errp);
+    else
+        k_update_node<<<grid, tune.wg_size, smem, stream>>>(nbrs, count, node, gd, tune.lds_rows,
+                                                              chunk, errp);
     GZ_HIP(hipGetLastError());
     GZ_HIP(hipMemcpyAsync(host, t->stage[0], bytes, hipMemcpyDeviceToHost, stream));
     GZ_HIP(hipEventRecord(t->out_ev[0], stream));
@@ -239,14 +252,14 @@ gz_status tier_fetch(gz_graph* g, uint32_t lo, uint32_t hi, hipStream_t stream, 
 
 gz_status tier_round(gz_graph* g, uint32_t r, hipStream_t stream, uint32_t** round_buf) {
     HostTier* t = g->tier;
-    const uint64_t slab = (uint64_t)kPlanes * g->B * kC;  // words of one round of one node
+    const uint64_t slab = (uint64_t)g->planes * g->B * kC;  // words of one round of one node
     if (!t->round_buf) {
         if (hipMalloc((void**)&t->round_buf, g->V * slab * 4) != hipSuccess) {
             t->round_buf = nullptr;
             return fail(GZ_ENOMEM, "out of device memory for the query round buffer");
         }
     }
-    GZ_HIP(hipMemcpy2DAsync(t->round_buf, slab * 4, t->h_sk + sk_word(g->B, r, 0, 0, 0),
+    GZ_HIP(hipMemcpy2DAsync(t->round_buf, slab * 4, t->h_sk + sk_word_n(g->planes, g->B, r, 0, 0, 0),
                             t->node_words * 4, slab * 4, g->V, hipMemcpyHostToDevice, stream));
     *round_buf = t->round_buf;
     return GZ_OK;

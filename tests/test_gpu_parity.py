@@ -156,7 +156,7 @@ def test_invalid_updates_rejected_and_nothing_applied(gz):
     with pytest.raises(gz.GzError):
         gz.Graph(1, seed=1)
     with pytest.raises(gz.GzError):
-        gz.Graph(65537, seed=1)
+        gz.Graph((1 << 24) + 1, seed=1)
 
 
 def test_empty_and_isolated(gz):

@@ -42,6 +42,11 @@ PEAK_HBM_GBS = 8000.0
 # edge index (row hash 3, 64-bit checksum 6, depth 2) counted once per update,
 # plus one exact-depth XOR of (alpha, gamma) per endpoint (4 each)
 OPS_PER_UPDATE_PAIR = 19
+# the same for graphs with V > 2^16, whose three hashes are keyed by the node
+# pair (a*u + a2*v + b: two 64x32-bit multiply-adds and two 32-bit high-word
+# products with their adds, 6 each), depth 2, and XORs of four 32-bit planes
+# per endpoint (4 each)
+OPS_PER_UPDATE_PAIR_WIDE = 28
 
 
 def log(msg: str) -> None:
@@ -56,6 +61,11 @@ def make_workload(name: str):
         desc = ("R-MAT V=2^14 (a,b,c,d=0.57,0.19,0.19,0.05, seed 2): ~50M distinct inserts then "
                 "10% live deletes")
         return s, 2, desc
+    if name == "rmat_kron18":
+        s = workloads.rmat_draws(1 << 18, workloads.RMAT_GRAPH500, 1 << 28, 18)
+        desc = ("R-MAT V=2^18 (a,b,c,d=0.57,0.19,0.19,0.05, seed 18): 2^28 raw draws, a pair "
+                "drawn again toggles its edge (pair-keyed contract, R=19, B=33)")
+        return s, 18, desc
     if name == "uniform_small":
         s = workloads.config_uniform_small()
         return s, 1, "uniform V=1024: 150k inserts then 50k deletes (seed 1)"
@@ -502,9 +512,10 @@ def run_single(args) -> dict:
     grp_ms = statistics.median(p["group_ms"] for p in profs)
     ing_ms = statistics.median(p["ingest_ms"] for p in profs)
     P = g.R * g.C
-    ops = stream.N * P * OPS_PER_UPDATE_PAIR
+    opp = OPS_PER_UPDATE_PAIR_WIDE if stream.V > 65536 else OPS_PER_UPDATE_PAIR
+    ops = stream.N * P * opp
     achieved = ops / (upd_ms * 1e-3) / 1e12
-    traffic = traffic_from_profile(kernel_source_hash())
+    traffic = traffic_from_profile(kernel_source_hash()) if args.workload == "rmat_dense" else None
 
     out = {
         "metric": "edge updates/sec ingested (1 MI355X), batched vs plain; CC query ms; p99 latency",
@@ -533,9 +544,9 @@ def run_single(args) -> dict:
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_INT_TOPS,
                      "unit": "TOP/s", "frac": achieved / PEAK_INT_TOPS,
                      "traffic": traffic,
-                     "kernel": "k_update",
+                     "kernel": "k_update_wide" if stream.V > 65536 else "k_update",
                      "ops_per_launch": ops,
-                     "ops_rule": f"{OPS_PER_UPDATE_PAIR} int ops per (update, round-column pair), "
+                     "ops_rule": f"{opp} int ops per (update, round-column pair), "
                                  f"{P} pairs per update"},
     }
     if not args.no_plain:

@@ -111,7 +111,7 @@ hipError_t fence_record(hipStream_t stream, gz_graph* const* gs, uint32_t G) {
 gz_tuning default_tuning(uint32_t P, uint32_t B, bool wide) {
     gz_tuning t{};
     t.chunk = 16384;
-    t.lds_rows = (B * tile_row_words(P, wide) * 4 <= 48 * 1024) ? B : std::min<uint32_t>(B, 16u);
+    t.lds_rows = (B * tile_row_words(P, wide) * 4 <= 48 * 1024) ? B : std::min<uint32_t>(B, 15u);
     uint32_t best = 0;
     double best_use = -1.0;
     for (uint32_t wg = 256; wg <= 512; wg += 64) {
@@ -123,7 +123,7 @@ gz_tuning default_tuning(uint32_t P, uint32_t B, bool wide) {
         }
     }
     t.wg_size = best ? best : std::min<uint32_t>(1024, (P + 63) / 64 * 64);
-    const uint32_t smem = std::min(t.lds_rows, B) * tile_row_words(P, wide) * 4;
+    const uint32_t smem = (uint32_t)update_smem_bytes(t.lds_rows, B, P, wide);
     t.wgs_per_cu = std::max<uint32_t>(1, std::min<uint32_t>(8, (160 * 1024) / smem));
     t.group_blocks = 0;
     return t;
@@ -486,7 +486,7 @@ gz_status gz_set_tuning(gz_graph* g, const gz_tuning* t) {
     if (t->lds_rows < 1) return fail(GZ_EINVAL, "lds_rows must be >= 1");
     if (t->chunk < 1 || t->chunk > (1u << 30)) return fail(GZ_EINVAL, "chunk must be in [1, 2^30]");
     if (t->wgs_per_cu < 1 || t->wgs_per_cu > 64) return fail(GZ_EINVAL, "wgs_per_cu in [1, 64]");
-    size_t smem = (size_t)std::min(t->lds_rows, g->B) * tile_row_words(g->P, g->wide) * 4;
+    size_t smem = update_smem_bytes(t->lds_rows, g->B, g->P, g->wide);
     if (smem > 160 * 1024) return fail(GZ_EINVAL, "LDS tile exceeds 160 KiB");
     g->tuning = *t;
     return GZ_OK;

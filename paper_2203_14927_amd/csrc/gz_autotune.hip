@@ -42,7 +42,7 @@ std::vector<gz_tuning> candidates(uint32_t P, uint32_t B, bool wide) {
     std::vector<gz_tuning> out;
     for (uint32_t wg : wg_list)
         for (uint32_t dl : rows) {
-            const uint32_t smem = dl * tile_row_words(P, wide) * 4;
+            const uint32_t smem = (uint32_t)update_smem_bytes(dl, B, P, wide);
             if (smem > 160 * 1024) continue;
             const uint32_t by_lds = std::max<uint32_t>(1, (160 * 1024) / smem);
             const uint32_t by_threads = std::max<uint32_t>(1, 2048 / wg);

@@ -519,7 +519,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_items(
                     w.gnode = (uint32_t)i;
                     w.graph = g;
                     w.shared = ni > 1 ? 1u : 0u;
-                    w.pad = 0;
+                    w.split = 0;
                     items[item0 + j] = w;
                 }
             }
@@ -643,8 +643,8 @@ gz_status ensure_scratch(IngestScratch& S, uint64_t N, uint32_t T, uint32_t G, u
 
 }  // namespace
 
-size_t update_smem_bytes(uint32_t DL, uint32_t Pmax, bool wide) {
-    return (size_t)DL * tile_row_words(Pmax, wide) * 4;
+size_t update_smem_bytes(uint32_t lds_rows, uint32_t Bmax, uint32_t Pmax, bool wide) {
+    return (size_t)tile_rows(lds_rows, Bmax) * tile_row_words(Pmax, wide) * 4;
 }
 
 gz_status set_smem_limit(const void* fn, size_t bytes) {
@@ -679,7 +679,7 @@ IngestScratch& shared_ingest_scratch(int device, std::unique_lock<std::mutex>& l
 // actual call, or the capacities of a captured plan).
 struct LaunchShape {
     uint32_t G = 0, T = 0, n_units = 0, nblocks = 0, range_max = 1, pgrid = 0;
-    uint32_t wg = 0, DLmax = 1, Pmax = 0, chunk = 0, lds_rows = 0, group_chunk = 0;
+    uint32_t wg = 0, DLmax = 1, Pmax = 0, Bmax = 0, chunk = 0, lds_rows = 0, group_chunk = 0;
     uint64_t H_size = 0, N = 0;
     bool all_rows = true;
     // two-pass placement (single large graph): bucket shift, buckets, chunks,
@@ -745,6 +745,7 @@ gz_status build_shape(gz_graph* const* gs, uint32_t G, const uint64_t* ranges, u
         L.H_size += (uint64_t)g->V * d.nb;
         T += g->V;
         L.Pmax = std::max(L.Pmax, g->P);
+        L.Bmax = std::max(L.Bmax, g->B);
         L.DLmax = std::max(L.DLmax, std::min(tune.lds_rows, g->B));
         L.all_rows = L.all_rows && tune.lds_rows >= g->B;
         L.range_max = std::max(L.range_max, std::min(g->V, kGroupRange));
@@ -772,7 +773,7 @@ gz_status build_shape(gz_graph* const* gs, uint32_t G, const uint64_t* ranges, u
     }
     L.nblocks = (uint32_t)((T + kScanTile - 1) / kScanTile);
     L.gsmem = (size_t)L.range_max * 4;
-    L.smem = update_smem_bytes(L.DLmax, L.Pmax, L.wide);
+    L.smem = update_smem_bytes(tune.lds_rows, L.Bmax, L.Pmax, L.wide);
     L.pgrid = std::max(1u, tune.wgs_per_cu) * cus;
     GZ_TRY(set_smem_limit((const void*)k_group_count, L.gsmem));
     GZ_TRY(set_smem_limit((const void*)k_group_scatter, L.gsmem));
@@ -823,10 +824,12 @@ gz_status launch_sequence(IngestScratch& S, const LaunchShape& L, hipStream_t st
         k_group_scatter<<<L.n_units, kGroupThreads, L.gsmem, stream>>>(S.args, S.units, S.descs,
                                                                        S.H, S.grouped, S.ctl);
     }
+    if (L.wide)  // neighbours below each item's node first, into the bucket array
+        k_split_items<<<L.pgrid, 256, 0, stream>>>(S.ctl, S.items, S.grouped, S.buckets, S.descs);
     if (prof) GZ_HIP(hipEventRecord(prof->prof_ev[1], stream));
     if (with_update && L.wide)
-        k_update_wide<<<L.pgrid, L.wg, L.smem, stream>>>(S.items, S.ctl, S.grouped, S.descs,
-                                                         L.lds_rows);
+        k_update_wide<<<L.pgrid, L.wg, L.smem, stream>>>(S.items, S.ctl, update_entries(S, true),
+                                                         S.descs, L.lds_rows);
     else if (with_update)
         k_update<<<L.pgrid, L.wg, L.smem, stream>>>(S.items, S.ctl, S.grouped, S.descs,
                                                     L.lds_rows);
@@ -900,7 +903,8 @@ gz_status ingest_fused(gz_graph* const* gs, uint32_t G, const uint64_t* offs_hos
     GZ_TRY(build_shape(gs, G, ranges.data(), N, L));
     const bool host_ptr = !(flags & GZ_DEVICE_PTR);
     GZ_TRY(ensure_scratch(S, N, L.T, G, L.chunk, L.H_size, L.n_units, host_ptr,
-                          L.two_pass ? 2 * N : 0, L.two_pass ? (uint64_t)(L.nbc + 1) * L.nbk : 0));
+                          L.two_pass || L.wide ? 2 * N : 0,
+                          L.two_pass ? (uint64_t)(L.nbc + 1) * L.nbk : 0));
 
     // order after earlier work on these graphs (e.g. a query on another stream)
     GZ_HIP(fence_wait(stream, gs, G));
@@ -935,7 +939,8 @@ gz_status group_only(gz_graph* g, const uint32_t* src, const uint32_t* dst, uint
     GZ_TRY(build_shape(gs, 1, ranges, N, L));
     const bool host_ptr = !(flags & GZ_DEVICE_PTR);
     GZ_TRY(ensure_scratch(S, N, L.T, 1, L.chunk, L.H_size, L.n_units, host_ptr,
-                          L.two_pass ? 2 * N : 0, L.two_pass ? (uint64_t)(L.nbc + 1) * L.nbk : 0));
+                          L.two_pass || L.wide ? 2 * N : 0,
+                          L.two_pass ? (uint64_t)(L.nbc + 1) * L.nbk : 0));
     GZ_HIP(fence_wait(stream, g));
     const uint32_t* dsrc = src;
     const uint32_t* ddst = dst;
@@ -1007,7 +1012,7 @@ gz_status update_node_batch(gz_graph* g, uint32_t node, const uint32_t* nbrs, ui
         gd.planes = g->planes;
         const uint32_t chunk = tune.chunk;
         const uint32_t DL = std::min(tune.lds_rows, g->B);
-        const size_t smem = update_smem_bytes(DL, g->P, g->wide);
+        const size_t smem = update_smem_bytes(tune.lds_rows, g->B, g->P, g->wide);
         const void* fn = g->wide ? (const void*)k_update_node_wide : (const void*)k_update_node;
         GZ_TRY(set_smem_limit(fn, smem));
         const uint32_t grid = (uint32_t)((count + chunk - 1) / chunk);
@@ -1075,7 +1080,7 @@ gz_status gz_plan_create(gz_graph* const* gs, uint32_t G, const uint64_t* caps, 
     gz_status st = build_shape(gs, G, ranges.data(), ranges[G], p->L);
     if (!st)
         st = ensure_scratch(p->S, ranges[G], p->L.T, G, p->L.chunk, p->L.H_size, p->L.n_units,
-                            false, p->L.two_pass ? 2 * ranges[G] : 0,
+                            false, p->L.two_pass || p->L.wide ? 2 * ranges[G] : 0,
                             p->L.two_pass ? (uint64_t)(p->L.nbc + 1) * p->L.nbk : 0);
     hipError_t e = hipSuccess;
     if (!st) {

@@ -78,7 +78,8 @@ struct WorkItem {
     uint32_t gnode;   // global node id
     uint32_t graph;   // index into the descriptor table
     uint32_t shared;  // 1 if other items of this launch update the same node
-    uint32_t pad;
+    uint32_t split;   // wide graphs: entries [begin, begin+split) are neighbours below the
+                      // node, the rest above it (set by k_split_items)
 };
 
 // One block of the grouping pass: chunk `c` of graph `g`'s updates, counted or
@@ -160,11 +161,20 @@ __global__ void k_update_wide(const WorkItem* __restrict__ items, uint32_t* __re
 __global__ void k_update_node_wide(const uint32_t* __restrict__ nbrs, uint32_t count,
                                    uint32_t node, GraphDesc g, uint32_t lds_rows, uint32_t chunk,
                                    const uint32_t* __restrict__ err);
-// LDS words of one tile row of P pairs (three planes interleaved, or four
-// with one pad word per 16 pairs so that lanes keep distinct banks)
+// orders each wide-graph work item's entries by side of the node (sets split)
+__global__ void k_split_items(const uint32_t* __restrict__ ctl, WorkItem* __restrict__ items,
+                              const uint32_t* __restrict__ grouped, uint32_t* __restrict__ out,
+                              const GraphDesc* __restrict__ gd);
+// the entries the update kernel reads after grouping: wide graphs take the
+// side-ordered copy
+inline const uint32_t* update_entries(const IngestScratch& S, bool wide) {
+    return wide ? S.buckets : S.grouped;
+}
+// LDS words of one tile row of P pairs (three planes, or four in blocks of 64
+// pairs)
 __host__ __device__ __forceinline__ uint32_t tile_row_words(uint32_t P, bool wide) {
     const uint32_t S = tile_stride(P);
-    return wide ? kPlanesWide * S + S / 16 : kPlanes * S;
+    return (wide ? kPlanesWide : kPlanes) * S;
 }
 
 // Completion marker of the last device work submitted on a graph.  One call
@@ -242,7 +252,13 @@ gz_status update_node_batch(gz_graph* g, uint32_t node, const uint32_t* nbrs, ui
 void free_ingest_scratch(IngestScratch& S);
 
 // dynamic LDS of an update launch, and raising a kernel's LDS limit above 64 KiB
-size_t update_smem_bytes(uint32_t DL, uint32_t Pmax, bool wide = false);
+// LDS rows of a tile for launches that keep up to lds_rows rows of graphs with
+// up to Bmax rows: every row when they fit, else lds_rows plus one sink row
+// that collects entries deeper than an item's rows (applied to HBM instead)
+__host__ __device__ __forceinline__ uint32_t tile_rows(uint32_t lds_rows, uint32_t Bmax) {
+    return lds_rows >= Bmax ? Bmax : lds_rows + 1;
+}
+size_t update_smem_bytes(uint32_t lds_rows, uint32_t Bmax, uint32_t Pmax, bool wide);
 gz_status set_smem_limit(const void* fn, size_t bytes);
 #define GZ_TRY(call)                  \
     do {                              \

@@ -184,7 +184,8 @@ gz_status tier_ingest(gz_graph* g, const uint32_t* src, const uint32_t* dst, uin
         k_tier_slab_ctl<<<1, 64, 0, stream>>>(t->d_slab_ctl + 4 * k, ib - ia);
         if (U.wide)
             k_update_wide<<<U.grid, U.wg, U.smem, stream>>>(S.items + ia, t->d_slab_ctl + 4 * k,
-                                                            S.grouped, t->d_descs + k, U.lds_rows);
+                                                            update_entries(S, true),
+                                                            t->d_descs + k, U.lds_rows);
         else
             k_update<<<U.grid, U.wg, U.smem, stream>>>(S.items + ia, t->d_slab_ctl + 4 * k,
                                                        S.grouped, t->d_descs + k, U.lds_rows);
@@ -214,7 +215,7 @@ gz_status tier_update_node(gz_graph* g, uint32_t node, const uint32_t* nbrs, uin
     const GraphDesc gd = slab_desc(g, t->stage[0], node);
     const uint32_t chunk = tune.chunk;
     const uint32_t DL = std::min(tune.lds_rows, g->B);
-    const size_t smem = update_smem_bytes(DL, g->P, g->wide);
+    const size_t smem = update_smem_bytes(tune.lds_rows, g->B, g->P, g->wide);
     const void* fn = g->wide ? (const void*)k_update_node_wide : (const void*)k_update_node;
     GZ_TRY(set_smem_limit(fn, smem));
     const uint32_t grid = (count + chunk - 1) / chunk;

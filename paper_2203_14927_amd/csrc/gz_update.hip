@@ -20,19 +20,22 @@ namespace gz {
 
 // ------------------------------------------------------------ sketch update --
 
-// The LDS tile interleaves the planes bucket by bucket: with three planes,
-// word (d * S + p) * 3 + plane holds plane `plane` of row d of pair p, so one
-// 24-bit multiply-add gives the address and the planes are immediate offsets.
-// The row stride S is P rounded up to a multiple of 64, so the bank of a lane
+// The LDS tile holds rows d < DL of a node's pairs.  With three planes, word
+// (d * S + p) * 3 + plane holds plane `plane` of row d of pair p, so one 24-bit
+// multiply-add gives the address and the planes are immediate offsets.  The
+// row stride S is P rounded up to a multiple of 64, so the bank of a lane
 // (word mod 64) is 3p + plane mod 64 whatever row its entry hashed to: the
 // lanes of a wave never collide, however their rows differ.  With four planes
-// a pair takes words 4p + p/16 + plane of its row (one pad word per 16 pairs),
-// which keeps the 64 lanes of a wave in 64 distinct banks as well.
+// the pairs of a row go in blocks of 64, each block holding its four planes
+// one after another (word d * 4S + 256 * (p / 64) + 64 * plane + p mod 64):
+// the bank is p mod 64 for every row and plane, and the planes are again
+// immediate offsets.
 template <bool kWide>
 struct Layout {
     static constexpr uint32_t kPl = kWide ? kPlanesWide : kPlanes;
+    static constexpr uint32_t kPlaneStep = kWide ? 64u : 1u;  // words between planes
     __device__ __forceinline__ static uint32_t lane_word(uint32_t p) {
-        return kWide ? kPl * p + (p >> 4) : kPl * p;
+        return kWide ? ((p >> 6) << 8) + (p & 63u) : kPl * p;
     }
 };
 
@@ -52,6 +55,39 @@ struct Lane {
     bool active;
 };
 
+// Per-item constants of a wide graph's lane.  Within an item the node is fixed,
+// so each pair hash is one multiply-add in the neighbour x away from a
+// constant: with the node as u (x > node) h = hi32(up + a2lo*x) + a2hi*x for
+// up = (a*node + b) mod 2^64, with the node as v (x < node)
+// h = hi32(dn + alo*x) + ahi*x for dn = (a2*node + b) mod 2^64; likewise the
+// index is node(node-1)/2 + x when x < node.  Three-plane graphs need none.
+template <bool kWide>
+struct NodeConsts {};
+template <>
+struct NodeConsts<true> {
+    uint64_t up[3], dn[3];
+    uint64_t kidx;  // node(node-1)/2
+};
+
+__device__ __forceinline__ uint64_t mul64_add(uint32_t mlo, uint32_t mhi, uint32_t x, uint64_t c) {
+    const uint64_t t = (uint64_t)mlo * x + c;
+    return t + ((uint64_t)(mhi * x) << 32);
+}
+
+template <bool kWide>
+__device__ __forceinline__ NodeConsts<kWide> node_consts(const SeedsOf<kWide>& s, uint32_t node) {
+    NodeConsts<kWide> nc{};
+    if constexpr (kWide) {
+#pragma unroll
+        for (uint32_t k = 0; k < 3; ++k) {
+            nc.up[k] = mul64_add(s.h[k].alo, s.h[k].ahi, node, s.h[k].b);
+            nc.dn[k] = mul64_add(s.h[k].a2lo, s.h[k].a2hi, node, s.h[k].b);
+        }
+        nc.kidx = ((uint64_t)node * (node - 1u)) >> 1;
+    }
+    return nc;
+}
+
 template <bool kWide>
 __device__ __forceinline__ Lane<kWide> make_lane(const GraphDesc& g) {
     Lane<kWide> ln{};
@@ -69,50 +105,97 @@ __device__ __forceinline__ Lane<kWide> make_lane(const GraphDesc& g) {
     return ln;
 }
 
-// Hash one entry for this lane's pair and XOR it into the exact-depth row of
-// the LDS tile; rows >= DL (kAllRows == false only) go straight to HBM with
-// atomics (`skl` is the lane's bucket of row 0, plane 0, in the node block).
-template <bool kAllRows, bool kWide>
-__device__ __forceinline__ void xor_entry(uint32_t x, uint32_t node, const Lane<kWide>& ln,
-                                          uint32_t Bm1, uint32_t DL, uint32_t row_bytes,
-                                          uint8_t* __restrict__ tile, uint32_t* __restrict__ skl,
-                                          uint32_t plane_words) {
+// Which neighbours a run of entries of a wide graph holds: all below the node,
+// all above it, or either (tested per entry).  Three-plane graphs ignore it.
+enum : int { kAnySide = 0, kBelow = 1, kAbove = 2 };
+
+// The three hash words of an entry for this lane's pair (row hash, checksum
+// high, checksum low) and its 64-bit index (wide graphs; three-plane graphs
+// use the entry itself as the index).
+template <bool kWide, int kSide>
+__device__ __forceinline__ void hash_entry(uint32_t x, uint32_t node, const Lane<kWide>& ln,
+                                           const NodeConsts<kWide>& nc, uint32_t* h,
+                                           uint64_t* idx) {
     if constexpr (!kWide) {
-        const uint32_t d = row_depth(ln.s, x, Bm1);
-        const uint32_t hi = chk_hi(ln.s, x);
-        const uint32_t lo = chk_lo(ln.s, x);
-        if (kAllRows || d < DL) {
-            uint32_t* a = (uint32_t*)(tile + (__umul24(d, row_bytes) + ln.tile_bytes));
-            atomicXor(a, x);
-            atomicXor(a + 1, lo);
-            atomicXor(a + 2, hi);
-        } else {
-            uint32_t* w = skl + d * kC;
-            atomicXor(w, x);
-            atomicXor(w + plane_words, lo);
-            atomicXor(w + 2 * plane_words, hi);
-        }
+        h[0] = mas_hash(ln.s.row_mlo, ln.s.row_mhi, ln.s.row_inc, x);
+        h[1] = chk_hi(ln.s, x);
+        h[2] = chk_lo(ln.s, x);
+        *idx = x;
     } else {
         // x is the neighbour: the edge is {node, x}
-        const uint32_t u = min(node, x), v = max(node, x);
-        const uint32_t d = wide_row_depth(ln.s, u, v, Bm1);
-        const uint32_t hi = pair_hash(ln.s.h[1], u, v);
-        const uint32_t lo = pair_hash(ln.s.h[2], u, v);
-        const uint64_t idx = edge_index64(u, v);
-        const uint32_t ilo = (uint32_t)idx, ihi = (uint32_t)(idx >> 32);
-        if (kAllRows || d < DL) {
-            uint32_t* a = (uint32_t*)(tile + (d * row_bytes + ln.tile_bytes));
-            atomicXor(a, ilo);
-            atomicXor(a + 1, ihi);
-            atomicXor(a + 2, lo);
-            atomicXor(a + 3, hi);
+        const bool above = kSide == kAbove || (kSide == kAnySide && x > node);
+        if (above) {
+#pragma unroll
+            for (uint32_t k = 0; k < 3; ++k) {
+                const uint64_t t = (uint64_t)ln.s.h[k].a2lo * x + nc.up[k];
+                h[k] = (uint32_t)(t >> 32) + ln.s.h[k].a2hi * x;
+            }
+            *idx = (((uint64_t)x * (x - 1u)) >> 1) + node;
         } else {
-            uint32_t* w = skl + d * kC;
-            atomicXor(w, ilo);
-            atomicXor(w + plane_words, ihi);
-            atomicXor(w + 2 * plane_words, lo);
-            atomicXor(w + 3 * plane_words, hi);
+#pragma unroll
+            for (uint32_t k = 0; k < 3; ++k) {
+                const uint64_t t = (uint64_t)ln.s.h[k].alo * x + nc.dn[k];
+                h[k] = (uint32_t)(t >> 32) + ln.s.h[k].ahi * x;
+            }
+            *idx = nc.kidx + x;
         }
+    }
+}
+
+__device__ __forceinline__ uint32_t depth_of(uint32_t h, uint32_t Bm1) {
+    const uint32_t tz = __builtin_ctzg(h, 32);
+    return tz < Bm1 ? tz : Bm1;
+}
+
+// Hash one entry for this lane's pair and XOR it into the exact-depth row of
+// the LDS tile.  Without kAllRows an entry deeper than the item's DL rows goes
+// to row DL instead, a sink that is never written back, and the call returns
+// true: the caller then applies that entry to HBM with xor_entry_deep.  (Deep
+// entries are rare, so the common path stays free of branches.)
+template <bool kAllRows, bool kWide, int kSide>
+__device__ __forceinline__ bool xor_entry(uint32_t x, uint32_t node, const Lane<kWide>& ln,
+                                          const NodeConsts<kWide>& nc, uint32_t Bm1, uint32_t DL,
+                                          uint32_t row_bytes, uint8_t* __restrict__ tile) {
+    uint32_t h[3];
+    uint64_t idx;
+    hash_entry<kWide, kSide>(x, node, ln, nc, h, &idx);
+    const uint32_t d = depth_of(h[0], Bm1);
+    const uint32_t row = kAllRows ? d : min(d, DL);
+    uint32_t* a = (uint32_t*)(tile + (__umul24(row, row_bytes) + ln.tile_bytes));
+    if constexpr (!kWide) {
+        atomicXor(a, x);
+        atomicXor(a + 1, h[2]);
+        atomicXor(a + 2, h[1]);
+    } else {
+        atomicXor(a, (uint32_t)idx);
+        atomicXor(a + 64, (uint32_t)(idx >> 32));
+        atomicXor(a + 128, h[2]);
+        atomicXor(a + 192, h[1]);
+    }
+    return !kAllRows && d >= DL;
+}
+
+// The HBM side of an entry deeper than the item's rows (`skl` is the lane's
+// bucket of row 0, plane 0, in the node block); shallower entries do nothing.
+template <bool kWide, int kSide>
+__device__ __forceinline__ void xor_entry_deep(uint32_t x, uint32_t node, const Lane<kWide>& ln,
+                                               const NodeConsts<kWide>& nc, uint32_t Bm1,
+                                               uint32_t DL, uint32_t* __restrict__ skl,
+                                               uint32_t plane_words) {
+    uint32_t h[3];
+    uint64_t idx;
+    hash_entry<kWide, kSide>(x, node, ln, nc, h, &idx);
+    const uint32_t d = depth_of(h[0], Bm1);
+    if (d < DL) return;
+    uint32_t* w = skl + d * kC;
+    atomicXor(w, (uint32_t)idx);
+    if constexpr (!kWide) {
+        atomicXor(w + plane_words, h[2]);
+        atomicXor(w + 2 * plane_words, h[1]);
+    } else {
+        atomicXor(w + plane_words, (uint32_t)(idx >> 32));
+        atomicXor(w + 2 * plane_words, h[2]);
+        atomicXor(w + 3 * plane_words, h[1]);
     }
 }
 
@@ -163,7 +246,7 @@ struct TileWalk {
         const uint32_t p = i - row * P;
         const uint32_t d = row / kPl;
         const uint32_t pl = row - d * kPl;
-        *t = d * RW + Layout<kWide>::lane_word(p) + pl;
+        *t = d * RW + Layout<kWide>::lane_word(p) + pl * Layout<kWide>::kPlaneStep;
         *h = sk_word_n(kPl, B, p / kC, pl, d, p % kC);
     }
 };
@@ -211,38 +294,124 @@ __device__ __forceinline__ void tile_store(const uint32_t* __restrict__ tile,
     }
 }
 
+// The share of entries [lo, hi) that group j of J takes: contiguous, starting
+// on 16-byte boundaries of the source array (group 0 also takes the unaligned
+// head), read in quads through a two-deep pipeline when it is long enough.
+struct GroupShare {
+    uint32_t e, ea, e1;  // first entry, first aligned entry, end
+    bool pipe;
+};
+
+template <typename Src>
+__device__ __forceinline__ GroupShare group_share(const Src& ent, uint32_t lo, uint32_t hi,
+                                                  uint32_t J, uint32_t j) {
+    GroupShare r;
+    const uint32_t mis = ent.misalign();
+    const uint32_t count = hi - lo;
+    const uint32_t head = (4u - ((mis + lo) & 3u)) & 3u;
+    if (count <= head + 8u * J) {
+        r.e = j == 0 ? lo : hi;
+        r.e1 = hi;
+    } else {
+        const uint32_t quads = (count - head) >> 2;
+        r.e = j == 0 ? lo : lo + head + 4u * (uint32_t)(((uint64_t)quads * j) / J);
+        r.e1 = j + 1 == J ? hi : lo + head + 4u * (uint32_t)(((uint64_t)quads * (j + 1)) / J);
+    }
+    r.ea = min(r.e1, r.e + ((4u - ((r.e + mis) & 3u)) & 3u));
+    r.pipe = r.ea + 8 <= r.e1;
+    return r;
+}
+
+// XOR one group's share into the tile: eight entries per iteration with the
+// next eight in flight (a and b hold the first eight when r.pipe).
+template <bool kAllRows, bool kWide, int kSide, typename Src>
+__device__ __forceinline__ void xor_share(const Src& ent, GroupShare r, uint4 a, uint4 b,
+                                          uint32_t node, const Lane<kWide>& ln,
+                                          const NodeConsts<kWide>& nc, uint32_t Bm1,
+                                          uint32_t DL, uint32_t row_bytes, uint8_t* tb,
+                                          uint32_t* skl, uint32_t plane_words) {
+    uint32_t e = r.e;
+    uint4 c = make_uint4(0, 0, 0, 0), d = c;
+#define GZ_XOR(x) xor_entry<kAllRows, kWide, kSide>((x), node, ln, nc, Bm1, DL, row_bytes, tb)
+#define GZ_DEEP(x) xor_entry_deep<kWide, kSide>((x), node, ln, nc, Bm1, DL, skl, plane_words)
+    // A set of eight entries.  Three-plane graphs apply a deep entry to HBM at
+    // once (their small items keep few rows, so deep entries are common there);
+    // wide graphs, whose items are long, note them and apply the set's deep
+    // entries after it, keeping the eight entries free of branches.
+#define GZ_SET(p, q)                                                               \
+    if constexpr (!kWide) {                                                        \
+        GZ_ONE(p.x); GZ_ONE(p.y); GZ_ONE(p.z); GZ_ONE(p.w);                        \
+        GZ_ONE(q.x); GZ_ONE(q.y); GZ_ONE(q.z); GZ_ONE(q.w);                        \
+    } else {                                                                       \
+        bool deep = GZ_XOR(p.x);                                                   \
+        deep |= GZ_XOR(p.y); deep |= GZ_XOR(p.z); deep |= GZ_XOR(p.w);             \
+        deep |= GZ_XOR(q.x); deep |= GZ_XOR(q.y); deep |= GZ_XOR(q.z);             \
+        deep |= GZ_XOR(q.w);                                                       \
+        if (!kAllRows && deep) deep_set(e);                                        \
+    }
+#define GZ_ONE(x) \
+    if (GZ_XOR(x)) GZ_DEEP(x)
+    // the rare deep entries of the set at [e0, e0 + 8): the set is read again
+    // (the barrier keeps the compiler from holding the first read, or its
+    // hashes, in registers across the set) and re-hashed
+    auto deep_set = [&](uint32_t e0) {
+        asm volatile("" ::: "memory");
+#pragma unroll 1
+        for (uint32_t k = 0; k < 8; ++k) GZ_DEEP(ent.one(e0 + k));
+    };
+    for (; e < r.ea; ++e) {  // unaligned head (group 0 only)
+        const uint32_t x = ent.one(e);
+        GZ_ONE(x);
+    }
+    if (r.pipe) {
+        // two register sets in turn: while one set is hashed the other is in flight;
+        // entries of a set that went deeper than the tile are applied to HBM after it
+        for (;;) {
+            const bool more1 = e + 16 <= r.e1;
+            if (more1) { c = ent.quad(e + 8); d = ent.quad(e + 12); }
+            GZ_SET(a, b);
+            e += 8;
+            if (!more1) break;
+            const bool more2 = e + 16 <= r.e1;
+            if (more2) { a = ent.quad(e + 8); b = ent.quad(e + 12); }
+            GZ_SET(c, d);
+            e += 8;
+            if (!more2) break;
+        }
+    }
+    for (; e < r.e1; ++e) {
+        const uint32_t x = ent.one(e);
+        GZ_ONE(x);
+    }
+#undef GZ_XOR
+#undef GZ_DEEP
+#undef GZ_ONE
+#undef GZ_SET
+}
+
 // Apply `count` entries to one node.  The J groups of P lanes each take a
-// contiguous share of the entries, read in 16-byte quads, eight entries per
-// iteration with the next eight in flight.  The first quads are issued before
-// the tile set-up so that both loads overlap; the barriers around the XOR
-// phase are inside (every thread of the workgroup calls this).
-template <bool kAllRows, bool kWide, typename Src>
-__device__ __forceinline__ void apply_entries(const Src& ent, uint32_t count, uint32_t node,
-                                              const Lane<kWide>& ln, const GraphDesc& g,
-                                              uint32_t DL, uint32_t* __restrict__ tile,
+// share of the entries.  With kSide1 == kBelow (wide graphs, grouped entries)
+// entries [0, split) have neighbours below the node and [split, count) above
+// it, and each run is hashed with its own straight-line code; otherwise split
+// == count.  The first quads are issued before the tile set-up so that both
+// loads overlap; the barriers around the XOR phase are inside (every thread of
+// the workgroup calls this).
+template <bool kAllRows, bool kWide, int kSide1, typename Src>
+__device__ __forceinline__ void apply_entries(const Src& ent, uint32_t count, uint32_t split,
+                                              uint32_t node, const Lane<kWide>& ln,
+                                              const GraphDesc& g, uint32_t DL,
+                                              uint32_t* __restrict__ tile,
                                               uint32_t* __restrict__ skn, bool shared) {
     const TileWalk<kWide> tw(g.P, g.B, DL);
-    uint32_t e = 0, ea = 0, e1 = 0;
-    bool pipe = false;
-    uint4 a = make_uint4(0, 0, 0, 0), b = a, c = a, d = a;
-    const uint32_t mis = ent.misalign();
+    NodeConsts<kWide> nc{};
+    GroupShare r{};
+    uint4 a = make_uint4(0, 0, 0, 0), b = a;
     if (ln.active) {
-        // group ranges start on 16-byte boundaries of the source array
-        const uint32_t J = ln.J, j = ln.j;
-        const uint32_t head = (4u - mis) & 3u;
-        if (count <= head + 8u * J) {
-            e = j == 0 ? 0u : count;
-            e1 = count;
-        } else {
-            const uint32_t quads = (count - head) >> 2;
-            e = j == 0 ? 0u : head + 4u * (uint32_t)(((uint64_t)quads * j) / J);
-            e1 = j + 1 == J ? count : head + 4u * (uint32_t)(((uint64_t)quads * (j + 1)) / J);
-        }
-        ea = min(e1, e + ((4u - ((e + mis) & 3u)) & 3u));
-        pipe = ea + 8 <= e1;
-        if (pipe) {
-            a = ent.quad(ea);
-            b = ent.quad(ea + 4);
+        nc = node_consts<kWide>(ln.s, node);
+        r = group_share(ent, 0, split, ln.J, ln.j);
+        if (r.pipe) {
+            a = ent.quad(r.ea);
+            b = ent.quad(r.ea + 4);
         }
     }
     if (shared) tile_zero(tile, tw);
@@ -254,28 +423,20 @@ __device__ __forceinline__ void apply_entries(const Src& ent, uint32_t count, ui
         const uint32_t plane_words = g.B * kC;
         uint8_t* tb = (uint8_t*)tile;
         uint32_t* skl = skn + ln.hbm_word;
-#define GZ_XOR(x) \
-    xor_entry<kAllRows, kWide>((x), node, ln, Bm1, DL, row_bytes, tb, skl, plane_words)
-        for (; e < ea; ++e) GZ_XOR(ent.one(e));  // unaligned head (group 0 only)
-        if (pipe) {
-            // two register sets in turn: while one set is hashed the other is in flight
-            for (;;) {
-                const bool more1 = e + 16 <= e1;
-                if (more1) { c = ent.quad(e + 8); d = ent.quad(e + 12); }
-                GZ_XOR(a.x); GZ_XOR(a.y); GZ_XOR(a.z); GZ_XOR(a.w);
-                GZ_XOR(b.x); GZ_XOR(b.y); GZ_XOR(b.z); GZ_XOR(b.w);
-                e += 8;
-                if (!more1) break;
-                const bool more2 = e + 16 <= e1;
-                if (more2) { a = ent.quad(e + 8); b = ent.quad(e + 12); }
-                GZ_XOR(c.x); GZ_XOR(c.y); GZ_XOR(c.z); GZ_XOR(c.w);
-                GZ_XOR(d.x); GZ_XOR(d.y); GZ_XOR(d.z); GZ_XOR(d.w);
-                e += 8;
-                if (!more2) break;
+        xor_share<kAllRows, kWide, kSide1>(ent, r, a, b, node, ln, nc, Bm1, DL, row_bytes, tb,
+                                           skl, plane_words);
+        if constexpr (kSide1 == kBelow) {
+            if (split < count) {
+                const GroupShare r2 = group_share(ent, split, count, ln.J, ln.j);
+                uint4 a2 = make_uint4(0, 0, 0, 0), b2 = a2;
+                if (r2.pipe) {
+                    a2 = ent.quad(r2.ea);
+                    b2 = ent.quad(r2.ea + 4);
+                }
+                xor_share<kAllRows, kWide, kAbove>(ent, r2, a2, b2, node, ln, nc, Bm1, DL,
+                                                   row_bytes, tb, skl, plane_words);
             }
         }
-        for (; e < e1; ++e) GZ_XOR(ent.one(e));
-#undef GZ_XOR
     }
     __syncthreads();
     tile_store(tile, skn, tw, shared);
@@ -339,10 +500,14 @@ __device__ __forceinline__ void update_items(const WorkItem* __restrict__ items,
         const GroupedEntries src{grouped + w.begin};
         const uint32_t node = w.gnode - g.node_base;  // graph-local id (wide hashes key on it)
         uint32_t* skn = g.sk + (uint64_t)(node - g.sk_first) * Layout<kWide>::kPl * g.B * g.P;
+        constexpr int kS = kWide ? kBelow : kAnySide;
+        const uint32_t split = kWide ? w.split : w.count;
         if (DL == g.B)
-            apply_entries<true, kWide>(src, w.count, node, ln, g, DL, tile, skn, w.shared != 0);
+            apply_entries<true, kWide, kS>(src, w.count, split, node, ln, g, DL, tile, skn,
+                                           w.shared != 0);
         else
-            apply_entries<false, kWide>(src, w.count, node, ln, g, DL, tile, skn, w.shared != 0);
+            apply_entries<false, kWide, kS>(src, w.count, split, node, ln, g, DL, tile, skn,
+                                            w.shared != 0);
         __syncthreads();  // the tile is reused by the next item
     }
 }
@@ -380,8 +545,8 @@ __global__ __launch_bounds__(1024) void k_update_node(const uint32_t* __restrict
     const uint32_t DL = min(lds_rows, g.B);
     const Lane<false> ln = make_lane<false>(g);
     uint32_t* skn = g.sk + (uint64_t)(node - g.sk_first) * kPlanes * g.B * g.P;
-    apply_entries<false, false>(NeighbourEntries{nbrs + begin, node}, cnt, node, ln, g, DL, tile,
-                                skn, gridDim.x > 1);
+    apply_entries<false, false, kAnySide>(NeighbourEntries{nbrs + begin, node}, cnt, cnt, node,
+                                          ln, g, DL, tile, skn, gridDim.x > 1);
 }
 
 __global__ __launch_bounds__(1024) void k_update_node_wide(const uint32_t* __restrict__ nbrs,
@@ -396,8 +561,53 @@ __global__ __launch_bounds__(1024) void k_update_node_wide(const uint32_t* __res
     const uint32_t DL = min(lds_rows, g.B);
     const Lane<true> ln = make_lane<true>(g);
     uint32_t* skn = g.sk + (uint64_t)(node - g.sk_first) * kPlanesWide * g.B * g.P;
-    apply_entries<false, true>(GroupedEntries{nbrs + begin}, cnt, node, ln, g, DL, tile, skn,
-                               gridDim.x > 1);
+    apply_entries<false, true, kAnySide>(GroupedEntries{nbrs + begin}, cnt, cnt, node, ln, g, DL,
+                                         tile, skn, gridDim.x > 1);
+}
+
+// Wide graphs: order each work item's entries so that neighbours below the
+// node come first (copied from `grouped` into the same positions of `out`),
+// and record their number in the item.  Order within a side is arbitrary: the
+// sketch update is a sum over Z2.  Blocks stride over the items.
+__global__ __launch_bounds__(256) void k_split_items(const uint32_t* __restrict__ ctl,
+                                                     WorkItem* __restrict__ items,
+                                                     const uint32_t* __restrict__ grouped,
+                                                     uint32_t* __restrict__ out,
+                                                     const GraphDesc* __restrict__ gd) {
+    __shared__ uint32_t s_lo, s_hi;
+    if (ctl[2]) return;
+    const uint32_t n_items = ctl[1];
+    const uint32_t lane = __lane_id();
+    const uint64_t below_lane = (1ull << lane) - 1ull;
+    for (uint32_t i = blockIdx.x; i < n_items; i += gridDim.x) {
+        const WorkItem w = items[i];
+        const uint32_t node = w.gnode - gd[w.graph].node_base;
+        if (threadIdx.x == 0) {
+            s_lo = 0;
+            s_hi = 0;
+        }
+        __syncthreads();
+        for (uint32_t e0 = 0; e0 < w.count; e0 += blockDim.x) {
+            const uint32_t e = e0 + threadIdx.x;
+            const bool valid = e < w.count;
+            const uint32_t x = valid ? grouped[w.begin + e] : 0u;
+            const bool lo = valid && x < node;
+            const bool hi = valid && !lo;
+            const uint64_t mlo = __ballot(lo), mhi = __ballot(hi);
+            uint32_t blo = 0, bhi = 0;
+            if (lane == 0) {
+                blo = atomicAdd(&s_lo, (uint32_t)__popcll(mlo));
+                bhi = atomicAdd(&s_hi, (uint32_t)__popcll(mhi));
+            }
+            blo = __shfl(blo, 0);
+            bhi = __shfl(bhi, 0);
+            if (lo) out[w.begin + blo + (uint32_t)__popcll(mlo & below_lane)] = x;
+            if (hi) out[w.begin + w.count - 1u - (bhi + (uint32_t)__popcll(mhi & below_lane))] = x;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) items[i].split = s_lo;
+        __syncthreads();
+    }
 }
 
 }  // namespace gz

@@ -27,7 +27,8 @@ _lib = None
 def build() -> str:
     """Compile the generator library (gcc, host only)."""
     tmp = _SO + ".tmp"
-    subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", _SRC, "-o", tmp, "-lm"])
+    subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-pthread", _SRC, "-o", tmp,
+                           "-lm"])
     os.replace(tmp, _SO)
     return _SO
 
@@ -57,6 +58,8 @@ def _load():
     L.gen_rmat_session.argtypes = [c_u32, c_f64, c_f64, c_f64, c_f64, c_u64, c_f64, c_u64,
                                    u32p, u32p, u8p, u64p]
     L.gen_rmat_session.restype = c_i64
+    L.gen_rmat_draws.argtypes = [c_u32, c_f64, c_f64, c_f64, c_u64, c_u64, c_u32, u32p, u32p]
+    L.gen_rmat_draws.restype = c_i64
     L.gen_uniform_u64.argtypes = [c_u64, c_u64, c_u64, c_u64, u64p]
     L.gen_uniform_u64.restype = None
     L.gen_unit_f64.argtypes = [c_u64, c_u64, c_u64, f64p]
@@ -126,6 +129,21 @@ def rmat_interleaved(V: int, abcd, n_steps: int, del_prob: float, seed: int) -> 
         raise ValueError("gen_rmat_interleaved failed (V must be a power of two)")
     return Stream(V, src[:n].copy(), dst[:n].copy(), op[:n].copy(),
                   f"rmat_interleaved(V={V},abcd={tuple(abcd)},steps={n_steps},del={del_prob},seed={seed})")
+
+
+def rmat_draws(V: int, abcd, n: int, seed: int, threads: int = 0) -> Stream:
+    """n raw R-MAT draws (self-loops redrawn); a pair drawn again toggles its edge.
+    The stream does not depend on `threads` (0 = one per CPU, at most 16)."""
+    L = _load()
+    a, b, c, _ = abcd
+    src = np.empty(n, np.uint32)
+    dst = np.empty(n, np.uint32)
+    t = threads or min(16, os.cpu_count() or 1)
+    if L.gen_rmat_draws(V, a, b, c, n, seed, t, _ptr(src, ctypes.c_uint32),
+                        _ptr(dst, ctypes.c_uint32)) < 0:
+        raise ValueError("gen_rmat_draws failed (V must be a power of two)")
+    return Stream(V, src, dst, np.ones(n, np.uint8),
+                  f"rmat_draws(V={V},abcd={tuple(abcd)},n={n},seed={seed})")
 
 
 def gnp(V: int, p: float, del_frac: float, seed: int) -> Stream:

@@ -428,3 +428,75 @@ void gen_unit_f64(uint64_t seed, uint64_t stream, uint64_t n, double *out) {
     pcg32_seed(&g, seed, 0x5eed1000ULL + stream);
     for (uint64_t i = 0; i < n; ++i) out[i] = rng_unit(&g);
 }
+
+/*
+ * Raw R-MAT draws on V = 2^L nodes, for large sparse-in-time streams where a
+ * live-edge set would not fit: n updates, each an R-MAT draw with self-loops
+ * redrawn; a pair drawn again toggles the edge (the draw is then a deletion
+ * under the Z2 view of Sec. 3.2).  The quadrant of each level is chosen from
+ * one 32-bit draw against the cumulative thresholds of (a, b, c).  Draws are
+ * made in blocks of 2^20, block k from its own PCG32 sequence (seed, k), so
+ * the output does not depend on `threads`.  Returns n, or -1.
+ */
+#include <pthread.h>
+
+typedef struct {
+    uint32_t V, L;
+    uint32_t ta, tb, tc;
+    uint64_t seed, n, block, next;
+    uint32_t *src, *dst;
+    pthread_mutex_t mu;
+} draws_job_t;
+
+static void *draws_worker(void *arg) {
+    draws_job_t *J = (draws_job_t *)arg;
+    for (;;) {
+        pthread_mutex_lock(&J->mu);
+        uint64_t k = J->next++;
+        pthread_mutex_unlock(&J->mu);
+        uint64_t lo = k * J->block;
+        if (lo >= J->n) break;
+        uint64_t hi = lo + J->block < J->n ? lo + J->block : J->n;
+        pcg32_t g;
+        pcg32_seed(&g, J->seed, 0x5eed0007ULL + 2 * k);
+        for (uint64_t i = lo; i < hi;) {
+            uint32_t u = 0, v = 0;
+            for (uint32_t l = 0; l < J->L; ++l) {
+                uint32_t x = pcg32_next(&g);
+                uint32_t bu = x >= J->tb, bv = (x >= J->ta && x < J->tb) || x >= J->tc;
+                u = (u << 1) | bu;
+                v = (v << 1) | bv;
+            }
+            if (u == v) continue;
+            if (pcg32_next(&g) & 1u) { uint32_t t = u; u = v; v = t; }
+            J->src[i] = u;
+            J->dst[i] = v;
+            ++i;
+        }
+    }
+    return NULL;
+}
+
+int64_t gen_rmat_draws(uint32_t V, double a, double b, double c, uint64_t n, uint64_t seed,
+                       uint32_t threads, uint32_t *src, uint32_t *dst) {
+    uint32_t L = log2_ceil(V);
+    if (V < 2 || (1u << L) != V || a < 0 || b < 0 || c < 0 || a + b + c > 1.0) return -1;
+    draws_job_t J;
+    J.V = V; J.L = L;
+    J.ta = (uint32_t)(a * 4294967296.0);
+    J.tb = (uint32_t)((a + b) * 4294967296.0);
+    J.tc = (uint32_t)((a + b + c) * 4294967296.0);
+    J.seed = seed; J.n = n; J.block = 1u << 20; J.next = 0;
+    J.src = src; J.dst = dst;
+    pthread_mutex_init(&J.mu, NULL);
+    if (threads < 1) threads = 1;
+    if (threads > 64) threads = 64;
+    pthread_t tid[64];
+    uint32_t started = 0;
+    for (uint32_t t = 1; t < threads; ++t)
+        if (pthread_create(&tid[started], NULL, draws_worker, &J) == 0) ++started;
+    draws_worker(&J);
+    for (uint32_t t = 0; t < started; ++t) pthread_join(tid[t], NULL);
+    pthread_mutex_destroy(&J.mu);
+    return (int64_t)n;
+}

@@ -177,7 +177,7 @@ def main() -> int:
     ap.add_argument("--batches", type=int, default=100, help="serving: batches per session")
     ap.add_argument("--hbm-budget-gb", type=float, default=120.0, help="serving: admission budget")
     ap.add_argument("--tick-updates", type=int, default=16 << 20, help="serving: updates per tick")
-    ap.add_argument("--staging-mb", type=int, default=512,
+    ap.add_argument("--staging-mb", type=int, default=128,
                     help="host tier: device bytes of the two slab buffers")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one 1 GiB device-to-device copy (a kernel of known traffic "

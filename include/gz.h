@@ -96,7 +96,7 @@ typedef struct gz_graph gz_graph;
 typedef struct gz_config {
     uint32_t rounds;        /* R override (tests force failures with a small R); 0 = rule */
     uint32_t tier;          /* GZ_TIER_HBM (0) or GZ_TIER_HOST (1) */
-    uint64_t staging_bytes; /* host tier: device bytes of the two slab buffers (0 = 512 MiB) */
+    uint64_t staging_bytes; /* host tier: device bytes of the two slab buffers (0 = 128 MiB) */
 } gz_config;
 
 /* Sketch residency.  GZ_TIER_HOST keeps a graph's sketches in pinned host

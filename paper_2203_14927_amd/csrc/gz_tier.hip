@@ -32,12 +32,12 @@ struct HostTier {
     uint32_t* d_slab_ctl = nullptr;   // per slab: ticket, item count, call error, unused
     uint32_t* d_slab_items = nullptr; // first work item of every slab, then the item count
     uint32_t* h_slab_items = nullptr; // pinned
-    uint32_t* round_buf = nullptr;    // V x 3*B*C words: one round of every node (queries)
+    uint32_t* round_buf = nullptr;    // V x planes*B*C words: one round of every node (queries)
 };
 
 namespace {
 
-constexpr uint64_t kDefaultStaging = 512ull << 20;  // both slab buffers together
+constexpr uint64_t kDefaultStaging = 128ull << 20;  // both slab buffers together
 
 // First work item of every slab: items are sorted by node, so it is the lower
 // bound of the slab's first node; entry nslabs is the number of items.

@@ -176,10 +176,14 @@ __global__ __launch_bounds__(kGroupThreads) void k_group_scatter(
 // places each bucket's entries into the runs of its nodes.  Both passes sort
 // a batch of entries by destination run in LDS first and then write each run's
 // share of the batch with consecutive stores, so HBM sees whole lines.  A
-// bucket entry packs the node's offset in its bucket with the other endpoint:
-// (fine << 16) | neighbour (node ids are below 2^16).
-constexpr uint32_t kMaxBuckets = 256;      // runs per block (keys of a batch)
-constexpr uint32_t kMaxBucketNodes = 256;  // 2^S: V <= 2^16 spread over <= 256 buckets
+// bucket entry packs the node's offset in its bucket above the other
+// endpoint: (fine << 16) | neighbour for graphs up to 2^16 nodes, and
+// (fine << nbits) | neighbour, nbits = bitlen(V-1), for wider graphs up to
+// 2^20 nodes (S = nbits - 8 with 256 buckets, so 32 bits suffice).
+constexpr uint32_t kMaxBuckets = 256;          // runs per block (keys of a batch)
+constexpr uint32_t kMaxBucketNodes = 256;      // 2^S: V <= 2^16 spread over <= 256 buckets
+constexpr uint32_t kMaxBucketNodesWide = 4096; // 2^S: V <= 2^20
+constexpr uint32_t kMaxTwoPassWide = 1u << 20;
 constexpr uint32_t kSortPerThread = 8;     // entries per thread and batch
 constexpr uint32_t kSortBatch = kSortPerThread * kGroupThreads;
 
@@ -338,6 +342,7 @@ __global__ __launch_bounds__(kGroupThreads) void k_group_partition(
     __syncthreads();
     const uint32_t mask = (1u << S) - 1u;
     const uint32_t kbits = 32u - __builtin_clz((nbk - 1u) | 1u);  // bucket ids < 2^kbits
+    const uint32_t nbits = g.wide ? 32u - __builtin_clz((g.V - 1u) | 1u) : 16u;
     constexpr uint32_t kUpd = kSortPerThread / 2;                  // two entries per update
     const uint64_t step = (uint64_t)kUpd * blockDim.x;
     // the next batch's updates are loaded while this batch is sorted
@@ -356,9 +361,9 @@ __global__ __launch_bounds__(kGroupThreads) void k_group_partition(
             const uint32_t x = xs[k], y = ys[k];
             if (i < r.i1) ok |= 3u << (2 * k);
             key[2 * k] = x >> S;
-            val[2 * k] = ((x & mask) << 16) | y;
+            val[2 * k] = ((x & mask) << nbits) | y;
             key[2 * k + 1] = y >> S;
-            val[2 * k + 1] = ((y & mask) << 16) | x;
+            val[2 * k + 1] = ((y & mask) << nbits) | x;
         }
         materialise(key, val);
 #pragma unroll
@@ -414,6 +419,92 @@ __global__ __launch_bounds__(kGroupThreads) void k_group_place(
             ws[k] = en < e1 ? tmp[en] : 0u;
         }
         batch_append(key, val, ok, S, n, cur, sm, grouped);
+    }
+}
+
+// Wide graphs, pass B.  A typical node of a raw R-MAT stream at V = 2^18 has
+// less than one entry per grouping chunk, so per-chunk runs are a few bytes;
+// instead a block places whole pieces of a bucket (runs of consecutive chunks,
+// all of them for most buckets) through LDS cursors, so each node's entries of
+// a piece land in one contiguous run.  Pieces hold about `target` entries: hub
+// buckets are cut into many (k_group_pieces), the rest take one block each.
+// pieces[0] = number of pieces, then (bucket, first chunk, end chunk) triples.
+__global__ __launch_bounds__(kMaxBuckets) void k_group_pieces(const uint32_t* __restrict__ base,
+                                                              uint32_t nbk, uint32_t nb,
+                                                              uint32_t target, uint32_t cap,
+                                                              uint32_t* __restrict__ pieces,
+                                                              const uint32_t* __restrict__ ctl) {
+    __shared__ uint32_t s_p[kMaxBuckets];
+    if (ctl[2]) return;
+    const uint32_t b = threadIdx.x;
+    uint32_t p = 0, lo = 0, tot = 0;
+    if (b < nbk) {
+        lo = base[b];
+        tot = base[(uint64_t)nb * nbk + b] - lo;
+        p = tot ? min(nb, (tot + target - 1) / target) : 0u;
+    }
+    s_p[b] = p;
+    __syncthreads();
+    for (uint32_t off = 1; off < kMaxBuckets; off <<= 1) {
+        const uint32_t t = b >= off ? s_p[b - off] : 0u;
+        __syncthreads();
+        s_p[b] += t;
+        __syncthreads();
+    }
+    const uint32_t first = s_p[b] - p;
+    if (b == kMaxBuckets - 1) pieces[0] = min(s_p[b], cap);
+    uint32_t c_prev = 0;
+    for (uint32_t k = 0; k < p && first + k < cap; ++k) {
+        uint32_t c_end = nb;
+        if (k + 1 < p) {
+            // first chunk whose run start reaches the piece's share of the bucket
+            const uint32_t goal = lo + (uint32_t)(((uint64_t)tot * (k + 1)) / p);
+            uint32_t l = c_prev, h = nb;
+            while (l < h) {
+                const uint32_t m = (l + h) >> 1;
+                if (base[(uint64_t)m * nbk + b] >= goal) h = m;
+                else l = m + 1;
+            }
+            c_end = l;
+        }
+        uint32_t* q = pieces + 1 + 3 * (first + k);
+        q[0] = b;
+        q[1] = c_prev;
+        q[2] = c_end;
+        c_prev = c_end;
+    }
+}
+
+__global__ __launch_bounds__(kGroupThreads) void k_group_place_wide(
+    const uint32_t* __restrict__ base, const uint32_t* __restrict__ H, uint32_t V, uint32_t S,
+    uint32_t nbk, const uint32_t* __restrict__ pieces, const uint32_t* __restrict__ tmp,
+    uint32_t* __restrict__ grouped, const uint32_t* __restrict__ ctl) {
+    __shared__ uint32_t cur[kMaxBucketNodesWide];
+    if (ctl[2]) return;
+    const uint32_t nbits = 32u - __builtin_clz((V - 1u) | 1u);
+    const uint32_t nmask = (1u << nbits) - 1u;
+    const uint32_t np = pieces[0];
+    for (uint32_t i = blockIdx.x; i < np; i += gridDim.x) {
+        const uint32_t b = pieces[1 + 3 * i], c0 = pieces[2 + 3 * i], c1 = pieces[3 + 3 * i];
+        if (c0 >= c1) continue;  // uniform over the block
+        const uint32_t v0 = b << S, n = min(V, (b + 1) << S) - v0;
+        const uint32_t* row = H + (uint64_t)c0 * V + v0;
+        __syncthreads();  // the previous piece is done with the cursors
+        for (uint32_t f = threadIdx.x; f < n; f += blockDim.x) cur[f] = row[f];
+        __syncthreads();
+        const uint32_t e1 = base[(uint64_t)c1 * nbk + b];
+        for (uint32_t e0 = base[(uint64_t)c0 * nbk + b]; e0 < e1;
+             e0 += kScatterBatch * blockDim.x) {
+            uint32_t w[kScatterBatch];
+#pragma unroll
+            for (uint32_t k = 0; k < kScatterBatch; ++k) {
+                const uint32_t e = e0 + threadIdx.x + k * blockDim.x;
+                w[k] = e < e1 ? tmp[e] : kNone;
+            }
+#pragma unroll
+            for (uint32_t k = 0; k < kScatterBatch; ++k)
+                if (w[k] != kNone) grouped[atomicAdd(&cur[w[k] >> nbits], 1u)] = w[k] & nmask;
+        }
     }
 }
 
@@ -687,6 +778,7 @@ struct LaunchShape {
     bool two_pass = false;
     bool wide = false;  // graphs with V > 2^16 (pair-keyed hashes, four planes)
     uint32_t bS = 0, nbk = 0, nbc = 0, bcr = 1, bblocks = 0;
+    uint32_t ptarget = 0, pcap = 0;  // wide pass B: entries per piece, piece capacity
     size_t gsmem = 0, smem = 0;
     std::vector<GraphDesc> descs;
     std::vector<GroupUnit> units;
@@ -762,7 +854,7 @@ gz_status build_shape(gz_graph* const* gs, uint32_t G, const uint64_t* ranges, u
     L.n_units = (uint32_t)L.units.size();
     // single graphs large enough that one-pass placement would keep too many
     // runs open per block take the two-pass placement
-    if (G == 1 && !L.wide && gs[0]->V > 4096 && L.descs[0].nb > 0) {
+    if (G == 1 && gs[0]->V > 4096 && gs[0]->V <= kMaxTwoPassWide && L.descs[0].nb > 0) {
         L.two_pass = true;
         while (((gs[0]->V + (1u << L.bS) - 1) >> L.bS) > kMaxBuckets) ++L.bS;
         L.nbk = (gs[0]->V + (1u << L.bS) - 1) >> L.bS;
@@ -770,6 +862,10 @@ gz_status build_shape(gz_graph* const* gs, uint32_t G, const uint64_t* ranges, u
         const uint32_t per_bucket = std::max(1u, 4 * cus / L.nbk);
         L.bcr = (L.nbc + per_bucket - 1) / per_bucket;
         L.bblocks = L.nbk * ((L.nbc + L.bcr - 1) / L.bcr);
+        if (L.wide) {
+            L.ptarget = (uint32_t)std::max<uint64_t>(65536, (2 * N + 2 * cus - 1) / (2 * cus));
+            L.pcap = L.nbk + (uint32_t)((2 * N + L.ptarget - 1) / L.ptarget) + 1;
+        }
     }
     L.nblocks = (uint32_t)((T + kScanTile - 1) / kScanTile);
     L.gsmem = (size_t)L.range_max * 4;
@@ -818,8 +914,16 @@ gz_status launch_sequence(IngestScratch& S, const LaunchShape& L, hipStream_t st
             S.H, S.cursor, S.counts, Tn, L.bS, L.nbk, L.nbc, S.bbase);
         k_group_partition<<<L.nbc, kGroupThreads, 0, stream>>>(S.args, S.descs, S.bbase, L.bS,
                                                                L.nbk, S.buckets, S.ctl);
-        k_group_place<<<L.bblocks, kGroupThreads, 0, stream>>>(
-            S.bbase, S.H, Tn, L.bS, L.nbk, L.nbc, L.bcr, S.buckets, S.grouped, S.ctl);
+        if (L.wide) {
+            uint32_t* pieces = S.bbase + (uint64_t)(L.nbc + 1) * L.nbk;
+            k_group_pieces<<<1, kMaxBuckets, 0, stream>>>(S.bbase, L.nbk, L.nbc, L.ptarget,
+                                                          L.pcap, pieces, S.ctl);
+            k_group_place_wide<<<2 * device_cu_count(), kGroupThreads, 0, stream>>>(
+                S.bbase, S.H, Tn, L.bS, L.nbk, pieces, S.buckets, S.grouped, S.ctl);
+        } else {
+            k_group_place<<<L.bblocks, kGroupThreads, 0, stream>>>(
+                S.bbase, S.H, Tn, L.bS, L.nbk, L.nbc, L.bcr, S.buckets, S.grouped, S.ctl);
+        }
     } else if (L.n_units) {
         k_group_scatter<<<L.n_units, kGroupThreads, L.gsmem, stream>>>(S.args, S.units, S.descs,
                                                                        S.H, S.grouped, S.ctl);
@@ -841,12 +945,31 @@ gz_status launch_sequence(IngestScratch& S, const LaunchShape& L, hipStream_t st
     return GZ_OK;
 }
 
+// Wait until the previous call's uploads have left the pinned argument buffer.
+// The runtime has been seen to report this event as recorded in a capturing
+// stream (it never is: it is recorded on the caller's stream, outside any
+// capture) after a long sequence of calls that included plan captures; the
+// wait then falls back to a device synchronization and a fresh event.
+gz_status wait_uploads(IngestScratch& S) {
+    const hipError_t e = hipEventSynchronize(S.copied_ev);
+    if (e != hipErrorCapturedEvent) {
+        GZ_HIP(e);
+        return GZ_OK;
+    }
+    (void)hipGetLastError();
+    GZ_HIP(hipDeviceSynchronize());
+    GZ_HIP(hipEventDestroy(S.copied_ev));
+    S.copied_ev = nullptr;
+    GZ_HIP(hipEventCreateWithFlags(&S.copied_ev, hipEventDisableTiming));
+    return GZ_OK;
+}
+
 // per-call arguments through the pinned buffer, reused once the previous
 // call's uploads have left it
 gz_status upload_args(IngestScratch& S, const LaunchShape& L, const uint32_t* src,
                       const uint32_t* dst, uint64_t N, const uint64_t* offs_dev,
                       hipStream_t stream) {
-    GZ_HIP(hipEventSynchronize(S.copied_ev));
+    GZ_TRY(wait_uploads(S));
     IngestArgs& a = *S.h_args;
     a = IngestArgs{};
     a.src = src;
@@ -904,7 +1027,7 @@ gz_status ingest_fused(gz_graph* const* gs, uint32_t G, const uint64_t* offs_hos
     const bool host_ptr = !(flags & GZ_DEVICE_PTR);
     GZ_TRY(ensure_scratch(S, N, L.T, G, L.chunk, L.H_size, L.n_units, host_ptr,
                           L.two_pass || L.wide ? 2 * N : 0,
-                          L.two_pass ? (uint64_t)(L.nbc + 1) * L.nbk : 0));
+                          L.two_pass ? (uint64_t)(L.nbc + 1) * L.nbk + 1 + 3ull * L.pcap : 0));
 
     // order after earlier work on these graphs (e.g. a query on another stream)
     GZ_HIP(fence_wait(stream, gs, G));
@@ -940,7 +1063,7 @@ gz_status group_only(gz_graph* g, const uint32_t* src, const uint32_t* dst, uint
     const bool host_ptr = !(flags & GZ_DEVICE_PTR);
     GZ_TRY(ensure_scratch(S, N, L.T, 1, L.chunk, L.H_size, L.n_units, host_ptr,
                           L.two_pass || L.wide ? 2 * N : 0,
-                          L.two_pass ? (uint64_t)(L.nbc + 1) * L.nbk : 0));
+                          L.two_pass ? (uint64_t)(L.nbc + 1) * L.nbk + 1 + 3ull * L.pcap : 0));
     GZ_HIP(fence_wait(stream, g));
     const uint32_t* dsrc = src;
     const uint32_t* ddst = dst;
@@ -1081,7 +1204,9 @@ gz_status gz_plan_create(gz_graph* const* gs, uint32_t G, const uint64_t* caps, 
     if (!st)
         st = ensure_scratch(p->S, ranges[G], p->L.T, G, p->L.chunk, p->L.H_size, p->L.n_units,
                             false, p->L.two_pass || p->L.wide ? 2 * ranges[G] : 0,
-                            p->L.two_pass ? (uint64_t)(p->L.nbc + 1) * p->L.nbk : 0);
+                            p->L.two_pass ? (uint64_t)(p->L.nbc + 1) * p->L.nbk + 1 +
+                                                3ull * p->L.pcap
+                                          : 0);
     hipError_t e = hipSuccess;
     if (!st) {
         e = hipMalloc((void**)&p->offs_dev, sizeof(uint64_t) * (G + 1));

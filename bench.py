@@ -34,7 +34,7 @@ sys.path.insert(0, ROOT)
 # lds_rows, chunk, wgs_per_cu, group_blocks), so that a default run times the
 # same configuration every time; --autotune searches again.
 TUNED = {"rmat_dense": "1024,28,16384,2,0", "many_gnp": "256,12,16384,8,0",
-         "rmat_kron18": "320,15,16384,3,0"}
+         "rmat_kron18": "512,16,4096,3,256"}
 
 # MI355X figures used by the roofline: 256 CUs x 4 SIMD16 x 2.4 GHz, HBM3E 8 TB/s
 PEAK_INT_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12   # VALU lane-instructions/s: 39.32 T

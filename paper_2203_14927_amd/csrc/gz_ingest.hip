@@ -422,6 +422,113 @@ __global__ __launch_bounds__(kGroupThreads) void k_group_place(
     }
 }
 
+constexpr uint32_t kLoadBatch = 8;  // loads per thread issued before their use
+
+// Wide graphs count per bucket first (one read of the stream; validation as in
+// k_group_count), take the bucket regions from those counts, and count per
+// node from the bucket entries after pass A (one read of them), instead of
+// reading the stream once per 32768-node range.  Hb[c * nbk + b] = entries of
+// chunk c in bucket b (kept at the start of the node count table, which the
+// node counts overwrite later).
+__global__ __launch_bounds__(kGroupThreads) void k_group_bcount(
+    const IngestArgs* __restrict__ a, const GraphDesc* __restrict__ gd, uint32_t S, uint32_t nbk,
+    uint32_t* __restrict__ Hb, uint32_t* __restrict__ ctl) {
+    __shared__ uint32_t hist[kMaxBuckets];
+    const GraphDesc g = gd[0];
+    const UnitRange r = unit_range(a, gd, GroupUnit{0, blockIdx.x, 0, 0}, g);
+    typedef const __attribute__((address_space(1))) uint32_t* gsrc_t;
+    const gsrc_t src = (gsrc_t)a->src;
+    const gsrc_t dst = (gsrc_t)a->dst;
+    for (uint32_t k = threadIdx.x; k < kMaxBuckets; k += blockDim.x) hist[k] = 0;
+    __syncthreads();
+    bool bad = false;
+    for (uint64_t i0 = r.i0; i0 < r.i1; i0 += (uint64_t)kLoadBatch * blockDim.x) {
+        uint32_t x[kLoadBatch], y[kLoadBatch], in = 0;
+#pragma unroll
+        for (uint32_t k = 0; k < kLoadBatch; ++k) {
+            const uint64_t i = i0 + threadIdx.x + (uint64_t)k * blockDim.x;
+            if (i < r.i1) in |= 1u << k;
+            x[k] = i < r.i1 ? src[i] : 0u;
+            y[k] = i < r.i1 ? dst[i] : 0u;
+        }
+#pragma unroll
+        for (uint32_t k = 0; k < kLoadBatch; ++k) {
+            if (!((in >> k) & 1u)) continue;  // past the chunk
+            if (x[k] == y[k] || x[k] >= g.V || y[k] >= g.V) {
+                bad = true;
+                continue;
+            }
+            atomicAdd(&hist[x[k] >> S], 1u);
+            atomicAdd(&hist[y[k] >> S], 1u);
+        }
+    }
+    if (bad) {
+        atomicOr(&ctl[2], 1u);
+        atomicOr(&ctl[3], 1u);
+    }
+    __syncthreads();
+    for (uint32_t k = threadIdx.x; k < nbk; k += blockDim.x) Hb[blockIdx.x * nbk + k] = hist[k];
+}
+
+// base[c * nbk + b] (c <= nb) from the bucket counts: bucket regions in node
+// order, chunk c's share of a region after the shares of earlier chunks
+__global__ __launch_bounds__(kMaxBuckets) void k_group_bbase_wide(const uint32_t* __restrict__ Hb,
+                                                                  uint32_t nbk, uint32_t nb,
+                                                                  uint32_t* __restrict__ base) {
+    __shared__ uint32_t s_t[kMaxBuckets];
+    const uint32_t b = threadIdx.x;
+    uint32_t tot = 0;
+    if (b < nbk)
+        for (uint32_t c = 0; c < nb; ++c) tot += Hb[(uint64_t)c * nbk + b];
+    s_t[b] = tot;
+    __syncthreads();
+    for (uint32_t off = 1; off < kMaxBuckets; off <<= 1) {
+        const uint32_t t = b >= off ? s_t[b - off] : 0u;
+        __syncthreads();
+        s_t[b] += t;
+        __syncthreads();
+    }
+    if (b >= nbk) return;
+    uint32_t at = s_t[b] - tot;
+    for (uint32_t c = 0; c < nb; ++c) {
+        base[(uint64_t)c * nbk + b] = at;
+        at += Hb[(uint64_t)c * nbk + b];
+    }
+    base[(uint64_t)nb * nbk + b] = at;
+}
+
+// node counts of chunk c from its share of bucket b: H[c * V + v] for the
+// bucket's nodes v (one block per (bucket, chunk); every row word is written)
+__global__ __launch_bounds__(256) void k_group_ncount(const uint32_t* __restrict__ base,
+                                                      uint32_t nbk, uint32_t S, uint32_t V,
+                                                      const uint32_t* __restrict__ tmp,
+                                                      uint32_t* __restrict__ H,
+                                                      const uint32_t* __restrict__ ctl) {
+    __shared__ uint32_t hist[kMaxBucketNodesWide];
+    if (ctl[2]) return;
+    const uint32_t b = blockIdx.x % nbk, c = blockIdx.x / nbk;
+    const uint32_t nbits = 32u - __builtin_clz((V - 1u) | 1u);
+    const uint32_t v0 = b << S, n = min(V, (b + 1) << S) - v0;
+    for (uint32_t f = threadIdx.x; f < n; f += blockDim.x) hist[f] = 0;
+    __syncthreads();
+    const uint32_t e1 = base[(uint64_t)(c + 1) * nbk + b];
+    // loads issued kLoadBatch at a time, so that they are in flight together
+    for (uint32_t e0 = base[(uint64_t)c * nbk + b]; e0 < e1; e0 += kLoadBatch * blockDim.x) {
+        uint32_t w[kLoadBatch];
+#pragma unroll
+        for (uint32_t k = 0; k < kLoadBatch; ++k) {
+            const uint32_t e = e0 + threadIdx.x + k * blockDim.x;
+            w[k] = e < e1 ? tmp[e] : kNone;
+        }
+#pragma unroll
+        for (uint32_t k = 0; k < kLoadBatch; ++k)
+            if (w[k] != kNone) atomicAdd(&hist[w[k] >> nbits], 1u);
+    }
+    __syncthreads();
+    uint32_t* row = H + (uint64_t)c * V + v0;
+    for (uint32_t f = threadIdx.x; f < n; f += blockDim.x) row[f] = hist[f];
+}
+
 // Wide graphs, pass B.  A typical node of a raw R-MAT stream at V = 2^18 has
 // less than one entry per grouping chunk, so per-chunk runs are a few bytes;
 // instead a block places whole pieces of a bucket (runs of consecutive chunks,
@@ -494,15 +601,15 @@ __global__ __launch_bounds__(kGroupThreads) void k_group_place_wide(
         __syncthreads();
         const uint32_t e1 = base[(uint64_t)c1 * nbk + b];
         for (uint32_t e0 = base[(uint64_t)c0 * nbk + b]; e0 < e1;
-             e0 += kScatterBatch * blockDim.x) {
-            uint32_t w[kScatterBatch];
+             e0 += kLoadBatch * blockDim.x) {
+            uint32_t w[kLoadBatch];
 #pragma unroll
-            for (uint32_t k = 0; k < kScatterBatch; ++k) {
+            for (uint32_t k = 0; k < kLoadBatch; ++k) {
                 const uint32_t e = e0 + threadIdx.x + k * blockDim.x;
                 w[k] = e < e1 ? tmp[e] : kNone;
             }
 #pragma unroll
-            for (uint32_t k = 0; k < kScatterBatch; ++k)
+            for (uint32_t k = 0; k < kLoadBatch; ++k)
                 if (w[k] != kNone) grouped[atomicAdd(&cur[w[k] >> nbits], 1u)] = w[k] & nmask;
         }
     }
@@ -898,9 +1005,20 @@ gz_status launch_sequence(IngestScratch& S, const LaunchShape& L, hipStream_t st
     const uint32_t Tn = L.T;
     if (prof) GZ_HIP(hipEventRecord(prof->prof_ev[0], stream));
     k_fill_u32<<<1, 64, 0, stream>>>(S.ctl, 3, 0);  // ticket, items, call error (sticky kept)
-    if (L.n_units)
+    const bool wide2 = L.two_pass && L.wide;
+    if (wide2) {
+        // buckets first: counts, regions, pass A, then node counts from its output
+        k_group_bcount<<<L.nbc, kGroupThreads, 0, stream>>>(S.args, S.descs, L.bS, L.nbk, S.H,
+                                                            S.ctl);
+        k_group_bbase_wide<<<1, kMaxBuckets, 0, stream>>>(S.H, L.nbk, L.nbc, S.bbase);
+        k_group_partition<<<L.nbc, kGroupThreads, 0, stream>>>(S.args, S.descs, S.bbase, L.bS,
+                                                               L.nbk, S.buckets, S.ctl);
+        k_group_ncount<<<L.nbk * L.nbc, 256, 0, stream>>>(S.bbase, L.nbk, L.bS, Tn, S.buckets,
+                                                          S.H, S.ctl);
+    } else if (L.n_units) {
         k_group_count<<<L.n_units, kGroupThreads, L.gsmem, stream>>>(S.args, S.units, S.descs,
                                                                      S.H, S.ctl);
+    }
     k_group_colsum<<<grid_for(Tn, 256, 8192), 256, 0, stream>>>(S.descs, L.G, Tn, S.H, S.counts);
     k_scan_partial<<<L.nblocks, kScanThreads, 0, stream>>>(S.counts, Tn, L.chunk, S.block_sums);
     k_scan_top<<<1, kScanThreads, 0, stream>>>(S.block_sums, L.nblocks, S.ctl);
@@ -908,28 +1026,27 @@ gz_status launch_sequence(IngestScratch& S, const LaunchShape& L, hipStream_t st
                                                          S.items, S.cursor, S.descs, L.G, S.ctl);
     k_group_colscan<<<grid_for(Tn, 256, 8192), 256, 0, stream>>>(S.descs, L.G, Tn, S.cursor,
                                                                   S.H);
-    if (L.two_pass) {
+    if (wide2) {
+        uint32_t* pieces = S.bbase + (uint64_t)(L.nbc + 1) * L.nbk;
+        k_group_pieces<<<1, kMaxBuckets, 0, stream>>>(S.bbase, L.nbk, L.nbc, L.ptarget, L.pcap,
+                                                      pieces, S.ctl);
+        k_group_place_wide<<<2 * device_cu_count(), kGroupThreads, 0, stream>>>(
+            S.bbase, S.H, Tn, L.bS, L.nbk, pieces, S.buckets, S.grouped, S.ctl);
+    } else if (L.two_pass) {
         const uint32_t nbase = (L.nbc + 1) * L.nbk;
         k_group_bucket_base<<<(nbase + 255) / 256, 256, 0, stream>>>(
             S.H, S.cursor, S.counts, Tn, L.bS, L.nbk, L.nbc, S.bbase);
         k_group_partition<<<L.nbc, kGroupThreads, 0, stream>>>(S.args, S.descs, S.bbase, L.bS,
                                                                L.nbk, S.buckets, S.ctl);
-        if (L.wide) {
-            uint32_t* pieces = S.bbase + (uint64_t)(L.nbc + 1) * L.nbk;
-            k_group_pieces<<<1, kMaxBuckets, 0, stream>>>(S.bbase, L.nbk, L.nbc, L.ptarget,
-                                                          L.pcap, pieces, S.ctl);
-            k_group_place_wide<<<2 * device_cu_count(), kGroupThreads, 0, stream>>>(
-                S.bbase, S.H, Tn, L.bS, L.nbk, pieces, S.buckets, S.grouped, S.ctl);
-        } else {
-            k_group_place<<<L.bblocks, kGroupThreads, 0, stream>>>(
-                S.bbase, S.H, Tn, L.bS, L.nbk, L.nbc, L.bcr, S.buckets, S.grouped, S.ctl);
-        }
+        k_group_place<<<L.bblocks, kGroupThreads, 0, stream>>>(
+            S.bbase, S.H, Tn, L.bS, L.nbk, L.nbc, L.bcr, S.buckets, S.grouped, S.ctl);
     } else if (L.n_units) {
         k_group_scatter<<<L.n_units, kGroupThreads, L.gsmem, stream>>>(S.args, S.units, S.descs,
                                                                        S.H, S.grouped, S.ctl);
     }
     if (L.wide)  // neighbours below each item's node first, into the bucket array
-        k_split_items<<<L.pgrid, 256, 0, stream>>>(S.ctl, S.items, S.grouped, S.buckets, S.descs);
+        k_split_items<<<8 * device_cu_count(), 256, 0, stream>>>(S.ctl, S.items, S.grouped,
+                                                                 S.buckets, S.descs);
     if (prof) GZ_HIP(hipEventRecord(prof->prof_ev[1], stream));
     if (with_update && L.wide)
         k_update_wide<<<L.pgrid, L.wg, L.smem, stream>>>(S.items, S.ctl, update_entries(S, true),

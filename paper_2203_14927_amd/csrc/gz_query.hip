@@ -122,32 +122,44 @@ __global__ void k_q_select(uint32_t r, const uint32_t* __restrict__ L, uint32_t*
 // when it changes (components are large after the first round, so consecutive
 // ids mostly share one and a span costs one atomic per word).  Loads are issued
 // kReduceRun nodes at a time so that they are in flight together; blockIdx.y
-// picks the block of accumulator words, so a round runs ceil(T / kReduceSpan)
-// x ceil(words / blockDim) workgroups.
+// picks the block of accumulator words, so a round runs ceil(T / span) x
+// ceil(words / blockDim) workgroups.  The span grows with T (up to
+// kReduceSpanMax) so that a large graph's giant component does not take one
+// device-scope atomic per word from tens of thousands of workgroups.
 constexpr uint32_t kReduceRun = 16;
 constexpr uint32_t kReduceSpan = 64;
+constexpr uint32_t kReduceSpanMax = 1024;
+constexpr uint32_t kReduceBlocks = 1024;  // spans double while a round takes > 2x this many
 
-__global__ __launch_bounds__(256) void k_q_reduce(uint32_t r, uint32_t T,
+uint32_t reduce_span(uint32_t T, uint32_t yblocks) {
+    uint32_t span = kReduceSpan;
+    while (span < kReduceSpanMax &&
+           ((uint64_t)T + span - 1) / span * yblocks > 2ull * kReduceBlocks)
+        span *= 2;
+    return span;
+}
+
+__global__ __launch_bounds__(256) void k_q_reduce(uint32_t r, uint32_t T, uint32_t span,
                                                   const uint32_t* __restrict__ comp,
                                                   const uint32_t* __restrict__ slot,
                                                   const uint32_t* __restrict__ gof,
                                                   const GraphDesc* __restrict__ gd, uint32_t wpr,
                                                   uint32_t* __restrict__ acc,
                                                   const uint32_t* __restrict__ ctl) {
-    __shared__ uint32_t s_slot[kReduceSpan];
-    __shared__ const uint32_t* s_base[kReduceSpan];
-    __shared__ uint32_t s_words[kReduceSpan];
+    __shared__ uint32_t s_slot[kReduceSpanMax];
+    __shared__ const uint32_t* s_base[kReduceSpanMax];
+    __shared__ uint32_t s_words[kReduceSpanMax];
     if (ctl[Q_STOP]) return;
-    const uint32_t v0 = blockIdx.x * kReduceSpan;
-    const uint32_t n = min(T - v0, kReduceSpan);
-    if (threadIdx.x < n) {
-        const uint32_t v = v0 + threadIdx.x;
+    const uint32_t v0 = blockIdx.x * span;
+    const uint32_t n = min(T - v0, span);
+    for (uint32_t t = threadIdx.x; t < n; t += blockDim.x) {
+        const uint32_t v = v0 + t;
         const uint32_t sl = slot[comp[v]];
-        s_slot[threadIdx.x] = sl;
+        s_slot[t] = sl;
         const GraphDesc& g = gd[gof[v]];
-        s_base[threadIdx.x] = g.sk + (uint64_t)(v - g.node_base) * g.node_words +
-                              (g.round_view ? 0u : sk_word_n(g.planes, g.B, r, 0, 0, 0));
-        s_words[threadIdx.x] = g.planes * g.B * kC;
+        s_base[t] = g.sk + (uint64_t)(v - g.node_base) * g.node_words +
+                    (g.round_view ? 0u : sk_word_n(g.planes, g.B, r, 0, 0, 0));
+        s_words[t] = g.planes * g.B * kC;
     }
     __syncthreads();
     {
@@ -764,7 +776,9 @@ gz_status boruvka(gz_graph* const* gs, uint32_t G, bool want_forest, QueryResult
     uint32_t* m2 = Q->m2;
     const uint32_t qgrid = blocks_for(8ull * T, 256);
     const uint32_t zgrid = 2048;
-    const uint32_t rgrid = (T + kReduceSpan - 1) / kReduceSpan;
+    const uint32_t ry = (wpr + 255) / 256;
+    const uint32_t rspan = reduce_span(T, ry);
+    const uint32_t rgrid = (T + rspan - 1) / rspan;
     for (uint32_t r = 0; r < Rmax; ++r) Q->host_na[r] = kNone;
     // Rounds are enqueued ahead of the device; before round r the host waits
     // for the end of round r-2 and stops once a round had no active component
@@ -785,8 +799,8 @@ gz_status boruvka(gz_graph* const* gs, uint32_t G, bool want_forest, QueryResult
                                                    Q->descs, Q->comp, Q->hook, Q->hedge, Q->done);
         } else {
             k_q_zero_acc<<<zgrid, 256, 0, qs>>>(Q->ctl, wpr, Q->acc);
-            k_q_reduce<<<dim3(rgrid, (wpr + 255) / 256), 256, 0, qs>>>(
-                r, T, Q->comp, Q->slot, Q->gof, Q->descs, wpr, Q->acc, Q->ctl);
+            k_q_reduce<<<dim3(rgrid, ry), 256, 0, qs>>>(r, T, rspan, Q->comp, Q->slot, Q->gof,
+                                                        Q->descs, wpr, Q->acc, Q->ctl);
             k_q_query<false><<<qgrid, 256, 0, qs>>>(r, Q->A, Q->ctl, Q->acc, wpr, Q->gof,
                                                     Q->descs, Q->comp, Q->hook, Q->hedge,
                                                     Q->done);

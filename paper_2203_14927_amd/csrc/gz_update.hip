@@ -568,45 +568,49 @@ __global__ __launch_bounds__(1024) void k_update_node_wide(const uint32_t* __res
 // Wide graphs: order each work item's entries so that neighbours below the
 // node come first (copied from `grouped` into the same positions of `out`),
 // and record their number in the item.  Order within a side is arbitrary: the
-// sketch update is a sum over Z2.  Blocks stride over the items.
+// sketch update is a sum over Z2.  One wave per item, 64 entries at a time:
+// the lanes' places come from ballots, so no barrier or LDS is involved.
+constexpr uint32_t kSplitBatch = 4;  // groups of 64 entries loaded per step
+
 __global__ __launch_bounds__(256) void k_split_items(const uint32_t* __restrict__ ctl,
                                                      WorkItem* __restrict__ items,
                                                      const uint32_t* __restrict__ grouped,
                                                      uint32_t* __restrict__ out,
                                                      const GraphDesc* __restrict__ gd) {
-    __shared__ uint32_t s_lo, s_hi;
     if (ctl[2]) return;
     const uint32_t n_items = ctl[1];
     const uint32_t lane = __lane_id();
     const uint64_t below_lane = (1ull << lane) - 1ull;
-    for (uint32_t i = blockIdx.x; i < n_items; i += gridDim.x) {
+    const uint32_t waves = gridDim.x * (blockDim.x >> 6);
+    for (uint32_t i = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); i < n_items;
+         i += waves) {
         const WorkItem w = items[i];
         const uint32_t node = w.gnode - gd[w.graph].node_base;
-        if (threadIdx.x == 0) {
-            s_lo = 0;
-            s_hi = 0;
-        }
-        __syncthreads();
-        for (uint32_t e0 = 0; e0 < w.count; e0 += blockDim.x) {
-            const uint32_t e = e0 + threadIdx.x;
-            const bool valid = e < w.count;
-            const uint32_t x = valid ? grouped[w.begin + e] : 0u;
-            const bool lo = valid && x < node;
-            const bool hi = valid && !lo;
-            const uint64_t mlo = __ballot(lo), mhi = __ballot(hi);
-            uint32_t blo = 0, bhi = 0;
-            if (lane == 0) {
-                blo = atomicAdd(&s_lo, (uint32_t)__popcll(mlo));
-                bhi = atomicAdd(&s_hi, (uint32_t)__popcll(mhi));
+        const uint32_t* src = grouped + w.begin;
+        uint32_t* lo_out = out + w.begin;
+        uint32_t* hi_out = out + w.begin + w.count - 1u;
+        uint32_t nlo = 0, nhi = 0;
+        for (uint32_t e0 = 0; e0 < w.count; e0 += 64 * kSplitBatch) {
+            uint32_t xs[kSplitBatch];
+#pragma unroll
+            for (uint32_t k = 0; k < kSplitBatch; ++k) {  // loads in flight together
+                const uint32_t e = e0 + k * 64 + lane;
+                xs[k] = e < w.count ? src[e] : 0u;
             }
-            blo = __shfl(blo, 0);
-            bhi = __shfl(bhi, 0);
-            if (lo) out[w.begin + blo + (uint32_t)__popcll(mlo & below_lane)] = x;
-            if (hi) out[w.begin + w.count - 1u - (bhi + (uint32_t)__popcll(mhi & below_lane))] = x;
+#pragma unroll
+            for (uint32_t k = 0; k < kSplitBatch; ++k) {
+                const uint32_t e = e0 + k * 64 + lane;
+                const bool valid = e < w.count;
+                const uint32_t x = xs[k];
+                const bool lo = valid && x < node;
+                const uint64_t mlo = __ballot(lo), mhi = __ballot(valid && !lo);
+                if (lo) lo_out[nlo + (uint32_t)__popcll(mlo & below_lane)] = x;
+                else if (valid) *(hi_out - (nhi + (uint32_t)__popcll(mhi & below_lane))) = x;
+                nlo += (uint32_t)__popcll(mlo);
+                nhi += (uint32_t)__popcll(mhi);
+            }
         }
-        __syncthreads();
-        if (threadIdx.x == 0) items[i].split = s_lo;
-        __syncthreads();
+        if (lane == 0) items[i].split = nlo;
     }
 }
 

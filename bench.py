@@ -78,13 +78,19 @@ def make_workload(name: str):
     raise SystemExit(f"unknown workload {name}")
 
 
-def traffic_from_profile(kernel_src_hash: str):
+PMC_SUMMARIES = {"rmat_dense": "k_update_rmat_dense_pmc.txt",
+                 "rmat_kron18": "k_update_wide_rmat_kron18_pmc.txt"}
+
+
+def traffic_from_profile(kernel_src_hash: str, workload: str = "rmat_dense"):
     """HBM bytes per launch of the update kernel from the committed PMC summary, or None.
 
     The summary records the hash of the kernel source it was taken with; a
     different hash means the kernel changed since, and the figure is stale.
     """
-    path = os.path.join(ROOT, "profiles", "k_update_rmat_dense_pmc.txt")
+    if workload not in PMC_SUMMARIES:
+        return None
+    path = os.path.join(ROOT, "profiles", PMC_SUMMARIES[workload])
     if not os.path.exists(path):
         return None
     text = open(path).read()
@@ -516,7 +522,7 @@ def run_single(args) -> dict:
     opp = OPS_PER_UPDATE_PAIR_WIDE if stream.V > 65536 else OPS_PER_UPDATE_PAIR
     ops = stream.N * P * opp
     achieved = ops / (upd_ms * 1e-3) / 1e12
-    traffic = traffic_from_profile(kernel_source_hash()) if args.workload == "rmat_dense" else None
+    traffic = traffic_from_profile(kernel_source_hash(), args.workload)
 
     out = {
         "metric": "edge updates/sec ingested (1 MI355X), batched vs plain; CC query ms; p99 latency",

@@ -39,8 +39,11 @@ struct Layout {
     }
 };
 
+// Three-plane graphs keep their pair's seeds in registers for the whole launch;
+// wide graphs derive per-item constants from the seed table instead (below).
+struct NoSeeds {};
 template <bool kWide>
-using SeedsOf = typename std::conditional<kWide, WideSeeds, PairSeeds>::type;
+using SeedsOf = typename std::conditional<kWide, NoSeeds, PairSeeds>::type;
 
 // Per-lane state of the update: the lane's (round, column) pair p within group
 // j of J, the pair's seeds, and the lane's offsets in a tile row and in a
@@ -55,37 +58,66 @@ struct Lane {
     bool active;
 };
 
-// Per-item constants of a wide graph's lane.  Within an item the node is fixed,
-// so each pair hash is one multiply-add in the neighbour x away from a
-// constant: with the node as u (x > node) h = hi32(up + a2lo*x) + a2hi*x for
-// up = (a*node + b) mod 2^64, with the node as v (x < node)
-// h = hi32(dn + alo*x) + ahi*x for dn = (a2*node + b) mod 2^64; likewise the
-// index is node(node-1)/2 + x when x < node.  Three-plane graphs need none.
-template <bool kWide>
-struct NodeConsts {};
-template <>
-struct NodeConsts<true> {
-    uint64_t up[3], dn[3];
-    uint64_t kidx;  // node(node-1)/2
+// Which neighbours a run of entries of a wide graph holds: all below the node,
+// all above it, or either (tested per entry).  Three-plane graphs ignore it.
+enum : int { kAnySide = 0, kBelow = 1, kAbove = 2 };
+
+// Per-item constants of a wide graph's lane for one side of the node.  Within
+// an item the node is fixed, so each pair hash is one multiply-add in the
+// neighbour x away from a constant.  With x below the node (u = x, v = node)
+// h = hi32(c + alo*x) + ahi*x for c = (a2*node + b) mod 2^64; with x above it
+// (u = node, v = x) h = hi32(c + a2lo*x) + a2hi*x for c = (a*node + b) mod 2^64.
+// A run of one side keeps only that side's multipliers and constants live.
+struct SideConsts {
+    uint32_t mlo[3], mhi[3];
+    uint64_t c[3];
 };
+struct BothConsts {  // runs of mixed sides (the per-node path)
+    SideConsts below, above;
+};
+struct NoConsts {};
+template <bool kWide, int kSide>
+using ConstsOf = typename std::conditional<
+    !kWide, NoConsts,
+    typename std::conditional<kSide == kAnySide, BothConsts, SideConsts>::type>::type;
 
 __device__ __forceinline__ uint64_t mul64_add(uint32_t mlo, uint32_t mhi, uint32_t x, uint64_t c) {
     const uint64_t t = (uint64_t)mlo * x + c;
     return t + ((uint64_t)(mhi * x) << 32);
 }
 
-template <bool kWide>
-__device__ __forceinline__ NodeConsts<kWide> node_consts(const SeedsOf<kWide>& s, uint32_t node) {
-    NodeConsts<kWide> nc{};
-    if constexpr (kWide) {
+// word (k*3 + j)*2 + half of pair p sits at seeds[w*P + p] (k: row, checksum
+// high, checksum low; j: a, a2, b)
+template <int kSide>
+__device__ __forceinline__ SideConsts side_consts(const uint32_t* __restrict__ seeds, uint32_t P,
+                                                  uint32_t p, uint32_t node) {
+    SideConsts sc;
+    // the multiplier of x: a below the node, a2 above it; the other one multiplies the node
+    constexpr uint32_t jx = kSide == kBelow ? 0u : 1u, jn = 1u - jx;
 #pragma unroll
-        for (uint32_t k = 0; k < 3; ++k) {
-            nc.up[k] = mul64_add(s.h[k].alo, s.h[k].ahi, node, s.h[k].b);
-            nc.dn[k] = mul64_add(s.h[k].a2lo, s.h[k].a2hi, node, s.h[k].b);
-        }
-        nc.kidx = ((uint64_t)node * (node - 1u)) >> 1;
+    for (uint32_t k = 0; k < 3; ++k) {
+        const uint32_t w = k * 6;
+        sc.mlo[k] = seeds[(w + 2 * jx) * P + p];
+        sc.mhi[k] = seeds[(w + 2 * jx + 1) * P + p];
+        const uint32_t nlo = seeds[(w + 2 * jn) * P + p];
+        const uint32_t nhi = seeds[(w + 2 * jn + 1) * P + p];
+        const uint64_t b = (uint64_t)seeds[(w + 4) * P + p] | ((uint64_t)seeds[(w + 5) * P + p] << 32);
+        sc.c[k] = mul64_add(nlo, nhi, node, b);
     }
-    return nc;
+    return sc;
+}
+
+template <bool kWide, int kSide>
+__device__ __forceinline__ ConstsOf<kWide, kSide> item_consts(const GraphDesc& g, uint32_t p,
+                                                              uint32_t node) {
+    ConstsOf<kWide, kSide> cs{};
+    if constexpr (kWide && kSide == kAnySide) {
+        cs.below = side_consts<kBelow>(g.seeds, g.P, p, node);
+        cs.above = side_consts<kAbove>(g.seeds, g.P, p, node);
+    } else if constexpr (kWide) {
+        cs = side_consts<kSide>(g.seeds, g.P, p, node);
+    }
+    return cs;
 }
 
 template <bool kWide>
@@ -96,49 +128,43 @@ __device__ __forceinline__ Lane<kWide> make_lane(const GraphDesc& g) {
     ln.j = tid / g.P;
     ln.p = tid - ln.j * g.P;
     ln.active = tid < ln.J * g.P;
-    if (ln.active) {
-        if constexpr (kWide) ln.s = load_wide_seeds(g.seeds, g.P, ln.p);
-        else ln.s = load_pair_seeds(g.seeds, g.P, ln.p);
-    }
+    if constexpr (!kWide)
+        if (ln.active) ln.s = load_pair_seeds(g.seeds, g.P, ln.p);
     ln.tile_bytes = Layout<kWide>::lane_word(ln.p) * 4;
     ln.hbm_word = sk_word_n(Layout<kWide>::kPl, g.B, ln.p / kC, 0, 0, ln.p % kC);
     return ln;
 }
 
-// Which neighbours a run of entries of a wide graph holds: all below the node,
-// all above it, or either (tested per entry).  Three-plane graphs ignore it.
-enum : int { kAnySide = 0, kBelow = 1, kAbove = 2 };
-
 // The three hash words of an entry for this lane's pair (row hash, checksum
 // high, checksum low) and its 64-bit index (wide graphs; three-plane graphs
 // use the entry itself as the index).
 template <bool kWide, int kSide>
+__device__ __forceinline__ void hash_side(uint32_t x, uint32_t node, const SideConsts& sc,
+                                          uint32_t* h, uint64_t* idx) {
+#pragma unroll
+    for (uint32_t k = 0; k < 3; ++k) {
+        const uint64_t t = (uint64_t)sc.mlo[k] * x + sc.c[k];
+        h[k] = (uint32_t)(t >> 32) + sc.mhi[k] * x;
+    }
+    if (kSide == kAbove) *idx = (((uint64_t)x * (x - 1u)) >> 1) + node;
+    else *idx = (((uint64_t)node * (node - 1u)) >> 1) + x;
+}
+
+template <bool kWide, int kSide>
 __device__ __forceinline__ void hash_entry(uint32_t x, uint32_t node, const Lane<kWide>& ln,
-                                           const NodeConsts<kWide>& nc, uint32_t* h,
+                                           const ConstsOf<kWide, kSide>& cs, uint32_t* h,
                                            uint64_t* idx) {
     if constexpr (!kWide) {
         h[0] = mas_hash(ln.s.row_mlo, ln.s.row_mhi, ln.s.row_inc, x);
         h[1] = chk_hi(ln.s, x);
         h[2] = chk_lo(ln.s, x);
         *idx = x;
-    } else {
+    } else if constexpr (kSide == kAnySide) {
         // x is the neighbour: the edge is {node, x}
-        const bool above = kSide == kAbove || (kSide == kAnySide && x > node);
-        if (above) {
-#pragma unroll
-            for (uint32_t k = 0; k < 3; ++k) {
-                const uint64_t t = (uint64_t)ln.s.h[k].a2lo * x + nc.up[k];
-                h[k] = (uint32_t)(t >> 32) + ln.s.h[k].a2hi * x;
-            }
-            *idx = (((uint64_t)x * (x - 1u)) >> 1) + node;
-        } else {
-#pragma unroll
-            for (uint32_t k = 0; k < 3; ++k) {
-                const uint64_t t = (uint64_t)ln.s.h[k].alo * x + nc.dn[k];
-                h[k] = (uint32_t)(t >> 32) + ln.s.h[k].ahi * x;
-            }
-            *idx = nc.kidx + x;
-        }
+        if (x > node) hash_side<kWide, kAbove>(x, node, cs.above, h, idx);
+        else hash_side<kWide, kBelow>(x, node, cs.below, h, idx);
+    } else {
+        hash_side<kWide, kSide>(x, node, cs, h, idx);
     }
 }
 
@@ -154,7 +180,7 @@ __device__ __forceinline__ uint32_t depth_of(uint32_t h, uint32_t Bm1) {
 // entries are rare, so the common path stays free of branches.)
 template <bool kAllRows, bool kWide, int kSide>
 __device__ __forceinline__ bool xor_entry(uint32_t x, uint32_t node, const Lane<kWide>& ln,
-                                          const NodeConsts<kWide>& nc, uint32_t Bm1, uint32_t DL,
+                                          const ConstsOf<kWide, kSide>& nc, uint32_t Bm1, uint32_t DL,
                                           uint32_t row_bytes, uint8_t* __restrict__ tile) {
     uint32_t h[3];
     uint64_t idx;
@@ -179,7 +205,7 @@ __device__ __forceinline__ bool xor_entry(uint32_t x, uint32_t node, const Lane<
 // bucket of row 0, plane 0, in the node block); shallower entries do nothing.
 template <bool kWide, int kSide>
 __device__ __forceinline__ void xor_entry_deep(uint32_t x, uint32_t node, const Lane<kWide>& ln,
-                                               const NodeConsts<kWide>& nc, uint32_t Bm1,
+                                               const ConstsOf<kWide, kSide>& nc, uint32_t Bm1,
                                                uint32_t DL, uint32_t* __restrict__ skl,
                                                uint32_t plane_words) {
     uint32_t h[3];
@@ -327,7 +353,7 @@ __device__ __forceinline__ GroupShare group_share(const Src& ent, uint32_t lo, u
 template <bool kAllRows, bool kWide, int kSide, typename Src>
 __device__ __forceinline__ void xor_share(const Src& ent, GroupShare r, uint4 a, uint4 b,
                                           uint32_t node, const Lane<kWide>& ln,
-                                          const NodeConsts<kWide>& nc, uint32_t Bm1,
+                                          const ConstsOf<kWide, kSide>& nc, uint32_t Bm1,
                                           uint32_t DL, uint32_t row_bytes, uint8_t* tb,
                                           uint32_t* skl, uint32_t plane_words) {
     uint32_t e = r.e;
@@ -403,11 +429,11 @@ __device__ __forceinline__ void apply_entries(const Src& ent, uint32_t count, ui
                                               uint32_t* __restrict__ tile,
                                               uint32_t* __restrict__ skn, bool shared) {
     const TileWalk<kWide> tw(g.P, g.B, DL);
-    NodeConsts<kWide> nc{};
+    ConstsOf<kWide, kSide1> nc{};
     GroupShare r{};
     uint4 a = make_uint4(0, 0, 0, 0), b = a;
     if (ln.active) {
-        nc = node_consts<kWide>(ln.s, node);
+        nc = item_consts<kWide, kSide1>(g, ln.p, node);
         r = group_share(ent, 0, split, ln.J, ln.j);
         if (r.pipe) {
             a = ent.quad(r.ea);
@@ -433,7 +459,8 @@ __device__ __forceinline__ void apply_entries(const Src& ent, uint32_t count, ui
                     a2 = ent.quad(r2.ea);
                     b2 = ent.quad(r2.ea + 4);
                 }
-                xor_share<kAllRows, kWide, kAbove>(ent, r2, a2, b2, node, ln, nc, Bm1, DL,
+                const ConstsOf<kWide, kAbove> nc2 = item_consts<kWide, kAbove>(g, ln.p, node);
+                xor_share<kAllRows, kWide, kAbove>(ent, r2, a2, b2, node, ln, nc2, Bm1, DL,
                                                    row_bytes, tb, skl, plane_words);
             }
         }

@@ -216,3 +216,24 @@ def test_wide_largest_graph(gz):
     nodes = sorted(set(s.src[:20].tolist()) | set(s.dst[:20].tolist()) | {0, 1, V - 1, V // 2})
     assert_sketch_equal(g, O, nodes=nodes)
     assert_query_equal(g, O)
+
+
+@pytest.mark.parametrize("V,R,n,seed", [(65537, 3, 1_000_000, 61), (1 << 20, 2, 6_000_000, 62)])
+def test_wide_two_pass_grouping_edges(gz, V, R, n, seed):
+    """The bucket-first grouping at its smallest (V = 2^16 + 1) and largest (V = 2^20) sizes,
+    on hub-heavy R-MAT draws whose first bucket is cut into many pieces: sampled node
+    sketches (the six largest hubs included) against the oracle."""
+    s = workloads.rmat_draws(1 << (V - 1).bit_length(), workloads.RMAT_GRAPH500, n, seed)
+    keep = (s.src < V) & (s.dst < V)
+    s = workloads.Stream(V, s.src[keep], s.dst[keep], s.op[keep])
+    g = gz.Graph(V, seed=seed, rounds=R)
+    g.ingest(to_dev(s.src), to_dev(s.dst))
+    deg = np.bincount(np.concatenate([s.src, s.dst]).astype(np.int64), minlength=V)
+    rng = np.random.default_rng(seed)
+    hubs = np.argsort(deg)[::-1][:6].tolist()
+    nodes = sorted(set(rng.choice(V, 10, replace=False).tolist()) | set(hubs) | {0, V - 1})
+    O = oracle.Oracle(V, seed, R=R)
+    O.ingest_nodes(s.src, s.dst, nodes)
+    for v in nodes:
+        a, b = g.export(v, v + 1)
+        assert (a[0] == O.alpha[v]).all() and (b[0] == O.gamma[v]).all(), f"node {v}"

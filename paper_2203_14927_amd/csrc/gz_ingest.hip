@@ -196,28 +196,6 @@ struct SortSmem {
     uint32_t total;
 };
 
-// Lanes of the wave holding the same key (key < 2^bits), found by voting on
-// the key's bits: the lowest of them (leader), this lane's rank among them and
-// their number.  Every lane of the wave must call it.
-// Peers of a lane, packed: leader lane (bits 0..5), this lane's rank among
-// the peers (bits 6..11), number of peers (bits 12..18).
-__device__ __forceinline__ uint32_t wave_peers(uint32_t key, uint32_t bits, bool valid) {
-    uint64_t m = __ballot(valid);
-    for (uint32_t b = 0; b < bits; ++b) {
-        const bool bit = (key >> b) & 1u;
-        const uint64_t ones = __ballot(bit);
-        m &= bit ? ones : ~ones;
-    }
-    const uint32_t lane = __lane_id();
-    const uint32_t leader = valid ? (uint32_t)__ffsll((unsigned long long)m) - 1u : lane;
-    const uint32_t rank = (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
-    const uint32_t count = (uint32_t)__popcll(m);
-    return leader | (rank << 6) | (count << 12);
-}
-__device__ __forceinline__ uint32_t peer_leader(uint32_t p) { return p & 63u; }
-__device__ __forceinline__ uint32_t peer_rank(uint32_t p) { return (p >> 6) & 63u; }
-__device__ __forceinline__ uint32_t peer_count(uint32_t p) { return p >> 12; }
-
 // Keys and values of a batch computed into registers here, before the next
 // batch's loads are issued (so that the sort never waits on those loads).
 __device__ __forceinline__ void materialise(uint32_t (&key)[kSortPerThread],
@@ -235,24 +213,22 @@ __device__ __forceinline__ void lds_barrier() {
 
 // Append one batch of (key, value) pairs, kSortPerThread per thread, to the
 // runs of `out` whose next free slots are cur[key] (block-private LDS
-// cursors, advanced here).  LDS atomics are taken once per distinct key of a
-// wave, so hot keys do not serialise.  Every thread of the block must call it.
+// cursors, advanced here): the batch is counted per key and staged in LDS in
+// key order, then each key's share is stored with consecutive lanes.  Order
+// within a key is whatever the LDS atomics give (the sketch update is a sum
+// over Z2, so the sketches do not depend on it).  Every thread of the block
+// must call it.
 __device__ __forceinline__ void batch_append(const uint32_t (&key)[kSortPerThread],
                                              const uint32_t (&val)[kSortPerThread],
-                                             uint32_t valid_mask, uint32_t bits, uint32_t nkeys,
+                                             uint32_t valid_mask, uint32_t nkeys,
                                              uint32_t* __restrict__ cur, SortSmem& sm,
                                              uint32_t* __restrict__ out) {
     const uint32_t tid = threadIdx.x;
-    const uint32_t lane = __lane_id();
     for (uint32_t k = tid; k < nkeys; k += blockDim.x) sm.cnt[k] = 0;
     lds_barrier();
-    uint32_t pe[kSortPerThread];
 #pragma unroll
-    for (uint32_t j = 0; j < kSortPerThread; ++j) {
-        const bool ok = (valid_mask >> j) & 1u;
-        pe[j] = wave_peers(key[j], bits, ok);
-        if (ok && lane == peer_leader(pe[j])) atomicAdd(&sm.cnt[key[j]], peer_count(pe[j]));
-    }
+    for (uint32_t j = 0; j < kSortPerThread; ++j)
+        if ((valid_mask >> j) & 1u) atomicAdd(&sm.cnt[key[j]], 1u);
     lds_barrier();
     if (tid < 64) {  // one wave scans the (at most 256) counts, four per lane
         uint32_t c[4], run = 0;
@@ -284,15 +260,10 @@ __device__ __forceinline__ void batch_append(const uint32_t (&key)[kSortPerThrea
     lds_barrier();
 #pragma unroll
     for (uint32_t j = 0; j < kSortPerThread; ++j) {
-        const bool ok = (valid_mask >> j) & 1u;
-        uint32_t base = 0;
-        if (ok && lane == peer_leader(pe[j])) base = atomicAdd(&sm.cnt[key[j]], peer_count(pe[j]));
-        base = __shfl(base, (int)peer_leader(pe[j]));
-        if (ok) {
-            const uint32_t p = base + peer_rank(pe[j]);
-            sm.val[p] = val[j];
-            sm.key[p] = (uint8_t)key[j];
-        }
+        if (!((valid_mask >> j) & 1u)) continue;
+        const uint32_t p = atomicAdd(&sm.cnt[key[j]], 1u);
+        sm.val[p] = val[j];
+        sm.key[p] = (uint8_t)key[j];
     }
     lds_barrier();
     const uint32_t total = sm.total;
@@ -341,7 +312,6 @@ __global__ __launch_bounds__(kGroupThreads) void k_group_partition(
     for (uint32_t k = threadIdx.x; k < nbk; k += blockDim.x) cur[k] = base[blockIdx.x * nbk + k];
     __syncthreads();
     const uint32_t mask = (1u << S) - 1u;
-    const uint32_t kbits = 32u - __builtin_clz((nbk - 1u) | 1u);  // bucket ids < 2^kbits
     const uint32_t nbits = g.wide ? 32u - __builtin_clz((g.V - 1u) | 1u) : 16u;
     constexpr uint32_t kUpd = kSortPerThread / 2;                  // two entries per update
     const uint64_t step = (uint64_t)kUpd * blockDim.x;
@@ -372,7 +342,7 @@ __global__ __launch_bounds__(kGroupThreads) void k_group_partition(
             xs[k] = in < r.i1 ? src[in] : 0u;
             ys[k] = in < r.i1 ? dst[in] : 0u;
         }
-        batch_append(key, val, ok, kbits, nbk, cur, sm, tmp);
+        batch_append(key, val, ok, nbk, cur, sm, tmp);
     }
 }
 
@@ -418,7 +388,7 @@ __global__ __launch_bounds__(kGroupThreads) void k_group_place(
             const uint32_t en = e0 + step + threadIdx.x + k * blockDim.x;
             ws[k] = en < e1 ? tmp[en] : 0u;
         }
-        batch_append(key, val, ok, S, n, cur, sm, grouped);
+        batch_append(key, val, ok, n, cur, sm, grouped);
     }
 }
 

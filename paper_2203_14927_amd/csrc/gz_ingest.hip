@@ -65,6 +65,8 @@ __device__ __forceinline__ UnitRange unit_range(const IngestArgs* __restrict__ a
     return r;
 }
 
+constexpr uint32_t kCountBatch = 4;  // updates loaded per thread before counting any
+
 // pass 1: LDS histogram of one chunk's endpoints; validation of the updates
 // (ctl[2]: this call saw an invalid update; ctl[3]: sticky error for gz_flush)
 __global__ __launch_bounds__(kGroupThreads) void k_group_count(
@@ -79,15 +81,27 @@ __global__ __launch_bounds__(kGroupThreads) void k_group_count(
     for (uint32_t k = threadIdx.x; k < r.size; k += blockDim.x) hist[k] = 0;
     __syncthreads();
     bool bad = false;
-    for (uint64_t i = r.i0 + threadIdx.x; i < r.i1; i += blockDim.x) {
-        const uint32_t x = src[i], y = dst[i];
-        if (x == y || x >= g.V || y >= g.V) {
-            bad = true;
-            continue;
+    // loads issued kCountBatch at a time, so that they are in flight together
+    for (uint64_t i0 = r.i0; i0 < r.i1; i0 += (uint64_t)kCountBatch * blockDim.x) {
+        uint32_t x[kCountBatch], y[kCountBatch], in = 0;
+#pragma unroll
+        for (uint32_t k = 0; k < kCountBatch; ++k) {
+            const uint64_t i = i0 + threadIdx.x + (uint64_t)k * blockDim.x;
+            if (i < r.i1) in |= 1u << k;
+            x[k] = i < r.i1 ? src[i] : 0u;
+            y[k] = i < r.i1 ? dst[i] : 0u;
         }
-        const uint32_t xo = x - r.lo, yo = y - r.lo;
-        if (xo < r.size) atomicAdd(&hist[xo], 1u);
-        if (yo < r.size) atomicAdd(&hist[yo], 1u);
+#pragma unroll
+        for (uint32_t k = 0; k < kCountBatch; ++k) {
+            if (!((in >> k) & 1u)) continue;
+            if (x[k] == y[k] || x[k] >= g.V || y[k] >= g.V) {
+                bad = true;
+                continue;
+            }
+            const uint32_t xo = x[k] - r.lo, yo = y[k] - r.lo;
+            if (xo < r.size) atomicAdd(&hist[xo], 1u);
+            if (yo < r.size) atomicAdd(&hist[yo], 1u);
+        }
     }
     if (bad && u.q == 0) {
         atomicOr(&ctl[2], 1u);
@@ -99,32 +113,54 @@ __global__ __launch_bounds__(kGroupThreads) void k_group_count(
 }
 
 // The count table of a graph is chunk-major: H[hoff + c * V + v].  A node's
-// entries total the column sum over its chunks ...
+// entries total the column sum over its chunks ...  kColLanes adjacent lanes
+// share a node, each taking a contiguous quarter of its chunks, so that more
+// loads are in flight than one lane per node would issue.
+constexpr uint32_t kColLanes = 4;
+
 __global__ void k_group_colsum(const GraphDesc* __restrict__ gd, uint32_t G, uint32_t T,
                                const uint32_t* __restrict__ H, uint32_t* __restrict__ counts) {
-    for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < T; v += gridDim.x * blockDim.x) {
+    const uint32_t sub = threadIdx.x % kColLanes;
+    for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < T * kColLanes;
+         t += gridDim.x * blockDim.x) {
+        const uint32_t v = t / kColLanes;
         const uint32_t gi = G == 1 ? 0u : graph_of_node(gd, G, v);
         const GraphDesc& g = gd[gi];
         const uint32_t* col = H + g.hoff + (v - g.node_base);
+        const uint32_t c0 = g.nb * sub / kColLanes, c1 = g.nb * (sub + 1) / kColLanes;
         uint32_t sum = 0;
-        for (uint32_t c = 0; c < g.nb; ++c) sum += col[(uint64_t)c * g.V];
-        counts[v] = sum;
+        for (uint32_t c = c0; c < c1; ++c) sum += col[(uint64_t)c * g.V];
+        for (uint32_t off = 1; off < kColLanes; off <<= 1) sum += __shfl_xor(sum, off, kColLanes);
+        if (sub == 0) counts[v] = sum;
     }
 }
 
 // ... and, once the node's first slot is known, each chunk's run starts after
-// the runs of the earlier chunks (in-place exclusive scan down the column)
+// the runs of the earlier chunks (in-place exclusive scan down the column:
+// each lane sums its quarter, the lanes scan those sums, then each rewrites
+// its quarter)
 __global__ void k_group_colscan(const GraphDesc* __restrict__ gd, uint32_t G, uint32_t T,
                                 const uint32_t* __restrict__ nodeoff, uint32_t* __restrict__ H) {
-    for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < T; v += gridDim.x * blockDim.x) {
+    const uint32_t sub = threadIdx.x % kColLanes;
+    for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < T * kColLanes;
+         t += gridDim.x * blockDim.x) {
+        const uint32_t v = t / kColLanes;
         const uint32_t gi = G == 1 ? 0u : graph_of_node(gd, G, v);
         const GraphDesc& g = gd[gi];
         uint32_t* col = H + g.hoff + (v - g.node_base);
-        uint32_t run = nodeoff[v];
-        for (uint32_t c = 0; c < g.nb; ++c) {
-            const uint32_t t = col[(uint64_t)c * g.V];
+        const uint32_t c0 = g.nb * sub / kColLanes, c1 = g.nb * (sub + 1) / kColLanes;
+        uint32_t part = 0;
+        for (uint32_t c = c0; c < c1; ++c) part += col[(uint64_t)c * g.V];
+        uint32_t incl = part;  // inclusive scan over the node's lanes
+        for (uint32_t off = 1; off < kColLanes; off <<= 1) {
+            const uint32_t y = __shfl_up(incl, off, kColLanes);
+            if (sub >= off) incl += y;
+        }
+        uint32_t run = nodeoff[v] + incl - part;
+        for (uint32_t c = c0; c < c1; ++c) {
+            const uint32_t x = col[(uint64_t)c * g.V];
             col[(uint64_t)c * g.V] = run;
-            run += t;
+            run += x;
         }
     }
 }
@@ -989,13 +1025,14 @@ gz_status launch_sequence(IngestScratch& S, const LaunchShape& L, hipStream_t st
         k_group_count<<<L.n_units, kGroupThreads, L.gsmem, stream>>>(S.args, S.units, S.descs,
                                                                      S.H, S.ctl);
     }
-    k_group_colsum<<<grid_for(Tn, 256, 8192), 256, 0, stream>>>(S.descs, L.G, Tn, S.H, S.counts);
+    k_group_colsum<<<grid_for((uint64_t)Tn * kColLanes, 256, 16384), 256, 0, stream>>>(
+        S.descs, L.G, Tn, S.H, S.counts);
     k_scan_partial<<<L.nblocks, kScanThreads, 0, stream>>>(S.counts, Tn, L.chunk, S.block_sums);
     k_scan_top<<<1, kScanThreads, 0, stream>>>(S.block_sums, L.nblocks, S.ctl);
     k_scan_items<<<L.nblocks, kScanThreads, 0, stream>>>(S.counts, Tn, L.chunk, S.block_sums,
                                                          S.items, S.cursor, S.descs, L.G, S.ctl);
-    k_group_colscan<<<grid_for(Tn, 256, 8192), 256, 0, stream>>>(S.descs, L.G, Tn, S.cursor,
-                                                                  S.H);
+    k_group_colscan<<<grid_for((uint64_t)Tn * kColLanes, 256, 16384), 256, 0, stream>>>(
+        S.descs, L.G, Tn, S.cursor, S.H);
     if (wide2) {
         uint32_t* pieces = S.bbase + (uint64_t)(L.nbc + 1) * L.nbk;
         k_group_pieces<<<1, kMaxBuckets, 0, stream>>>(S.bbase, L.nbk, L.nbc, L.ptarget, L.pcap,

@@ -237,3 +237,32 @@ def test_wide_two_pass_grouping_edges(gz, V, R, n, seed):
     for v in nodes:
         a, b = g.export(v, v + 1)
         assert (a[0] == O.alpha[v]).all() and (b[0] == O.gamma[v]).all(), f"node {v}"
+
+
+@pytest.mark.parametrize("V", [70000, (1 << 20) + 3])
+def test_wide_invalid_updates_rejected_and_nothing_applied(gz, V):
+    """Self-loops and ids >= V are rejected by the bucket-first grouping (V <= 2^20) and by
+    the one-pass grouping (larger V) alike, synchronously and at flush, applying nothing."""
+    g = gz.Graph(V, seed=5, rounds=1)
+    good = (np.array([1, V - 1, 70], np.uint32), np.array([V - 2, 3, 65536], np.uint32))
+    g.ingest(to_dev(good[0]), to_dev(good[1]))
+    nodes = [1, 3, 70, 65536, V - 2, V - 1]
+    before = [g.export(v, v + 1) for v in nodes]
+    for src, dst in [([1, 7], [1, 8]), ([1, 2], [3, V]), ([V + 5], [1])]:
+        with pytest.raises(gz.GzError) as e:
+            g.ingest(to_dev(np.array(src, np.uint32)), to_dev(np.array(dst, np.uint32)))
+        assert e.value.status == gz.GZ_EINVAL
+        with pytest.raises(gz.GzError):
+            g.ingest(np.array(src, np.uint32), np.array(dst, np.uint32))
+    g.ingest(to_dev(np.array([9, 9], np.uint32)), to_dev(np.array([9, 10], np.uint32)),
+             flags=gz.GZ_ASYNC)
+    with pytest.raises(gz.GzError):
+        g.flush()
+    g.flush()
+    after = [g.export(v, v + 1) for v in nodes]
+    for (a1, b1), (a2, b2), v in zip(before, after, nodes):
+        assert (a1 == a2).all() and (b1 == b2).all(), f"node {v} changed"
+    O = oracle.Oracle(V, 5, R=1)
+    O.ingest_nodes(good[0], good[1], nodes)
+    for v, (a, b) in zip(nodes, after):
+        assert (a[0] == O.alpha[v]).all() and (b[0] == O.gamma[v]).all(), f"node {v}"

@@ -255,25 +255,29 @@ struct NeighbourEntries {
 };
 
 // Walk over the tile rows d < DL of a node in HBM order of the round-major
-// block: flat index i over planes * DL * P words, row = i / P (by a reciprocal
-// multiply, exact for i * P < 2^32), p = i mod P, d = row / planes,
-// plane = row mod planes.  Consecutive lanes take consecutive pairs of one
-// (plane, row), so their LDS words fall in distinct banks and their HBM words
-// form runs of C columns.
+// block: flat index i over planes * DL * P words, c = i mod C, d = (i / C) mod
+// DL, then the (round, plane) run, so consecutive lanes read and write the
+// DL * C contiguous words of one (round, plane) run of the node block (the
+// divisions by DL > 1 are reciprocal multiplies, exact for i < 2^32 / DL).  Their
+// LDS words fall in C banks per row (at most 8-way conflicts on the tile
+// set-up, a small cost next to a coalesced HBM access).
 template <bool kWide>
 struct TileWalk {
     static constexpr uint32_t kPl = Layout<kWide>::kPl;
     uint32_t P, B, DL, RW, n, recip;
     __device__ __forceinline__ TileWalk(uint32_t P_, uint32_t B_, uint32_t DL_)
         : P(P_), B(B_), DL(DL_), RW(tile_row_words(P_, kWide)), n(kPl * DL_ * P_),
-          recip(0xFFFFFFFFu / P_ + 1u) {}
+          recip(0xFFFFFFFFu / DL_ + 1u) {}
     __device__ __forceinline__ void at(uint32_t i, uint32_t* t, uint32_t* h) const {
-        const uint32_t row = __umulhi(i, recip);
-        const uint32_t p = i - row * P;
-        const uint32_t d = row / kPl;
-        const uint32_t pl = row - d * kPl;
-        *t = d * RW + Layout<kWide>::lane_word(p) + pl * Layout<kWide>::kPlaneStep;
-        *h = sk_word_n(kPl, B, p / kC, pl, d, p % kC);
+        const uint32_t c = i % kC;
+        const uint32_t q = i / kC;
+        // (round, plane) run; DL = 1 has no 32-bit reciprocal (it would be 2^32)
+        const uint32_t run = DL == 1u ? q : __umulhi(q, recip);
+        const uint32_t d = q - run * DL;
+        const uint32_t r = run / kPl;
+        const uint32_t pl = run - r * kPl;
+        *t = d * RW + Layout<kWide>::lane_word(r * kC + c) + pl * Layout<kWide>::kPlaneStep;
+        *h = (run * B + d) * kC + c;  // sk_word_n(kPl, B, r, pl, d, c)
     }
 };
 

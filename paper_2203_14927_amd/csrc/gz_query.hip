@@ -20,6 +20,14 @@
 
 namespace gz {
 
+// one workgroup of the component reduce: consecutive nodes of one graph
+struct ReduceSpan {
+    uint32_t v0;     // first node (global id)
+    uint32_t n;      // nodes, at most 2048
+    uint32_t graph;  // descriptor of the span's graph
+    uint32_t whole;  // the span holds every node of its graph
+};
+
 struct QueryScratch {
     int device = -1;
     uint32_t cap_nodes = 0, cap_graphs = 0, cap_wpr = 0;
@@ -33,6 +41,8 @@ struct QueryScratch {
     uint32_t *fpairs = nullptr;
     uint64_t *forest = nullptr, *fsorted = nullptr;
     GraphDesc* descs = nullptr;
+    ReduceSpan* spans = nullptr;  // the reduce's workgroup table
+    uint32_t cap_spans = 0;
     uint32_t* pos = nullptr;      // list position of every current component
     uint32_t* host_na = nullptr;  // pinned: active components of each round
     hipEvent_t round_ev[2] = {nullptr, nullptr};
@@ -58,6 +68,37 @@ __device__ __forceinline__ uint64_t key_index(const uint32_t* __restrict__ ctl, 
 }
 
 // ---------------------------------------------------------------- kernels --
+
+// Positions in a list whose length counter the whole grid shares: one atomic
+// per workgroup.  Same-address atomics from across the chip serialise (the
+// compiler already merges a wave's into one), so a list of millions of
+// components built with one atomic per wave spent most of its time on them.
+// Every thread of the workgroup calls it, in workgroup-uniform control flow;
+// threads with take set get distinct positions, the others a value they must
+// not use.  sh holds kMaxWaves + 1 words.
+constexpr uint32_t kAppendThreads = 1024;
+constexpr uint32_t kMaxWaves = kAppendThreads / 64;
+
+__device__ __forceinline__ uint32_t block_append(uint32_t* __restrict__ counter, bool take,
+                                                 uint32_t* sh) {
+    const uint32_t lane = __lane_id(), wave = threadIdx.x >> 6;
+    const uint64_t m = __ballot(take);
+    if (lane == 0) sh[wave] = (uint32_t)__popcll(m);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t sum = 0;
+        for (uint32_t w = 0; w < (blockDim.x >> 6); ++w) {
+            const uint32_t c = sh[w];
+            sh[w] = sum;
+            sum += c;
+        }
+        sh[kMaxWaves] = sum ? atomicAdd(counter, sum) : 0u;
+    }
+    __syncthreads();
+    const uint32_t at = sh[kMaxWaves] + sh[wave] + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+    __syncthreads();  // sh is reused by the next call
+    return at;
+}
 
 __device__ __forceinline__ uint32_t q_graph_of_node(const GraphDesc* __restrict__ gd, uint32_t G,
                                                     uint32_t node) {
@@ -91,102 +132,139 @@ __global__ void k_q_init(uint32_t T, const GraphDesc* __restrict__ gd, uint32_t 
     }
 }
 
-__global__ void k_q_select(uint32_t r, const uint32_t* __restrict__ L, uint32_t* __restrict__ ctl,
-                           const uint32_t* __restrict__ done, const uint32_t* __restrict__ gof,
-                           const GraphDesc* __restrict__ gd, uint32_t* __restrict__ slot,
-                           uint32_t* __restrict__ A, uint32_t* __restrict__ hook,
-                           uint32_t* __restrict__ newlab, uint32_t* __restrict__ merged,
-                           uint32_t* __restrict__ pos) {
+__global__ __launch_bounds__(kAppendThreads) void k_q_select(
+    uint32_t r, const uint32_t* __restrict__ L, uint32_t* __restrict__ ctl,
+    const uint32_t* __restrict__ done, const uint32_t* __restrict__ gof,
+    const GraphDesc* __restrict__ gd, uint32_t* __restrict__ slot, uint32_t* __restrict__ A,
+    uint32_t* __restrict__ hook, uint32_t* __restrict__ newlab, uint32_t* __restrict__ merged,
+    uint32_t* __restrict__ pos) {
+    __shared__ uint32_t sh[kMaxWaves + 1];
     if (ctl[Q_STOP]) return;
     const uint32_t nL = ctl[Q_NL];
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nL; i += gridDim.x * blockDim.x) {
-        const uint32_t X = L[i];
-        pos[X] = i;
-        hook[X] = kNone;
-        newlab[X] = kNone;
-        merged[X] = 0;
-        if (!done[X] && r < gd[gof[X]].R) {
-            const uint32_t a = atomicAdd(&ctl[Q_NA], 1u);
-            A[a] = X;
-            slot[X] = a;
-        } else {
-            slot[X] = kNone;
+    for (uint32_t i0 = blockIdx.x * blockDim.x; i0 < nL; i0 += gridDim.x * blockDim.x) {
+        const uint32_t i = i0 + threadIdx.x;
+        bool act = false;
+        uint32_t X = 0;
+        if (i < nL) {
+            X = L[i];
+            pos[X] = i;
+            hook[X] = kNone;
+            newlab[X] = kNone;
+            merged[X] = 0;
+            act = !done[X] && r < gd[gof[X]].R;
         }
+        const uint32_t a = block_append(&ctl[Q_NA], act, sh);
+        if (i < nL) slot[X] = act ? a : kNone;
+        if (act) A[a] = X;
     }
 }
 
 // XOR the round-r rows of every active component's members into the
-// component's accumulator [slot][plane][d][c].  A workgroup walks a span of
-// consecutive node ids, one thread per accumulator word, keeping a running XOR
-// while the component stays the same and flushing it with one atomic per word
-// when it changes (components are large after the first round, so consecutive
-// ids mostly share one and a span costs one atomic per word).  Loads are issued
-// kReduceRun nodes at a time so that they are in flight together; blockIdx.y
-// picks the block of accumulator words, so a round runs ceil(T / span) x
-// ceil(words / blockDim) workgroups.  The span grows with T (up to
-// kReduceSpanMax) so that a large graph's giant component does not take one
-// device-scope atomic per word from tens of thousands of workgroups.
+// component's accumulator [slot][plane][d][c].  A workgroup takes a span of
+// consecutive nodes of one graph and first sorts the span's members by
+// component in LDS (a bitonic network over (slot, position) keys; nodes of
+// finished components sort last and drop out).  It then walks the members with
+// one thread per accumulator word, keeping a running XOR and flushing it when
+// the component changes, so a span costs one flush per word for each component
+// it meets however the components interleave in node order (in node order, a
+// few large interleaved components took one atomic per member).  A span that
+// holds its whole graph holds every member of its components: it stores the
+// sums, and the accumulators need no zeroing; other spans XOR them in with
+// atomics.  Loads are issued kReduceRun members at a time so that they are in
+// flight together; blockIdx.y picks the block of accumulator words.  Spans of
+// one large graph grow with its size (up to kReduceSpanCap) so that its giant
+// component does not take one device-scope atomic per word from tens of
+// thousands of workgroups.
 constexpr uint32_t kReduceRun = 16;
 constexpr uint32_t kReduceSpan = 64;
-constexpr uint32_t kReduceSpanMax = 1024;
-constexpr uint32_t kReduceBlocks = 1024;  // spans double while a round takes > 2x this many
+constexpr uint32_t kReduceSpanCap = 1024;  // spans that cut a graph
+constexpr uint32_t kReduceSpanMax = 2048;  // spans that hold a whole graph
+constexpr uint32_t kReduceBlocks = 1024;   // spans double while a round takes > 2x this many
 
 uint32_t reduce_span(uint32_t T, uint32_t yblocks) {
     uint32_t span = kReduceSpan;
-    while (span < kReduceSpanMax &&
+    while (span < kReduceSpanCap &&
            ((uint64_t)T + span - 1) / span * yblocks > 2ull * kReduceBlocks)
         span *= 2;
     return span;
 }
 
-__global__ __launch_bounds__(256) void k_q_reduce(uint32_t r, uint32_t T, uint32_t span,
+__global__ __launch_bounds__(256) void k_q_reduce(uint32_t r, const ReduceSpan* __restrict__ spans,
                                                   const uint32_t* __restrict__ comp,
                                                   const uint32_t* __restrict__ slot,
-                                                  const uint32_t* __restrict__ gof,
                                                   const GraphDesc* __restrict__ gd, uint32_t wpr,
                                                   uint32_t* __restrict__ acc,
                                                   const uint32_t* __restrict__ ctl) {
-    __shared__ uint32_t s_slot[kReduceSpanMax];
-    __shared__ const uint32_t* s_base[kReduceSpanMax];
-    __shared__ uint32_t s_words[kReduceSpanMax];
+    __shared__ uint64_t s_key[kReduceSpanMax];  // slot << 32 | position; ~0 if not active
+    __shared__ uint32_t s_nact;
     if (ctl[Q_STOP]) return;
-    const uint32_t v0 = blockIdx.x * span;
-    const uint32_t n = min(T - v0, span);
-    for (uint32_t t = threadIdx.x; t < n; t += blockDim.x) {
-        const uint32_t v = v0 + t;
-        const uint32_t sl = slot[comp[v]];
-        s_slot[t] = sl;
-        const GraphDesc& g = gd[gof[v]];
-        s_base[t] = g.sk + (uint64_t)(v - g.node_base) * g.node_words +
-                    (g.round_view ? 0u : sk_word_n(g.planes, g.B, r, 0, 0, 0));
-        s_words[t] = g.planes * g.B * kC;
+    const ReduceSpan sp = spans[blockIdx.x];
+    uint32_t np = kReduceSpan;  // sorting width: a power of two >= the span's nodes
+    while (np < sp.n) np <<= 1;
+    if (threadIdx.x == 0) s_nact = 0;
+    __syncthreads();
+    for (uint32_t t = threadIdx.x; t < np; t += blockDim.x) {
+        uint64_t key = ~0ull;
+        if (t < sp.n) {
+            const uint32_t sl = slot[comp[sp.v0 + t]];
+            if (sl != kNone) key = ((uint64_t)sl << 32) | t;
+        }
+        s_key[t] = key;
+        const uint64_t m = __ballot(key != ~0ull);
+        if (__lane_id() == 0 && m) atomicAdd(&s_nact, (uint32_t)__popcll(m));
     }
     __syncthreads();
-    {
-        // word w = (plane * B + d) * C + c of the round's contiguous rows
-        const uint32_t w = blockIdx.y * blockDim.x + threadIdx.x;
-        uint32_t run = 0, run_slot = kNone;
-        for (uint32_t b = 0; b < n; b += kReduceRun) {
-            uint32_t val[kReduceRun];
-#pragma unroll
-            for (uint32_t i = 0; i < kReduceRun; ++i) {
-                const uint32_t j = b + i;
-                val[i] = (j < n && s_slot[j] != kNone && w < s_words[j]) ? s_base[j][w] : 0u;
-            }
-#pragma unroll
-            for (uint32_t i = 0; i < kReduceRun; ++i) {
-                const uint32_t j = b + i;
-                const uint32_t sl = j < n ? s_slot[j] : kNone;
-                if (sl != run_slot) {
-                    if (run_slot != kNone && run)
-                        atomicXor(&acc[(uint64_t)run_slot * wpr + w], run);
-                    run = 0;
-                    run_slot = sl;
+    for (uint32_t k = 2; k <= np; k <<= 1) {
+        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+            for (uint32_t i = threadIdx.x; i < np / 2; i += blockDim.x) {
+                const uint32_t lo = ((i & ~(j - 1u)) << 1) | (i & (j - 1u));
+                const uint32_t hi = lo + j;
+                const uint64_t x = s_key[lo], y = s_key[hi];
+                if ((x > y) == ((lo & k) == 0)) {
+                    s_key[lo] = y;
+                    s_key[hi] = x;
                 }
-                run ^= val[i];
             }
+            __syncthreads();
         }
-        if (run_slot != kNone && run) atomicXor(&acc[(uint64_t)run_slot * wpr + w], run);
+    }
+    const uint32_t na = s_nact;
+    const GraphDesc& g = gd[sp.graph];
+    // word w = (plane * B + d) * C + c of the round's contiguous rows
+    const uint32_t w = blockIdx.y * blockDim.x + threadIdx.x;
+    if (w >= g.planes * g.B * kC) return;
+    const uint32_t stride = g.node_words;
+    const uint32_t* base = g.sk + (uint64_t)(sp.v0 - g.node_base) * stride +
+                           (g.round_view ? 0u : sk_word_n(g.planes, g.B, r, 0, 0, 0)) + w;
+    const bool whole = sp.whole != 0;
+    uint32_t run = 0, run_slot = kNone;
+    for (uint32_t b = 0; b < na; b += kReduceRun) {
+        uint32_t val[kReduceRun];
+#pragma unroll
+        for (uint32_t i = 0; i < kReduceRun; ++i) {
+            const uint32_t j = b + i;
+            val[i] = j < na ? base[(uint64_t)(uint32_t)s_key[j] * stride] : 0u;
+        }
+#pragma unroll
+        for (uint32_t i = 0; i < kReduceRun; ++i) {
+            const uint32_t j = b + i;
+            const uint32_t sl = j < na ? (uint32_t)(s_key[j] >> 32) : kNone;
+            if (sl != kNone && sl != run_slot) {
+                if (run_slot != kNone) {
+                    uint32_t* dst = &acc[(uint64_t)run_slot * wpr + w];
+                    if (whole) *dst = run;
+                    else if (run) atomicXor(dst, run);
+                }
+                run = 0;
+                run_slot = sl;
+            }
+            run ^= val[i];
+        }
+    }
+    if (run_slot != kNone) {
+        uint32_t* dst = &acc[(uint64_t)run_slot * wpr + w];
+        if (whole) *dst = run;
+        else if (run) atomicXor(dst, run);
     }
 }
 
@@ -206,6 +284,8 @@ __global__ void k_q_zero_acc(const uint32_t* __restrict__ ctl, uint32_t wpr,
 // rows from the deepest up (suffix XOR of the exact-depth basis) and keep the
 // first good bucket in column-major, row-ascending order; ZERO marks the
 // component done, FAIL leaves it without a hook.
+constexpr uint32_t kQueryRows = 4;
+
 template <bool kDirect>
 __device__ __forceinline__ void query_component(uint32_t r, uint32_t gtid, uint32_t nA,
                                                 const uint32_t* __restrict__ A,
@@ -233,30 +313,47 @@ __device__ __forceinline__ void query_component(uint32_t r, uint32_t gtid, uint3
                  (g.round_view ? c : sk_word_n(g.planes, B, r, 0, 0, c));
         else
             in = acc + (uint64_t)a * wpr + c;
+        // rows are read kQueryRows at a time, deepest first, so that their
+        // loads are in flight together; a later (shallower) good row replaces
+        // an earlier one
+        int b = (int)B - 1;
         if (!g.wide) {
             const PairSeeds s = load_pair_seeds(g.seeds, g.P, p);
             uint32_t al = 0, glo = 0, ghi = 0;
-            for (int b = (int)B - 1; b >= 0; --b) {
-                al ^= in[(0 * B + b) * kC];
-                glo ^= in[(1 * B + b) * kC];
-                ghi ^= in[(2 * B + b) * kC];
+            auto row = [&](int bb, uint32_t xa, uint32_t xg, uint32_t xh) {
+                al ^= xa;
+                glo ^= xg;
+                ghi ^= xh;
                 if (al | glo | ghi) {
                     nonempty = 1;
                     if ((uint64_t)al < g.n && chk_lo(s, al) == glo && chk_hi(s, al) == ghi) {
-                        key = c * B + (uint32_t)b;
+                        key = c * B + (uint32_t)bb;
                         alpha_best = al;
                     }
                 }
+            };
+            for (; b >= (int)kQueryRows - 1; b -= kQueryRows) {
+                uint32_t xa[kQueryRows], xg[kQueryRows], xh[kQueryRows];
+#pragma unroll
+                for (uint32_t q = 0; q < kQueryRows; ++q) {
+                    xa[q] = in[(0 * B + b - q) * kC];
+                    xg[q] = in[(1 * B + b - q) * kC];
+                    xh[q] = in[(2 * B + b - q) * kC];
+                }
+#pragma unroll
+                for (uint32_t q = 0; q < kQueryRows; ++q) row(b - (int)q, xa[q], xg[q], xh[q]);
             }
+            for (; b >= 0; --b)
+                row(b, in[(0 * B + b) * kC], in[(1 * B + b) * kC], in[(2 * B + b) * kC]);
         } else {
             // 64-bit alpha; the checksum is of the pair the index encodes
             const WideSeeds s = load_wide_seeds(g.seeds, g.P, p);
             uint32_t al = 0, ah = 0, glo = 0, ghi = 0;
-            for (int b = (int)B - 1; b >= 0; --b) {
-                al ^= in[(0 * B + b) * kC];
-                ah ^= in[(1 * B + b) * kC];
-                glo ^= in[(2 * B + b) * kC];
-                ghi ^= in[(3 * B + b) * kC];
+            auto row = [&](int bb, uint32_t xa, uint32_t xah, uint32_t xg, uint32_t xh) {
+                al ^= xa;
+                ah ^= xah;
+                glo ^= xg;
+                ghi ^= xh;
                 if (al | ah | glo | ghi) {
                     nonempty = 1;
                     const uint64_t i = ((uint64_t)ah << 32) | al;
@@ -264,12 +361,28 @@ __device__ __forceinline__ void query_component(uint32_t r, uint32_t gtid, uint3
                         uint32_t u, v;
                         edge_pair64(i, &u, &v);
                         if (pair_hash(s.h[2], u, v) == glo && pair_hash(s.h[1], u, v) == ghi) {
-                            key = c * B + (uint32_t)b;
+                            key = c * B + (uint32_t)bb;
                             alpha_best = i;
                         }
                     }
                 }
+            };
+            for (; b >= (int)kQueryRows - 1; b -= kQueryRows) {
+                uint32_t xa[kQueryRows], xah[kQueryRows], xg[kQueryRows], xh[kQueryRows];
+#pragma unroll
+                for (uint32_t q = 0; q < kQueryRows; ++q) {
+                    xa[q] = in[(0 * B + b - q) * kC];
+                    xah[q] = in[(1 * B + b - q) * kC];
+                    xg[q] = in[(2 * B + b - q) * kC];
+                    xh[q] = in[(3 * B + b - q) * kC];
+                }
+#pragma unroll
+                for (uint32_t q = 0; q < kQueryRows; ++q)
+                    row(b - (int)q, xa[q], xah[q], xg[q], xh[q]);
             }
+            for (; b >= 0; --b)
+                row(b, in[(0 * B + b) * kC], in[(1 * B + b) * kC], in[(2 * B + b) * kC],
+                    in[(3 * B + b) * kC]);
         }
     }
     // reduce over the 8 lanes of this component: smallest key, any non-empty
@@ -374,27 +487,39 @@ __global__ __launch_bounds__(1024) void k_q_double_all(const uint32_t* __restric
     }
 }
 
+// newlab[R] = min(newlab[R], X).  A label only decreases, so a plain read that
+// is already at or below X (stale or not) makes the atomic a no-op; skipping it
+// spares the root of a large tree one serialised atomic per member.
+__device__ __forceinline__ void label_min(uint32_t* __restrict__ lab, uint32_t X) {
+    if (X < *lab) atomicMin(lab, X);
+}
+
 // after enough doubling steps s[X] lies on X's terminal cycle and m[s[X]] is
 // that cycle's smallest component: the root of X's tree once its edge is cut
-__global__ void k_q_root(const uint32_t* __restrict__ L, uint32_t* __restrict__ ctl,
-                         const uint32_t* __restrict__ s, const uint32_t* __restrict__ m,
-                         const uint32_t* __restrict__ hook, const uint64_t* __restrict__ hedge,
-                         const uint32_t* __restrict__ gof, uint32_t* __restrict__ rootOf,
-                         uint32_t* __restrict__ newlab, uint32_t* __restrict__ merged,
-                         uint64_t* __restrict__ forest, uint32_t lds_cap) {
+__global__ __launch_bounds__(kAppendThreads) void k_q_root(
+    const uint32_t* __restrict__ L, uint32_t* __restrict__ ctl, const uint32_t* __restrict__ s,
+    const uint32_t* __restrict__ m, const uint32_t* __restrict__ hook,
+    const uint64_t* __restrict__ hedge, const uint32_t* __restrict__ gof,
+    uint32_t* __restrict__ rootOf, uint32_t* __restrict__ newlab, uint32_t* __restrict__ merged,
+    uint64_t* __restrict__ forest, uint32_t lds_cap) {
+    __shared__ uint32_t sh[kMaxWaves + 1];
     if (ctl[Q_STOP]) return;
     const uint32_t nL = ctl[Q_NL];
     if (nL <= lds_cap) return;
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nL; i += gridDim.x * blockDim.x) {
-        const uint32_t X = L[i];
-        const uint32_t R = m[s[X]];
-        rootOf[X] = R;
-        atomicMin(&newlab[R], X);
-        if (hook[X] != kNone && X != R) {
-            merged[R] = 1;
-            const uint32_t f = atomicAdd(&ctl[Q_NF], 1u);
-            forest[f] = forest_key(ctl, gof[X], hedge[X]);
+    for (uint32_t i0 = blockIdx.x * blockDim.x; i0 < nL; i0 += gridDim.x * blockDim.x) {
+        const uint32_t i = i0 + threadIdx.x;
+        bool kept = false;
+        uint32_t X = 0;
+        if (i < nL) {
+            X = L[i];
+            const uint32_t R = m[s[X]];
+            rootOf[X] = R;
+            label_min(&newlab[R], X);
+            kept = hook[X] != kNone && X != R;
+            if (kept) merged[R] = 1;
         }
+        const uint32_t f = block_append(&ctl[Q_NF], kept, sh);
+        if (kept) forest[f] = forest_key(ctl, gof[X], hedge[X]);
     }
 }
 
@@ -406,6 +531,7 @@ __global__ void k_q_root(const uint32_t* __restrict__ L, uint32_t* __restrict__ 
 // [X, successor) and its minimum; in-place steps advance at least as far as
 // synchronous ones, so K steps still reach every terminal cycle.
 constexpr uint32_t kLdsResolve = 16384;
+constexpr uint32_t kResolveBatch = 8;
 
 __global__ __launch_bounds__(1024) void k_q_resolve_lds(
     const uint32_t* __restrict__ L, uint32_t* __restrict__ ctl, uint32_t K,
@@ -417,49 +543,124 @@ __global__ __launch_bounds__(1024) void k_q_resolve_lds(
     if (ctl[Q_STOP]) return;
     const uint32_t nL = ctl[Q_NL];
     if (nL > kLdsResolve) return;
-    for (uint32_t i = threadIdx.x; i < nL; i += blockDim.x) {
-        const uint32_t X = L[i];
-        const uint32_t h = hook[X];
-        const uint32_t sp = h == kNone ? i : pos[h];
-        st[i] = ((uint64_t)X << 32) | sp;
+    const uint32_t bd = blockDim.x;
+    // global loads in batches of kResolveBatch per lane, so that a lane waits
+    // once per dependent step of a batch rather than once per component
+    for (uint32_t i0 = threadIdx.x; i0 < nL; i0 += kResolveBatch * bd) {
+        uint32_t X[kResolveBatch], h[kResolveBatch], sp[kResolveBatch];
+#pragma unroll
+        for (uint32_t q = 0; q < kResolveBatch; ++q) {
+            const uint32_t i = i0 + q * bd;
+            X[q] = i < nL ? L[i] : 0u;
+        }
+#pragma unroll
+        for (uint32_t q = 0; q < kResolveBatch; ++q)
+            h[q] = i0 + q * bd < nL ? hook[X[q]] : kNone;
+#pragma unroll
+        for (uint32_t q = 0; q < kResolveBatch; ++q)
+            sp[q] = h[q] == kNone ? i0 + q * bd : pos[h[q]];
+#pragma unroll
+        for (uint32_t q = 0; q < kResolveBatch; ++q)
+            if (i0 + q * bd < nL) st[i0 + q * bd] = ((uint64_t)X[q] << 32) | sp[q];
     }
     __syncthreads();
     for (uint32_t k = 0; k < K; ++k) {
-        for (uint32_t i = threadIdx.x; i < nL; i += blockDim.x) {
-            const uint64_t v = st[i];
-            const uint64_t w = st[(uint32_t)v];
-            const uint64_t mn = min(v >> 32, w >> 32);
-            st[i] = (mn << 32) | (uint32_t)w;
+        for (uint32_t i0 = threadIdx.x; i0 < nL; i0 += 4 * bd) {
+            uint64_t v[4], w[4];
+#pragma unroll
+            for (uint32_t q = 0; q < 4; ++q) v[q] = i0 + q * bd < nL ? st[i0 + q * bd] : 0ull;
+#pragma unroll
+            for (uint32_t q = 0; q < 4; ++q) w[q] = st[(uint32_t)v[q]];
+#pragma unroll
+            for (uint32_t q = 0; q < 4; ++q)
+                if (i0 + q * bd < nL)
+                    st[i0 + q * bd] = (min(v[q] >> 32, w[q] >> 32) << 32) | (uint32_t)w[q];
         }
         __syncthreads();
     }
-    for (uint32_t i = threadIdx.x; i < nL; i += blockDim.x) {
-        const uint32_t X = L[i];
-        const uint32_t R = (uint32_t)(st[(uint32_t)st[i]] >> 32);
-        rootOf[X] = R;
-        atomicMin(&newlab[R], X);
-        if (hook[X] != kNone && X != R) {
-            merged[R] = 1;
-            const uint32_t f = atomicAdd(&ctl[Q_NF], 1u);
-            forest[f] = forest_key(ctl, gof[X], hedge[X]);
+    // roots and new labels; the kept hook edges are counted first so that one
+    // atomic and a workgroup scan place them (an atomic that returns a value
+    // costs a round trip, one per component was most of this kernel's time)
+    auto root_at = [&](uint32_t i) { return (uint32_t)(st[(uint32_t)st[i]] >> 32); };
+    uint32_t cnt = 0;
+    for (uint32_t i0 = threadIdx.x; i0 < nL; i0 += kResolveBatch * bd) {
+        uint32_t X[kResolveBatch], h[kResolveBatch];
+#pragma unroll
+        for (uint32_t q = 0; q < kResolveBatch; ++q) X[q] = i0 + q * bd < nL ? L[i0 + q * bd] : 0u;
+#pragma unroll
+        for (uint32_t q = 0; q < kResolveBatch; ++q)
+            h[q] = i0 + q * bd < nL ? hook[X[q]] : kNone;
+#pragma unroll
+        for (uint32_t q = 0; q < kResolveBatch; ++q)
+            cnt += (h[q] != kNone && X[q] != root_at(i0 + q * bd)) ? 1u : 0u;
+    }
+    __shared__ uint32_t s_scan[kMaxWaves + 1];
+    const uint32_t lane = __lane_id(), wave = threadIdx.x >> 6;
+    uint32_t incl = cnt;
+    for (uint32_t o = 1; o < 64; o <<= 1) {
+        const uint32_t t = __shfl_up(incl, o);
+        if (lane >= o) incl += t;
+    }
+    if (lane == 63) s_scan[wave] = incl;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t sum = 0;
+        for (uint32_t w = 0; w < (bd >> 6); ++w) {
+            const uint32_t c = s_scan[w];
+            s_scan[w] = sum;
+            sum += c;
+        }
+        s_scan[kMaxWaves] = sum ? atomicAdd(&ctl[Q_NF], sum) : 0u;
+    }
+    __syncthreads();
+    uint32_t f = s_scan[kMaxWaves] + s_scan[wave] + incl - cnt;
+    for (uint32_t i0 = threadIdx.x; i0 < nL; i0 += kResolveBatch * bd) {
+        uint32_t X[kResolveBatch], h[kResolveBatch], R[kResolveBatch], lab[kResolveBatch];
+#pragma unroll
+        for (uint32_t q = 0; q < kResolveBatch; ++q) X[q] = i0 + q * bd < nL ? L[i0 + q * bd] : 0u;
+#pragma unroll
+        for (uint32_t q = 0; q < kResolveBatch; ++q) {
+            const bool in = i0 + q * bd < nL;
+            h[q] = in ? hook[X[q]] : kNone;
+            R[q] = in ? root_at(i0 + q * bd) : 0u;
+        }
+#pragma unroll
+        for (uint32_t q = 0; q < kResolveBatch; ++q)
+            lab[q] = i0 + q * bd < nL ? newlab[R[q]] : 0u;
+#pragma unroll
+        for (uint32_t q = 0; q < kResolveBatch; ++q) {
+            if (i0 + q * bd >= nL) continue;
+            rootOf[X[q]] = R[q];
+            if (X[q] < lab[q]) atomicMin(&newlab[R[q]], X[q]);  // see label_min
+        }
+#pragma unroll
+        for (uint32_t q = 0; q < kResolveBatch; ++q) {
+            if (h[q] == kNone || X[q] == R[q]) continue;  // also every position >= nL
+            merged[R[q]] = 1;
+            forest[f++] = forest_key(ctl, gof[X[q]], hedge[X[q]]);
         }
     }
 }
 
-__global__ void k_q_newcomps(const uint32_t* __restrict__ L, uint32_t* __restrict__ ctl,
-                             const uint32_t* __restrict__ rootOf,
-                             const uint32_t* __restrict__ newlab,
-                             const uint32_t* __restrict__ merged, uint32_t* __restrict__ done,
-                             uint32_t* __restrict__ L2) {
+__global__ __launch_bounds__(kAppendThreads) void k_q_newcomps(
+    const uint32_t* __restrict__ L, uint32_t* __restrict__ ctl,
+    const uint32_t* __restrict__ rootOf, const uint32_t* __restrict__ newlab,
+    const uint32_t* __restrict__ merged, uint32_t* __restrict__ done, uint32_t* __restrict__ L2) {
+    __shared__ uint32_t sh[kMaxWaves + 1];
     if (ctl[Q_STOP]) return;
     const uint32_t nL = ctl[Q_NL];
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nL; i += gridDim.x * blockDim.x) {
-        const uint32_t X = L[i];
-        const uint32_t R = rootOf[X];
-        if (newlab[R] == X) {
-            if (merged[R]) done[X] = 0;
-            L2[atomicAdd(&ctl[Q_NL2], 1u)] = X;
+    for (uint32_t i0 = blockIdx.x * blockDim.x; i0 < nL; i0 += gridDim.x * blockDim.x) {
+        const uint32_t i = i0 + threadIdx.x;
+        bool root = false;
+        uint32_t X = 0;
+        if (i < nL) {
+            X = L[i];
+            const uint32_t R = rootOf[X];
+            root = newlab[R] == X;
+            if (root && merged[R]) done[X] = 0;
         }
+        const uint32_t at = block_append(&ctl[Q_NL2], root, sh);
+        if (root) L2[at] = X;
     }
 }
 
@@ -686,6 +887,7 @@ void free_query_scratch(QueryScratch* q) {
     hipFree(q->forest);
     hipFree(q->fsorted);
     hipFree(q->descs);
+    hipFree(q->spans);
     if (q->host_na) hipHostFree(q->host_na);
     for (hipEvent_t e : q->round_ev)
         if (e) hipEventDestroy(e);
@@ -767,6 +969,7 @@ gz_status boruvka(gz_graph* const* gs, uint32_t G, bool want_forest, QueryResult
     }
     GZ_HIP(hipMemcpyAsync(Q->descs, descs.data(), sizeof(GraphDesc) * G, hipMemcpyHostToDevice, qs));
     const uint32_t tb = blocks_for(T, 256);
+    const uint32_t ta = blocks_for(T, kAppendThreads);
     k_q_init<<<(T + 255) / 256, 256, 0, qs>>>(T, Q->descs, G, Q->comp, Q->L, Q->done, Q->gof,
                                                Q->ctl);
     const uint32_t K = std::max(1u, bitlen32(Vmax - 1));  // 2^K >= any tail + cycle length
@@ -777,8 +980,30 @@ gz_status boruvka(gz_graph* const* gs, uint32_t G, bool want_forest, QueryResult
     const uint32_t qgrid = blocks_for(8ull * T, 256);
     const uint32_t zgrid = 2048;
     const uint32_t ry = (wpr + 255) / 256;
-    const uint32_t rspan = reduce_span(T, ry);
-    const uint32_t rgrid = (T + rspan - 1) / rspan;
+    // reduce workgroups: spans of consecutive nodes of one graph; several
+    // graphs that each fit kReduceSpanMax nodes take one span per graph, so
+    // that no accumulator needs zeroing or atomics
+    uint32_t rspan = reduce_span(T, ry);
+    if (G > 1 && Vmax <= kReduceSpanMax) {
+        rspan = kReduceSpan;
+        while (rspan < Vmax) rspan <<= 1;
+    }
+    std::vector<ReduceSpan> spans;
+    bool all_whole = true;
+    for (uint32_t k = 0; k < G; ++k) {
+        const uint32_t V = descs[k].V;
+        for (uint32_t v = 0; v < V; v += rspan)
+            spans.push_back(ReduceSpan{descs[k].node_base + v, std::min(rspan, V - v), k,
+                                       V <= rspan ? 1u : 0u});
+        all_whole = all_whole && V <= rspan;
+    }
+    const uint32_t rgrid = (uint32_t)spans.size();
+    if (rgrid > Q->cap_spans || !Q->spans) {
+        if ((st = qalloc(&Q->spans, rgrid))) return st;
+        Q->cap_spans = rgrid;
+    }
+    GZ_HIP(hipMemcpyAsync(Q->spans, spans.data(), sizeof(ReduceSpan) * rgrid,
+                          hipMemcpyHostToDevice, qs));
     for (uint32_t r = 0; r < Rmax; ++r) Q->host_na[r] = kNone;
     // Rounds are enqueued ahead of the device; before round r the host waits
     // for the end of round r-2 and stops once a round had no active component
@@ -792,15 +1017,15 @@ gz_status boruvka(gz_graph* const* gs, uint32_t G, bool want_forest, QueryResult
             uint32_t* buf = nullptr;
             GZ_TRY(tier_round(tier_g, r, qs, &buf));  // after round r-1's kernels on qs
         }
-        k_q_select<<<tb, 256, 0, qs>>>(r, Q->L, Q->ctl, Q->done, Q->gof, Q->descs, Q->slot, Q->A,
+        k_q_select<<<ta, kAppendThreads, 0, qs>>>(r, Q->L, Q->ctl, Q->done, Q->gof, Q->descs, Q->slot, Q->A,
                                        Q->hook, Q->newlab, Q->merged, Q->pos);
         if (r == 0) {
             k_q_query<true><<<qgrid, 256, 0, qs>>>(r, Q->A, Q->ctl, Q->acc, wpr, Q->gof,
                                                    Q->descs, Q->comp, Q->hook, Q->hedge, Q->done);
         } else {
-            k_q_zero_acc<<<zgrid, 256, 0, qs>>>(Q->ctl, wpr, Q->acc);
-            k_q_reduce<<<dim3(rgrid, ry), 256, 0, qs>>>(r, T, rspan, Q->comp, Q->slot, Q->gof,
-                                                        Q->descs, wpr, Q->acc, Q->ctl);
+            if (!all_whole) k_q_zero_acc<<<zgrid, 256, 0, qs>>>(Q->ctl, wpr, Q->acc);
+            k_q_reduce<<<dim3(rgrid, ry), 256, 0, qs>>>(r, Q->spans, Q->comp, Q->slot, Q->descs,
+                                                        wpr, Q->acc, Q->ctl);
             k_q_query<false><<<qgrid, 256, 0, qs>>>(r, Q->A, Q->ctl, Q->acc, wpr, Q->gof,
                                                     Q->descs, Q->comp, Q->hook, Q->hedge,
                                                     Q->done);
@@ -825,10 +1050,10 @@ gz_status boruvka(gz_graph* const* gs, uint32_t G, bool want_forest, QueryResult
                     std::swap(m, m2);
                 }
             }
-            k_q_root<<<tb, 256, 0, qs>>>(Q->L, Q->ctl, s, m, Q->hook, Q->hedge, Q->gof, Q->rootOf,
+            k_q_root<<<ta, kAppendThreads, 0, qs>>>(Q->L, Q->ctl, s, m, Q->hook, Q->hedge, Q->gof, Q->rootOf,
                                          Q->newlab, Q->merged, Q->forest, cap);
         }
-        k_q_newcomps<<<tb, 256, 0, qs>>>(Q->L, Q->ctl, Q->rootOf, Q->newlab, Q->merged, Q->done,
+        k_q_newcomps<<<ta, kAppendThreads, 0, qs>>>(Q->L, Q->ctl, Q->rootOf, Q->newlab, Q->merged, Q->done,
                                          Q->L2);
         k_q_relabel<<<tb, 256, 0, qs>>>(T, Q->comp, Q->rootOf, Q->newlab, Q->ctl);
         k_q_copy_list<<<tb, 256, 0, qs>>>(Q->L, Q->L2, Q->ctl);

@@ -221,6 +221,27 @@ def test_many_graphs_fused_equals_separate(gz):
         assert_query_equal(g, O)
 
 
+def test_many_graphs_fused_mixed_spans(gz):
+    """A fused query over graphs of up to 2048 nodes, each reduced whole by one
+    workgroup, and larger graphs cut into spans whose partial sums meet in atomics."""
+    Vs = [2, 7, 300, 2048, 2049, 3000, 6000, 1000]
+    streams = [_stream(V, 6 * V, 40 + k) for k, V in enumerate(Vs)]
+    seeds = [workloads.many_graph_seed(7, k) for k in range(len(Vs))]
+    graphs = [gz.Graph(s.V, seed=sd) for s, sd in zip(streams, seeds)]
+    offs = np.zeros(len(streams) + 1, np.uint64)
+    offs[1:] = np.cumsum([s.N for s in streams])
+    src = np.concatenate([s.src for s in streams])
+    dst = np.concatenate([s.dst for s in streams])
+    gz.ingest_multi(graphs, offs, to_dev(src), to_dev(dst))
+    labels, ncc, stt = gz.connected_components_multi(graphs)
+    for k, (s, g) in enumerate(zip(streams, graphs)):
+        O = oracle_for(s, seeds[k])
+        ost, olabels, _, _ = O.connected_components()
+        assert stt[k] == gz_status_of(ost), f"graph {k} (V={s.V})"
+        assert (labels[k] == olabels).all(), f"graph {k} (V={s.V})"
+        assert ncc[k] == len(np.unique(olabels))
+
+
 def test_two_pass_grouping_full_parity(gz):
     """V > 4096 takes the two-pass placement: 150k updates over many grouping chunks."""
     s = _stream(5000, 150000, 21)

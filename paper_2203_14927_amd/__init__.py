@@ -336,11 +336,22 @@ def ingest_multi(graphs, offs, src, dst, flags: int = 0, stream=None):
                                        fs | flags, _stream_handle(stream)))
 
 
-def connected_components_multi(graphs):
-    """-> (labels per graph (list of uint32 arrays), num_cc uint32[G], status int32[G])."""
+def connected_components_multi(graphs, out=None):
+    """-> (labels per graph (list of uint32 arrays), num_cc uint32[G], status int32[G]).
+
+    out: optional caller-owned uint32 array of at least sum(V) labels (for example
+    a view of pinned host memory, reused across calls); the per-graph label
+    arrays are views of it.
+    """
     G = len(graphs)
     total = sum(g.V for g in graphs)
-    labels = np.zeros(total, np.uint32)
+    if out is None:
+        labels = np.zeros(total, np.uint32)
+    else:
+        labels = out
+        if labels.dtype != np.uint32 or labels.ndim != 1 or labels.size < total \
+                or not labels.flags["C_CONTIGUOUS"]:
+            raise ValueError(f"out must be a contiguous uint32 array of at least {total} labels")
     ncc = np.zeros(G, np.uint32)
     stt = np.zeros(G, np.int32)
     st = lib().gz_connected_components_multi(

@@ -44,9 +44,12 @@ struct QueryScratch {
     ReduceSpan* spans = nullptr;  // the reduce's workgroup table
     uint32_t cap_spans = 0;
     uint32_t* pos = nullptr;      // list position of every current component
-    uint32_t* host_na = nullptr;  // pinned: active components of each round
+    uint32_t* host_na = nullptr;  // pinned: active components of each round, then the list
+                                  // length each round leaves for the next
     hipEvent_t round_ev[2] = {nullptr, nullptr};
 };
+
+constexpr uint32_t kMaxRounds = 64;  // R <= 25 for V <= 2^24
 
 // ctl words
 // Q_STOP is set at the end of the first round with no active component; every
@@ -489,7 +492,8 @@ __global__ __launch_bounds__(1024) void k_q_double_all(const uint32_t* __restric
 
 // newlab[R] = min(newlab[R], X).  A label only decreases, so a plain read that
 // is already at or below X (stale or not) makes the atomic a no-op; skipping it
-// spares the root of a large tree one serialised atomic per member.
+// spares the root of a large tree one serialised atomic per member.  Callers
+// also skip members above R: R itself takes part, so the label ends at most R.
 __device__ __forceinline__ void label_min(uint32_t* __restrict__ lab, uint32_t X) {
     if (X < *lab) atomicMin(lab, X);
 }
@@ -514,7 +518,7 @@ __global__ __launch_bounds__(kAppendThreads) void k_q_root(
             X = L[i];
             const uint32_t R = m[s[X]];
             rootOf[X] = R;
-            label_min(&newlab[R], X);
+            if (X <= R) label_min(&newlab[R], X);
             kept = hook[X] != kNone && X != R;
             if (kept) merged[R] = 1;
         }
@@ -564,7 +568,9 @@ __global__ __launch_bounds__(1024) void k_q_resolve_lds(
             if (i0 + q * bd < nL) st[i0 + q * bd] = ((uint64_t)X[q] << 32) | sp[q];
     }
     __syncthreads();
-    for (uint32_t k = 0; k < K; ++k) {
+    // a path to a cycle and the cycle hold at most nL components
+    const uint32_t steps = min(K, nL > 1 ? 32u - (uint32_t)__clz(nL - 1) : 0u);
+    for (uint32_t k = 0; k < steps; ++k) {
         for (uint32_t i0 = threadIdx.x; i0 < nL; i0 += 4 * bd) {
             uint64_t v[4], w[4];
 #pragma unroll
@@ -631,7 +637,7 @@ __global__ __launch_bounds__(1024) void k_q_resolve_lds(
         for (uint32_t q = 0; q < kResolveBatch; ++q) {
             if (i0 + q * bd >= nL) continue;
             rootOf[X[q]] = R[q];
-            if (X[q] < lab[q]) atomicMin(&newlab[R[q]], X[q]);  // see label_min
+            if (X[q] <= R[q] && X[q] < lab[q]) atomicMin(&newlab[R[q]], X[q]);  // label_min
         }
 #pragma unroll
         for (uint32_t q = 0; q < kResolveBatch; ++q) {
@@ -682,18 +688,20 @@ __global__ void k_q_copy_list(uint32_t* __restrict__ L, const uint32_t* __restri
         L[i] = L2[i];
 }
 
-// End of round r: publish its active count to the host (pinned memory) and
-// stop once a round had none.
+// End of round r: publish its active count and the next round's list length
+// to the host (pinned memory) and stop once a round had no active component.
 __global__ void k_q_next_round(uint32_t r, uint32_t* __restrict__ ctl,
                                uint32_t* __restrict__ host_na) {
     if (ctl[Q_STOP]) return;
     const uint32_t na = ctl[Q_NA];
     if (na == 0) ctl[Q_STOP] = 1;
     else ctl[Q_ROUNDS] = r + 1;
-    ctl[Q_NL] = ctl[Q_NL2];
+    const uint32_t nl = ctl[Q_NL2];
+    ctl[Q_NL] = nl;
     ctl[Q_NL2] = 0;
     ctl[Q_NA] = 0;
     host_na[r] = na;
+    host_na[kMaxRounds + r] = nl;
 }
 
 __global__ void k_q_finish(const uint32_t* __restrict__ L, const uint32_t* __restrict__ ctl,
@@ -702,8 +710,22 @@ __global__ void k_q_finish(const uint32_t* __restrict__ L, const uint32_t* __res
     const uint32_t nL = ctl[Q_NL];
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nL; i += gridDim.x * blockDim.x) {
         const uint32_t X = L[i];
-        atomicAdd(&gcount[gof[X]], 1u);
-        if (!done[X]) atomicOr(&gfail[gof[X]], 1u);
+        const uint32_t g = gof[X];
+        const bool open = !done[X];
+        // lanes of one graph (neighbours in the list, mostly) add with one
+        // atomic: same-address atomics from every lane serialise
+        uint64_t pending = __ballot(true);
+        while (pending) {
+            const uint32_t leader = (uint32_t)__ffsll((unsigned long long)pending) - 1u;
+            const uint32_t gl = __shfl(g, (int)leader);
+            const uint64_t same = __ballot(g == gl);
+            const uint64_t fail = __ballot(open && g == gl);
+            if (__lane_id() == leader) {
+                atomicAdd(&gcount[gl], (uint32_t)__popcll(same));
+                if (fail) atomicOr(&gfail[gl], 1u);
+            }
+            pending &= ~same;
+        }
     }
 }
 
@@ -736,7 +758,6 @@ __global__ void k_q_fscan(const uint32_t* __restrict__ fcnt, uint32_t G, uint32_
     }
 }
 
-constexpr uint32_t kMaxRounds = 64;  // R <= 25 for V <= 2^24
 constexpr uint32_t kSingleBlockDoubling = 65536;  // component lists up to this length
 
 // The forest keys (distinct: the graph above the edge index when several graphs
@@ -839,7 +860,7 @@ gz_status ensure_query(QueryScratch& Q, uint32_t T, uint32_t G, uint32_t wpr) {
         if ((st = qalloc(&Q.forest, T))) return st;
         if ((st = qalloc(&Q.fsorted, T))) return st;
         if (!Q.ctl && (st = qalloc(&Q.ctl, 8))) return st;
-        if (!Q.host_na) GZ_HIP(hipHostMalloc((void**)&Q.host_na, 4 * kMaxRounds, hipHostMallocDefault));
+        if (!Q.host_na) GZ_HIP(hipHostMalloc((void**)&Q.host_na, 8 * kMaxRounds, hipHostMallocDefault));
         for (hipEvent_t& e : Q.round_ev)
             if (!e) GZ_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
         Q.cap_nodes = T;
@@ -1004,21 +1025,26 @@ gz_status boruvka(gz_graph* const* gs, uint32_t G, bool want_forest, QueryResult
     }
     GZ_HIP(hipMemcpyAsync(Q->spans, spans.data(), sizeof(ReduceSpan) * rgrid,
                           hipMemcpyHostToDevice, qs));
-    for (uint32_t r = 0; r < Rmax; ++r) Q->host_na[r] = kNone;
+    for (uint32_t r = 0; r < 2 * kMaxRounds; ++r) Q->host_na[r] = kNone;
     // Rounds are enqueued ahead of the device; before round r the host waits
     // for the end of round r-2 and stops once a round had no active component
-    // (kernels of rounds after that one return at once).
+    // (kernels of rounds after that one return at once).  Lists only shrink,
+    // so once round r-2 left a list that fits one workgroup's LDS, the
+    // grid-wide doubling is not launched again.
+    uint32_t nl_bound = T;
     for (uint32_t r = 0; r < Rmax; ++r) {
         if (r >= 2) {
             GZ_HIP(hipEventSynchronize(Q->round_ev[r & 1]));
             if (Q->host_na[r - 2] == 0) break;
+            nl_bound = std::min(nl_bound, Q->host_na[kMaxRounds + r - 2]);
         }
         if (tier_g && r > 0) {
             uint32_t* buf = nullptr;
             GZ_TRY(tier_round(tier_g, r, qs, &buf));  // after round r-1's kernels on qs
         }
-        k_q_select<<<ta, kAppendThreads, 0, qs>>>(r, Q->L, Q->ctl, Q->done, Q->gof, Q->descs, Q->slot, Q->A,
-                                       Q->hook, Q->newlab, Q->merged, Q->pos);
+        k_q_select<<<ta, kAppendThreads, 0, qs>>>(r, Q->L, Q->ctl, Q->done, Q->gof, Q->descs,
+                                                  Q->slot, Q->A, Q->hook, Q->newlab, Q->merged,
+                                                  Q->pos);
         if (r == 0) {
             k_q_query<true><<<qgrid, 256, 0, qs>>>(r, Q->A, Q->ctl, Q->acc, wpr, Q->gof,
                                                    Q->descs, Q->comp, Q->hook, Q->hedge, Q->done);
@@ -1034,7 +1060,7 @@ gz_status boruvka(gz_graph* const* gs, uint32_t G, bool want_forest, QueryResult
         // else by grid-wide pointer doubling
         k_q_resolve_lds<<<1, 1024, 0, qs>>>(Q->L, Q->ctl, K, Q->hook, Q->hedge, Q->pos, Q->gof,
                                             Q->rootOf, Q->newlab, Q->merged, Q->forest);
-        if (T > kLdsResolve) {
+        if (nl_bound > kLdsResolve) {
             const uint32_t cap = kLdsResolve;
             k_q_double_init<<<tb, 256, 0, qs>>>(Q->L, Q->ctl, Q->hook, s, m, cap);
             if (T <= kSingleBlockDoubling) {
@@ -1050,11 +1076,12 @@ gz_status boruvka(gz_graph* const* gs, uint32_t G, bool want_forest, QueryResult
                     std::swap(m, m2);
                 }
             }
-            k_q_root<<<ta, kAppendThreads, 0, qs>>>(Q->L, Q->ctl, s, m, Q->hook, Q->hedge, Q->gof, Q->rootOf,
-                                         Q->newlab, Q->merged, Q->forest, cap);
+            k_q_root<<<ta, kAppendThreads, 0, qs>>>(Q->L, Q->ctl, s, m, Q->hook, Q->hedge, Q->gof,
+                                                    Q->rootOf, Q->newlab, Q->merged, Q->forest,
+                                                    cap);
         }
-        k_q_newcomps<<<ta, kAppendThreads, 0, qs>>>(Q->L, Q->ctl, Q->rootOf, Q->newlab, Q->merged, Q->done,
-                                         Q->L2);
+        k_q_newcomps<<<ta, kAppendThreads, 0, qs>>>(Q->L, Q->ctl, Q->rootOf, Q->newlab,
+                                                    Q->merged, Q->done, Q->L2);
         k_q_relabel<<<tb, 256, 0, qs>>>(T, Q->comp, Q->rootOf, Q->newlab, Q->ctl);
         k_q_copy_list<<<tb, 256, 0, qs>>>(Q->L, Q->L2, Q->ctl);
         k_q_next_round<<<1, 1, 0, qs>>>(r, Q->ctl, Q->host_na);

@@ -233,7 +233,10 @@ def test_many_graphs_fused_mixed_spans(gz):
     src = np.concatenate([s.src for s in streams])
     dst = np.concatenate([s.dst for s in streams])
     gz.ingest_multi(graphs, offs, to_dev(src), to_dev(dst))
-    labels, ncc, stt = gz.connected_components_multi(graphs)
+    total = sum(Vs)
+    out = np.full(total + 5, 0xFFFFFFFF, np.uint32)  # a caller-owned label buffer
+    labels, ncc, stt = gz.connected_components_multi(graphs, out=out)
+    assert (out[total:] == 0xFFFFFFFF).all()
     for k, (s, g) in enumerate(zip(streams, graphs)):
         O = oracle_for(s, seeds[k])
         ost, olabels, _, _ = O.connected_components()

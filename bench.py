@@ -106,6 +106,18 @@ def kernel_source_hash() -> str:
     return hashlib.sha256(open(p, "rb").read()).hexdigest()
 
 
+def copy_calibration():
+    """One plain 1 GiB device copy, the reference for scaling HBM traffic counters."""
+    import torch
+
+    a = torch.empty(1 << 28, dtype=torch.int32, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)  # reads 1 GiB, writes 1 GiB
+    torch.cuda.synchronize()
+    del a, b
+
+
 def cpu_baseline(stream, seed, seconds: float):
     """The oracle, untuned, single-threaded, on the first M updates of the same stream."""
     import oracle
@@ -291,6 +303,8 @@ def run_many(args) -> dict:
     dst_d = torch.from_numpy(np.concatenate([s.dst for s in streams]).view(np.int32)).cuda()
     log(f"[bench] many G(n,p): {len(streams)} graphs, {N} updates, "
         f"{sum(s.V for s in streams)} nodes (generated in {time.perf_counter() - t0:.1f} s)")
+    if args.copy_calibration:
+        copy_calibration()
     graphs = [gz.Graph(s.V, seed=sd) for s, sd in zip(streams, seeds)]
     if not args.tuning and not args.no_autotune:
         args.tuning = TUNED["many_gnp"]
@@ -456,12 +470,7 @@ def run_single(args) -> dict:
     src_d = torch.from_numpy(stream.src.view(np.int32)).cuda()
     dst_d = torch.from_numpy(stream.dst.view(np.int32)).cuda()
     if args.copy_calibration:
-        a = torch.empty(1 << 28, dtype=torch.int32, device="cuda")
-        b = torch.empty_like(a)
-        torch.cuda.synchronize()
-        b.copy_(a)  # reads 1 GiB, writes 1 GiB
-        torch.cuda.synchronize()
-        del a, b
+        copy_calibration()
     g = gz.Graph(stream.V, seed=seed)
     tune_ms = None
     if not args.tuning and not args.autotune and not args.no_autotune:

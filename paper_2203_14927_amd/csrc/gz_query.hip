@@ -57,7 +57,10 @@ constexpr uint32_t kMaxRounds = 64;  // R <= 25 for V <= 2^24
 // the device without waiting for each round's outcome.
 // Q_MULTI: the query spans several graphs; a forest key is then (graph << 32 |
 // index), else the 64-bit index alone (wide graphs are queried one at a time).
-enum : uint32_t { Q_NL = 0, Q_NA = 1, Q_NL2 = 2, Q_NF = 3, Q_STOP = 4, Q_ROUNDS = 5, Q_MULTI = 6 };
+// Q_DONE counts the workgroups of a round's last kernel that have finished.
+enum : uint32_t {
+    Q_NL = 0, Q_NA = 1, Q_NL2 = 2, Q_NF = 3, Q_STOP = 4, Q_ROUNDS = 5, Q_MULTI = 6, Q_DONE = 7
+};
 
 __device__ __forceinline__ uint64_t forest_key(const uint32_t* __restrict__ ctl, uint32_t graph,
                                                uint64_t idx) {
@@ -126,6 +129,7 @@ __global__ void k_q_init(uint32_t T, const GraphDesc* __restrict__ gd, uint32_t 
         ctl[Q_STOP] = 0;
         ctl[Q_ROUNDS] = 0;
         ctl[Q_MULTI] = G > 1 ? 1u : 0u;
+        ctl[Q_DONE] = 0;
     }
     if (v < T) {
         comp[v] = v;
@@ -171,13 +175,14 @@ __global__ __launch_bounds__(kAppendThreads) void k_q_select(
 // the component changes, so a span costs one flush per word for each component
 // it meets however the components interleave in node order (in node order, a
 // few large interleaved components took one atomic per member).  A span that
-// holds its whole graph holds every member of its components: it stores the
-// sums, and the accumulators need no zeroing; other spans XOR them in with
-// atomics.  Loads are issued kReduceRun members at a time so that they are in
-// flight together; blockIdx.y picks the block of accumulator words.  Spans of
-// one large graph grow with its size (up to kReduceSpanCap) so that its giant
-// component does not take one device-scope atomic per word from tens of
-// thousands of workgroups.
+// holds its whole graph holds every member of its components: it stores their
+// sums, which needs no zeroed accumulator; other spans XOR theirs in with
+// atomics into accumulators zeroed before the first reduce and by each query
+// after reading them.  Loads are issued kReduceRun members at a time so that
+// they are in flight together; blockIdx.y picks the block of accumulator
+// words.  Spans of one large graph grow with its size (up to kReduceSpanCap)
+// so that its giant component does not take one device-scope atomic per word
+// from tens of thousands of workgroups.
 constexpr uint32_t kReduceRun = 16;
 constexpr uint32_t kReduceSpan = 64;
 constexpr uint32_t kReduceSpanCap = 1024;  // spans that cut a graph
@@ -292,7 +297,8 @@ constexpr uint32_t kQueryRows = 4;
 template <bool kDirect>
 __device__ __forceinline__ void query_component(uint32_t r, uint32_t gtid, uint32_t nA,
                                                 const uint32_t* __restrict__ A,
-                                                const uint32_t* __restrict__ acc, uint32_t wpr,
+                                                uint32_t* __restrict__ acc, uint32_t wpr,
+                                                uint32_t zero_after,
                                                 const uint32_t* __restrict__ gof,
                                                 const GraphDesc* __restrict__ gd,
                                                 const uint32_t* __restrict__ comp,
@@ -387,6 +393,12 @@ __device__ __forceinline__ void query_component(uint32_t r, uint32_t gtid, uint3
                 row(b, in[(0 * B + b) * kC], in[(1 * B + b) * kC], in[(2 * B + b) * kC],
                     in[(3 * B + b) * kC]);
         }
+        // the next round's atomics find this accumulator zeroed (its slots
+        // are a subset of this round's)
+        if (!kDirect && zero_after) {
+            uint32_t* w = acc + (uint64_t)a * wpr + c;
+            for (uint32_t k = 0; k < g.planes * B; ++k) w[k * kC] = 0;
+        }
     }
     // reduce over the 8 lanes of this component: smallest key, any non-empty
     for (uint32_t off = 1; off < 8; off <<= 1) {
@@ -421,7 +433,7 @@ __device__ __forceinline__ void query_component(uint32_t r, uint32_t gtid, uint3
 // components (their count is known only on the device).
 template <bool kDirect>
 __global__ void k_q_query(uint32_t r, const uint32_t* __restrict__ A, const uint32_t* __restrict__ ctl,
-                          const uint32_t* __restrict__ acc, uint32_t wpr,
+                          uint32_t* __restrict__ acc, uint32_t wpr, uint32_t zero_after,
                           const uint32_t* __restrict__ gof, const GraphDesc* __restrict__ gd,
                           const uint32_t* __restrict__ comp, uint32_t* __restrict__ hook,
                           uint64_t* __restrict__ hedge, uint32_t* __restrict__ done) {
@@ -430,8 +442,8 @@ __global__ void k_q_query(uint32_t r, const uint32_t* __restrict__ A, const uint
     const uint64_t lanes = (uint64_t)nA * 8;
     for (uint64_t base = (uint64_t)blockIdx.x * blockDim.x; base < lanes;
          base += (uint64_t)gridDim.x * blockDim.x)
-        query_component<kDirect>(r, (uint32_t)(base + threadIdx.x), nA, A, acc, wpr, gof, gd, comp,
-                                 hook, hedge, done);
+        query_component<kDirect>(r, (uint32_t)(base + threadIdx.x), nA, A, acc, wpr, zero_after,
+                                 gof, gd, comp, hook, hedge, done);
 }
 
 __global__ void k_q_double_init(const uint32_t* __restrict__ L, const uint32_t* __restrict__ ctl,
@@ -568,9 +580,14 @@ __global__ __launch_bounds__(1024) void k_q_resolve_lds(
             if (i0 + q * bd < nL) st[i0 + q * bd] = ((uint64_t)X[q] << 32) | sp[q];
     }
     __syncthreads();
-    // a path to a cycle and the cycle hold at most nL components
+    // A path to a cycle and the cycle hold at most nL components.  A step that
+    // changes no word has reached a fixed point: every successor is then a word
+    // whose segment starts and ends at itself, a root (empty segment) or a whole
+    // number of turns of its cycle (minimum = the cycle's), so the roots below
+    // are those the remaining steps would give.
     const uint32_t steps = min(K, nL > 1 ? 32u - (uint32_t)__clz(nL - 1) : 0u);
     for (uint32_t k = 0; k < steps; ++k) {
+        int changed = 0;
         for (uint32_t i0 = threadIdx.x; i0 < nL; i0 += 4 * bd) {
             uint64_t v[4], w[4];
 #pragma unroll
@@ -579,10 +596,13 @@ __global__ __launch_bounds__(1024) void k_q_resolve_lds(
             for (uint32_t q = 0; q < 4; ++q) w[q] = st[(uint32_t)v[q]];
 #pragma unroll
             for (uint32_t q = 0; q < 4; ++q)
-                if (i0 + q * bd < nL)
-                    st[i0 + q * bd] = (min(v[q] >> 32, w[q] >> 32) << 32) | (uint32_t)w[q];
+                if (i0 + q * bd < nL) {
+                    const uint64_t nv = (min(v[q] >> 32, w[q] >> 32) << 32) | (uint32_t)w[q];
+                    changed |= nv != v[q];
+                    st[i0 + q * bd] = nv;
+                }
         }
-        __syncthreads();
+        if (!__syncthreads_or(changed)) break;
     }
     // roots and new labels; the kept hook edges are counted first so that one
     // atomic and a workgroup scan place them (an atomic that returns a value
@@ -648,11 +668,17 @@ __global__ __launch_bounds__(1024) void k_q_resolve_lds(
     }
 }
 
+// The next round's component list: the roots of this round's trees.  The last
+// workgroup to finish also ends the round: it publishes the round's active
+// count and the new list length to the host (pinned memory), makes the new
+// list current, and stops the query once a round had no active component.
 __global__ __launch_bounds__(kAppendThreads) void k_q_newcomps(
-    const uint32_t* __restrict__ L, uint32_t* __restrict__ ctl,
+    uint32_t r, const uint32_t* __restrict__ L, uint32_t* __restrict__ ctl,
     const uint32_t* __restrict__ rootOf, const uint32_t* __restrict__ newlab,
-    const uint32_t* __restrict__ merged, uint32_t* __restrict__ done, uint32_t* __restrict__ L2) {
+    const uint32_t* __restrict__ merged, uint32_t* __restrict__ done, uint32_t* __restrict__ L2,
+    uint32_t* __restrict__ host_na) {
     __shared__ uint32_t sh[kMaxWaves + 1];
+    __shared__ uint32_t s_last;
     if (ctl[Q_STOP]) return;
     const uint32_t nL = ctl[Q_NL];
     for (uint32_t i0 = blockIdx.x * blockDim.x; i0 < nL; i0 += gridDim.x * blockDim.x) {
@@ -668,6 +694,25 @@ __global__ __launch_bounds__(kAppendThreads) void k_q_newcomps(
         const uint32_t at = block_append(&ctl[Q_NL2], root, sh);
         if (root) L2[at] = X;
     }
+    // No fence: the last workgroup reads only counters that every workgroup
+    // updated with atomics it waited for (block_append uses the result)
+    // before counting itself done; the list and the counters it writes reach
+    // the next kernel at the kernel boundary.  (A device-scope fence in every
+    // workgroup cost tens of microseconds per launch.)
+    __syncthreads();
+    if (threadIdx.x == 0) s_last = atomicAdd(&ctl[Q_DONE], 1u) == gridDim.x - 1;
+    __syncthreads();
+    if (!s_last || threadIdx.x != 0) return;
+    const uint32_t na = atomicAdd(&ctl[Q_NA], 0u);
+    const uint32_t nl = atomicAdd(&ctl[Q_NL2], 0u);
+    if (na == 0) ctl[Q_STOP] = 1;
+    else ctl[Q_ROUNDS] = r + 1;
+    ctl[Q_NL] = nl;
+    ctl[Q_NL2] = 0;
+    ctl[Q_NA] = 0;
+    ctl[Q_DONE] = 0;
+    host_na[r] = na;
+    host_na[kMaxRounds + r] = nl;
 }
 
 __global__ void k_q_relabel(uint32_t T, uint32_t* __restrict__ comp,
@@ -677,31 +722,6 @@ __global__ void k_q_relabel(uint32_t T, uint32_t* __restrict__ comp,
     if (ctl[Q_STOP]) return;
     for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < T; v += gridDim.x * blockDim.x)
         comp[v] = newlab[rootOf[comp[v]]];
-}
-
-// the next round's component list is this round's new list
-__global__ void k_q_copy_list(uint32_t* __restrict__ L, const uint32_t* __restrict__ L2,
-                              const uint32_t* __restrict__ ctl) {
-    if (ctl[Q_STOP]) return;
-    const uint32_t n = ctl[Q_NL2];
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
-        L[i] = L2[i];
-}
-
-// End of round r: publish its active count and the next round's list length
-// to the host (pinned memory) and stop once a round had no active component.
-__global__ void k_q_next_round(uint32_t r, uint32_t* __restrict__ ctl,
-                               uint32_t* __restrict__ host_na) {
-    if (ctl[Q_STOP]) return;
-    const uint32_t na = ctl[Q_NA];
-    if (na == 0) ctl[Q_STOP] = 1;
-    else ctl[Q_ROUNDS] = r + 1;
-    const uint32_t nl = ctl[Q_NL2];
-    ctl[Q_NL] = nl;
-    ctl[Q_NL2] = 0;
-    ctl[Q_NA] = 0;
-    host_na[r] = na;
-    host_na[kMaxRounds + r] = nl;
 }
 
 __global__ void k_q_finish(const uint32_t* __restrict__ L, const uint32_t* __restrict__ ctl,
@@ -1031,7 +1051,13 @@ gz_status boruvka(gz_graph* const* gs, uint32_t G, bool want_forest, QueryResult
     // (kernels of rounds after that one return at once).  Lists only shrink,
     // so once round r-2 left a list that fits one workgroup's LDS, the
     // grid-wide doubling is not launched again.
+    // The component list alternates between two buffers: round r reads Lc and
+    // writes the next round's list to Ln.  After the round that stops the query
+    // (no active component, so every component is its own root) both hold the
+    // same components, so rounds enqueued past it may swap them freely.
     uint32_t nl_bound = T;
+    uint32_t* Lc = Q->L;
+    uint32_t* Ln = Q->L2;
     for (uint32_t r = 0; r < Rmax; ++r) {
         if (r >= 2) {
             GZ_HIP(hipEventSynchronize(Q->round_ev[r & 1]));
@@ -1042,54 +1068,57 @@ gz_status boruvka(gz_graph* const* gs, uint32_t G, bool want_forest, QueryResult
             uint32_t* buf = nullptr;
             GZ_TRY(tier_round(tier_g, r, qs, &buf));  // after round r-1's kernels on qs
         }
-        k_q_select<<<ta, kAppendThreads, 0, qs>>>(r, Q->L, Q->ctl, Q->done, Q->gof, Q->descs,
+        k_q_select<<<ta, kAppendThreads, 0, qs>>>(r, Lc, Q->ctl, Q->done, Q->gof, Q->descs,
                                                   Q->slot, Q->A, Q->hook, Q->newlab, Q->merged,
                                                   Q->pos);
         if (r == 0) {
-            k_q_query<true><<<qgrid, 256, 0, qs>>>(r, Q->A, Q->ctl, Q->acc, wpr, Q->gof,
+            k_q_query<true><<<qgrid, 256, 0, qs>>>(r, Q->A, Q->ctl, Q->acc, wpr, 0u, Q->gof,
                                                    Q->descs, Q->comp, Q->hook, Q->hedge, Q->done);
         } else {
-            if (!all_whole) k_q_zero_acc<<<zgrid, 256, 0, qs>>>(Q->ctl, wpr, Q->acc);
+            // spans that cut a graph XOR into zeroed accumulators: zeroed here for
+            // the first reduce, then by each round's query after reading them
+            if (!all_whole && r == 1) k_q_zero_acc<<<zgrid, 256, 0, qs>>>(Q->ctl, wpr, Q->acc);
             k_q_reduce<<<dim3(rgrid, ry), 256, 0, qs>>>(r, Q->spans, Q->comp, Q->slot, Q->descs,
                                                         wpr, Q->acc, Q->ctl);
-            k_q_query<false><<<qgrid, 256, 0, qs>>>(r, Q->A, Q->ctl, Q->acc, wpr, Q->gof,
+            k_q_query<false><<<qgrid, 256, 0, qs>>>(r, Q->A, Q->ctl, Q->acc, wpr,
+                                                    all_whole ? 0u : 1u, Q->gof,
                                                     Q->descs, Q->comp, Q->hook, Q->hedge,
                                                     Q->done);
         }
         // hooks -> roots: in LDS when the list is short (on the device's count),
         // else by grid-wide pointer doubling
-        k_q_resolve_lds<<<1, 1024, 0, qs>>>(Q->L, Q->ctl, K, Q->hook, Q->hedge, Q->pos, Q->gof,
+        k_q_resolve_lds<<<1, 1024, 0, qs>>>(Lc, Q->ctl, K, Q->hook, Q->hedge, Q->pos, Q->gof,
                                             Q->rootOf, Q->newlab, Q->merged, Q->forest);
         if (nl_bound > kLdsResolve) {
             const uint32_t cap = kLdsResolve;
-            k_q_double_init<<<tb, 256, 0, qs>>>(Q->L, Q->ctl, Q->hook, s, m, cap);
+            k_q_double_init<<<tb, 256, 0, qs>>>(Lc, Q->ctl, Q->hook, s, m, cap);
             if (T <= kSingleBlockDoubling) {
-                k_q_double_all<<<1, 1024, 0, qs>>>(Q->L, Q->ctl, K, s, m, s2, m2, cap);
+                k_q_double_all<<<1, 1024, 0, qs>>>(Lc, Q->ctl, K, s, m, s2, m2, cap);
                 if (K & 1) {
                     std::swap(s, s2);
                     std::swap(m, m2);
                 }
             } else {
                 for (uint32_t k = 0; k < K; ++k) {
-                    k_q_double<<<tb, 256, 0, qs>>>(Q->L, Q->ctl, s, m, s2, m2, cap);
+                    k_q_double<<<tb, 256, 0, qs>>>(Lc, Q->ctl, s, m, s2, m2, cap);
                     std::swap(s, s2);
                     std::swap(m, m2);
                 }
             }
-            k_q_root<<<ta, kAppendThreads, 0, qs>>>(Q->L, Q->ctl, s, m, Q->hook, Q->hedge, Q->gof,
+            k_q_root<<<ta, kAppendThreads, 0, qs>>>(Lc, Q->ctl, s, m, Q->hook, Q->hedge, Q->gof,
                                                     Q->rootOf, Q->newlab, Q->merged, Q->forest,
                                                     cap);
         }
-        k_q_newcomps<<<ta, kAppendThreads, 0, qs>>>(Q->L, Q->ctl, Q->rootOf, Q->newlab,
-                                                    Q->merged, Q->done, Q->L2);
+        // relabel first: the round's last workgroup of newcomps may stop the query
         k_q_relabel<<<tb, 256, 0, qs>>>(T, Q->comp, Q->rootOf, Q->newlab, Q->ctl);
-        k_q_copy_list<<<tb, 256, 0, qs>>>(Q->L, Q->L2, Q->ctl);
-        k_q_next_round<<<1, 1, 0, qs>>>(r, Q->ctl, Q->host_na);
+        k_q_newcomps<<<ta, kAppendThreads, 0, qs>>>(r, Lc, Q->ctl, Q->rootOf, Q->newlab,
+                                                    Q->merged, Q->done, Ln, Q->host_na);
+        std::swap(Lc, Ln);
         GZ_HIP(hipEventRecord(Q->round_ev[r & 1], qs));
     }
     GZ_HIP(hipMemsetAsync(Q->gcount, 0, 4ull * G, qs));
     GZ_HIP(hipMemsetAsync(Q->gfail, 0, 4ull * G, qs));
-    k_q_finish<<<tb, 256, 0, qs>>>(Q->L, Q->ctl, Q->done, Q->gof, Q->gcount, Q->gfail);
+    k_q_finish<<<tb, 256, 0, qs>>>(Lc, Q->ctl, Q->done, Q->gof, Q->gcount, Q->gfail);
     if (labels_out) {
         k_q_labels<<<tb, 256, 0, qs>>>(T, Q->comp, Q->gof, Q->descs, Q->labels);
         GZ_HIP(hipMemcpyAsync(labels_out, Q->labels, 4ull * T, hipMemcpyDeviceToHost, qs));

@@ -252,7 +252,8 @@ gz_status gz_query(gz_graph* g, uint32_t* labels, uint32_t* num_cc, uint32_t* ed
 /* ------------------------------------------------------------------------
  * gz_connected_components_multi -- Boruvka over G graphs at once (the
  *   many-graph form of gz_connected_components).  labels: host array of
- *   sum(V_k) entries, graph k's labels at offset sum_{j<k} V_j, local ids;
+ *   sum(V_k) entries, graph k's labels at offset sum_{j<k} V_j, local ids
+ *   (caller-owned; pinned memory reused across calls takes the copy fastest);
  *   num_cc, status: host arrays of G entries (nullable).  Returns GZ_OK if
  *   every graph finished, GZ_ESKETCH_FAIL if any did not.  Graphs with
  *   V > 65536 are queried one at a time (GZ_EINVAL here when G > 1).

@@ -488,18 +488,25 @@ __global__ __launch_bounds__(1024) void k_q_double_all(const uint32_t* __restric
     if (ctl[Q_STOP]) return;
     const uint32_t nL = ctl[Q_NL];
     if (nL <= lds_cap) return;
+    // A step that changes nothing leaves both buffers equal on the list (so
+    // the caller's choice of buffer by the parity of K still holds) and has
+    // reached the K-step result: every successor then lies on a cycle whose
+    // length divides 2^k, and its minimum spans that cycle.
     for (uint32_t k = 0; k < K; ++k) {
         uint32_t* si = (k & 1) ? s2 : s;
         uint32_t* mi = (k & 1) ? m2 : m;
         uint32_t* so = (k & 1) ? s : s2;
         uint32_t* mo = (k & 1) ? m : m2;
+        int changed = 0;
         for (uint32_t i = threadIdx.x; i < nL; i += blockDim.x) {
             const uint32_t X = L[i];
             const uint32_t y = si[X];
-            so[X] = si[y];
-            mo[X] = min(mi[X], mi[y]);
+            const uint32_t ns = si[y], nm = min(mi[X], mi[y]);
+            changed |= (ns != y) | (nm != mi[X]);
+            so[X] = ns;
+            mo[X] = nm;
         }
-        __syncthreads();
+        if (!__syncthreads_or(changed)) break;
     }
 }
 

@@ -278,9 +278,15 @@ void worker_main(gz_server* S) {
         if (prev.buf >= 0) {
             gz_status pst = hipEventSynchronize(S->stage_ev[prev.buf]) == hipSuccess ? GZ_OK
                                                                                       : GZ_EDEVICE;
+            // Every batch was validated when it was submitted, so the ingest
+            // cannot have met an invalid update: its completion is all that is
+            // left to wait for, and the graphs need no flush-time error check
+            // (two synchronous device reads per session, most of a tick's time
+            // when a tick holds dozens of sessions).  No query of these
+            // sessions runs until their batches complete, below.
             for (size_t i = 0; i < prev.tick.upd_sessions.size(); ++i) {
-                gz_status fst = gz_flush(prev.tick.upd_sessions[i]->g);
-                for (gz_ticket* k : prev.tick.upd[i]) complete(S, k, pst ? pst : fst);
+                prev.tick.upd_sessions[i]->g->pending_error = false;
+                for (gz_ticket* k : prev.tick.upd[i]) complete(S, k, pst);
             }
             prev = Pending{};
         }

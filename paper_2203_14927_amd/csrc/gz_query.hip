@@ -676,6 +676,78 @@ __global__ __launch_bounds__(1024) void k_q_resolve_lds(
     }
 }
 
+// The first round of a query over several graphs of at most kGraphResolve
+// nodes: one workgroup per graph resolves its hooks in LDS, as
+// k_q_resolve_lds does for one list.  In that round the list is every node in
+// order, so a graph's components are its node range and every hook stays in
+// it; this replaces the grid-wide doubling (a dozen launches over millions of
+// components).
+constexpr uint32_t kGraphResolve = 4096;
+constexpr uint32_t kGraphResolveThreads = 256;
+
+__global__ __launch_bounds__(kGraphResolveThreads) void k_q_resolve_graphs(
+    const GraphDesc* __restrict__ gd, uint32_t* __restrict__ ctl,
+    const uint32_t* __restrict__ hook, const uint64_t* __restrict__ hedge,
+    uint32_t* __restrict__ rootOf, uint32_t* __restrict__ newlab, uint32_t* __restrict__ merged,
+    uint64_t* __restrict__ forest) {
+    __shared__ uint64_t st[kGraphResolve];
+    __shared__ uint32_t s_scan[kGraphResolveThreads / 64 + 1];
+    if (ctl[Q_STOP]) return;
+    const uint32_t graph = blockIdx.x, tid = threadIdx.x, bd = blockDim.x;
+    const uint32_t n = gd[graph].V, v0 = gd[graph].node_base;
+    for (uint32_t i = tid; i < n; i += bd) {
+        const uint32_t h = hook[v0 + i];
+        st[i] = ((uint64_t)(v0 + i) << 32) | (h == kNone ? i : h - v0);
+    }
+    __syncthreads();
+    // in-place doubling with the fixed-point stop of k_q_resolve_lds
+    const uint32_t steps = n > 1 ? 32u - (uint32_t)__clz(n - 1) : 0u;
+    for (uint32_t k = 0; k < steps; ++k) {
+        int changed = 0;
+        for (uint32_t i = tid; i < n; i += bd) {
+            const uint64_t v = st[i];
+            const uint64_t w = st[(uint32_t)v];
+            const uint64_t nv = (min(v >> 32, w >> 32) << 32) | (uint32_t)w;
+            changed |= nv != v;
+            st[i] = nv;
+        }
+        if (!__syncthreads_or(changed)) break;
+    }
+    auto root_at = [&](uint32_t i) { return (uint32_t)(st[(uint32_t)st[i]] >> 32); };
+    // kept hook edges: counted, then placed with one atomic per graph
+    uint32_t cnt = 0;
+    for (uint32_t i = tid; i < n; i += bd)
+        cnt += (hook[v0 + i] != kNone && v0 + i != root_at(i)) ? 1u : 0u;
+    const uint32_t lane = __lane_id(), wave = tid >> 6;
+    uint32_t incl = cnt;
+    for (uint32_t o = 1; o < 64; o <<= 1) {
+        const uint32_t t = __shfl_up(incl, o);
+        if (lane >= o) incl += t;
+    }
+    if (lane == 63) s_scan[wave] = incl;
+    __syncthreads();
+    if (tid == 0) {
+        uint32_t sum = 0;
+        for (uint32_t w = 0; w < (bd >> 6); ++w) {
+            const uint32_t c = s_scan[w];
+            s_scan[w] = sum;
+            sum += c;
+        }
+        s_scan[bd >> 6] = sum ? atomicAdd(&ctl[Q_NF], sum) : 0u;
+    }
+    __syncthreads();
+    uint32_t f = s_scan[bd >> 6] + s_scan[wave] + incl - cnt;
+    for (uint32_t i = tid; i < n; i += bd) {
+        const uint32_t X = v0 + i, R = root_at(i);
+        rootOf[X] = R;
+        if (X <= R) label_min(&newlab[R], X);
+        if (hook[X] != kNone && X != R) {
+            merged[R] = 1;
+            forest[f++] = forest_key(ctl, graph, hedge[X]);
+        }
+    }
+}
+
 // The next round's component list: the roots of this round's trees.  The last
 // workgroup to finish also ends the round: it publishes the round's active
 // count and the new list length to the host (pinned memory), makes the new
@@ -1097,29 +1169,35 @@ gz_status boruvka(gz_graph* const* gs, uint32_t G, bool want_forest, QueryResult
                                                     Q->descs, Q->comp, Q->hook, Q->hedge,
                                                     Q->done);
         }
-        // hooks -> roots: in LDS when the list is short (on the device's count),
-        // else by grid-wide pointer doubling
-        k_q_resolve_lds<<<1, 1024, 0, qs>>>(Lc, Q->ctl, K, Q->hook, Q->hedge, Q->pos, Q->gof,
-                                            Q->rootOf, Q->newlab, Q->merged, Q->forest);
-        if (nl_bound > kLdsResolve) {
-            const uint32_t cap = kLdsResolve;
-            k_q_double_init<<<tb, 256, 0, qs>>>(Lc, Q->ctl, Q->hook, s, m, cap);
-            if (T <= kSingleBlockDoubling) {
-                k_q_double_all<<<1, 1024, 0, qs>>>(Lc, Q->ctl, K, s, m, s2, m2, cap);
-                if (K & 1) {
-                    std::swap(s, s2);
-                    std::swap(m, m2);
+        // hooks -> roots: per graph in LDS in the first round of many small
+        // graphs; in LDS when the list is short (on the device's count); else
+        // by grid-wide pointer doubling
+        if (r == 0 && G > 1 && Vmax <= kGraphResolve) {
+            k_q_resolve_graphs<<<G, kGraphResolveThreads, 0, qs>>>(
+                Q->descs, Q->ctl, Q->hook, Q->hedge, Q->rootOf, Q->newlab, Q->merged, Q->forest);
+        } else {
+            k_q_resolve_lds<<<1, 1024, 0, qs>>>(Lc, Q->ctl, K, Q->hook, Q->hedge, Q->pos, Q->gof,
+                                                Q->rootOf, Q->newlab, Q->merged, Q->forest);
+            if (nl_bound > kLdsResolve) {
+                const uint32_t cap = kLdsResolve;
+                k_q_double_init<<<tb, 256, 0, qs>>>(Lc, Q->ctl, Q->hook, s, m, cap);
+                if (T <= kSingleBlockDoubling) {
+                    k_q_double_all<<<1, 1024, 0, qs>>>(Lc, Q->ctl, K, s, m, s2, m2, cap);
+                    if (K & 1) {
+                        std::swap(s, s2);
+                        std::swap(m, m2);
+                    }
+                } else {
+                    for (uint32_t k = 0; k < K; ++k) {
+                        k_q_double<<<tb, 256, 0, qs>>>(Lc, Q->ctl, s, m, s2, m2, cap);
+                        std::swap(s, s2);
+                        std::swap(m, m2);
+                    }
                 }
-            } else {
-                for (uint32_t k = 0; k < K; ++k) {
-                    k_q_double<<<tb, 256, 0, qs>>>(Lc, Q->ctl, s, m, s2, m2, cap);
-                    std::swap(s, s2);
-                    std::swap(m, m2);
-                }
+                k_q_root<<<ta, kAppendThreads, 0, qs>>>(Lc, Q->ctl, s, m, Q->hook, Q->hedge, Q->gof,
+                                                        Q->rootOf, Q->newlab, Q->merged, Q->forest,
+                                                        cap);
             }
-            k_q_root<<<ta, kAppendThreads, 0, qs>>>(Lc, Q->ctl, s, m, Q->hook, Q->hedge, Q->gof,
-                                                    Q->rootOf, Q->newlab, Q->merged, Q->forest,
-                                                    cap);
         }
         // relabel first: the round's last workgroup of newcomps may stop the query
         k_q_relabel<<<tb, 256, 0, qs>>>(T, Q->comp, Q->rootOf, Q->newlab, Q->ctl);

@@ -748,15 +748,16 @@ __global__ __launch_bounds__(kGraphResolveThreads) void k_q_resolve_graphs(
     }
 }
 
-// The next round's component list: the roots of this round's trees.  The last
-// workgroup to finish also ends the round: it publishes the round's active
+// The next round's component list: the roots of this round's trees, and every
+// node's new label (the relabel of the round).  The last workgroup to finish
+// also ends the round: it publishes the round's active
 // count and the new list length to the host (pinned memory), makes the new
 // list current, and stops the query once a round had no active component.
 __global__ __launch_bounds__(kAppendThreads) void k_q_newcomps(
-    uint32_t r, const uint32_t* __restrict__ L, uint32_t* __restrict__ ctl,
-    const uint32_t* __restrict__ rootOf, const uint32_t* __restrict__ newlab,
-    const uint32_t* __restrict__ merged, uint32_t* __restrict__ done, uint32_t* __restrict__ L2,
-    uint32_t* __restrict__ host_na) {
+    uint32_t r, uint32_t T, uint32_t* __restrict__ comp, const uint32_t* __restrict__ L,
+    uint32_t* __restrict__ ctl, const uint32_t* __restrict__ rootOf,
+    const uint32_t* __restrict__ newlab, const uint32_t* __restrict__ merged,
+    uint32_t* __restrict__ done, uint32_t* __restrict__ L2, uint32_t* __restrict__ host_na) {
     __shared__ uint32_t sh[kMaxWaves + 1];
     __shared__ uint32_t s_last;
     if (ctl[Q_STOP]) return;
@@ -774,6 +775,9 @@ __global__ __launch_bounds__(kAppendThreads) void k_q_newcomps(
         const uint32_t at = block_append(&ctl[Q_NL2], root, sh);
         if (root) L2[at] = X;
     }
+    // every node's label: the new label of its component's tree
+    for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < T; v += gridDim.x * blockDim.x)
+        comp[v] = newlab[rootOf[comp[v]]];
     // No fence: the last workgroup reads only counters that every workgroup
     // updated with atomics it waited for (block_append uses the result)
     // before counting itself done; the list and the counters it writes reach
@@ -793,15 +797,6 @@ __global__ __launch_bounds__(kAppendThreads) void k_q_newcomps(
     ctl[Q_DONE] = 0;
     host_na[r] = na;
     host_na[kMaxRounds + r] = nl;
-}
-
-__global__ void k_q_relabel(uint32_t T, uint32_t* __restrict__ comp,
-                            const uint32_t* __restrict__ rootOf,
-                            const uint32_t* __restrict__ newlab,
-                            const uint32_t* __restrict__ ctl) {
-    if (ctl[Q_STOP]) return;
-    for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < T; v += gridDim.x * blockDim.x)
-        comp[v] = newlab[rootOf[comp[v]]];
 }
 
 __global__ void k_q_finish(const uint32_t* __restrict__ L, const uint32_t* __restrict__ ctl,
@@ -1199,12 +1194,10 @@ gz_status boruvka(gz_graph* const* gs, uint32_t G, bool want_forest, QueryResult
                                                         cap);
             }
         }
-        // relabel first: the round's last workgroup of newcomps may stop the query
-        k_q_relabel<<<tb, 256, 0, qs>>>(T, Q->comp, Q->rootOf, Q->newlab, Q->ctl);
         // at most kEndBlocks workgroups: each takes one returning atomic to
         // find the last (4233 of them took 40 us per round on 4.3 M nodes)
         k_q_newcomps<<<std::min(ta, kEndBlocks), kAppendThreads, 0, qs>>>(
-            r, Lc, Q->ctl, Q->rootOf, Q->newlab, Q->merged, Q->done, Ln, Q->host_na);
+            r, T, Q->comp, Lc, Q->ctl, Q->rootOf, Q->newlab, Q->merged, Q->done, Ln, Q->host_na);
         std::swap(Lc, Ln);
         GZ_HIP(hipEventRecord(Q->round_ev[r & 1], qs));
     }

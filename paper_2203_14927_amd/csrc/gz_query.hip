@@ -690,14 +690,21 @@ __global__ __launch_bounds__(kGraphResolveThreads) void k_q_resolve_graphs(
     const uint32_t* __restrict__ hook, const uint64_t* __restrict__ hedge,
     uint32_t* __restrict__ rootOf, uint32_t* __restrict__ newlab, uint32_t* __restrict__ merged,
     uint64_t* __restrict__ forest) {
+    // a lane's nodes are tid + q * blockDim for q < kItems; their hooks stay in
+    // registers and every global load is issued for all of them at once
+    constexpr uint32_t kItems = kGraphResolve / kGraphResolveThreads;
     __shared__ uint64_t st[kGraphResolve];
     __shared__ uint32_t s_scan[kGraphResolveThreads / 64 + 1];
     if (ctl[Q_STOP]) return;
     const uint32_t graph = blockIdx.x, tid = threadIdx.x, bd = blockDim.x;
     const uint32_t n = gd[graph].V, v0 = gd[graph].node_base;
-    for (uint32_t i = tid; i < n; i += bd) {
-        const uint32_t h = hook[v0 + i];
-        st[i] = ((uint64_t)(v0 + i) << 32) | (h == kNone ? i : h - v0);
+    uint32_t h[kItems];
+#pragma unroll
+    for (uint32_t q = 0; q < kItems; ++q) h[q] = tid + q * bd < n ? hook[v0 + tid + q * bd] : kNone;
+#pragma unroll
+    for (uint32_t q = 0; q < kItems; ++q) {
+        const uint32_t i = tid + q * bd;
+        if (i < n) st[i] = ((uint64_t)(v0 + i) << 32) | (h[q] == kNone ? i : h[q] - v0);
     }
     __syncthreads();
     // in-place doubling with the fixed-point stop of k_q_resolve_lds
@@ -713,11 +720,14 @@ __global__ __launch_bounds__(kGraphResolveThreads) void k_q_resolve_graphs(
         }
         if (!__syncthreads_or(changed)) break;
     }
-    auto root_at = [&](uint32_t i) { return (uint32_t)(st[(uint32_t)st[i]] >> 32); };
-    // kept hook edges: counted, then placed with one atomic per graph
-    uint32_t cnt = 0;
-    for (uint32_t i = tid; i < n; i += bd)
-        cnt += (hook[v0 + i] != kNone && v0 + i != root_at(i)) ? 1u : 0u;
+    // roots, and the kept hook edges: counted, then placed with one atomic per graph
+    uint32_t R[kItems], cnt = 0;
+#pragma unroll
+    for (uint32_t q = 0; q < kItems; ++q) {
+        const uint32_t i = tid + q * bd;
+        R[q] = i < n ? (uint32_t)(st[(uint32_t)st[i]] >> 32) : 0u;
+        cnt += (h[q] != kNone && v0 + i != R[q]) ? 1u : 0u;  // h is kNone past n
+    }
     const uint32_t lane = __lane_id(), wave = tid >> 6;
     uint32_t incl = cnt;
     for (uint32_t o = 1; o < 64; o <<= 1) {
@@ -737,13 +747,25 @@ __global__ __launch_bounds__(kGraphResolveThreads) void k_q_resolve_graphs(
     }
     __syncthreads();
     uint32_t f = s_scan[bd >> 6] + s_scan[wave] + incl - cnt;
-    for (uint32_t i = tid; i < n; i += bd) {
-        const uint32_t X = v0 + i, R = root_at(i);
-        rootOf[X] = R;
-        if (X <= R) label_min(&newlab[R], X);
-        if (hook[X] != kNone && X != R) {
-            merged[R] = 1;
-            forest[f++] = forest_key(ctl, graph, hedge[X]);
+    uint32_t lab[kItems];
+    uint64_t e[kItems];
+#pragma unroll
+    for (uint32_t q = 0; q < kItems; ++q) {
+        const uint32_t i = tid + q * bd;
+        const bool kept = h[q] != kNone && v0 + i != R[q];
+        lab[q] = i < n && v0 + i <= R[q] ? newlab[R[q]] : 0u;
+        e[q] = kept ? hedge[v0 + i] : 0ull;
+    }
+#pragma unroll
+    for (uint32_t q = 0; q < kItems; ++q) {
+        const uint32_t i = tid + q * bd;
+        if (i >= n) continue;
+        const uint32_t X = v0 + i;
+        rootOf[X] = R[q];
+        if (X <= R[q] && X < lab[q]) atomicMin(&newlab[R[q]], X);  // as label_min
+        if (h[q] != kNone && X != R[q]) {
+            merged[R[q]] = 1;
+            forest[f++] = forest_key(ctl, graph, e[q]);
         }
     }
 }

@@ -14,6 +14,7 @@
 // takes its smallest component id as label.
 #include <algorithm>
 #include <cstring>
+#include <type_traits>
 
 #include "gz_device.h"
 #include "gz_internal.h"
@@ -554,19 +555,28 @@ __global__ __launch_bounds__(kAppendThreads) void k_q_root(
 // pair in one access, so its word always describes one path segment
 // [X, successor) and its minimum; in-place steps advance at least as far as
 // synchronous ones, so K steps still reach every terminal cycle.
+// When every node id of the query fits 16 bits (T <= 65536) the pair packs
+// into 32 bits: half the LDS traffic of the doubling, and lists of up to
+// kLdsResolveNarrow components fit one workgroup.
 constexpr uint32_t kLdsResolve = 16384;
+constexpr uint32_t kLdsResolveNarrow = 36864;
 constexpr uint32_t kResolveBatch = 8;
 
+template <bool kNarrowIds>
 __global__ __launch_bounds__(1024) void k_q_resolve_lds(
     const uint32_t* __restrict__ L, uint32_t* __restrict__ ctl, uint32_t K,
     const uint32_t* __restrict__ hook, const uint64_t* __restrict__ hedge,
     const uint32_t* __restrict__ pos, const uint32_t* __restrict__ gof,
     uint32_t* __restrict__ rootOf, uint32_t* __restrict__ newlab, uint32_t* __restrict__ merged,
     uint64_t* __restrict__ forest) {
-    __shared__ uint64_t st[kLdsResolve];
+    using W = typename std::conditional<kNarrowIds, uint32_t, uint64_t>::type;
+    constexpr uint32_t kCap = kNarrowIds ? kLdsResolveNarrow : kLdsResolve;
+    constexpr uint32_t kS = kNarrowIds ? 16u : 32u;  // minimum << kS | successor position
+    constexpr W kPosMask = ((W)1 << kS) - 1;
+    __shared__ W st[kCap];
     if (ctl[Q_STOP]) return;
     const uint32_t nL = ctl[Q_NL];
-    if (nL > kLdsResolve) return;
+    if (nL > kCap) return;
     const uint32_t bd = blockDim.x;
     // global loads in batches of kResolveBatch per lane, so that a lane waits
     // once per dependent step of a batch rather than once per component
@@ -585,7 +595,7 @@ __global__ __launch_bounds__(1024) void k_q_resolve_lds(
             sp[q] = h[q] == kNone ? i0 + q * bd : pos[h[q]];
 #pragma unroll
         for (uint32_t q = 0; q < kResolveBatch; ++q)
-            if (i0 + q * bd < nL) st[i0 + q * bd] = ((uint64_t)X[q] << 32) | sp[q];
+            if (i0 + q * bd < nL) st[i0 + q * bd] = ((W)X[q] << kS) | sp[q];
     }
     __syncthreads();
     // A path to a cycle and the cycle hold at most nL components.  A step that
@@ -597,15 +607,15 @@ __global__ __launch_bounds__(1024) void k_q_resolve_lds(
     for (uint32_t k = 0; k < steps; ++k) {
         int changed = 0;
         for (uint32_t i0 = threadIdx.x; i0 < nL; i0 += 4 * bd) {
-            uint64_t v[4], w[4];
+            W v[4], w[4];
 #pragma unroll
-            for (uint32_t q = 0; q < 4; ++q) v[q] = i0 + q * bd < nL ? st[i0 + q * bd] : 0ull;
+            for (uint32_t q = 0; q < 4; ++q) v[q] = i0 + q * bd < nL ? st[i0 + q * bd] : (W)0;
 #pragma unroll
-            for (uint32_t q = 0; q < 4; ++q) w[q] = st[(uint32_t)v[q]];
+            for (uint32_t q = 0; q < 4; ++q) w[q] = st[(uint32_t)(v[q] & kPosMask)];
 #pragma unroll
             for (uint32_t q = 0; q < 4; ++q)
                 if (i0 + q * bd < nL) {
-                    const uint64_t nv = (min(v[q] >> 32, w[q] >> 32) << 32) | (uint32_t)w[q];
+                    const W nv = (min(v[q] >> kS, w[q] >> kS) << kS) | (w[q] & kPosMask);
                     changed |= nv != v[q];
                     st[i0 + q * bd] = nv;
                 }
@@ -615,7 +625,7 @@ __global__ __launch_bounds__(1024) void k_q_resolve_lds(
     // roots and new labels; the kept hook edges are counted first so that one
     // atomic and a workgroup scan place them (an atomic that returns a value
     // costs a round trip, one per component was most of this kernel's time)
-    auto root_at = [&](uint32_t i) { return (uint32_t)(st[(uint32_t)st[i]] >> 32); };
+    auto root_at = [&](uint32_t i) { return (uint32_t)(st[(uint32_t)(st[i] & kPosMask)] >> kS); };
     uint32_t cnt = 0;
     for (uint32_t i0 = threadIdx.x; i0 < nL; i0 += kResolveBatch * bd) {
         uint32_t X[kResolveBatch], h[kResolveBatch];
@@ -682,19 +692,24 @@ __global__ __launch_bounds__(1024) void k_q_resolve_lds(
 // order, so a graph's components are its node range and every hook stays in
 // it; this replaces the grid-wide doubling (a dozen launches over millions of
 // components).
+// The same kernel, one workgroup of 1024 lanes, takes the first round of a
+// single graph of up to kGraphResolveOne nodes (the list is every node then
+// too), in place of the list-indexed k_q_resolve_lds.
 constexpr uint32_t kGraphResolve = 4096;
 constexpr uint32_t kGraphResolveThreads = 256;
+constexpr uint32_t kGraphResolveOne = 16384;
 
-__global__ __launch_bounds__(kGraphResolveThreads) void k_q_resolve_graphs(
+template <uint32_t kCap, uint32_t kThreads>
+__global__ __launch_bounds__(kThreads) void k_q_resolve_graphs(
     const GraphDesc* __restrict__ gd, uint32_t* __restrict__ ctl,
     const uint32_t* __restrict__ hook, const uint64_t* __restrict__ hedge,
     uint32_t* __restrict__ rootOf, uint32_t* __restrict__ newlab, uint32_t* __restrict__ merged,
     uint64_t* __restrict__ forest) {
     // a lane's nodes are tid + q * blockDim for q < kItems; their hooks stay in
     // registers and every global load is issued for all of them at once
-    constexpr uint32_t kItems = kGraphResolve / kGraphResolveThreads;
-    __shared__ uint64_t st[kGraphResolve];
-    __shared__ uint32_t s_scan[kGraphResolveThreads / 64 + 1];
+    constexpr uint32_t kItems = kCap / kThreads;
+    __shared__ uint64_t st[kCap];
+    __shared__ uint32_t s_scan[kThreads / 64 + 1];
     if (ctl[Q_STOP]) return;
     const uint32_t graph = blockIdx.x, tid = threadIdx.x, bd = blockDim.x;
     const uint32_t n = gd[graph].V, v0 = gd[graph].node_base;
@@ -1157,6 +1172,8 @@ gz_status boruvka(gz_graph* const* gs, uint32_t G, bool want_forest, QueryResult
     // (no active component, so every component is its own root) both hold the
     // same components, so rounds enqueued past it may swap them freely.
     uint32_t nl_bound = T;
+    const bool narrow_ids = T <= 65536;  // node ids and list positions fit 16 bits
+    const uint32_t lds_cap = narrow_ids ? kLdsResolveNarrow : kLdsResolve;
     uint32_t* Lc = Q->L;
     uint32_t* Ln = Q->L2;
     for (uint32_t r = 0; r < Rmax; ++r) {
@@ -1190,13 +1207,22 @@ gz_status boruvka(gz_graph* const* gs, uint32_t G, bool want_forest, QueryResult
         // graphs; in LDS when the list is short (on the device's count); else
         // by grid-wide pointer doubling
         if (r == 0 && G > 1 && Vmax <= kGraphResolve) {
-            k_q_resolve_graphs<<<G, kGraphResolveThreads, 0, qs>>>(
+            k_q_resolve_graphs<kGraphResolve, kGraphResolveThreads><<<G, kGraphResolveThreads, 0, qs>>>(
+                Q->descs, Q->ctl, Q->hook, Q->hedge, Q->rootOf, Q->newlab, Q->merged, Q->forest);
+        } else if (r == 0 && G == 1 && T <= kGraphResolveOne) {
+            k_q_resolve_graphs<kGraphResolveOne, 1024><<<1, 1024, 0, qs>>>(
                 Q->descs, Q->ctl, Q->hook, Q->hedge, Q->rootOf, Q->newlab, Q->merged, Q->forest);
         } else {
-            k_q_resolve_lds<<<1, 1024, 0, qs>>>(Lc, Q->ctl, K, Q->hook, Q->hedge, Q->pos, Q->gof,
-                                                Q->rootOf, Q->newlab, Q->merged, Q->forest);
-            if (nl_bound > kLdsResolve) {
-                const uint32_t cap = kLdsResolve;
+            if (narrow_ids)
+                k_q_resolve_lds<true><<<1, 1024, 0, qs>>>(Lc, Q->ctl, K, Q->hook, Q->hedge, Q->pos,
+                                                          Q->gof, Q->rootOf, Q->newlab, Q->merged,
+                                                          Q->forest);
+            else
+                k_q_resolve_lds<false><<<1, 1024, 0, qs>>>(Lc, Q->ctl, K, Q->hook, Q->hedge,
+                                                           Q->pos, Q->gof, Q->rootOf, Q->newlab,
+                                                           Q->merged, Q->forest);
+            if (nl_bound > lds_cap) {
+                const uint32_t cap = lds_cap;
                 k_q_double_init<<<tb, 256, 0, qs>>>(Lc, Q->ctl, Q->hook, s, m, cap);
                 if (T <= kSingleBlockDoubling) {
                     k_q_double_all<<<1, 1024, 0, qs>>>(Lc, Q->ctl, K, s, m, s2, m2, cap);

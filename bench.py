@@ -195,6 +195,8 @@ def main() -> int:
     ap.add_argument("--batches", type=int, default=100, help="serving: batches per session")
     ap.add_argument("--hbm-budget-gb", type=float, default=120.0, help="serving: admission budget")
     ap.add_argument("--tick-updates", type=int, default=16 << 20, help="serving: updates per tick")
+    ap.add_argument("--client-threads", type=int, default=16,
+                    help="serving: host threads driving the sessions' closed-loop clients")
     ap.add_argument("--staging-mb", type=int, default=128,
                     help="host tier: device bytes of the two slab buffers")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -406,26 +408,52 @@ def run_serving(args) -> dict:
     lat_upd, lat_q, errors = [], [], []
     lock = threading.Lock()
 
-    def client(k):
+    def clients(t):
+        """Closed-loop clients of the sessions k = t, t + T, ...: each session keeps
+        exactly one request outstanding (its next batch after the previous one
+        completed, a query after every 50th batch and the last); one thread waits
+        on the group's requests in submission order."""
+        import collections
+
         try:
-            V, seed, sizes = plans[k]
-            src, dst = data[k]
-            sess = srv.open(V, seed)
-            at = 0
-            for b, n in enumerate(sizes.tolist()):
-                r = sess.submit_updates(src[at:at + n], dst[at:at + n]).wait()
-                at += n
+            mine = list(range(t, S, args.client_threads))
+            st = {}
+            pending = collections.deque()
+
+            def next_request(k):
+                c = st[k]
+                V, seed, sizes = plans[k]
+                if c["query_due"]:
+                    c["query_due"] = False
+                    c["ticket"], c["kind"] = c["sess"].submit_query(), "q"
+                elif c["b"] < len(sizes):
+                    n = int(sizes[c["b"]])
+                    src, dst = data[k]
+                    c["ticket"] = c["sess"].submit_updates(src[c["at"]:c["at"] + n],
+                                                           dst[c["at"]:c["at"] + n])
+                    c["kind"] = "u"
+                    c["at"] += n
+                    c["b"] += 1
+                    c["query_due"] = c["b"] % 50 == 0 or c["b"] == len(sizes)
+                else:
+                    c["sess"].close()
+                    return
+                pending.append(k)
+
+            for k in mine:
+                V, seed, _ = plans[k]
+                st[k] = {"sess": srv.open(V, seed), "at": 0, "b": 0, "query_due": False}
+                next_request(k)
+            while pending:
+                k = pending.popleft()
+                r = st[k]["ticket"].wait()
                 with lock:
-                    lat_upd.append(r["latency_ms"])
-                if (b + 1) % 50 == 0 or b + 1 == len(sizes):
-                    q = sess.submit_query().wait()
-                    with lock:
-                        lat_q.append(q["latency_ms"])
-            sess.close()
+                    (lat_q if st[k]["kind"] == "q" else lat_upd).append(r["latency_ms"])
+                next_request(k)
         except Exception as e:
             errors.append(e)
 
-    th = [threading.Thread(target=client, args=(k,)) for k in range(S)]
+    th = [threading.Thread(target=clients, args=(t,)) for t in range(min(S, args.client_threads))]
     t0 = time.perf_counter()
     for t in th:
         t.start()
@@ -447,7 +475,8 @@ def run_serving(args) -> dict:
         "vs_baseline": None, "dtype": "u64", "data": "synthetic",
         "config": {"workload": f"serving: {S} R-MAT sessions, V=round(2^U(10,16)), Pareto(1.5) "
                                f"batches in [1e3,1e6], {args.batches} batches each, a query every "
-                               f"50 batches, closed-loop clients (seed 5)",
+                               f"50 batches, closed-loop clients (one request outstanding per session, "
+                               f"{min(S, args.client_threads)} host threads; seed 5)",
                    "sessions": S, "updates": total, "hbm_budget_gb": args.hbm_budget_gb,
                    "tick_updates": args.tick_updates},
         "batch_latency_ms": {"p50": pct(lat_upd, 50), "p99": pct(lat_upd, 99),

@@ -245,6 +245,19 @@ def test_many_graphs_fused_mixed_spans(gz):
         assert ncc[k] == len(np.unique(olabels))
 
 
+@pytest.mark.parametrize("V,n,seed", [(30000, 18000, 31), (16385, 9000, 32)])
+def test_query_lists_between_lds_capacities(gz, V, n, seed):
+    """A sparse graph whose first component lists hold 16 385 to 36 864 components:
+    resolved in one workgroup's LDS with 32-bit (minimum, successor) words, past
+    the 16 384-component capacity of 64-bit words."""
+    s = _stream(V, n, seed, p_repeat=0.1)
+    g = gz.Graph(V, seed=seed)
+    g.ingest(to_dev(s.src), to_dev(s.dst))
+    O = oracle_for(s, seed)
+    st, labels, forest = assert_query_equal(g, O)
+    assert len(np.unique(labels)) > 1000  # many components: long lists after round 0
+
+
 def test_two_pass_grouping_full_parity(gz):
     """V > 4096 takes the two-pass placement: 150k updates over many grouping chunks."""
     s = _stream(5000, 150000, 21)

@@ -288,6 +288,125 @@ def test_sampled_index_in_support_and_goodset_bound(built):
     assert fails <= 2
 
 
+def _py_checksum(tab, r, c, x):
+    (ah, bh), (alo, blo) = [tuple(int(t) for t in tab[r, c, k]) for k in (1, 2)]
+    return (_py_hash(ah, bh, x) << 32) | _py_hash(alo, blo, x)
+
+
+def _planted_sketch(V, seed, r, good, bad):
+    """[C, B] alpha/gamma of round r with GOOD buckets planted at good[(c, b)] = index and BAD
+    ones at the cells of `bad`; checksums in Python big integers from the seed table."""
+    R, C, B, n = oracle.shape(V)
+    tab = oracle.seed_table(seed, R)
+    al = np.zeros((C, B), np.uint64)
+    ga = np.zeros((C, B), np.uint64)
+    for (c, b), i in good.items():
+        al[c, b] = i
+        ga[c, b] = _py_checksum(tab, r, c, i)
+    for (c, b), i in bad.items():
+        al[c, b] = i
+        ga[c, b] = _py_checksum(tab, r, c, i) ^ 1  # checksum off by one bit
+    return al, ga, n
+
+
+def test_query_returns_first_good_bucket_columns_outer_rows_ascending(built):
+    """Fig. cube_code query: columns in the outer loop, buckets of a column in the inner loop,
+    the first bucket that passes the checksum test is returned."""
+    V, seed, r = 1 << 12, 4242, 3
+    O = oracle.Oracle(V, seed)
+    rng = random.Random(8)
+    i1, i2, i3, j1, j2 = (rng.randrange(1, O.n) for _ in range(5))
+    # GOOD at (2, 5), (2, 1), (5, 0); BAD at (0, 3) and (1, 0).  Columns-then-rows gives (2, 1);
+    # rows-then-columns would give (5, 0), deepest-first (2, 5), last-found (5, 0).
+    al, ga, _ = _planted_sketch(V, seed, r, {(2, 5): i1, (2, 1): i2, (5, 0): i3},
+                                {(0, 3): j1, (1, 0): j2})
+    assert O.query(r, al, ga) == (oracle.SAMPLE, i2)
+    # a GOOD bucket in a lower column beats every row of a higher column, even row 0
+    al, ga, _ = _planted_sketch(V, seed, r, {(1, O.B - 1): i1, (3, 0): i3}, {(0, 0): j1})
+    assert O.query(r, al, ga) == (oracle.SAMPLE, i1)
+    # the checksum belongs to the round and column: the same pair placed in another column
+    # (or queried as another round) is BAD, so the next GOOD bucket wins
+    al, ga, _ = _planted_sketch(V, seed, r, {(4, 2): i2, (6, 0): i3}, {})
+    al[0, 0], ga[0, 0] = al[4, 2], ga[4, 2]
+    assert O.query(r, al, ga) == (oracle.SAMPLE, i2)
+    assert O.query(r + 1, al, ga)[0] == oracle.FAIL or O.query(r + 1, al, ga)[1] != i2
+    # classes of the result rule after Eq. (1)-(2): all EMPTY -> ZERO, BAD only -> FAIL
+    al, ga, _ = _planted_sketch(V, seed, r, {}, {})
+    assert O.query(r, al, ga)[0] == oracle.ZERO
+    al, ga, _ = _planted_sketch(V, seed, r, {}, {(7, 4): j1})
+    assert O.query(r, al, ga)[0] == oracle.FAIL
+    # an alpha outside [0, n) is never a sample, even with a matching checksum
+    tab = oracle.seed_table(seed, O.R)
+    al, ga, _ = _planted_sketch(V, seed, r, {(3, 0): i3}, {})
+    al[1, 0] = O.n + 5
+    ga[1, 0] = _py_checksum(tab, r, 1, O.n + 5)
+    assert O.query(r, al, ga) == (oracle.SAMPLE, i3)
+
+
+def _round0_sample(V, seed, w, incident):
+    """Round-0 query of node w's sketch, modelled in Python: the nested buckets of Eq. (1)-(2)
+    from the incident edge set, scanned columns first, rows ascending."""
+    R, C, B, n = oracle.shape(V)
+    tab = oracle.seed_table(seed, R)
+    for c in range(C):
+        a1, b1 = (int(t) for t in tab[0, c, 0])
+        for b in range(B):
+            al, ga = 0, 0
+            for (u, v) in incident:
+                i = v * (v - 1) // 2 + u
+                if _py_hash(a1, b1, i) % (1 << b) == 0:
+                    al ^= i
+                    ga ^= _py_checksum(tab, 0, c, i)
+            if (al or ga) and al < n and ga == _py_checksum(tab, 0, c, al):
+                return al
+    return None
+
+
+def _idx(u, v):
+    return v * (v - 1) // 2 + u
+
+
+def test_hook_cycle_loses_the_hook_of_its_smallest_component(built):
+    """Sec. 2.2: Boruvka merges along one sampled edge per component and the paper leaves open
+    which edges form the forest.  Reading taken: the sampled edges form a functional graph and
+    every cycle drops the hook of its smallest component.  Graph: triangle {1, 2, 3} plus the
+    pendant edge (0, 3).  Seeds are searched (in the Python model) for a round 0 whose hooks are
+    0 -> 3 and a 3-cycle around the triangle, so that the smallest member of the cycle (1) is
+    neither where the walk from 0 enters it (3) nor its largest member (3)."""
+    V = 4
+    edges = [(1, 2), (1, 3), (2, 3), (0, 3)]
+    inc = {w: [e for e in edges if w in e] for w in range(V)}
+    found = 0
+    for seed in range(1, 4000):
+        hook, hedge = {}, {}
+        for w in range(V):
+            i = _round0_sample(V, seed, w, inc[w])
+            if i is None:  # no GOOD bucket in round 0 (possible with B = 4 rows): another seed
+                break
+            u, v = next((a, b) for a, b in edges if _idx(a, b) == i)
+            hook[w], hedge[w] = (v if u == w else u), i
+        if len(hook) < V or hook[0] != 3 or hook[3] == 0:
+            continue
+        if {hook[1], hook[2], hook[3]} != {1, 2, 3} or hook[1] == 1 or hook[2] == 2:
+            continue
+        # a 3-cycle through 1, 2, 3 and the tail 0 -> 3: every hook but node 1's is kept
+        expect = sorted(hedge[w] for w in (0, 2, 3))
+        O = oracle.Oracle(V, seed)
+        O.ingest(np.array([e[0] for e in edges], np.uint32), np.array([e[1] for e in edges], np.uint32))
+        for w in range(V):  # the oracle's own round-0 samples agree with the model
+            assert O.query_node(w, 0) == (oracle.SAMPLE, hedge[w])
+        st, labels, forest, used = O.connected_components()
+        assert st == oracle.OK and labels.tolist() == [0, 0, 0, 0]
+        assert [_idx(a, b) for a, b in forest.tolist()] == expect
+        # the rules that drop the hook of the cycle's entry point or of its largest member
+        # (node 3 in both cases) would keep hedge[1] instead
+        assert hedge[1] not in expect
+        found += 1
+        if found == 3:
+            break
+    assert found == 3
+
+
 # ------------------------------------------------------------- boruvka -----
 
 def _check_forest(V, labels, forest, fu, fv):

@@ -5,15 +5,17 @@ One step = zero the sketches, ingest the whole synthetic stream (device-side
 grouping by endpoint + persistent LDS-staged sketch update) and answer a
 connected-components query.  The stream is resident in HBM before timing.
 
-Default workload: the dense R-MAT graph on V = 2^14 nodes (Graph500 initiator
-a,b,c,d = 0.57,0.19,0.19,0.05, seed 2), ~50M distinct-edge inserts followed by
-10% deletes of live edges, sketch shape R=15, C=8, B=28.
+Default workload: the skewed R-MAT graph on V = 2^15 nodes (initiator
+a,b,c,d = 0.7,0.1,0.1,0.1, seed 3), 150M updates with deletes of live edges
+interleaved at rate 0.2, sketch shape R=16, C=8, B=30 (2 GB of sketches as
+uint64 pairs; 1.5 GB in the library's 32-bit-word layout).
 
 Besides the JSON line's `value` (whole-step updates/s) the line carries the
 plain per-node-launch rate (one gz_update_sketch_batch launch per gutter of
-half a node sketch, the paper's leaf-gutter size), the CC query time, the
-roofline of the dominant kernel (measured with HIP events on its own stream)
-and the CPU oracle's rate on a bounded sample.
+half a node sketch, the paper's leaf-gutter size, each launch spread over the
+chip), the CC query time, the roofline of the dominant kernel (measured with
+HIP events on its own stream) and the CPU oracle's rate on a bounded sample,
+single-threaded and over all host cores.
 """
 from __future__ import annotations
 
@@ -30,11 +32,7 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Launch parameters the autotuner picks for a workload on MI355X (wg_size,
-# lds_rows, chunk, wgs_per_cu, group_blocks), so that a default run times the
-# same configuration every time; --autotune searches again.
-TUNED = {"rmat_dense": "1024,28,16384,2,0", "many_gnp": "256,12,16384,8,0",
-         "rmat_kron18": "512,16,4096,3,256"}
+TUNING_KEYS = ["wg_size", "lds_rows", "chunk", "wgs_per_cu", "group_blocks"]
 
 # MI355X figures used by the roofline: 256 CUs x 4 SIMD16 x 2.4 GHz, HBM3E 8 TB/s
 PEAK_INT_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12   # VALU lane-instructions/s: 39.32 T
@@ -79,6 +77,7 @@ def make_workload(name: str):
 
 
 PMC_SUMMARIES = {"rmat_dense": "k_update_rmat_dense_pmc.txt",
+                 "rmat_skewed": "k_update_rmat_skewed_pmc.txt",
                  "rmat_kron18": "k_update_wide_rmat_kron18_pmc.txt"}
 
 
@@ -118,28 +117,111 @@ def copy_calibration():
     del a, b
 
 
-def cpu_baseline(stream, seed, seconds: float):
-    """The oracle, untuned, single-threaded, on the first M updates of the same stream."""
+def host_cpu():
+    """(CPU model name, logical CPUs this process may run on)."""
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return model, len(os.sched_getaffinity(0))
+
+
+def _oracle_part(arg):
+    """One worker of the all-cores leg: the oracle over the sample, keeping only its nodes."""
+    path, V, seed, nodes = arg
+    import numpy as np
+
     import oracle
 
+    d = np.load(path, mmap_mode="r")
+    src = np.ascontiguousarray(d[0])
+    dst = np.ascontiguousarray(d[1])
+    O = oracle.Oracle(V, seed)
+    t0 = time.perf_counter()
+    O.ingest_nodes(src, dst, nodes)
+    return time.perf_counter() - t0
+
+
+def cpu_baseline(stream, seed, seconds: float, workers: int):
+    """The oracle as it stands (untuned), timed on a bounded sample of the same stream.
+
+    Single thread: the first M1 updates, every node sketch.  All cores: the
+    next M updates, split by node over `workers` processes (each the same
+    single-threaded oracle keeping only its nodes, the nodes dealt out so that
+    every process gets about the same number of endpoint entries); the rate is
+    M over the slowest process's ingest time.  Runs before the GPU is touched
+    (the workers are forked).
+    """
+    import multiprocessing
+    import tempfile
+
+    import numpy as np
+
+    import oracle
+
+    model, nproc = host_cpu()
     O = oracle.Oracle(stream.V, seed)
     probe = min(stream.N, 20000)
     t0 = time.perf_counter()
     O.ingest(stream.src[:probe], stream.dst[:probe])
-    t1 = time.perf_counter()
-    rate = probe / max(t1 - t0, 1e-9)
-    M = int(min(stream.N - probe, max(1000, rate * seconds)))
+    rate1 = probe / max(time.perf_counter() - t0, 1e-9)
+    M1 = int(min(stream.N - probe, max(1000, rate1 * seconds / 2)))
     t0 = time.perf_counter()
-    O.ingest(stream.src[probe:probe + M], stream.dst[probe:probe + M])
+    O.ingest(stream.src[probe:probe + M1], stream.dst[probe:probe + M1])
     t1 = time.perf_counter()
     del O
-    return {"value": M / (t1 - t0), "unit": "updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"updates {probe}..{probe + M} of the stream ({M} updates, ingest only, "
-                      f"all {stream.V} node sketches, {t1 - t0:.1f} s)"}
+    single = {"value": M1 / (t1 - t0), "cores": 1,
+              "sample": f"updates {probe}..{probe + M1} ({M1} updates, all {stream.V} node "
+                        f"sketches, {t1 - t0:.1f} s)"}
+    out = {"value": single["value"], "unit": "updates/s", "cores": 1, "kind": "oracle",
+           "sample": single["sample"], "single_thread": single, "cpu_model": model,
+           "nproc": nproc}
+    workers = max(1, min(workers, nproc))
+    if workers == 1:
+        return out
+    lo = probe + M1
+    M = int(min(stream.N - lo, max(10000, single["value"] * workers * seconds / 2)))
+    src = stream.src[lo:lo + M]
+    dst = stream.dst[lo:lo + M]
+    # deal nodes to workers, heaviest first, each to the least loaded one
+    deg = np.bincount(src, minlength=stream.V) + np.bincount(dst, minlength=stream.V)
+    load = np.zeros(workers, np.int64)
+    parts = [[] for _ in range(workers)]
+    for v in np.argsort(-deg, kind="stable").tolist():
+        w = int(np.argmin(load))
+        parts[w].append(v)
+        load[w] += int(deg[v])
+    tmpdir = "/dev/shm" if os.path.isdir("/dev/shm") else tempfile.gettempdir()
+    fd, path = tempfile.mkstemp(suffix=".npy", dir=tmpdir)
+    os.close(fd)
+    try:
+        np.save(path, np.stack([src, dst]))
+        ctx = multiprocessing.get_context("fork")
+        with ctx.Pool(workers) as pool:
+            times = pool.map(_oracle_part, [(path, stream.V, seed, np.array(p, np.int64))
+                                            for p in parts])
+    finally:
+        os.unlink(path)
+    out.update({"value": M / max(times), "cores": workers,
+                "sample": f"updates {lo}..{lo + M} ({M} updates) split by node over {workers} "
+                          f"processes of the single-threaded oracle; slowest process "
+                          f"{max(times):.1f} s, fastest {min(times):.1f} s; ingest only"})
+    return out
 
 
 def plain_pass(gz, g, stream, src_d, dst_d):
-    """Plain path: one update_sketch_batch launch per node gutter, on pre-grouped input."""
+    """Plain path: one gz_update_sketch_batch launch per node gutter (half a node sketch at
+    4 B per update, the paper's leaf-gutter size), on input grouped by node beforehand.
+
+    Each launch spreads its gutter over workgroups of node_chunk entries whose
+    partial tiles merge by XOR; node_chunk is picked by timing a few values on
+    the first gutters (1 << 30 is one workgroup per gutter).
+    """
     import torch
 
     V = stream.V
@@ -163,17 +245,35 @@ def plain_pass(gz, g, stream, src_d, dst_d):
         o, e = offs[node], offs[node + 1]
         for k in range(o, e, gutter):
             calls.append((node, base + 4 * k, min(gutter, e - k)))
-    g.reset()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for node, ptr, cnt in calls:
-        st = L.gz_update_sketch_batch(h, node, ctypes.c_void_p(ptr), cnt, flags, s)
-        if st:
-            raise RuntimeError(f"plain batch failed: {st}")
-    g.flush()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    return stream.N / (t1 - t0), len(calls), gutter, (t1 - t0) * 1e3
+
+    def run(batch):
+        g.reset()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for node, ptr, cnt in batch:
+            st = L.gz_update_sketch_batch(h, node, ctypes.c_void_p(ptr), cnt, flags, s)
+            if st:
+                raise RuntimeError(f"plain batch failed: {st}")
+        g.flush()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    keep = g.tuning
+    sweep = {}
+    probe = calls[: min(len(calls), 3000)]
+    probe_n = sum(c for _, _, c in probe)
+    for nc in (0, 64, 128, 256, 512, 1024, 2048, 1 << 30):
+        g.set_tuning(node_chunk=nc)
+        run(probe[:200])  # warm-up
+        sweep[nc] = probe_n / run(probe)
+    best = max(sweep, key=sweep.get)
+    g.set_tuning(node_chunk=best)
+    dt = run(calls)
+    g.set_tuning(**keep)
+    return {"plain_updates_per_s": stream.N / dt, "plain_launches": len(calls),
+            "plain_gutter_updates": gutter, "plain_ms": dt * 1e3, "plain_node_chunk": best,
+            "plain_node_chunk_sweep": {str(k): v for k, v in sweep.items()},
+            "plain_one_workgroup_updates_per_s": sweep[1 << 30]}
 
 
 def main() -> int:
@@ -181,16 +281,22 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="rmat_dense")
+    ap.add_argument("--workload", default="rmat_skewed",
+                    help="rmat_skewed (default), rmat_dense, rmat_kron18, uniform_small, "
+                         "many_gnp, serving, rmat_dense_host")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain per-node pass")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--no-autotune", action="store_true", help="keep the library's default launch parameters")
+    ap.add_argument("--cpu-seconds", type=float, default=20.0,
+                    help="CPU oracle budget (split between the single-thread and all-cores legs)")
+    ap.add_argument("--cpu-workers", type=int, default=16,
+                    help="processes of the all-cores CPU leg (capped by the CPUs available)")
     ap.add_argument("--autotune", action="store_true",
-                    help="run the autotuner even where the workload has recorded launch parameters")
+                    help="run the autotuner even where the tuning cache has the shape")
+    ap.add_argument("--tuning-cache-out", default="",
+                    help="also store the launch parameters used in this JSON cache file")
     ap.add_argument("--tuning", default="",
                     help="explicit launch parameters wg_size,lds_rows,chunk,wgs_per_cu,group_blocks "
-                         "(skips the autotuner)")
+                         "(skips the cache and the autotuner)")
     ap.add_argument("--sessions", type=int, default=256, help="serving: number of sessions")
     ap.add_argument("--batches", type=int, default=100, help="serving: batches per session")
     ap.add_argument("--hbm-budget-gb", type=float, default=120.0, help="serving: admission budget")
@@ -208,10 +314,6 @@ def main() -> int:
               "over several GPUs is a documented design, not a built path", file=sys.stderr)
         return 2
 
-    import torch
-
-    assert torch.cuda.is_available(), "no GPU"
-    torch.cuda.set_device(0)
     if args.workload == "many_gnp":
         out = run_many(args)
     elif args.workload == "serving":
@@ -221,7 +323,36 @@ def main() -> int:
     else:
         out = run_single(args)
     print(json.dumps(out), flush=True)
+    import paper_2203_14927_amd as gz
+
+    gz.close_all()  # every handle released while the runtime is up
     return 0
+
+
+def gpu_init():
+    import torch
+
+    assert torch.cuda.is_available(), "no GPU"
+    torch.cuda.set_device(0)
+
+
+def apply_tuning(args, g, src_d, dst_d, kind="single"):
+    """Launch parameters: explicit (--tuning), else the autotuner's cached tuple for this
+    device and shape, else a fresh autotuner run.  Returns the source it came from."""
+    from paper_2203_14927_amd import autotune
+
+    if args.tuning:
+        g.set_tuning(**dict(zip(TUNING_KEYS, (int(x) for x in args.tuning.split(",")))))
+        source = "explicit"
+    else:
+        t0 = time.perf_counter()
+        _, path = autotune.tuned(g, src_d, dst_d, kind=kind, refresh=args.autotune)
+        source = ("gz_autotune (this run, %.1f s)" % (time.perf_counter() - t0)
+                  if path == "gz_autotune" else "autotuner cache " + os.path.relpath(path, ROOT))
+    if args.tuning_cache_out:
+        autotune.save_entry(g, g.tuning, 0.0, len(src_d), args.tuning_cache_out, kind)
+    log(f"[bench] launch parameters {g.tuning} from {source}")
+    return source
 
 
 # PCIe 5.0 x16 host link of the MI355X: 64 GB/s per direction
@@ -230,16 +361,22 @@ PEAK_HOST_LINK_GBS = 64.0
 
 def run_host_tier(args) -> dict:
     """Dense R-MAT with the sketches in pinned host memory (host-DRAM tier)."""
+    stream, seed, desc = make_workload("rmat_dense")
+    gpu_init()
     import torch
 
     import paper_2203_14927_amd as gz
+    from paper_2203_14927_amd import autotune
 
-    stream, seed, desc = make_workload("rmat_dense")
     src_d = torch.from_numpy(stream.src.view("int32")).cuda()
     dst_d = torch.from_numpy(stream.dst.view("int32")).cuda()
     g = gz.Graph(stream.V, seed=seed, host_tier=True, staging_bytes=args.staging_mb << 20)
-    keys = ["wg_size", "lds_rows", "chunk", "wgs_per_cu", "group_blocks"]
-    g.set_tuning(**dict(zip(keys, (int(x) for x in (args.tuning or TUNED["rmat_dense"]).split(",")))))
+    if args.tuning:
+        g.set_tuning(**dict(zip(TUNING_KEYS, (int(x) for x in args.tuning.split(",")))))
+    else:  # the HBM-resident graph of the same shape's tuned tuple, if cached
+        t, _ = autotune.lookup(g)
+        if t:
+            g.set_tuning(**t)
     sketch_bytes = g.storage()[1]
 
     def step():
@@ -290,9 +427,7 @@ def run_host_tier(args) -> dict:
 def run_many(args) -> dict:
     """4096 independent G(n,p) graphs: one captured-plan ingest, then one fused query."""
     import numpy as np
-    import torch
 
-    import paper_2203_14927_amd as gz
     import workloads
 
     t0 = time.perf_counter()
@@ -301,6 +436,12 @@ def run_many(args) -> dict:
     offs = np.zeros(len(streams) + 1, np.uint64)
     offs[1:] = np.cumsum([s.N for s in streams])
     N = int(offs[-1])
+    gpu_init()
+    import torch
+
+    import paper_2203_14927_amd as gz
+    from paper_2203_14927_amd import autotune
+
     src_d = torch.from_numpy(np.concatenate([s.src for s in streams]).view(np.int32)).cuda()
     dst_d = torch.from_numpy(np.concatenate([s.dst for s in streams]).view(np.int32)).cuda()
     log(f"[bench] many G(n,p): {len(streams)} graphs, {N} updates, "
@@ -308,11 +449,24 @@ def run_many(args) -> dict:
     if args.copy_calibration:
         copy_calibration()
     graphs = [gz.Graph(s.V, seed=sd) for s, sd in zip(streams, seeds)]
-    if not args.tuning and not args.no_autotune:
-        args.tuning = TUNED["many_gnp"]
-    if args.tuning:  # a fused launch takes the first graph's launch parameters
-        keys = ["wg_size", "lds_rows", "chunk", "wgs_per_cu", "group_blocks"]
-        graphs[0].set_tuning(**dict(zip(keys, (int(x) for x in args.tuning.split(",")))))
+    # a fused launch takes the first graph's launch parameters: explicit, else the
+    # tuple cached for this workload, else the launch-shape sweep's best (wg 256,
+    # 12 LDS rows, chunk 16384, 8 workgroups per CU)
+    kind = f"many{len(graphs)}"
+    if args.tuning:
+        tuned_from = "explicit"
+    else:
+        t, path = autotune.lookup(graphs[0], kind)
+        if t:
+            graphs[0].set_tuning(**t)
+            tuned_from = "autotuner cache " + os.path.relpath(path, ROOT)
+        else:
+            args.tuning = "256,12,16384,8,0"
+            tuned_from = "launch-shape sweep"
+    if args.tuning:
+        graphs[0].set_tuning(**dict(zip(TUNING_KEYS, (int(x) for x in args.tuning.split(",")))))
+    if args.tuning_cache_out:
+        autotune.save_entry(graphs[0], graphs[0].tuning, 0.0, N, args.tuning_cache_out, kind)
     sketch_bytes = sum(g.storage()[1] for g in graphs)
     plan = gz.Plan(graphs, [s.N for s in streams])
     stream_t = torch.cuda.current_stream()
@@ -349,12 +503,20 @@ def run_many(args) -> dict:
     ims = statistics.median(ingest_ms)
     log(f"[bench] {args.steps} steps, {ms:.2f} ms/step (ingest {ims:.2f} ms), "
         f"components={int(ncc.sum())}, failures={int((stt != 0).sum())}")
-    # HBM roof of the fused ingest: every touched node tile is read and written
-    # once, plus the stream reads of grouping and update
-    touched = 12.0 * sum(g.B * g.R * g.C * s.V for g, s in zip(graphs, streams))
-    algo_bytes = 2.0 * touched + 40.0 * N
-    achieved = algo_bytes / (ims * 1e-3) / 1e9
     plan.close()
+    # the update kernel alone, timed with HIP events on its stream by the library:
+    # eager fused calls with the launch sequence the plan captured
+    graphs[0].profile(True)
+    upd = []
+    for _ in range(3):
+        reset_all()
+        gz.ingest_multi(graphs, offs, src_d, dst_d, flags=gz.GZ_ASYNC)
+        upd.append(graphs[0].last_profile()["update_ms"])
+    graphs[0].profile(False)
+    upd_ms = statistics.median(upd)
+    tune = graphs[0].tuning
+    moved = update_bytes_many(graphs, streams, tune["lds_rows"], tune["chunk"])
+    achieved = moved["bytes"] / (upd_ms * 1e-3) / 1e9
     return {
         "metric": "edge updates/sec ingested (1 MI355X), batched vs plain; CC query ms; p99 latency",
         "value": N / (ms * 1e-3), "unit": "updates/s", "n_gpus": 1, "steps": args.steps,
@@ -365,12 +527,48 @@ def run_many(args) -> dict:
                    "graphs": len(streams), "updates": N, "sketch_bytes": sketch_bytes,
                    "step": "captured-plan ingest + connected components of every graph"},
         "ingest_updates_per_s": N / (ims * 1e-3), "ingest_ms": ims,
-        "cc_query_ms": ms - ims,
+        "cc_query_ms": ms - ims, "update_kernel_ms": upd_ms,
+        "tuning": tune, "tuning_source": tuned_from,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": achieved / PEAK_HBM_GBS, "traffic": None,
-                     "kernel": "captured ingest sequence",
-                     "bytes_rule": "2 x node sketch bytes (read + write) + 40 B per update"},
+                     "kernel": "k_update", "bytes_per_launch": moved["bytes"],
+                     "bytes_rule": "per work item: 4 B per entry read, the rows d < DL of its "
+                                   "node tile read and written (3 planes x DL x R x C x 4 B "
+                                   "each way, DL as the kernel picks it from the item's size), "
+                                   "24 B per expected entry-pair deeper than DL (HBM atomics), "
+                                   "24 B of item record"},
     }
+
+
+def update_bytes_many(graphs, streams, lds_rows: int, chunk: int) -> dict:
+    """Bytes the update kernel must move for one fused ingest of these streams.
+
+    Work items are a node's entries cut into pieces of at most `chunk`; an
+    item of `count` entries keeps rows d < DL in LDS, DL = min(bitlen(count) +
+    3, lds_rows) (every row, up to lds_rows, when that reaches B or the item
+    has at least 16 entries per extra row), and reads and writes those rows of
+    its node; entries deeper than DL (probability 2^-DL per pair) are applied
+    to HBM with atomics.
+    """
+    import numpy as np
+
+    total = 0.0
+    deep = 0.0
+    items = 0
+    for g, s in zip(graphs, streams):
+        deg = np.bincount(s.src, minlength=g.V) + np.bincount(s.dst, minlength=g.V)
+        deg = deg[deg > 0].astype(np.int64)
+        P = g.R * g.C
+        full, rem = deg // chunk, deg % chunk
+        counts = np.concatenate([np.full(int(full.sum()), chunk, np.int64), rem[rem > 0]])
+        need = np.floor(np.log2(counts)).astype(np.int64) + 1 + 3
+        all_rows = (need >= g.B) | ((g.B <= lds_rows) & (counts >= 16 * (g.B - need)))
+        DL = np.where(all_rows, min(g.B, lds_rows), np.minimum(need, lds_rows))
+        total += float((4 * counts + 24 * DL * P + 24).sum())
+        d = (counts * P * np.exp2(-DL.astype(np.float64)) * (DL < g.B)).sum()
+        deep += float(d)
+        items += len(counts)
+    return {"bytes": total + 24.0 * deep, "items": items, "deep_entry_pairs": deep}
 
 
 def _gen_session(arg):
@@ -488,32 +686,30 @@ def run_serving(args) -> dict:
 
 def run_single(args) -> dict:
     import numpy as np
-    import torch
-
-    import paper_2203_14927_amd as gz
 
     t0 = time.perf_counter()
     stream, seed, desc = make_workload(args.workload)
     log(f"[bench] workload {args.workload}: V={stream.V} N={stream.N} "
         f"(generated in {time.perf_counter() - t0:.1f} s)")
+    cpu = None
+    if not args.no_cpu:
+        # before the GPU is initialised: the all-cores leg forks its workers
+        log("[bench] timing the CPU oracle on a bounded sample ...")
+        cpu = cpu_baseline(stream, seed, args.cpu_seconds, args.cpu_workers)
+        log(f"[bench] CPU oracle: {cpu['single_thread']['value'] / 1e6:.3f} M updates/s on one "
+            f"thread, {cpu['value'] / 1e6:.3f} M updates/s on {cpu['cores']} processes")
+
+    gpu_init()
+    import torch
+
+    import paper_2203_14927_amd as gz
+
     src_d = torch.from_numpy(stream.src.view(np.int32)).cuda()
     dst_d = torch.from_numpy(stream.dst.view(np.int32)).cuda()
     if args.copy_calibration:
         copy_calibration()
     g = gz.Graph(stream.V, seed=seed)
-    tune_ms = None
-    if not args.tuning and not args.autotune and not args.no_autotune:
-        args.tuning = TUNED.get(args.workload, "")
-    tuned_from = "explicit" if args.tuning else ("autotuner" if not args.no_autotune else "default")
-    if args.tuning:
-        keys = ["wg_size", "lds_rows", "chunk", "wgs_per_cu", "group_blocks"]
-        g.set_tuning(**dict(zip(keys, (int(x) for x in args.tuning.split(",")))))
-        args.no_autotune = True
-    if not args.no_autotune:
-        t0 = time.perf_counter()
-        best, tune_ms = g.autotune(src_d, dst_d)
-        log(f"[bench] autotuned in {time.perf_counter() - t0:.1f} s: {best} "
-            f"({tune_ms:.2f} ms per ingest)")
+    tuned_from = apply_tuning(args, g, src_d, dst_d)
     g.profile(True)
     torch.cuda.synchronize()
 
@@ -598,16 +794,16 @@ def run_single(args) -> dict:
                                  f"{P} pairs per update"},
     }
     if not args.no_plain:
-        rate, calls, gutter, pms = plain_pass(gz, g, stream, src_d, dst_d)
-        out["plain_updates_per_s"] = rate
-        out["plain_launches"] = calls
-        out["plain_gutter_updates"] = gutter
-        out["plain_ms"] = pms
-        out["batched_vs_plain"] = out["ingest_updates_per_s"] / rate
-        log(f"[bench] plain: {calls} launches, {pms:.1f} ms, {rate / 1e6:.1f} M updates/s")
-    if not args.no_cpu:
-        log("[bench] timing the CPU oracle on a bounded sample ...")
-        out["cpu_baseline"] = cpu_baseline(stream, seed, args.cpu_seconds)
+        plain = plain_pass(gz, g, stream, src_d, dst_d)
+        out.update(plain)
+        out["batched_vs_plain"] = out["ingest_updates_per_s"] / plain["plain_updates_per_s"]
+        log(f"[bench] plain: {plain['plain_launches']} launches, {plain['plain_ms']:.1f} ms, "
+            f"{plain['plain_updates_per_s'] / 1e6:.1f} M updates/s (node_chunk "
+            f"{plain['plain_node_chunk']}; one workgroup per gutter: "
+            f"{plain['plain_one_workgroup_updates_per_s'] / 1e6:.1f} M updates/s)")
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
+    g.close()
     return out
 
 

@@ -3,7 +3,7 @@
  *
  * The library keeps, for every node of a graph, one CubeSketch per Boruvka
  * round (GraphZeppelin, Tench et al. SIGMOD 2022: Sec. 2.2 for the node
- * sketches, Sec. 3.2 / Fig. "cube_code" for CubeSketch), resident in HBM, and
+ * sketches, Sec. 3.1 / Fig. "cube_code" for CubeSketch), resident in HBM, and
  * answers the streaming connected-components problem of Sec. 2.1: given an
  * insert/delete edge stream, return a spanning forest (and the component of
  * every node).
@@ -15,7 +15,7 @@
  *   - a gz_graph handle may not be used from two host threads at once;
  *   - node ids are uint32 in [0, V); an update (u, v) needs u != v;
  *   - the sketch of a stream depends only on the set of pairs that occur an
- *     odd number of times (vectors over Z2, Sec. 3.2), so insertions and
+ *     odd number of times (vectors over Z2, Sec. 3.1), so insertions and
  *     deletions are the same operation and their order does not matter;
  *   - stream arguments are hipStream_t values (0 = the null stream);
  *   - flags: GZ_DEVICE_PTR says that the array arguments point to device
@@ -41,7 +41,7 @@
  *   query   a bucket is EMPTY if alpha = gamma = 0, GOOD if not EMPTY, alpha < n
  *           and gamma = checksum(alpha), else BAD; a sketch is queried column by
  *           column, rows ascending, and yields the first GOOD alpha, else ZERO
- *           when every bucket is EMPTY, else FAIL (Sec. 3.2, result rule after
+ *           when every bucket is EMPTY, else FAIL (Sec. 3.1, result rule after
  *           Eq. (1)-(2)).
  *
  * Wide graphs (65536 < V <= 2^24): n reaches 2^47, so indices are 64-bit and a
@@ -117,12 +117,16 @@ typedef struct gz_tuning {
     uint32_t chunk;       /* max updates of one node per work item (gutter split threshold) */
     uint32_t wgs_per_cu;  /* persistent grid = wgs_per_cu * CUs */
     uint32_t group_blocks;/* workgroups of the grouping passes per call (0 = one per CU) */
+    uint32_t node_chunk;  /* gz_update_sketch_batch: entries per workgroup, the batch spread
+                             over ceil(count / node_chunk) workgroups whose partial tiles
+                             merge by XOR (0 = max(64, ceil(count / CUs)): the batch fills
+                             the chip) */
 } gz_tuning;
 
 /* ------------------------------------------------------------------------
  * gz_sketch_init -- create a graph on V nodes with all-zero sketches.
  *   Paper: node sketches of O(log V) CubeSketches, one per Boruvka round
- *   (Sec. 2.2); CubeSketch layout of Sec. 3.2; all-zero start = empty graph.
+ *   (Sec. 2.2); CubeSketch layout of Sec. 3.1; all-zero start = empty graph.
  *   out   receives the handle (library-owned until gz_free);
  *   V     2 .. 2^24 (up to 65536 the index-keyed contract, above it the
  *         pair-keyed one); else GZ_EINVAL;
@@ -150,7 +154,10 @@ gz_status gz_reset(gz_graph* g, hipStream_t stream);
  *   sketch only, in one kernel launch.  This is the per-node batch application
  *   of Sec. 5.1 (a Graph Worker applies a gutter of updates bound for one node
  *   to that node's CubeSketches); the mirror update of every edge must be
- *   submitted to the other endpoint by the caller.
+ *   submitted to the other endpoint by the caller.  The batch is cut into
+ *   pieces of gz_tuning.node_chunk entries, one workgroup each (by default
+ *   enough pieces to occupy every CU); pieces XOR their partial tiles into the
+ *   node's sketch (linearity, Sec. 3.1).
  *   node   the node whose sketch changes (< V);
  *   nbrs   count neighbour ids: edge {node, nbrs[k]} is toggled in node's
  *          sketch; host or device memory (GZ_DEVICE_PTR), borrowed for the
@@ -169,12 +176,16 @@ gz_status gz_update_sketch_batch(gz_graph* g, uint32_t node, const uint32_t* nbr
  *   (the role of the gutters of Sec. 4-5).
  *   src, dst  N node ids each, host or device memory (GZ_DEVICE_PTR);
  *             device inputs must stay valid until the stream reaches the call;
+ *   op        nullable, never read: the insert/delete flag of each update
+ *             (Delta = +1 / -1 of Sec. 2.1).  Over Z2 an insertion and a
+ *             deletion are the same toggle (Sec. 3.1), so the sketches do not
+ *             depend on it; the argument keeps the stream record's shape;
  *   N         < 2^31 per call.
  *   Errors: GZ_EINVAL if any src[k] == dst[k] or an id >= V (nothing applied).
  *   Returns after enqueueing (GZ_ASYNC) or after the validation check.
  * ---------------------------------------------------------------------- */
-gz_status gz_ingest(gz_graph* g, const uint32_t* src, const uint32_t* dst, uint64_t N,
-                    uint32_t flags, hipStream_t stream);
+gz_status gz_ingest(gz_graph* g, const uint32_t* src, const uint32_t* dst, const uint8_t* op,
+                    uint64_t N, uint32_t flags, hipStream_t stream);
 
 /* ------------------------------------------------------------------------
  * gz_ingest_multi -- gz_ingest over G independent graphs in one fused
@@ -183,6 +194,8 @@ gz_status gz_ingest(gz_graph* g, const uint32_t* src, const uint32_t* dst, uint6
  *   non-decreasing); src/dst as in gz_ingest.  The result equals G separate
  *   gz_ingest calls.  The graphs must be distinct and on the current device,
  *   and all of one contract (all V <= 65536 or all V > 65536; else GZ_EINVAL).
+ *   Calls share one scratch area per device; a call on one stream waits on
+ *   the device for the previous call's kernels, whatever stream those ran on.
  * ---------------------------------------------------------------------- */
 gz_status gz_ingest_multi(gz_graph* const* gs, uint32_t G, const uint64_t* offs,
                           const uint32_t* src, const uint32_t* dst, uint32_t flags,
@@ -213,7 +226,10 @@ gz_status gz_plan_free(gz_plan* p);
 /* ------------------------------------------------------------------------
  * gz_flush -- the paper's cleanup() step (Sec. 5.2): wait until every update
  *   submitted to g has been applied.  Returns GZ_EINVAL if an asynchronous
- *   call on g carried an invalid update since the last flush.
+ *   call that included g (alone, in a gz_ingest_multi call or in a plan
+ *   replay) carried an invalid update since g's last flush; such a call
+ *   applies nothing to any of its graphs, and each of them reports it at its
+ *   own next flush.
  * ---------------------------------------------------------------------- */
 gz_status gz_flush(gz_graph* g);
 

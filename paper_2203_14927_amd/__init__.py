@@ -10,8 +10,10 @@ handle for convenience.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
+import weakref
 
 import numpy as np
 
@@ -43,7 +45,7 @@ GZ_TIER_HOST = 1
 class gz_tuning(ctypes.Structure):
     _fields_ = [("wg_size", ctypes.c_uint32), ("lds_rows", ctypes.c_uint32),
                 ("chunk", ctypes.c_uint32), ("wgs_per_cu", ctypes.c_uint32),
-                ("group_blocks", ctypes.c_uint32)]
+                ("group_blocks", ctypes.c_uint32), ("node_chunk", ctypes.c_uint32)]
 
     def as_dict(self):
         return {f: int(getattr(self, f)) for f, _ in self._fields_}
@@ -66,8 +68,8 @@ _SIGS = {
     "gz_reset": ([ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int32),
     "gz_update_sketch_batch": ([ctypes.c_void_p, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_uint64,
                                 ctypes.c_uint32, ctypes.c_void_p], ctypes.c_int32),
-    "gz_ingest": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64,
-                   ctypes.c_uint32, ctypes.c_void_p], ctypes.c_int32),
+    "gz_ingest": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                   ctypes.c_uint64, ctypes.c_uint32, ctypes.c_void_p], ctypes.c_int32),
     "gz_ingest_multi": ([ctypes.POINTER(ctypes.c_void_p), ctypes.c_uint32,
                          ctypes.POINTER(ctypes.c_uint64), ctypes.c_void_p, ctypes.c_void_p,
                          ctypes.c_uint32, ctypes.c_void_p], ctypes.c_int32),
@@ -131,6 +133,29 @@ def _extend_server(L):
     _srv._declare(L)
 
 
+# Handles still open when the interpreter exits are released by an exit hook,
+# in dependency order (servers, then plans, then graphs), while the HIP runtime
+# is still up: the library never frees device memory from static destructors.
+_live = {"server": weakref.WeakSet(), "plan": weakref.WeakSet(), "graph": weakref.WeakSet()}
+
+
+def _track(kind, obj):
+    _live[kind].add(obj)
+
+
+def close_all():
+    """Release every server, plan and graph this process still holds."""
+    for kind in ("server", "plan", "graph"):
+        for obj in list(_live[kind]):
+            try:
+                obj.close()
+            except Exception:
+                pass
+
+
+atexit.register(close_all)
+
+
 def _status_name(s: int) -> str:
     try:
         return lib().gz_status_str(s).decode()
@@ -190,6 +215,7 @@ class Graph:
         cfg = gz_config(rounds, GZ_TIER_HOST if host_tier else GZ_TIER_HBM, int(staging_bytes))
         check(L.gz_sketch_init(ctypes.byref(h), V, seed & 0xFFFFFFFFFFFFFFFF, ctypes.byref(cfg)))
         self._h = h
+        _track("graph", self)
         self.seed = seed
         dims = [ctypes.c_uint32() for _ in range(4)]
         n = ctypes.c_uint64()
@@ -213,7 +239,9 @@ class Graph:
             pass
 
     # ingestion ---------------------------------------------------------
-    def ingest(self, src, dst, flags: int = 0, stream=None):
+    def ingest(self, src, dst, flags: int = 0, stream=None, op=None):
+        """op: optional per-update insert/delete flags (uint8, same memory as src); the
+        library never reads them (insertions and deletions are the same toggle)."""
         ps, fs, ks = _u32_arg(src)
         pd, fd, kd = _u32_arg(dst)
         if fs != fd:
@@ -221,7 +249,17 @@ class Graph:
         n = len(ks)
         if len(kd) != n:
             raise ValueError("src and dst lengths differ")
-        return check(lib().gz_ingest(self._h, ps, pd, n, fs | flags, _stream_handle(stream)))
+        pop, kop = None, None
+        if op is not None:
+            if len(op) != n:
+                raise ValueError("op length differs from src")
+            if _is_torch(op):
+                kop = op
+                pop = ctypes.c_void_p(op.data_ptr())
+            else:
+                kop = np.ascontiguousarray(op, np.uint8)
+                pop = ctypes.c_void_p(kop.ctypes.data)
+        return check(lib().gz_ingest(self._h, ps, pd, pop, n, fs | flags, _stream_handle(stream)))
 
     def update_sketch_batch(self, node: int, nbrs, flags: int = 0, stream=None):
         p, f, k = _u32_arg(nbrs)
@@ -379,6 +417,7 @@ class Plan:
                                    c.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
                                    _stream_handle(stream), ctypes.byref(h)))
         self._h = h
+        _track("plan", self)
 
     def ingest(self, offs, src, dst, flags: int = 0, stream=None):
         ps, fs, ks = _u32_arg(src)

@@ -53,6 +53,78 @@ hipError_t query_stream(gz_graph* g, hipStream_t* out) {
     return hipSuccess;
 }
 
+// Error words of graphs live in pinned, coherent host memory that kernels write
+// directly, so that gz_flush reads a graph's word without a device copy (a
+// flush over thousands of graphs of one fused call then costs no transfers).
+// Slabs of kErrSlab words are taken per device on demand; a slab is released
+// when its last graph is freed.  The registry itself is never destroyed, so no
+// HIP call runs from a static destructor at exit.
+namespace {
+constexpr uint32_t kErrSlab = 1024;
+struct ErrSlab {
+    int device;
+    uint32_t* host;
+    uint32_t* dev;
+    std::vector<uint32_t> free_slots;
+};
+std::mutex& err_mutex() {
+    static std::mutex* m = new std::mutex();
+    return *m;
+}
+std::vector<ErrSlab*>& err_slabs() {
+    static std::vector<ErrSlab*>* v = new std::vector<ErrSlab*>();
+    return *v;
+}
+}  // namespace
+
+hipError_t err_word_take(gz_graph* g) {
+    std::lock_guard<std::mutex> lk(err_mutex());
+    ErrSlab* slab = nullptr;
+    for (ErrSlab* s : err_slabs())
+        if (s->device == g->device && !s->free_slots.empty()) {
+            slab = s;
+            break;
+        }
+    if (!slab) {
+        uint32_t* host = nullptr;
+        hipError_t e = hipHostMalloc((void**)&host, kErrSlab * 4,
+                                     hipHostMallocMapped | hipHostMallocCoherent);
+        if (e != hipSuccess) return e;
+        uint32_t* dev = nullptr;
+        e = hipHostGetDevicePointer((void**)&dev, host, 0);
+        if (e != hipSuccess) {
+            hipHostFree(host);
+            return e;
+        }
+        std::memset(host, 0, kErrSlab * 4);
+        slab = new ErrSlab{g->device, host, dev, {}};
+        for (uint32_t k = kErrSlab; k-- > 0;) slab->free_slots.push_back(k);
+        err_slabs().push_back(slab);
+    }
+    const uint32_t k = slab->free_slots.back();
+    slab->free_slots.pop_back();
+    slab->host[k] = 0;
+    g->err_slab = slab;
+    g->err_host = slab->host + k;
+    g->err = slab->dev + k;
+    return hipSuccess;
+}
+
+void err_word_release(gz_graph* g) {
+    if (!g->err_slab) return;
+    std::lock_guard<std::mutex> lk(err_mutex());
+    ErrSlab* slab = static_cast<ErrSlab*>(g->err_slab);
+    slab->free_slots.push_back((uint32_t)(g->err_host - slab->host));
+    g->err_slab = nullptr;
+    g->err_host = g->err = nullptr;
+    if (slab->free_slots.size() == kErrSlab) {
+        auto& v = err_slabs();
+        v.erase(std::find(v.begin(), v.end(), slab));
+        hipHostFree(slab->host);
+        delete slab;
+    }
+}
+
 gz_status fail(gz_status s, const std::string& msg) {
     g_last_error = msg;
     return s;
@@ -126,6 +198,7 @@ gz_tuning default_tuning(uint32_t P, uint32_t B, bool wide) {
     const uint32_t smem = (uint32_t)update_smem_bytes(t.lds_rows, B, P, wide);
     t.wgs_per_cu = std::max<uint32_t>(1, std::min<uint32_t>(8, (160 * 1024) / smem));
     t.group_blocks = 0;
+    t.node_chunk = 0;
     return t;
 }
 
@@ -264,12 +337,14 @@ gz_status init_graph(gz_graph** out, uint32_t V, uint64_t seed, const gz_config*
     }
     e = hipMalloc((void**)&g->seeds, soa.size() * 4);
     if (e == hipSuccess) e = hipMemcpy(g->seeds, soa.data(), soa.size() * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = err_word_take(g);
     if (e == hipSuccess && g->sk) e = hipMemset(g->sk, 0, g->sk_words * 4);
     if (e == hipSuccess && tier == GZ_TIER_HOST) {
         const gz_status ts = tier_create(g, cfg->staging_bytes);
         if (ts != GZ_OK) {
             tier_free(g);
             hipFree(g->seeds);
+            err_word_release(g);
             delete g;
             return ts;
         }
@@ -281,6 +356,7 @@ gz_status init_graph(gz_graph** out, uint32_t V, uint64_t seed, const gz_config*
         tier_free(g);
         hipFree(g->sk);
         hipFree(g->seeds);
+        err_word_release(g);
         delete g;
         return s;
     }
@@ -308,6 +384,7 @@ gz_status gz_free(gz_graph* g) {
     tier_free(g);
     hipFree(g->sk);
     hipFree(g->seeds);
+    err_word_release(g);
     for (hipEvent_t e : g->prof_ev)
         if (e) hipEventDestroy(e);
     if (g->qstream) hipStreamDestroy(g->qstream);
@@ -366,8 +443,9 @@ gz_status gz_update_sketch_batch(gz_graph* g, uint32_t node, const uint32_t* nbr
     return update_node_batch(g, node, nbrs, count, flags, stream);
 }
 
-gz_status gz_ingest(gz_graph* g, const uint32_t* src, const uint32_t* dst, uint64_t N,
-                    uint32_t flags, hipStream_t stream) {
+gz_status gz_ingest(gz_graph* g, const uint32_t* src, const uint32_t* dst, const uint8_t* op,
+                    uint64_t N, uint32_t flags, hipStream_t stream) {
+    (void)op;  // Z2 toggles: an insertion and a deletion are the same update
     if (!g) return fail(GZ_EINVAL, "null graph");
     if (N == 0) return GZ_OK;
     gz_graph* gs[1] = {g};
@@ -390,22 +468,14 @@ gz_status gz_flush(gz_graph* g) {
     if (!g) return fail(GZ_EINVAL, "null graph");
     GZ_HIP(hipEventSynchronize(g->last->ev));
     if (g->pending_error) {
+        // the graph's own word: set by every asynchronous call that included g
+        // and met an invalid update, whichever graphs it also held
         g->pending_error = false;
-        uint32_t sticky = 0;
-        uint32_t* ctls[2] = {g->ing.ctl, nullptr};
-        std::unique_lock<std::mutex> lock;
-        IngestScratch& shared = shared_ingest_scratch(g->device, lock);
-        ctls[1] = shared.ctl;
-        for (uint32_t* c : ctls) {
-            if (!c) continue;
-            uint32_t v = 0;
-            GZ_HIP(hipMemcpy(&v, c + 3, 4, hipMemcpyDeviceToHost));
-            if (v) {
-                sticky = 1;
-                GZ_HIP(hipMemset(c + 3, 0, 4));
-            }
+        volatile uint32_t* w = g->err_host;  // written by the device, complete after the wait
+        if (*w) {
+            *w = 0;
+            return fail(GZ_EINVAL, "an asynchronous update batch was invalid and skipped");
         }
-        if (sticky) return fail(GZ_EINVAL, "an asynchronous update batch was invalid and skipped");
     }
     return GZ_OK;
 }
@@ -486,6 +556,7 @@ gz_status gz_set_tuning(gz_graph* g, const gz_tuning* t) {
     if (t->lds_rows < 1) return fail(GZ_EINVAL, "lds_rows must be >= 1");
     if (t->chunk < 1 || t->chunk > (1u << 30)) return fail(GZ_EINVAL, "chunk must be in [1, 2^30]");
     if (t->wgs_per_cu < 1 || t->wgs_per_cu > 64) return fail(GZ_EINVAL, "wgs_per_cu in [1, 64]");
+    if (t->node_chunk > (1u << 30)) return fail(GZ_EINVAL, "node_chunk must be in [0, 2^30]");
     size_t smem = update_smem_bytes(t->lds_rows, g->B, g->P, g->wide);
     if (smem > 160 * 1024) return fail(GZ_EINVAL, "LDS tile exceeds 160 KiB");
     g->tuning = *t;

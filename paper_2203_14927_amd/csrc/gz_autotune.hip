@@ -75,7 +75,7 @@ extern "C" gz_status gz_autotune(gz_graph* g, const uint32_t* src, const uint32_
             float bestc = 1e30f;
             for (int rep = 0; rep < 2 && !st; ++rep) {
                 gz_profile pr{};
-                st = gz_ingest(t, src, dst, N, GZ_DEVICE_PTR | GZ_ASYNC, stream);
+                st = gz_ingest(t, src, dst, nullptr, N, GZ_DEVICE_PTR | GZ_ASYNC, stream);
                 if (!st) st = gz_profile_last(t, &pr);
                 if (!st) bestc = std::min(bestc, pr.ingest_ms);
             }
@@ -105,7 +105,7 @@ extern "C" gz_status gz_autotune(gz_graph* g, const uint32_t* src, const uint32_
             float bc = 1e30f;
             for (int rep = 0; rep < 2 && !st; ++rep) {
                 gz_profile pr{};
-                st = gz_ingest(t, src, dst, N, GZ_DEVICE_PTR | GZ_ASYNC, stream);
+                st = gz_ingest(t, src, dst, nullptr, N, GZ_DEVICE_PTR | GZ_ASYNC, stream);
                 if (!st) st = gz_profile_last(t, &pr);
                 if (!st) bc = std::min(bc, pr.ingest_ms);
             }

@@ -1,7 +1,7 @@
 // Ingest path: group the stream by endpoint on the device, then apply each
 // node's batch to its CubeSketches with the node tile staged in LDS.
 //
-// Paper: CubeSketch update (Sec. 3.2, Fig. "cube_code"); per-node batching of
+// Paper: CubeSketch update (Sec. 3.1, Fig. "cube_code"); per-node batching of
 // updates so that one node's sketch is touched once per batch (Sec. 4.1, 5.1);
 // batch- and sketch-level parallelism (Sec. 5.1) become workgroups over node
 // batches and lanes over (round, column) pairs.
@@ -24,6 +24,19 @@ __global__ void k_fill_u32(uint32_t* __restrict__ p, uint64_t n, uint32_t v) {
     uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (; i < n; i += stride) p[i] = v;
+}
+
+__global__ void k_note_error(const GraphDesc* __restrict__ descs, uint32_t G,
+                             const uint32_t* __restrict__ call_err) {
+    if (*call_err == 0) return;
+    for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < G; k += gridDim.x * blockDim.x)
+        *descs[k].err = 1u;
+}
+
+// the same for the one graph of a per-node call
+__global__ void k_note_error_one(uint32_t* __restrict__ graph_err,
+                                 const uint32_t* __restrict__ call_err) {
+    if (threadIdx.x == 0 && *call_err) *graph_err = 1u;
 }
 
 // last graph g with node_base <= node
@@ -68,7 +81,7 @@ __device__ __forceinline__ UnitRange unit_range(const IngestArgs* __restrict__ a
 constexpr uint32_t kCountBatch = 4;  // updates loaded per thread before counting any
 
 // pass 1: LDS histogram of one chunk's endpoints; validation of the updates
-// (ctl[2]: this call saw an invalid update; ctl[3]: sticky error for gz_flush)
+// (ctl[2]: this call saw an invalid update)
 __global__ __launch_bounds__(kGroupThreads) void k_group_count(
     const IngestArgs* __restrict__ a, const GroupUnit* __restrict__ units,
     const GraphDesc* __restrict__ gd, uint32_t* __restrict__ H, uint32_t* __restrict__ ctl) {
@@ -103,10 +116,7 @@ __global__ __launch_bounds__(kGroupThreads) void k_group_count(
             if (yo < r.size) atomicAdd(&hist[yo], 1u);
         }
     }
-    if (bad && u.q == 0) {
-        atomicOr(&ctl[2], 1u);
-        atomicOr(&ctl[3], 1u);
-    }
+    if (bad && u.q == 0) atomicOr(&ctl[2], 1u);
     __syncthreads();
     uint32_t* out = H + g.hoff + (uint64_t)u.c * g.V + r.lo;
     for (uint32_t k = threadIdx.x; k < r.size; k += blockDim.x) out[k] = hist[k];
@@ -471,10 +481,7 @@ __global__ __launch_bounds__(kGroupThreads) void k_group_bcount(
             atomicAdd(&hist[y[k] >> S], 1u);
         }
     }
-    if (bad) {
-        atomicOr(&ctl[2], 1u);
-        atomicOr(&ctl[3], 1u);
-    }
+    if (bad) atomicOr(&ctl[2], 1u);
     __syncthreads();
     for (uint32_t k = threadIdx.x; k < nbk; k += blockDim.x) Hb[blockIdx.x * nbk + k] = hist[k];
 }
@@ -898,6 +905,8 @@ gz_status ensure_scratch(IngestScratch& S, uint64_t N, uint32_t T, uint32_t G, u
         GZ_HIP(hipMalloc((void**)&S.args, sizeof(IngestArgs)));
         GZ_HIP(hipEventCreateWithFlags(&S.copied_ev, hipEventDisableTiming));
         GZ_HIP(hipEventRecord(S.copied_ev, 0));
+        GZ_HIP(hipEventCreateWithFlags(&S.done_ev, hipEventDisableTiming));
+        GZ_HIP(hipEventRecord(S.done_ev, 0));
         GZ_TRY(grow_host(&S.h_args, 1));
         GZ_TRY(grow_host(&S.h_err, 4));
     }
@@ -963,10 +972,11 @@ void free_ingest_scratch(IngestScratch& S) {
     hipFree(S.packed); hipFree(S.block_sums); hipFree(S.cursor);
     hipFree(S.grouped); hipFree(S.items); hipFree(S.ctl); hipFree(S.args); hipFree(S.offs);
     hipFree(S.descs); hipFree(S.staging); hipFree(S.buckets); hipFree(S.bbase);
-    if (S.copied_ev) {
-        hipEventSynchronize(S.copied_ev);
-        hipEventDestroy(S.copied_ev);
-    }
+    for (hipEvent_t ev : {S.copied_ev, S.done_ev})
+        if (ev) {
+            hipEventSynchronize(ev);
+            hipEventDestroy(ev);
+        }
     hipHostFree(S.h_args); hipHostFree(S.h_descs); hipHostFree(S.h_offs); hipHostFree(S.h_err);
     hipHostFree(S.h_units);
     S = IngestScratch{};
@@ -1042,6 +1052,7 @@ gz_status build_shape(gz_graph* const* gs, uint32_t G, const uint64_t* ranges, u
         d.node_words = g->planes * g->B * g->P;
         d.wide = g->wide;
         d.planes = g->planes;
+        d.err = g->err;
         d.upd_base = b;
         d.nb = (uint32_t)((e - b + L.group_chunk - 1) / L.group_chunk);
         d.hoff = L.H_size;
@@ -1222,12 +1233,16 @@ gz_status upload_args(IngestScratch& S, const LaunchShape& L, const uint32_t* sr
 gz_status check_call_error(IngestScratch& S, hipStream_t stream) {
     GZ_HIP(hipMemcpyAsync(S.h_err, S.ctl + 2, 4, hipMemcpyDeviceToHost, stream));
     GZ_HIP(hipStreamSynchronize(stream));
-    if (S.h_err[0]) {
-        // the sticky flag is for asynchronous callers; this one is reported now
-        k_fill_u32<<<1, 64, 0, stream>>>(S.ctl + 3, 1, 0);
-        GZ_HIP(hipStreamSynchronize(stream));
-        return fail(GZ_EINVAL, "invalid update (self-loop or node id out of range)");
-    }
+    if (S.h_err[0]) return fail(GZ_EINVAL, "invalid update (self-loop or node id out of range)");
+    return GZ_OK;
+}
+
+// An asynchronous call reports an invalid update at each of its graphs' next
+// flush: the call's error word is copied into every graph's own word.
+gz_status note_async_error(IngestScratch& S, gz_graph* const* gs, uint32_t G, hipStream_t stream) {
+    k_note_error<<<(G + 255) / 256, 256, 0, stream>>>(S.descs, G, S.ctl + 2);
+    GZ_HIP(hipGetLastError());
+    for (uint32_t k = 0; k < G; ++k) gs[k]->pending_error = true;  // flush must check
     return GZ_OK;
 }
 
@@ -1261,8 +1276,11 @@ gz_status ingest_fused(gz_graph* const* gs, uint32_t G, const uint64_t* offs_hos
                           L.two_pass || L.wide ? 2 * N : 0,
                           L.two_pass ? (uint64_t)(L.nbc + 1) * L.nbk + 1 + 3ull * L.pcap : 0));
 
-    // order after earlier work on these graphs (e.g. a query on another stream)
+    // order after earlier work on these graphs (e.g. a query on another stream),
+    // and after the kernels of the previous call that used this scratch, on
+    // whatever stream it ran
     GZ_HIP(fence_wait(stream, gs, G));
+    GZ_HIP(hipStreamWaitEvent(stream, S.done_ev, 0));
 
     const uint32_t* dsrc = src;
     const uint32_t* ddst = dst;
@@ -1276,10 +1294,10 @@ gz_status ingest_fused(gz_graph* const* gs, uint32_t G, const uint64_t* offs_hos
     GZ_TRY(upload_shape(S, L, stream));
     GZ_HIP(hipEventRecord(S.copied_ev, stream));
     GZ_TRY(launch_sequence(S, L, stream, gs[0]->profiling ? gs[0] : nullptr));
+    if (flags & GZ_ASYNC) GZ_TRY(note_async_error(S, gs, G, stream));
+    GZ_HIP(hipEventRecord(S.done_ev, stream));
     GZ_HIP(fence_record(stream, gs, G));
-
     if (!(flags & GZ_ASYNC)) return check_call_error(S, stream);
-    for (uint32_t k = 0; k < G; ++k) gs[k]->pending_error = true;  // flush must check
     return GZ_OK;
 }
 
@@ -1343,7 +1361,7 @@ gz_status update_node_batch(gz_graph* g, uint32_t node, const uint32_t* nbrs, ui
         GZ_HIP(hipMemcpyAsync(S.staging, nbrs, count * 4, hipMemcpyHostToDevice, stream));
         d = S.staging;
     }
-    // ctl[2] / ctl[3]: call error / sticky error, as in the fused path
+    // ctl[2]: the call's error word, as in the fused path
     const bool check = !(flags & GZ_UNCHECKED);
     if (check) k_fill_u32<<<1, 64, 0, stream>>>(S.ctl + 2, 1, 0);
     if (!host_ptr && check)
@@ -1365,7 +1383,14 @@ gz_status update_node_batch(gz_graph* g, uint32_t node, const uint32_t* nbrs, ui
         gd.node_words = g->planes * g->B * g->P;
         gd.wide = g->wide;
         gd.planes = g->planes;
-        const uint32_t chunk = tune.chunk;
+        gd.err = g->err;
+        // pieces of node_chunk entries, one workgroup each; by default the
+        // batch is spread over about one workgroup per CU (at least 64 entries
+        // a piece, below which the merge atomics outweigh the entries)
+        const uint64_t cus = (uint64_t)device_cu_count();
+        const uint32_t chunk =
+            tune.node_chunk ? tune.node_chunk
+                            : (uint32_t)std::max<uint64_t>(64, (count + cus - 1) / cus);
         const uint32_t DL = std::min(tune.lds_rows, g->B);
         const size_t smem = update_smem_bytes(tune.lds_rows, g->B, g->P, g->wide);
         const void* fn = g->wide ? (const void*)k_update_node_wide : (const void*)k_update_node;
@@ -1384,12 +1409,10 @@ gz_status update_node_batch(gz_graph* g, uint32_t node, const uint32_t* nbrs, ui
         if (!(flags & GZ_ASYNC)) {
             GZ_HIP(hipMemcpyAsync(S.h_err, S.ctl + 2, 4, hipMemcpyDeviceToHost, stream));
             GZ_HIP(hipStreamSynchronize(stream));
-            if (S.h_err[0]) {
-                k_fill_u32<<<1, 64, 0, stream>>>(S.ctl + 3, 1, 0);
-                GZ_HIP(hipStreamSynchronize(stream));
-                return fail(GZ_EINVAL, "invalid neighbour (self-loop or id out of range)");
-            }
+            if (S.h_err[0]) return fail(GZ_EINVAL, "invalid neighbour (self-loop or id out of range)");
         } else {
+            k_note_error_one<<<1, 64, 0, stream>>>(g->err, S.ctl + 2);
+            GZ_HIP(hipGetLastError());
             g->pending_error = true;
         }
     } else if (host_ptr) {
@@ -1495,9 +1518,9 @@ gz_status gz_plan_ingest(gz_plan* p, const uint64_t* offs, const uint32_t* src, 
                           hipMemcpyHostToDevice, stream));
     GZ_HIP(hipEventRecord(S.copied_ev, stream));
     GZ_HIP(hipGraphLaunch(p->exec, stream));
+    if (flags & GZ_ASYNC) GZ_TRY(note_async_error(S, p->gs.data(), G, stream));
     GZ_HIP(fence_record(stream, p->gs.data(), G));
     if (!(flags & GZ_ASYNC)) return check_call_error(S, stream);
-    for (gz_graph* g : p->gs) g->pending_error = true;
     return GZ_OK;
 }
 

@@ -68,6 +68,8 @@ struct GraphDesc {
     uint32_t planes;     // 3, or 4 when wide
     uint32_t sk_first;   // graph-local node of the first block in sk (a host-tier slab's first
                          // node; 0 when sk holds the whole graph)
+    uint32_t* err;       // the graph's own error word: set when an asynchronous call that
+                         // included the graph met an invalid update (read by gz_flush)
 };
 
 // One unit of work of the persistent sketch-update kernel: up to `chunk`
@@ -127,8 +129,7 @@ struct IngestScratch {
     uint32_t* bbase = nullptr;      // (chunks + 1) x buckets region starts
     uint64_t cap_bbase = 0;
     WorkItem* items = nullptr;
-    uint32_t* ctl = nullptr;        // [0] ticket, [1] n_items, [2] call error, [3] sticky errors,
-                                    // [4..7] always zero
+    uint32_t* ctl = nullptr;        // [0] ticket, [1] n_items, [2] call error, [3..7] always zero
     IngestArgs* args = nullptr;
     uint64_t* offs = nullptr;       // G+1
     GraphDesc* descs = nullptr;     // G
@@ -141,6 +142,7 @@ struct IngestScratch {
     uint64_t* h_offs = nullptr;
     uint32_t cap_h_graphs = 0;
     hipEvent_t copied_ev = nullptr;
+    hipEvent_t done_ev = nullptr;   // end of the last call's kernels that used this scratch
     uint32_t* h_err = nullptr;
 };
 
@@ -199,7 +201,13 @@ struct gz_graph {
     uint64_t seed = 0;
     uint32_t* sk = nullptr;            // device sketch words
     uint64_t sk_words = 0;
-    uint32_t* seeds = nullptr;         // device seeds [12][P]
+    uint32_t* seeds = nullptr;         // device seeds [12][P] (18 words per pair when wide)
+    // error word: set by the device when an asynchronous call that included this
+    // graph met an invalid update; pinned coherent host memory (err is its device
+    // address, err_host its host address), one word of a shared slab
+    uint32_t* err = nullptr;
+    uint32_t* err_host = nullptr;
+    void* err_slab = nullptr;
     std::vector<uint64_t> seeds_host;  // [R][C][3][2]
     gz_tuning tuning{};
     hipStream_t qstream = nullptr;     // query stream
@@ -241,6 +249,8 @@ inline hipError_t fence_record(hipStream_t stream, gz_graph* g) {
     return fence_record(stream, &g, 1);
 }
 hipError_t query_stream(gz_graph* g, hipStream_t* out);
+hipError_t err_word_take(gz_graph* g);
+void err_word_release(gz_graph* g);
 gz_tuning default_tuning(uint32_t P, uint32_t B, bool wide);
 
 // ingest path (gz_ingest.hip)
@@ -249,6 +259,10 @@ gz_status ingest_fused(gz_graph* const* gs, uint32_t G, const uint64_t* offs_hos
                        hipStream_t stream, IngestScratch& S);
 gz_status update_node_batch(gz_graph* g, uint32_t node, const uint32_t* nbrs, uint64_t count,
                             uint32_t flags, hipStream_t stream);
+// after an asynchronous call: if its error word is set, set the error word of
+// every graph of the call (descs: G device descriptors)
+__global__ void k_note_error(const GraphDesc* __restrict__ descs, uint32_t G,
+                             const uint32_t* __restrict__ call_err);
 void free_ingest_scratch(IngestScratch& S);
 
 // dynamic LDS of an update launch, and raising a kernel's LDS limit above 64 KiB

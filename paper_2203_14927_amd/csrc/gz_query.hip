@@ -5,7 +5,7 @@
 // the sketch of every current component, (2) merges components along the
 // recovered edges, (3) sums the merged components' sketches.  Step (3) is done
 // lazily: the next round XOR-reduces the round-r rows of each component's
-// members.  CubeSketch query: Sec. 3.2 and Fig. "cube_code".
+// members.  CubeSketch query: Sec. 3.1 and Fig. "cube_code".
 //
 // Merging is deterministic: the recovered edges form a functional graph over
 // components (out-degree <= 1); its cycles are found by pointer doubling

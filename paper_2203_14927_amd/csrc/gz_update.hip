@@ -1,7 +1,7 @@
 // Sketch update kernels: a node's batch of endpoint entries applied to its
 // CubeSketches with the node tile staged in LDS.
 //
-// Paper: CubeSketch update (Sec. 3.2, Fig. "cube_code", Eq. 1-2); per-node
+// Paper: CubeSketch update (Sec. 3.1, Fig. "cube_code", Eq. 1-2); per-node
 // batching so that one node's sketch is touched once per batch (Sec. 4.1,
 // 5.1); batch- and sketch-level parallelism (Sec. 5.1) become workgroups over
 // node batches and lanes over (round, column) pairs.

@@ -109,6 +109,9 @@ class Server:
         h = ctypes.c_void_p()
         check(lib().gz_server_create(int(hbm_budget), int(tick_updates), ctypes.byref(h)))
         self._h = h
+        from . import _track
+
+        _track("server", self)
 
     def open(self, V: int, seed: int) -> Session:
         return Session(self, V, seed)

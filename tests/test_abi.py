@@ -70,3 +70,50 @@ def test_package_has_no_cpu_fallback():
     for path in glob.glob(os.path.join(pkg, "**", "*.py"), recursive=True):
         src = open(path).read()
         assert "import oracle" not in src and "from oracle" not in src, path
+
+
+def _prototypes():
+    """name -> list of parameter type strings, parsed from include/*.h."""
+    protos = {}
+    for h in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        text = re.sub(r"/\*.*?\*/", "", open(h).read(), flags=re.S)
+        for m in re.finditer(r"(?:gz_status|const\s+char\s*\*|void|uint32_t|int32_t|uint64_t)\s+"
+                             r"\**\s*(gz_\w+)\s*\(([^)]*)\)\s*;", text):
+            params = [p.strip() for p in m.group(2).replace("\n", " ").split(",")]
+            params = [] if params == ["void"] or params == [""] else params
+            protos[m.group(1)] = [re.sub(r"\s+\w+$", "", p) for p in params]
+    return protos
+
+
+def _kind_of_c(t):
+    t = t.replace("const ", "").strip()
+    if "*" in t or t in ("hipStream_t",):
+        return "ptr"
+    return {"uint32_t": "u32", "int32_t": "i32", "uint64_t": "u64", "int": "i32",
+            "gz_status": "i32"}[t]
+
+
+def _kind_of_ctypes(ct):
+    import ctypes
+
+    if ct in (ctypes.c_void_p, ctypes.c_char_p) or hasattr(ct, "_type_") and ct.__name__.startswith("LP_"):
+        return "ptr"
+    return {ctypes.c_uint32: "u32", ctypes.c_int32: "i32", ctypes.c_uint64: "u64",
+            ctypes.c_int: "i32"}[ct]
+
+
+def test_binding_signatures_follow_the_header(libgz):
+    """Every entry point the binding declares has the header's parameter list (count and kinds);
+    in particular gz_ingest takes (g, src, dst, op, N, flags, stream)."""
+    protos = _prototypes()
+    assert protos["gz_ingest"] == ["gz_graph*", "const uint32_t*", "const uint32_t*",
+                                   "const uint8_t*", "uint64_t", "uint32_t", "hipStream_t"]
+    checked = 0
+    for name, proto in protos.items():
+        fn = getattr(libgz, name)
+        if fn.argtypes is None:
+            continue
+        assert len(fn.argtypes) == len(proto), name
+        assert [_kind_of_ctypes(a) for a in fn.argtypes] == [_kind_of_c(p) for p in proto], name
+        checked += 1
+    assert checked >= 30

@@ -1,4 +1,5 @@
-"""Parity at the full workload sizes, in the launch configuration the benchmark times.
+"""Parity at the full workload sizes, in the launch configuration the benchmark times
+(the same tuning source: the autotuner cache, else the autotuner).
 
 The oracle cannot hold every node sketch of these graphs, so it recomputes a
 sample of nodes one by one (only the updates touching them); component labels
@@ -62,11 +63,15 @@ def _check_forest_against_final(V, labels, forest, fu, fv):
 
 
 def _full_single(gz, stream, seed, sample=48):
+    from paper_2203_14927_amd import autotune
+
     t0 = time.time()
     g = gz.Graph(stream.V, seed=seed)
     src, dst = to_dev(stream.src), to_dev(stream.dst)
-    best, ms = g.autotune(src, dst)
-    log(f"  autotuned {best} ({ms:.2f} ms/ingest)")
+    # the benchmark's tuple: the autotuner's cached result for this device and shape,
+    # or a fresh autotuner run when the cache has none
+    best, source = autotune.tuned(g, src, dst)
+    log(f"  launch parameters {best} from {source}")
     g.ingest(src, dst)
     st, labels, ncc, forest = g.query()
     assert st == gz.GZ_OK
@@ -113,6 +118,12 @@ def test_full_many_gnp_plan(gz):
     log(f"many G(n,p): {len(streams)} graphs, {int(offs[-1])} updates "
         f"({time.time() - t0:.1f} s)")
     graphs = [gz.Graph(s.V, seed=sd) for s, sd in zip(streams, seeds)]
+    from paper_2203_14927_amd import autotune
+
+    t, source = autotune.lookup(graphs[0], f"many{len(graphs)}")
+    graphs[0].set_tuning(**(t or dict(wg_size=256, lds_rows=12, chunk=16384, wgs_per_cu=8,
+                                      group_blocks=0)))
+    log(f"  launch parameters {graphs[0].tuning} from {source or 'launch-shape sweep'}")
     plan = gz.Plan(graphs, [s.N for s in streams])
     plan.ingest(offs, to_dev(src), to_dev(dst))
     torch.cuda.synchronize()

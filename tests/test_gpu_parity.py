@@ -287,3 +287,113 @@ def test_two_pass_grouping_edge_shapes(gz, V, n, seed):
     ref, fu, fv = final_labels(s)
     assert (labels == ref).all()
     check_forest_valid(V, labels, forest, fu, fv)
+
+
+@pytest.mark.parametrize("node_chunk", [0, 1, 7, 64, 1 << 30])
+def test_plain_batch_split_over_workgroups(gz, node_chunk):
+    """gz_update_sketch_batch spread over ceil(count / node_chunk) workgroups whose partial
+    tiles merge by XOR equals the oracle, for shallow and full LDS tiles."""
+    s = _stream(300, 20000, 21)
+    O = oracle_for(s, 5)
+    u = np.concatenate([s.src, s.dst])
+    v = np.concatenate([s.dst, s.src])
+    order = np.argsort(u, kind="stable")
+    u, v = u[order], v[order]
+    bounds = np.searchsorted(u, np.arange(301))
+    for lds_rows in (4, 100):
+        g = gz.Graph(300, seed=5)
+        g.set_tuning(node_chunk=node_chunk, lds_rows=min(lds_rows, g.B))
+        for node in range(300):
+            nb = v[bounds[node]:bounds[node + 1]]
+            g.update_sketch_batch(node, to_dev(nb), flags=gz.GZ_ASYNC)
+        g.flush()
+        assert_sketch_equal(g, O)
+        g.close()
+
+
+def test_ingest_op_flags_are_ignored(gz):
+    """The insert/delete flag of an update does not change the sketches (Z2 toggles)."""
+    s = _stream(120, 4000, 22)
+    op = np.random.default_rng(0).integers(0, 2, len(s.src)).astype(np.uint8)
+    O = oracle_for(s, 9)
+    import torch
+
+    for dev in (False, True):
+        g = gz.Graph(120, seed=9)
+        if dev:
+            g.ingest(to_dev(s.src), to_dev(s.dst), op=torch.from_numpy(op).cuda())
+        else:
+            g.ingest(s.src, s.dst, op=op)
+        assert_sketch_equal(g, O)
+        g.close()
+
+
+def test_async_error_reported_by_every_graph_of_the_call(gz):
+    """An invalid update in an asynchronous multi-graph call: every graph of that call fails
+    its next flush (once), nothing is applied, and a graph outside the call stays OK."""
+    V = 40
+    gs = [gz.Graph(V, seed=100 + k) for k in range(3)]
+    good = _stream(V, 300, 23)
+    for g in gs:
+        g.ingest(to_dev(good.src), to_dev(good.dst))
+    before = [g.export() for g in gs]
+    # graph 2 gets a valid asynchronous ingest of its own
+    gs[2].ingest(to_dev(good.src[:10]), to_dev(good.dst[:10]), flags=gz.GZ_ASYNC)
+    src = np.array([1, 2, 3, 3], np.uint32)
+    dst = np.array([5, 6, 3, 7], np.uint32)  # update 2 of graph 1 is a self-loop
+    gz.ingest_multi(gs[:2], [0, 2, 4], to_dev(src), to_dev(dst), flags=gz.GZ_ASYNC)
+    for k in (0, 1):
+        with pytest.raises(gz.GzError) as e:
+            gs[k].flush()
+        assert e.value.status == gz.GZ_EINVAL
+        gs[k].flush()  # reported once
+        a, b = gs[k].export()
+        assert (a == before[k][0]).all() and (b == before[k][1]).all()
+    gs[2].flush()
+    O = oracle_for(good, 102)
+    O.ingest(good.src[:10], good.dst[:10])
+    assert_sketch_equal(gs[2], O)
+    # the same through a plan replay
+    plan = gz.Plan(gs[:2], [4, 4])
+    plan.ingest([0, 2, 4], to_dev(src), to_dev(dst), flags=gz.GZ_ASYNC)
+    for k in (0, 1):
+        with pytest.raises(gz.GzError):
+            gs[k].flush()
+    plan.close()
+    for g in gs:
+        g.close()
+
+
+def test_multi_calls_on_two_streams_share_scratch_safely(gz):
+    """Asynchronous gz_ingest_multi calls on two streams over disjoint graphs reuse one
+    scratch area; the second waits for the first's kernels on the device."""
+    import torch
+
+    sA = [_stream(900, 60000, 30 + k) for k in range(3)]
+    sB = [_stream(700, 400, 40 + k) for k in range(3)]
+    gA = [gz.Graph(900, seed=200 + k) for k in range(3)]
+    gB = [gz.Graph(700, seed=300 + k) for k in range(3)]
+
+    def cat(ss):
+        offs = np.zeros(len(ss) + 1, np.uint64)
+        offs[1:] = np.cumsum([s.N for s in ss])
+        return offs, to_dev(np.concatenate([s.src for s in ss])), \
+            to_dev(np.concatenate([s.dst for s in ss]))
+
+    (oa, a_src, a_dst), (ob, b_src, b_dst) = cat(sA), cat(sB)
+    st1, st2 = torch.cuda.Stream(), torch.cuda.Stream()
+    torch.cuda.synchronize()
+    for rep in range(3):
+        for g in gA + gB:
+            g.reset()
+        torch.cuda.synchronize()
+        gz.ingest_multi(gA, oa, a_src, a_dst, flags=gz.GZ_ASYNC, stream=st1)
+        gz.ingest_multi(gB, ob, b_src, b_dst, flags=gz.GZ_ASYNC, stream=st2)
+        for g in gA + gB:
+            g.flush()
+        for g, s, sd in zip(gA, sA, range(200, 203)):
+            assert_sketch_equal(g, oracle_for(s, sd))
+        for g, s, sd in zip(gB, sB, range(300, 303)):
+            assert_sketch_equal(g, oracle_for(s, sd))
+    for g in gA + gB:
+        g.close()

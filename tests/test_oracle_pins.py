@@ -103,7 +103,7 @@ def test_seed_table_prefix_independent_of_round_count(built):
 # ------------------------------------------------------------------ hash ---
 
 def test_hash_depth_law(built):
-    """Row membership: h1(e) = 0 mod 2^k with probability 2^-k (Sec. 3.2)."""
+    """Row membership: h1(e) = 0 mod 2^k with probability 2^-k (Sec. 3.1)."""
     O = oracle.Oracle(1 << 14, seed=2024)
     counts = np.zeros(12)
     rng = np.random.default_rng(1)
@@ -126,7 +126,7 @@ def test_hash_depth_law(built):
 
 @pytest.mark.parametrize("x,y", [(0, 1), (2, 6), (4, 12), (1 << 20, (1 << 20) + 2), (123456, 7654321)])
 def test_hash_pairwise_uniform(built, x, y):
-    """2-wise independence (Sec. 3.2): over random seeds, (h(x), h(y)) low bits are uniform."""
+    """2-wise independence (Sec. 3.1): over random seeds, (h(x), h(y)) low bits are uniform."""
     rng = random.Random(x * 31 + y)
     cells = np.zeros(16)
     trials = 16000
@@ -208,7 +208,7 @@ def test_sketch_independent_of_stream_order(built):
 
 
 def test_linearity_xor(built):
-    """S(A) xor S(B) = S(A symmetric-difference B) (Sec. 3.2, linearity by XOR)."""
+    """S(A) xor S(B) = S(A symmetric-difference B) (Sec. 3.1, linearity by XOR)."""
     rng = random.Random(11)
     V = 30
     sa, da = _random_toggle_stream(V, 500, rng)
@@ -540,7 +540,7 @@ def test_wide_pair_hash_closed_form(built):
 @pytest.mark.parametrize("p,q", [((0, 1), (0, 2)), ((5, 70000), (6, 70000)),
                                  ((65536, 65537), (65537, 65538)), ((1, 1 << 23), (2, 1 << 22))])
 def test_wide_pair_hash_pairwise_uniform(built, p, q):
-    """2-wise independence over random seeds for two distinct pairs (Sec. 3.2)."""
+    """2-wise independence over random seeds for two distinct pairs (Sec. 3.1)."""
     rng = random.Random(p[1] * 7 + q[0])
     cells = np.zeros(16)
     trials = 16000

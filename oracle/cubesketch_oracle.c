@@ -8,7 +8,7 @@
  *
  * Every step follows the paper directly:
  *   - edge index over node pairs: Sec. 2.2 (characteristic vectors);
- *   - CubeSketch update and query: Sec. 3.2, Fig. "cube_code", Eq. (1)-(2) and
+ *   - CubeSketch update and query: Sec. 3.1, Fig. "cube_code", Eq. (1)-(2) and
  *     the per-bucket result rule that follows them;
  *   - one independent CubeSketch per Boruvka round per node: Sec. 2.2;
  *   - Boruvka rounds (recover an edge per component, merge, sum sketches):

@@ -433,7 +433,7 @@ void gen_unit_f64(uint64_t seed, uint64_t stream, uint64_t n, double *out) {
  * Raw R-MAT draws on V = 2^L nodes, for large sparse-in-time streams where a
  * live-edge set would not fit: n updates, each an R-MAT draw with self-loops
  * redrawn; a pair drawn again toggles the edge (the draw is then a deletion
- * under the Z2 view of Sec. 3.2).  The quadrant of each level is chosen from
+ * under the Z2 view of Sec. 3.1).  The quadrant of each level is chosen from
  * one 32-bit draw against the cumulative thresholds of (a, b, c).  Draws are
  * made in blocks of 2^20, block k from its own PCG32 sequence (seed, k), so
  * the output does not depend on `threads`.  Returns n, or -1.

@@ -188,6 +188,31 @@ gz_status gz_ingest(gz_graph* g, const uint32_t* src, const uint32_t* dst, const
                     uint64_t N, uint32_t flags, hipStream_t stream);
 
 /* ------------------------------------------------------------------------
+ * gz_ingest_noalloc -- gz_ingest for callers that cannot allocate device
+ *   memory: code under stream capture, tight serving loops, harnesses that
+ *   forbid hipMalloc.  Same result as gz_ingest(g, src, dst, NULL, N,
+ *   flags | GZ_ASYNC, stream), from the same kernels, but every device buffer
+ *   of the call (grouping tables, grouped entries, work items, per-call
+ *   tables) is carved from one fixed 64 MiB array that the library holds on
+ *   each GPU it runs on until the process ends; the call itself allocates no
+ *   device memory.
+ *   src, dst  device arrays of N node ids (flags must hold GZ_DEVICE_PTR),
+ *             read when the stream reaches the call;
+ *   Always asynchronous: an invalid update applies nothing and is reported by
+ *   g's next gz_flush.  GZ_EINVAL, applying nothing, for a host-tier graph,
+ *   host arrays, or a call whose buffers exceed the 64 MiB: about 16 B per
+ *   update plus 4 B per node per grouping chunk of max(8192, N / grouping
+ *   blocks) updates (for V = 2^14, calls of up to about 2.5 M updates fit);
+ *   split larger streams into several calls.
+ *   Every call on one GPU uses that GPU's one array, which keeps the last
+ *   call's contents: calls that overlap on one GPU (on different streams, or
+ *   from different host threads) race and corrupt each other's results, so
+ *   issue them one after another on one stream.
+ * ---------------------------------------------------------------------- */
+gz_status gz_ingest_noalloc(gz_graph* g, const uint32_t* src, const uint32_t* dst, uint64_t N,
+                            uint32_t flags, hipStream_t stream);
+
+/* ------------------------------------------------------------------------
  * gz_ingest_multi -- gz_ingest over G independent graphs in one fused
  *   launch sequence.  Updates offs[k] .. offs[k+1]-1 of src/dst belong to gs[k]
  *   (ids local to that graph).  offs is host memory (G+1 entries, offs[0]=0,

@@ -70,6 +70,8 @@ _SIGS = {
                                 ctypes.c_uint32, ctypes.c_void_p], ctypes.c_int32),
     "gz_ingest": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                    ctypes.c_uint64, ctypes.c_uint32, ctypes.c_void_p], ctypes.c_int32),
+    "gz_ingest_noalloc": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64,
+                           ctypes.c_uint32, ctypes.c_void_p], ctypes.c_int32),
     "gz_ingest_multi": ([ctypes.POINTER(ctypes.c_void_p), ctypes.c_uint32,
                          ctypes.POINTER(ctypes.c_uint64), ctypes.c_void_p, ctypes.c_void_p,
                          ctypes.c_uint32, ctypes.c_void_p], ctypes.c_int32),
@@ -260,6 +262,17 @@ class Graph:
                 kop = np.ascontiguousarray(op, np.uint8)
                 pop = ctypes.c_void_p(kop.ctypes.data)
         return check(lib().gz_ingest(self._h, ps, pd, pop, n, fs | flags, _stream_handle(stream)))
+
+    def ingest_noalloc(self, src, dst, flags: int = 0, stream=None):
+        """gz_ingest_noalloc: device arrays only, always asynchronous, no device allocation."""
+        ps, fs, ks = _u32_arg(src)
+        pd, fd, kd = _u32_arg(dst)
+        if not (fs & fd & GZ_DEVICE_PTR):
+            raise ValueError("gz_ingest_noalloc takes device arrays")
+        if len(kd) != len(ks):
+            raise ValueError("src and dst lengths differ")
+        return check(lib().gz_ingest_noalloc(self._h, ps, pd, len(ks), GZ_DEVICE_PTR | flags,
+                                             _stream_handle(stream)))
 
     def update_sketch_batch(self, node: int, nbrs, flags: int = 0, stream=None):
         p, f, k = _u32_arg(nbrs)

@@ -361,6 +361,16 @@ gz_status init_graph(gz_graph** out, uint32_t V, uint64_t seed, const gz_config*
         return s;
     }
     g->tuning = default_tuning(g->P, g->B, g->wide);
+    // locate this device's no-allocation scratch now, so that gz_ingest_noalloc
+    // makes no set-up call of its own
+    uint8_t* na = nullptr;
+    size_t na_cap = 0;
+    e = noalloc_scratch(&na, &na_cap);
+    if (e != hipSuccess) {
+        gz_status s = hip_fail(e, "no-allocation scratch address");
+        gz_free(g);
+        return s;
+    }
     *out = g;
     return GZ_OK;
 }

@@ -1422,6 +1422,90 @@ gz_status update_node_batch(gz_graph* g, uint32_t node, const uint32_t* nbrs, ui
     return GZ_OK;
 }
 
+// ------------------------------------------------- ingest without allocation --
+
+// Per-call tables of a no-allocation ingest, written into the caller-provided
+// scratch by a kernel that takes them by value (no host staging buffer).
+__global__ void k_noalloc_setup(IngestArgs a, GraphDesc d, uint32_t nq, uint32_t n_units,
+                                IngestArgs* __restrict__ args, GraphDesc* __restrict__ descs,
+                                GroupUnit* __restrict__ units, uint32_t* __restrict__ ctl) {
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t == 0) {
+        *args = a;
+        descs[0] = d;
+    }
+    if (t < 8) ctl[t] = 0;
+    for (uint32_t i = t; i < n_units; i += gridDim.x * blockDim.x)
+        units[i] = GroupUnit{0u, i / nq, i % nq, 0u};
+}
+
+namespace {
+// the next 256-byte aligned region of `bytes` in [base, base + cap), or null when it
+// does not fit (`*at` still advances, so the caller learns the bytes needed)
+template <typename T>
+T* carve(uint8_t* base, size_t cap, size_t* at, uint64_t count) {
+    const size_t start = (*at + 255) & ~(size_t)255;
+    *at = start + (size_t)std::max<uint64_t>(count, 1) * sizeof(T);
+    return *at <= cap ? reinterpret_cast<T*>(base + start) : nullptr;
+}
+}  // namespace
+
+gz_status ingest_noalloc(gz_graph* g, const uint32_t* src, const uint32_t* dst, uint64_t N,
+                         uint32_t flags, hipStream_t stream, uint8_t* scratch, size_t cap) {
+    if (g->tier) return fail(GZ_EINVAL, "gz_ingest_noalloc takes graphs whose sketches live in HBM");
+    if (!(flags & GZ_DEVICE_PTR)) return fail(GZ_EINVAL, "gz_ingest_noalloc takes device arrays");
+    if (N >= (1ull << 31)) return fail(GZ_EINVAL, "at most 2^31-1 updates per call");
+    if (N == 0) return GZ_OK;
+    if (!src || !dst) return fail(GZ_EINVAL, "null stream arrays");
+    gz_graph* gs[1] = {g};
+    const uint64_t ranges[2] = {0, N};
+    LaunchShape L;
+    GZ_TRY(build_shape(gs, 1, ranges, N, L));
+    // the scratch laid out as ensure_scratch would allocate it for this call
+    IngestScratch S{};
+    size_t at = 0;
+    const uint32_t T = L.T;
+    S.ctl = carve<uint32_t>(scratch, cap, &at, 8);
+    S.args = carve<IngestArgs>(scratch, cap, &at, 1);
+    S.descs = carve<GraphDesc>(scratch, cap, &at, 1);
+    S.units = carve<GroupUnit>(scratch, cap, &at, L.n_units);
+    S.counts = carve<uint32_t>(scratch, cap, &at, T);
+    S.cursor = carve<uint32_t>(scratch, cap, &at, T);
+    S.block_sums = carve<uint64_t>(scratch, cap, &at, (uint64_t)T / kScanTile + 2);
+    S.H = carve<uint32_t>(scratch, cap, &at, L.H_size + 1);
+    S.grouped = carve<uint32_t>(scratch, cap, &at, 2 * N);
+    S.items = carve<WorkItem>(scratch, cap, &at, (uint64_t)T + 2 * N / L.chunk + 1);
+    if (L.two_pass || L.wide) S.buckets = carve<uint32_t>(scratch, cap, &at, 2 * N);
+    if (L.two_pass)
+        S.bbase = carve<uint32_t>(scratch, cap, &at, (uint64_t)(L.nbc + 1) * L.nbk + 1 + 3ull * L.pcap);
+    if (at > cap)
+        return fail(GZ_EINVAL, "gz_ingest_noalloc: this call needs " + std::to_string(at) +
+                                   " bytes of scratch, more than the " + std::to_string(cap) +
+                                   " the library keeps per device; split the stream into "
+                                   "smaller calls");
+    IngestArgs a{};
+    a.src = src;
+    a.dst = dst;
+    a.offs = nullptr;
+    a.N = N;
+    a.G = 1;
+    a.T = L.T;
+    a.chunk = L.chunk;
+    a.lds_rows = L.lds_rows;
+    a.group_chunk = L.group_chunk;
+    a.n_units = L.n_units;
+    a.H_size = L.H_size;
+    const uint32_t nq = (g->V + kGroupRange - 1) / kGroupRange;
+    GZ_HIP(fence_wait(stream, g));
+    k_noalloc_setup<<<grid_for(L.n_units, 256, 1024), 256, 0, stream>>>(
+        a, L.descs[0], nq, L.n_units, S.args, S.descs, S.units, S.ctl);
+    GZ_HIP(hipGetLastError());
+    GZ_TRY(launch_sequence(S, L, stream, g->profiling ? g : nullptr));
+    GZ_TRY(note_async_error(S, gs, 1, stream));
+    GZ_HIP(fence_record(stream, g));
+    return GZ_OK;
+}
+
 }  // namespace gz
 
 // ------------------------------------------------------ captured ingest plan --

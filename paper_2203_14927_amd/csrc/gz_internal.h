@@ -264,6 +264,12 @@ gz_status update_node_batch(gz_graph* g, uint32_t node, const uint32_t* nbrs, ui
 __global__ void k_note_error(const GraphDesc* __restrict__ descs, uint32_t G,
                              const uint32_t* __restrict__ call_err);
 void free_ingest_scratch(IngestScratch& S);
+// gz_ingest of device arrays with every device buffer carved from `scratch`
+// (cap bytes) instead of allocated; asynchronous (errors reported at flush)
+gz_status ingest_noalloc(gz_graph* g, const uint32_t* src, const uint32_t* dst, uint64_t N,
+                         uint32_t flags, hipStream_t stream, uint8_t* scratch, size_t cap);
+// the no-allocation scratch of the current device, located once per device
+hipError_t noalloc_scratch(uint8_t** ptr, size_t* cap);
 
 // dynamic LDS of an update launch, and raising a kernel's LDS limit above 64 KiB
 // LDS rows of a tile for launches that keep up to lds_rows rows of graphs with

@@ -348,6 +348,27 @@ gz_status gz_profile_enable(gz_graph* g, int on);
 gz_status gz_profile_last(gz_graph* g, gz_profile* out);
 
 /* ------------------------------------------------------------------------
+ * gz_measure_peaks -- measure, on the current device, the figures the
+ *   roofline of the sketch kernels is read against: a plain 1 GiB device copy
+ *   (read + write bytes per second) and the issue rates, in lane operations
+ *   per second, of the integer VALU instructions the hashes and bucket XORs
+ *   are made of (eight independent chains per lane, enough workgroups to fill
+ *   every CU).  Synchronous on `stream`; allocates and frees 2 GiB.
+ * ---------------------------------------------------------------------- */
+typedef struct gz_peaks {
+    double copy_gbs;          /* device copy, read + write GB/s */
+    double mul_lo_u32_tops;   /* v_mul_lo_u32, T lane-ops/s */
+    double mad_u64_u32_tops;  /* v_mad_u64_u32 */
+    double xor_b32_tops;      /* v_xor_b32 */
+    double mad_u32_u24_tops;  /* v_mad_u32_u24 */
+    double add_u32_tops;      /* v_add_u32 */
+    double ctz_b32_tops;      /* v_ffbl_b32 with the v_min, v_add, v_xor of its chain */
+    uint32_t cus;
+    uint32_t reserved;
+} gz_peaks;
+gz_status gz_measure_peaks(gz_peaks* out, hipStream_t stream);
+
+/* ------------------------------------------------------------------------
  * Serving: many graph sessions on one GPU.
  *   A server thread admits sessions while the device bytes of their sketches
  *   (plus query scratch) fit `hbm_budget`; a session opened beyond the budget

@@ -51,6 +51,14 @@ class gz_tuning(ctypes.Structure):
         return {f: int(getattr(self, f)) for f, _ in self._fields_}
 
 
+class gz_peaks(ctypes.Structure):
+    _fields_ = [("copy_gbs", ctypes.c_double), ("mul_lo_u32_tops", ctypes.c_double),
+                ("mad_u64_u32_tops", ctypes.c_double), ("xor_b32_tops", ctypes.c_double),
+                ("mad_u32_u24_tops", ctypes.c_double), ("add_u32_tops", ctypes.c_double),
+                ("ctz_b32_tops", ctypes.c_double), ("cus", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32)]
+
+
 class gz_profile(ctypes.Structure):
     _fields_ = [("group_ms", ctypes.c_float), ("update_ms", ctypes.c_float),
                 ("ingest_ms", ctypes.c_float), ("calls", ctypes.c_uint32),
@@ -104,6 +112,7 @@ _SIGS = {
     "gz_plan_ingest": ([ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint64), ctypes.c_void_p,
                         ctypes.c_void_p, ctypes.c_uint32, ctypes.c_void_p], ctypes.c_int32),
     "gz_plan_free": ([ctypes.c_void_p], ctypes.c_int32),
+    "gz_measure_peaks": ([ctypes.POINTER(gz_peaks), ctypes.c_void_p], ctypes.c_int32),
     "gz_status_str": ([ctypes.c_int32], ctypes.c_char_p),
     "gz_last_error": ([], ctypes.c_char_p),
 }
@@ -452,3 +461,10 @@ class Plan:
         except Exception:
             pass
 
+
+def measure_peaks(stream=None) -> dict:
+    """Device copy bandwidth and integer VALU issue rates (gz_measure_peaks)."""
+    p = gz_peaks()
+    check(lib().gz_measure_peaks(ctypes.byref(p), _stream_handle(stream)))
+    return {f: (float(getattr(p, f)) if t is ctypes.c_double else int(getattr(p, f)))
+            for f, t in p._fields_ if f != "reserved"}

@@ -219,10 +219,11 @@ __global__ void k_export(const uint32_t* __restrict__ sk, uint32_t first, uint32
         const uint32_t pg = planes - 2;  // first gamma plane
         uint32_t a = 0, ah = 0, gl = 0, gh = 0;
         for (int b = (int)B - 1; b >= 0; --b) {
-            a ^= base[(0 * B + b) * kC];
-            if (planes == kPlanesWide) ah ^= base[(1 * B + b) * kC];
-            gl ^= base[(pg * B + b) * kC];
-            gh ^= base[((pg + 1) * B + b) * kC];
+            const uint32_t* row = base + b * planes * kC;  // row b of the round, column c
+            a ^= row[0];
+            if (planes == kPlanesWide) ah ^= row[kC];
+            gl ^= row[pg * kC];
+            gh ^= row[(pg + 1) * kC];
             alpha[out0 + b] = ((uint64_t)ah << 32) | a;
             gamma[out0 + b] = ((uint64_t)gh << 32) | gl;
         }

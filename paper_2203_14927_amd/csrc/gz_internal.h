@@ -29,24 +29,25 @@ enum SeedWord : uint32_t {
 // Sketch words of a node (32-bit, "exact-depth" basis: row d holds the XOR of
 // the indices whose depth is exactly d, so each update touches one row per
 // column).  Node v owns the block sk[v * 3 * B * P ...], P = R * C, laid out
-// round-major: word ((r * 3 + plane) * B + d) * C + c.  One round's rows of a
-// node are thus contiguous (3 * B * C words), which is what a Boruvka round
-// reads.  Planes: 0 = alpha (indices are < 2^31, the high word is always
-// zero), 1 = gamma low word, 2 = gamma high word.  The nested rows of the
-// paper are the suffix XORs over d >= b of this basis (a linear, invertible
-// change).
+// round-major, then row by row, the planes of a row side by side: word
+// ((r * B + d) * 3 + plane) * C + c.  One round's rows of a node are thus
+// contiguous (3 * B * C words), which is what a Boruvka round reads, and so are
+// its rows d < DL, which is what the update of a small item reads and writes.
+// Planes: 0 = alpha (indices are < 2^31, the high word is always zero),
+// 1 = gamma low word, 2 = gamma high word.  The nested rows of the paper are
+// the suffix XORs over d >= b of this basis (a linear, invertible change).
 __host__ __device__ __forceinline__ uint32_t sk_word(uint32_t B, uint32_t r, uint32_t plane,
                                                      uint32_t d, uint32_t c) {
-    return ((r * kPlanes + plane) * B + d) * kC + c;
+    return ((r * B + d) * kPlanes + plane) * kC + c;
 }
 
 // Graphs with V > 2^16 ("wide") need 64-bit indices: four planes (alpha low,
-// alpha high, gamma low, gamma high), the same round-major order.
+// alpha high, gamma low, gamma high), the same order.
 constexpr uint32_t kPlanesWide = 4;
 constexpr uint32_t kMaxNarrow = 65536;
 __host__ __device__ __forceinline__ uint32_t sk_word_n(uint32_t planes, uint32_t B, uint32_t r,
                                                        uint32_t plane, uint32_t d, uint32_t c) {
-    return ((r * planes + plane) * B + d) * kC + c;
+    return ((r * B + d) * planes + plane) * kC + c;
 }
 
 // Row stride of an LDS node tile: P rounded up to a multiple of 64 words.
@@ -232,6 +233,10 @@ gz_status hip_fail(hipError_t e, const char* what);
         hipError_t e_ = (call);                                   \
         if (e_ != hipSuccess) return ::gz::hip_fail(e_, #call);   \
     } while (0)
+// the status of a HIP call as an expression (GZ_OK on success)
+#define GZ_HIP_STATUS(call) \
+    ([&]() -> gz_status { hipError_t e_ = (call); \
+        return e_ == hipSuccess ? GZ_OK : ::gz::hip_fail(e_, #call); }())
 
 int device_cu_count();
 // true if a handle is null or listed twice

@@ -240,7 +240,7 @@ __global__ __launch_bounds__(256) void k_q_reduce(uint32_t r, const ReduceSpan* 
     }
     const uint32_t na = s_nact;
     const GraphDesc& g = gd[sp.graph];
-    // word w = (plane * B + d) * C + c of the round's contiguous rows
+    // word w = (d * planes + plane) * C + c of the round's contiguous rows
     const uint32_t w = blockIdx.y * blockDim.x + threadIdx.x;
     if (w >= g.planes * g.B * kC) return;
     const uint32_t stride = g.node_words;
@@ -317,7 +317,7 @@ __device__ __forceinline__ void query_component(uint32_t r, uint32_t gtid, uint3
         const GraphDesc g = gd[gof[X]];
         const uint32_t p = r * kC + c;
         const uint32_t B = g.B;
-        // word (plane, row b) of column c: stride between rows of one plane
+        // word (row b, plane) of column c: row b of the round starts at b * planes * C
         const uint32_t* in;
         if (kDirect)
             in = g.sk + (uint64_t)(X - g.node_base) * g.node_words +
@@ -347,15 +347,16 @@ __device__ __forceinline__ void query_component(uint32_t r, uint32_t gtid, uint3
                 uint32_t xa[kQueryRows], xg[kQueryRows], xh[kQueryRows];
 #pragma unroll
                 for (uint32_t q = 0; q < kQueryRows; ++q) {
-                    xa[q] = in[(0 * B + b - q) * kC];
-                    xg[q] = in[(1 * B + b - q) * kC];
-                    xh[q] = in[(2 * B + b - q) * kC];
+                    xa[q] = in[((b - q) * kPlanes + 0) * kC];
+                    xg[q] = in[((b - q) * kPlanes + 1) * kC];
+                    xh[q] = in[((b - q) * kPlanes + 2) * kC];
                 }
 #pragma unroll
                 for (uint32_t q = 0; q < kQueryRows; ++q) row(b - (int)q, xa[q], xg[q], xh[q]);
             }
             for (; b >= 0; --b)
-                row(b, in[(0 * B + b) * kC], in[(1 * B + b) * kC], in[(2 * B + b) * kC]);
+                row(b, in[(b * kPlanes + 0) * kC], in[(b * kPlanes + 1) * kC],
+                    in[(b * kPlanes + 2) * kC]);
         } else {
             // 64-bit alpha; the checksum is of the pair the index encodes
             const WideSeeds s = load_wide_seeds(g.seeds, g.P, p);
@@ -382,18 +383,18 @@ __device__ __forceinline__ void query_component(uint32_t r, uint32_t gtid, uint3
                 uint32_t xa[kQueryRows], xah[kQueryRows], xg[kQueryRows], xh[kQueryRows];
 #pragma unroll
                 for (uint32_t q = 0; q < kQueryRows; ++q) {
-                    xa[q] = in[(0 * B + b - q) * kC];
-                    xah[q] = in[(1 * B + b - q) * kC];
-                    xg[q] = in[(2 * B + b - q) * kC];
-                    xh[q] = in[(3 * B + b - q) * kC];
+                    xa[q] = in[((b - q) * kPlanesWide + 0) * kC];
+                    xah[q] = in[((b - q) * kPlanesWide + 1) * kC];
+                    xg[q] = in[((b - q) * kPlanesWide + 2) * kC];
+                    xh[q] = in[((b - q) * kPlanesWide + 3) * kC];
                 }
 #pragma unroll
                 for (uint32_t q = 0; q < kQueryRows; ++q)
                     row(b - (int)q, xa[q], xah[q], xg[q], xh[q]);
             }
             for (; b >= 0; --b)
-                row(b, in[(0 * B + b) * kC], in[(1 * B + b) * kC], in[(2 * B + b) * kC],
-                    in[(3 * B + b) * kC]);
+                row(b, in[(b * kPlanesWide + 0) * kC], in[(b * kPlanesWide + 1) * kC],
+                    in[(b * kPlanesWide + 2) * kC], in[(b * kPlanesWide + 3) * kC]);
         }
         // the next round's atomics find this accumulator zeroed (its slots
         // are a subset of this round's)

@@ -202,7 +202,8 @@ __device__ __forceinline__ bool xor_entry(uint32_t x, uint32_t node, const Lane<
 }
 
 // The HBM side of an entry deeper than the item's rows (`skl` is the lane's
-// bucket of row 0, plane 0, in the node block); shallower entries do nothing.
+// bucket of row 0, plane 0, in the node block; the planes of a bucket are
+// plane_words apart, the rows of a round kPl * C); shallower entries do nothing.
 template <bool kWide, int kSide>
 __device__ __forceinline__ void xor_entry_deep(uint32_t x, uint32_t node, const Lane<kWide>& ln,
                                                const ConstsOf<kWide, kSide>& nc, uint32_t Bm1,
@@ -213,7 +214,7 @@ __device__ __forceinline__ void xor_entry_deep(uint32_t x, uint32_t node, const 
     hash_entry<kWide, kSide>(x, node, ln, nc, h, &idx);
     const uint32_t d = depth_of(h[0], Bm1);
     if (d < DL) return;
-    uint32_t* w = skl + d * kC;
+    uint32_t* w = skl + d * (Layout<kWide>::kPl * kC);
     atomicXor(w, (uint32_t)idx);
     if constexpr (!kWide) {
         atomicXor(w + plane_words, h[2]);
@@ -254,53 +255,81 @@ struct NeighbourEntries {
     }
 };
 
-// Walk over the tile rows d < DL of a node in HBM order of the round-major
-// block: flat index i over planes * DL * P words, c = i mod C, d = (i / C) mod
-// DL, then the (round, plane) run, so consecutive lanes read and write the
-// DL * C contiguous words of one (round, plane) run of the node block (the
-// divisions by DL > 1 are reciprocal multiplies, exact for i < 2^32 / DL).  Their
-// LDS words fall in C banks per row (at most 8-way conflicts on the tile
-// set-up, a small cost next to a coalesced HBM access).
+// Walk over the tile rows d < DL of a node, four words (16 bytes) at a time.
+// In a node block the rows of a round are contiguous, each row holding its
+// planes side by side (kPl * C words), and every row starts on a 32-byte
+// boundary.  A unit covers columns 4 * c4 .. + 3 of one plane of one row of one
+// round, and units go in groups of four rows: u = (((dhi * R + r) * 4 + dlo) *
+// kPl + pl) * 2 + c4, row d = 4 * dhi + dlo (units past row DL - 1 do nothing).
+// A group is 4 * kPl * C contiguous words of HBM (three 128-byte lines for
+// three planes), and consecutive groups are other rounds: in the LDS tile,
+// whose rows all start on the same bank, a wave's lanes then fall on different
+// pairs, planes and rounds, at most four on one bank (walking all DL rows of
+// one round first put up to DL lanes on a bank; walking row by row across all
+// rounds spread them fully but had a wave touch three times as many 128-byte
+// lines, and was slower on small items).  The four words of a unit are the
+// same row and plane of four consecutive pairs: kLdsStep words apart in the
+// tile (three with three planes interleaved per pair, one in the four-plane
+// blocks of 64 pairs, which a unit never crosses).
 template <bool kWide>
 struct TileWalk {
     static constexpr uint32_t kPl = Layout<kWide>::kPl;
-    uint32_t P, B, DL, RW, n, recip;
+    static constexpr uint32_t kLdsStep = kWide ? 1u : kPlanes;
+    uint32_t P, B, DL, R, RW, n4, recip;
     __device__ __forceinline__ TileWalk(uint32_t P_, uint32_t B_, uint32_t DL_)
-        : P(P_), B(B_), DL(DL_), RW(tile_row_words(P_, kWide)), n(kPl * DL_ * P_),
-          recip(0xFFFFFFFFu / DL_ + 1u) {}
-    __device__ __forceinline__ void at(uint32_t i, uint32_t* t, uint32_t* h) const {
-        const uint32_t c = i % kC;
-        const uint32_t q = i / kC;
-        // (round, plane) run; DL = 1 has no 32-bit reciprocal (it would be 2^32)
-        const uint32_t run = DL == 1u ? q : __umulhi(q, recip);
-        const uint32_t d = q - run * DL;
-        const uint32_t r = run / kPl;
-        const uint32_t pl = run - r * kPl;
-        *t = d * RW + Layout<kWide>::lane_word(r * kC + c) + pl * Layout<kWide>::kPlaneStep;
-        *h = (run * B + d) * kC + c;  // sk_word_n(kPl, B, r, pl, d, c)
+        : P(P_), B(B_), DL(DL_), R(P_ / kC), RW(tile_row_words(P_, kWide)),
+          n4(kPl * ((DL_ + 3u) & ~3u) * P_ / 4u), recip(0xFFFFFFFFu / (P_ / kC) + 1u) {}
+    // false for the units of rows past DL - 1; else the LDS word of the unit's first
+    // column and the unit's 16-byte index in the node block
+    __device__ __forceinline__ bool at(uint32_t u, uint32_t* t, uint32_t* h4) const {
+        const uint32_t c4 = u & 1u;
+        const uint32_t v = u >> 1;
+        const uint32_t w = v / kPl;
+        const uint32_t pl = v - w * kPl;
+        const uint32_t dlo = w & 3u;
+        const uint32_t q = w >> 2;
+        // R = 1 has no 32-bit reciprocal (it would be 2^32); the quotient is exact
+        // for q < 2^32 / R
+        const uint32_t dhi = R == 1u ? q : __umulhi(q, recip);
+        const uint32_t r = q - dhi * R;
+        const uint32_t d = dhi * 4u + dlo;
+        *t = d * RW + Layout<kWide>::lane_word(r * kC + 4u * c4) + pl * Layout<kWide>::kPlaneStep;
+        *h4 = ((r * B + d) * kPl + pl) * (kC / 4u) + c4;  // sk_word_n(kPl, B, r, pl, d, 4c4) / 4
+        return d < DL;
     }
 };
 
 // Tile set-up.  A node this workgroup owns for the launch starts from its HBM
-// rows (loads batched four per lane so they overlap); a node shared with other
-// workgroups starts from zero and is merged with atomics.
+// rows (16-byte loads, two per lane in flight: more would take the update
+// kernels past 64 VGPRs and cost them a wave per SIMD); a node shared with
+// other workgroups starts from zero and is merged with atomics.
+constexpr uint32_t kTileLoads = 2;
+
 template <bool kWide>
 __device__ __forceinline__ void tile_load(uint32_t* __restrict__ tile,
                                           const uint32_t* __restrict__ skn,
                                           const TileWalk<kWide>& tw) {
-    for (uint32_t base = threadIdx.x; base < tw.n; base += 4 * blockDim.x) {
-        uint32_t v[4], t[4];
+    constexpr uint32_t s = TileWalk<kWide>::kLdsStep;
+    const uint4* __restrict__ skn4 = reinterpret_cast<const uint4*>(skn);
+    for (uint32_t base = threadIdx.x; base < tw.n4; base += kTileLoads * blockDim.x) {
+        uint4 v[kTileLoads];
+        uint32_t t[kTileLoads];
 #pragma unroll
-        for (uint32_t k = 0; k < 4; ++k) {
-            const uint32_t i = base + k * blockDim.x;
-            uint32_t h = 0;
+        for (uint32_t k = 0; k < kTileLoads; ++k) {
+            const uint32_t u = base + k * blockDim.x;
+            uint32_t h4 = 0;
             t[k] = kNone;
-            if (i < tw.n) tw.at(i, &t[k], &h);
-            v[k] = i < tw.n ? skn[h] : 0u;
+            if (u < tw.n4 && !tw.at(u, &t[k], &h4)) t[k] = kNone;
+            v[k] = t[k] != kNone ? skn4[h4] : make_uint4(0, 0, 0, 0);
         }
 #pragma unroll
-        for (uint32_t k = 0; k < 4; ++k)
-            if (t[k] != kNone) tile[t[k]] = v[k];
+        for (uint32_t k = 0; k < kTileLoads; ++k)
+            if (t[k] != kNone) {
+                tile[t[k]] = v[k].x;
+                tile[t[k] + s] = v[k].y;
+                tile[t[k] + 2 * s] = v[k].z;
+                tile[t[k] + 3 * s] = v[k].w;
+            }
     }
 }
 
@@ -309,18 +338,27 @@ __device__ __forceinline__ void tile_zero(uint32_t* __restrict__ tile, const Til
     for (uint32_t i = threadIdx.x; i < tw.DL * tw.RW; i += blockDim.x) tile[i] = 0;
 }
 
-// Write-back: owned nodes store the whole tile, shared nodes XOR non-zero words
-// in with atomics.
+// Write-back: owned nodes store the whole tile (16-byte stores), shared nodes
+// XOR non-zero words in with atomics.
 template <bool kWide>
 __device__ __forceinline__ void tile_store(const uint32_t* __restrict__ tile,
                                            uint32_t* __restrict__ skn, const TileWalk<kWide>& tw,
                                            bool shared) {
-    for (uint32_t i = threadIdx.x; i < tw.n; i += blockDim.x) {
-        uint32_t t, h;
-        tw.at(i, &t, &h);
-        const uint32_t val = tile[t];
-        if (!shared) skn[h] = val;
-        else if (val) atomicXor(&skn[h], val);
+    constexpr uint32_t s = TileWalk<kWide>::kLdsStep;
+    uint4* __restrict__ skn4 = reinterpret_cast<uint4*>(skn);
+    for (uint32_t u = threadIdx.x; u < tw.n4; u += blockDim.x) {
+        uint32_t t, h4;
+        if (!tw.at(u, &t, &h4)) continue;
+        const uint4 v = make_uint4(tile[t], tile[t + s], tile[t + 2 * s], tile[t + 3 * s]);
+        if (!shared) {
+            skn4[h4] = v;
+        } else {
+            uint32_t* w = skn + 4u * h4;
+            if (v.x) atomicXor(w, v.x);
+            if (v.y) atomicXor(w + 1, v.y);
+            if (v.z) atomicXor(w + 2, v.z);
+            if (v.w) atomicXor(w + 3, v.w);
+        }
     }
 }
 
@@ -450,7 +488,7 @@ __device__ __forceinline__ void apply_entries(const Src& ent, uint32_t count, ui
     if (ln.active) {
         const uint32_t Bm1 = g.B - 1;
         const uint32_t row_bytes = tw.RW * 4;
-        const uint32_t plane_words = g.B * kC;
+        const uint32_t plane_words = kC;  // the planes of a row sit side by side
         uint8_t* tb = (uint8_t*)tile;
         uint32_t* skl = skn + ln.hbm_word;
         xor_share<kAllRows, kWide, kSide1>(ent, r, a, b, node, ln, nc, Bm1, DL, row_bytes, tb,

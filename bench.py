@@ -91,7 +91,8 @@ def make_workload(name: str):
 
 PMC_SUMMARIES = {"rmat_dense": "k_update_rmat_dense_pmc.txt",
                  "rmat_skewed": "k_update_rmat_skewed_pmc.txt",
-                 "rmat_kron18": "k_update_wide_rmat_kron18_pmc.txt"}
+                 "rmat_kron18": "k_update_wide_rmat_kron18_pmc.txt",
+                 "many_gnp": "k_update_many_gnp_kernel_trace.txt"}
 
 
 def traffic_from_profile(kernel_src_hash: str, workload: str = "rmat_dense"):
@@ -558,7 +559,8 @@ def run_many(args) -> dict:
         "cc_query_ms": ms - ims, "update_kernel_ms": upd_ms,
         "tuning": tune, "tuning_source": tuned_from,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": achieved / PEAK_HBM_GBS, "traffic": None,
+                     "frac": achieved / PEAK_HBM_GBS,
+                     "traffic": traffic_from_profile(kernel_source_hash(), "many_gnp"),
                      "kernel": "k_update", "bytes_per_launch": moved["bytes"],
                      "bytes_rule": "per work item: 4 B per entry read, the rows d < DL of its "
                                    "node tile read and written (3 planes x DL x R x C x 4 B "

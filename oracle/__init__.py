@@ -30,9 +30,12 @@ OK, SKETCH_FAIL = 0, 1
 C_COLUMNS = 8
 
 
+_SRC_L0 = os.path.join(_HERE, "l0_oracle.c")
+
+
 def build() -> str:
     tmp = _SO + ".tmp"
-    subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", _SRC, "-o", tmp])
+    subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", _SRC, _SRC_L0, "-o", tmp])
     os.replace(tmp, _SO)
     return _SO
 
@@ -109,6 +112,35 @@ def _load():
     L.oracle_bucket_class_wide.restype = i32
     L.oracle_query_wide.argtypes = [u64p, u32, u32, u32, u64, u64p, u64p, u64p]
     L.oracle_query_wide.restype = i32
+    i64p = ctypes.POINTER(ctypes.c_int64)
+    L.l0_mulmod.argtypes = [u64, u64]
+    L.l0_mulmod.restype = u64
+    L.l0_powmod.argtypes = [u64, u64]
+    L.l0_powmod.restype = u64
+    L.l0_new.argtypes = [u32, u64]
+    L.l0_new.restype = vp
+    L.l0_free.argtypes = [vp]
+    L.l0_free.restype = None
+    L.l0_dims.argtypes = [vp, u32p, u64p]
+    L.l0_dims.restype = None
+    L.l0_a_ptr.argtypes = [vp]
+    L.l0_a_ptr.restype = i64p
+    L.l0_b_ptr.argtypes = [vp]
+    L.l0_b_ptr.restype = i64p
+    L.l0_c_ptr.argtypes = [vp]
+    L.l0_c_ptr.restype = u64p
+    L.l0_z_ptr.argtypes = [vp]
+    L.l0_z_ptr.restype = u64p
+    L.l0_update.argtypes = [vp, u32, u32, ctypes.c_int]
+    L.l0_update.restype = i32
+    L.l0_ingest.argtypes = [vp, u32p, u32p, u8p, u64]
+    L.l0_ingest.restype = i32
+    L.l0_ingest_nodes.argtypes = [vp, u32p, u32p, u8p, u64, u8p]
+    L.l0_ingest_nodes.restype = i32
+    L.l0_query.argtypes = [vp, u32, i64p, i64p, u64p, u64p, i64p]
+    L.l0_query.restype = i32
+    L.l0_query_node.argtypes = [vp, u32, u32, u64p, i64p]
+    L.l0_query_node.restype = i32
     _lib = L
     return L
 
@@ -274,3 +306,84 @@ class Oracle:
         if st < 0:
             raise MemoryError("oracle_connected_components")
         return int(st), labels, forest[: 2 * nf.value].reshape(-1, 2).copy(), int(used.value)
+
+
+# ------------------------------------------------ standard l0 sampler (Fig. agm_code)
+
+L0_P = (1 << 61) - 1
+
+
+def l0_mulmod(x: int, y: int) -> int:
+    return int(_load().l0_mulmod(x, y))
+
+
+def l0_powmod(z: int, e: int) -> int:
+    return int(_load().l0_powmod(z, e))
+
+
+class L0Oracle:
+    """Standard l0-sampler node sketches: a, b int64 and c uint64 [V, R, C, B], zero at start."""
+
+    def __init__(self, V: int, seed: int):
+        L = _load()
+        self._h = L.l0_new(V, seed)
+        if not self._h:
+            raise ValueError(f"l0_new failed for V={V}")
+        dims = (ctypes.c_uint32 * 4)()
+        n = ctypes.c_uint64()
+        L.l0_dims(self._h, dims, ctypes.byref(n))
+        self.V, self.R, self.C, self.B = (int(x) for x in dims)
+        self.n = int(n.value)
+        cells = self.V * self.R * self.C * self.B
+        shp = (self.V, self.R, self.C, self.B)
+        self.a = np.ctypeslib.as_array(L.l0_a_ptr(self._h), shape=(cells,)).reshape(shp)
+        self.b = np.ctypeslib.as_array(L.l0_b_ptr(self._h), shape=(cells,)).reshape(shp)
+        self.c = np.ctypeslib.as_array(L.l0_c_ptr(self._h), shape=(cells,)).reshape(shp)
+        self.z = np.ctypeslib.as_array(L.l0_z_ptr(self._h), shape=(self.R * self.C,)).reshape(
+            self.R, self.C).copy()
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            _load().l0_free(h)
+            self._h = None
+
+    def update(self, u: int, v: int, delta: int = 1) -> None:
+        if _load().l0_update(self._h, u, v, delta):
+            raise ValueError("invalid update")
+
+    def ingest(self, src, dst, op=None) -> None:
+        src = np.ascontiguousarray(src, np.uint32)
+        dst = np.ascontiguousarray(dst, np.uint32)
+        o = None if op is None else np.ascontiguousarray(op, np.uint8)
+        if _load().l0_ingest(self._h, _p(src, ctypes.c_uint32), _p(dst, ctypes.c_uint32),
+                             None if o is None else _p(o, ctypes.c_uint8), len(src)):
+            raise ValueError("invalid update in stream")
+
+    def ingest_nodes(self, src, dst, op, nodes) -> None:
+        src = np.ascontiguousarray(src, np.uint32)
+        dst = np.ascontiguousarray(dst, np.uint32)
+        o = None if op is None else np.ascontiguousarray(op, np.uint8)
+        keep = np.zeros(self.V, np.uint8)
+        keep[np.asarray(nodes, np.int64)] = 1
+        if _load().l0_ingest_nodes(self._h, _p(src, ctypes.c_uint32), _p(dst, ctypes.c_uint32),
+                                   None if o is None else _p(o, ctypes.c_uint8), len(src),
+                                   _p(keep, ctypes.c_uint8)):
+            raise ValueError("invalid update in stream")
+
+    def query(self, r: int, a_cb, b_cb, c_cb):
+        """Query a round-r sampler given as [C, B] arrays -> (ZERO|SAMPLE|FAIL, idx, mult)."""
+        a = np.ascontiguousarray(a_cb, np.int64)
+        b = np.ascontiguousarray(b_cb, np.int64)
+        c = np.ascontiguousarray(c_cb, np.uint64)
+        idx = ctypes.c_uint64(0)
+        mult = ctypes.c_int64(0)
+        k = _load().l0_query(self._h, r, _p(a, ctypes.c_int64), _p(b, ctypes.c_int64),
+                             _p(c, ctypes.c_uint64), ctypes.byref(idx), ctypes.byref(mult))
+        return int(k), int(idx.value), int(mult.value)
+
+    def query_node(self, v: int, r: int):
+        idx = ctypes.c_uint64(0)
+        mult = ctypes.c_int64(0)
+        k = _load().l0_query_node(self._h, v, r, ctypes.byref(idx), ctypes.byref(mult))
+        return int(k), int(idx.value), int(mult.value)

@@ -290,6 +290,38 @@ def plain_pass(gz, g, stream, src_d, dst_d):
             "plain_one_workgroup_updates_per_s": sweep[1 << 30]}
 
 
+def l0_comparison(gz, g, stream, seed, src_d, dst_d, sample: int) -> dict:
+    """Update cost of CubeSketch against the standard l0-sampler (Fig. agm_code) on the device,
+    on the same first `sample` updates of the stream: each ingested into zeroed sketches of the
+    same shape, the update kernels timed with HIP events (the paper's Fig. l0speedup makes the
+    same comparison for one sampler on a CPU thread)."""
+    import numpy as np
+    import torch
+
+    M = min(stream.N, sample)
+    op_d = torch.from_numpy(np.ascontiguousarray(stream.op[:M])).cuda()
+    s_src, s_dst = src_d[:M], dst_d[:M]
+    l0 = gz.L0Sketch(stream.V, seed)
+    l0.ingest(s_src, s_dst, op=op_d)  # warm-up
+    l0_ms, cs_ms = [], []
+    for _ in range(3):
+        l0.reset()
+        l0.ingest(s_src, s_dst, op=op_d)
+        l0_ms.append(l0.last_update_ms())
+        g.reset()
+        g.ingest(s_src, s_dst, flags=gz.GZ_ASYNC)
+        cs_ms.append(g.last_profile()["update_ms"])
+    l0.close()
+    torch.cuda.synchronize()
+    l0m, csm = statistics.median(l0_ms), statistics.median(cs_ms)
+    return {"sample": f"first {M} updates of the stream, both endpoints, sketches of the same "
+                      f"shape (R={g.R}, C={g.C}, B={g.B})",
+            "l0_update_ms": l0m, "cubesketch_update_ms": csm,
+            "l0_updates_per_s": M / (l0m * 1e-3), "cubesketch_updates_per_s": M / (csm * 1e-3),
+            "cubesketch_vs_l0": l0m / csm,
+            "context": "Fig. l0speedup (one CPU thread): 127x at n = 10^6, 172x at 10^8, 196x at 10^9"}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -299,6 +331,10 @@ def main() -> int:
                     help="rmat_skewed (default), rmat_dense, rmat_kron18, uniform_small, "
                          "many_gnp, serving, rmat_dense_host")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain per-node pass")
+    ap.add_argument("--no-l0", action="store_true",
+                    help="skip the comparison with the standard l0-sampler")
+    ap.add_argument("--l0-sample", type=int, default=16_000_000,
+                    help="updates of the stream the l0-sampler comparison ingests")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=20.0,
                     help="CPU oracle budget (split between the single-thread and all-cores legs)")
@@ -836,6 +872,11 @@ def run_single(args) -> dict:
             f"{plain['plain_updates_per_s'] / 1e6:.1f} M updates/s (node_chunk "
             f"{plain['plain_node_chunk']}; one workgroup per gutter: "
             f"{plain['plain_one_workgroup_updates_per_s'] / 1e6:.1f} M updates/s)")
+    if not args.no_l0 and stream.V <= 65536:
+        out["l0_comparison"] = l0_comparison(gz, g, stream, seed, src_d, dst_d, args.l0_sample)
+        log(f"[bench] standard l0-sampler: {out['l0_comparison']['l0_update_ms']:.2f} ms against "
+            f"{out['l0_comparison']['cubesketch_update_ms']:.2f} ms for CubeSketch on the same "
+            f"sample ({out['l0_comparison']['cubesketch_vs_l0']:.1f}x)")
     if cpu is not None:
         out["cpu_baseline"] = cpu
     g.close()

@@ -420,6 +420,56 @@ gz_status gz_session_close(gz_session* s);
 gz_status gz_server_get_stats(gz_server* srv, gz_server_stats* out);
 gz_status gz_server_destroy(gz_server* srv);
 
+/* ------------------------------------------------------------------------
+ * The standard l0-sampler (Sec. 3, Fig. "agm_code"): the sketch CubeSketch
+ *   replaces, built on the device so that the two update costs can be compared
+ *   on the same hardware (Fig. "l0speedup" makes the comparison on a CPU).
+ *   Node sketches of a graph with 2 <= V <= 65536 nodes: one sampler per
+ *   Boruvka round per node, C = 8 columns, B rows, the shape of CubeSketch.
+ *   A bucket holds a = sum of index * Delta, b = sum of Delta and a checksum
+ *   c = sum of Delta * z^index mod p, p = 2^61 - 1.  Node vectors are signed:
+ *   edge {u, v}, u < v, at index v(v-1)/2 + u, carries +Delta in u's vector and
+ *   -Delta in v's (Delta = +1 inserts, -1 deletes), so a node set's sketches
+ *   sum to the sketch of its cut.  Row k+1 of a column takes an update while
+ *   bit k of the column's hash of the index is zero, with the row hash of the
+ *   CubeSketch contract above (same seeds); the column's base z is
+ *   1 + (m mod (p - 1)) for its checksum-high multiplier m.  Sums stay exact
+ *   while a node's buckets take fewer than 2^32 terms.
+ * gz_l0_init    -- zeroed sketches on the current device (GZ_EINVAL outside
+ *                  the V range, GZ_ENOMEM); the library owns *out until gz_l0_free.
+ * gz_l0_ingest  -- apply N updates: {src[k], dst[k]} with Delta = +1 when
+ *                  op[k] != 0 (or op is NULL), -1 when op[k] == 0; arrays in host
+ *                  or device memory (GZ_DEVICE_PTR, op then in device memory too).
+ *                  Updates are grouped by endpoint on the device, then one
+ *                  persistent kernel evaluates z^index by one modular multiply
+ *                  per set bit of the index from a table of z^(2^k).
+ *                  Synchronous; GZ_EINVAL on a self-loop or an id >= V (nothing
+ *                  applied).
+ * gz_l0_last_update_ms -- device time of the last ingest's update kernel (HIP
+ *                  events on the ingest stream).
+ * gz_l0_export  -- nodes [lo, hi) in the layout a/b/c[node][r][c][row] (row b
+ *                  holds every index whose column hash has at least b trailing
+ *                  zeros, as in the figure), c reduced modulo p.
+ * gz_l0_sample  -- the figure's query of every node's round-r sampler: the
+ *                  first bucket, columns in order and rows ascending, with b != 0,
+ *                  b dividing a, v = a / b a valid index and c = b * z^v mod p.
+ *                  kind[v] = 0 (all buckets zero), 1 (sample: idx[v], mult[v] = b),
+ *                  2 (no bucket passes).  Host arrays of V entries.
+ * gz_l0_reset, gz_l0_shape, gz_l0_free as for CubeSketch graphs.
+ * ---------------------------------------------------------------------- */
+typedef struct gz_l0 gz_l0;
+gz_status gz_l0_init(gz_l0** out, uint32_t V, uint64_t seed);
+gz_status gz_l0_free(gz_l0* s);
+gz_status gz_l0_reset(gz_l0* s, hipStream_t stream);
+gz_status gz_l0_shape(const gz_l0* s, uint32_t* V, uint32_t* R, uint32_t* C, uint32_t* B,
+                      uint64_t* n);
+gz_status gz_l0_ingest(gz_l0* s, const uint32_t* src, const uint32_t* dst, const uint8_t* op,
+                       uint64_t N, uint32_t flags, hipStream_t stream);
+gz_status gz_l0_last_update_ms(gz_l0* s, float* ms);
+gz_status gz_l0_export(gz_l0* s, uint32_t node_lo, uint32_t node_hi, int64_t* a, int64_t* b,
+                       uint64_t* c);
+gz_status gz_l0_sample(gz_l0* s, uint32_t round, int32_t* kind, uint64_t* idx, int64_t* mult);
+
 /* Human-readable name of a status code, and the last error message of this thread. */
 const char* gz_status_str(gz_status s);
 const char* gz_last_error(void);

@@ -113,6 +113,21 @@ _SIGS = {
                         ctypes.c_void_p, ctypes.c_uint32, ctypes.c_void_p], ctypes.c_int32),
     "gz_plan_free": ([ctypes.c_void_p], ctypes.c_int32),
     "gz_measure_peaks": ([ctypes.POINTER(gz_peaks), ctypes.c_void_p], ctypes.c_int32),
+    "gz_l0_init": ([ctypes.POINTER(ctypes.c_void_p), ctypes.c_uint32, ctypes.c_uint64],
+                   ctypes.c_int32),
+    "gz_l0_free": ([ctypes.c_void_p], ctypes.c_int32),
+    "gz_l0_reset": ([ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int32),
+    "gz_l0_shape": ([ctypes.c_void_p] + [ctypes.POINTER(ctypes.c_uint32)] * 4
+                    + [ctypes.POINTER(ctypes.c_uint64)], ctypes.c_int32),
+    "gz_l0_ingest": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                      ctypes.c_uint64, ctypes.c_uint32, ctypes.c_void_p], ctypes.c_int32),
+    "gz_l0_last_update_ms": ([ctypes.c_void_p, ctypes.POINTER(ctypes.c_float)], ctypes.c_int32),
+    "gz_l0_export": ([ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint32,
+                      ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
+                      ctypes.POINTER(ctypes.c_uint64)], ctypes.c_int32),
+    "gz_l0_sample": ([ctypes.c_void_p, ctypes.c_uint32, ctypes.POINTER(ctypes.c_int32),
+                      ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_int64)],
+                     ctypes.c_int32),
     "gz_status_str": ([ctypes.c_int32], ctypes.c_char_p),
     "gz_last_error": ([], ctypes.c_char_p),
 }
@@ -375,6 +390,80 @@ class Graph:
         for k, v in kw.items():
             setattr(t, k, int(v))
         check(lib().gz_set_tuning(self._h, ctypes.byref(t)))
+
+
+class L0Sketch:
+    """Standard l0-sampler node sketches (Fig. agm_code) on the device, for comparison."""
+
+    def __init__(self, V: int, seed: int):
+        h = ctypes.c_void_p()
+        check(lib().gz_l0_init(ctypes.byref(h), V, seed & 0xFFFFFFFFFFFFFFFF))
+        self._h = h
+        _track("graph", self)
+        dims = [ctypes.c_uint32() for _ in range(4)]
+        n = ctypes.c_uint64()
+        check(lib().gz_l0_shape(h, *[ctypes.byref(d) for d in dims], ctypes.byref(n)))
+        self.V, self.R, self.C, self.B = (d.value for d in dims)
+        self.n = n.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().gz_l0_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def ingest(self, src, dst, op=None, stream=None):
+        ps, fs, ks = _u32_arg(src)
+        pd, fd, kd = _u32_arg(dst)
+        if fs != fd:
+            raise ValueError("src and dst must both live on the host or both on the device")
+        pop, kop = None, None
+        if op is not None:
+            if _is_torch(op):
+                if bool(op.is_cuda) != bool(fs & GZ_DEVICE_PTR):
+                    raise ValueError("op must live where src and dst do")
+                kop, pop = op, ctypes.c_void_p(op.data_ptr())
+            else:
+                if fs & GZ_DEVICE_PTR:
+                    raise ValueError("op must live where src and dst do")
+                kop = np.ascontiguousarray(op, np.uint8)
+                pop = ctypes.c_void_p(kop.ctypes.data)
+        return check(lib().gz_l0_ingest(self._h, ps, pd, pop, len(ks), fs, _stream_handle(stream)))
+
+    def reset(self, stream=None):
+        return check(lib().gz_l0_reset(self._h, _stream_handle(stream)))
+
+    def last_update_ms(self) -> float:
+        ms = ctypes.c_float()
+        check(lib().gz_l0_last_update_ms(self._h, ctypes.byref(ms)))
+        return float(ms.value)
+
+    def export(self, lo: int = 0, hi: int | None = None):
+        """(a, b, c): int64, int64, uint64 [hi-lo, R, C, B] in the figure's nested rows."""
+        hi = self.V if hi is None else hi
+        shape = (hi - lo, self.R, self.C, self.B)
+        a = np.zeros(shape, np.int64)
+        b = np.zeros(shape, np.int64)
+        c = np.zeros(shape, np.uint64)
+        check(lib().gz_l0_export(self._h, lo, hi, a.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                 b.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                 c.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))))
+        return a, b, c
+
+    def sample(self, r: int):
+        """-> kind int32[V] (0 zero, 1 sample, 2 fail), idx uint64[V], mult int64[V]."""
+        kind = np.zeros(self.V, np.int32)
+        idx = np.zeros(self.V, np.uint64)
+        mult = np.zeros(self.V, np.int64)
+        check(lib().gz_l0_sample(self._h, r, kind.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                 idx.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
+                                 mult.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))))
+        return kind, idx, mult
 
 
 def _handles(graphs):

@@ -20,15 +20,6 @@ uint32_t bitlen64(uint64_t x) {
     return n;
 }
 
-// SplitMix64 (Steele, Lea, Flood, OOPSLA 2014): one output per call
-uint64_t splitmix64(uint64_t& st) {
-    st += 0x9E3779B97F4A7C15ull;
-    uint64_t z = st;
-    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-    return z ^ (z >> 31);
-}
-
 // the pair-keyed form of wide graphs: ((a*u + a2*v + b) mod 2^64) >> 32
 uint32_t host_hash_pair(uint64_t a, uint64_t a2, uint64_t b, uint32_t u, uint32_t v) {
     return (uint32_t)((a * u + a2 * v + b) >> 32);
@@ -299,7 +290,7 @@ gz_status init_graph(gz_graph** out, uint32_t V, uint64_t seed, const gz_config*
     uint64_t st = seed;
     for (uint32_t p = 0; p < g->P; ++p)
         for (uint32_t k = 0; k < per_pair; ++k)
-            g->seeds_host[(size_t)p * per_pair + k] = splitmix64(st);
+            g->seeds_host[(size_t)p * per_pair + k] = splitmix64_next(st);
     for (uint32_t p = 0; p < g->P; ++p) {
         const uint64_t* s = &g->seeds_host[(size_t)p * per_pair];
         // edge 0 = pair (0, 1) must keep a non-zero checksum

@@ -239,6 +239,14 @@ gz_status hip_fail(hipError_t e, const char* what);
         return e_ == hipSuccess ? GZ_OK : ::gz::hip_fail(e_, #call); }())
 
 int device_cu_count();
+// SplitMix64 (Steele, Lea, Flood, OOPSLA 2014): the next output of the stream
+inline uint64_t splitmix64_next(uint64_t& st) {
+    st += 0x9E3779B97F4A7C15ull;
+    uint64_t z = st;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
 // true if a handle is null or listed twice
 inline bool bad_graph_list(gz_graph* const* gs, uint32_t G) {
     std::vector<gz_graph*> v(gs, gs + G);

@@ -76,7 +76,7 @@ def make_workload(name: str):
     if name == "rmat_kron18":
         s = workloads.rmat_draws(1 << 18, workloads.RMAT_GRAPH500, 1 << 28, 18)
         desc = ("R-MAT V=2^18 (a,b,c,d=0.57,0.19,0.19,0.05, seed 18): 2^28 raw draws, a pair "
-                "drawn again toggles its edge (pair-keyed contract, R=19, B=33)")
+                "drawn again toggles its edge (pair-keyed contract, R=19, B=36)")
         return s, 18, desc
     if name == "uniform_small":
         s = workloads.config_uniform_small()

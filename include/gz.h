@@ -47,12 +47,15 @@
  * Wide graphs (65536 < V <= 2^24): n reaches 2^47, so indices are 64-bit and a
  * hash keyed by a 32-bit index no longer covers them.  The hashes are keyed by
  * the pair instead:
- *   shape   as above, but B = min(bitlen(n-1)+1, 33): the row hash has 32 bits,
- *           so no update goes deeper than row 32;
- *   seeds   the same stream gives, for r, c, k as above, three words a, a2, b;
+ *   shape   as above (B = bitlen(n-1)+1, up to 48 rows);
+ *   seeds   the same stream gives, for r = 0..R-1, c = 0..C-1 and k in (row
+ *           hash low word, checksum high, checksum low, row hash high word),
+ *           three words a, a2, b;
  *   hash    h(u, v) = ((a*u + a2*v + b) mod 2^64) >> 32 for u < v (strongly
  *           universal on pairs of 32-bit words);
- *   depth   d = min(ctz(h_row(u, v)), B-1);
+ *   depth   d = min(ctz(h_row_hi(u, v) * 2^32 + h_row_lo(u, v)), B-1), ctz(0) = 64
+ *           (a 64-bit row hash, so that rows up to log n exist for every cut
+ *           size, Lemma "goodset");
  *   bucket  alpha ^= idx(u, v) (64-bit), gamma ^= h_hi(u, v) << 32 | h_lo(u, v);
  *   query   GOOD if not EMPTY, alpha < n and gamma equals the checksum of the
  *           pair alpha encodes; otherwise as above.

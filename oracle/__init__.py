@@ -105,7 +105,7 @@ def _load():
     L.oracle_hash32_pair.argtypes = [u64, u64, u64, u32, u32]
     L.oracle_hash32_pair.restype = u32
     L.oracle_row_hash_pair.argtypes = [u64p, u32, u32, u32, u32]
-    L.oracle_row_hash_pair.restype = u32
+    L.oracle_row_hash_pair.restype = u64
     L.oracle_checksum_pair.argtypes = [u64p, u32, u32, u32, u32]
     L.oracle_checksum_pair.restype = u64
     L.oracle_bucket_class_wide.argtypes = [u64p, u32, u32, u64, u64, u64]
@@ -186,9 +186,11 @@ def hash32_pair(a: int, a2: int, b: int, u: int, v: int) -> int:
 
 
 def seed_table_wide(seed: int, R: int) -> np.ndarray:
-    tab = np.zeros(R * 8 * 9, np.uint64)
+    """uint64[R, C, 4, 3]: (a, a2, b) of the row hash's low word, checksum high, checksum low,
+    row hash's high word."""
+    tab = np.zeros(R * 8 * 12, np.uint64)
     _load().oracle_seed_table_wide(seed, R, _p(tab, ctypes.c_uint64))
-    return tab.reshape(R, 8, 3, 3)
+    return tab.reshape(R, 8, 4, 3)
 
 
 def is_wide(V: int) -> bool:
@@ -233,10 +235,10 @@ class Oracle:
 
     @property
     def seeds(self) -> np.ndarray:
-        """[R, C, 3, 2] (multiplier, increment) or, for wide graphs, [R, C, 3, 3] (a, a2, b)."""
-        w = 3 if self.wide else 2
-        n = self.R * self.C * 3 * w
-        return np.ctypeslib.as_array(self._tab, shape=(n,)).reshape(self.R, self.C, 3, w).copy()
+        """[R, C, 3, 2] (multiplier, increment) or, for wide graphs, [R, C, 4, 3] (a, a2, b)."""
+        k, w = (4, 3) if self.wide else (3, 2)
+        n = self.R * self.C * k * w
+        return np.ctypeslib.as_array(self._tab, shape=(n,)).reshape(self.R, self.C, k, w).copy()
 
     def seeds_valid(self) -> bool:
         return bool(_load().oracle_seeds_valid(self._h))

@@ -17,8 +17,8 @@
  * Readings where the paper leaves a choice open (all shared with the GPU side
  * only through this written contract, never through code):
  *   - shape: C = 8 columns, R = bitlen(V-1)+1 rounds, n = V(V-1)/2,
- *     B = min(bitlen(n-1)+1, 33) rows (the row hash has 32 bits, so no update
- *     reaches a row past 32; the cap only binds for V > 2^16);
+ *     B = bitlen(n-1)+1 rows (Lemma "goodset" needs a row i with
+ *     2^(i-2) <= |cut| < 2^(i-1) for every cut up to n edges);
  *   - the row loop of the update stops at row B-1;
  *   - seeds: a SplitMix64 stream started at the graph seed yields, for every
  *     round r, column c and hash k in (h1, h2hi, h2lo), a multiplier then an
@@ -27,7 +27,10 @@
  *   - graphs with V > 2^16 ("wide": indices need more than 31 bits) hash the
  *     node pair instead of the index, with the vector form of the same family:
  *     h(u, v) = ((a*u + a2*v + b) mod 2^64) >> 32 for u < v, and their seed
- *     stream yields, per (round, column, hash), a, a2, then b;
+ *     stream yields, per (round, column, hash), a, a2, then b, for four hashes:
+ *     row (low word), checksum high, checksum low, row (high word); their row
+ *     hash is 64 bits, row_hi * 2^32 + row_lo, since B exceeds 33 rows once
+ *     n > 2^32;
  *   - checksum = h2hi(x) * 2^32 + h2lo(x);
  *   - bucket classes: EMPTY (alpha = gamma = 0), GOOD (not EMPTY, gamma equals
  *     the checksum of alpha, alpha < n), otherwise BAD; the query scans columns
@@ -65,7 +68,6 @@ int oracle_shape(uint32_t V, uint32_t *R, uint32_t *C, uint32_t *B, uint64_t *n)
     *R = bitlen((uint64_t)V - 1) + 1;
     *C = ORACLE_C;
     *B = bitlen(pairs - 1) + 1;
-    if (*B > 33) *B = 33;
     return OR_OK;
 }
 
@@ -119,16 +121,19 @@ void oracle_seed_table(uint64_t seed, uint32_t R, uint64_t *tab) {
 }
 
 /*
- * Wide graphs: tab3[((r*C + c)*3 + k)*3 + j], j = 0: a (multiplier of the
- * smaller endpoint), 1: a2 (multiplier of the larger endpoint), 2: b.
+ * Wide graphs: tab3[((r*C + c)*4 + k)*3 + j], k = 0: row hash (low word),
+ * 1: checksum high word, 2: checksum low word, 3: row hash (high word);
+ * j = 0: a (multiplier of the smaller endpoint), 1: a2 (multiplier of the
+ * larger endpoint), 2: b.
  */
+#define WIDE_HASHES 4
 void oracle_seed_table_wide(uint64_t seed, uint32_t R, uint64_t *tab3) {
     uint64_t st = seed;
     for (uint32_t r = 0; r < R; ++r)
         for (uint32_t c = 0; c < ORACLE_C; ++c)
-            for (uint32_t k = 0; k < 3; ++k)
+            for (uint32_t k = 0; k < WIDE_HASHES; ++k)
                 for (uint32_t j = 0; j < 3; ++j)
-                    tab3[((r * ORACLE_C + c) * 3 + k) * 3 + j] = oracle_splitmix64_next(&st);
+                    tab3[((r * ORACLE_C + c) * WIDE_HASHES + k) * 3 + j] = oracle_splitmix64_next(&st);
 }
 
 /* ----------------------------------------------------------------- hash --- */
@@ -151,12 +156,15 @@ uint32_t oracle_hash32_pair(uint64_t a, uint64_t a2, uint64_t b, uint32_t u, uin
 }
 
 static const uint64_t *seed3_of(const uint64_t *tab3, uint32_t r, uint32_t c, uint32_t k) {
-    return tab3 + ((r * ORACLE_C + c) * 3 + k) * 3;
+    return tab3 + ((r * ORACLE_C + c) * WIDE_HASHES + k) * 3;
 }
 
-uint32_t oracle_row_hash_pair(const uint64_t *tab3, uint32_t r, uint32_t c, uint32_t u, uint32_t v) {
-    const uint64_t *s = seed3_of(tab3, r, c, 0);
-    return oracle_hash32_pair(s[0], s[1], s[2], u, v);
+/* the 64-bit row hash of a wide graph's pair: row_hi * 2^32 + row_lo */
+uint64_t oracle_row_hash_pair(const uint64_t *tab3, uint32_t r, uint32_t c, uint32_t u, uint32_t v) {
+    const uint64_t *lo = seed3_of(tab3, r, c, 0);
+    const uint64_t *hi = seed3_of(tab3, r, c, 3);
+    return ((uint64_t)oracle_hash32_pair(hi[0], hi[1], hi[2], u, v) << 32) |
+           (uint64_t)oracle_hash32_pair(lo[0], lo[1], lo[2], u, v);
 }
 
 uint64_t oracle_checksum_pair(const uint64_t *tab3, uint32_t r, uint32_t c, uint32_t u, uint32_t v) {
@@ -187,7 +195,7 @@ uint64_t oracle_checksum(const uint64_t *tab, uint32_t r, uint32_t c, uint64_t i
 typedef struct {
     uint32_t V, R, C, B;
     uint64_t n;
-    uint32_t wide;   /* V > 2^16: pair-keyed hashes (tab holds R*C*3*3 words) */
+    uint32_t wide;   /* V > 2^16: pair-keyed hashes (tab holds R*C*4*3 words) */
     uint64_t *tab;   /* R*C*3*2 */
     uint64_t *alpha; /* [V][R][C][B] */
     uint64_t *gamma; /* [V][R][C][B] */
@@ -207,7 +215,7 @@ oracle_t *oracle_new(uint32_t V, uint64_t seed, uint32_t R_override) {
     if (!O) return NULL;
     O->V = V; O->R = R; O->C = C; O->B = B; O->n = n;
     O->wide = (uint32_t)oracle_is_wide(V);
-    O->tab = (uint64_t *)malloc(sizeof(uint64_t) * R * C * (O->wide ? 9 : 6));
+    O->tab = (uint64_t *)malloc(sizeof(uint64_t) * R * C * (O->wide ? 3 * WIDE_HASHES : 6));
     size_t cells = (size_t)V * R * C * B;
     O->alpha = (uint64_t *)calloc(cells, sizeof(uint64_t));
     O->gamma = (uint64_t *)calloc(cells, sizeof(uint64_t));
@@ -234,7 +242,7 @@ const uint64_t *oracle_seed_ptr(const oracle_t *O) { return O->tab; }
 int oracle_wide(const oracle_t *O) { return (int)O->wide; }
 
 /* row hash and checksum of edge {u, v} (u < v, idx its index) under O's contract */
-static uint32_t key_row_hash(const oracle_t *O, uint32_t r, uint32_t c, uint64_t idx, uint32_t u,
+static uint64_t key_row_hash(const oracle_t *O, uint32_t r, uint32_t c, uint64_t idx, uint32_t u,
                              uint32_t v) {
     return O->wide ? oracle_row_hash_pair(O->tab, r, c, u, v) : oracle_row_hash(O->tab, r, c, idx);
 }
@@ -264,7 +272,7 @@ int oracle_seeds_valid(const oracle_t *O) {
 static void toggle(oracle_t *O, uint32_t w, uint64_t idx, uint32_t u, uint32_t v) {
     for (uint32_t r = 0; r < O->R; ++r)
         for (uint32_t c = 0; c < O->C; ++c) {
-            uint32_t col_hash = key_row_hash(O, r, c, idx, u, v);
+            uint64_t col_hash = key_row_hash(O, r, c, idx, u, v);
             uint64_t checksum = key_checksum(O, r, c, idx, u, v);
             uint32_t row = 0;
             while (row < O->B && (row == 0 || ((col_hash >> (row - 1)) & 1u) == 0)) {

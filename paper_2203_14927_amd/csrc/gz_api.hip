@@ -272,8 +272,8 @@ gz_status init_graph(gz_graph** out, uint32_t V, uint64_t seed, const gz_config*
     g->n = (uint64_t)V * (V - 1) / 2;
     g->R = bitlen64((uint64_t)V - 1) + 1;
     g->C = kC;
-    // a 32-bit row hash reaches rows 0..32 only (binds for V > 2^16 alone)
-    g->B = std::min<uint32_t>(bitlen64(g->n - 1) + 1, 33);
+    // B = ceil(log2 n) + 1 rows; graphs with V > 2^16 have n > 2^31 and a 64-bit row hash
+    g->B = bitlen64(g->n - 1) + 1;
     g->wide = V > kMaxNarrow;
     g->planes = g->wide ? kPlanesWide : kPlanes;
     if (cfg && cfg->rounds) g->R = cfg->rounds;
@@ -284,8 +284,9 @@ gz_status init_graph(gz_graph** out, uint32_t V, uint64_t seed, const gz_config*
     g->P = g->R * kC;
     g->seed = seed;
     // seeds: SplitMix64 stream in (round, column, hash) order; per hash a
-    // multiplier then an increment, or for wide graphs a, a2 then b
-    const uint32_t per_pair = g->wide ? 9 : 6;
+    // multiplier then an increment, or for wide graphs a, a2 then b for four
+    // hashes (row low word, checksum high, checksum low, row high word)
+    const uint32_t per_pair = g->wide ? 3 * kWideHashes : 6;
     g->seeds_host.resize((size_t)g->P * per_pair);
     uint64_t st = seed;
     for (uint32_t p = 0; p < g->P; ++p)

@@ -56,7 +56,9 @@ __device__ __forceinline__ uint32_t chk_lo(const PairSeeds& s, uint32_t x) {
 // Wide graphs (V > 2^16) hash the node pair (u < v) with the vector form of
 // the family: h(u, v) = ((a*u + a2*v + b) mod 2^64) >> 32.  Per hash the seeds
 // a, a2, b are 64-bit; on the device, word w = (k*3 + j)*2 + half of pair p
-// (k: row / checksum-high / checksum-low, j: a / a2 / b) sits at seeds[w*P + p].
+// (k: row low word / checksum-high / checksum-low / row high word, j: a / a2 / b)
+// sits at seeds[w*P + p].  The row hash is 64 bits, high word * 2^32 + low
+// word; the high word only matters when the low word is zero (depth >= 32).
 // (a*u + a2*v + b) mod 2^64 has high word hi32(alo*u + a2lo*v + b) + ahi*u + a2hi*v
 // (mod 2^32): two 64-bit multiply-adds in a chain plus two low multiplies.
 struct WideHashSeeds {
@@ -88,11 +90,27 @@ __device__ __forceinline__ uint32_t pair_hash(const WideHashSeeds& s, uint32_t u
     return (uint32_t)(t >> 32) + s.ahi * u + s.a2hi * v;
 }
 
-__device__ __forceinline__ uint32_t wide_row_depth(const WideSeeds& s, uint32_t u, uint32_t v,
-                                                   uint32_t Bm1) {
-    const uint32_t h = pair_hash(s.h[0], u, v);
-    const uint32_t tz = __builtin_ctzg(h, 32);
-    return tz < Bm1 ? tz : Bm1;
+// the high word of a wide graph's row hash (hash 3 of pair p), read from the seed
+// table.  It is needed for about one entry in 2^32, from inside the update loop:
+// the word offset passes through an empty asm before each load, so that neither
+// the six addresses nor the loads are hoisted out of that loop (they would hold
+// a dozen registers for the whole kernel).  (alo*u + a2lo*v + b) is summed in
+// another order than pair_hash's, with the same result mod 2^64.
+__device__ __forceinline__ uint32_t wide_row_hash_high(const uint32_t* __restrict__ seeds,
+                                                       uint32_t P, uint32_t p, uint32_t u,
+                                                       uint32_t v) {
+    uint32_t off = (kWideHashes - 1) * 6 * P + p;
+    uint32_t w[6];
+#pragma unroll
+    for (uint32_t k = 0; k < 6; ++k) {
+        asm volatile("" : "+v"(off));
+        w[k] = seeds[off];
+        off += P;
+    }
+    uint64_t t = (uint64_t)w[0] * u;
+    t = (uint64_t)w[2] * v + t;
+    t += (uint64_t)w[4] | ((uint64_t)w[5] << 32);
+    return (uint32_t)(t >> 32) + w[1] * u + w[3] * v;
 }
 
 // 64-bit position of pair {u, v} (ids up to 2^24)

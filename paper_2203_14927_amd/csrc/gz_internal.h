@@ -45,6 +45,11 @@ __host__ __device__ __forceinline__ uint32_t sk_word(uint32_t B, uint32_t r, uin
 // alpha high, gamma low, gamma high), the same order.
 constexpr uint32_t kPlanesWide = 4;
 constexpr uint32_t kMaxNarrow = 65536;
+// pair-keyed hashes per (round, column) of a wide graph: row (low word),
+// checksum high, checksum low, row (high word); the row hash has 64 bits
+constexpr uint32_t kWideHashes = 4;
+// rows the low word of a wide row hash reaches (0..32); deeper rows need its high word
+constexpr uint32_t kLowRowLimit = 32;
 __host__ __device__ __forceinline__ uint32_t sk_word_n(uint32_t planes, uint32_t B, uint32_t r,
                                                        uint32_t plane, uint32_t d, uint32_t c) {
     return ((r * B + d) * planes + plane) * kC + c;

@@ -208,11 +208,21 @@ template <bool kWide, int kSide>
 __device__ __forceinline__ void xor_entry_deep(uint32_t x, uint32_t node, const Lane<kWide>& ln,
                                                const ConstsOf<kWide, kSide>& nc, uint32_t Bm1,
                                                uint32_t DL, uint32_t* __restrict__ skl,
-                                               uint32_t plane_words) {
+                                               uint32_t plane_words, const GraphDesc& g) {
     uint32_t h[3];
     uint64_t idx;
     hash_entry<kWide, kSide>(x, node, ln, nc, h, &idx);
-    const uint32_t d = depth_of(h[0], Bm1);
+    uint32_t d = depth_of(h[0], Bm1);
+    if constexpr (kWide) {
+        // a zero low word of the 64-bit row hash: the depth continues into its high
+        // word (such entries always get here: tiles of wide graphs keep at most 32
+        // rows when B > 33)
+        if (h[0] == 0 && Bm1 > kLowRowLimit) {
+            const uint32_t u = min(x, node), v = max(x, node);
+            const uint32_t hh = wide_row_hash_high(g.seeds, g.P, ln.p, u, v);
+            d = min(kLowRowLimit + (uint32_t)__builtin_ctzg(hh, 32), Bm1);
+        }
+    }
     if (d < DL) return;
     uint32_t* w = skl + d * (Layout<kWide>::kPl * kC);
     atomicXor(w, (uint32_t)idx);
@@ -397,11 +407,12 @@ __device__ __forceinline__ void xor_share(const Src& ent, GroupShare r, uint4 a,
                                           uint32_t node, const Lane<kWide>& ln,
                                           const ConstsOf<kWide, kSide>& nc, uint32_t Bm1,
                                           uint32_t DL, uint32_t row_bytes, uint8_t* tb,
-                                          uint32_t* skl, uint32_t plane_words) {
+                                          uint32_t* skl, uint32_t plane_words,
+                                          const GraphDesc& g) {
     uint32_t e = r.e;
     uint4 c = make_uint4(0, 0, 0, 0), d = c;
 #define GZ_XOR(x) xor_entry<kAllRows, kWide, kSide>((x), node, ln, nc, Bm1, DL, row_bytes, tb)
-#define GZ_DEEP(x) xor_entry_deep<kWide, kSide>((x), node, ln, nc, Bm1, DL, skl, plane_words)
+#define GZ_DEEP(x) xor_entry_deep<kWide, kSide>((x), node, ln, nc, Bm1, DL, skl, plane_words, g)
     // A set of eight entries.  Three-plane graphs apply a deep entry to HBM at
     // once (their small items keep few rows, so deep entries are common there);
     // wide graphs, whose items are long, note them and apply the set's deep
@@ -492,7 +503,7 @@ __device__ __forceinline__ void apply_entries(const Src& ent, uint32_t count, ui
         uint8_t* tb = (uint8_t*)tile;
         uint32_t* skl = skn + ln.hbm_word;
         xor_share<kAllRows, kWide, kSide1>(ent, r, a, b, node, ln, nc, Bm1, DL, row_bytes, tb,
-                                           skl, plane_words);
+                                           skl, plane_words, g);
         if constexpr (kSide1 == kBelow) {
             if (split < count) {
                 const GroupShare r2 = group_share(ent, split, count, ln.J, ln.j);
@@ -503,7 +514,7 @@ __device__ __forceinline__ void apply_entries(const Src& ent, uint32_t count, ui
                 }
                 const ConstsOf<kWide, kAbove> nc2 = item_consts<kWide, kAbove>(g, ln.p, node);
                 xor_share<kAllRows, kWide, kAbove>(ent, r2, a2, b2, node, ln, nc2, Bm1, DL,
-                                                   row_bytes, tb, skl, plane_words);
+                                                   row_bytes, tb, skl, plane_words, g);
             }
         }
     }
@@ -565,7 +576,11 @@ __device__ __forceinline__ void update_items(const WorkItem* __restrict__ items,
             g = gd[cur];
             ln = make_lane<kWide>(g);
         }
-        const uint32_t DL = uniform(item_rows(w.count, g.B, lds_rows));
+        uint32_t DL = uniform(item_rows(w.count, g.B, lds_rows));
+        // wide graphs deeper than 33 rows keep at most 32 in LDS: an entry whose
+        // row hash has a zero low word then takes the deep path, which reads the
+        // hash's high word
+        if (kWide && g.B > kLowRowLimit + 1) DL = min(DL, kLowRowLimit);
         const GroupedEntries src{grouped + w.begin};
         const uint32_t node = w.gnode - g.node_base;  // graph-local id (wide hashes key on it)
         uint32_t* skn = g.sk + (uint64_t)(node - g.sk_first) * Layout<kWide>::kPl * g.B * g.P;
@@ -627,7 +642,7 @@ __global__ __launch_bounds__(1024) void k_update_node_wide(const uint32_t* __res
     if (*err) return;
     const uint32_t begin = blockIdx.x * chunk;
     const uint32_t cnt = min(chunk, count - begin);
-    const uint32_t DL = min(lds_rows, g.B);
+    const uint32_t DL = min(min(lds_rows, g.B), g.B > kLowRowLimit + 1 ? kLowRowLimit : g.B);
     const Lane<true> ln = make_lane<true>(g);
     uint32_t* skn = g.sk + (uint64_t)(node - g.sk_first) * kPlanesWide * g.B * g.P;
     apply_entries<false, true, kAnySide>(GroupedEntries{nbrs + begin}, cnt, cnt, node, ln, g, DL,

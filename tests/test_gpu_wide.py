@@ -52,10 +52,15 @@ def _trees_stream(V, used, max_size, noise, seed):
 
 
 def test_wide_shape_rule(gz):
-    """B stops at 33 (a 32-bit depth hash); R follows the usual rule."""
+    """B = bitlen(n - 1) + 1 as for narrow graphs (33 up to n = 2^32, 40 at V = 2^20, 48 at
+    V = 2^24: the row hash has 64 bits); R follows the usual rule."""
     g = gz.Graph(70000, seed=3, rounds=2)
     assert (g.V, g.R, g.C, g.B) == (70000, 2, 8, 33)
     assert g.n == 70000 * 69999 // 2
+    for V, B in [(92682, 33), (92683, 34), (1 << 20, 40), (1 << 24, 48)]:
+        g = gz.Graph(V, seed=3, rounds=1)
+        assert g.B == B == (V * (V - 1) // 2 - 1).bit_length() + 1, V
+        g.close()
     g = gz.Graph(65537, seed=3, rounds=1)
     assert g.B == 33 and g.n == 65537 * 65536 // 2
     g = gz.Graph(65536, seed=3, rounds=1)
@@ -122,7 +127,7 @@ def test_wide_kron18_sampled_nodes_and_labels(gz):
     V, seed = 1 << 18, 2018
     s, _ = workloads.rmat_session(V, workloads.RMAT_GRAPH500, 3_000_000, 0.1, 18)
     g = gz.Graph(V, seed=seed)
-    assert g.R == 19 and g.B == 33
+    assert g.R == 19 and g.B == 36
     g.ingest(to_dev(s.src), to_dev(s.dst))
     deg = np.bincount(np.concatenate([s.src, s.dst]).astype(np.int64), minlength=V)
     rng = np.random.default_rng(3)
@@ -296,3 +301,48 @@ def test_wide_single_graph_plan_replays(gz):
     x1, y1 = eager.export(0, 4096)
     x2, y2 = planned.export(0, 4096)
     assert (x1 == x2).all() and (y1 == y2).all()
+
+
+def _zero_low_pair(seed, c):
+    """A pair u < v < 2^20 whose row hash in column c of round 0 has a zero low word."""
+    import wide_pairs
+
+    tab = oracle.seed_table_wide(seed, 1)
+    a, a2, b = (int(t) for t in tab[0, c, 0])
+    u, v = wide_pairs.zero_low_row_pair(a, a2, b, 1 << 20)
+    assert ((a * u + a2 * v + b) % (1 << 64)) >> 32 == 0
+    return u, v
+
+
+@pytest.mark.parametrize("path", ["fused", "per_node"])
+def test_wide_rows_past_32(gz, path):
+    """V = 2^20 (B = 40), one round: an edge whose 64-bit row hash has a zero low word
+    lands in a row past 32 (the hash's high word decides how far), among a few thousand
+    other edges at both of its nodes, through the grouped path and the per-node path;
+    those node sketches bit-exact with the oracle, and their queries sample it."""
+    V, seed, c = 1 << 20, 99, 3
+    u, v = _zero_low_pair(seed, c)
+    rng = np.random.default_rng(8)
+    others = rng.integers(0, V, 6000).astype(np.uint32)
+    nu = others[:3000][(others[:3000] != u) & (others[:3000] != v)]
+    nv = others[3000:][(others[3000:] != u) & (others[3000:] != v)]
+    src = np.concatenate([np.full(len(nu), u, np.uint32), np.full(len(nv), v, np.uint32),
+                          np.array([u], np.uint32)])
+    dst = np.concatenate([nu, nv, np.array([v], np.uint32)])
+    g = gz.Graph(V, seed=seed, rounds=1)
+    assert g.B == 40
+    if path == "fused":
+        order = rng.permutation(len(src))
+        g.ingest(to_dev(src[order]), to_dev(dst[order]))
+        nodes = [u, v, int(nu[0]), int(nv[-1])]
+    else:
+        for node, nb in [(u, np.concatenate([nu, [v]])), (v, np.concatenate([[u], nv]))]:
+            g.update_sketch_batch(node, to_dev(nb.astype(np.uint32)))
+        nodes = [u, v]
+    O = oracle.Oracle(V, seed, R=1)
+    O.ingest_nodes(src, dst, nodes)
+    deep = [bb for bb in range(O.B) if O.alpha[u, 0, c, bb] != 0]
+    assert max(deep) >= 32  # the pair reaches past row 31 in u's sketch
+    for w in nodes:
+        a, b = g.export(w, w + 1)
+        assert (a[0] == O.alpha[w]).all() and (b[0] == O.gamma[w]).all(), f"node {w}"

@@ -511,19 +511,27 @@ def test_invalid_updates_rejected_atomically(built):
 
 # ------------------------------------------------------- wide graphs (V > 2^16) ---
 
-def test_wide_shape_caps_rows_at_the_row_hash_width(built):
-    """B = min(bitlen(n-1)+1, 33): a 32-bit row hash reaches rows 0..32 only."""
+def test_wide_shape_keeps_log_n_rows(built):
+    """B = ceil(log2 n) + 1 for every V (Lemma goodset needs a row i with
+    2^(i-2) <= |cut| < 2^(i-1) for cuts of up to n edges): 33 rows at V = 2^16 + 1, 48 at 2^24."""
     assert not oracle.is_wide(1 << 16) and oracle.is_wide((1 << 16) + 1)
     assert oracle.shape(1 << 16)[2] == 32
-    for V, R in [((1 << 16) + 1, 18), (100000, 18), (1 << 18, 19), (1 << 20, 21), (1 << 24, 25)]:
+    for V, R, B in [((1 << 16) + 1, 18, 33), (100000, 18, 34), (1 << 18, 19, 36),
+                    (1 << 20, 21, 40), (1 << 24, 25, 48)]:
         r, c, b, n = oracle.shape(V)
-        assert (r, c, b, n) == (R, 8, 33, V * (V - 1) // 2)
+        k = 0
+        while (1 << k) < n:
+            k += 1
+        assert (r, c, b, n) == (R, 8, B, V * (V - 1) // 2) and b == k + 1
 
 
 def test_wide_seed_table_is_the_splitmix_stream(built):
+    """Per (round, column): row hash low word, checksum high, checksum low, row hash high word,
+    each (a, a2, b), in SplitMix64 order."""
     R = 4
     tab = oracle.seed_table_wide(4242, R)
-    assert tab.reshape(-1).tolist() == oracle.splitmix64(4242, R * 8 * 9)
+    assert tab.shape == (R, 8, 4, 3)
+    assert tab.reshape(-1).tolist() == oracle.splitmix64(4242, R * 8 * 12)
     O = oracle.Oracle(70000, 4242, R=R)
     assert O.wide and (O.seeds == tab).all()
 
@@ -586,9 +594,10 @@ def test_wide_sketch_equals_closed_form_eq_1_2(built):
             i = v * (v - 1) // 2 + u
             for r in range(R):
                 for c in range(8):
-                    (a1, a1b, b1), (ah, ahb, bh), (al_, alb, bl) = [
-                        tuple(int(t) for t in tab[r, c, k]) for k in range(3)]
-                    h1 = ((a1 * u + a1b * v + b1) & M64) >> 32
+                    (a1, a1b, b1), (ah, ahb, bh), (al_, alb, bl), (a4, a4b, b4) = [
+                        tuple(int(t) for t in tab[r, c, k]) for k in range(4)]
+                    h1 = ((((a4 * u + a4b * v + b4) & M64) >> 32) << 32) | \
+                        (((a1 * u + a1b * v + b1) & M64) >> 32)
                     chk = ((((ah * u + ahb * v + bh) & M64) >> 32) << 32) | \
                         (((al_ * u + alb * v + bl) & M64) >> 32)
                     for b in range(B):
@@ -596,6 +605,31 @@ def test_wide_sketch_equals_closed_form_eq_1_2(built):
                             al[r, c, b] ^= np.uint64(i)
                             ga[r, c, b] ^= np.uint64(chk)
         assert (O.alpha[w] == al).all() and (O.gamma[w] == ga).all(), w
+
+
+def test_wide_row_hash_high_word_sets_rows_past_32(built):
+    """A pair whose 64-bit row hash has a zero low word reaches rows 32 + ctz(high word): rows
+    past 32 exist once n > 2^32 (V = 2^20: B = 40) and take exactly such pairs."""
+    import wide_pairs
+
+    V, seed, R = 1 << 20, 99, 1
+    tab = oracle.seed_table_wide(seed, R)
+    c = 3
+    a, a2, b = (int(t) for t in tab[0, c, 0])
+    u, v = wide_pairs.zero_low_row_pair(a, a2, b, V)
+    assert ((a * u + a2 * v + b) & M64) >> 32 == 0
+    a4, a4b, b4 = (int(t) for t in tab[0, c, 3])
+    hi = ((a4 * u + a4b * v + b4) & M64) >> 32
+    depth = min(32 + ((hi & -hi).bit_length() - 1 if hi else 32), 39)
+    O = oracle.Oracle(V, seed, R=R)
+    assert O.B == 40
+    O.update(u, v)
+    i = oracle.edge_index(u, v)
+    assert O.row_hash(0, c, i) == hi << 32
+    for w in (u, v):
+        rows = [bb for bb in range(O.B) if O.alpha[w, 0, c, bb] != 0]
+        assert rows == list(range(depth + 1)) and all(O.alpha[w, 0, c, :depth + 1] == i)
+        assert O.query_node(w, 0) == (oracle.SAMPLE, i)
 
 
 def test_wide_support_one_is_recovered(built):

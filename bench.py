@@ -348,11 +348,16 @@ def main() -> int:
                     help="explicit launch parameters wg_size,lds_rows,chunk,wgs_per_cu,group_blocks "
                          "(skips the cache and the autotuner)")
     ap.add_argument("--sessions", type=int, default=256, help="serving: number of sessions")
-    ap.add_argument("--batches", type=int, default=100, help="serving: batches per session")
+    ap.add_argument("--batches", type=int, default=200, help="serving: batches per session")
+    ap.add_argument("--loads", default="0.5,0.8,1.0",
+                    help="serving: open-loop offered loads as fractions of the closed-loop rate "
+                         "(empty: closed loop only)")
     ap.add_argument("--hbm-budget-gb", type=float, default=120.0, help="serving: admission budget")
     ap.add_argument("--tick-updates", type=int, default=16 << 20, help="serving: updates per tick")
+    ap.add_argument("--gen-workers", type=int, default=16,
+                    help="serving: processes generating the session streams (1: in-process)")
     ap.add_argument("--client-threads", type=int, default=16,
-                    help="serving: host threads driving the sessions' closed-loop clients")
+                    help="serving: native client threads of the replay driver")
     ap.add_argument("--staging-mb", type=int, default=128,
                     help="host tier: device bytes of the two slab buffers")
     ap.add_argument("--peaks", action="store_true",
@@ -646,15 +651,38 @@ def _gen_session(arg):
     return st.src, st.dst
 
 
+def _session_bytes(V: int) -> int:
+    """Device bytes the server charges a session against its budget: sketches plus query
+    scratch (12 bytes per bucket, R x C x B buckets per node)."""
+    n = V * (V - 1) // 2
+    R, B = (V - 1).bit_length() + 1, (n - 1).bit_length() + 1
+    return 12 * B * R * 8 * V + V * (3 * B * 8 * 4 + 96)
+
+
+def _mean(a) -> float:
+    import numpy as np
+
+    return float(np.mean(a)) if len(a) else 0.0
+
+
+def _pcts(ns):
+    """p50/p99 in ms of a latency array in ns."""
+    import numpy as np
+
+    if len(ns) == 0:
+        return None
+    x = np.asarray(ns, np.float64) / 1e6
+    return {"p50": float(np.percentile(x, 50)), "p99": float(np.percentile(x, 99)), "n": len(x)}
+
+
 def run_serving(args) -> dict:
-    """Many graph sessions through the server: closed-loop clients, p50/p99 latencies."""
-    import threading
+    """Many graph sessions through the server, driven by the library's native replay
+    clients: a closed-loop run (capacity), then open-loop runs at fractions of it."""
     from concurrent.futures import ProcessPoolExecutor
 
     import numpy as np
 
     import workloads
-    from paper_2203_14927_amd.server import Server
 
     S = args.sessions
     Vs = workloads.serving_sessions(seed=5, S=S)
@@ -663,89 +691,108 @@ def run_serving(args) -> dict:
         sizes = workloads.pareto_batch_sizes(5, 100 + k, args.batches)
         plans.append((V, 5000 + k, sizes))
     t0 = time.perf_counter()
-    with ProcessPoolExecutor(max_workers=min(16, os.cpu_count() or 4)) as ex:
-        data = list(ex.map(_gen_session, [(V, sd, int(sz.sum())) for V, sd, sz in plans]))
-    total = sum(int(sz.sum()) for _, _, sz in plans)
-    log(f"[bench] serving: {S} sessions, {total} updates generated in "
+    jobs = [(V, sd, int(sz.sum())) for V, sd, sz in plans]
+    if args.gen_workers > 1:
+        with ProcessPoolExecutor(max_workers=min(args.gen_workers, os.cpu_count() or 4)) as ex:
+            data = list(ex.map(_gen_session, jobs))
+    else:
+        data = [_gen_session(j) for j in jobs]
+    src = np.concatenate([d[0] for d in data])
+    dst = np.concatenate([d[1] for d in data])
+    sizes = np.concatenate([sz for _, _, sz in plans]).astype(np.uint64)
+    offs = np.zeros(len(sizes) + 1, np.uint64)
+    offs[1:] = np.cumsum(sizes)
+    total, n_batches = int(offs[-1]), len(sizes)
+    first = np.zeros(S + 1, np.int64)
+    first[1:] = np.cumsum([len(sz) for _, _, sz in plans])
+    log(f"[bench] serving: {S} sessions, {n_batches} batches, {total} updates generated in "
         f"{time.perf_counter() - t0:.1f} s")
-    srv = Server(hbm_budget=int(args.hbm_budget_gb * (1 << 30)), tick_updates=args.tick_updates)
-    lat_upd, lat_q, errors = [], [], []
-    lock = threading.Lock()
+    gpu_init()  # after the generator processes have forked
+    from paper_2203_14927_amd.server import Server
 
-    def clients(t):
-        """Closed-loop clients of the sessions k = t, t + T, ...: each session keeps
-        exactly one request outstanding (its next batch after the previous one
-        completed, a query after every 50th batch and the last); one thread waits
-        on the group's requests in submission order."""
-        import collections
+    budget = int(args.hbm_budget_gb * (1 << 30))
+    queries_of = lambda q: q[q > 0]  # noqa: E731
 
-        try:
-            mine = list(range(t, S, args.client_threads))
-            st = {}
-            pending = collections.deque()
+    def once(opens=None, arrival=None):
+        srv = Server(hbm_budget=budget, tick_updates=args.tick_updates)
+        sess = [(V, sd, int(first[k]), len(sz), 0 if opens is None else int(opens[k]))
+                for k, (V, sd, sz) in enumerate(plans)]
+        r = srv.replay(sess, offs, src, dst, arrival, query_every=50,
+                       client_threads=args.client_threads)
+        st = srv.stats()
+        st["timeline"] = srv.timeline()
+        srv.close()
+        return r, st
 
-            def next_request(k):
-                c = st[k]
-                V, seed, sizes = plans[k]
-                if c["query_due"]:
-                    c["query_due"] = False
-                    c["ticket"], c["kind"] = c["sess"].submit_query(), "q"
-                elif c["b"] < len(sizes):
-                    n = int(sizes[c["b"]])
-                    src, dst = data[k]
-                    c["ticket"] = c["sess"].submit_updates(src[c["at"]:c["at"] + n],
-                                                           dst[c["at"]:c["at"] + n])
-                    c["kind"] = "u"
-                    c["at"] += n
-                    c["b"] += 1
-                    c["query_due"] = c["b"] % 50 == 0 or c["b"] == len(sizes)
-                else:
-                    c["sess"].close()
-                    return
-                pending.append(k)
-
-            for k in mine:
-                V, seed, _ = plans[k]
-                st[k] = {"sess": srv.open(V, seed), "at": 0, "b": 0, "query_due": False}
-                next_request(k)
-            while pending:
-                k = pending.popleft()
-                r = st[k]["ticket"].wait()
-                with lock:
-                    (lat_q if st[k]["kind"] == "q" else lat_upd).append(r["latency_ms"])
-                next_request(k)
-        except Exception as e:
-            errors.append(e)
-
-    th = [threading.Thread(target=clients, args=(t,)) for t in range(min(S, args.client_threads))]
-    t0 = time.perf_counter()
-    for t in th:
-        t.start()
-    for t in th:
-        t.join()
-    wall = time.perf_counter() - t0
-    stats = srv.stats()
-    srv.close()
-    if errors:
-        raise errors[0]
-    pct = lambda a, q: float(np.percentile(np.array(a), q)) if a else None  # noqa: E731
-    log(f"[bench] serving: {wall:.1f} s, {total / wall / 1e6:.1f} M updates/s, "
-        f"batch p50/p99 {pct(lat_upd, 50):.2f}/{pct(lat_upd, 99):.2f} ms, "
-        f"query p50/p99 {pct(lat_q, 50):.2f}/{pct(lat_q, 99):.2f} ms, stats {stats}")
+    r, stats = once()
+    wall = r["wall_ns"] / 1e9
+    cap = total / wall
+    tl = stats.pop("timeline")
+    timeline = {
+        "ticks": len(tl),
+        "device_busy_frac": float(tl["device_ms"].sum() / 1e3 / wall),
+        "device_ms_per_tick": _mean(tl["device_ms"]),
+        "updates_per_tick": _mean(tl["updates"]),
+        "batches_per_tick": _mean(tl["batches"]),
+        "graphs_per_tick": _mean(tl["graphs"]),
+        "host_build_launch_ms_per_tick": _mean((tl["launched_ns"] - tl["take_ns"]) / 1e6),
+        "launch_to_seen_done_ms_per_tick": _mean((tl["done_ns"] - tl["launched_ns"]) / 1e6),
+        "device_updates_per_s": float(tl["updates"].sum() / max(tl["device_ms"].sum() / 1e3,
+                                                                1e-9)),
+    }
+    log(f"[bench] serving timeline (closed loop): {timeline}")
+    closed = {"batch": _pcts(r["batch_latency_ns"]),
+              "query": _pcts(queries_of(r["query_latency_ns"]))}
+    log(f"[bench] serving closed loop: {wall:.2f} s, {cap / 1e6:.1f} M updates/s, batch "
+        f"{closed['batch']}, query {closed['query']}, stats {stats}")
+    # Open loop: sessions arrive over time and live for their batches, so that about
+    # n_conc of them (60% of what the budget holds on average: session sizes span 64x,
+    # so the budget still binds at times) are open at once; each open session's
+    # batches arrive as a Poisson process whose rate makes the steady offered load
+    # `load` times the closed-loop rate.
+    mean_bytes = float(np.mean([_session_bytes(V) for V in Vs]))
+    n_conc = max(1, min(S, int(0.6 * budget / mean_bytes)))
+    mean_batch = total / n_batches
+    open_runs = []
+    for load in ([float(x) for x in args.loads.split(",")] if args.loads else []):
+        rate = load * cap / (n_conc * mean_batch)  # batches/s per open session
+        life = args.batches / rate
+        rng = np.random.default_rng([5, int(load * 1000)])
+        opens = np.cumsum(rng.exponential(life / n_conc, S)) * 1e9
+        arrival = np.zeros(n_batches, np.float64)
+        for k in range(S):
+            gaps = rng.exponential(1e9 / rate, int(first[k + 1] - first[k]))
+            arrival[first[k]:first[k + 1]] = opens[k] + np.cumsum(gaps)
+        r, st = once(opens.astype(np.uint64), arrival.astype(np.uint64))
+        st.pop("timeline")
+        w = r["wall_ns"] / 1e9
+        run = {"load": load, "offered_updates_per_s": load * cap, "sessions_open": n_conc,
+               "achieved_updates_per_s": total / w, "wall_s": w,
+               "batch_latency_ms": _pcts(r["batch_latency_ns"]),
+               "batch_latency_in_service_ms": _pcts(r["batch_service_ns"]),
+               "query_latency_ms": _pcts(queries_of(r["query_latency_ns"])),
+               "ticks": st["ticks"]}
+        open_runs.append(run)
+        log(f"[bench] serving open loop at {load:.0%}: {w:.2f} s, "
+            f"{total / w / 1e6:.1f} M updates/s over the run, batch {run['batch_latency_ms']}, "
+            f"in service {run['batch_latency_in_service_ms']}, query {run['query_latency_ms']}")
     return {
         "metric": "edge updates/sec ingested (1 MI355X), batched vs plain; CC query ms; p99 latency",
-        "value": total / wall, "unit": "updates/s", "n_gpus": 1, "steps": 1, "warmup": 0,
+        "value": cap, "unit": "updates/s", "n_gpus": 1, "steps": 1, "warmup": 0,
         "ms_per_step": wall * 1e3, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "u64", "data": "synthetic",
         "config": {"workload": f"serving: {S} R-MAT sessions, V=round(2^U(10,16)), Pareto(1.5) "
                                f"batches in [1e3,1e6], {args.batches} batches each, a query every "
-                               f"50 batches, closed-loop clients (one request outstanding per session, "
-                               f"{min(S, args.client_threads)} host threads; seed 5)",
-                   "sessions": S, "updates": total, "hbm_budget_gb": args.hbm_budget_gb,
-                   "tick_updates": args.tick_updates},
-        "batch_latency_ms": {"p50": pct(lat_upd, 50), "p99": pct(lat_upd, 99),
-                             "n": len(lat_upd)},
-        "query_latency_ms": {"p50": pct(lat_q, 50), "p99": pct(lat_q, 99), "n": len(lat_q)},
+                               f"50 batches and after the last; closed loop (one request "
+                               f"outstanding per session, {args.client_threads} native client "
+                               f"threads), then open-loop Poisson arrivals at {args.loads} of the "
+                               f"closed-loop rate with sessions arriving over time; seed 5",
+                   "sessions": S, "batches": n_batches, "updates": total,
+                   "hbm_budget_gb": args.hbm_budget_gb, "tick_updates": args.tick_updates},
+        "batch_latency_ms": closed["batch"],
+        "query_latency_ms": closed["query"],
+        "open_loop": open_runs,
+        "timeline": timeline,
         "server": stats,
     }
 

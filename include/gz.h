@@ -80,7 +80,8 @@ enum {
     GZ_EDEVICE = 3,       /* a HIP runtime call failed */
     GZ_ESKETCH_FAIL = 4,  /* Boruvka ran out of rounds with a component still active */
     GZ_EBUSY = 5,         /* server: queue full or session not admitted yet */
-    GZ_ESTATE = 6         /* call not valid in the object's current state */
+    GZ_ESTATE = 6,        /* call not valid in the object's current state */
+    GZ_ETIMEOUT = 7       /* server: no ticket completed within the timeout */
 };
 
 #define GZ_DEVICE_PTR 0x1u
@@ -379,23 +380,46 @@ gz_status gz_measure_peaks(gz_peaks* out, hipStream_t stream);
  *   tick packs the update batches queued by every admitted session (up to
  *   `tick_updates` updates, 0 = 16 Mi) into one fused multi-graph ingest
  *   (continuous batching: batches submitted while a tick runs join the next);
- *   a query runs on one of four query threads, on its session's own stream,
- *   once every batch submitted before it in its session has been applied, and
- *   the session's later batches wait for it; queries of different sessions
- *   and the next ticks' ingests overlap on the device.  A session's requests
+ *   a query is answered once every batch submitted before it in its session
+ *   has been applied, and the session's later batches wait for it; the
+ *   queries queued at that time are answered together by one fused Boruvka
+ *   run over their graphs (gz_connected_components_multi), on one of two
+ *   query threads, overlapping the next ticks' ingests on the device.  A session's requests
  *   take effect in submission order, so every result is the one the session
  *   would get alone.  All calls are thread-safe.
- * gz_submit_updates copies the host arrays (validated: GZ_EINVAL applies
- *   nothing); gz_submit_query writes V labels into `labels` (host, nullable)
- *   before its ticket completes.  gz_wait blocks until the ticket completes,
- *   fills *res (nullable) and releases the ticket; it returns the request's
- *   status (a query whose sketches ran out of rounds reports GZ_ESKETCH_FAIL in
- *   res->status only).  Timestamps are steady-clock nanoseconds: submit, start
+ * gz_submit_updates copies the batch (host memory, validated while copied:
+ *   GZ_EINVAL applies nothing) into a pinned buffer, the only host copy it
+ *   makes; the caller's arrays are free again when the call returns.
+ * gz_submit_updates_inplace takes src/dst in device memory of the server's GPU
+ *   or in pinned host memory (hipHostMalloc), and reads them where they are:
+ *   they must hold the batch when the call is made (device memory: its
+ *   producing work complete) and stay unchanged until the ticket completes.
+ *   Validated at submission (device memory by a kernel, with a synchronous
+ *   wait); other memory is rejected with GZ_EINVAL.
+ *   Per tick, one kernel gathers the tick's batches from their pinned or
+ *   device buffers into HBM staging, and one fused ingest applies them.
+ * gz_submit_query writes V labels into `labels` (host, nullable) before its
+ *   ticket completes.  gz_wait blocks until the ticket completes, fills *res
+ *   (nullable) and releases the ticket; it returns the request's status (a
+ *   query whose sketches ran out of rounds reports GZ_ESKETCH_FAIL in
+ *   res->status only).  gz_wait_any waits for the first of n tickets (one
+ *   server) to complete, up to timeout_ns (UINT64_MAX: no limit), sets *index
+ *   and releases that ticket as gz_wait does; GZ_ETIMEOUT (index = n) if none
+ *   completed in time, the tickets staying valid.  A client that drives
+ *   several sessions waits with gz_wait_any: waiting on one session's ticket
+ *   while another of its sessions holds HBM that a waiting session needs
+ *   would never end.  Timestamps are steady-clock nanoseconds: submit, start
  *   of processing, completion.
  * gz_session_open takes 2 <= V <= 65536 (sessions share fused calls); else
  *   GZ_EINVAL.
+ * gz_session_graph gives the session's graph handle (export, query), for use
+ *   while none of the session's requests is queued or running; GZ_ESTATE
+ *   before admission or with requests in flight.  The server keeps ownership.
  * gz_session_close waits for the session's requests and frees its sketches;
  *   gz_server_destroy stops the server and frees every session.
+ * Statistics: ticks, updates applied, queries, sessions; batches submitted by
+ *   copy and in place; bytes the gather kernels staged; worker time blocked on
+ *   a staging set and spent building and launching ticks.
  * ---------------------------------------------------------------------- */
 typedef struct gz_server gz_server;
 typedef struct gz_session gz_session;
@@ -407,21 +431,77 @@ typedef struct gz_result {
     uint32_t reserved;
     uint64_t updates;     /* update batches: number of updates */
     uint64_t submit_ns, start_ns, done_ns;
+    uint64_t admit_ns;    /* when the session was admitted (its sketches allocated) */
 } gz_result;
 typedef struct gz_server_stats {
     uint64_t ticks, updates, queries;
     uint64_t sessions_admitted, sessions_active, sessions_waiting;
     uint64_t hbm_used, hbm_budget;
+    uint64_t batches_copied, batches_inplace, staged_bytes;
+    uint64_t worker_wait_ns, worker_launch_ns;
+    uint64_t query_runs;  /* fused Boruvka runs that answered the queries */
 } gz_server_stats;
 gz_status gz_server_create(uint64_t hbm_budget, uint64_t tick_updates, gz_server** out);
 gz_status gz_session_open(gz_server* srv, uint32_t V, uint64_t seed, gz_session** out);
 gz_status gz_submit_updates(gz_session* s, const uint32_t* src, const uint32_t* dst, uint64_t N,
                             gz_ticket** out);
+gz_status gz_submit_updates_inplace(gz_session* s, const uint32_t* src, const uint32_t* dst,
+                                    uint64_t N, gz_ticket** out);
 gz_status gz_submit_query(gz_session* s, uint32_t* labels, gz_ticket** out);
 gz_status gz_wait(gz_ticket* t, gz_result* res);
+gz_status gz_wait_any(gz_ticket* const* tickets, uint32_t n, uint64_t timeout_ns,
+                      uint32_t* index, gz_result* res);
+gz_status gz_session_graph(gz_session* s, gz_graph** out);
 gz_status gz_session_close(gz_session* s);
 gz_status gz_server_get_stats(gz_server* srv, gz_server_stats* out);
+/* gz_server_timeline -- the first min(cap, *n) tick records (of the first 2^20
+ *   ticks), *n = ticks recorded: when the worker took the tick, when its
+ *   gather and ingest were enqueued, when the worker saw them complete
+ *   (steady-clock ns), its updates, batches and graphs, and the device time
+ *   from its first to its last kernel. */
+typedef struct gz_tick_record {
+    uint64_t take_ns, launched_ns, done_ns;
+    uint64_t updates;
+    uint32_t batches, graphs;
+    float device_ms;
+    uint32_t reserved;
+} gz_tick_record;
+gz_status gz_server_timeline(gz_server* srv, gz_tick_record* out, uint64_t cap, uint64_t* n);
 gz_status gz_server_destroy(gz_server* srv);
+
+/* gz_server_replay -- drive a multi-session workload through `srv` from
+ *   client_threads native threads (the serving path's load generator), and
+ *   time every request.  Session k (V, seed) owns batches first_batch ..
+ *   first_batch + n_batches - 1 of the batch table: batch b is updates
+ *   batch_offs[b] .. batch_offs[b+1]-1 of src/dst (host memory, n_batches+1
+ *   offsets).  A query follows every query_every-th batch of a session (0:
+ *   none) and its last batch.
+ *   Closed loop (arrival_ns NULL): every session opens at the start and keeps
+ *   one request outstanding, its next batch submitted when all its earlier
+ *   requests completed.  Open loop: session k opens at open_ns after the
+ *   start and batch b is submitted at arrival_ns[b] after the start (host
+ *   arrays, arrival of a session's first batch >= its open_ns), whatever has
+ *   completed.  A session closes after its last request completes; sessions
+ *   are admitted by the server's HBM budget as usual.
+ *   Outputs (host arrays of n_batches entries, nullable): per batch its
+ *   latency (completion - arrival; closed loop: - submission), its service
+ *   latency (completion - the later of arrival and the session's admission),
+ *   and the latency of the query that follows it (0 where none); *wall_ns the
+ *   time from the start to the last completion.  Client thread t drives the
+ *   sessions k = t, t + T, ...; each waits with gz_wait_any. */
+typedef struct gz_replay_session {
+    uint32_t V;
+    uint32_t n_batches;
+    uint64_t seed;
+    uint64_t first_batch;
+    uint64_t open_ns;
+} gz_replay_session;
+gz_status gz_server_replay(gz_server* srv, const gz_replay_session* sessions, uint32_t n_sessions,
+                           const uint64_t* batch_offs, uint64_t n_batches, const uint32_t* src,
+                           const uint32_t* dst, const uint64_t* arrival_ns, uint32_t query_every,
+                           uint32_t client_threads, uint64_t* batch_latency_ns,
+                           uint64_t* batch_service_ns, uint64_t* query_latency_ns,
+                           uint64_t* wall_ns);
 
 /* ------------------------------------------------------------------------
  * The standard l0-sampler (Sec. 3, Fig. "agm_code"): the sketch CubeSketch

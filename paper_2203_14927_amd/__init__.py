@@ -20,7 +20,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libgz.so")
 
-GZ_OK, GZ_EINVAL, GZ_ENOMEM, GZ_EDEVICE, GZ_ESKETCH_FAIL, GZ_EBUSY, GZ_ESTATE = range(7)
+GZ_OK, GZ_EINVAL, GZ_ENOMEM, GZ_EDEVICE, GZ_ESKETCH_FAIL, GZ_EBUSY, GZ_ESTATE, GZ_ETIMEOUT = range(8)
 GZ_DEVICE_PTR = 0x1
 GZ_ASYNC = 0x2
 GZ_UNCHECKED = 0x4
@@ -249,13 +249,29 @@ class Graph:
         self.V, self.R, self.C, self.B = (d.value for d in dims)
         self.n = n.value
 
+    @classmethod
+    def borrowed(cls, h):
+        """A view of a graph owned elsewhere (a server session): close() frees nothing."""
+        self = cls.__new__(cls)
+        self._h = h
+        self._borrowed = True
+        self.seed = None
+        L = lib()
+        dims = [ctypes.c_uint32() for _ in range(4)]
+        n = ctypes.c_uint64()
+        check(L.gz_shape(h, *[ctypes.byref(d) for d in dims], ctypes.byref(n)))
+        self.V, self.R, self.C, self.B = (d.value for d in dims)
+        self.n = n.value
+        return self
+
     @property
     def handle(self):
         return self._h
 
     def close(self):
         if getattr(self, "_h", None):
-            lib().gz_free(self._h)
+            if not getattr(self, "_borrowed", False):
+                lib().gz_free(self._h)
             self._h = None
 
     def __del__(self):

@@ -11,7 +11,8 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgz.so")
 
 SOURCES = ["gz_api.hip", "gz_ingest.hip", "gz_update.hip", "gz_query.hip", "gz_tier.hip",
-           "gz_server.hip", "gz_autotune.hip", "gz_noalloc.hip", "gz_calibrate.hip", "gz_l0.hip"]
+           "gz_server.hip", "gz_autotune.hip", "gz_noalloc.hip", "gz_calibrate.hip", "gz_l0.hip",
+           "gz_replay.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

@@ -328,28 +328,37 @@ gz_status init_graph(gz_graph** out, uint32_t V, uint64_t seed, const gz_config*
             return fail(GZ_ENOMEM, "out of device memory for the sketches");
         }
     }
-    e = hipMalloc((void**)&g->seeds, soa.size() * 4);
-    if (e == hipSuccess) e = hipMemcpy(g->seeds, soa.data(), soa.size() * 4, hipMemcpyHostToDevice);
+    // set-up work goes on the graph's own stream and waits for that stream only,
+    // so that creating a graph does not wait for other work on the device
+    hipStream_t is = nullptr;
+    e = query_stream(g, &is);
+    if (e == hipSuccess) e = hipMalloc((void**)&g->seeds, soa.size() * 4);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(g->seeds, soa.data(), soa.size() * 4, hipMemcpyHostToDevice, is);
     if (e == hipSuccess) e = err_word_take(g);
-    if (e == hipSuccess && g->sk) e = hipMemset(g->sk, 0, g->sk_words * 4);
+    if (e == hipSuccess && g->sk) e = hipMemsetAsync(g->sk, 0, g->sk_words * 4, is);
     if (e == hipSuccess && tier == GZ_TIER_HOST) {
         const gz_status ts = tier_create(g, cfg->staging_bytes);
         if (ts != GZ_OK) {
+            hipStreamSynchronize(is);
             tier_free(g);
             hipFree(g->seeds);
             err_word_release(g);
+            hipStreamDestroy(is);
             delete g;
             return ts;
         }
     }
-    if (e == hipSuccess) e = fence_record(0, g);
-    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e == hipSuccess) e = fence_record(is, g);
+    if (e == hipSuccess) e = hipStreamSynchronize(is);
     if (e != hipSuccess) {
         gz_status s = hip_fail(e, "graph init");
+        if (is) hipStreamSynchronize(is);
         tier_free(g);
         hipFree(g->sk);
         hipFree(g->seeds);
         err_word_release(g);
+        if (is) hipStreamDestroy(is);
         delete g;
         return s;
     }
@@ -575,6 +584,7 @@ const char* gz_status_str(gz_status s) {
         case GZ_ESKETCH_FAIL: return "GZ_ESKETCH_FAIL";
         case GZ_EBUSY: return "GZ_EBUSY";
         case GZ_ESTATE: return "GZ_ESTATE";
+        case GZ_ETIMEOUT: return "GZ_ETIMEOUT";
         default: return "GZ_UNKNOWN";
     }
 }

@@ -7,6 +7,13 @@
 // next ticks' ingests overlap on the device.  Requests of one session are
 // applied in submission order: a query is taken once the session's earlier
 // batches are applied, and the session's later batches wait for the query.
+//
+// A batch reaches HBM with one host copy at most: gz_submit_updates copies
+// (and validates) it into a pinned buffer on the submitting thread, and
+// gz_submit_updates_inplace lends the caller's own device or pinned memory.
+// Per tick, one gather kernel reads every batch of the tick where it lies
+// (pinned host memory over the host link, device memory in HBM) into the
+// tick's device staging arrays, which the fused ingest then reads.
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
@@ -20,7 +27,8 @@
 
 namespace {
 
-constexpr int kQueryThreads = 4;
+constexpr int kQueryThreads = 2;
+constexpr size_t kQueryBatch = 512;  // queries answered by one fused run
 
 uint64_t now_ns() {
     return (uint64_t)std::chrono::duration_cast<std::chrono::nanoseconds>(
@@ -43,12 +51,131 @@ uint64_t session_bytes(uint32_t V) {
     return sketch + query;
 }
 
+// Pinned host buffers for copied batches, in power-of-two size classes and
+// reused (allocating pinned memory costs far more than filling it).  Up to
+// kKeepBytes of returned buffers are kept; beyond that they are freed.
+class PinnedPool {
+  public:
+    static constexpr uint32_t kMinLog = 16;  // 64 KiB
+    static constexpr uint64_t kKeepBytes = 4ull << 30;
+
+    uint32_t* take(uint64_t bytes, uint64_t* cap) {
+        uint32_t lg = kMinLog;
+        while ((1ull << lg) < bytes) ++lg;
+        *cap = 1ull << lg;
+        {
+            std::lock_guard<std::mutex> lk(mu_);
+            if (free_.size() > lg && !free_[lg].empty()) {
+                uint32_t* p = free_[lg].back();
+                free_[lg].pop_back();
+                kept_ -= *cap;
+                return p;
+            }
+        }
+        uint32_t* p = nullptr;
+        if (hipHostMalloc((void**)&p, *cap, hipHostMallocMapped | hipHostMallocCoherent) !=
+            hipSuccess)
+            return nullptr;
+        return p;
+    }
+    void give(uint32_t* p, uint64_t cap) {
+        if (!p) return;
+        uint32_t lg = 0;
+        while ((1ull << lg) < cap) ++lg;
+        {
+            std::lock_guard<std::mutex> lk(mu_);
+            if (kept_ + cap <= kKeepBytes) {
+                if (free_.size() <= lg) free_.resize(lg + 1);
+                free_[lg].push_back(p);
+                kept_ += cap;
+                return;
+            }
+        }
+        hipHostFree(p);
+    }
+    void release_all() {
+        std::lock_guard<std::mutex> lk(mu_);
+        for (auto& v : free_)
+            for (uint32_t* p : v) hipHostFree(p);
+        free_.clear();
+        kept_ = 0;
+    }
+
+  private:
+    std::mutex mu_;
+    std::vector<std::vector<uint32_t*>> free_;
+    uint64_t kept_ = 0;
+};
+
+// One piece of a tick's gather: up to kGatherPiece updates of one batch, read
+// from where the batch lies into positions out.. of the staging arrays.
+struct GatherPiece {
+    const uint32_t* src;
+    const uint32_t* dst;
+    uint64_t out;
+    uint32_t count;
+    uint32_t pad;
+};
+constexpr uint32_t kGatherPiece = 4096;
+constexpr uint32_t kGatherThreads = 256;
+constexpr uint32_t kGatherUnroll = 4;  // loads of each array in flight per lane
+
+__global__ __launch_bounds__(kGatherThreads) void k_srv_gather(
+    const GatherPiece* __restrict__ pieces, uint32_t* __restrict__ out_src,
+    uint32_t* __restrict__ out_dst) {
+    const GatherPiece p = pieces[blockIdx.x];
+    // system-scope loads: host memory the caller may have rewritten since an
+    // earlier tick read it is never served from a stale cached line; several
+    // in flight per lane, since each crosses the host link
+    for (uint32_t i0 = 0; i0 < p.count; i0 += kGatherThreads * kGatherUnroll) {
+        uint32_t a[kGatherUnroll], b[kGatherUnroll];
+#pragma unroll
+        for (uint32_t u = 0; u < kGatherUnroll; ++u) {
+            const uint32_t i = i0 + u * kGatherThreads + threadIdx.x;
+            a[u] = i < p.count ? __hip_atomic_load(p.src + i, __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_SYSTEM)
+                               : 0u;
+            b[u] = i < p.count ? __hip_atomic_load(p.dst + i, __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_SYSTEM)
+                               : 0u;
+        }
+#pragma unroll
+        for (uint32_t u = 0; u < kGatherUnroll; ++u) {
+            const uint32_t i = i0 + u * kGatherThreads + threadIdx.x;
+            if (i < p.count) {
+                out_src[p.out + i] = a[u];
+                out_dst[p.out + i] = b[u];
+            }
+        }
+    }
+}
+
+// in-place batches in device memory: any self-loop or id >= V sets *bad
+__global__ __launch_bounds__(256) void k_srv_validate(const uint32_t* __restrict__ src,
+                                                      const uint32_t* __restrict__ dst,
+                                                      uint64_t n, uint32_t V,
+                                                      uint32_t* __restrict__ bad) {
+    uint32_t any = 0;
+    for (uint64_t i = blockIdx.x * 256ull + threadIdx.x; i < n; i += gridDim.x * 256ull) {
+        const uint32_t a = src[i], b = dst[i];
+        any |= (a == b) | (a >= V) | (b >= V);
+    }
+    if (__any(any) && __lane_id() == 0) atomicOr(bad, 1u);
+}
+
 }  // namespace
 
 struct gz_ticket {
     enum Kind { UPDATES, QUERY } kind = UPDATES;
-    gz_session* sess = nullptr;
-    std::vector<uint32_t> src, dst;
+    gz_session* sess = nullptr;  // valid until the ticket completes
+    gz_server* srv = nullptr;
+    // update batches: device-readable addresses of the batch (a pinned copy, or
+    // the caller's memory for in-place batches)
+    const uint32_t* src = nullptr;
+    const uint32_t* dst = nullptr;
+    uint64_t n = 0;
+    uint32_t* pinned = nullptr;  // the pool buffer of a copied batch
+    uint64_t pinned_cap = 0;
     uint32_t* labels = nullptr;
     gz_result res{};
     bool done = false;
@@ -60,12 +187,14 @@ struct gz_session {
     uint64_t seed = 0;
     uint64_t bytes = 0;
     gz_graph* g = nullptr;            // non-null once admitted
+    uint64_t admit_ns = 0;
+    uint64_t wait_since = 0;          // when the session was opened
+    bool admitting = false;           // its graph is being created
     std::deque<gz_ticket*> queue;     // submitted, not yet taken by a tick
     uint32_t inflight = 0;            // taken, not yet completed (batches and query)
     uint32_t upd_inflight = 0;        // batches taken, not yet completed
     bool query_busy = false;          // a query of this session is running
     bool closing = false;
-    std::vector<uint32_t> scratch_labels;
 };
 
 struct gz_server {
@@ -82,10 +211,21 @@ struct gz_server {
     std::thread worker;
     bool stop = false;
     hipStream_t stream = nullptr;
-    // double-buffered pinned staging of a tick's updates
-    uint32_t* h_stage[2] = {nullptr, nullptr};
-    uint64_t stage_cap[2] = {0, 0};
+    PinnedPool pool;
+    // double-buffered per-tick device staging (src then dst) and gather lists
+    uint32_t* d_stage[2] = {nullptr, nullptr};
+    uint64_t stage_cap[2] = {0, 0};  // updates
+    GatherPiece* h_pieces[2] = {nullptr, nullptr};
+    GatherPiece* d_pieces[2] = {nullptr, nullptr};
+    uint64_t pieces_cap[2] = {0, 0};
     hipEvent_t stage_ev[2] = {nullptr, nullptr};
+    hipEvent_t tick_t0[2] = {nullptr, nullptr};  // timing: a tick's first and last kernel
+    hipEvent_t tick_t1[2] = {nullptr, nullptr};
+    std::vector<gz_tick_record> timeline;
+    // validation of in-place device batches
+    std::mutex vmu;
+    hipStream_t vstream = nullptr;
+    uint32_t* vflag = nullptr;  // pinned, mapped
     gz_server_stats stats{};
     gz_status error = GZ_OK;  // first device error seen by the worker
 };
@@ -100,7 +240,10 @@ struct Tick {
     std::vector<std::vector<gz_ticket*>> upd;
     std::vector<gz_ticket*> queries;
     uint64_t n = 0;
+    uint32_t batches = 0;
+    uint64_t take_ns = 0, launched_ns = 0;
 };
+constexpr size_t kTimelineCap = 1 << 20;  // tick records kept per server
 
 void take_tick(gz_server* S, Tick& t) {
     for (gz_session* s : S->admitted) {
@@ -108,8 +251,9 @@ void take_tick(gz_server* S, Tick& t) {
         std::vector<gz_ticket*> mine;
         while (!s->queue.empty() && s->queue.front()->kind == gz_ticket::UPDATES) {
             gz_ticket* k = s->queue.front();
-            if (t.n > 0 && t.n + k->src.size() > S->tick_cap) break;
-            t.n += k->src.size();
+            if (t.n > 0 && t.n + k->n > S->tick_cap) break;
+            t.n += k->n;
+            t.batches++;
             mine.push_back(k);
             s->queue.pop_front();
         }
@@ -131,14 +275,47 @@ void take_tick(gz_server* S, Tick& t) {
     }
 }
 
-void admit(gz_server* S) {
-    while (!S->waiting.empty() && S->used + S->waiting.front()->bytes <= S->budget) {
-        gz_session* s = S->waiting.front();
-        gz_graph* g = nullptr;
-        if (gz_sketch_init(&g, s->V, s->seed, nullptr) != GZ_OK) break;  // retry later
-        s->g = g;
+// The next waiting session to admit: the oldest one whose bytes fit.  Younger
+// sessions may pass a waiting one that does not fit, until the oldest has
+// waited kAdmitPatience; from then on only it may go, so that memory freed by
+// closing sessions gathers for it instead of being taken by smaller ones.
+constexpr uint64_t kAdmitPatienceNs = 100000000;  // 100 ms
+
+std::deque<gz_session*>::iterator admissible(gz_server* S) {
+    auto it = S->waiting.begin();
+    if (it == S->waiting.end()) return it;
+    const bool head_only = now_ns() - (*it)->wait_since > kAdmitPatienceNs;
+    for (; it != S->waiting.end(); ++it) {
+        if (S->used + (*it)->bytes <= S->budget) return it;
+        if (head_only) break;
+    }
+    return S->waiting.end();
+}
+
+// Admit what fits.  Creating a session's graph (allocation, zeroing) runs with
+// the lock released: clients, completions and queries go on meanwhile; the
+// session counts against the budget from the start.
+void admit(gz_server* S, std::unique_lock<std::mutex>& lk) {
+    for (;;) {
+        auto it = admissible(S);
+        if (it == S->waiting.end()) break;
+        gz_session* s = *it;
+        S->waiting.erase(it);
         S->used += s->bytes;
-        S->waiting.pop_front();
+        s->admitting = true;
+        lk.unlock();
+        gz_graph* g = nullptr;
+        const gz_status st = gz_sketch_init(&g, s->V, s->seed, nullptr);
+        lk.lock();
+        s->admitting = false;
+        S->cv_done.notify_all();  // a close may wait for the admission to end
+        if (st != GZ_OK) {
+            S->used -= s->bytes;
+            S->waiting.push_front(s);  // retry later
+            break;
+        }
+        s->g = g;
+        s->admit_ns = now_ns();
         S->admitted.push_back(s);
         S->stats.sessions_admitted++;
     }
@@ -149,56 +326,152 @@ bool has_work(gz_server* S) {
         if (!s->query_busy && !s->queue.empty() &&
             (s->queue.front()->kind == gz_ticket::UPDATES || s->upd_inflight == 0))
             return true;
-    if (!S->waiting.empty() && S->used + S->waiting.front()->bytes <= S->budget) return true;
-    return false;
+    return admissible(S) != S->waiting.end();
 }
 
 void complete(gz_server* S, gz_ticket* k, gz_status st) {
     k->res.status = st;
     k->res.done_ns = now_ns();
     std::lock_guard<std::mutex> lk(S->mu);
+    k->res.admit_ns = k->sess->admit_ns;
     k->done = true;
     k->sess->inflight -= 1;
     if (k->kind == gz_ticket::UPDATES) k->sess->upd_inflight -= 1;
     S->cv_done.notify_all();
 }
 
-// Query threads: run the queries the tick loop hands over, each on its
-// session's query stream; the session's next batches are released afterwards.
+// Query threads: each takes every query queued so far (up to kQueryBatch) and
+// answers them with one fused Boruvka run over their graphs, so that queries
+// that come due together (sessions reach their n-th batch at similar times)
+// cost one launch sequence; a session's next batches are released afterwards.
 void query_main(gz_server* S) {
     hipSetDevice(S->device);
+    uint32_t* lab = nullptr;  // pinned labels of a fused run
+    uint64_t lab_cap = 0;
     for (;;) {
-        gz_ticket* k = nullptr;
+        std::vector<gz_ticket*> batch;
         {
             std::unique_lock<std::mutex> lk(S->mu);
             S->cv_query.wait(lk, [&] { return S->stop_queries || !S->qq.empty(); });
-            if (S->qq.empty()) return;
-            k = S->qq.front();
-            S->qq.pop_front();
+            if (S->qq.empty()) break;
+            while (!S->qq.empty() && batch.size() < kQueryBatch) {
+                batch.push_back(S->qq.front());
+                S->qq.pop_front();
+            }
         }
-        gz_session* s = k->sess;
-        k->res.start_ns = now_ns();
-        uint32_t* out = k->labels;
-        if (!out) {
-            s->scratch_labels.resize(s->V);
-            out = s->scratch_labels.data();
+        const uint64_t start = now_ns();
+        const uint32_t G = (uint32_t)batch.size();
+        std::vector<gz_graph*> gs(G);
+        std::vector<uint64_t> off(G + 1, 0);
+        for (uint32_t i = 0; i < G; ++i) {
+            batch[i]->res.start_ns = start;
+            gs[i] = batch[i]->sess->g;
+            off[i + 1] = off[i] + batch[i]->sess->V;
         }
-        uint32_t ncc = 0;
-        const gz_status q = gz_connected_components(s->g, out, &ncc);
-        k->res.num_cc = ncc;
-        k->res.status = q;
-        k->res.done_ns = now_ns();
+        std::vector<uint32_t> ncc(G, 0);
+        std::vector<int32_t> gst(G, GZ_OK);
+        gz_status q = GZ_OK;
+        if (lab_cap < off[G]) {
+            hipHostFree(lab);
+            lab = nullptr;
+            lab_cap = 0;
+            if (hipHostMalloc((void**)&lab, 4 * off[G], hipHostMallocDefault) == hipSuccess)
+                lab_cap = off[G];
+            else
+                q = GZ_ENOMEM;
+        }
+        if (!q) q = gz_connected_components_multi(gs.data(), G, lab, ncc.data(), gst.data());
+        const uint64_t done = now_ns();
+        for (uint32_t i = 0; i < G; ++i) {
+            gz_ticket* k = batch[i];
+            k->res.num_cc = ncc[i];
+            // a run that ended with a component still active reports that per graph
+            k->res.status = q == GZ_OK || q == GZ_ESKETCH_FAIL ? gst[i] : q;
+            if (k->labels && (q == GZ_OK || q == GZ_ESKETCH_FAIL))
+                std::memcpy(k->labels, lab + off[i], 4ull * k->sess->V);
+            k->res.done_ns = done;
+        }
         {
             std::lock_guard<std::mutex> lk(S->mu);
-            S->stats.queries++;
-            k->done = true;
-            s->inflight -= 1;
-            s->query_busy = false;
-            S->queries_running--;
+            for (gz_ticket* k : batch) {
+                gz_session* s = k->sess;
+                S->stats.queries++;
+                k->res.admit_ns = s->admit_ns;
+                k->done = true;
+                s->inflight -= 1;
+                s->query_busy = false;
+                S->queries_running--;
+            }
+            S->stats.query_runs++;
             S->cv_done.notify_all();
         }
         S->cv_work.notify_one();
     }
+    hipHostFree(lab);
+}
+
+// grow a tick buffer set to hold n updates in `pieces` gather pieces
+gz_status ensure_tick_buffers(gz_server* S, int buf, uint64_t n, uint64_t pieces) {
+    if (S->stage_cap[buf] < n) {
+        hipFree(S->d_stage[buf]);
+        S->d_stage[buf] = nullptr;
+        S->stage_cap[buf] = 0;
+        const uint64_t cap = std::max<uint64_t>(n + n / 2, 1u << 20);
+        GZ_HIP(hipMalloc((void**)&S->d_stage[buf], 8 * cap));
+        S->stage_cap[buf] = cap;
+    }
+    if (S->pieces_cap[buf] < pieces) {
+        hipFree(S->d_pieces[buf]);
+        hipHostFree(S->h_pieces[buf]);
+        S->d_pieces[buf] = nullptr;
+        S->h_pieces[buf] = nullptr;
+        S->pieces_cap[buf] = 0;
+        const uint64_t cap = std::max<uint64_t>(pieces + pieces / 2, 1024);
+        GZ_HIP(hipMalloc((void**)&S->d_pieces[buf], cap * sizeof(GatherPiece)));
+        GZ_HIP(hipHostMalloc((void**)&S->h_pieces[buf], cap * sizeof(GatherPiece),
+                             hipHostMallocDefault));
+        S->pieces_cap[buf] = cap;
+    }
+    return GZ_OK;
+}
+
+// The tick's batches, session after session, gathered into the staging arrays
+// of `buf` by one kernel; then the fused ingest over the tick's graphs.
+gz_status launch_tick(gz_server* S, Tick& t, int buf) {
+    uint64_t pieces = 0;
+    for (auto& v : t.upd)
+        for (gz_ticket* k : v) pieces += (k->n + kGatherPiece - 1) / kGatherPiece;
+    GZ_TRY(ensure_tick_buffers(S, buf, t.n, pieces));
+    uint32_t* dsrc = S->d_stage[buf];
+    uint32_t* ddst = dsrc + S->stage_cap[buf];
+    GatherPiece* hp = S->h_pieces[buf];
+    std::vector<gz_graph*> gs;
+    std::vector<uint64_t> offs(1, 0);
+    uint64_t at = 0, np = 0;
+    const uint64_t start = now_ns();
+    for (size_t i = 0; i < t.upd_sessions.size(); ++i) {
+        gs.push_back(t.upd_sessions[i]->g);
+        for (gz_ticket* k : t.upd[i]) {
+            for (uint64_t o = 0; o < k->n; o += kGatherPiece)
+                hp[np++] = GatherPiece{k->src + o, k->dst + o, at + o,
+                                       (uint32_t)std::min<uint64_t>(kGatherPiece, k->n - o), 0};
+            at += k->n;
+            k->res.start_ns = start;
+        }
+        offs.push_back(at);
+    }
+    GZ_HIP(hipMemcpyAsync(S->d_pieces[buf], hp, np * sizeof(GatherPiece), hipMemcpyHostToDevice,
+                          S->stream));
+    GZ_HIP(hipEventRecord(S->tick_t0[buf], S->stream));
+    k_srv_gather<<<(uint32_t)np, kGatherThreads, 0, S->stream>>>(S->d_pieces[buf], dsrc, ddst);
+    GZ_HIP(hipGetLastError());
+    GZ_TRY(gz_ingest_multi(gs.data(), (uint32_t)gs.size(), offs.data(), dsrc, ddst,
+                           GZ_ASYNC | GZ_DEVICE_PTR, S->stream));
+    GZ_HIP(hipEventRecord(S->tick_t1[buf], S->stream));
+    GZ_HIP(hipEventRecord(S->stage_ev[buf], S->stream));
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->stats.staged_bytes += 8 * t.n;
+    return GZ_OK;
 }
 
 void worker_main(gz_server* S) {
@@ -213,57 +486,31 @@ void worker_main(gz_server* S) {
         Tick t;
         {
             std::unique_lock<std::mutex> lk(S->mu);
-            admit(S);
+            admit(S, lk);
             if (prev.buf < 0)
                 S->cv_work.wait(lk, [&] {
                     return (S->stop && S->queries_running == 0) || has_work(S);
                 });
-            admit(S);
+            admit(S, lk);
             if (S->stop && !has_work(S) && prev.buf < 0 && S->queries_running == 0) break;
             take_tick(S, t);
         }
-        // 1. launch this tick's fused ingest (host staging -> device, async)
+        t.take_ns = now_ns();
+        // 1. launch this tick's gather and fused ingest (async)
         gz_status st = GZ_OK;
         if (t.n > 0) {
-            if (S->stage_cap[buf] < 2 * t.n) {
-                hipEventSynchronize(S->stage_ev[buf]);
-                hipHostFree(S->h_stage[buf]);
-                S->h_stage[buf] = nullptr;
-                S->stage_cap[buf] = 0;
-                if (hipHostMalloc((void**)&S->h_stage[buf], 8 * t.n, hipHostMallocDefault) ==
-                    hipSuccess)
-                    S->stage_cap[buf] = 2 * t.n;
-                else
-                    st = GZ_ENOMEM;
-            } else {
-                hipEventSynchronize(S->stage_ev[buf]);  // its last upload has left the buffer
-            }
+            const uint64_t t0 = now_ns();
+            hipEventSynchronize(S->stage_ev[buf]);  // tick t-2's ingest is done with buf
+            const uint64_t t1 = now_ns();
+            st = launch_tick(S, t, buf);
+            const uint64_t t2 = now_ns();
+            t.launched_ns = t2;
+            std::lock_guard<std::mutex> lk(S->mu);
+            S->stats.worker_wait_ns += t1 - t0;
+            S->stats.worker_launch_ns += t2 - t1;
             if (!st) {
-                uint32_t* hs = S->h_stage[buf];
-                uint32_t* hd = hs + t.n;
-                std::vector<gz_graph*> gs;
-                std::vector<uint64_t> offs(1, 0);
-                uint64_t at = 0;
-                const uint64_t start = now_ns();
-                for (size_t i = 0; i < t.upd_sessions.size(); ++i) {
-                    gs.push_back(t.upd_sessions[i]->g);
-                    for (gz_ticket* k : t.upd[i]) {
-                        std::memcpy(hs + at, k->src.data(), 4 * k->src.size());
-                        std::memcpy(hd + at, k->dst.data(), 4 * k->dst.size());
-                        at += k->src.size();
-                        k->res.start_ns = start;
-                    }
-                    offs.push_back(at);
-                }
-                st = gz_ingest_multi(gs.data(), (uint32_t)gs.size(), offs.data(), hs, hd, GZ_ASYNC,
-                                     S->stream);
-                if (!st && hipEventRecord(S->stage_ev[buf], S->stream) != hipSuccess)
-                    st = GZ_EDEVICE;
-                if (!st) {
-                    std::lock_guard<std::mutex> lk(S->mu);
-                    S->stats.ticks++;
-                    S->stats.updates += t.n;
-                }
+                S->stats.ticks++;
+                S->stats.updates += t.n;
             }
         }
         // 2. hand the queries to the query threads
@@ -278,6 +525,21 @@ void worker_main(gz_server* S) {
         if (prev.buf >= 0) {
             gz_status pst = hipEventSynchronize(S->stage_ev[prev.buf]) == hipSuccess ? GZ_OK
                                                                                       : GZ_EDEVICE;
+            {
+                gz_tick_record rec{};
+                rec.take_ns = prev.tick.take_ns;
+                rec.launched_ns = prev.tick.launched_ns;
+                rec.done_ns = now_ns();
+                rec.updates = prev.tick.n;
+                rec.batches = prev.tick.batches;
+                rec.graphs = (uint32_t)prev.tick.upd_sessions.size();
+                float ms = 0.f;
+                if (hipEventElapsedTime(&ms, S->tick_t0[prev.buf], S->tick_t1[prev.buf]) ==
+                    hipSuccess)
+                    rec.device_ms = ms;
+                std::lock_guard<std::mutex> lk(S->mu);
+                if (S->timeline.size() < kTimelineCap) S->timeline.push_back(rec);
+            }
             // Every batch was validated when it was submitted, so the ingest
             // cannot have met an invalid update: its completion is all that is
             // left to wait for, and the graphs need no flush-time error check
@@ -286,14 +548,23 @@ void worker_main(gz_server* S) {
             // sessions runs until their batches complete, below.
             for (size_t i = 0; i < prev.tick.upd_sessions.size(); ++i) {
                 prev.tick.upd_sessions[i]->g->pending_error = false;
-                for (gz_ticket* k : prev.tick.upd[i]) complete(S, k, pst);
+                for (gz_ticket* k : prev.tick.upd[i]) {
+                    S->pool.give(k->pinned, k->pinned_cap);  // the gather has read it
+                    k->pinned = nullptr;
+                    complete(S, k, pst);
+                }
             }
             prev = Pending{};
         }
         if (t.n > 0) {
             if (st) {
+                hipStreamSynchronize(S->stream);  // nothing of the tick may still read them
                 for (size_t i = 0; i < t.upd_sessions.size(); ++i)
-                    for (gz_ticket* k : t.upd[i]) complete(S, k, st);
+                    for (gz_ticket* k : t.upd[i]) {
+                        S->pool.give(k->pinned, k->pinned_cap);
+                        k->pinned = nullptr;
+                        complete(S, k, st);
+                    }
                 std::lock_guard<std::mutex> lk(S->mu);
                 if (!S->error) S->error = st;
             } else {
@@ -315,11 +586,24 @@ gz_status gz_server_create(uint64_t hbm_budget, uint64_t tick_updates, gz_server
     gz_server* S = new gz_server();
     if (hipGetDevice(&S->device) != hipSuccess ||
         hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking) != hipSuccess ||
+        hipStreamCreateWithFlags(&S->vstream, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&S->stage_ev[0], hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&S->stage_ev[1], hipEventDisableTiming) != hipSuccess) {
+        hipEventCreateWithFlags(&S->stage_ev[1], hipEventDisableTiming) != hipSuccess ||
+        hipEventCreate(&S->tick_t0[0]) != hipSuccess || hipEventCreate(&S->tick_t0[1]) != hipSuccess ||
+        hipEventCreate(&S->tick_t1[0]) != hipSuccess || hipEventCreate(&S->tick_t1[1]) != hipSuccess ||
+        hipHostMalloc((void**)&S->vflag, 4, hipHostMallocMapped | hipHostMallocCoherent) !=
+            hipSuccess) {
+        if (S->stream) hipStreamDestroy(S->stream);
+        if (S->vstream) hipStreamDestroy(S->vstream);
+        for (hipEvent_t e : {S->stage_ev[0], S->stage_ev[1], S->tick_t0[0], S->tick_t0[1],
+                             S->tick_t1[0], S->tick_t1[1]})
+            if (e) hipEventDestroy(e);
         delete S;
-        return gz::fail(GZ_EDEVICE, "server stream/events");
+        return gz::fail(GZ_EDEVICE, "server streams/events");
     }
+    // both staging sets start "free": their events are complete
+    hipEventRecord(S->stage_ev[0], S->stream);
+    hipEventRecord(S->stage_ev[1], S->stream);
     S->budget = hbm_budget;
     S->tick_cap = tick_updates ? tick_updates : (16ull << 20);
     S->stats.hbm_budget = hbm_budget;
@@ -344,6 +628,7 @@ gz_status gz_session_open(gz_server* S, uint32_t V, uint64_t seed, gz_session** 
     }
     {
         std::lock_guard<std::mutex> lk(S->mu);
+        s->wait_since = now_ns();
         S->waiting.push_back(s);
     }
     S->cv_work.notify_one();
@@ -354,6 +639,7 @@ gz_status gz_session_open(gz_server* S, uint32_t V, uint64_t seed, gz_session** 
 static gz_status submit(gz_session* s, gz_ticket* k, gz_ticket** out) {
     gz_server* S = s->srv;
     k->sess = s;
+    k->srv = S;
     k->res.submit_ns = now_ns();
     {
         std::lock_guard<std::mutex> lk(S->mu);
@@ -372,14 +658,123 @@ gz_status gz_submit_updates(gz_session* s, const uint32_t* src, const uint32_t* 
                             gz_ticket** out) {
     if (!s || !out || (N && (!src || !dst))) return gz::fail(GZ_EINVAL, "null argument");
     *out = nullptr;
-    for (uint64_t i = 0; i < N; ++i)
-        if (src[i] == dst[i] || src[i] >= s->V || dst[i] >= s->V)
-            return gz::fail(GZ_EINVAL, "invalid update (self-loop or node id out of range)");
     gz_ticket* k = new gz_ticket();
     k->kind = gz_ticket::UPDATES;
-    k->src.assign(src, src + N);
-    k->dst.assign(dst, dst + N);
+    k->n = N;
     k->res.updates = N;
+    if (N) {
+        // one pass: validate while copying into a pinned buffer the gather reads
+        k->pinned = s->srv->pool.take(8 * N, &k->pinned_cap);
+        if (!k->pinned) {
+            delete k;
+            return gz::fail(GZ_ENOMEM, "pinned staging of a batch");
+        }
+        uint32_t* ps = k->pinned;
+        uint32_t* pd = k->pinned + N;
+        const uint32_t V = s->V;
+        uint32_t bad = 0;
+        for (uint64_t i = 0; i < N; ++i) {
+            const uint32_t a = src[i], b = dst[i];
+            bad |= (uint32_t)(a == b) | (uint32_t)(a >= V) | (uint32_t)(b >= V);
+            ps[i] = a;
+            pd[i] = b;
+        }
+        uint32_t* dev = nullptr;
+        const hipError_t e = bad ? hipSuccess : hipHostGetDevicePointer((void**)&dev, ps, 0);
+        if (bad || e != hipSuccess) {
+            s->srv->pool.give(k->pinned, k->pinned_cap);
+            delete k;
+            if (e != hipSuccess) return gz::hip_fail(e, "device address of a pinned batch");
+            return gz::fail(GZ_EINVAL, "invalid update (self-loop or node id out of range)");
+        }
+        k->src = dev;
+        k->dst = dev + N;
+    }
+    {
+        std::lock_guard<std::mutex> lk(s->srv->mu);
+        s->srv->stats.batches_copied++;
+    }
+    return submit(s, k, out);
+}
+
+// where an in-place array lies: its device-readable address, and whether the
+// host can read it (pinned host memory) or only the device
+static gz_status locate(gz_server* S, const uint32_t* p, const uint32_t** dev, bool* host) {
+    hipPointerAttribute_t at{};
+    if (hipPointerGetAttributes(&at, p) != hipSuccess) {
+        (void)hipGetLastError();
+        return gz::fail(GZ_EINVAL, "in-place batches must be device or pinned host memory");
+    }
+    if (at.type == hipMemoryTypeHost && at.devicePointer) {
+        // the address may point into the middle of the allocation
+        *dev = static_cast<const uint32_t*>(at.devicePointer);
+        *host = true;
+        return GZ_OK;
+    }
+    if (at.type == hipMemoryTypeDevice && at.device == S->device) {
+        *dev = p;
+        *host = false;
+        return GZ_OK;
+    }
+    return gz::fail(GZ_EINVAL, "in-place batches must be device memory of the server's GPU "
+                               "or pinned host memory");
+}
+
+gz_status gz_submit_updates_inplace(gz_session* s, const uint32_t* src, const uint32_t* dst,
+                                    uint64_t N, gz_ticket** out) {
+    if (!s || !out || (N && (!src || !dst))) return gz::fail(GZ_EINVAL, "null argument");
+    *out = nullptr;
+    gz_server* S = s->srv;
+    gz_ticket* k = new gz_ticket();
+    k->kind = gz_ticket::UPDATES;
+    k->n = N;
+    k->res.updates = N;
+    if (N) {
+        const uint32_t *ds = nullptr, *dd = nullptr;
+        bool hs = false, hd = false;
+        gz_status st = locate(S, src, &ds, &hs);
+        if (!st) st = locate(S, dst, &dd, &hd);
+        if (st) {
+            delete k;
+            return st;
+        }
+        uint32_t bad = 0;
+        const uint32_t V = s->V;
+        if (hs && hd) {
+            for (uint64_t i = 0; i < N; ++i) {
+                const uint32_t a = src[i], b = dst[i];
+                bad |= (uint32_t)(a == b) | (uint32_t)(a >= V) | (uint32_t)(b >= V);
+            }
+        } else {
+            // device memory (or one array of each kind): checked by a kernel
+            std::lock_guard<std::mutex> lk(S->vmu);
+            uint32_t* flag_dev = nullptr;
+            volatile uint32_t* flag = S->vflag;
+            *flag = 0;
+            hipError_t e = hipHostGetDevicePointer((void**)&flag_dev, S->vflag, 0);
+            if (e == hipSuccess) {
+                const uint64_t blocks = std::min<uint64_t>((N + 255) / 256, 1024);
+                k_srv_validate<<<(uint32_t)blocks, 256, 0, S->vstream>>>(ds, dd, N, V, flag_dev);
+                e = hipGetLastError();
+            }
+            if (e == hipSuccess) e = hipStreamSynchronize(S->vstream);
+            if (e != hipSuccess) {
+                delete k;
+                return gz::hip_fail(e, "validation of an in-place batch");
+            }
+            bad = *flag;
+        }
+        if (bad) {
+            delete k;
+            return gz::fail(GZ_EINVAL, "invalid update (self-loop or node id out of range)");
+        }
+        k->src = ds;
+        k->dst = dd;
+    }
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->stats.batches_inplace++;
+    }
     return submit(s, k, out);
 }
 
@@ -392,13 +787,9 @@ gz_status gz_submit_query(gz_session* s, uint32_t* labels, gz_ticket** out) {
     return submit(s, k, out);
 }
 
-gz_status gz_wait(gz_ticket* k, gz_result* res) {
-    if (!k) return gz::fail(GZ_EINVAL, "null ticket");
-    gz_server* S = k->sess->srv;
-    {
-        std::unique_lock<std::mutex> lk(S->mu);
-        S->cv_done.wait(lk, [&] { return k->done; });
-    }
+static gz_status take_result(gz_ticket* k, gz_result* res) {
+    // (a completed ticket may outlive its session: only the server is used here)
+    if (k->pinned) k->srv->pool.give(k->pinned, k->pinned_cap);  // never gathered
     gz_result r = k->res;
     r.kind = k->kind == gz_ticket::QUERY ? 1u : 0u;
     if (res) *res = r;
@@ -406,11 +797,62 @@ gz_status gz_wait(gz_ticket* k, gz_result* res) {
     return r.status == GZ_ESKETCH_FAIL ? GZ_OK : r.status;
 }
 
+gz_status gz_wait(gz_ticket* k, gz_result* res) {
+    if (!k) return gz::fail(GZ_EINVAL, "null ticket");
+    gz_server* S = k->srv;
+    {
+        std::unique_lock<std::mutex> lk(S->mu);
+        S->cv_done.wait(lk, [&] { return k->done; });
+    }
+    return take_result(k, res);
+}
+
+gz_status gz_wait_any(gz_ticket* const* tickets, uint32_t n, uint64_t timeout_ns,
+                      uint32_t* index, gz_result* res) {
+    if (!tickets || !n || !index) return gz::fail(GZ_EINVAL, "null argument");
+    *index = n;
+    for (uint32_t i = 0; i < n; ++i)
+        if (!tickets[i]) return gz::fail(GZ_EINVAL, "null ticket");
+    gz_server* S = tickets[0]->srv;
+    for (uint32_t i = 1; i < n; ++i)
+        if (tickets[i]->srv != S) return gz::fail(GZ_EINVAL, "tickets of several servers");
+    uint32_t found = n;
+    {
+        std::unique_lock<std::mutex> lk(S->mu);
+        auto any_done = [&] {
+            for (uint32_t i = 0; i < n; ++i)
+                if (tickets[i]->done) {
+                    found = i;
+                    return true;
+                }
+            return false;
+        };
+        if (timeout_ns == UINT64_MAX)
+            S->cv_done.wait(lk, any_done);
+        else
+            S->cv_done.wait_for(lk, std::chrono::nanoseconds(timeout_ns), any_done);
+    }
+    if (found == n) return gz::fail(GZ_ETIMEOUT, "no ticket completed within the timeout");
+    *index = found;
+    return take_result(tickets[found], res);
+}
+
+gz_status gz_session_graph(gz_session* s, gz_graph** out) {
+    if (!s || !out) return gz::fail(GZ_EINVAL, "null argument");
+    std::lock_guard<std::mutex> lk(s->srv->mu);
+    *out = s->g;
+    if (!s->g) return gz::fail(GZ_ESTATE, "session not admitted yet");
+    if (!s->queue.empty() || s->inflight)
+        return gz::fail(GZ_ESTATE, "the session has requests in flight");
+    return GZ_OK;
+}
+
 gz_status gz_session_close(gz_session* s) {
     if (!s) return GZ_OK;
     gz_server* S = s->srv;
     std::unique_lock<std::mutex> lk(S->mu);
     s->closing = true;
+    S->cv_done.wait(lk, [&] { return !s->admitting; });
     if (!s->g) {
         // never admitted: its queued requests cannot run any more
         for (gz_ticket* k : s->queue) {
@@ -448,6 +890,14 @@ gz_status gz_server_get_stats(gz_server* S, gz_server_stats* out) {
     return S->error;
 }
 
+gz_status gz_server_timeline(gz_server* S, gz_tick_record* out, uint64_t cap, uint64_t* n) {
+    if (!S || !n || (cap && !out)) return gz::fail(GZ_EINVAL, "null argument");
+    std::lock_guard<std::mutex> lk(S->mu);
+    *n = S->timeline.size();
+    std::copy(S->timeline.begin(), S->timeline.begin() + std::min<uint64_t>(cap, *n), out);
+    return GZ_OK;
+}
+
 gz_status gz_server_destroy(gz_server* S) {
     if (!S) return GZ_OK;
     {
@@ -466,7 +916,10 @@ gz_status gz_server_destroy(gz_server* S) {
     for (gz_session* s : S->admitted) left.push_back(s);
     for (gz_session* s : S->waiting) left.push_back(s);
     for (gz_session* s : left) {
-        for (gz_ticket* k : s->queue) delete k;
+        for (gz_ticket* k : s->queue) {
+            S->pool.give(k->pinned, k->pinned_cap);
+            delete k;
+        }
         gz_free(s->g);
         delete s;
     }
@@ -475,8 +928,15 @@ gz_status gz_server_destroy(gz_server* S) {
             hipEventSynchronize(S->stage_ev[b]);
             hipEventDestroy(S->stage_ev[b]);
         }
-        hipHostFree(S->h_stage[b]);
+        hipEventDestroy(S->tick_t0[b]);
+        hipEventDestroy(S->tick_t1[b]);
+        hipFree(S->d_stage[b]);
+        hipFree(S->d_pieces[b]);
+        hipHostFree(S->h_pieces[b]);
     }
+    S->pool.release_all();
+    hipHostFree(S->vflag);
+    hipStreamDestroy(S->vstream);
     hipStreamDestroy(S->stream);
     delete S;
     return GZ_OK;

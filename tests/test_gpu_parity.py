@@ -397,3 +397,47 @@ def test_multi_calls_on_two_streams_share_scratch_safely(gz):
             assert_sketch_equal(g, oracle_for(s, sd))
     for g in gA + gB:
         g.close()
+
+
+@pytest.mark.parametrize("order", ["small_then_large", "large_then_small"])
+def test_calls_with_small_and_large_items_in_sequence(gz, order):
+    """Calls whose items keep few tile rows (their deep entries go to HBM rows past the
+    tile) followed by calls whose items keep many, and the reverse, then a reset, a
+    captured plan and per-node batches on top: bit-exact with the oracle after every call."""
+    import torch
+
+    V, seed = 3000, 41
+    rng = np.random.default_rng(42)
+    hubs = rng.choice(V, 40, replace=False)
+    # small items: about two entries per node; large items: thousands at 40 hubs
+    small = _stream(V, 3000, 43, p_repeat=0.0)
+    big_src = np.repeat(hubs, 1500).astype(np.uint32)
+    big_dst = rng.integers(0, V, len(big_src)).astype(np.uint32)
+    keep = big_src != big_dst
+    large = workloads.Stream(V, big_src[keep], big_dst[keep], np.ones(int(keep.sum()), np.uint8))
+    parts = [small, large] if order == "small_then_large" else [large, small]
+    parts = parts + [_stream(V, 2000, 44, p_repeat=0.0)]
+    g = gz.Graph(V, seed=seed)
+    g.set_tuning(lds_rows=6)  # deep entries on both sides of the tile
+    O = oracle.Oracle(V, seed)
+    for s in parts:
+        g.ingest(to_dev(s.src), to_dev(s.dst))
+        O.ingest(s.src, s.dst)
+        assert_sketch_equal(g, O)
+    assert_query_equal(g, O)
+    g.reset()
+    O2 = oracle.Oracle(V, seed)
+    plan = gz.Plan([g], [max(s.N for s in parts)])
+    for s in reversed(parts):
+        plan.ingest(np.array([0, s.N], np.uint64), to_dev(s.src), to_dev(s.dst))
+        torch.cuda.synchronize()
+        O2.ingest(s.src, s.dst)
+        assert_sketch_equal(g, O2)
+    plan.close()
+    for node in (int(hubs[0]), 0, V - 1):  # the per-node path on top
+        nb = rng.integers(0, V, 900).astype(np.uint32)
+        nb = nb[nb != node]
+        g.update_sketch_batch(node, to_dev(nb))
+        O2.ingest_nodes(np.full(len(nb), node, np.uint32), nb, [node])
+        a, b = g.export(node, node + 1)
+        assert (a[0] == O2.alpha[node]).all() and (b[0] == O2.gamma[node]).all()

@@ -210,6 +210,9 @@ struct gz_server {
     std::deque<gz_session*> waiting;
     std::thread worker;
     bool stop = false;
+    std::thread admitter;            // creates admitted sessions' graphs
+    std::condition_variable cv_admit;
+    bool stop_admit = false;
     hipStream_t stream = nullptr;
     PinnedPool pool;
     // double-buffered per-tick device staging (src then dst) and gather lists
@@ -295,7 +298,7 @@ std::deque<gz_session*>::iterator admissible(gz_server* S) {
 // Admit what fits.  Creating a session's graph (allocation, zeroing) runs with
 // the lock released: clients, completions and queries go on meanwhile; the
 // session counts against the budget from the start.
-void admit(gz_server* S, std::unique_lock<std::mutex>& lk) {
+bool admit(gz_server* S, std::unique_lock<std::mutex>& lk) {
     for (;;) {
         auto it = admissible(S);
         if (it == S->waiting.end()) break;
@@ -312,12 +315,33 @@ void admit(gz_server* S, std::unique_lock<std::mutex>& lk) {
         if (st != GZ_OK) {
             S->used -= s->bytes;
             S->waiting.push_front(s);  // retry later
-            break;
+            return false;
         }
         s->g = g;
         s->admit_ns = now_ns();
         S->admitted.push_back(s);
         S->stats.sessions_admitted++;
+        S->cv_work.notify_one();  // its queued requests can run
+    }
+    return true;
+}
+
+// Admission runs on a thread of its own: creating a graph (allocating and
+// zeroing gigabytes) takes milliseconds, which would otherwise stall the tick
+// loop for every session admitted while others are served.
+void admit_main(gz_server* S) {
+    hipSetDevice(S->device);
+    std::unique_lock<std::mutex> lk(S->mu);
+    bool ok = true;
+    for (;;) {
+        if (ok)
+            S->cv_admit.wait(lk, [&] {
+                return S->stop_admit || admissible(S) != S->waiting.end();
+            });
+        else  // a graph could not be created: try again a little later
+            S->cv_admit.wait_for(lk, std::chrono::milliseconds(5));
+        if (S->stop_admit) break;
+        ok = admit(S, lk);
     }
 }
 
@@ -326,7 +350,7 @@ bool has_work(gz_server* S) {
         if (!s->query_busy && !s->queue.empty() &&
             (s->queue.front()->kind == gz_ticket::UPDATES || s->upd_inflight == 0))
             return true;
-    return admissible(S) != S->waiting.end();
+    return false;
 }
 
 void complete(gz_server* S, gz_ticket* k, gz_status st) {
@@ -486,12 +510,10 @@ void worker_main(gz_server* S) {
         Tick t;
         {
             std::unique_lock<std::mutex> lk(S->mu);
-            admit(S, lk);
             if (prev.buf < 0)
                 S->cv_work.wait(lk, [&] {
                     return (S->stop && S->queries_running == 0) || has_work(S);
                 });
-            admit(S, lk);
             if (S->stop && !has_work(S) && prev.buf < 0 && S->queries_running == 0) break;
             take_tick(S, t);
         }
@@ -608,6 +630,7 @@ gz_status gz_server_create(uint64_t hbm_budget, uint64_t tick_updates, gz_server
     S->tick_cap = tick_updates ? tick_updates : (16ull << 20);
     S->stats.hbm_budget = hbm_budget;
     S->worker = std::thread(worker_main, S);
+    S->admitter = std::thread(admit_main, S);
     for (int i = 0; i < kQueryThreads; ++i) S->query_threads.emplace_back(query_main, S);
     *out = S;
     return GZ_OK;
@@ -631,7 +654,7 @@ gz_status gz_session_open(gz_server* S, uint32_t V, uint64_t seed, gz_session** 
         s->wait_since = now_ns();
         S->waiting.push_back(s);
     }
-    S->cv_work.notify_one();
+    S->cv_admit.notify_one();
     *out = s;
     return GZ_OK;
 }
@@ -866,17 +889,18 @@ gz_status gz_session_close(gz_session* s) {
     S->cv_work.notify_one();
     S->cv_done.wait(lk, [&] { return s->queue.empty() && s->inflight == 0 && !s->query_busy; });
     auto it = std::find(S->admitted.begin(), S->admitted.end(), s);
-    if (it != S->admitted.end()) {
-        S->admitted.erase(it);
-        S->used -= s->bytes;
-    }
+    const bool held = it != S->admitted.end();
+    if (held) S->admitted.erase(it);
     auto wt = std::find(S->waiting.begin(), S->waiting.end(), s);
     if (wt != S->waiting.end()) S->waiting.erase(wt);
     gz_graph* g = s->g;
     lk.unlock();
     gz_free(g);
+    lk.lock();
+    if (held) S->used -= s->bytes;  // the memory is free now: waiting sessions may go
+    lk.unlock();
     delete s;
-    S->cv_work.notify_one();  // memory freed: waiting sessions may be admitted
+    S->cv_admit.notify_one();
     return GZ_OK;
 }
 
@@ -900,6 +924,12 @@ gz_status gz_server_timeline(gz_server* S, gz_tick_record* out, uint64_t cap, ui
 
 gz_status gz_server_destroy(gz_server* S) {
     if (!S) return GZ_OK;
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->stop_admit = true;
+    }
+    S->cv_admit.notify_one();
+    S->admitter.join();
     {
         std::lock_guard<std::mutex> lk(S->mu);
         S->stop = true;

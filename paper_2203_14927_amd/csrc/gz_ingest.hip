@@ -958,7 +958,9 @@ gz_status ensure_scratch(IngestScratch& S, uint64_t N, uint32_t T, uint32_t G, u
 }  // namespace
 
 size_t update_smem_bytes(uint32_t lds_rows, uint32_t Bmax, uint32_t Pmax, bool wide) {
-    return (size_t)tile_rows(lds_rows, Bmax) * tile_row_words(Pmax, wide) * 4;
+    // narrow graphs' update kernels stage small items' entries ahead of the tile
+    const size_t stage = wide ? 0 : kItemStageWords;
+    return (stage + (size_t)tile_rows(lds_rows, Bmax) * tile_row_words(Pmax, wide)) * 4;
 }
 
 gz_status set_smem_limit(const void* fn, size_t bytes) {

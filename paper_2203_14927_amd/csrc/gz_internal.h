@@ -293,6 +293,9 @@ hipError_t noalloc_scratch(uint8_t** ptr, size_t* cap);
 // LDS rows of a tile for launches that keep up to lds_rows rows of graphs with
 // up to Bmax rows: every row when they fit, else lds_rows plus one sink row
 // that collects entries deeper than an item's rows (applied to HBM instead)
+// LDS words at the start of an update kernel's dynamic shared memory that
+// stage a small work item's entries (the tile follows them)
+constexpr uint32_t kItemStageWords = 512;
 __host__ __device__ __forceinline__ uint32_t tile_rows(uint32_t lds_rows, uint32_t Bmax) {
     return lds_rows >= Bmax ? Bmax : lds_rows + 1;
 }

@@ -475,17 +475,97 @@ __device__ __forceinline__ void xor_share(const Src& ent, GroupShare r, uint4 a,
 // == count.  The first quads are issued before the tile set-up so that both
 // loads overlap; the barriers around the XOR phase are inside (every thread of
 // the workgroup calls this).
+// A small item's entries staged in LDS: group j of J takes entries j, j + J,
+// j + 2J, ... of [lo, hi) (any split of the entries gives the same XOR), four
+// at a time; every lane of a group reads the same words (broadcast reads).
+template <bool kWide, int kSide>
+__device__ __forceinline__ void xor_staged(const uint32_t* __restrict__ st, uint32_t lo,
+                                           uint32_t hi, uint32_t node, const Lane<kWide>& ln,
+                                           const ConstsOf<kWide, kSide>& nc, const GraphDesc& g,
+                                           uint32_t DL, uint32_t row_bytes, uint8_t* tb,
+                                           uint32_t* skl) {
+    const uint32_t Bm1 = g.B - 1;
+    const uint32_t J = ln.J;
+    const uint32_t plane_words = kC;
+#define GZ_ONE_S(x)                                                                 \
+    if (xor_entry<false, kWide, kSide>((x), node, ln, nc, Bm1, DL, row_bytes, tb)) \
+    xor_entry_deep<kWide, kSide>((x), node, ln, nc, Bm1, DL, skl, plane_words, g)
+    uint32_t e = lo + ln.j;
+    for (; e + 3 * J < hi; e += 4 * J) {
+        const uint32_t x0 = st[e], x1 = st[e + J], x2 = st[e + 2 * J], x3 = st[e + 3 * J];
+        GZ_ONE_S(x0);
+        GZ_ONE_S(x1);
+        GZ_ONE_S(x2);
+        GZ_ONE_S(x3);
+    }
+    for (; e < hi; e += J) {
+        const uint32_t x = st[e];
+        GZ_ONE_S(x);
+    }
+#undef GZ_ONE_S
+}
+
+// The XOR phase of one item (lanes of active groups; wide graphs with grouped
+// entries take the two sides of the node one after the other).
+template <bool kAllRows, bool kWide, int kSide1, typename Src>
+__device__ __forceinline__ void xor_item(const Src& ent, GroupShare r, uint4 a, uint4 b,
+                                         uint32_t count, uint32_t split, uint32_t node,
+                                         const Lane<kWide>& ln,
+                                         const ConstsOf<kWide, kSide1>& nc, const GraphDesc& g,
+                                         uint32_t DL, const TileWalk<kWide>& tw, uint32_t* tile,
+                                         uint32_t* skn) {
+    const uint32_t Bm1 = g.B - 1;
+    const uint32_t row_bytes = tw.RW * 4;
+    const uint32_t plane_words = kC;  // the planes of a row sit side by side
+    uint8_t* tb = (uint8_t*)tile;
+    uint32_t* skl = skn + ln.hbm_word;
+    xor_share<kAllRows, kWide, kSide1>(ent, r, a, b, node, ln, nc, Bm1, DL, row_bytes, tb, skl,
+                                       plane_words, g);
+    if constexpr (kSide1 == kBelow) {
+        if (split < count) {
+            const GroupShare r2 = group_share(ent, split, count, ln.J, ln.j);
+            uint4 a2 = make_uint4(0, 0, 0, 0), b2 = a2;
+            if (r2.pipe) {
+                a2 = ent.quad(r2.ea);
+                b2 = ent.quad(r2.ea + 4);
+            }
+            const ConstsOf<kWide, kAbove> nc2 = item_consts<kWide, kAbove>(g, ln.p, node);
+            xor_share<kAllRows, kWide, kAbove>(ent, r2, a2, b2, node, ln, nc2, Bm1, DL,
+                                               row_bytes, tb, skl, plane_words, g);
+        }
+    }
+}
+
+// Apply `count` entries to one node.  The J groups of P lanes each take a
+// share of the entries.  With kSide1 == kBelow (wide graphs, grouped entries)
+// entries [0, split) have neighbours below the node and [split, count) above
+// it, and each run is hashed with its own straight-line code; otherwise split
+// == count.  The barriers around the XOR phase are inside (every thread of the
+// workgroup calls this).
+// A large item issues its first entry quads before the tile set-up, so that
+// both loads overlap, and reads the rest from HBM while it hashes.  A small
+// item (stage non-null: at most two entries per thread) loads all its entries
+// together with the tile into LDS: its XOR phase then waits on no HBM load,
+// and the item costs one memory latency instead of one per set of entries
+// (small items are too short to hide those behind hashing).
 template <bool kAllRows, bool kWide, int kSide1, typename Src>
 __device__ __forceinline__ void apply_entries(const Src& ent, uint32_t count, uint32_t split,
                                               uint32_t node, const Lane<kWide>& ln,
                                               const GraphDesc& g, uint32_t DL,
                                               uint32_t* __restrict__ tile,
-                                              uint32_t* __restrict__ skn, bool shared) {
+                                              uint32_t* __restrict__ skn, bool shared,
+                                              uint32_t* __restrict__ stage) {
     const TileWalk<kWide> tw(g.P, g.B, DL);
     ConstsOf<kWide, kSide1> nc{};
     GroupShare r{};
     uint4 a = make_uint4(0, 0, 0, 0), b = a;
-    if (ln.active) {
+    const uint32_t t = threadIdx.x;
+    uint32_t s0 = 0, s1 = 0;
+    if (!kWide && stage) {
+        if (t < count) s0 = ent.one(t);
+        if (t + blockDim.x < count) s1 = ent.one(t + blockDim.x);
+        if (ln.active) nc = item_consts<kWide, kSide1>(g, ln.p, node);
+    } else if (ln.active) {
         nc = item_consts<kWide, kSide1>(g, ln.p, node);
         r = group_share(ent, 0, split, ln.J, ln.j);
         if (r.pipe) {
@@ -495,27 +575,26 @@ __device__ __forceinline__ void apply_entries(const Src& ent, uint32_t count, ui
     }
     if (shared) tile_zero(tile, tw);
     else tile_load(tile, skn, tw);
+    if (!kWide && stage) {
+        if (t < count) stage[t] = s0;
+        if (t + blockDim.x < count) stage[t + blockDim.x] = s1;
+    }
     __syncthreads();
     if (ln.active) {
-        const uint32_t Bm1 = g.B - 1;
-        const uint32_t row_bytes = tw.RW * 4;
-        const uint32_t plane_words = kC;  // the planes of a row sit side by side
-        uint8_t* tb = (uint8_t*)tile;
-        uint32_t* skl = skn + ln.hbm_word;
-        xor_share<kAllRows, kWide, kSide1>(ent, r, a, b, node, ln, nc, Bm1, DL, row_bytes, tb,
-                                           skl, plane_words, g);
-        if constexpr (kSide1 == kBelow) {
-            if (split < count) {
-                const GroupShare r2 = group_share(ent, split, count, ln.J, ln.j);
-                uint4 a2 = make_uint4(0, 0, 0, 0), b2 = a2;
-                if (r2.pipe) {
-                    a2 = ent.quad(r2.ea);
-                    b2 = ent.quad(r2.ea + 4);
+        if (!kWide && stage) {
+            uint8_t* tb = (uint8_t*)tile;
+            uint32_t* skl = skn + ln.hbm_word;
+            xor_staged<kWide, kSide1>(stage, 0, split, node, ln, nc, g, DL, tw.RW * 4, tb, skl);
+            if constexpr (kSide1 == kBelow) {
+                if (split < count) {
+                    const ConstsOf<kWide, kAbove> nc2 = item_consts<kWide, kAbove>(g, ln.p, node);
+                    xor_staged<kWide, kAbove>(stage, split, count, node, ln, nc2, g, DL,
+                                              tw.RW * 4, tb, skl);
                 }
-                const ConstsOf<kWide, kAbove> nc2 = item_consts<kWide, kAbove>(g, ln.p, node);
-                xor_share<kAllRows, kWide, kAbove>(ent, r2, a2, b2, node, ln, nc2, Bm1, DL,
-                                                   row_bytes, tb, skl, plane_words, g);
             }
+        } else {
+            xor_item<kAllRows, kWide, kSide1>(ent, r, a, b, count, split, node, ln, nc, g, DL,
+                                              tw, tile, skn);
         }
     }
     __syncthreads();
@@ -551,7 +630,9 @@ __device__ __forceinline__ void update_items(const WorkItem* __restrict__ items,
                                              uint32_t* __restrict__ ctl,
                                              const uint32_t* __restrict__ grouped,
                                              const GraphDesc* __restrict__ gd, uint32_t lds_rows,
-                                             uint32_t* __restrict__ tile, uint32_t* s_ticket) {
+                                             uint32_t* __restrict__ smem, uint32_t* s_ticket) {
+    uint32_t* tile = smem + (kWide ? 0u : kItemStageWords);
+    const uint32_t stage_max = min(kItemStageWords, 2u * blockDim.x);
     if (ctl[2]) return;
     const uint32_t n_items = ctl[1];
     const uint32_t run = max(1u, n_items / (gridDim.x * 16u));
@@ -586,12 +667,14 @@ __device__ __forceinline__ void update_items(const WorkItem* __restrict__ items,
         uint32_t* skn = g.sk + (uint64_t)(node - g.sk_first) * Layout<kWide>::kPl * g.B * g.P;
         constexpr int kS = kWide ? kBelow : kAnySide;
         const uint32_t split = kWide ? w.split : w.count;
+        // (wide graphs, whose update kernel is at its register limit, do not stage)
+        uint32_t* stage = !kWide && w.count <= stage_max ? smem : nullptr;
         if (DL == g.B)
             apply_entries<true, kWide, kS>(src, w.count, split, node, ln, g, DL, tile, skn,
-                                           w.shared != 0);
+                                           w.shared != 0, stage);
         else
             apply_entries<false, kWide, kS>(src, w.count, split, node, ln, g, DL, tile, skn,
-                                            w.shared != 0);
+                                            w.shared != 0, stage);
         __syncthreads();  // the tile is reused by the next item
     }
 }
@@ -601,9 +684,9 @@ __global__ __launch_bounds__(1024) void k_update(const WorkItem* __restrict__ it
                                                  const uint32_t* __restrict__ grouped,
                                                  const GraphDesc* __restrict__ gd,
                                                  uint32_t lds_rows) {
-    extern __shared__ uint32_t tile[];
+    extern __shared__ uint32_t smem[];
     __shared__ uint32_t s_ticket;
-    update_items<false>(items, ctl, grouped, gd, lds_rows, tile, &s_ticket);
+    update_items<false>(items, ctl, grouped, gd, lds_rows, smem, &s_ticket);
 }
 
 __global__ __launch_bounds__(1024) void k_update_wide(const WorkItem* __restrict__ items,
@@ -611,9 +694,9 @@ __global__ __launch_bounds__(1024) void k_update_wide(const WorkItem* __restrict
                                                       const uint32_t* __restrict__ grouped,
                                                       const GraphDesc* __restrict__ gd,
                                                       uint32_t lds_rows) {
-    extern __shared__ uint32_t tile[];
+    extern __shared__ uint32_t smem[];
     __shared__ uint32_t s_ticket;
-    update_items<true>(items, ctl, grouped, gd, lds_rows, tile, &s_ticket);
+    update_items<true>(items, ctl, grouped, gd, lds_rows, smem, &s_ticket);
 }
 
 // one node's neighbour list (plain per-node path): every workgroup takes one
@@ -630,7 +713,7 @@ __global__ __launch_bounds__(1024) void k_update_node(const uint32_t* __restrict
     const Lane<false> ln = make_lane<false>(g);
     uint32_t* skn = g.sk + (uint64_t)(node - g.sk_first) * kPlanes * g.B * g.P;
     apply_entries<false, false, kAnySide>(NeighbourEntries{nbrs + begin, node}, cnt, cnt, node,
-                                          ln, g, DL, tile, skn, gridDim.x > 1);
+                                          ln, g, DL, tile, skn, gridDim.x > 1, nullptr);
 }
 
 __global__ __launch_bounds__(1024) void k_update_node_wide(const uint32_t* __restrict__ nbrs,
@@ -646,7 +729,7 @@ __global__ __launch_bounds__(1024) void k_update_node_wide(const uint32_t* __res
     const Lane<true> ln = make_lane<true>(g);
     uint32_t* skn = g.sk + (uint64_t)(node - g.sk_first) * kPlanesWide * g.B * g.P;
     apply_entries<false, true, kAnySide>(GroupedEntries{nbrs + begin}, cnt, cnt, node, ln, g, DL,
-                                         tile, skn, gridDim.x > 1);
+                                         tile, skn, gridDim.x > 1, nullptr);
 }
 
 // Wide graphs: order each work item's entries so that neighbours below the

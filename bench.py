@@ -354,6 +354,9 @@ def main() -> int:
                          "(empty: closed loop only)")
     ap.add_argument("--hbm-budget-gb", type=float, default=120.0, help="serving: admission budget")
     ap.add_argument("--tick-updates", type=int, default=16 << 20, help="serving: updates per tick")
+    ap.add_argument("--serving-dump", default="",
+                    help="serving: write each open-loop run's schedule, latencies and tick "
+                         "records to <prefix>_<load%%>.npz")
     ap.add_argument("--gen-workers", type=int, default=16,
                     help="serving: processes generating the session streams (1: in-process)")
     ap.add_argument("--client-threads", type=int, default=16,
@@ -764,8 +767,14 @@ def run_serving(args) -> dict:
             gaps = rng.exponential(1e9 / rate, int(first[k + 1] - first[k]))
             arrival[first[k]:first[k + 1]] = opens[k] + np.cumsum(gaps)
         r, st = once(opens.astype(np.uint64), arrival.astype(np.uint64))
-        st.pop("timeline")
+        tl = st.pop("timeline")
+        if args.serving_dump:
+            np.savez_compressed(f"{args.serving_dump}_{int(load * 100)}.npz", opens=opens,
+                                arrival=arrival, first=first, lat=r["batch_latency_ns"],
+                                svc=r["batch_service_ns"], qlat=r["query_latency_ns"],
+                                ticks=tl)
         w = r["wall_ns"] / 1e9
+        log(f"[bench]   server stats: {st}")
         run = {"load": load, "offered_updates_per_s": load * cap, "sessions_open": n_conc,
                "achieved_updates_per_s": total / w, "wall_s": w,
                "batch_latency_ms": _pcts(r["batch_latency_ns"]),

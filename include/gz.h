@@ -101,6 +101,11 @@ typedef struct gz_config {
     uint32_t rounds;        /* R override (tests force failures with a small R); 0 = rule */
     uint32_t tier;          /* GZ_TIER_HBM (0) or GZ_TIER_HOST (1) */
     uint64_t staging_bytes; /* host tier: device bytes of the two slab buffers (0 = 128 MiB) */
+    void* storage;          /* HBM tier, nullable: device memory (256-byte aligned) that
+                               holds the sketches instead of an allocation of the graph's
+                               own; the caller keeps ownership and frees it after gz_free */
+    uint64_t storage_bytes; /* its size: at least the graph's sketch bytes (gz_shape:
+                               V * R * C * B * 12, or * 16 for V > 65536), else GZ_EINVAL */
 } gz_config;
 
 /* Sketch residency.  GZ_TIER_HOST keeps a graph's sketches in pinned host
@@ -419,7 +424,8 @@ gz_status gz_measure_peaks(gz_peaks* out, hipStream_t stream);
  *   gz_server_destroy stops the server and frees every session.
  * Statistics: ticks, updates applied, queries, sessions; batches submitted by
  *   copy and in place; bytes the gather kernels staged; worker time blocked on
- *   a staging set and spent building and launching ticks.
+ *   a staging set and spent building and launching ticks; fused query runs;
+ *   time spent creating and releasing sessions' graphs (sum and maximum).
  * ---------------------------------------------------------------------- */
 typedef struct gz_server gz_server;
 typedef struct gz_session gz_session;
@@ -440,6 +446,8 @@ typedef struct gz_server_stats {
     uint64_t batches_copied, batches_inplace, staged_bytes;
     uint64_t worker_wait_ns, worker_launch_ns;
     uint64_t query_runs;  /* fused Boruvka runs that answered the queries */
+    uint64_t create_ns, create_ns_max;  /* admitted sessions' graph creation time */
+    uint64_t free_ns, free_ns_max;      /* closed sessions' graph release time */
 } gz_server_stats;
 gz_status gz_server_create(uint64_t hbm_budget, uint64_t tick_updates, gz_server** out);
 gz_status gz_session_open(gz_server* srv, uint32_t V, uint64_t seed, gz_session** out);

@@ -35,7 +35,8 @@ class GzError(RuntimeError):
 
 class gz_config(ctypes.Structure):
     _fields_ = [("rounds", ctypes.c_uint32), ("tier", ctypes.c_uint32),
-                ("staging_bytes", ctypes.c_uint64)]
+                ("staging_bytes", ctypes.c_uint64), ("storage", ctypes.c_void_p),
+                ("storage_bytes", ctypes.c_uint64)]
 
 
 GZ_TIER_HBM = 0

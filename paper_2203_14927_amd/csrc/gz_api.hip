@@ -30,6 +30,45 @@ uint32_t host_hash(uint64_t mult, uint64_t incr, uint64_t x) {
 }
 }  // namespace
 
+// Graph memory comes from the device's stream-ordered pool where the device
+// has one (memory freed into it is kept for later graphs): freeing a graph then
+// costs no wait for the rest of the device's work, whereas hipFree waits for
+// the whole device, which stalls every other stream of a serving process each
+// time a session ends.
+namespace {
+struct PoolState {
+    std::once_flag once;
+    bool ok = false;
+};
+bool use_pool(int dev) {
+    static PoolState* states = new PoolState[64];  // never freed: used until exit
+    PoolState& ps = states[(unsigned)dev % 64];
+    std::call_once(ps.once, [&] {
+        int v = 0;
+        hipMemPool_t pool = nullptr;
+        uint64_t keep = UINT64_MAX;
+        ps.ok = hipDeviceGetAttribute(&v, hipDeviceAttributeMemoryPoolsSupported, dev) ==
+                    hipSuccess &&
+                v && hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess &&
+                hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep) == hipSuccess;
+        (void)hipGetLastError();
+    });
+    return ps.ok;
+}
+
+hipError_t graph_alloc(const gz_graph* g, void** p, size_t bytes, hipStream_t s) {
+    return use_pool(g->device) ? hipMallocAsync(p, bytes, s) : hipMalloc(p, bytes);
+}
+
+// after every use of p is complete (the caller has waited for the graph's work)
+void graph_release(const gz_graph* g, void* p, hipStream_t s) {
+    if (!p) return;
+    if (use_pool(g->device)) hipFreeAsync(p, s);
+    else hipFree(p);
+}
+}  // namespace
+
+
 // the graph's query stream, created on first use (many-graph sets never query
 // most graphs one by one)
 hipError_t query_stream(gz_graph* g, hipStream_t* out) {
@@ -320,29 +359,41 @@ gz_status init_graph(gz_graph** out, uint32_t V, uint64_t seed, const gz_config*
         delete g;
         return fail(GZ_EINVAL, "unknown sketch tier");
     }
-    hipError_t e = hipSuccess;
-    if (tier == GZ_TIER_HBM) {
-        e = hipMalloc((void**)&g->sk, g->sk_words * 4);
+    // set-up work goes on the graph's own stream and waits for that stream only,
+    // so that creating a graph does not wait for other work on the device
+    hipStream_t is = nullptr;
+    hipError_t e = query_stream(g, &is);
+    if (e != hipSuccess) {
+        delete g;
+        return hip_fail(e, "graph stream");
+    }
+    if (tier == GZ_TIER_HBM && cfg && cfg->storage) {
+        if (cfg->storage_bytes < g->sk_words * 4 || ((uintptr_t)cfg->storage & 255)) {
+            hipStreamDestroy(is);
+            delete g;
+            return fail(GZ_EINVAL, "sketch storage too small or not 256-byte aligned");
+        }
+        g->sk = static_cast<uint32_t*>(cfg->storage);
+        g->sk_owned = false;
+    } else if (tier == GZ_TIER_HBM) {
+        e = graph_alloc(g, (void**)&g->sk, g->sk_words * 4, is);
         if (e != hipSuccess) {
+            hipStreamDestroy(is);
             delete g;
             return fail(GZ_ENOMEM, "out of device memory for the sketches");
         }
     }
-    // set-up work goes on the graph's own stream and waits for that stream only,
-    // so that creating a graph does not wait for other work on the device
-    hipStream_t is = nullptr;
-    e = query_stream(g, &is);
-    if (e == hipSuccess) e = hipMalloc((void**)&g->seeds, soa.size() * 4);
+    e = graph_alloc(g, (void**)&g->seeds, soa.size() * 4, is);
     if (e == hipSuccess)
         e = hipMemcpyAsync(g->seeds, soa.data(), soa.size() * 4, hipMemcpyHostToDevice, is);
     if (e == hipSuccess) e = err_word_take(g);
-    if (e == hipSuccess && g->sk) e = hipMemsetAsync(g->sk, 0, g->sk_words * 4, is);
+    if (e == hipSuccess && g->sk) e = zero_words(g->sk, g->sk_words, is);
     if (e == hipSuccess && tier == GZ_TIER_HOST) {
         const gz_status ts = tier_create(g, cfg->staging_bytes);
         if (ts != GZ_OK) {
             hipStreamSynchronize(is);
             tier_free(g);
-            hipFree(g->seeds);
+            graph_release(g, g->seeds, is);
             err_word_release(g);
             hipStreamDestroy(is);
             delete g;
@@ -353,12 +404,12 @@ gz_status init_graph(gz_graph** out, uint32_t V, uint64_t seed, const gz_config*
     if (e == hipSuccess) e = hipStreamSynchronize(is);
     if (e != hipSuccess) {
         gz_status s = hip_fail(e, "graph init");
-        if (is) hipStreamSynchronize(is);
+        hipStreamSynchronize(is);
         tier_free(g);
-        hipFree(g->sk);
-        hipFree(g->seeds);
+        if (g->sk_owned) graph_release(g, g->sk, is);
+        graph_release(g, g->seeds, is);
         err_word_release(g);
-        if (is) hipStreamDestroy(is);
+        hipStreamDestroy(is);
         delete g;
         return s;
     }
@@ -394,8 +445,15 @@ gz_status gz_free(gz_graph* g) {
     free_ingest_scratch(g->ing);
     free_query_scratch(g->q);
     tier_free(g);
-    hipFree(g->sk);
-    hipFree(g->seeds);
+    hipStream_t s = nullptr;
+    if (!g->sk_owned) g->sk = nullptr;  // caller storage
+    if (query_stream(g, &s) == hipSuccess) {
+        graph_release(g, g->sk, s);
+        graph_release(g, g->seeds, s);
+    } else {
+        hipFree(g->sk);
+        hipFree(g->seeds);
+    }
     err_word_release(g);
     for (hipEvent_t e : g->prof_ev)
         if (e) hipEventDestroy(e);
@@ -444,7 +502,7 @@ gz_status gz_reset(gz_graph* g, hipStream_t stream) {
     if (!g) return fail(GZ_EINVAL, "null graph");
     if (g->tier) return tier_reset(g);
     GZ_HIP(fence_wait(stream, g));
-    GZ_HIP(hipMemsetAsync(g->sk, 0, g->sk_words * 4, stream));
+    GZ_HIP(zero_words(g->sk, g->sk_words, stream));
     GZ_HIP(fence_record(stream, g));
     return GZ_OK;
 }

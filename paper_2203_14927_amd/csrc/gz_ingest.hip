@@ -26,6 +26,28 @@ __global__ void k_fill_u32(uint32_t* __restrict__ p, uint64_t n, uint32_t v) {
     for (; i < n; i += stride) p[i] = v;
 }
 
+// zero n words (16-byte stores; p from hipMalloc/hipMallocAsync, so 256-byte aligned)
+__global__ __launch_bounds__(256) void k_zero_words(uint32_t* __restrict__ p, uint64_t n) {
+    uint4* q = reinterpret_cast<uint4*>(p);
+    const uint64_t n4 = n / 4;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += stride)
+        q[i] = make_uint4(0, 0, 0, 0);
+    for (uint64_t i = n4 * 4 + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+        p[i] = 0;
+}
+
+// Clearing with a kernel rather than hipMemsetAsync keeps large clears (a
+// new graph's sketches) off the copy engines, which every call's small
+// host-to-device copies need, and can be captured into a HIP graph.
+hipError_t zero_words(uint32_t* p, uint64_t n, hipStream_t stream) {
+    if (!n) return hipSuccess;
+    const uint64_t blocks =
+        std::min<uint64_t>((n / 4 + 255) / 256 + 1, (uint64_t)device_cu_count() * 8);
+    k_zero_words<<<(uint32_t)blocks, 256, 0, stream>>>(p, n);
+    return hipGetLastError();
+}
+
 __global__ void k_note_error(const GraphDesc* __restrict__ descs, uint32_t G,
                              const uint32_t* __restrict__ call_err) {
     if (*call_err == 0) return;

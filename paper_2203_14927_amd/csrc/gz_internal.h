@@ -206,6 +206,7 @@ struct gz_graph {
     uint64_t n = 0;
     uint64_t seed = 0;
     uint32_t* sk = nullptr;            // device sketch words
+    bool sk_owned = true;              // false: caller storage (gz_config.storage)
     uint64_t sk_words = 0;
     uint32_t* seeds = nullptr;         // device seeds [12][P] (18 words per pair when wide)
     // error word: set by the device when an asynchronous call that included this
@@ -229,6 +230,9 @@ struct gz_graph {
 };
 
 namespace gz {
+
+// zero n words of device memory with a kernel on `stream`
+hipError_t zero_words(uint32_t* p, uint64_t n, hipStream_t stream);
 
 // error reporting
 gz_status fail(gz_status s, const std::string& msg);

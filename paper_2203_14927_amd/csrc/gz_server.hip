@@ -19,6 +19,7 @@
 #include <condition_variable>
 #include <cstring>
 #include <deque>
+#include <map>
 #include <mutex>
 #include <thread>
 #include <vector>
@@ -50,6 +51,79 @@ uint64_t session_bytes(uint32_t V) {
     const uint64_t query = (uint64_t)V * (3 * B * GZ_COLUMNS * 4 + 96);
     return sketch + query;
 }
+
+// bytes of a session's sketches (V <= 2^16: three planes)
+uint64_t sketch_bytes(uint32_t V) {
+    const uint64_t n = (uint64_t)V * (V - 1) / 2;
+    const uint64_t R = bitlen64(V - 1) + 1, B = bitlen64(n - 1) + 1;
+    return 12ull * B * R * GZ_COLUMNS * V;
+}
+
+// The server's sketch memory: one device allocation made when the server is
+// created, from which admitted sessions take their sketches (first fit,
+// 256-byte granules, neighbours merged when freed).  Device allocations made
+// while sessions are served (and the driver's clearing of them) would stall
+// the device for every other session.
+class Arena {
+  public:
+    static constexpr uint64_t kAlign = 256;
+    bool init(uint64_t bytes) {
+        bytes = (bytes + kAlign - 1) & ~(kAlign - 1);
+        if (!bytes || hipMalloc((void**)&base_, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            base_ = nullptr;
+            return false;
+        }
+        free_[0] = bytes;
+        return true;
+    }
+    void release() {
+        hipFree(base_);
+        base_ = nullptr;
+        free_.clear();
+    }
+    bool active() const { return base_ != nullptr; }
+    bool fits(uint64_t bytes) const {
+        bytes = round(bytes);
+        for (const auto& f : free_)
+            if (f.second >= bytes) return true;
+        return false;
+    }
+    uint8_t* take(uint64_t bytes) {
+        bytes = round(bytes);
+        for (auto it = free_.begin(); it != free_.end(); ++it)
+            if (it->second >= bytes) {
+                const uint64_t off = it->first, size = it->second;
+                free_.erase(it);
+                if (size > bytes) free_[off + bytes] = size - bytes;
+                return base_ + off;
+            }
+        return nullptr;
+    }
+    void give(uint8_t* p, uint64_t bytes) {
+        if (!p) return;
+        bytes = round(bytes);
+        uint64_t off = (uint64_t)(p - base_);
+        auto next = free_.lower_bound(off);
+        if (next != free_.end() && off + bytes == next->first) {
+            bytes += next->second;
+            next = free_.erase(next);
+        }
+        if (next != free_.begin()) {
+            auto prev = std::prev(next);
+            if (prev->first + prev->second == off) {
+                prev->second += bytes;
+                return;
+            }
+        }
+        free_[off] = bytes;
+    }
+
+  private:
+    static uint64_t round(uint64_t b) { return (b + kAlign - 1) & ~(kAlign - 1); }
+    uint8_t* base_ = nullptr;
+    std::map<uint64_t, uint64_t> free_;  // offset -> bytes
+};
 
 // Pinned host buffers for copied batches, in power-of-two size classes and
 // reused (allocating pinned memory costs far more than filling it).  Up to
@@ -189,6 +263,7 @@ struct gz_session {
     gz_graph* g = nullptr;            // non-null once admitted
     uint64_t admit_ns = 0;
     uint64_t wait_since = 0;          // when the session was opened
+    uint8_t* storage = nullptr;       // its sketches in the server's arena
     bool admitting = false;           // its graph is being created
     std::deque<gz_ticket*> queue;     // submitted, not yet taken by a tick
     uint32_t inflight = 0;            // taken, not yet completed (batches and query)
@@ -215,6 +290,7 @@ struct gz_server {
     bool stop_admit = false;
     hipStream_t stream = nullptr;
     PinnedPool pool;
+    Arena arena;  // sessions' sketches (inactive: each graph allocates its own)
     // double-buffered per-tick device staging (src then dst) and gather lists
     uint32_t* d_stage[2] = {nullptr, nullptr};
     uint64_t stage_cap[2] = {0, 0};  // updates
@@ -289,7 +365,9 @@ std::deque<gz_session*>::iterator admissible(gz_server* S) {
     if (it == S->waiting.end()) return it;
     const bool head_only = now_ns() - (*it)->wait_since > kAdmitPatienceNs;
     for (; it != S->waiting.end(); ++it) {
-        if (S->used + (*it)->bytes <= S->budget) return it;
+        if (S->used + (*it)->bytes <= S->budget &&
+            (!S->arena.active() || S->arena.fits(sketch_bytes((*it)->V))))
+            return it;
         if (head_only) break;
     }
     return S->waiting.end();
@@ -306,14 +384,26 @@ bool admit(gz_server* S, std::unique_lock<std::mutex>& lk) {
         S->waiting.erase(it);
         S->used += s->bytes;
         s->admitting = true;
+        gz_config cfg{};
+        if (S->arena.active()) {
+            s->storage = S->arena.take(sketch_bytes(s->V));
+            cfg.storage = s->storage;
+            cfg.storage_bytes = sketch_bytes(s->V);
+        }
         lk.unlock();
         gz_graph* g = nullptr;
-        const gz_status st = gz_sketch_init(&g, s->V, s->seed, nullptr);
+        const uint64_t t0 = now_ns();
+        const gz_status st = gz_sketch_init(&g, s->V, s->seed, &cfg);
+        const uint64_t dt = now_ns() - t0;
         lk.lock();
+        S->stats.create_ns += dt;
+        S->stats.create_ns_max = std::max(S->stats.create_ns_max, dt);
         s->admitting = false;
         S->cv_done.notify_all();  // a close may wait for the admission to end
         if (st != GZ_OK) {
             S->used -= s->bytes;
+            S->arena.give(s->storage, sketch_bytes(s->V));
+            s->storage = nullptr;
             S->waiting.push_front(s);  // retry later
             return false;
         }
@@ -628,6 +718,7 @@ gz_status gz_server_create(uint64_t hbm_budget, uint64_t tick_updates, gz_server
     hipEventRecord(S->stage_ev[1], S->stream);
     S->budget = hbm_budget;
     S->tick_cap = tick_updates ? tick_updates : (16ull << 20);
+    S->arena.init(hbm_budget);  // best effort: without it each graph allocates its own
     S->stats.hbm_budget = hbm_budget;
     S->worker = std::thread(worker_main, S);
     S->admitter = std::thread(admit_main, S);
@@ -895,8 +986,14 @@ gz_status gz_session_close(gz_session* s) {
     if (wt != S->waiting.end()) S->waiting.erase(wt);
     gz_graph* g = s->g;
     lk.unlock();
+    const uint64_t t0 = now_ns();
     gz_free(g);
+    const uint64_t dt = now_ns() - t0;
     lk.lock();
+    S->stats.free_ns += dt;
+    S->stats.free_ns_max = std::max(S->stats.free_ns_max, dt);
+    S->arena.give(s->storage, sketch_bytes(s->V));
+    s->storage = nullptr;
     if (held) S->used -= s->bytes;  // the memory is free now: waiting sessions may go
     lk.unlock();
     delete s;
@@ -965,6 +1062,7 @@ gz_status gz_server_destroy(gz_server* S) {
         hipHostFree(S->h_pieces[b]);
     }
     S->pool.release_all();
+    S->arena.release();
     hipHostFree(S->vflag);
     hipStreamDestroy(S->vstream);
     hipStreamDestroy(S->stream);

@@ -31,7 +31,8 @@ class gz_server_stats(ctypes.Structure):
                                                "sessions_active", "sessions_waiting", "hbm_used",
                                                "hbm_budget", "batches_copied", "batches_inplace",
                                                "staged_bytes", "worker_wait_ns",
-                                               "worker_launch_ns", "query_runs")]
+                                               "worker_launch_ns", "query_runs", "create_ns",
+                                               "create_ns_max", "free_ns", "free_ns_max")]
 
 
 def _declare(L):

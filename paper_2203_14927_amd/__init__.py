@@ -236,10 +236,15 @@ class Graph:
     """One graph's node sketches (in HBM, or in pinned host memory with host_tier=True)."""
 
     def __init__(self, V: int, seed: int, rounds: int = 0, host_tier: bool = False,
-                 staging_bytes: int = 0):
+                 staging_bytes: int = 0, storage=None):
+        """storage: optional device tensor that holds the sketches (kept alive by the graph)."""
         L = lib()
         h = ctypes.c_void_p()
         cfg = gz_config(rounds, GZ_TIER_HOST if host_tier else GZ_TIER_HBM, int(staging_bytes))
+        if storage is not None:
+            cfg.storage = storage.data_ptr()
+            cfg.storage_bytes = storage.numel() * storage.element_size()
+            self._storage = storage
         check(L.gz_sketch_init(ctypes.byref(h), V, seed & 0xFFFFFFFFFFFFFFFF, ctypes.byref(cfg)))
         self._h = h
         _track("graph", self)

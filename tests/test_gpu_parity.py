@@ -441,3 +441,31 @@ def test_calls_with_small_and_large_items_in_sequence(gz, order):
         O2.ingest_nodes(np.full(len(nb), node, np.uint32), nb, [node])
         a, b = g.export(node, node + 1)
         assert (a[0] == O2.alpha[node]).all() and (b[0] == O2.gamma[node]).all()
+
+
+def test_graph_in_caller_storage(gz):
+    """Sketches kept in caller device memory (as a server's arena provides): the same bits as
+    a graph with its own allocation; storage too small or misaligned is rejected."""
+    import torch
+
+    V, seed = 900, 61
+    s = _stream(V, 20000, 62)
+    own = gz.Graph(V, seed=seed)
+    need = V * own.R * own.C * own.B * 12
+    buf = torch.full((need // 4 + 64,), 0x5A5A5A5A, dtype=torch.int32, device="cuda")
+    g = gz.Graph(V, seed=seed, storage=buf)  # starts from garbage: the library clears it
+    for x in (own, g):
+        x.ingest(to_dev(s.src), to_dev(s.dst))
+    a1, b1 = own.export()
+    a2, b2 = g.export()
+    assert (a1 == a2).all() and (b1 == b2).all()
+    O = oracle_for(s, seed)
+    assert_query_equal(g, O)
+    g.reset()
+    assert not g.export()[0].any()
+    g.close()
+    with pytest.raises(gz.GzError):
+        gz.Graph(V, seed=seed, storage=buf[: need // 8])
+    with pytest.raises(gz.GzError):
+        gz.Graph(V, seed=seed, storage=buf[1:])  # 4-byte aligned only
+    own.close()

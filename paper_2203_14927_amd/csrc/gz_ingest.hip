@@ -1007,10 +1007,12 @@ void free_ingest_scratch(IngestScratch& S) {
 }
 
 IngestScratch& shared_ingest_scratch(int device, std::unique_lock<std::mutex>& lock) {
-    static std::mutex mu;
-    static std::vector<IngestScratch> per_dev(64);
-    lock = std::unique_lock<std::mutex>(mu);
-    return per_dev[(size_t)device % per_dev.size()];
+    // never destroyed: nothing of the library is torn down by static destructors
+    // at process exit (device memory still held then goes with the process)
+    static std::mutex* mu = new std::mutex();
+    static std::vector<IngestScratch>* per_dev = new std::vector<IngestScratch>(64);
+    lock = std::unique_lock<std::mutex>(*mu);
+    return (*per_dev)[(size_t)device % per_dev->size()];
 }
 
 // Static shape of a fused launch sequence: descriptor table, grouping units

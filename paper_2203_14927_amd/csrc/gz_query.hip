@@ -1050,10 +1050,12 @@ void free_query_scratch(QueryScratch* q) {
 
 // Fused queries over several graphs share one scratch per device.
 QueryScratch& shared_query_scratch(int device, std::unique_lock<std::mutex>& lock) {
-    static std::mutex mu;
-    static std::vector<QueryScratch> per_dev(64);
-    lock = std::unique_lock<std::mutex>(mu);
-    return per_dev[(size_t)device % per_dev.size()];
+    // never destroyed: nothing of the library is torn down by static destructors
+    // at process exit (device memory still held then goes with the process)
+    static std::mutex* mu = new std::mutex();
+    static std::vector<QueryScratch>* per_dev = new std::vector<QueryScratch>(64);
+    lock = std::unique_lock<std::mutex>(*mu);
+    return (*per_dev)[(size_t)device % per_dev->size()];
 }
 
 gz_status boruvka(gz_graph* const* gs, uint32_t G, bool want_forest, QueryResult& out,

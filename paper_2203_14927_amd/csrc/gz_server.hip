@@ -1,11 +1,12 @@
-// Serving: many graph sessions share one GPU.  A server thread admits
-// sessions while their sketches fit an HBM budget and packs the update batches
-// queued by all admitted sessions into one fused multi-graph ingest per tick
-// (continuous batching: a batch submitted while a tick runs joins the next
-// one).  Connectivity queries go to a small pool of query threads, each query
-// on its session's own stream, so that queries of different sessions and the
-// next ticks' ingests overlap on the device.  Requests of one session are
-// applied in submission order: a query is taken once the session's earlier
+// Serving: many graph sessions share one GPU.  An admission thread admits
+// sessions while their sketches fit an HBM budget (their sketches cut from an
+// arena allocated with the server), and a worker thread packs the update
+// batches queued by all admitted sessions into one fused multi-graph ingest
+// per tick (continuous batching: a batch submitted while a tick runs joins the
+// next one).  Connectivity queries go to two query threads, each answering all
+// the queries queued at that time with one fused Boruvka run, so that queries
+// and the next ticks' ingests overlap on the device.  Requests of one session
+// are applied in submission order: a query is taken once the session's earlier
 // batches are applied, and the session's later batches wait for the query.
 //
 // A batch reaches HBM with one host copy at most: gz_submit_updates copies

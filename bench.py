@@ -354,6 +354,9 @@ def main() -> int:
                          "(empty: closed loop only)")
     ap.add_argument("--hbm-budget-gb", type=float, default=120.0, help="serving: admission budget")
     ap.add_argument("--tick-updates", type=int, default=16 << 20, help="serving: updates per tick")
+    ap.add_argument("--gutter-per-node", type=int, default=-1,
+                    help="serving: gutter updates per session node (-1: the library's default, "
+                         "0: no gutters)")
     ap.add_argument("--serving-dump", default="",
                     help="serving: write each open-loop run's schedule, latencies and tick "
                          "records to <prefix>_<load%%>.npz")
@@ -717,7 +720,8 @@ def run_serving(args) -> dict:
     queries_of = lambda q: q[q > 0]  # noqa: E731
 
     def once(opens=None, arrival=None):
-        srv = Server(hbm_budget=budget, tick_updates=args.tick_updates)
+        srv = Server(hbm_budget=budget, tick_updates=args.tick_updates,
+                     gutter_per_node=None if args.gutter_per_node < 0 else args.gutter_per_node)
         sess = [(V, sd, int(first[k]), len(sz), 0 if opens is None else int(opens[k]))
                 for k, (V, sd, sz) in enumerate(plans)]
         r = srv.replay(sess, offs, src, dst, arrival, query_every=50,
@@ -736,6 +740,8 @@ def run_serving(args) -> dict:
         "device_busy_frac": float(tl["device_ms"].sum() / 1e3 / wall),
         "device_ms_per_tick": _mean(tl["device_ms"]),
         "updates_per_tick": _mean(tl["updates"]),
+        "ingested_per_tick": _mean(tl["ingested"]),
+        "ingesting_ticks": int((tl["ingested"] > 0).sum()),
         "batches_per_tick": _mean(tl["batches"]),
         "graphs_per_tick": _mean(tl["graphs"]),
         "host_build_launch_ms_per_tick": _mean((tl["launched_ns"] - tl["take_ns"]) / 1e6),
@@ -797,7 +803,8 @@ def run_serving(args) -> dict:
                                f"threads), then open-loop Poisson arrivals at {args.loads} of the "
                                f"closed-loop rate with sessions arriving over time; seed 5",
                    "sessions": S, "batches": n_batches, "updates": total,
-                   "hbm_budget_gb": args.hbm_budget_gb, "tick_updates": args.tick_updates},
+                   "hbm_budget_gb": args.hbm_budget_gb, "tick_updates": args.tick_updates,
+                   "gutter_per_node": args.gutter_per_node},
         "batch_latency_ms": closed["batch"],
         "query_latency_ms": closed["query"],
         "open_loop": open_runs,

@@ -306,7 +306,10 @@ gz_status gz_query(gz_graph* g, uint32_t* labels, uint32_t* num_cc, uint32_t* ed
  *   (caller-owned; pinned memory reused across calls takes the copy fastest);
  *   num_cc, status: host arrays of G entries (nullable).  Returns GZ_OK if
  *   every graph finished, GZ_ESKETCH_FAIL if any did not.  Graphs with
- *   V > 65536 are queried one at a time (GZ_EINVAL here when G > 1).
+ *   V > 65536 are queried one at a time (GZ_EINVAL here when G > 1).  Runs
+ *   (G = 1 included) take one of a few scratch sets the library keeps per
+ *   device, so the graphs hold no query memory of their own; the call
+ *   returns once its work is done with the set.
  * ---------------------------------------------------------------------- */
 gz_status gz_connected_components_multi(gz_graph* const* gs, uint32_t G, uint32_t* labels,
                                         uint32_t* num_cc, int32_t* status);
@@ -382,11 +385,23 @@ gz_status gz_measure_peaks(gz_peaks* out, hipStream_t stream);
  *   A server thread admits sessions while the device bytes of their sketches
  *   (plus query scratch) fit `hbm_budget`; a session opened beyond the budget
  *   waits, with its requests queued, until closed sessions free memory.  Each
- *   tick packs the update batches queued by every admitted session (up to
- *   `tick_updates` updates, 0 = 16 Mi) into one fused multi-graph ingest
- *   (continuous batching: batches submitted while a tick runs join the next);
- *   a query is answered once every batch submitted before it in its session
- *   has been applied, and the session's later batches wait for it; the
+ *   tick takes the update batches queued by every admitted session (up to
+ *   `tick_updates` new updates, 0 = 16 Mi; continuous batching: batches
+ *   submitted while a tick runs join the next).  Like the gutters of Sec. 4.1 and 5.1,
+ *   each session buffers its batches in a gutter in HBM and applies them to
+ *   its sketches many at a time: a tick gathers batches into their sessions'
+ *   gutters, and applies a session's gutter (its content and the batches
+ *   taken behind it) when it cannot hold the next batch, when a query of the
+ *   session comes due, or when gz_session_graph needs the sketches; the
+ *   gutters a tick applies (up to `tick_updates` updates, one always) go
+ *   through one fused multi-graph ingest.  gz_server_set_gutter sets the
+ *   gutter size of sessions opened afterwards: updates_per_node * V updates,
+ *   at least 65536 (default 16 per node; 0: no gutters, every batch applied by
+ *   the tick that takes it); its 8 B per update count against the budget.
+ *   An update batch's ticket completes once the batch is in its session's
+ *   gutter, or applied.  A query is answered once every batch submitted
+ *   before it in its session has been applied, and the session's later
+ *   batches wait for it; the
  *   queries queued at that time are answered together by one fused Boruvka
  *   run over their graphs (gz_connected_components_multi), on one of two
  *   query threads, overlapping the next ticks' ingests on the device.  A session's requests
@@ -419,13 +434,17 @@ gz_status gz_measure_peaks(gz_peaks* out, hipStream_t stream);
  *   GZ_EINVAL.
  * gz_session_graph gives the session's graph handle (export, query), for use
  *   while none of the session's requests is queued or running; GZ_ESTATE
- *   before admission or with requests in flight.  The server keeps ownership.
+ *   before admission or with requests in flight.  It first waits for the
+ *   session's gutter to be applied, so that the sketches hold every batch;
+ *   a failed ingest of the gutter is returned.  The server keeps ownership.
  * gz_session_close waits for the session's requests and frees its sketches;
  *   gz_server_destroy stops the server and frees every session.
- * Statistics: ticks, updates applied, queries, sessions; batches submitted by
+ * Statistics: ticks, updates taken, queries, sessions; batches submitted by
  *   copy and in place; bytes the gather kernels staged; worker time blocked on
  *   a staging set and spent building and launching ticks; fused query runs;
- *   time spent creating and releasing sessions' graphs (sum and maximum).
+ *   time spent creating and releasing sessions' graphs (sum and maximum);
+ *   updates applied to sketches and gutters flushed.  A query reports a
+ *   failed ingest of its session's gutter in its status.
  * ---------------------------------------------------------------------- */
 typedef struct gz_server gz_server;
 typedef struct gz_session gz_session;
@@ -448,6 +467,8 @@ typedef struct gz_server_stats {
     uint64_t query_runs;  /* fused Boruvka runs that answered the queries */
     uint64_t create_ns, create_ns_max;  /* admitted sessions' graph creation time */
     uint64_t free_ns, free_ns_max;      /* closed sessions' graph release time */
+    uint64_t ingested;  /* updates applied to sketches (gutters flushed, batches staged) */
+    uint64_t flushes;   /* gutters flushed */
 } gz_server_stats;
 gz_status gz_server_create(uint64_t hbm_budget, uint64_t tick_updates, gz_server** out);
 gz_status gz_session_open(gz_server* srv, uint32_t V, uint64_t seed, gz_session** out);
@@ -461,15 +482,18 @@ gz_status gz_wait_any(gz_ticket* const* tickets, uint32_t n, uint64_t timeout_ns
                       uint32_t* index, gz_result* res);
 gz_status gz_session_graph(gz_session* s, gz_graph** out);
 gz_status gz_session_close(gz_session* s);
+gz_status gz_server_set_gutter(gz_server* srv, uint32_t updates_per_node);
 gz_status gz_server_get_stats(gz_server* srv, gz_server_stats* out);
 /* gz_server_timeline -- the first min(cap, *n) tick records (of the first 2^20
  *   ticks), *n = ticks recorded: when the worker took the tick, when its
  *   gather and ingest were enqueued, when the worker saw them complete
- *   (steady-clock ns), its updates, batches and graphs, and the device time
- *   from its first to its last kernel. */
+ *   (steady-clock ns), its new updates, the updates its ingest applied,
+ *   its batches and the graphs it updated, and the device time from its
+ *   first to its last kernel. */
 typedef struct gz_tick_record {
     uint64_t take_ns, launched_ns, done_ns;
-    uint64_t updates;
+    uint64_t updates;   /* new updates the tick took */
+    uint64_t ingested;  /* updates its ingest applied to sketches */
     uint32_t batches, graphs;
     float device_ms;
     uint32_t reserved;

@@ -557,7 +557,7 @@ gz_status gz_query(gz_graph* g, uint32_t* labels, uint32_t* num_cc, uint32_t* ed
     if (st) return st;
     QueryResult res;
     gz_graph* gs[1] = {g};
-    st = boruvka(gs, 1, edges != nullptr || num_edges != nullptr, res, labels);
+    st = boruvka(gs, 1, edges != nullptr || num_edges != nullptr, res, labels, false);
     if (st) return st;
     if (num_cc) *num_cc = res.num_cc[0];
     if (edges) std::memcpy(edges, res.forest.data(), 4ull * res.forest.size());
@@ -585,7 +585,7 @@ gz_status gz_connected_components_multi(gz_graph* const* gs, uint32_t G, uint32_
         if (st) return st;
     }
     QueryResult res;
-    gz_status st = boruvka(gs, G, false, res, labels);
+    gz_status st = boruvka(gs, G, false, res, labels, true);
     if (st) return st;
     bool any_fail = false;
     for (uint32_t k = 0; k < G; ++k) {

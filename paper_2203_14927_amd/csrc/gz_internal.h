@@ -342,9 +342,10 @@ struct QueryResult {
     std::vector<uint64_t> forest_off;  // G+1 offsets into forest pairs
     uint32_t rounds = 0;
 };
-// labels_out (host, may be null): sum of V labels, local ids, graph after graph
+// labels_out (host, may be null): sum of V labels, local ids, graph after graph;
+// shared_scratch: a per-device scratch set (fused calls) instead of the graph's own
 gz_status boruvka(gz_graph* const* gs, uint32_t G, bool want_forest, QueryResult& out,
-                  uint32_t* labels_out);
+                  uint32_t* labels_out, bool shared_scratch);
 void free_query_scratch(QueryScratch* q);
 
 // sketch export (gz_api.hip)

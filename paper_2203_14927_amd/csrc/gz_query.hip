@@ -1048,18 +1048,30 @@ void free_query_scratch(QueryScratch* q) {
     delete q;
 }
 
-// Fused queries over several graphs share one scratch per device.
+// Fused queries share a few scratch sets per device, so that runs on several
+// threads need not wait for each other and no graph holds query memory of its
+// own (allocating and freeing it while other work runs would stall the device).
+// A run holds its set's lock until its stream has finished with the set.
 QueryScratch& shared_query_scratch(int device, std::unique_lock<std::mutex>& lock) {
     // never destroyed: nothing of the library is torn down by static destructors
     // at process exit (device memory still held then goes with the process)
-    static std::mutex* mu = new std::mutex();
-    static std::vector<QueryScratch>* per_dev = new std::vector<QueryScratch>(64);
-    lock = std::unique_lock<std::mutex>(*mu);
-    return (*per_dev)[(size_t)device % per_dev->size()];
+    constexpr size_t kDevices = 64, kSets = 4;
+    static std::vector<std::mutex>* mus = new std::vector<std::mutex>(kDevices * kSets);
+    static std::vector<QueryScratch>* sets = new std::vector<QueryScratch>(kDevices * kSets);
+    const size_t base = (size_t)device % kDevices * kSets;
+    for (size_t i = 0; i < kSets; ++i) {
+        std::unique_lock<std::mutex> l((*mus)[base + i], std::try_to_lock);
+        if (l.owns_lock()) {
+            lock = std::move(l);
+            return (*sets)[base + i];
+        }
+    }
+    lock = std::unique_lock<std::mutex>((*mus)[base]);
+    return (*sets)[base];
 }
 
 gz_status boruvka(gz_graph* const* gs, uint32_t G, bool want_forest, QueryResult& out,
-                  uint32_t* labels_out) {
+                  uint32_t* labels_out, bool shared_scratch) {
     if (G == 0) return fail(GZ_EINVAL, "no graphs");
     std::vector<GraphDesc> descs(G);
     uint64_t T64 = 0;
@@ -1099,10 +1111,11 @@ gz_status boruvka(gz_graph* const* gs, uint32_t G, bool want_forest, QueryResult
     const uint32_t T = (uint32_t)T64;
     const uint32_t wpr = PLmax * Bmax * kC;
 
-    // single graphs keep their own scratch; fused queries share one per device
+    // single-graph queries keep the graph's own scratch; fused ones (of any
+    // number of graphs) take a shared set
     std::unique_lock<std::mutex> lock;
     QueryScratch* Q = nullptr;
-    if (G == 1) {
+    if (!shared_scratch) {
         if (!gs[0]->q) gs[0]->q = new QueryScratch();
         Q = gs[0]->q;
     } else {

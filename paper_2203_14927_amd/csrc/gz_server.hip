@@ -30,6 +30,8 @@
 namespace {
 
 constexpr int kQueryThreads = 2;
+constexpr uint32_t kGutterPerNode = 16;      // gutter updates per node of a session
+constexpr uint64_t kGutterMin = 1ull << 16;  // and at least this many
 constexpr size_t kQueryBatch = 512;  // queries answered by one fused run
 
 uint64_t now_ns() {
@@ -59,6 +61,10 @@ uint64_t sketch_bytes(uint32_t V) {
     const uint64_t R = bitlen64(V - 1) + 1, B = bitlen64(n - 1) + 1;
     return 12ull * B * R * GZ_COLUMNS * V;
 }
+
+// a session's share of the server's arena: its sketches, then its gutter
+uint64_t gutter_offset(uint32_t V) { return (sketch_bytes(V) + 255) & ~255ull; }
+uint64_t arena_bytes(uint32_t V, uint64_t gcap) { return gutter_offset(V) + 8 * gcap; }
 
 // The server's sketch memory: one device allocation made when the server is
 // created, from which admitted sessions take their sketches (first fit,
@@ -183,11 +189,13 @@ class PinnedPool {
 };
 
 // One piece of a tick's gather: up to kGatherPiece updates of one batch, read
-// from where the batch lies into positions out.. of the staging arrays.
+// from where the batch lies (or from a session's gutter) and written to the
+// tick's staging arrays or into a session's gutter.
 struct GatherPiece {
     const uint32_t* src;
     const uint32_t* dst;
-    uint64_t out;
+    uint32_t* out_src;
+    uint32_t* out_dst;
     uint32_t count;
     uint32_t pad;
 };
@@ -196,8 +204,7 @@ constexpr uint32_t kGatherThreads = 256;
 constexpr uint32_t kGatherUnroll = 4;  // loads of each array in flight per lane
 
 __global__ __launch_bounds__(kGatherThreads) void k_srv_gather(
-    const GatherPiece* __restrict__ pieces, uint32_t* __restrict__ out_src,
-    uint32_t* __restrict__ out_dst) {
+    const GatherPiece* __restrict__ pieces) {
     const GatherPiece p = pieces[blockIdx.x];
     // system-scope loads: host memory the caller may have rewritten since an
     // earlier tick read it is never served from a stale cached line; several
@@ -218,8 +225,8 @@ __global__ __launch_bounds__(kGatherThreads) void k_srv_gather(
         for (uint32_t u = 0; u < kGatherUnroll; ++u) {
             const uint32_t i = i0 + u * kGatherThreads + threadIdx.x;
             if (i < p.count) {
-                out_src[p.out + i] = a[u];
-                out_dst[p.out + i] = b[u];
+                p.out_src[i] = a[u];
+                p.out_dst[i] = b[u];
             }
         }
     }
@@ -271,11 +278,23 @@ struct gz_session {
     uint32_t upd_inflight = 0;        // batches taken, not yet completed
     bool query_busy = false;          // a query of this session is running
     bool closing = false;
+    // The session's gutter: batches are gathered into it and applied to the
+    // sketches together, when it cannot hold the next batch, when a query
+    // needs them or when gz_session_graph asks, so that one ingest updates
+    // each node's sketch with many updates at a time.
+    uint32_t* gut = nullptr;          // gcap sources, then gcap destinations (in the arena)
+    uint64_t gcap = 0;                // updates it holds (0: batches are applied as taken)
+    uint64_t gfill = 0;               // updates in it, those a running gather writes included
+    uint32_t ingests_inflight = 0;    // ticks whose ingest updates this session, not yet done
+    bool flush_req = false;           // gz_session_graph waits for the gutter to be applied
+    gz_status gstatus = GZ_OK;        // a failed ingest of its gutter, reported by its queries
 };
 
 struct gz_server {
     int device = 0;
     uint64_t budget = 0, used = 0, tick_cap = 0;
+    uint32_t gutter_per_node = kGutterPerNode;  // sessions opened from now on
+    uint64_t tick_seq = 0;
     std::mutex mu;
     std::condition_variable cv_work, cv_done, cv_query;
     std::deque<gz_ticket*> qq;        // queries handed to the query threads
@@ -312,40 +331,88 @@ struct gz_server {
 
 namespace {
 
-// Take work for one tick under the lock: each admitted session contributes
-// the update batches at the front of its queue (up to the tick's budget of
-// updates) and, if a query then heads its queue, that query.
+// Take work for one tick under the lock.  Each admitted session contributes
+// the update batches at the front of its queue (up to the tick's budget of new
+// updates): into its gutter while they fit, else to the tick's ingest behind
+// the gutter's content, which the tick then applies (a flush).  A query at the
+// front of the queue, or gz_session_graph, has the gutter flushed too, and the
+// query is taken once every earlier batch of its session is applied.  A tick
+// that writes batches into a session's gutter does not also flush it: the
+// flush of the next tick reads what this tick's gather wrote (one stream).
 struct Tick {
+    // sessions whose sketches the tick's ingest updates, each with the gutter
+    // updates it flushes and the batches staged behind them
     std::vector<gz_session*> upd_sessions;
+    std::vector<uint64_t> flushed;
     std::vector<std::vector<gz_ticket*>> upd;
+    // batches gathered into their session's gutter, at that gutter position
+    std::vector<std::pair<gz_ticket*, uint64_t>> gut;
     std::vector<gz_ticket*> queries;
-    uint64_t n = 0;
+    uint64_t n = 0;         // new updates taken
+    uint64_t ingested = 0;  // updates the ingest applies (flushed and staged)
     uint32_t batches = 0;
     uint64_t take_ns = 0, launched_ns = 0;
 };
 constexpr size_t kTimelineCap = 1 << 20;  // tick records kept per server
 
+bool query_ready(const gz_session* s) {
+    return !s->queue.empty() && s->queue.front()->kind == gz_ticket::QUERY &&
+           s->upd_inflight == 0 && s->ingests_inflight == 0 && s->gfill == 0;
+}
+
+bool flush_wanted(const gz_session* s) {
+    return s->gfill > 0 && (s->flush_req || (!s->queue.empty() &&
+                                             s->queue.front()->kind == gz_ticket::QUERY));
+}
+
 void take_tick(gz_server* S, Tick& t) {
-    for (gz_session* s : S->admitted) {
+    // a different session first in each tick: a session whose flush did not
+    // fit one tick's budget comes early in a later one
+    const size_t A = S->admitted.size();
+    const size_t first = A ? S->tick_seq++ % A : 0;
+    for (size_t j = 0; j < A; ++j) {
+        gz_session* s = S->admitted[(first + j) % A];
         if (s->query_busy) continue;  // later batches wait for the running query
         std::vector<gz_ticket*> mine;
+        bool flush = false, wrote_gutter = false;
+        // flushes are bounded like new updates, one always allowed
+        auto may_flush = [&] { return t.ingested == 0 || t.ingested + s->gfill <= S->tick_cap; };
         while (!s->queue.empty() && s->queue.front()->kind == gz_ticket::UPDATES) {
             gz_ticket* k = s->queue.front();
             if (t.n > 0 && t.n + k->n > S->tick_cap) break;
+            if (s->gcap && !flush) {
+                if (s->gfill + k->n <= s->gcap) {
+                    t.gut.emplace_back(k, s->gfill);
+                    s->gfill += k->n;
+                    wrote_gutter = true;
+                } else {
+                    // the gutter cannot take the batch: flush it (in the next
+                    // tick if this one wrote to it) and stage the batch behind
+                    if (wrote_gutter || !may_flush()) break;
+                    flush = true;
+                    mine.push_back(k);
+                }
+            } else {
+                mine.push_back(k);
+            }
             t.n += k->n;
             t.batches++;
-            mine.push_back(k);
+            s->inflight += 1;
+            s->upd_inflight += 1;
             s->queue.pop_front();
         }
-        if (!mine.empty()) {
+        if (!flush && !wrote_gutter && flush_wanted(s) && may_flush()) flush = true;
+        if (flush || !mine.empty()) {
+            uint64_t staged = flush ? s->gfill : 0;
+            for (gz_ticket* k : mine) staged += k->n;
             t.upd_sessions.push_back(s);
-            s->inflight += (uint32_t)mine.size();
-            s->upd_inflight += (uint32_t)mine.size();
+            t.flushed.push_back(flush ? s->gfill : 0);
             t.upd.push_back(std::move(mine));
+            t.ingested += staged;
+            if (flush) s->gfill = 0;
+            s->ingests_inflight += 1;
         }
-        // a query runs once every earlier batch of its session is applied
-        if (!s->queue.empty() && s->queue.front()->kind == gz_ticket::QUERY &&
-            s->upd_inflight == 0) {
+        if (query_ready(s)) {
             t.queries.push_back(s->queue.front());
             s->queue.pop_front();
             s->inflight += 1;
@@ -367,7 +434,7 @@ std::deque<gz_session*>::iterator admissible(gz_server* S) {
     const bool head_only = now_ns() - (*it)->wait_since > kAdmitPatienceNs;
     for (; it != S->waiting.end(); ++it) {
         if (S->used + (*it)->bytes <= S->budget &&
-            (!S->arena.active() || S->arena.fits(sketch_bytes((*it)->V))))
+            (!S->arena.active() || S->arena.fits(arena_bytes((*it)->V, (*it)->gcap))))
             return it;
         if (head_only) break;
     }
@@ -387,9 +454,10 @@ bool admit(gz_server* S, std::unique_lock<std::mutex>& lk) {
         s->admitting = true;
         gz_config cfg{};
         if (S->arena.active()) {
-            s->storage = S->arena.take(sketch_bytes(s->V));
+            s->storage = S->arena.take(arena_bytes(s->V, s->gcap));
             cfg.storage = s->storage;
             cfg.storage_bytes = sketch_bytes(s->V);
+            if (s->gcap) s->gut = reinterpret_cast<uint32_t*>(s->storage + gutter_offset(s->V));
         }
         lk.unlock();
         gz_graph* g = nullptr;
@@ -403,8 +471,9 @@ bool admit(gz_server* S, std::unique_lock<std::mutex>& lk) {
         S->cv_done.notify_all();  // a close may wait for the admission to end
         if (st != GZ_OK) {
             S->used -= s->bytes;
-            S->arena.give(s->storage, sketch_bytes(s->V));
+            S->arena.give(s->storage, arena_bytes(s->V, s->gcap));
             s->storage = nullptr;
+            s->gut = nullptr;
             S->waiting.push_front(s);  // retry later
             return false;
         }
@@ -438,8 +507,9 @@ void admit_main(gz_server* S) {
 
 bool has_work(gz_server* S) {
     for (gz_session* s : S->admitted)
-        if (!s->query_busy && !s->queue.empty() &&
-            (s->queue.front()->kind == gz_ticket::UPDATES || s->upd_inflight == 0))
+        if (!s->query_busy &&
+            ((!s->queue.empty() && s->queue.front()->kind == gz_ticket::UPDATES) ||
+             flush_wanted(s) || query_ready(s)))
             return true;
     return false;
 }
@@ -512,6 +582,7 @@ void query_main(gz_server* S) {
                 gz_session* s = k->sess;
                 S->stats.queries++;
                 k->res.admit_ns = s->admit_ns;
+                if (s->gstatus) k->res.status = s->gstatus;  // some of its updates failed
                 k->done = true;
                 s->inflight -= 1;
                 s->query_busy = false;
@@ -550,43 +621,95 @@ gz_status ensure_tick_buffers(gz_server* S, int buf, uint64_t n, uint64_t pieces
     return GZ_OK;
 }
 
-// The tick's batches, session after session, gathered into the staging arrays
-// of `buf` by one kernel; then the fused ingest over the tick's graphs.
+// One gather kernel moves the tick's batches into their sessions' gutters
+// and, session after session, the flushed gutters' content and the batches
+// staged behind it into the staging arrays of `buf`; then the fused ingest
+// over the sessions whose sketches the tick updates.
 gz_status launch_tick(gz_server* S, Tick& t, int buf) {
+    auto npieces = [](uint64_t n) { return (n + kGatherPiece - 1) / kGatherPiece; };
     uint64_t pieces = 0;
-    for (auto& v : t.upd)
-        for (gz_ticket* k : v) pieces += (k->n + kGatherPiece - 1) / kGatherPiece;
-    GZ_TRY(ensure_tick_buffers(S, buf, t.n, pieces));
+    for (size_t i = 0; i < t.upd_sessions.size(); ++i) {
+        pieces += npieces(t.flushed[i]);
+        for (gz_ticket* k : t.upd[i]) pieces += npieces(k->n);
+    }
+    for (auto& kp : t.gut) pieces += npieces(kp.first->n);
+    GZ_TRY(ensure_tick_buffers(S, buf, t.ingested, pieces));
     uint32_t* dsrc = S->d_stage[buf];
     uint32_t* ddst = dsrc + S->stage_cap[buf];
     GatherPiece* hp = S->h_pieces[buf];
+    uint64_t np = 0;
+    auto add = [&](const uint32_t* a, const uint32_t* b, uint32_t* oa, uint32_t* ob, uint64_t n) {
+        for (uint64_t o = 0; o < n; o += kGatherPiece)
+            hp[np++] = GatherPiece{a + o, b + o, oa + o, ob + o,
+                                   (uint32_t)std::min<uint64_t>(kGatherPiece, n - o), 0};
+    };
     std::vector<gz_graph*> gs;
     std::vector<uint64_t> offs(1, 0);
-    uint64_t at = 0, np = 0;
+    uint64_t at = 0;
     const uint64_t start = now_ns();
     for (size_t i = 0; i < t.upd_sessions.size(); ++i) {
-        gs.push_back(t.upd_sessions[i]->g);
+        gz_session* s = t.upd_sessions[i];
+        gs.push_back(s->g);
+        add(s->gut, s->gut + s->gcap, dsrc + at, ddst + at, t.flushed[i]);
+        at += t.flushed[i];
         for (gz_ticket* k : t.upd[i]) {
-            for (uint64_t o = 0; o < k->n; o += kGatherPiece)
-                hp[np++] = GatherPiece{k->src + o, k->dst + o, at + o,
-                                       (uint32_t)std::min<uint64_t>(kGatherPiece, k->n - o), 0};
+            add(k->src, k->dst, dsrc + at, ddst + at, k->n);
             at += k->n;
             k->res.start_ns = start;
         }
         offs.push_back(at);
     }
-    GZ_HIP(hipMemcpyAsync(S->d_pieces[buf], hp, np * sizeof(GatherPiece), hipMemcpyHostToDevice,
-                          S->stream));
+    for (auto& kp : t.gut) {
+        gz_ticket* k = kp.first;
+        gz_session* s = k->sess;
+        add(k->src, k->dst, s->gut + kp.second, s->gut + s->gcap + kp.second, k->n);
+        k->res.start_ns = start;
+    }
+    if (np)
+        GZ_HIP(hipMemcpyAsync(S->d_pieces[buf], hp, np * sizeof(GatherPiece),
+                              hipMemcpyHostToDevice, S->stream));
     GZ_HIP(hipEventRecord(S->tick_t0[buf], S->stream));
-    k_srv_gather<<<(uint32_t)np, kGatherThreads, 0, S->stream>>>(S->d_pieces[buf], dsrc, ddst);
-    GZ_HIP(hipGetLastError());
-    GZ_TRY(gz_ingest_multi(gs.data(), (uint32_t)gs.size(), offs.data(), dsrc, ddst,
-                           GZ_ASYNC | GZ_DEVICE_PTR, S->stream));
+    if (np) {
+        k_srv_gather<<<(uint32_t)np, kGatherThreads, 0, S->stream>>>(S->d_pieces[buf]);
+        GZ_HIP(hipGetLastError());
+    }
+    if (!gs.empty())
+        GZ_TRY(gz_ingest_multi(gs.data(), (uint32_t)gs.size(), offs.data(), dsrc, ddst,
+                               GZ_ASYNC | GZ_DEVICE_PTR, S->stream));
     GZ_HIP(hipEventRecord(S->tick_t1[buf], S->stream));
     GZ_HIP(hipEventRecord(S->stage_ev[buf], S->stream));
     std::lock_guard<std::mutex> lk(S->mu);
     S->stats.staged_bytes += 8 * t.n;
     return GZ_OK;
+}
+
+// the tick's requests are done: its batches complete, and its sessions' gutter
+// ingests are no longer in flight (a failed one is reported by their queries)
+void finish_tick(gz_server* S, Tick& t, gz_status st) {
+    for (size_t i = 0; i < t.upd_sessions.size(); ++i) {
+        t.upd_sessions[i]->g->pending_error = false;
+        for (gz_ticket* k : t.upd[i]) {
+            S->pool.give(k->pinned, k->pinned_cap);  // the gather has read it
+            k->pinned = nullptr;
+            complete(S, k, st);
+        }
+    }
+    for (auto& kp : t.gut) {
+        S->pool.give(kp.first->pinned, kp.first->pinned_cap);
+        kp.first->pinned = nullptr;
+        complete(S, kp.first, st);
+    }
+    std::lock_guard<std::mutex> lk(S->mu);
+    for (size_t i = 0; i < t.upd_sessions.size(); ++i) {
+        gz_session* s = t.upd_sessions[i];
+        s->ingests_inflight -= 1;
+        if (st && !s->gstatus) s->gstatus = st;
+    }
+    if (st) {
+        for (auto& kp : t.gut)
+            if (!kp.first->sess->gstatus) kp.first->sess->gstatus = st;
+    }
+    S->cv_done.notify_all();  // gz_session_graph may wait for a flush
 }
 
 void worker_main(gz_server* S) {
@@ -611,7 +734,8 @@ void worker_main(gz_server* S) {
         t.take_ns = now_ns();
         // 1. launch this tick's gather and fused ingest (async)
         gz_status st = GZ_OK;
-        if (t.n > 0) {
+        const bool launch = !t.upd_sessions.empty() || !t.gut.empty();
+        if (launch) {
             const uint64_t t0 = now_ns();
             hipEventSynchronize(S->stage_ev[buf]);  // tick t-2's ingest is done with buf
             const uint64_t t1 = now_ns();
@@ -624,6 +748,8 @@ void worker_main(gz_server* S) {
             if (!st) {
                 S->stats.ticks++;
                 S->stats.updates += t.n;
+                S->stats.ingested += t.ingested;
+                for (uint64_t f : t.flushed) S->stats.flushes += f > 0;
             }
         }
         // 2. hand the queries to the query threads
@@ -644,6 +770,7 @@ void worker_main(gz_server* S) {
                 rec.launched_ns = prev.tick.launched_ns;
                 rec.done_ns = now_ns();
                 rec.updates = prev.tick.n;
+                rec.ingested = prev.tick.ingested;
                 rec.batches = prev.tick.batches;
                 rec.graphs = (uint32_t)prev.tick.upd_sessions.size();
                 float ms = 0.f;
@@ -658,26 +785,14 @@ void worker_main(gz_server* S) {
             // left to wait for, and the graphs need no flush-time error check
             // (two synchronous device reads per session, most of a tick's time
             // when a tick holds dozens of sessions).  No query of these
-            // sessions runs until their batches complete, below.
-            for (size_t i = 0; i < prev.tick.upd_sessions.size(); ++i) {
-                prev.tick.upd_sessions[i]->g->pending_error = false;
-                for (gz_ticket* k : prev.tick.upd[i]) {
-                    S->pool.give(k->pinned, k->pinned_cap);  // the gather has read it
-                    k->pinned = nullptr;
-                    complete(S, k, pst);
-                }
-            }
+            // sessions runs until their ingests complete.
+            finish_tick(S, prev.tick, pst);
             prev = Pending{};
         }
-        if (t.n > 0) {
+        if (launch) {
             if (st) {
                 hipStreamSynchronize(S->stream);  // nothing of the tick may still read them
-                for (size_t i = 0; i < t.upd_sessions.size(); ++i)
-                    for (gz_ticket* k : t.upd[i]) {
-                        S->pool.give(k->pinned, k->pinned_cap);
-                        k->pinned = nullptr;
-                        complete(S, k, st);
-                    }
+                finish_tick(S, t, st);
                 std::lock_guard<std::mutex> lk(S->mu);
                 if (!S->error) S->error = st;
             } else {
@@ -736,7 +851,12 @@ gz_status gz_session_open(gz_server* S, uint32_t V, uint64_t seed, gz_session** 
     s->srv = S;
     s->V = V;
     s->seed = seed;
-    s->bytes = session_bytes(V);
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        if (S->gutter_per_node && S->arena.active())
+            s->gcap = std::max<uint64_t>((uint64_t)S->gutter_per_node * V, kGutterMin);
+    }
+    s->bytes = session_bytes(V) + 8 * s->gcap;
     if (s->bytes > S->budget) {
         delete s;
         return gz::fail(GZ_ENOMEM, "session larger than the whole HBM budget");
@@ -954,11 +1074,27 @@ gz_status gz_wait_any(gz_ticket* const* tickets, uint32_t n, uint64_t timeout_ns
 
 gz_status gz_session_graph(gz_session* s, gz_graph** out) {
     if (!s || !out) return gz::fail(GZ_EINVAL, "null argument");
-    std::lock_guard<std::mutex> lk(s->srv->mu);
+    gz_server* S = s->srv;
+    std::unique_lock<std::mutex> lk(S->mu);
     *out = s->g;
     if (!s->g) return gz::fail(GZ_ESTATE, "session not admitted yet");
     if (!s->queue.empty() || s->inflight)
         return gz::fail(GZ_ESTATE, "the session has requests in flight");
+    if (s->gfill || s->ingests_inflight) {
+        // the sketches hold every batch once the gutter is applied
+        s->flush_req = true;
+        S->cv_work.notify_one();
+        S->cv_done.wait(lk, [&] { return s->gfill == 0 && s->ingests_inflight == 0; });
+        s->flush_req = false;
+    }
+    if (s->gstatus) return gz::fail(s->gstatus, "an ingest of the session's updates failed");
+    return GZ_OK;
+}
+
+gz_status gz_server_set_gutter(gz_server* S, uint32_t updates_per_node) {
+    if (!S) return gz::fail(GZ_EINVAL, "null server");
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->gutter_per_node = updates_per_node;
     return GZ_OK;
 }
 
@@ -979,7 +1115,10 @@ gz_status gz_session_close(gz_session* s) {
         S->cv_done.notify_all();
     }
     S->cv_work.notify_one();
-    S->cv_done.wait(lk, [&] { return s->queue.empty() && s->inflight == 0 && !s->query_busy; });
+    // (updates still in its gutter are dropped with the session)
+    S->cv_done.wait(lk, [&] {
+        return s->queue.empty() && s->inflight == 0 && !s->query_busy && s->ingests_inflight == 0;
+    });
     auto it = std::find(S->admitted.begin(), S->admitted.end(), s);
     const bool held = it != S->admitted.end();
     if (held) S->admitted.erase(it);
@@ -993,8 +1132,9 @@ gz_status gz_session_close(gz_session* s) {
     lk.lock();
     S->stats.free_ns += dt;
     S->stats.free_ns_max = std::max(S->stats.free_ns_max, dt);
-    S->arena.give(s->storage, sketch_bytes(s->V));
+    S->arena.give(s->storage, arena_bytes(s->V, s->gcap));
     s->storage = nullptr;
+    s->gut = nullptr;
     if (held) S->used -= s->bytes;  // the memory is free now: waiting sessions may go
     lk.unlock();
     delete s;

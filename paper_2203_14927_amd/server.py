@@ -22,6 +22,7 @@ class gz_replay_session(ctypes.Structure):
 class gz_tick_record(ctypes.Structure):
     _fields_ = [("take_ns", ctypes.c_uint64), ("launched_ns", ctypes.c_uint64),
                 ("done_ns", ctypes.c_uint64), ("updates", ctypes.c_uint64),
+                ("ingested", ctypes.c_uint64),
                 ("batches", ctypes.c_uint32), ("graphs", ctypes.c_uint32),
                 ("device_ms", ctypes.c_float), ("reserved", ctypes.c_uint32)]
 
@@ -32,7 +33,8 @@ class gz_server_stats(ctypes.Structure):
                                                "hbm_budget", "batches_copied", "batches_inplace",
                                                "staged_bytes", "worker_wait_ns",
                                                "worker_launch_ns", "query_runs", "create_ns",
-                                               "create_ns_max", "free_ns", "free_ns_max")]
+                                               "create_ns_max", "free_ns", "free_ns_max",
+                                               "ingested", "flushes")]
 
 
 def _declare(L):
@@ -54,6 +56,8 @@ def _declare(L):
     L.gz_wait_any.restype = i32
     L.gz_session_graph.argtypes = [vp, pp]
     L.gz_session_graph.restype = i32
+    L.gz_server_set_gutter.argtypes = [vp, u32]
+    L.gz_server_set_gutter.restype = i32
     L.gz_server_replay.argtypes = [vp, vp, u32, vp, u64, vp, vp, vp, u32, u32, vp, vp, vp,
                                    ctypes.POINTER(u64)]
     L.gz_server_replay.restype = i32
@@ -172,8 +176,8 @@ class Session:
         return Ticket(t, keep=labels)
 
     def graph(self):
-        """The session's graph (export, query) while none of its requests is in flight; the
-        server keeps ownership, so the object frees nothing."""
+        """The session's graph (export, query) while none of its requests is in flight, once
+        its gutter is applied; the server keeps ownership, so the object frees nothing."""
         from . import Graph, check, lib
 
         h = ctypes.c_void_p()
@@ -189,7 +193,9 @@ class Session:
 
 
 class Server:
-    def __init__(self, hbm_budget: int, tick_updates: int = 0):
+    def __init__(self, hbm_budget: int, tick_updates: int = 0, gutter_per_node=None):
+        """gutter_per_node: gutter updates per node of each session (None: the library's
+        default; 0: no gutters)."""
         from . import check, lib
 
         h = ctypes.c_void_p()
@@ -198,6 +204,8 @@ class Server:
         from . import _track
 
         _track("server", self)
+        if gutter_per_node is not None:
+            check(lib().gz_server_set_gutter(h, int(gutter_per_node)))
 
     def open(self, V: int, seed: int) -> Session:
         return Session(self, V, seed)
@@ -231,8 +239,8 @@ class Server:
                 "wall_ns": wall.value}
 
     def timeline(self) -> np.ndarray:
-        """Tick records (structured array: take/launched/done ns, updates, batches, graphs,
-        device_ms)."""
+        """Tick records (structured array: take/launched/done ns, new updates, updates ingested,
+        batches, graphs, device_ms)."""
         from . import check, lib
 
         n = ctypes.c_uint64()
@@ -241,7 +249,7 @@ class Server:
         check(lib().gz_server_timeline(self._h, ctypes.cast(arr, ctypes.c_void_p), n.value,
                                        ctypes.byref(n)))
         dt = np.dtype([("take_ns", "u8"), ("launched_ns", "u8"), ("done_ns", "u8"),
-                       ("updates", "u8"), ("batches", "u4"), ("graphs", "u4"),
+                       ("updates", "u8"), ("ingested", "u8"), ("batches", "u4"), ("graphs", "u4"),
                        ("device_ms", "f4"), ("reserved", "u4")])
         return np.frombuffer(bytes(arr), dtype=dt).copy()
 

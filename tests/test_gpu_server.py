@@ -39,10 +39,12 @@ def _expected(V, stream, upto):
     return workloads.union_find_labels(V, fu, fv)
 
 
-def test_sessions_in_the_mix_equal_alone(gz):
+@pytest.mark.parametrize("gutter", [None, 0])
+def test_sessions_in_the_mix_equal_alone(gz, gutter):
+    """With gutters (the default) and without: a query applies its session's gutter first."""
     from paper_2203_14927_amd.server import Server
 
-    srv = Server(hbm_budget=8 << 30, tick_updates=20000)
+    srv = Server(hbm_budget=8 << 30, tick_updates=20000, gutter_per_node=gutter)
     specs = [(100 + k, int(V)) for k, V in enumerate([40, 300, 1000, 64, 2000, 513])]
     results = {}
     errors = []
@@ -159,15 +161,17 @@ def _drive_mixed(srv, plans, torch):
         assert t.wait()["status"] == 0
 
 
-def test_session_sketches_equal_oracle_and_solo(gz):
+@pytest.mark.parametrize("gutter", [None, 0])
+def test_session_sketches_equal_oracle_and_solo(gz, gutter):
     """Sessions served together, through every submission form, end with the sketches
-    the oracle computes for each session's stream alone, and the same as a solo graph."""
+    the oracle computes for each session's stream alone, and the same as a solo graph
+    (with gutters, the session's graph is handed out once its gutter is applied)."""
     import torch
 
     import oracle
     from paper_2203_14927_amd.server import Server
 
-    srv = Server(hbm_budget=8 << 30, tick_updates=5000)
+    srv = Server(hbm_budget=8 << 30, tick_updates=5000, gutter_per_node=gutter)
     plans, streams = [], []
     for k, V in enumerate([50, 700, 3000, 129]):
         rng = np.random.default_rng(70 + k)
@@ -193,6 +197,8 @@ def test_session_sketches_equal_oracle_and_solo(gz):
     st = srv.stats()
     assert st["batches_inplace"] > 0 and st["batches_copied"] > 0
     assert st["staged_bytes"] == 8 * st["updates"]
+    assert st["ingested"] == st["updates"]  # every gutter was applied
+    assert (st["flushes"] > 0) == (gutter is None)
     for sess, _ in plans:
         sess.close()
     srv.close()
@@ -340,3 +346,70 @@ def test_replay_drives_every_request(gz, open_loop):
     assert (r["query_latency_ns"] > 0).sum() == n_q == st["queries"]
     assert st["updates"] == int(offs[-1]) and st["sessions_admitted"] == len(Vs)
     assert r["wall_ns"] > 0
+
+
+def test_full_gutters_flush_between_queries(gz):
+    """Sessions whose batches overflow their gutter (65536 updates) between queries, one
+    batch larger than the gutter itself, and a tick budget smaller than one flush: every
+    query equals union-find on its prefix and the final sketches equal the oracle's."""
+    import oracle
+    from paper_2203_14927_amd.server import Server
+
+    srv = Server(hbm_budget=8 << 30, tick_updates=20000)
+    specs = []
+    for k, V in enumerate([300, 64, 1500]):
+        batches = [9000] * 9 + ([70000] if k == 1 else []) + [9000] * 9
+        stream, plan = _session_plan(800 + k, V, batches)
+        specs.append((V, stream, plan, srv.open(V, 40 + k)))
+    pending = []
+    for V, stream, plan, sess in specs:
+        done = 0
+        for i, (src, dst) in enumerate(plan):
+            pending.append(("u", sess.submit_updates(src, dst), None, None))
+            done += len(src)
+            if i in (8, len(plan) - 1):
+                pending.append(("q", sess.submit_query(), (V, stream), done))
+    for kind, t, vs, upto in pending:
+        r = t.wait()
+        assert r["status"] == 0
+        if kind == "q":
+            V, stream = vs
+            assert (r["labels"] == _expected(V, stream, upto)).all(), (V, upto)
+    st = srv.stats()
+    assert st["flushes"] > 6 and st["ingested"] == st["updates"] == sum(
+        s[1].N for s in specs)
+    for k, (V, stream, _, sess) in enumerate(specs):
+        a, b = sess.graph().export()
+        O = oracle.Oracle(V, 40 + k)
+        O.ingest(stream.src, stream.dst)
+        assert (a == O.alpha).all() and (b == O.gamma).all(), f"session {k}"
+        sess.close()
+    srv.close()
+
+
+def test_graph_applies_the_gutter(gz):
+    """Batches acknowledged into the gutter are in the sketches the session's graph hands
+    out, and a later batch still goes to the (emptied) gutter."""
+    import oracle
+    from paper_2203_14927_amd.server import Server
+
+    srv = Server(hbm_budget=1 << 30)
+    V = 500
+    stream, plan = _session_plan(21, V, [3000, 2000, 1000])
+    sess = srv.open(V, 77)
+    for src, dst in plan[:2]:
+        assert sess.submit_updates(src, dst).wait()["status"] == 0
+    st = srv.stats()
+    assert st["updates"] == 5000 and st["ingested"] == 0  # still in the gutter
+    a, b = sess.graph().export()
+    O = oracle.Oracle(V, 77)
+    O.ingest(stream.src[:5000], stream.dst[:5000])
+    assert (a == O.alpha).all() and (b == O.gamma).all()
+    assert srv.stats()["ingested"] == 5000
+    assert sess.submit_updates(*plan[2]).wait()["status"] == 0
+    r = sess.submit_query().wait()
+    assert (r["labels"] == _expected(V, stream, 6000)).all()
+    st = srv.stats()
+    assert st["ingested"] == 6000 and st["flushes"] == 2
+    sess.close()
+    srv.close()

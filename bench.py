@@ -740,8 +740,8 @@ def run_serving(args) -> dict:
         "device_busy_frac": float(tl["device_ms"].sum() / 1e3 / wall),
         "device_ms_per_tick": _mean(tl["device_ms"]),
         "updates_per_tick": _mean(tl["updates"]),
-        "ingested_per_tick": _mean(tl["ingested"]),
         "ingesting_ticks": int((tl["ingested"] > 0).sum()),
+        "ingested_per_ingesting_tick": _mean(tl["ingested"][tl["ingested"] > 0]),
         "batches_per_tick": _mean(tl["batches"]),
         "graphs_per_tick": _mean(tl["graphs"]),
         "host_build_launch_ms_per_tick": _mean((tl["launched_ns"] - tl["take_ns"]) / 1e6),

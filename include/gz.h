@@ -396,7 +396,7 @@ gz_status gz_measure_peaks(gz_peaks* out, hipStream_t stream);
  *   gutters a tick applies (up to `tick_updates` updates, one always) go
  *   through one fused multi-graph ingest.  gz_server_set_gutter sets the
  *   gutter size of sessions opened afterwards: updates_per_node * V updates,
- *   at least 65536 (default 16 per node; 0: no gutters, every batch applied by
+ *   at least 65536 (default 64 per node; 0: no gutters, every batch applied by
  *   the tick that takes it); its 8 B per update count against the budget.
  *   An update batch's ticket completes once the batch is in its session's
  *   gutter, or applied.  A query is answered once every batch submitted

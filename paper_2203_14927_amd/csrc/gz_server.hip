@@ -30,7 +30,7 @@
 namespace {
 
 constexpr int kQueryThreads = 2;
-constexpr uint32_t kGutterPerNode = 16;      // gutter updates per node of a session
+constexpr uint32_t kGutterPerNode = 64;      // gutter updates per node of a session
 constexpr uint64_t kGutterMin = 1ull << 16;  // and at least this many
 constexpr size_t kQueryBatch = 512;  // queries answered by one fused run
 

@@ -376,7 +376,10 @@ def test_full_gutters_flush_between_queries(gz):
             V, stream = vs
             assert (r["labels"] == _expected(V, stream, upto)).all(), (V, upto)
     st = srv.stats()
-    assert st["flushes"] > 6 and st["ingested"] == st["updates"] == sum(
+    # at least one flush per query interval (each holds more than a gutter; where a
+    # batch that overflows the gutter shares a tick with the batches before the
+    # query, that one flush serves the query too)
+    assert st["flushes"] >= 6 and st["ingested"] == st["updates"] == sum(
         s[1].N for s in specs)
     for k, (V, stream, _, sess) in enumerate(specs):
         a, b = sess.graph().export()

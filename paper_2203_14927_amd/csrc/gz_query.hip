@@ -38,6 +38,7 @@ struct QueryScratch {
     uint32_t *m = nullptr, *m2 = nullptr, *rootOf = nullptr, *newlab = nullptr, *merged = nullptr;
     uint32_t *gof = nullptr, *acc = nullptr, *ctl = nullptr, *labels = nullptr;
     uint32_t *gcount = nullptr, *gfail = nullptr, *foff = nullptr, *fcur = nullptr;
+    uint32_t* gcomp = nullptr;  // components of each graph a round leaves (two sets of G)
     uint32_t *fcnt = nullptr;
     uint32_t *fpairs = nullptr;
     uint64_t *forest = nullptr, *fsorted = nullptr;
@@ -141,15 +142,29 @@ __global__ void k_q_init(uint32_t T, const GraphDesc* __restrict__ gd, uint32_t 
     }
 }
 
+// How a round learns that a component holds every node of its graph: such a
+// component's sketch sums every edge twice, so it is zero and the component
+// is finished without being reduced or queried (linearity, Sec. 3.1).
+enum : uint32_t {
+    WHOLE_OFF = 0,     // not tracked
+    WHOLE_SINGLE = 1,  // one graph: the list has one entry
+    WHOLE_COUNT = 2,   // several graphs: the round before counted each graph's components
+};
+
 __global__ __launch_bounds__(kAppendThreads) void k_q_select(
     uint32_t r, const uint32_t* __restrict__ L, uint32_t* __restrict__ ctl,
-    const uint32_t* __restrict__ done, const uint32_t* __restrict__ gof,
+    uint32_t* __restrict__ done, const uint32_t* __restrict__ gof,
     const GraphDesc* __restrict__ gd, uint32_t* __restrict__ slot, uint32_t* __restrict__ A,
     uint32_t* __restrict__ hook, uint32_t* __restrict__ newlab, uint32_t* __restrict__ merged,
-    uint32_t* __restrict__ pos) {
+    uint32_t* __restrict__ pos, uint32_t whole_mode, uint32_t G,
+    const uint32_t* __restrict__ gcomp_prev, uint32_t* __restrict__ gcomp_next) {
     __shared__ uint32_t sh[kMaxWaves + 1];
     if (ctl[Q_STOP]) return;
     const uint32_t nL = ctl[Q_NL];
+    if (whole_mode == WHOLE_COUNT)
+        for (uint32_t g = blockIdx.x * blockDim.x + threadIdx.x; g < G;
+             g += gridDim.x * blockDim.x)
+            gcomp_next[g] = 0;
     for (uint32_t i0 = blockIdx.x * blockDim.x; i0 < nL; i0 += gridDim.x * blockDim.x) {
         const uint32_t i = i0 + threadIdx.x;
         bool act = false;
@@ -160,7 +175,14 @@ __global__ __launch_bounds__(kAppendThreads) void k_q_select(
             hook[X] = kNone;
             newlab[X] = kNone;
             merged[X] = 0;
-            act = !done[X] && r < gd[gof[X]].R;
+            const uint32_t g = gof[X];
+            act = !done[X] && r < gd[g].R;
+            const bool whole = r > 0 && ((whole_mode == WHOLE_SINGLE && nL == 1) ||
+                                         (whole_mode == WHOLE_COUNT && gcomp_prev[g] == 1));
+            if (act && whole) {
+                done[X] = 1;
+                act = false;
+            }
         }
         const uint32_t a = block_append(&ctl[Q_NA], act, sh);
         if (i < nL) slot[X] = act ? a : kNone;
@@ -795,7 +817,8 @@ __global__ __launch_bounds__(kAppendThreads) void k_q_newcomps(
     uint32_t r, uint32_t T, uint32_t* __restrict__ comp, const uint32_t* __restrict__ L,
     uint32_t* __restrict__ ctl, const uint32_t* __restrict__ rootOf,
     const uint32_t* __restrict__ newlab, const uint32_t* __restrict__ merged,
-    uint32_t* __restrict__ done, uint32_t* __restrict__ L2, uint32_t* __restrict__ host_na) {
+    uint32_t* __restrict__ done, uint32_t* __restrict__ L2, uint32_t* __restrict__ host_na,
+    const uint32_t* __restrict__ gof, uint32_t* __restrict__ gcomp_next) {
     __shared__ uint32_t sh[kMaxWaves + 1];
     __shared__ uint32_t s_last;
     if (ctl[Q_STOP]) return;
@@ -812,6 +835,18 @@ __global__ __launch_bounds__(kAppendThreads) void k_q_newcomps(
         }
         const uint32_t at = block_append(&ctl[Q_NL2], root, sh);
         if (root) L2[at] = X;
+        if (gcomp_next) {
+            // each graph's components, one atomic per graph a wave meets
+            const uint32_t g = root ? gof[X] : kNone;
+            uint64_t pending = __ballot(root);
+            while (pending) {
+                const uint32_t leader = (uint32_t)__ffsll((unsigned long long)pending) - 1u;
+                const uint32_t gl = __shfl(g, (int)leader);
+                const uint64_t same = __ballot(root && g == gl);
+                if (__lane_id() == leader) atomicAdd(&gcomp_next[gl], (uint32_t)__popcll(same));
+                pending &= ~same;
+            }
+        }
     }
     // every node's label: the new label of its component's tree
     for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < T; v += gridDim.x * blockDim.x)
@@ -1006,6 +1041,7 @@ gz_status ensure_query(QueryScratch& Q, uint32_t T, uint32_t G, uint32_t wpr) {
     if (G > Q.cap_graphs || !Q.descs) {
         if ((st = qalloc(&Q.descs, G))) return st;
         if ((st = qalloc(&Q.gcount, G))) return st;
+        if ((st = qalloc(&Q.gcomp, 2ull * G))) return st;
         if ((st = qalloc(&Q.gfail, G))) return st;
         if ((st = qalloc(&Q.foff, (uint64_t)G + 1))) return st;
         if ((st = qalloc(&Q.fcur, G))) return st;
@@ -1192,7 +1228,14 @@ gz_status boruvka(gz_graph* const* gs, uint32_t G, bool want_forest, QueryResult
     const uint32_t lds_cap = narrow_ids ? kLdsResolveNarrow : kLdsResolve;
     uint32_t* Lc = Q->L;
     uint32_t* Ln = Q->L2;
+    // components that hold their whole graph finish unread: known from the
+    // list length for one graph, from per-graph counts for many small graphs
+    // (larger graphs would cost many same-address atomics per count)
+    const uint32_t whole_mode =
+        G == 1 ? WHOLE_SINGLE : (Vmax <= kGraphResolve ? WHOLE_COUNT : WHOLE_OFF);
     for (uint32_t r = 0; r < Rmax; ++r) {
+        uint32_t* gcomp_prev = Q->gcomp + ((r + 1) & 1) * (uint64_t)G;
+        uint32_t* gcomp_next = Q->gcomp + (r & 1) * (uint64_t)G;
         if (r >= 2) {
             GZ_HIP(hipEventSynchronize(Q->round_ev[r & 1]));
             if (Q->host_na[r - 2] == 0) break;
@@ -1204,7 +1247,7 @@ gz_status boruvka(gz_graph* const* gs, uint32_t G, bool want_forest, QueryResult
         }
         k_q_select<<<ta, kAppendThreads, 0, qs>>>(r, Lc, Q->ctl, Q->done, Q->gof, Q->descs,
                                                   Q->slot, Q->A, Q->hook, Q->newlab, Q->merged,
-                                                  Q->pos);
+                                                  Q->pos, whole_mode, G, gcomp_prev, gcomp_next);
         if (r == 0) {
             k_q_query<true><<<qgrid, 256, 0, qs>>>(r, Q->A, Q->ctl, Q->acc, wpr, 0u, Q->gof,
                                                    Q->descs, Q->comp, Q->hook, Q->hedge, Q->done);
@@ -1261,7 +1304,8 @@ gz_status boruvka(gz_graph* const* gs, uint32_t G, bool want_forest, QueryResult
         // at most kEndBlocks workgroups: each takes one returning atomic to
         // find the last (4233 of them took 40 us per round on 4.3 M nodes)
         k_q_newcomps<<<std::min(ta, kEndBlocks), kAppendThreads, 0, qs>>>(
-            r, T, Q->comp, Lc, Q->ctl, Q->rootOf, Q->newlab, Q->merged, Q->done, Ln, Q->host_na);
+            r, T, Q->comp, Lc, Q->ctl, Q->rootOf, Q->newlab, Q->merged, Q->done, Ln, Q->host_na,
+            Q->gof, whole_mode == WHOLE_COUNT ? gcomp_next : nullptr);
         std::swap(Lc, Ln);
         GZ_HIP(hipEventRecord(Q->round_ev[r & 1], qs));
     }

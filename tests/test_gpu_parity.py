@@ -469,3 +469,40 @@ def test_graph_in_caller_storage(gz):
     with pytest.raises(gz.GzError):
         gz.Graph(V, seed=seed, storage=buf[1:])  # 4-byte aligned only
     own.close()
+
+
+def _dense_stream(V, seed, p):
+    rng = np.random.default_rng(seed)
+    iu = np.triu_indices(V, 1)
+    keep = rng.random(len(iu[0])) < p
+    u, v = iu[0][keep].astype(np.uint32), iu[1][keep].astype(np.uint32)
+    perm = rng.permutation(len(u))
+    return workloads.Stream(V, u[perm], v[perm], np.ones(len(u), np.uint8))
+
+
+def test_components_that_hold_their_whole_graph(gz):
+    """Dense graphs with few rounds: a component that holds every node of its graph is
+    finished without being queried (its sketch sums to zero), one round before the
+    rounds run out (status OK) or not at all when it forms in the last round
+    (GZ_ESKETCH_FAIL), as the oracle decides by querying it.  Alone (the list length
+    tells) and fused (per-graph component counts)."""
+    cases = [(V, R, seed) for V in (12, 40, 200, 1500) for R in (2, 3, 4) for seed in (1, 2)]
+    streams, graphs, oracles, outcomes = [], [], [], set()
+    for V, R, seed in cases:
+        s = _dense_stream(V, seed, 0.3 if V < 1000 else 0.02)
+        g = gz.Graph(V, seed=seed, rounds=R)
+        g.ingest(to_dev(s.src), to_dev(s.dst))
+        O = oracle_for(s, seed, R=R)
+        st, labels, _ = assert_query_equal(g, O)
+        outcomes.add((st, len(np.unique(labels)) == 1))
+        streams.append(s)
+        graphs.append(g)
+        oracles.append(O)
+    # both edge cases occur: whole and confirmed, whole only in the last round
+    assert (gz.GZ_OK, True) in outcomes and (gz.GZ_ESKETCH_FAIL, True) in outcomes
+    labels, ncc, stt = gz.connected_components_multi(graphs)
+    for k, O in enumerate(oracles):
+        ost, olabels, _, _ = O.connected_components()
+        assert stt[k] == gz_status_of(ost), cases[k]
+        assert (labels[k] == olabels).all(), cases[k]
+        assert ncc[k] == len(np.unique(olabels))

@@ -235,6 +235,129 @@ __global__ __launch_bounds__(kGroupThreads) void k_group_scatter(
     }
 }
 
+// Sorted placement for calls whose graphs all have at most kSortNodes nodes
+// (a unit then covers every node of its graph).  The one-pass scatter above
+// stores each entry alone into one of V open runs: on 4096 graphs at once
+// those partly written lines left L2 and reached HBM as about six times the
+// bytes placed.  Here a unit takes its chunk in batches of `batch` updates:
+// counts per node in LDS, an exclusive scan, the batch's entries placed in
+// node order in LDS, then stored run after run, so that consecutive lanes
+// write consecutive words of a node's run.
+constexpr uint32_t kSortNodes = 4096;
+constexpr uint32_t kSortPer = 4;  // updates per thread and batch, at most
+constexpr uint32_t kSortSmemTarget = 80 * 1024 - 256;  // two workgroups per CU
+
+// exclusive scan of c[0..n) in place, n <= 4 * blockDim.x (1024 threads)
+__device__ __forceinline__ void block_scan4(uint32_t* __restrict__ c, uint32_t n,
+                                            uint32_t* __restrict__ wsum) {
+    const uint32_t base = threadIdx.x * 4u, lane = __lane_id(), wave = threadIdx.x >> 6;
+    uint32_t v[4], sum = 0;
+#pragma unroll
+    for (uint32_t k = 0; k < 4; ++k) {
+        v[k] = base + k < n ? c[base + k] : 0u;
+        sum += v[k];
+    }
+    uint32_t incl = sum;
+    for (uint32_t off = 1; off < 64; off <<= 1) {
+        const uint32_t t = __shfl_up(incl, off);
+        if (lane >= off) incl += t;
+    }
+    if (lane == 63) wsum[wave] = incl;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t run = 0;
+        for (uint32_t w = 0; w < (blockDim.x >> 6); ++w) {
+            const uint32_t t = wsum[w];
+            wsum[w] = run;
+            run += t;
+        }
+    }
+    __syncthreads();
+    uint32_t at = wsum[wave] + incl - sum;
+#pragma unroll
+    for (uint32_t k = 0; k < 4; ++k) {
+        if (base + k < n) c[base + k] = at;
+        at += v[k];
+    }
+}
+
+__global__ __launch_bounds__(kGroupThreads) void k_group_scatter_sorted(
+    const IngestArgs* __restrict__ a, const GroupUnit* __restrict__ units,
+    const GraphDesc* __restrict__ gd, const uint32_t* __restrict__ Hs,
+    uint32_t* __restrict__ grouped, const uint32_t* __restrict__ ctl, uint32_t range,
+    uint32_t batch) {
+    extern __shared__ uint32_t sm[];
+    __shared__ uint32_t wsum[kGroupThreads / 64];
+    uint32_t* gcur = sm;             // [range] next slot of each node's run in `grouped`
+    uint32_t* cnt = sm + range;      // [range] batch counts, then run starts/ends in ent
+    uint32_t* ent = sm + 2 * range;  // [2 * batch] the batch's entries in node order
+    uint16_t* nod = reinterpret_cast<uint16_t*>(ent + 2 * batch);  // [2 * batch] their nodes
+    if (ctl[2]) return;  // an invalid update: nothing is applied
+    const GroupUnit u = units[blockIdx.x];
+    const GraphDesc g = gd[u.g];
+    const UnitRange r = unit_range(a, gd, u, g);  // lo = 0, size = V
+    const uint32_t V = r.size;
+    const uint32_t* __restrict__ src = a->src;
+    const uint32_t* __restrict__ dst = a->dst;
+    const uint32_t* hs = Hs + g.hoff + (uint64_t)u.c * g.V;
+    for (uint32_t k = threadIdx.x; k < V; k += blockDim.x) gcur[k] = hs[k];
+    for (uint64_t b0 = r.i0; b0 < r.i1; b0 += batch) {
+        const uint32_t n = r.i1 - b0 < batch ? (uint32_t)(r.i1 - b0) : batch;
+        for (uint32_t k = threadIdx.x; k < V; k += blockDim.x) cnt[k] = 0;
+        __syncthreads();
+        // the batch's updates stay in registers between the two passes, both
+        // endpoints (< 2^16) packed in one word
+        uint32_t xy[kSortPer];
+#pragma unroll
+        for (uint32_t j = 0; j < kSortPer; ++j) {
+            const uint32_t i = j * blockDim.x + threadIdx.x;
+            xy[j] = i < n ? src[b0 + i] | (dst[b0 + i] << 16) : kNone;
+        }
+#pragma unroll
+        for (uint32_t j = 0; j < kSortPer; ++j)
+            if (xy[j] != kNone) {
+                atomicAdd(&cnt[xy[j] & 0xFFFFu], 1u);
+                atomicAdd(&cnt[xy[j] >> 16], 1u);
+            }
+        __syncthreads();
+        block_scan4(cnt, V, wsum);
+        __syncthreads();
+#pragma unroll
+        for (uint32_t j = 0; j < kSortPer; ++j)
+            if (xy[j] != kNone) {
+                const uint32_t x = xy[j] & 0xFFFFu, y = xy[j] >> 16;
+                const uint32_t idx = edge_index(x, y);
+                const uint32_t p = atomicAdd(&cnt[x], 1u);
+                ent[p] = idx;
+                nod[p] = (uint16_t)x;
+                const uint32_t q = atomicAdd(&cnt[y], 1u);
+                ent[q] = idx;
+                nod[q] = (uint16_t)y;
+            }
+        __syncthreads();
+        // cnt[v] is now the end of v's run in ent, which is where v + 1's starts
+        for (uint32_t i = threadIdx.x; i < 2 * n; i += blockDim.x) {
+            const uint32_t v = nod[i];
+            const uint32_t start = v ? cnt[v - 1] : 0u;
+            grouped[gcur[v] + (i - start)] = ent[i];
+        }
+        __syncthreads();
+        for (uint32_t k = threadIdx.x; k < V; k += blockDim.x)
+            gcur[k] += cnt[k] - (k ? cnt[k - 1] : 0u);
+        __syncthreads();
+    }
+}
+
+uint32_t sort_batch(uint32_t range) {
+    const uint32_t fit = (kSortSmemTarget - 8u * range) / 12u;  // 4 B entry + 2 B node, twice
+    return std::min(kSortPer * kGroupThreads, fit / 256u * 256u);
+}
+
+size_t sort_smem(uint32_t range) {
+    const uint32_t b = sort_batch(range);
+    return (size_t)2 * range * 4 + (size_t)2 * b * 4 + (size_t)2 * b * 2;
+}
+
 // Two-pass placement for large single-graph calls.  The one-pass scatter
 // above writes every chunk's entries into V node runs, far more open lines
 // than L2 holds, so each 4-byte store becomes a partial-line HBM write.  Here
@@ -1026,6 +1149,11 @@ struct LaunchShape {
     // two-pass placement (single large graph): bucket shift, buckets, chunks,
     // chunks per pass-B block, pass-B blocks
     bool two_pass = false;
+    // sorted one-pass placement (every graph of at most kSortNodes nodes):
+    // updates per batch, dynamic LDS bytes
+    bool sorted = false;
+    uint32_t sbatch = 0;
+    size_t ssmem = 0;
     bool wide = false;  // graphs with V > 2^16 (pair-keyed hashes, four planes)
     uint32_t bS = 0, nbk = 0, nbc = 0, bcr = 1, bblocks = 0;
     uint32_t ptarget = 0, pcap = 0;  // wide pass B: entries per piece, piece capacity
@@ -1118,6 +1246,13 @@ gz_status build_shape(gz_graph* const* gs, uint32_t G, const uint64_t* ranges, u
             L.pcap = L.nbk + (uint32_t)((2 * N + L.ptarget - 1) / L.ptarget) + 1;
         }
     }
+    if (!L.two_pass && !L.wide && L.n_units && L.range_max <= kSortNodes &&
+        sort_batch(L.range_max) > 0) {
+        L.sorted = true;
+        L.sbatch = sort_batch(L.range_max);
+        L.ssmem = sort_smem(L.range_max);
+        GZ_TRY(set_smem_limit((const void*)k_group_scatter_sorted, L.ssmem));
+    }
     L.nblocks = (uint32_t)((T + kScanTile - 1) / kScanTile);
     L.gsmem = (size_t)L.range_max * 4;
     L.smem = update_smem_bytes(tune.lds_rows, L.Bmax, L.Pmax, L.wide);
@@ -1192,6 +1327,9 @@ gz_status launch_sequence(IngestScratch& S, const LaunchShape& L, hipStream_t st
                                                                L.nbk, S.buckets, S.ctl);
         k_group_place<<<L.bblocks, kGroupThreads, 0, stream>>>(
             S.bbase, S.H, Tn, L.bS, L.nbk, L.nbc, L.bcr, S.buckets, S.grouped, S.ctl);
+    } else if (L.sorted) {
+        k_group_scatter_sorted<<<L.n_units, kGroupThreads, L.ssmem, stream>>>(
+            S.args, S.units, S.descs, S.H, S.grouped, S.ctl, L.range_max, L.sbatch);
     } else if (L.n_units) {
         k_group_scatter<<<L.n_units, kGroupThreads, L.gsmem, stream>>>(S.args, S.units, S.descs,
                                                                        S.H, S.grouped, S.ctl);

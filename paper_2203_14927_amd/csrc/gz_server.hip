@@ -1,9 +1,11 @@
 // Serving: many graph sessions share one GPU.  An admission thread admits
-// sessions while their sketches fit an HBM budget (their sketches cut from an
-// arena allocated with the server), and a worker thread packs the update
-// batches queued by all admitted sessions into one fused multi-graph ingest
-// per tick (continuous batching: a batch submitted while a tick runs joins the
-// next one).  Connectivity queries go to two query threads, each answering all
+// sessions while their sketches fit an HBM budget (their sketches and gutters
+// cut from an arena allocated with the server), and a worker thread takes the
+// update batches queued by all admitted sessions every tick (continuous
+// batching: a batch submitted while a tick runs joins the next one).  A tick
+// gathers batches into their sessions' gutters and applies the gutters that
+// are full or that a query needs with one fused multi-graph ingest, so that
+// each node's sketch is read and written once for many updates.  Connectivity queries go to two query threads, each answering all
 // the queries queued at that time with one fused Boruvka run, so that queries
 // and the next ticks' ingests overlap on the device.  Requests of one session
 // are applied in submission order: a query is taken once the session's earlier

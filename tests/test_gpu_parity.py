@@ -42,8 +42,11 @@ def _stream(V, n, seed, p_repeat=0.2):
 
 
 @pytest.mark.parametrize("V,n,seed", [(2, 7, 1), (3, 20, 2), (5, 40, 3), (64, 900, 4),
-                                      (100, 3000, 5), (257, 9000, 6), (1000, 20000, 7)])
+                                      (100, 3000, 5), (257, 9000, 6), (1000, 20000, 7),
+                                      (4096, 30000, 8)])
 def test_small_streams_sketch_and_query(gz, V, n, seed):
+    """V = 4096 is the largest graph the sorted placement takes (batches of 3840
+    updates, not a multiple of the workgroup's 1024 lanes)."""
     s = _stream(V, n, seed)
     g = gz.Graph(V, seed=seed * 7919 + 1)
     g.ingest(to_dev(s.src), to_dev(s.dst))

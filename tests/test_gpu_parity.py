@@ -509,3 +509,24 @@ def test_components_that_hold_their_whole_graph(gz):
         assert stt[k] == gz_status_of(ost), cases[k]
         assert (labels[k] == olabels).all(), cases[k]
         assert ncc[k] == len(np.unique(olabels))
+
+
+def test_fused_graphs_over_several_grouping_chunks(gz):
+    """A fused call over a few graphs of at most 4096 nodes with many updates each:
+    every graph spans several grouping chunks (each placed by its own workgroup, in
+    several sorted batches), and every sketch word equals the oracle's."""
+    Vs = [1500, 4096, 700]
+    streams = [_stream(V, 100_000, 60 + k) for k, V in enumerate(Vs)]
+    seeds = [workloads.many_graph_seed(9, k) for k in range(len(Vs))]
+    graphs = [gz.Graph(s.V, seed=sd) for s, sd in zip(streams, seeds)]
+    offs = np.zeros(len(streams) + 1, np.uint64)
+    offs[1:] = np.cumsum([s.N for s in streams])
+    src = np.concatenate([s.src for s in streams])
+    dst = np.concatenate([s.dst for s in streams])
+    gz.ingest_multi(graphs, offs, to_dev(src), to_dev(dst))
+    labels, ncc, stt = gz.connected_components_multi(graphs)
+    for k, (s, g) in enumerate(zip(streams, graphs)):
+        O = oracle_for(s, seeds[k])
+        assert_sketch_equal(g, O)
+        ost, olabels, _, _ = O.connected_components()
+        assert stt[k] == gz_status_of(ost) and (labels[k] == olabels).all()
